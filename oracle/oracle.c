@@ -1,0 +1,693 @@
+/*
+ * oracle.c - plain single-threaded CPU reference of the exact-cover layout
+ * decomposition path.  TEST INFRASTRUCTURE ONLY (see oracle.h): used by the
+ * tests and the benchmark's CPU-baseline leg; the product library neither
+ * links nor calls it, and the two share no code.
+ *
+ * Pipeline, in the paper's order (Sec. 2.2): layout -> layout graph ->
+ * simplification -> sub-graphs -> exact-cover solve (Sec. 2.3, Algorithm 1,
+ * Eq. 2) -> recovery of removed nodes -> stitch / conflict counts (Eq. 1).
+ */
+#include "oracle.h"
+
+#include <pthread.h>
+#include <stdlib.h>
+#include <string.h>
+
+void orc_free(void* p) { free(p); }
+
+/* ------------------------------------------------------------------------
+ * Layout graph (Sec. 2.1): one node per feature; a conflict edge joins two
+ * features closer than the minimum coloring distance.  Reading: distance is
+ * the Euclidean gap between the closed boxes, strict "<".  Stitch insertion
+ * (Sec. 2.2; Fig. 1c splits features to break odd cliques) is realised as a
+ * midpoint split of every rectangle longer than split_len: the two halves
+ * are joined by a stitch edge and never by a conflict edge.
+ * ---------------------------------------------------------------------- */
+
+static int64_t gap2(const orc_rect* a, const orc_rect* b) {
+  int64_t gx = 0, gy = 0;
+  if ((int64_t)b->x0 - a->x1 > gx) gx = (int64_t)b->x0 - a->x1;
+  if ((int64_t)a->x0 - b->x1 > gx) gx = (int64_t)a->x0 - b->x1;
+  if ((int64_t)b->y0 - a->y1 > gy) gy = (int64_t)b->y0 - a->y1;
+  if ((int64_t)a->y0 - b->y1 > gy) gy = (int64_t)a->y0 - b->y1;
+  return gx * gx + gy * gy;
+}
+
+static const orc_rect* g_sort_nodes; /* qsort context (single-threaded use) */
+
+static int cmp_by_x0(const void* pa, const void* pb) {
+  int32_t a = *(const int32_t*)pa, b = *(const int32_t*)pb;
+  if (g_sort_nodes[a].x0 != g_sort_nodes[b].x0)
+    return g_sort_nodes[a].x0 < g_sort_nodes[b].x0 ? -1 : 1;
+  return a < b ? -1 : (a > b);
+}
+
+static int cmp_pair(const void* pa, const void* pb) {
+  const int32_t* a = (const int32_t*)pa;
+  const int32_t* b = (const int32_t*)pb;
+  if (a[0] != b[0]) return a[0] < b[0] ? -1 : 1;
+  return a[1] < b[1] ? -1 : (a[1] > b[1]);
+}
+
+static int cmp_i32(const void* pa, const void* pb) {
+  int32_t a = *(const int32_t*)pa, b = *(const int32_t*)pb;
+  return a < b ? -1 : (a > b);
+}
+
+int32_t orc_build_graph(const orc_rect* rects, int32_t n, int32_t dmin,
+                        int32_t split_len, int32_t* num_nodes,
+                        int64_t* num_ce, int32_t** ce, int64_t* num_se,
+                        int32_t** se) {
+  if (n < 0 || dmin < 0 || split_len < 0 || (n > 0 && !rects)) return -1;
+  /* 1. nodes, with the midpoint split */
+  orc_rect* nodes = (orc_rect*)malloc(sizeof(orc_rect) * 2 * (size_t)(n + 1));
+  int32_t* partner = (int32_t*)malloc(sizeof(int32_t) * 2 * (size_t)(n + 1));
+  int32_t* sep = (int32_t*)malloc(sizeof(int32_t) * 2 * (size_t)(n + 1));
+  if (!nodes || !partner || !sep) { free(nodes); free(partner); free(sep); return -2; }
+  int32_t nn = 0;
+  int64_t ns = 0;
+  for (int32_t i = 0; i < n; ++i) {
+    orc_rect r = rects[i];
+    int32_t w = r.x1 - r.x0, h = r.y1 - r.y0;
+    int32_t len = w > h ? w : h;
+    if (split_len > 0 && len > split_len) {
+      orc_rect a = r, b = r;
+      if (w >= h) { a.x1 = r.x0 + len / 2; b.x0 = a.x1; }   /* left half first */
+      else        { a.y1 = r.y0 + len / 2; b.y0 = a.y1; }   /* lower half first */
+      nodes[nn] = a; partner[nn] = nn + 1;
+      nodes[nn + 1] = b; partner[nn + 1] = nn;
+      sep[2 * ns] = nn; sep[2 * ns + 1] = nn + 1; ++ns;
+      nn += 2;
+    } else {
+      nodes[nn] = r; partner[nn] = -1; ++nn;
+    }
+  }
+  /* 2. conflict edges: sweep over nodes sorted by x0.  For x0_i <= x0_j the
+   * horizontal gap is max(0, x0_j - x1_i); once it reaches dmin no later
+   * node in the order can be closer than dmin. */
+  int32_t* order = (int32_t*)malloc(sizeof(int32_t) * (size_t)(nn + 1));
+  int64_t cap = 1024, m = 0;
+  int32_t* e = (int32_t*)malloc(sizeof(int32_t) * 2 * (size_t)cap);
+  if (!order || !e) { free(nodes); free(partner); free(sep); free(order); free(e); return -2; }
+  for (int32_t i = 0; i < nn; ++i) order[i] = i;
+  g_sort_nodes = nodes;
+  qsort(order, (size_t)nn, sizeof(int32_t), cmp_by_x0);
+  const int64_t d2 = (int64_t)dmin * dmin;
+  for (int32_t a = 0; a < nn; ++a) {
+    const int32_t i = order[a];
+    for (int32_t b = a + 1; b < nn; ++b) {
+      const int32_t j = order[b];
+      if ((int64_t)nodes[j].x0 - nodes[i].x1 >= dmin) break;
+      if (partner[i] == j) continue;              /* stitch pair: no conflict */
+      if (gap2(&nodes[i], &nodes[j]) >= d2) continue;
+      if (m == cap) {
+        cap *= 2;
+        int32_t* ne = (int32_t*)realloc(e, sizeof(int32_t) * 2 * (size_t)cap);
+        if (!ne) { free(nodes); free(partner); free(sep); free(order); free(e); return -2; }
+        e = ne;
+      }
+      e[2 * m] = i < j ? i : j;
+      e[2 * m + 1] = i < j ? j : i;
+      ++m;
+    }
+  }
+  qsort(e, (size_t)m, 2 * sizeof(int32_t), cmp_pair);
+  free(nodes); free(partner); free(order);
+  *num_nodes = nn;
+  *num_ce = m;
+  *ce = e;
+  *num_se = ns;
+  *se = sep;
+  return 0;
+}
+
+/* ------------------------------------------------------------------------
+ * Exact-cover matrix (Sec. 2.3, Fig. 3 caption): one row per (node, color),
+ * one primary column per node (each node gets exactly one color) and one
+ * secondary column per (conflict edge, color) (two ends of a conflict edge
+ * may not share a color: at most one 1 chosen per secondary column).  A set
+ * of rows with exactly one 1 in every primary column and at most one in
+ * every secondary column is a proper k-coloring of the no-stitch graph.
+ * ---------------------------------------------------------------------- */
+
+typedef struct {
+  int32_t n, k;
+  int64_t m;
+  int32_t* edges;      /* sorted local pairs (u < w) */
+  int64_t* inc_ptr;    /* incident edge ids per node, ascending */
+  int32_t* inc;
+} orc_comp_graph;
+
+static int32_t make_comp_graph(int32_t n, int64_t m, const int32_t* edges,
+                               int32_t k, orc_comp_graph* g) {
+  g->n = n; g->k = k; g->m = m;
+  g->edges = (int32_t*)malloc(sizeof(int32_t) * 2 * (size_t)(m + 1));
+  g->inc_ptr = (int64_t*)calloc((size_t)n + 1, sizeof(int64_t));
+  g->inc = (int32_t*)malloc(sizeof(int32_t) * 2 * (size_t)(m + 1));
+  if (!g->edges || !g->inc_ptr || !g->inc) return -2;
+  for (int64_t i = 0; i < m; ++i) {
+    int32_t u = edges[2 * i], w = edges[2 * i + 1];
+    if (u < 0 || w < 0 || u >= n || w >= n || u == w) return -1;
+    g->edges[2 * i] = u < w ? u : w;
+    g->edges[2 * i + 1] = u < w ? w : u;
+  }
+  qsort(g->edges, (size_t)m, 2 * sizeof(int32_t), cmp_pair);
+  for (int64_t i = 1; i < m; ++i)
+    if (g->edges[2 * i] == g->edges[2 * i - 2] && g->edges[2 * i + 1] == g->edges[2 * i - 1])
+      return -1; /* duplicate edge */
+  for (int64_t i = 0; i < m; ++i) {
+    g->inc_ptr[g->edges[2 * i] + 1]++;
+    g->inc_ptr[g->edges[2 * i + 1] + 1]++;
+  }
+  for (int32_t v = 0; v < n; ++v) g->inc_ptr[v + 1] += g->inc_ptr[v];
+  int64_t* fill = (int64_t*)malloc(sizeof(int64_t) * ((size_t)n + 1));
+  if (!fill) return -2;
+  memcpy(fill, g->inc_ptr, sizeof(int64_t) * ((size_t)n + 1));
+  for (int64_t i = 0; i < m; ++i) {   /* edge ids ascending per node */
+    g->inc[fill[g->edges[2 * i]]++] = (int32_t)i;
+    g->inc[fill[g->edges[2 * i + 1]]++] = (int32_t)i;
+  }
+  free(fill);
+  return 0;
+}
+
+static void free_comp_graph(orc_comp_graph* g) {
+  free(g->edges); free(g->inc_ptr); free(g->inc);
+}
+
+int32_t orc_ec_matrix(int32_t n, int64_t m, const int32_t* edges, int32_t k,
+                      int64_t** row_ptr, int32_t** col_idx) {
+  if (n < 0 || m < 0 || k < 1) return -1;
+  orc_comp_graph g;
+  int32_t rc = make_comp_graph(n, m, edges, k, &g);
+  if (rc) { free_comp_graph(&g); return rc; }
+  const int64_t rows = (int64_t)n * k;
+  int64_t* rp = (int64_t*)malloc(sizeof(int64_t) * (size_t)(rows + 1));
+  int32_t* ci = (int32_t*)malloc(sizeof(int32_t) * (size_t)(rows + 2 * m * k + 1));
+  if (!rp || !ci) { free(rp); free(ci); free_comp_graph(&g); return -2; }
+  int64_t p = 0;
+  for (int32_t v = 0; v < n; ++v)
+    for (int32_t c = 0; c < k; ++c) {
+      rp[(int64_t)v * k + c] = p;
+      ci[p++] = v;
+      for (int64_t t = g.inc_ptr[v]; t < g.inc_ptr[v + 1]; ++t)
+        ci[p++] = n + g.inc[t] * k + c;
+    }
+  rp[rows] = p;
+  free_comp_graph(&g);
+  *row_ptr = rp;
+  *col_idx = ci;
+  return 0;
+}
+
+/* ------------------------------------------------------------------------
+ * Dancing links (Knuth) on the exact-cover matrix.  Node 0 is the root;
+ * nodes 1..C are column headers (column j -> header j+1); primary headers
+ * sit on the root's horizontal ring in index order, secondary headers are
+ * self-linked.  Each 1 of the matrix is a node linked into its row
+ * (horizontal ring) and its column (vertical ring, rows in ascending order).
+ * Cover/uncover are Eq. 2 applied to the header and to every node of every
+ * row in the column.
+ * ---------------------------------------------------------------------- */
+
+typedef struct {
+  int32_t *L, *R, *U, *D, *col, *row;
+  int32_t* size;
+  int32_t nprim;
+  /* search state */
+  int64_t budget, nodes;
+  uint64_t hash;
+  int32_t status; /* -1 while running */
+  int32_t depth_at_stop;
+  int32_t* sol;   /* row chosen at each depth */
+} orc_dlx;
+
+static void dlx_cover(orc_dlx* x, int32_t c) {
+  x->L[x->R[c]] = x->L[c];
+  x->R[x->L[c]] = x->R[c];
+  for (int32_t i = x->D[c]; i != c; i = x->D[i])
+    for (int32_t j = x->R[i]; j != i; j = x->R[j]) {
+      x->U[x->D[j]] = x->U[j];
+      x->D[x->U[j]] = x->D[j];
+      x->size[x->col[j]]--;
+    }
+}
+
+static void dlx_uncover(orc_dlx* x, int32_t c) {
+  for (int32_t i = x->U[c]; i != c; i = x->U[i])
+    for (int32_t j = x->L[i]; j != i; j = x->L[j]) {
+      x->size[x->col[j]]++;
+      x->U[x->D[j]] = j;
+      x->D[x->U[j]] = j;
+    }
+  x->L[x->R[c]] = c;
+  x->R[x->L[c]] = c;
+}
+
+/* Trace hash: FNV-1a 64 (Fowler/Noll/Vo) over the 16 bytes of each counted
+ * search node: depth, entering row, chosen column, its size; each u32
+ * little-endian (entering row 0xFFFFFFFF at the root, column 0xFFFFFFFF at a
+ * solution). */
+static uint64_t fnv_u32(uint64_t h, uint32_t v) {
+  for (int b = 0; b < 4; ++b) {
+    h ^= (v >> (8 * b)) & 0xffu;
+    h *= 0x100000001b3ULL;
+  }
+  return h;
+}
+
+static void trace_node(orc_dlx* x, uint32_t depth, uint32_t row_in, uint32_t col,
+                       uint32_t size) {
+  uint64_t h = x->hash;
+  h = fnv_u32(h, depth);
+  h = fnv_u32(h, row_in);
+  h = fnv_u32(h, col);
+  h = fnv_u32(h, size);
+  x->hash = h;
+}
+
+/* Algorithm X (Algorithm 1): stop when every primary column is covered (the
+ * first solution ends the search); otherwise take the uncovered primary
+ * column with the fewest rows, ties to the lowest index (reading of "a
+ * column with only one related row or in BFS order": the index is the BFS
+ * position), cover it, and try its rows in ascending order - include the
+ * row, cover its other columns, recurse, uncover, exclude - then uncover the
+ * column.  An empty column is a dead end (the hot path reports INFEASIBLE
+ * instead of marking conflict candidates).  A search node is an entry that
+ * passes the budget test; the budget is tested before counting. */
+static void dlx_search(orc_dlx* x, int32_t depth, int32_t row_in) {
+  if (x->nodes == x->budget) {
+    x->status = ORC_BUDGET;
+    x->depth_at_stop = depth;
+    return;
+  }
+  x->nodes++;
+  if (x->R[0] == 0) {
+    trace_node(x, (uint32_t)depth, (uint32_t)row_in, 0xffffffffu, 0);
+    x->status = ORC_FEASIBLE;
+    x->depth_at_stop = depth;
+    return;
+  }
+  int32_t c = x->R[0];
+  for (int32_t j = x->R[c]; j != 0 && x->size[c] > 0; j = x->R[j])
+    if (x->size[j] < x->size[c]) c = j;
+  trace_node(x, (uint32_t)depth, (uint32_t)row_in, (uint32_t)(c - 1),
+             (uint32_t)x->size[c]);
+  if (x->size[c] == 0) return;
+  dlx_cover(x, c);
+  for (int32_t r = x->D[c]; r != c; r = x->D[r]) {
+    x->sol[depth] = x->row[r];
+    for (int32_t j = x->R[r]; j != r; j = x->R[j]) dlx_cover(x, x->col[j]);
+    dlx_search(x, depth + 1, x->row[r]);
+    if (x->status >= 0) return;
+    for (int32_t j = x->L[r]; j != r; j = x->L[j]) dlx_uncover(x, x->col[j]);
+  }
+  dlx_uncover(x, c);
+}
+
+int32_t orc_solve_component(int32_t n, int64_t m, const int32_t* edges,
+                            int32_t k, int64_t budget, int8_t* colors,
+                            int32_t* status, int64_t* nodes,
+                            uint64_t* trace_hash, int32_t* depth_at_stop) {
+  if (n < 0 || m < 0 || k < 1 || k > 127 || budget < 1) return -1;
+  if (m > 0 && !edges) return -1;
+  orc_comp_graph g;
+  int32_t rc = make_comp_graph(n, m, edges, k, &g);
+  if (rc) { free_comp_graph(&g); return rc; }
+  int64_t* rp = NULL;
+  int32_t* ci = NULL;
+  rc = orc_ec_matrix(n, m, g.edges, k, &rp, &ci);
+  if (rc) { free_comp_graph(&g); return rc; }
+  const int32_t ncols = (int32_t)(n + m * k);
+  const int64_t rows = (int64_t)n * k;
+  const int64_t ones = rp[rows];
+  const int64_t total = 1 + (int64_t)ncols + ones;
+  orc_dlx x;
+  memset(&x, 0, sizeof(x));
+  x.L = (int32_t*)malloc(sizeof(int32_t) * (size_t)total);
+  x.R = (int32_t*)malloc(sizeof(int32_t) * (size_t)total);
+  x.U = (int32_t*)malloc(sizeof(int32_t) * (size_t)total);
+  x.D = (int32_t*)malloc(sizeof(int32_t) * (size_t)total);
+  x.col = (int32_t*)malloc(sizeof(int32_t) * (size_t)total);
+  x.row = (int32_t*)malloc(sizeof(int32_t) * (size_t)total);
+  x.size = (int32_t*)calloc((size_t)total, sizeof(int32_t));
+  x.sol = (int32_t*)malloc(sizeof(int32_t) * ((size_t)n + 1));
+  if (!x.L || !x.R || !x.U || !x.D || !x.col || !x.row || !x.size || !x.sol) {
+    rc = -2;
+    goto done;
+  }
+  /* root and headers */
+  for (int32_t h = 0; h <= ncols; ++h) {
+    x.U[h] = x.D[h] = h;
+    x.col[h] = h;
+    x.row[h] = -1;
+    x.L[h] = x.R[h] = h;
+  }
+  x.nprim = n;
+  for (int32_t h = 1; h <= n; ++h) {  /* primary ring: root, 1, 2, ..., n */
+    x.L[h] = h - 1;
+    x.R[h - 1] = h;
+  }
+  if (n > 0) { x.R[n] = 0; x.L[0] = n; }
+  /* rows, ascending */
+  int32_t next = ncols + 1;
+  for (int64_t r = 0; r < rows; ++r) {
+    int32_t first = -1;
+    for (int64_t p = rp[r]; p < rp[r + 1]; ++p) {
+      const int32_t h = ci[p] + 1;
+      const int32_t nd = next++;
+      x.col[nd] = h;
+      x.row[nd] = (int32_t)r;
+      x.U[nd] = x.U[h]; x.D[nd] = h;
+      x.D[x.U[h]] = nd; x.U[h] = nd;
+      x.size[h]++;
+      if (first < 0) { first = nd; x.L[nd] = x.R[nd] = nd; }
+      else { x.L[nd] = x.L[first]; x.R[nd] = first; x.R[x.L[first]] = nd; x.L[first] = nd; }
+    }
+  }
+  x.budget = budget;
+  x.nodes = 0;
+  x.hash = 0xcbf29ce484222325ULL;
+  x.status = -1;
+  x.depth_at_stop = 0;
+  dlx_search(&x, 0, -1);
+  if (x.status < 0) x.status = ORC_INFEASIBLE;
+  for (int32_t v = 0; v < n; ++v) colors[v] = -1;
+  if (x.status == ORC_FEASIBLE)
+    for (int32_t d = 0; d < x.depth_at_stop; ++d)
+      colors[x.sol[d] / k] = (int8_t)(x.sol[d] % k);
+  *status = x.status;
+  *nodes = x.nodes;
+  *trace_hash = x.hash;
+  if (depth_at_stop) *depth_at_stop = x.status == ORC_INFEASIBLE ? 0 : x.depth_at_stop;
+  rc = 0;
+done:
+  free(x.L); free(x.R); free(x.U); free(x.D); free(x.col); free(x.row);
+  free(x.size); free(x.sol);
+  free(rp); free(ci);
+  free_comp_graph(&g);
+  return rc;
+}
+
+/* ------------------------------------------------------------------------
+ * Whole flow (Sec. 2.2).
+ * Simplification reading: iterative removal of nodes with conflict degree
+ * < k, first-in first-out - seed the queue with every such node in
+ * ascending id, then pop a node, remove it, lower its remaining
+ * neighbours' degrees in ascending id and queue each one that drops below
+ * k.  The removal order is kept for recovery.
+ * Sub-graphs (Algorithm 1): connected components of the remaining nodes
+ * over conflict edges, ordered by smallest id; local index = BFS order from
+ * that node, neighbours in ascending id.
+ * Recovery reading: in reverse removal order a node takes its stitch
+ * partner's color when the partner is colored and no colored conflict
+ * neighbour uses it, else the lowest color no colored conflict neighbour
+ * uses.
+ * ---------------------------------------------------------------------- */
+
+/* Adjacency lists (ascending) and stitch partners; validates the input. */
+static int32_t build_adjacency(int32_t n, int64_t num_ce, const int32_t* ce,
+                               int64_t num_se, const int32_t* se, int64_t* ap,
+                               int32_t* adj, int32_t* partner) {
+  for (int32_t v = 0; v <= n; ++v) ap[v] = 0;
+  for (int64_t i = 0; i < num_ce; ++i) {
+    int32_t u = ce[2 * i], v = ce[2 * i + 1];
+    if (u < 0 || v < 0 || u >= n || v >= n || u == v) return -1;
+    ap[u + 1]++; ap[v + 1]++;
+  }
+  for (int32_t v = 0; v < n; ++v) ap[v + 1] += ap[v];
+  int64_t* fill = (int64_t*)malloc(sizeof(int64_t) * ((size_t)n + 1));
+  if (!fill) return -2;
+  memcpy(fill, ap, sizeof(int64_t) * ((size_t)n + 1));
+  for (int64_t i = 0; i < num_ce; ++i) {
+    adj[fill[ce[2 * i]]++] = ce[2 * i + 1];
+    adj[fill[ce[2 * i + 1]]++] = ce[2 * i];
+  }
+  free(fill);
+  for (int32_t v = 0; v < n; ++v) {
+    qsort(adj + ap[v], (size_t)(ap[v + 1] - ap[v]), sizeof(int32_t), cmp_i32);
+    for (int64_t t = ap[v] + 1; t < ap[v + 1]; ++t)
+      if (adj[t] == adj[t - 1]) return -1;   /* duplicate edge */
+    partner[v] = -1;
+  }
+  for (int64_t i = 0; i < num_se; ++i) {
+    int32_t u = se[2 * i], v = se[2 * i + 1];
+    if (u < 0 || v < 0 || u >= n || v >= n || u == v) return -1;
+    if (partner[u] >= 0 || partner[v] >= 0) return -1;  /* one partner per node */
+    partner[u] = v; partner[v] = u;
+  }
+  for (int64_t i = 0; i < num_se; ++i) {           /* a stitch pair is no conflict pair */
+    int32_t u = se[2 * i], v = se[2 * i + 1];
+    for (int64_t t = ap[u]; t < ap[u + 1]; ++t)
+      if (adj[t] == v) return -1;
+  }
+  return 0;
+}
+
+/* Simplification and sub-graphs.  removal[0 .. *nrem-1] = removal order;
+ * comp_of[v] = component or -1; bfs = core nodes grouped by component, each
+ * in local (BFS) order; comp_ptr[c] .. comp_ptr[c+1] delimits component c. */
+static int32_t simplify_split(int32_t n, const int64_t* ap, const int32_t* adj,
+                              int32_t k, uint32_t flags, int32_t* removal,
+                              int32_t* nrem_out, int32_t* comp_of, int32_t* bfs,
+                              int32_t* comp_ptr, int32_t* nc_out) {
+  int32_t* deg = (int32_t*)malloc(sizeof(int32_t) * ((size_t)n + 1));
+  char* removed = (char*)calloc((size_t)n + 1, 1);
+  char* queued = (char*)calloc((size_t)n + 1, 1);
+  if (!deg || !removed || !queued) { free(deg); free(removed); free(queued); return -2; }
+  for (int32_t v = 0; v < n; ++v) deg[v] = (int32_t)(ap[v + 1] - ap[v]);
+  int32_t head = 0, tail = 0;
+  if (flags & ORC_SIMPLIFY) {
+    for (int32_t v = 0; v < n; ++v)
+      if (deg[v] < k) { removal[tail++] = v; queued[v] = 1; }
+    while (head < tail) {
+      const int32_t u = removal[head++];
+      removed[u] = 1;
+      for (int64_t t = ap[u]; t < ap[u + 1]; ++t) {
+        const int32_t w = adj[t];
+        if (removed[w]) continue;
+        deg[w]--;
+        if (deg[w] < k && !queued[w]) { removal[tail++] = w; queued[w] = 1; }
+      }
+    }
+  }
+  *nrem_out = tail;
+  int32_t nc = 0, pos = 0;
+  for (int32_t v = 0; v < n; ++v) comp_of[v] = -1;
+  comp_ptr[0] = 0;
+  for (int32_t s = 0; s < n; ++s) {
+    if (removed[s] || comp_of[s] >= 0) continue;
+    int32_t h = pos;
+    bfs[pos++] = s;
+    comp_of[s] = nc;
+    while (h < pos) {
+      const int32_t x = bfs[h++];
+      for (int64_t t = ap[x]; t < ap[x + 1]; ++t) {
+        const int32_t w = adj[t];
+        if (removed[w] || comp_of[w] >= 0) continue;
+        comp_of[w] = nc;
+        bfs[pos++] = w;
+      }
+    }
+    comp_ptr[++nc] = pos;
+  }
+  *nc_out = nc;
+  free(deg); free(removed); free(queued);
+  return 0;
+}
+
+int32_t orc_simplify(int32_t num_nodes, int64_t num_ce, const int32_t* ce,
+                     int32_t k, uint32_t flags, int32_t* removal_order,
+                     int32_t* num_removed, int32_t* comp_of, int32_t* bfs_order,
+                     int32_t* comp_ptr, int32_t* num_comps) {
+  if (num_nodes < 0 || num_ce < 0 || k < 1) return -1;
+  const int32_t n = num_nodes;
+  int64_t* ap = (int64_t*)malloc(sizeof(int64_t) * ((size_t)n + 1));
+  int32_t* adj = (int32_t*)malloc(sizeof(int32_t) * 2 * (size_t)(num_ce + 1));
+  int32_t* partner = (int32_t*)malloc(sizeof(int32_t) * ((size_t)n + 1));
+  int32_t rc = -2;
+  if (ap && adj && partner) {
+    rc = build_adjacency(n, num_ce, ce, 0, NULL, ap, adj, partner);
+    if (!rc)
+      rc = simplify_split(n, ap, adj, k, flags, removal_order, num_removed,
+                          comp_of, bfs_order, comp_ptr, num_comps);
+  }
+  free(ap); free(adj); free(partner);
+  return rc;
+}
+
+int32_t orc_decompose(int32_t num_nodes, int64_t num_ce, const int32_t* ce,
+                      int64_t num_se, const int32_t* se, int32_t k,
+                      int64_t budget, uint32_t flags, int8_t* colors,
+                      int32_t* comp_of, int32_t* num_comps, orc_comp** comps,
+                      int64_t* total_stitches, int64_t* total_conflicts,
+                      int64_t* total_uncolored) {
+  if (num_nodes < 0 || num_ce < 0 || num_se < 0 || k < 1 || k > 64 || budget < 1)
+    return -1;
+  const int32_t n = num_nodes;
+  int32_t rc = 0;
+  int64_t* ap = (int64_t*)malloc(sizeof(int64_t) * ((size_t)n + 1));
+  int32_t* adj = (int32_t*)malloc(sizeof(int32_t) * 2 * (size_t)(num_ce + 1));
+  int32_t* partner = (int32_t*)malloc(sizeof(int32_t) * ((size_t)n + 1));
+  int32_t* removal = (int32_t*)malloc(sizeof(int32_t) * ((size_t)n + 1));
+  int32_t* bfs = (int32_t*)malloc(sizeof(int32_t) * ((size_t)n + 1));
+  int32_t* comp_ptr = (int32_t*)malloc(sizeof(int32_t) * ((size_t)n + 2));
+  int32_t* local = (int32_t*)malloc(sizeof(int32_t) * ((size_t)n + 1));
+  int32_t* ledges = (int32_t*)malloc(sizeof(int32_t) * 2 * (size_t)(num_ce + 1));
+  int8_t* lcolors = (int8_t*)malloc((size_t)n + 1);
+  orc_comp* cs = NULL;
+  int32_t nrem = 0, nc = 0;
+  if (!ap || !adj || !partner || !removal || !bfs || !comp_ptr || !local ||
+      !ledges || !lcolors) { rc = -2; goto out; }
+  rc = build_adjacency(n, num_ce, ce, num_se, se, ap, adj, partner);
+  if (rc) goto out;
+  rc = simplify_split(n, ap, adj, k, flags, removal, &nrem, comp_of, bfs,
+                      comp_ptr, &nc);
+  if (rc) goto out;
+  cs = (orc_comp*)malloc(sizeof(orc_comp) * ((size_t)nc + 1));
+  if (!cs) { rc = -2; goto out; }
+
+  /* solve every sub-graph in its local numbering */
+  for (int32_t v = 0; v < n; ++v) { colors[v] = -1; local[v] = -1; }
+  for (int32_t c = 0; c < nc; ++c) {
+    const int32_t* nodes = bfs + comp_ptr[c];
+    const int32_t size = comp_ptr[c + 1] - comp_ptr[c];
+    for (int32_t i = 0; i < size; ++i) local[nodes[i]] = i;
+    int64_t lm = 0;
+    for (int32_t i = 0; i < size; ++i) {
+      const int32_t x = nodes[i];
+      for (int64_t t = ap[x]; t < ap[x + 1]; ++t) {
+        const int32_t w = adj[t];
+        if (comp_of[w] != c || local[w] <= i) continue;
+        ledges[2 * lm] = i;
+        ledges[2 * lm + 1] = local[w];
+        ++lm;
+      }
+    }
+    orc_comp* r = &cs[c];
+    r->size = size;
+    r->first_node = nodes[0];
+    r->num_edges = (int32_t)lm;
+    rc = orc_solve_component(size, lm, ledges, k, budget, lcolors, &r->status,
+                             &r->nodes, &r->trace_hash, &r->depth_at_stop);
+    if (rc) goto out;
+    for (int32_t i = 0; i < size; ++i) colors[nodes[i]] = lcolors[i];
+    r->stitches = 0;
+    for (int32_t i = 0; i < size; ++i) {
+      const int32_t x = nodes[i], p = partner[x];
+      if (p > x && comp_of[p] == c && colors[p] != colors[x]) r->stitches++;
+    }
+    if (r->status != ORC_FEASIBLE) r->stitches = -1;
+  }
+
+  /* recovery, reverse removal order */
+  for (int32_t i = nrem - 1; i >= 0; --i) {
+    const int32_t x = removal[i];
+    uint64_t used = 0;
+    for (int64_t t = ap[x]; t < ap[x + 1]; ++t)
+      if (colors[adj[t]] >= 0) used |= 1ULL << colors[adj[t]];
+    const int32_t p = partner[x];
+    if (p >= 0 && colors[p] >= 0 && !((used >> colors[p]) & 1)) {
+      colors[x] = colors[p];
+    } else {
+      int32_t c = 0;
+      while (c < k && ((used >> c) & 1)) ++c;
+      if (c == k) { rc = -6; goto out; }   /* impossible: degree < k at removal */
+      colors[x] = (int8_t)c;
+    }
+  }
+
+  /* Eq. 1 tallies: stitches = stitch pairs colored differently, conflicts =
+   * conflict pairs colored alike (uncolored nodes take part in neither) */
+  {
+    int64_t st = 0, cn = 0, un = 0;
+    for (int32_t v = 0; v < n; ++v) {
+      if (colors[v] < 0) ++un;
+      if (partner[v] > v && colors[v] >= 0 && colors[partner[v]] >= 0 &&
+          colors[v] != colors[partner[v]])
+        ++st;
+    }
+    for (int64_t i = 0; i < num_ce; ++i) {
+      const int8_t a = colors[ce[2 * i]], b = colors[ce[2 * i + 1]];
+      if (a >= 0 && a == b) ++cn;
+    }
+    if (total_stitches) *total_stitches = st;
+    if (total_conflicts) *total_conflicts = cn;
+    if (total_uncolored) *total_uncolored = un;
+  }
+  *num_comps = nc;
+  *comps = cs;
+  cs = NULL;
+out:
+  free(ap); free(adj); free(partner); free(removal); free(bfs); free(comp_ptr);
+  free(local); free(ledges); free(lcolors); free(cs);
+  return rc;
+}
+
+/* ------------------------------------------------------------------------
+ * Many components on several host threads (timing only; per component the
+ * result is orc_solve_component's).
+ * ---------------------------------------------------------------------- */
+
+typedef struct {
+  int32_t count, k;
+  int64_t budget;
+  const int32_t* sizes;
+  const int64_t* edge_off;
+  const int64_t* node_off;
+  const int32_t* edges;
+  int8_t* colors;
+  int32_t* status;
+  int64_t* nodes;
+  uint64_t* hash;
+  int32_t next;          /* next component to take (guarded by mu) */
+  int32_t err;
+  pthread_mutex_t mu;
+} orc_pool;
+
+static void* pool_worker(void* arg) {
+  orc_pool* p = (orc_pool*)arg;
+  for (;;) {
+    pthread_mutex_lock(&p->mu);
+    const int32_t i = p->next++;
+    pthread_mutex_unlock(&p->mu);
+    if (i >= p->count) break;
+    const int64_t m = p->edge_off[i + 1] - p->edge_off[i];
+    int32_t rc = orc_solve_component(p->sizes[i], m, p->edges + 2 * p->edge_off[i],
+                                     p->k, p->budget, p->colors + p->node_off[i],
+                                     &p->status[i], &p->nodes[i], &p->hash[i], NULL);
+    if (rc) {
+      pthread_mutex_lock(&p->mu);
+      p->err = rc;
+      pthread_mutex_unlock(&p->mu);
+    }
+  }
+  return NULL;
+}
+
+int32_t orc_solve_many(int32_t count, const int32_t* sizes,
+                       const int64_t* edge_counts, const int32_t* edges,
+                       int32_t k, int64_t budget, int32_t threads,
+                       int8_t* colors, int32_t* status, int64_t* nodes,
+                       uint64_t* trace_hash) {
+  if (count < 0 || threads < 1) return -1;
+  int64_t* eo = (int64_t*)malloc(sizeof(int64_t) * ((size_t)count + 1));
+  int64_t* no = (int64_t*)malloc(sizeof(int64_t) * ((size_t)count + 1));
+  pthread_t* th = (pthread_t*)malloc(sizeof(pthread_t) * (size_t)threads);
+  if (!eo || !no || !th) { free(eo); free(no); free(th); return -2; }
+  eo[0] = 0; no[0] = 0;
+  for (int32_t i = 0; i < count; ++i) {
+    eo[i + 1] = eo[i] + edge_counts[i];
+    no[i + 1] = no[i] + sizes[i];
+  }
+  orc_pool p = {count, k, budget, sizes, eo, no, edges, colors, status, nodes,
+                trace_hash, 0, 0, PTHREAD_MUTEX_INITIALIZER};
+  int32_t started = 0;
+  for (int32_t t = 0; t < threads; ++t)
+    if (pthread_create(&th[t], NULL, pool_worker, &p) == 0) ++started;
+  if (started == 0) pool_worker(&p);
+  for (int32_t t = 0; t < started; ++t) pthread_join(th[t], NULL);
+  free(eo); free(no); free(th);
+  return p.err;
+}

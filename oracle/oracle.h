@@ -1,0 +1,104 @@
+/*
+ * oracle.h - plain, slow, single-threaded CPU reference of the exact-cover
+ * layout decomposition path.  TEST INFRASTRUCTURE ONLY: it is linked by the
+ * tests and by the benchmark's CPU-baseline leg, never by the product
+ * library, and it shares no code with it.
+ *
+ * Everything is integer arithmetic.  Each function cites the passage of the
+ * paper it follows ("GPU-Accelerated Matrix Cover Algorithm for Multiple
+ * Patterning Layout Decomposition", Chen, Yang, Yu, 2023):
+ *   - Sec. 2.1: layout graph G = (V, CE u SE), colors x_i, conflicts and
+ *     stitches (Eq. 1).
+ *   - Sec. 2.2: flow - layout graph, simplification with stitch insertion,
+ *     coloring solver, recovery of removed nodes.
+ *   - Sec. 2.3: exact-cover matrix of the no-stitch graph, dancing-links
+ *     cover/uncover (Eq. 2), Algorithm 1 (sub-graphs, column choice, row
+ *     loop, first solution ends the search).
+ * Where the paper is silent the readings used are stated at each function.
+ */
+#ifndef MPLD_ORACLE_H
+#define MPLD_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { ORC_FEASIBLE = 0, ORC_INFEASIBLE = 1, ORC_BUDGET = 2 };
+enum { ORC_SIMPLIFY = 1 };
+
+typedef struct { int32_t x0, y0, x1, y1; } orc_rect;
+
+/* Per component record of the pipeline. */
+typedef struct {
+  int32_t size;          /* nodes in the component                     */
+  int32_t status;        /* ORC_FEASIBLE / ORC_INFEASIBLE / ORC_BUDGET */
+  int64_t nodes;         /* search nodes counted                       */
+  uint64_t trace_hash;   /* FNV-1a 64 over the node trace              */
+  int32_t depth_at_stop; /* rows in the partial solution at the stop   */
+  int32_t stitches;      /* SE pairs inside, colored differently; -1 unless feasible */
+  int32_t first_node;    /* smallest original node id                  */
+  int32_t num_edges;     /* conflict edges inside                      */
+} orc_comp;
+
+/* Builds the node list and conflict/stitch edges of a rectangle layout.
+ * split_len > 0 splits every rectangle whose long side exceeds split_len at
+ * floor(L/2) into two nodes (lower/left first) joined by a stitch edge.
+ * Conflict edge iff the Euclidean gap of the closed boxes is < dmin.
+ * Outputs are malloc'ed (free with orc_free): ce and se hold pairs (u < v),
+ * ce sorted lexicographically.  Returns 0 or negative on error. */
+int32_t orc_build_graph(const orc_rect* rects, int32_t n, int32_t dmin,
+                        int32_t split_len, int32_t* num_nodes,
+                        int64_t* num_ce, int32_t** ce, int64_t* num_se,
+                        int32_t** se);
+
+/* Full decomposition of a graph.  colors (num_nodes, -1 = uncolored) and
+ * comp_of (num_nodes, -1 = removed by simplification) are caller-allocated;
+ * *comps is malloc'ed (free with orc_free).  Totals may be NULL. */
+int32_t orc_decompose(int32_t num_nodes, int64_t num_ce, const int32_t* ce,
+                      int64_t num_se, const int32_t* se, int32_t k,
+                      int64_t budget, uint32_t flags, int8_t* colors,
+                      int32_t* comp_of, int32_t* num_comps, orc_comp** comps,
+                      int64_t* total_stitches, int64_t* total_conflicts,
+                      int64_t* total_uncolored);
+
+/* Simplification and sub-graph split only (no search), for inspection:
+ * removal_order (num_nodes), comp_of (num_nodes), bfs_order (num_nodes; core
+ * nodes grouped by component in local order) and comp_ptr (num_nodes + 1)
+ * are caller-allocated. */
+int32_t orc_simplify(int32_t num_nodes, int64_t num_ce, const int32_t* ce,
+                     int32_t k, uint32_t flags, int32_t* removal_order,
+                     int32_t* num_removed, int32_t* comp_of, int32_t* bfs_order,
+                     int32_t* comp_ptr, int32_t* num_comps);
+
+/* Solves one component given in local numbering (edges are local pairs,
+ * any order, no duplicates).  colors (n) caller-allocated. */
+int32_t orc_solve_component(int32_t n, int64_t m, const int32_t* edges,
+                            int32_t k, int64_t budget, int8_t* colors,
+                            int32_t* status, int64_t* nodes,
+                            uint64_t* trace_hash, int32_t* depth_at_stop);
+
+/* Solves many components (concatenated local edge lists) on `threads`
+ * threads, each component independently with orc_solve_component's
+ * semantics.  Used only to time the oracle on all host cores. */
+int32_t orc_solve_many(int32_t count, const int32_t* sizes,
+                       const int64_t* edge_counts, const int32_t* edges,
+                       int32_t k, int64_t budget, int32_t threads,
+                       int8_t* colors, int32_t* status, int64_t* nodes,
+                       uint64_t* trace_hash);
+
+/* Builds the exact-cover matrix of a component (for inspection in tests):
+ * rows R = n*k, columns C = n + m*k; returns CSR over rows (row_ptr R+1,
+ * col_idx) malloc'ed.  Row r = v*k + c has a 1 in primary column v and in
+ * secondary column n + e*k + c for each local edge e (sorted pairs u < w)
+ * incident to v. */
+int32_t orc_ec_matrix(int32_t n, int64_t m, const int32_t* edges, int32_t k,
+                      int64_t** row_ptr, int32_t** col_idx);
+
+void orc_free(void* p);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

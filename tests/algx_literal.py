@@ -1,0 +1,161 @@
+"""Second, independent implementations used to pin the oracle (tests only).
+
+* ``algx_sets`` - Algorithm X written directly on sets (no linked lists): the
+  matrix is a dict column -> set of rows and a dict row -> list of columns;
+  choosing a row deletes every column the row has a 1 in and every other row
+  that has a 1 in one of those columns.  Same deterministic rules as the
+  oracle (min-size uncovered primary column, lowest index on ties; rows in
+  ascending order; first solution stops; budget tested before counting) and
+  the same node trace hash, so status, node count, hash and colors must
+  agree with the oracle's dancing-links search exactly.
+* ``brute_force_colorable`` - exhaustive k-coloring test for tiny graphs.
+"""
+from __future__ import annotations
+
+import itertools
+
+import numpy as np
+
+FEASIBLE, INFEASIBLE, BUDGET = 0, 1, 2
+_FNV_OFFSET = 0xCBF29CE484222325
+_FNV_PRIME = 0x100000001B3
+_M64 = (1 << 64) - 1
+NONE32 = 0xFFFFFFFF
+
+
+def fnv1a_words(h: int, words) -> int:
+    for w in words:
+        for b in int(w).to_bytes(4, "little"):
+            h ^= b
+            h = (h * _FNV_PRIME) & _M64
+    return h
+
+
+def algx_sets(n: int, edges, k: int, budget: int):
+    edges = sorted((min(u, w), max(u, w)) for u, w in edges)
+    rows = {}
+    for v in range(n):
+        inc = [e for e, (a, b) in enumerate(edges) if v in (a, b)]
+        for c in range(k):
+            rows[v * k + c] = [("p", v)] + [("s", e, c) for e in inc]
+    cols = {}
+    for r, cl in rows.items():
+        for col in cl:
+            cols.setdefault(col, set()).add(r)
+    for v in range(n):
+        cols.setdefault(("p", v), set())
+
+    st = {"nodes": 0, "hash": _FNV_OFFSET, "status": None, "depth": 0}
+    solution = []
+
+    def choose_row(r):
+        """Delete r's columns and every row clashing with r; return undo log."""
+        removed = []
+        for col in rows[r]:
+            for other in cols[col]:
+                for col2 in rows[other]:
+                    if col2 != col:
+                        cols[col2].discard(other)
+            removed.append((col, cols.pop(col)))
+        return removed
+
+    def unchoose_row(r, removed):
+        for col, members in reversed(removed):
+            cols[col] = members
+            for other in members:
+                for col2 in rows[other]:
+                    if col2 != col:
+                        cols[col2].add(other)
+
+    def search(depth, row_in):
+        if st["nodes"] == budget:
+            st["status"] = BUDGET
+            st["depth"] = depth
+            return
+        st["nodes"] += 1
+        open_prim = [v for v in range(n) if ("p", v) in cols]
+        if not open_prim:
+            st["hash"] = fnv1a_words(st["hash"], [depth, row_in, NONE32, 0])
+            st["status"] = FEASIBLE
+            st["depth"] = depth
+            return
+        best = min(open_prim, key=lambda v: (len(cols[("p", v)]), v))
+        size = len(cols[("p", best)])
+        st["hash"] = fnv1a_words(st["hash"], [depth, row_in, best, size])
+        if size == 0:
+            return
+        for r in sorted(cols[("p", best)]):
+            solution.append(r)
+            undo = choose_row(r)
+            search(depth + 1, r)
+            if st["status"] is not None:
+                return
+            unchoose_row(r, undo)
+            solution.pop()
+
+    search(0, NONE32)
+    status = INFEASIBLE if st["status"] is None else st["status"]
+    colors = np.full(n, -1, dtype=np.int8)
+    if status == FEASIBLE:
+        for r in solution:
+            colors[r // k] = r % k
+    depth = 0 if status == INFEASIBLE else st["depth"]
+    return status, st["nodes"], st["hash"], depth, colors
+
+
+def brute_force_colorable(n: int, edges, k: int) -> bool:
+    if n == 0:
+        return True
+    e = np.asarray(list(edges), dtype=np.int64).reshape(-1, 2)
+    if len(e) == 0:
+        return True
+    for chunk in _colorings(n, k):
+        ok = np.all(chunk[:, e[:, 0]] != chunk[:, e[:, 1]], axis=1)
+        if ok.any():
+            return True
+    return False
+
+
+def _colorings(n, k, chunk=1 << 16):
+    it = itertools.product(range(k), repeat=n)
+    while True:
+        block = list(itertools.islice(it, chunk))
+        if not block:
+            return
+        yield np.asarray(block, dtype=np.int8)
+
+
+def random_graph(rng: np.random.Generator, n: int, p: float):
+    return [(i, j) for i in range(n) for j in range(i + 1, n) if rng.random() < p]
+
+
+def complete(n):
+    return [(i, j) for i in range(n) for j in range(i + 1, n)]
+
+
+def cycle(n):
+    return [(i, (i + 1) % n) for i in range(n)]
+
+
+def petersen():
+    outer = [(i, (i + 1) % 5) for i in range(5)]
+    spokes = [(i, i + 5) for i in range(5)]
+    inner = [(5 + i, 5 + (i + 2) % 5) for i in range(5)]
+    return 10, outer + spokes + inner
+
+
+def wheel(rim: int):
+    """Hub 0 joined to a cycle 1..rim."""
+    return rim + 1, [(0, i) for i in range(1, rim + 1)] + [
+        (i, i % rim + 1) for i in range(1, rim + 1)]
+
+
+def grotzsch():
+    """Mycielskian of C5: 11 nodes, triangle-free, chromatic number 4."""
+    c5 = [(i, (i + 1) % 5) for i in range(5)]
+    e = list(c5)
+    for u, v in c5:             # shadow u' = u + 5 joined to N(u)
+        e.append((u + 5, v))
+        e.append((v + 5, u))
+    e += [(10, i + 5) for i in range(5)]
+    return 11, e
