@@ -1,0 +1,232 @@
+/*
+ * mpld.h - C ABI of the MI355X exact-cover layout decomposer.
+ *
+ * What it computes (Chen, Yang, Yu, "GPU-Accelerated Matrix Cover Algorithm
+ * for Multiple Patterning Layout Decomposition", 2023):
+ *   Sec. 2.1  A layout graph G = (V, CE u SE) and a mask count k go in; a
+ *             color x_i in {0..k-1} per node comes out, with the conflict
+ *             count (conflict-edge ends colored alike) and the stitch count
+ *             (stitch-edge ends colored differently) of Eq. 1.
+ *   Sec. 2.2  Flow: layout graph -> simplification (removal of nodes the
+ *             coloring can always extend to) -> sub-graphs -> coloring
+ *             solver -> recovery of the removed nodes.
+ *   Sec. 2.3  The solver is exact cover on the 0/1 matrix with one row per
+ *             (node, color), one primary column per node and one secondary
+ *             column per (conflict edge, color), searched with Algorithm X
+ *             (Algorithm 1); the dancing-links cover/uncover of Eq. 2 is
+ *             replaced by data-parallel bitset operations on the GPU.
+ *
+ * Readings where the paper is silent (all deterministic, so the GPU result
+ * is reproducible bit for bit):
+ *   - simplification: first-in first-out removal of nodes with conflict
+ *     degree < k (queue seeded in ascending id, neighbours visited in
+ *     ascending id); recovery in reverse removal order: the stitch partner's
+ *     color if free, else the lowest color free among colored conflict
+ *     neighbours;
+ *   - sub-graphs: connected components of the remaining nodes, ordered by
+ *     smallest id; local index = BFS order from that node (neighbours in
+ *     ascending id);
+ *   - column choice (Algorithm 1 "only one related row or in BFS order"):
+ *     the uncovered primary column with the fewest rows, lowest local index
+ *     on ties; rows tried in ascending color; the first exact cover ends the
+ *     search; an empty column is a dead end (no conflict-candidate marking);
+ *   - a search node is one entry into the search that passes the budget
+ *     test (budget tested before counting), so nodes <= budget always and
+ *     BUDGET_EXHAUSTED implies nodes == budget;
+ *   - trace hash: FNV-1a 64 over 16 bytes per search node - depth, entering
+ *     row (v*k + c; 0xFFFFFFFF at the root), chosen column (0xFFFFFFFF at a
+ *     solution), its row count - each u32 little-endian.
+ *
+ * Conventions:
+ *   - Return codes are int32: 0 = ok, negative = error (enum below).  No
+ *     C++ exception crosses the ABI.  mpld_last_error() gives a thread-local
+ *     detail string valid until the next call on that thread.
+ *   - Inputs are caller-owned, read-only and copied before return.
+ *   - Outputs (mpld_result, mpld_owned_graph, mpld_batch, mpld_server) are
+ *     library-owned; free them with their *_free call.  Accessors return
+ *     borrowed pointers valid until that free.
+ *   - A context owns one device, one HIP stream and its device memory.  One
+ *     thread per context, or external locking.  After MPLD_E_DEVICE the
+ *     context is unusable and must be destroyed.
+ *   - Every device step is HIP code; there is no host fallback: a missing
+ *     device returns MPLD_E_DEVICE.
+ */
+#ifndef MPLD_H
+#define MPLD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MPLD_ABI_VERSION 1u
+#define MPLD_MAX_K 8
+
+enum {
+  MPLD_OK = 0,
+  MPLD_E_INVALID = -1,     /* bad argument: k, ids, self loop, duplicate, CE n SE, budget */
+  MPLD_E_NOMEM = -2,       /* host or device allocation failed / larger than the arena */
+  MPLD_E_DEVICE = -3,      /* HIP error; the context is unusable */
+  MPLD_E_NOT_READY = -4,   /* serving: ticket not finished yet */
+  MPLD_E_CANCELLED = -5,   /* serving: server shut down before the ticket ran */
+  MPLD_E_INTERNAL = -6,    /* broken invariant (a bug) */
+  MPLD_E_UNSUPPORTED = -7  /* a forced tier cannot take this component */
+};
+
+/* per component status */
+enum { MPLD_FEASIBLE = 0, MPLD_INFEASIBLE = 1, MPLD_BUDGET_EXHAUSTED = 2 };
+
+/* option flags */
+enum {
+  MPLD_SIMPLIFY = 1u << 0,     /* degree < k removal + recovery (default on) */
+  MPLD_TRACE_HASH = 1u << 1,   /* accumulate the per-component trace hash      */
+  MPLD_PLAIN = 1u << 2,        /* one kernel launch per component (comparison) */
+  MPLD_FORCE_WAVE = 1u << 3,   /* force the register tier (n <= 64)           */
+  MPLD_FORCE_LDS = 1u << 4,    /* force the LDS tier                          */
+  MPLD_FORCE_GLOBAL = 1u << 5  /* force the global-memory tier                */
+};
+
+typedef struct { int32_t x0, y0, x1, y1; } mpld_rect;  /* nm, closed box */
+
+/* A layout graph (Sec. 2.1).  ce: num_ce pairs (u, v), 0 <= u, v <
+ * num_nodes, u != v, no duplicate pair in either orientation.  se: num_se
+ * stitch pairs (may be 0 / NULL); each node is in at most one stitch pair
+ * and no stitch pair is also a conflict pair.  Caller-owned. */
+typedef struct {
+  int32_t num_nodes;
+  int32_t reserved;
+  int64_t num_ce;
+  const int32_t* ce;
+  int64_t num_se;
+  const int32_t* se;
+} mpld_graph;
+
+typedef struct {
+  uint32_t struct_size;   /* sizeof(mpld_options)                       */
+  int32_t k;              /* mask count, 2 .. MPLD_MAX_K                */
+  int64_t node_budget;    /* per component, >= 1                        */
+  uint32_t flags;         /* MPLD_* flags                               */
+  int32_t reserved;
+} mpld_options;
+
+/* Per component record (40 bytes). */
+typedef struct {
+  int32_t size;           /* nodes                                          */
+  int32_t status;         /* MPLD_FEASIBLE / MPLD_INFEASIBLE / MPLD_BUDGET_EXHAUSTED */
+  int64_t nodes;          /* search nodes                                   */
+  uint64_t trace_hash;    /* FNV-1a trace hash (0 unless MPLD_TRACE_HASH)   */
+  int32_t depth_at_stop;  /* rows in the partial solution when it stopped (0 if infeasible) */
+  int32_t stitches;       /* stitch pairs inside colored differently; -1 unless feasible */
+  int32_t first_node;     /* smallest original node id                      */
+  int32_t num_edges;      /* conflict edges inside                          */
+} mpld_comp_record;
+
+/* One component given directly in its local numbering (no simplification,
+ * no renumbering): n nodes, m local pairs. */
+typedef struct {
+  int32_t n;
+  int32_t reserved;
+  int64_t m;
+  const int32_t* edges;
+} mpld_component;
+
+/* Optional device allocator (e.g. a framework's caching allocator).  alloc
+ * returns device memory of at least `bytes` bytes aligned to 256, or NULL. */
+typedef struct {
+  void* (*alloc)(size_t bytes, void* user);
+  void (*free)(void* ptr, void* user);
+  void* user;
+} mpld_allocator;
+
+typedef struct mpld_context mpld_context;
+typedef struct mpld_result mpld_result;
+typedef struct mpld_owned_graph mpld_owned_graph;
+typedef struct mpld_batch mpld_batch;
+
+uint32_t mpld_abi_version(void);
+const char* mpld_error_string(int32_t err);   /* static string */
+const char* mpld_last_error(void);            /* thread-local detail */
+
+/* ---- host front-end (Sec. 2.1, 2.2) ------------------------------------
+ * Layout graph of n rectangles: a conflict edge joins two features whose
+ * closed boxes are less than dmin_nm apart (Euclidean gap).  split_len_nm >
+ * 0 splits every rectangle whose long side exceeds it at floor(L/2) into
+ * two consecutive nodes (lower/left first) joined by a stitch edge and
+ * never by a conflict edge.  Conflict pairs come out as (u < v) sorted.
+ * Errors: MPLD_E_INVALID for n < 0, dmin < 0, split < 0, a box with
+ * x1 < x0 or y1 < y0. */
+int32_t mpld_build_graph(const mpld_rect* rects, int32_t n, int32_t dmin_nm,
+                         int32_t split_len_nm, mpld_owned_graph** out);
+/* Borrowed view of an owned graph (valid until mpld_owned_graph_free). */
+int32_t mpld_owned_graph_view(const mpld_owned_graph* g, mpld_graph* view);
+void mpld_owned_graph_free(mpld_owned_graph* g);
+
+/* ---- context ----------------------------------------------------------
+ * device: HIP ordinal.  alloc: NULL = hipMalloc/hipFree.  hip_stream: a
+ * hipStream_t the caller keeps alive (e.g. a framework's current stream),
+ * or NULL for a stream the context creates.  Errors: MPLD_E_DEVICE when no
+ * such device or it is not gfx950. */
+int32_t mpld_context_create(int32_t device, const mpld_allocator* alloc,
+                            void* hip_stream, mpld_context** out);
+int32_t mpld_context_destroy(mpld_context* ctx);
+
+/* ---- one-shot decomposition (Sec. 2.2 flow, synchronous) --------------- */
+int32_t mpld_decompose(mpld_context* ctx, const mpld_graph* g,
+                       const mpld_options* opt, mpld_result** out);
+
+/* ---- staged decomposition: device-resident batch -----------------------
+ * mpld_batch_create runs the host front-end (simplification, sub-graphs,
+ * exact-cover packing) and uploads the packed image to device memory.
+ * mpld_batch_solve enqueues the whole device search on the context stream
+ * (queue reset, tiered persistent search or, with MPLD_PLAIN in `flags`,
+ * one launch per component; per-component results stay on the device); it
+ * does not wait.  mpld_batch_result waits, copies the results back and runs
+ * recovery and the Eq. 1 tallies. */
+int32_t mpld_batch_create(mpld_context* ctx, const mpld_graph* g,
+                          const mpld_options* opt, mpld_batch** out);
+int32_t mpld_batch_solve(mpld_batch* b, uint32_t flags);
+int32_t mpld_batch_result(mpld_batch* b, mpld_result** out);
+/* Batch statistics: components per tier, core nodes, image bytes, and the
+ * device time (ms) of the last solve's search kernels measured with HIP
+ * events on the context stream (valid after mpld_batch_result or a stream
+ * synchronisation). */
+typedef struct {
+  int32_t num_components;
+  int32_t num_wave;          /* components on the register tier (n <= 64) */
+  int32_t num_lds;           /* components on the LDS tier                */
+  int32_t num_global;        /* components on the global-memory tier      */
+  int32_t core_nodes;        /* nodes left after simplification           */
+  int32_t max_size;
+  int64_t image_bytes;       /* packed device image                       */
+  int64_t core_edges;
+  float last_search_ms;      /* search kernels of the last solve          */
+  float last_total_ms;       /* whole enqueued solve of the last solve    */
+  int32_t launches;          /* kernel launches of the last solve         */
+  int32_t reserved;
+} mpld_batch_info;
+int32_t mpld_batch_get_info(mpld_batch* b, mpld_batch_info* info);
+void mpld_batch_free(mpld_batch* b);
+
+/* ---- components directly (no simplification, no renumbering) -----------
+ * Solves `count` components given in local numbering.  out: count records;
+ * colors_out: sum of n entries, component after component (-1 unless
+ * feasible).  Synchronous. */
+int32_t mpld_solve_components(mpld_context* ctx, const mpld_component* comps,
+                              int32_t count, const mpld_options* opt,
+                              mpld_comp_record* out, int8_t* colors_out);
+
+/* ---- results ------------------------------------------------------------ */
+const int8_t* mpld_result_colors(const mpld_result* r, int32_t* num_nodes);
+const int32_t* mpld_result_component_of(const mpld_result* r); /* -1 = removed */
+int32_t mpld_result_num_components(const mpld_result* r);
+const mpld_comp_record* mpld_result_components(const mpld_result* r);
+void mpld_result_totals(const mpld_result* r, int64_t* stitches,
+                        int64_t* conflicts, int64_t* uncolored);
+void mpld_result_free(mpld_result* r);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,271 @@
+"""MI355X exact-cover multiple-patterning layout decomposer (Python binding).
+
+Thin wrapper over the C ABI in ``include/mpld.h``: every function here only
+marshals arguments; every step of the decomposition runs in the native
+library (host front-end in C++, the search in HIP kernels for gfx950).
+PyTorch supplies device memory (through the library's allocator hook) and
+the HIP stream.  There is no CPU fallback: without ``libmpld.so`` importing
+the binding raises, and without a gfx950 device the context call fails.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import _ffi
+from ._ffi import (MPLD_BUDGET_EXHAUSTED, MPLD_FEASIBLE, MPLD_FORCE_GLOBAL,  # noqa: F401
+                   MPLD_FORCE_LDS, MPLD_FORCE_WAVE, MPLD_INFEASIBLE, MPLD_PLAIN,
+                   MPLD_SIMPLIFY, MPLD_TRACE_HASH)
+
+_lib = _ffi.load()
+
+RECORD_DTYPE = np.dtype([("size", np.int32), ("status", np.int32), ("nodes", np.int64),
+                         ("trace_hash", np.uint64), ("depth_at_stop", np.int32),
+                         ("stitches", np.int32), ("first_node", np.int32),
+                         ("num_edges", np.int32)])
+assert RECORD_DTYPE.itemsize == ctypes.sizeof(_ffi.mpld_comp_record)
+
+
+class MpldError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        msg = _lib.mpld_error_string(code).decode()
+        detail = (_lib.mpld_last_error() or b"").decode()
+        super().__init__(f"{where}: {msg} ({code}): {detail}")
+
+
+def _check(code: int, where: str) -> None:
+    if code != 0:
+        raise MpldError(code, where)
+
+
+def mpld_abi_version() -> int:
+    return int(_lib.mpld_abi_version())
+
+
+def options(k: int, budget: int, flags: int = MPLD_SIMPLIFY) -> _ffi.mpld_options:
+    return _ffi.mpld_options(ctypes.sizeof(_ffi.mpld_options), k, budget, flags, 0)
+
+
+# ---- graphs -------------------------------------------------------------
+
+@dataclass
+class Graph:
+    """A layout graph (nodes, conflict pairs, stitch pairs) in numpy arrays."""
+    num_nodes: int
+    ce: np.ndarray
+    se: np.ndarray
+
+    def view(self) -> _ffi.mpld_graph:
+        self.ce = np.ascontiguousarray(self.ce, dtype=np.int32).reshape(-1, 2)
+        self.se = np.ascontiguousarray(self.se, dtype=np.int32).reshape(-1, 2)
+        return _ffi.mpld_graph(self.num_nodes, 0, len(self.ce), self.ce.ctypes.data,
+                               len(self.se), self.se.ctypes.data)
+
+
+def mpld_build_graph(rects: np.ndarray, dmin_nm: int, split_len_nm: int = 0) -> Graph:
+    """Layout graph of rectangles (x0, y0, x1, y1) - see include/mpld.h."""
+    r = np.ascontiguousarray(rects, dtype=np.int32).reshape(-1, 4)
+    h = ctypes.c_void_p()
+    _check(_lib.mpld_build_graph(r.ctypes.data, len(r), dmin_nm, split_len_nm,
+                                 ctypes.byref(h)), "mpld_build_graph")
+    try:
+        v = _ffi.mpld_graph()
+        _check(_lib.mpld_owned_graph_view(h, ctypes.byref(v)), "mpld_owned_graph_view")
+        ce = np.ctypeslib.as_array((ctypes.c_int32 * (2 * v.num_ce)).from_address(v.ce)).copy() \
+            if v.num_ce else np.zeros(0, np.int32)
+        se = np.ctypeslib.as_array((ctypes.c_int32 * (2 * v.num_se)).from_address(v.se)).copy() \
+            if v.num_se else np.zeros(0, np.int32)
+        return Graph(v.num_nodes, ce.reshape(-1, 2), se.reshape(-1, 2))
+    finally:
+        _lib.mpld_owned_graph_free(h)
+
+
+# ---- context ------------------------------------------------------------
+
+class _TorchAllocator:
+    """Device memory from torch's caching allocator, kept alive by handle."""
+
+    def __init__(self, device):
+        import torch
+        self._torch = torch
+        self.device = device
+        self.live = {}
+
+        def alloc(nbytes, _user):
+            t = torch.empty(int(nbytes), dtype=torch.uint8, device=self.device)
+            p = t.data_ptr()
+            self.live[p] = t
+            return p
+
+        def free(ptr, _user):
+            self.live.pop(ptr, None)
+
+        self._a = _ffi.ALLOC_FN(alloc)
+        self._f = _ffi.FREE_FN(free)
+        self.struct = _ffi.mpld_allocator(self._a, self._f, None)
+
+
+class Context:
+    """One device, one stream (torch's current stream by default)."""
+
+    def __init__(self, device: int = 0, use_torch: bool = True):
+        self.handle = ctypes.c_void_p()
+        self._alloc = None
+        stream = None
+        alloc_ptr = None
+        if use_torch:
+            import torch
+            dev = torch.device("cuda", device)
+            self._alloc = _TorchAllocator(dev)
+            alloc_ptr = ctypes.byref(self._alloc.struct)
+            stream = ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+        _check(_lib.mpld_context_create(device, alloc_ptr, stream, ctypes.byref(self.handle)),
+               "mpld_context_create")
+
+    def close(self):
+        if self.handle:
+            _lib.mpld_context_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def mpld_context_create(device: int = 0, use_torch: bool = True) -> Context:
+    return Context(device, use_torch)
+
+
+def mpld_context_destroy(ctx: Context) -> None:
+    ctx.close()
+
+
+# ---- results ------------------------------------------------------------
+
+@dataclass
+class Result:
+    colors: np.ndarray        # int8 per node, -1 = uncolored
+    component_of: np.ndarray  # int32 per node, -1 = removed by simplification
+    components: np.ndarray    # RECORD_DTYPE per component
+    stitches: int
+    conflicts: int
+    uncolored: int
+
+
+def _take_result(h) -> Result:
+    try:
+        n = ctypes.c_int32()
+        pc = _lib.mpld_result_colors(h, ctypes.byref(n))
+        colors = (np.ctypeslib.as_array((ctypes.c_int8 * n.value).from_address(pc)).copy()
+                  if n.value else np.zeros(0, np.int8))
+        po = _lib.mpld_result_component_of(h)
+        comp_of = (np.ctypeslib.as_array((ctypes.c_int32 * n.value).from_address(po)).copy()
+                   if n.value else np.zeros(0, np.int32))
+        nc = _lib.mpld_result_num_components(h)
+        if nc:
+            pr = _lib.mpld_result_components(h)
+            raw = (ctypes.c_uint8 * (nc * RECORD_DTYPE.itemsize)).from_address(pr)
+            comps = np.frombuffer(bytes(raw), dtype=RECORD_DTYPE).copy()
+        else:
+            comps = np.zeros(0, RECORD_DTYPE)
+        st, cn, un = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        _lib.mpld_result_totals(h, ctypes.byref(st), ctypes.byref(cn), ctypes.byref(un))
+        return Result(colors, comp_of, comps, st.value, cn.value, un.value)
+    finally:
+        _lib.mpld_result_free(h)
+
+
+def mpld_decompose(ctx: Context, g: Graph, k: int, budget: int,
+                   flags: int = MPLD_SIMPLIFY) -> Result:
+    opt = options(k, budget, flags)
+    view = g.view()
+    h = ctypes.c_void_p()
+    _check(_lib.mpld_decompose(ctx.handle, ctypes.byref(view), ctypes.byref(opt),
+                               ctypes.byref(h)), "mpld_decompose")
+    return _take_result(h)
+
+
+class Batch:
+    """Front-end + packed image resident on the device; solve repeatedly."""
+
+    def __init__(self, ctx: Context, g: Graph, k: int, budget: int, flags: int = MPLD_SIMPLIFY):
+        self.ctx = ctx
+        self.handle = ctypes.c_void_p()
+        opt = options(k, budget, flags)
+        view = g.view()
+        _check(_lib.mpld_batch_create(ctx.handle, ctypes.byref(view), ctypes.byref(opt),
+                                      ctypes.byref(self.handle)), "mpld_batch_create")
+
+    def solve(self, plain: bool = False) -> None:
+        _check(_lib.mpld_batch_solve(self.handle, MPLD_PLAIN if plain else 0), "mpld_batch_solve")
+
+    def result(self) -> Result:
+        h = ctypes.c_void_p()
+        _check(_lib.mpld_batch_result(self.handle, ctypes.byref(h)), "mpld_batch_result")
+        return _take_result(h)
+
+    def info(self) -> dict:
+        i = _ffi.mpld_batch_info()
+        _check(_lib.mpld_batch_get_info(self.handle, ctypes.byref(i)), "mpld_batch_get_info")
+        return {name: getattr(i, name) for name, _ in i._fields_ if name != "reserved"}
+
+    def close(self):
+        if self.handle:
+            _lib.mpld_batch_free(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def mpld_batch_create(ctx: Context, g: Graph, k: int, budget: int,
+                      flags: int = MPLD_SIMPLIFY) -> Batch:
+    return Batch(ctx, g, k, budget, flags)
+
+
+def mpld_batch_solve(b: Batch, plain: bool = False) -> None:
+    b.solve(plain)
+
+
+def mpld_batch_result(b: Batch) -> Result:
+    return b.result()
+
+
+def mpld_batch_get_info(b: Batch) -> dict:
+    return b.info()
+
+
+def mpld_batch_free(b: Batch) -> None:
+    b.close()
+
+
+def mpld_solve_components(ctx: Context, comps, k: int, budget: int, flags: int = 0):
+    """comps: list of (n, edges [m, 2]) in local numbering.  Returns
+    (records RECORD_DTYPE[count], list of per-component int8 colors)."""
+    arrs = []
+    cs = (_ffi.mpld_component * max(len(comps), 1))()
+    total = 0
+    for i, (n, e) in enumerate(comps):
+        a = np.ascontiguousarray(np.asarray(e, dtype=np.int32).reshape(-1, 2))
+        arrs.append(a)
+        cs[i] = _ffi.mpld_component(n, 0, len(a), a.ctypes.data)
+        total += n
+    recs = (_ffi.mpld_comp_record * max(len(comps), 1))()
+    colors = np.zeros(max(total, 1), dtype=np.int8)
+    opt = options(k, budget, flags)
+    _check(_lib.mpld_solve_components(ctx.handle, cs, len(comps), ctypes.byref(opt), recs,
+                                      colors.ctypes.data), "mpld_solve_components")
+    out = np.frombuffer(bytes(recs), dtype=RECORD_DTYPE)[: len(comps)].copy()
+    per, off = [], 0
+    for n, _ in comps:
+        per.append(colors[off: off + n].copy())
+        off += n
+    return out, per

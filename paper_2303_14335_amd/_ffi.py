@@ -1,0 +1,116 @@
+"""ctypes declarations of include/mpld.h (argument marshalling only)."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmpld.so")
+
+MPLD_OK = 0
+MPLD_E_INVALID = -1
+MPLD_E_NOMEM = -2
+MPLD_E_DEVICE = -3
+MPLD_E_NOT_READY = -4
+MPLD_E_CANCELLED = -5
+MPLD_E_INTERNAL = -6
+MPLD_E_UNSUPPORTED = -7
+
+MPLD_FEASIBLE, MPLD_INFEASIBLE, MPLD_BUDGET_EXHAUSTED = 0, 1, 2
+
+MPLD_SIMPLIFY = 1 << 0
+MPLD_TRACE_HASH = 1 << 1
+MPLD_PLAIN = 1 << 2
+MPLD_FORCE_WAVE = 1 << 3
+MPLD_FORCE_LDS = 1 << 4
+MPLD_FORCE_GLOBAL = 1 << 5
+
+c_i32, c_i64, c_u32, c_u64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint64
+vp = ctypes.c_void_p
+
+
+class mpld_rect(ctypes.Structure):
+    _fields_ = [("x0", c_i32), ("y0", c_i32), ("x1", c_i32), ("y1", c_i32)]
+
+
+class mpld_graph(ctypes.Structure):
+    _fields_ = [("num_nodes", c_i32), ("reserved", c_i32), ("num_ce", c_i64), ("ce", vp),
+                ("num_se", c_i64), ("se", vp)]
+
+
+class mpld_options(ctypes.Structure):
+    _fields_ = [("struct_size", c_u32), ("k", c_i32), ("node_budget", c_i64),
+                ("flags", c_u32), ("reserved", c_i32)]
+
+
+class mpld_comp_record(ctypes.Structure):
+    _fields_ = [("size", c_i32), ("status", c_i32), ("nodes", c_i64), ("trace_hash", c_u64),
+                ("depth_at_stop", c_i32), ("stitches", c_i32), ("first_node", c_i32),
+                ("num_edges", c_i32)]
+
+
+class mpld_component(ctypes.Structure):
+    _fields_ = [("n", c_i32), ("reserved", c_i32), ("m", c_i64), ("edges", vp)]
+
+
+ALLOC_FN = ctypes.CFUNCTYPE(vp, ctypes.c_size_t, vp)
+FREE_FN = ctypes.CFUNCTYPE(None, vp, vp)
+
+
+class mpld_allocator(ctypes.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("user", vp)]
+
+
+class mpld_batch_info(ctypes.Structure):
+    _fields_ = [("num_components", c_i32), ("num_wave", c_i32), ("num_lds", c_i32),
+                ("num_global", c_i32), ("core_nodes", c_i32), ("max_size", c_i32),
+                ("image_bytes", c_i64), ("core_edges", c_i64), ("last_search_ms", ctypes.c_float),
+                ("last_total_ms", ctypes.c_float), ("launches", c_i32), ("reserved", c_i32)]
+
+
+P = ctypes.POINTER
+
+# name -> (restype, argtypes); every entry point of include/mpld.h
+SIGNATURES = {
+    "mpld_abi_version": (c_u32, []),
+    "mpld_error_string": (ctypes.c_char_p, [c_i32]),
+    "mpld_last_error": (ctypes.c_char_p, []),
+    "mpld_build_graph": (c_i32, [vp, c_i32, c_i32, c_i32, P(vp)]),
+    "mpld_owned_graph_view": (c_i32, [vp, P(mpld_graph)]),
+    "mpld_owned_graph_free": (None, [vp]),
+    "mpld_context_create": (c_i32, [c_i32, P(mpld_allocator), vp, P(vp)]),
+    "mpld_context_destroy": (c_i32, [vp]),
+    "mpld_decompose": (c_i32, [vp, P(mpld_graph), P(mpld_options), P(vp)]),
+    "mpld_batch_create": (c_i32, [vp, P(mpld_graph), P(mpld_options), P(vp)]),
+    "mpld_batch_solve": (c_i32, [vp, c_u32]),
+    "mpld_batch_result": (c_i32, [vp, P(vp)]),
+    "mpld_batch_get_info": (c_i32, [vp, P(mpld_batch_info)]),
+    "mpld_batch_free": (None, [vp]),
+    "mpld_solve_components": (c_i32, [vp, P(mpld_component), c_i32, P(mpld_options),
+                                      P(mpld_comp_record), vp]),
+    "mpld_result_colors": (vp, [vp, P(c_i32)]),
+    "mpld_result_component_of": (vp, [vp]),
+    "mpld_result_num_components": (c_i32, [vp]),
+    "mpld_result_components": (vp, [vp]),
+    "mpld_result_totals": (None, [vp, P(c_i64), P(c_i64), P(c_i64)]),
+    "mpld_result_free": (None, [vp]),
+}
+
+_lib = None
+
+
+def load():
+    """Loads libmpld.so; raises if it is not built (there is no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(
+                f"{LIB_PATH} is missing: the HIP library must be built "
+                "(python -m paper_2303_14335_amd.build) - there is no CPU fallback")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib

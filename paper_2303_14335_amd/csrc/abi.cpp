@@ -1,0 +1,393 @@
+// abi.cpp - the C ABI of include/mpld.h: argument checks, error mapping,
+// and the flow of Sec. 2.2 (front-end -> device search -> recovery).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <exception>
+#include <new>
+
+#include "runtime.h"
+
+namespace mpld {
+const char* last_error_cstr();
+}
+
+using namespace mpld;
+
+namespace {
+
+template <class F>
+int32_t guard(F&& f) {
+  try {
+    f();
+    set_last_error("");
+    return MPLD_OK;
+  } catch (const Error& e) {
+    set_last_error(e.what);
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    set_last_error("host allocation failed");
+    return MPLD_E_NOMEM;
+  } catch (const std::exception& e) {
+    set_last_error(e.what());
+    return MPLD_E_INTERNAL;
+  } catch (...) {
+    set_last_error("unknown exception");
+    return MPLD_E_INTERNAL;
+  }
+}
+
+void check_options(const mpld_options* opt) {
+  if (!opt) fail(MPLD_E_INVALID, "options are NULL");
+  if (opt->struct_size != sizeof(mpld_options))
+    fail(MPLD_E_INVALID, "options.struct_size does not match this library's mpld_options");
+  if (opt->k < 2 || opt->k > MPLD_MAX_K) fail(MPLD_E_INVALID, "k must be in [2, 8]");
+  if (opt->node_budget < 1) fail(MPLD_E_INVALID, "node_budget must be >= 1");
+  const uint32_t forced = opt->flags & (MPLD_FORCE_WAVE | MPLD_FORCE_LDS | MPLD_FORCE_GLOBAL);
+  if (forced & (forced - 1)) fail(MPLD_E_INVALID, "at most one MPLD_FORCE_* flag");
+}
+
+void use_device(mpld_context* ctx) {
+  if (!ctx) fail(MPLD_E_INVALID, "context is NULL");
+  check_hip(hipSetDevice(ctx->device), "hipSetDevice");
+}
+
+// Builds the batch: front-end, packing, upload.
+void batch_build(mpld_context* ctx, const mpld_graph* g, const mpld_options* opt, mpld_batch* b) {
+  if (!g) fail(MPLD_E_INVALID, "graph is NULL");
+  check_options(opt);
+  b->ctx = ctx;
+  b->opt = *opt;
+  b->g = make_graph(*g);
+  b->s = simplify_and_split(b->g, opt->k, opt->flags & MPLD_SIMPLIFY);
+  const int32_t nc = (int32_t)b->s.comp_ptr.size() - 1;
+  std::vector<int32_t> pairs;
+  for (int32_t c = 0; c < nc; ++c) {
+    local_edges(b->g, b->s, c, pairs);
+    const int32_t n = b->s.comp_ptr[c + 1] - b->s.comp_ptr[c];
+    image_add(b->im, ctx, n, pairs.data(), (int64_t)pairs.size() / 2, opt->k, opt->node_budget,
+              opt->flags);
+  }
+  image_finish(b->im);
+  device_upload(ctx, b->im, b->db);
+}
+
+void batch_collect(mpld_batch* b, mpld_result* r) {
+  std::vector<DevRecord> recs;
+  std::vector<int8_t> lcol;
+  device_fetch(b->db, recs, lcol);
+  const Graph& g = b->g;
+  const Split& s = b->s;
+  const bool trace = b->opt.flags & MPLD_TRACE_HASH;
+  r->colors.assign((size_t)g.n, -1);
+  r->comp_of = s.comp_of;
+  const int32_t nc = (int32_t)s.comp_ptr.size() - 1;
+  r->comps.resize((size_t)nc);
+  for (int32_t c = 0; c < nc; ++c) {
+    const DevDesc& d = b->im.desc[c];
+    for (int32_t i = 0; i < d.n; ++i) r->colors[s.order[s.comp_ptr[c] + i]] = lcol[d.out_off + i];
+  }
+  for (int32_t c = 0; c < nc; ++c) {
+    const DevDesc& d = b->im.desc[c];
+    mpld_comp_record& rec = r->comps[c];
+    rec.size = d.n;
+    rec.status = recs[c].status;
+    rec.nodes = (int64_t)recs[c].nodes;
+    rec.trace_hash = trace ? recs[c].hash : 0;
+    rec.depth_at_stop = recs[c].depth;
+    rec.first_node = s.order[s.comp_ptr[c]];
+    int64_t edges2 = 0;
+    int32_t st = 0;
+    for (int32_t p = s.comp_ptr[c]; p < s.comp_ptr[c + 1]; ++p) {
+      const int32_t x = s.order[p];
+      for (int64_t t = g.ptr[x]; t < g.ptr[x + 1]; ++t) edges2 += s.comp_of[g.adj[t]] == c;
+      const int32_t q = g.partner[x];
+      if (q > x && s.comp_of[q] == c && r->colors[q] != r->colors[x]) ++st;
+    }
+    rec.num_edges = (int32_t)(edges2 / 2);
+    rec.stitches = rec.status == MPLD_FEASIBLE ? st : -1;
+  }
+  if (b->opt.flags & MPLD_SIMPLIFY) recover(g, s, b->opt.k, r->colors);
+  tallies(g, r->colors, &r->stitches, &r->conflicts, &r->uncolored);
+}
+
+}  // namespace
+
+extern "C" {
+
+uint32_t mpld_abi_version(void) { return MPLD_ABI_VERSION; }
+
+const char* mpld_error_string(int32_t err) {
+  switch (err) {
+    case MPLD_OK: return "ok";
+    case MPLD_E_INVALID: return "invalid argument";
+    case MPLD_E_NOMEM: return "out of memory";
+    case MPLD_E_DEVICE: return "device error";
+    case MPLD_E_NOT_READY: return "not ready";
+    case MPLD_E_CANCELLED: return "cancelled";
+    case MPLD_E_INTERNAL: return "internal error";
+    case MPLD_E_UNSUPPORTED: return "unsupported";
+    default: return "unknown error code";
+  }
+}
+
+const char* mpld_last_error(void) { return last_error_cstr(); }
+
+int32_t mpld_build_graph(const mpld_rect* rects, int32_t n, int32_t dmin_nm, int32_t split_len_nm,
+                         mpld_owned_graph** out) {
+  return guard([&] {
+    if (!out) fail(MPLD_E_INVALID, "out is NULL");
+    *out = nullptr;
+    auto* g = new mpld_owned_graph();
+    try {
+      build_layout_graph(rects, n, dmin_nm, split_len_nm, g->g);
+    } catch (...) {
+      delete g;
+      throw;
+    }
+    *out = g;
+  });
+}
+
+int32_t mpld_owned_graph_view(const mpld_owned_graph* g, mpld_graph* view) {
+  return guard([&] {
+    if (!g || !view) fail(MPLD_E_INVALID, "NULL argument");
+    view->num_nodes = g->g.num_nodes;
+    view->reserved = 0;
+    view->num_ce = (int64_t)g->g.ce.size() / 2;
+    view->ce = g->g.ce.data();
+    view->num_se = (int64_t)g->g.se.size() / 2;
+    view->se = g->g.se.data();
+  });
+}
+
+void mpld_owned_graph_free(mpld_owned_graph* g) { delete g; }
+
+int32_t mpld_context_create(int32_t device, const mpld_allocator* alloc, void* hip_stream,
+                            mpld_context** out) {
+  return guard([&] {
+    if (!out) fail(MPLD_E_INVALID, "out is NULL");
+    *out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count == 0)
+      fail(MPLD_E_DEVICE, "no HIP device is visible");
+    if (device < 0 || device >= count) fail(MPLD_E_DEVICE, "device ordinal out of range");
+    check_hip(hipSetDevice(device), "hipSetDevice");
+    hipDeviceProp_t prop;
+    check_hip(hipGetDeviceProperties(&prop, device), "hipGetDeviceProperties");
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+      fail(MPLD_E_DEVICE, std::string("device is ") + prop.gcnArchName + ", this library is built for gfx950");
+    if (alloc && (!alloc->alloc || !alloc->free)) fail(MPLD_E_INVALID, "allocator lacks alloc or free");
+    auto* ctx = new mpld_context();
+    ctx->device = device;
+    ctx->num_cus = prop.multiProcessorCount;
+    ctx->lds_per_block = (int)prop.sharedMemPerBlock;
+    if (alloc) {
+      ctx->alloc = *alloc;
+      ctx->has_alloc = true;
+    }
+    try {
+      if (hip_stream) {
+        ctx->stream = static_cast<hipStream_t>(hip_stream);
+      } else {
+        check_hip(hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking), "stream");
+        ctx->own_stream = true;
+      }
+      for (auto& e : ctx->ev) check_hip(hipEventCreate(&e), "event");
+      ctx->reg_blocks_per_cu = reg_batched_blocks_per_cu(false);
+    } catch (...) {
+      mpld_context_destroy(ctx);
+      throw;
+    }
+    *out = ctx;
+  });
+}
+
+int32_t mpld_context_destroy(mpld_context* ctx) {
+  if (!ctx) return MPLD_OK;
+  (void)hipSetDevice(ctx->device);
+  if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+  for (auto& e : ctx->ev)
+    if (e) (void)hipEventDestroy(e);
+  if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
+  delete ctx;
+  return MPLD_OK;
+}
+
+int32_t mpld_batch_create(mpld_context* ctx, const mpld_graph* g, const mpld_options* opt,
+                          mpld_batch** out) {
+  return guard([&] {
+    if (!out) fail(MPLD_E_INVALID, "out is NULL");
+    *out = nullptr;
+    use_device(ctx);
+    auto* b = new mpld_batch();
+    try {
+      batch_build(ctx, g, opt, b);
+    } catch (...) {
+      delete b;
+      throw;
+    }
+    *out = b;
+  });
+}
+
+int32_t mpld_batch_solve(mpld_batch* b, uint32_t flags) {
+  return guard([&] {
+    if (!b) fail(MPLD_E_INVALID, "batch is NULL");
+    use_device(b->ctx);
+    device_solve(b->db, (b->opt.flags & ~MPLD_PLAIN) | (flags & MPLD_PLAIN));
+    b->solved = true;
+  });
+}
+
+int32_t mpld_batch_result(mpld_batch* b, mpld_result** out) {
+  return guard([&] {
+    if (!b || !out) fail(MPLD_E_INVALID, "NULL argument");
+    *out = nullptr;
+    if (!b->solved) fail(MPLD_E_INVALID, "batch was not solved");
+    use_device(b->ctx);
+    auto* r = new mpld_result();
+    try {
+      batch_collect(b, r);
+    } catch (...) {
+      delete r;
+      throw;
+    }
+    *out = r;
+  });
+}
+
+int32_t mpld_batch_get_info(mpld_batch* b, mpld_batch_info* info) {
+  return guard([&] {
+    if (!b || !info) fail(MPLD_E_INVALID, "NULL argument");
+    std::memset(info, 0, sizeof(*info));
+    info->num_components = b->db.num_comps;
+    info->num_wave = b->db.n_reg;
+    info->num_lds = b->db.n_lds;
+    info->num_global = b->db.n_big;
+    info->core_nodes = b->im.total_nodes;
+    info->max_size = b->im.max_size;
+    info->image_bytes = (int64_t)(b->db.desc.bytes + b->db.masks.bytes + b->db.adj32.bytes +
+                                  b->db.queues.bytes);
+    info->core_edges = b->im.core_edges;
+    info->last_search_ms = b->db.last_search_ms;
+    info->last_total_ms = b->db.last_total_ms;
+    info->launches = b->db.launches;
+  });
+}
+
+void mpld_batch_free(mpld_batch* b) {
+  if (!b) return;
+  if (b->ctx) {
+    (void)hipSetDevice(b->ctx->device);
+    (void)hipStreamSynchronize(b->ctx->stream);
+  }
+  delete b;
+}
+
+int32_t mpld_decompose(mpld_context* ctx, const mpld_graph* g, const mpld_options* opt,
+                       mpld_result** out) {
+  return guard([&] {
+    if (!out) fail(MPLD_E_INVALID, "out is NULL");
+    *out = nullptr;
+    use_device(ctx);
+    mpld_batch b;
+    batch_build(ctx, g, opt, &b);
+    device_solve(b.db, opt->flags);
+    b.solved = true;
+    auto* r = new mpld_result();
+    try {
+      batch_collect(&b, r);
+    } catch (...) {
+      delete r;
+      throw;
+    }
+    *out = r;
+  });
+}
+
+int32_t mpld_solve_components(mpld_context* ctx, const mpld_component* comps, int32_t count,
+                              const mpld_options* opt, mpld_comp_record* out, int8_t* colors_out) {
+  return guard([&] {
+    use_device(ctx);
+    check_options(opt);
+    if (count < 0 || (count > 0 && (!comps || !out || !colors_out)))
+      fail(MPLD_E_INVALID, "bad component array");
+    Image im;
+    std::vector<int32_t> pairs;
+    for (int32_t c = 0; c < count; ++c) {
+      const mpld_component& cp = comps[c];
+      if (cp.n < 0 || cp.m < 0 || (cp.m > 0 && !cp.edges))
+        fail(MPLD_E_INVALID, "component " + std::to_string(c) + " has a bad size or edge array");
+      std::vector<uint64_t> keys((size_t)cp.m);
+      for (int64_t e = 0; e < cp.m; ++e) {
+        int32_t a = cp.edges[2 * e], b = cp.edges[2 * e + 1];
+        if (a < 0 || b < 0 || a >= cp.n || b >= cp.n || a == b)
+          fail(MPLD_E_INVALID, "component " + std::to_string(c) + " edge " + std::to_string(e) +
+                                   " is out of range or a self loop");
+        if (a > b) std::swap(a, b);
+        keys[e] = ((uint64_t)(uint32_t)a << 32) | (uint32_t)b;
+      }
+      std::sort(keys.begin(), keys.end());
+      if (std::adjacent_find(keys.begin(), keys.end()) != keys.end())
+        fail(MPLD_E_INVALID, "component " + std::to_string(c) + " has a duplicate edge");
+      pairs.resize(2 * keys.size());
+      for (size_t e = 0; e < keys.size(); ++e) {
+        pairs[2 * e] = (int32_t)(keys[e] >> 32);
+        pairs[2 * e + 1] = (int32_t)(keys[e] & 0xffffffffu);
+      }
+      image_add(im, ctx, cp.n, pairs.data(), cp.m, opt->k, opt->node_budget, opt->flags);
+    }
+    image_finish(im);
+    DeviceBatch db;
+    device_upload(ctx, im, db);
+    device_solve(db, opt->flags);
+    std::vector<DevRecord> recs;
+    std::vector<int8_t> lcol;
+    device_fetch(db, recs, lcol);
+    const bool trace = opt->flags & MPLD_TRACE_HASH;
+    for (int32_t c = 0; c < count; ++c) {
+      mpld_comp_record& r = out[c];
+      r.size = comps[c].n;
+      r.status = recs[c].status;
+      r.nodes = (int64_t)recs[c].nodes;
+      r.trace_hash = trace ? recs[c].hash : 0;
+      r.depth_at_stop = recs[c].depth;
+      r.stitches = r.status == MPLD_FEASIBLE ? 0 : -1;
+      r.first_node = -1;
+      r.num_edges = (int32_t)comps[c].m;
+    }
+    if (!lcol.empty()) std::memcpy(colors_out, lcol.data(), lcol.size());
+  });
+}
+
+const int8_t* mpld_result_colors(const mpld_result* r, int32_t* num_nodes) {
+  if (!r) return nullptr;
+  if (num_nodes) *num_nodes = (int32_t)r->colors.size();
+  return r->colors.data();
+}
+
+const int32_t* mpld_result_component_of(const mpld_result* r) {
+  return r ? r->comp_of.data() : nullptr;
+}
+
+int32_t mpld_result_num_components(const mpld_result* r) {
+  return r ? (int32_t)r->comps.size() : 0;
+}
+
+const mpld_comp_record* mpld_result_components(const mpld_result* r) {
+  return r ? r->comps.data() : nullptr;
+}
+
+void mpld_result_totals(const mpld_result* r, int64_t* stitches, int64_t* conflicts,
+                        int64_t* uncolored) {
+  if (!r) return;
+  if (stitches) *stitches = r->stitches;
+  if (conflicts) *conflicts = r->conflicts;
+  if (uncolored) *uncolored = r->uncolored;
+}
+
+void mpld_result_free(mpld_result* r) { delete r; }
+
+}  // extern "C"

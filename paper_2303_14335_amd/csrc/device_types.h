@@ -1,0 +1,35 @@
+// device_types.h - layout of the packed exact-cover image in device memory,
+// shared by the host packer/runtime and the HIP kernels.
+#pragma once
+
+#include <cstdint>
+
+namespace mpld {
+
+enum Tier : int32_t { kTierReg = 0, kTierLds = 1, kTierGlobal = 2 };
+
+// One descriptor per component (32 bytes).
+//   register tier: nbr_off indexes `masks` (one uint64 neighbour mask per
+//                  local node, bit u set iff u is a conflict neighbour).
+//   LDS / global tier: nbr_off indexes `adj32`: n+1 row offsets (relative to
+//                  nbr_off + n + 1) followed by the local neighbour ids.
+struct DevDesc {
+  int32_t n;        // nodes
+  int32_t k;        // colors
+  int64_t budget;   // search-node budget
+  int64_t nbr_off;
+  int32_t out_off;  // first entry of the component in the colors output
+  int32_t tier;
+};
+static_assert(sizeof(DevDesc) == 32, "descriptor is 32 bytes");
+
+// One record per component (24 bytes), written by the search.
+struct DevRecord {
+  int32_t status;   // MPLD_FEASIBLE / MPLD_INFEASIBLE / MPLD_BUDGET_EXHAUSTED
+  int32_t depth;    // rows in the partial solution at the stop (0 if infeasible)
+  uint64_t nodes;   // search nodes
+  uint64_t hash;    // FNV-1a trace hash (offset basis when tracing is off)
+};
+static_assert(sizeof(DevRecord) == 24, "record is 24 bytes");
+
+}  // namespace mpld

@@ -1,0 +1,253 @@
+// runtime.cpp - device context, exact-cover image packing, upload, tiered
+// launches and result download (host side of the decomposer library).
+#include "runtime.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+
+namespace mpld {
+
+void check_hip(hipError_t e, const char* what) {
+  if (e == hipSuccess) return;
+  const int32_t code = (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) ? MPLD_E_NOMEM
+                                                                                   : MPLD_E_DEVICE;
+  fail(code, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// ---------------------------------------------------------------------------
+// Packing.  Register tier (n <= 64): one uint64 neighbour mask per node.
+// LDS tiers: row offsets (n + 1), neighbour ids (2m), largest degree.
+
+void image_add(Image& im, mpld_context* ctx, int32_t n, const int32_t* pairs, int64_t m, int32_t k,
+               int64_t budget, uint32_t flags) {
+  DevDesc d{};
+  d.n = n;
+  d.k = k;
+  d.budget = budget;
+  d.out_off = im.total_nodes;
+  const int32_t id = (int32_t)im.desc.size();
+  const bool force_lds = flags & MPLD_FORCE_LDS, force_glb = flags & MPLD_FORCE_GLOBAL,
+             force_reg = flags & MPLD_FORCE_WAVE;
+  if (n <= 64 && !force_lds && !force_glb) {
+    d.tier = kTierReg;
+    d.nbr_off = (int64_t)im.masks.size();
+    im.masks.resize(im.masks.size() + (size_t)n, 0ull);
+    uint64_t* mk = im.masks.data() + d.nbr_off;
+    for (int64_t e = 0; e < m; ++e) {
+      const int32_t a = pairs[2 * e], b = pairs[2 * e + 1];
+      mk[a] |= 1ull << b;
+      mk[b] |= 1ull << a;
+    }
+    im.q_reg.push_back(id);
+  } else {
+    if (force_reg) fail(MPLD_E_UNSUPPORTED, "register tier takes at most 64 nodes, component has " + std::to_string(n));
+    d.nbr_off = (int64_t)im.adj32.size();
+    const int64_t adj_words = (int64_t)n + 1 + 2 * m;
+    im.adj32.resize(im.adj32.size() + (size_t)adj_words + 1, 0u);
+    uint32_t* ptr = im.adj32.data() + d.nbr_off;
+    uint32_t* ids = ptr + n + 1;
+    for (int64_t e = 0; e < m; ++e) {
+      ++ptr[pairs[2 * e] + 1];
+      ++ptr[pairs[2 * e + 1] + 1];
+    }
+    uint32_t maxdeg = 0;
+    for (int32_t v = 0; v < n; ++v) {
+      maxdeg = std::max(maxdeg, ptr[v + 1]);
+      ptr[v + 1] += ptr[v];
+    }
+    std::vector<uint32_t> fill(ptr, ptr + n);
+    for (int64_t e = 0; e < m; ++e) {
+      const int32_t a = pairs[2 * e], b = pairs[2 * e + 1];
+      ids[fill[a]++] = (uint32_t)b;
+      ids[fill[b]++] = (uint32_t)a;
+    }
+    for (int32_t v = 0; v < n; ++v) std::sort(ids + ptr[v], ids + ptr[v + 1]);
+    ids[2 * m] = maxdeg;
+    const int64_t small = lds_bytes_for(n, k, adj_words, (int32_t)maxdeg, false);
+    const int64_t big = lds_bytes_for(n, k, adj_words, (int32_t)maxdeg, true);
+    const int64_t limit = std::min<int64_t>(kLdsSmallLimit, ctx->lds_per_block);
+    if (!force_glb && small <= limit) {
+      d.tier = kTierLds;
+      im.lds_bytes_small = std::max(im.lds_bytes_small, small);
+      im.q_lds.push_back(id);
+    } else if (big <= ctx->lds_per_block) {
+      d.tier = kTierGlobal;
+      im.lds_bytes_big = std::max(im.lds_bytes_big, big);
+      im.big_stack_words = std::max(im.big_stack_words, lds_stack_words(n, (int32_t)maxdeg));
+      im.q_big.push_back(id);
+    } else {
+      fail(MPLD_E_UNSUPPORTED, "component of " + std::to_string(n) + " nodes needs " +
+                                   std::to_string(big) + " bytes of LDS, more than the " +
+                                   std::to_string(ctx->lds_per_block) + " a workgroup gets");
+    }
+  }
+  im.desc.push_back(d);
+  im.total_nodes += n;
+  im.max_size = std::max(im.max_size, n);
+  im.core_edges += m;
+}
+
+void image_finish(Image& im) {
+  auto by_size = [&](int32_t a, int32_t b) {
+    if (im.desc[a].n != im.desc[b].n) return im.desc[a].n > im.desc[b].n;
+    return a < b;
+  };
+  std::sort(im.q_reg.begin(), im.q_reg.end(), by_size);
+  std::sort(im.q_lds.begin(), im.q_lds.end(), by_size);
+  std::sort(im.q_big.begin(), im.q_big.end(), by_size);
+}
+
+// ---------------------------------------------------------------------------
+
+DeviceBatch::~DeviceBatch() {
+  if (graph) hipGraphExecDestroy(graph);
+}
+
+static int blocks_for_lds(mpld_context* ctx, int lds_bytes) {
+  // one wave per workgroup: bounded by LDS and by 32 waves per CU
+  const int per_cu_lds = 160 * 1024;
+  int by_lds = lds_bytes > 0 ? per_cu_lds / lds_bytes : 32;
+  by_lds = std::max(1, std::min(by_lds, 32));
+  return by_lds * ctx->num_cus;
+}
+
+void device_upload(mpld_context* ctx, const Image& im, DeviceBatch& db) {
+  db.ctx = ctx;
+  db.num_comps = (int32_t)im.desc.size();
+  db.total_nodes = im.total_nodes;
+  db.n_reg = (int32_t)im.q_reg.size();
+  db.n_lds = (int32_t)im.q_lds.size();
+  db.n_big = (int32_t)im.q_big.size();
+  db.lds_small = (int)im.lds_bytes_small;
+  db.lds_big = (int)im.lds_bytes_big;
+  db.big_stack_words = (uint64_t)im.big_stack_words;
+  db.grid_reg = std::max(1, std::min((db.n_reg + 3) / 4, ctx->num_cus * ctx->reg_blocks_per_cu));
+  db.grid_lds = std::max(1, std::min(db.n_lds, blocks_for_lds(ctx, db.lds_small)));
+  db.grid_big = std::max(1, std::min(db.n_big, blocks_for_lds(ctx, db.lds_big)));
+
+  db.host_queue.clear();
+  db.host_queue.insert(db.host_queue.end(), im.q_reg.begin(), im.q_reg.end());
+  db.host_queue.insert(db.host_queue.end(), im.q_lds.begin(), im.q_lds.end());
+  db.host_queue.insert(db.host_queue.end(), im.q_big.begin(), im.q_big.end());
+
+  db.desc.alloc(ctx, sizeof(DevDesc) * im.desc.size());
+  db.masks.alloc(ctx, sizeof(uint64_t) * im.masks.size());
+  db.adj32.alloc(ctx, sizeof(uint32_t) * im.adj32.size());
+  db.queues.alloc(ctx, sizeof(int32_t) * db.host_queue.size());
+  db.counters.alloc(ctx, sizeof(int32_t) * 8);
+  db.recs.alloc(ctx, sizeof(DevRecord) * im.desc.size());
+  db.colors.alloc(ctx, (size_t)im.total_nodes);
+  if (db.n_big) db.gstack.alloc(ctx, sizeof(uint64_t) * db.big_stack_words * (size_t)db.grid_big);
+
+  hipStream_t s = ctx->stream;
+  check_hip(hipMemcpyAsync(db.desc.p, im.desc.data(), sizeof(DevDesc) * im.desc.size(),
+                           hipMemcpyHostToDevice, s), "upload descriptors");
+  if (!im.masks.empty())
+    check_hip(hipMemcpyAsync(db.masks.p, im.masks.data(), sizeof(uint64_t) * im.masks.size(),
+                             hipMemcpyHostToDevice, s), "upload masks");
+  if (!im.adj32.empty())
+    check_hip(hipMemcpyAsync(db.adj32.p, im.adj32.data(), sizeof(uint32_t) * im.adj32.size(),
+                             hipMemcpyHostToDevice, s), "upload adjacency");
+  if (!db.host_queue.empty())
+    check_hip(hipMemcpyAsync(db.queues.p, db.host_queue.data(),
+                             sizeof(int32_t) * db.host_queue.size(), hipMemcpyHostToDevice, s),
+              "upload queues");
+  check_hip(hipMemsetAsync(db.counters.p, 0, sizeof(int32_t) * 8, s), "clear counters");
+  check_hip(hipStreamSynchronize(s), "upload");
+}
+
+void device_solve(DeviceBatch& db, uint32_t flags) {
+  mpld_context* ctx = db.ctx;
+  hipStream_t s = ctx->stream;
+  const bool trace = flags & MPLD_TRACE_HASH;
+  const auto* desc = db.desc.as<DevDesc>();
+  const auto* masks = db.masks.as<uint64_t>();
+  const auto* adj = db.adj32.as<uint32_t>();
+  const auto* q = db.queues.as<int32_t>();
+  auto* cnt = db.counters.as<int32_t>();
+  auto* recs = db.recs.as<DevRecord>();
+  auto* colors = db.colors.as<int8_t>();
+  auto* gstack = db.gstack.as<uint64_t>();
+  db.launches = 0;
+  check_hip(hipEventRecord(ctx->ev[0], s), "event");
+  if (flags & MPLD_PLAIN) {
+    // one launch per component, same search code
+    for (int32_t i = 0; i < (int32_t)db.host_queue.size(); ++i) {
+      const int32_t comp = db.host_queue[i];
+      hipError_t e;
+      if (i < db.n_reg)
+        e = launch_reg_single(trace, desc, masks, comp, recs, colors, s);
+      else if (i < db.n_reg + db.n_lds)
+        e = launch_lds_single(trace, false, db.lds_small, desc, adj, comp, nullptr, recs, colors, s);
+      else
+        e = launch_lds_single(trace, true, db.lds_big, desc, adj, comp, gstack, recs, colors, s);
+      check_hip(e, "plain launch");
+      ++db.launches;
+    }
+  } else {
+    if (db.n_reg) {
+      check_hip(launch_reg_batched(trace, db.grid_reg, desc, masks, q, db.n_reg, cnt, recs, colors, s),
+                "register-tier launch");
+      ++db.launches;
+    }
+    if (db.n_lds) {
+      check_hip(launch_lds_batched(trace, false, db.grid_lds, db.lds_small, desc, adj, q + db.n_reg,
+                                   db.n_lds, cnt + 2, nullptr, 0, recs, colors, s),
+                "LDS-tier launch");
+      ++db.launches;
+    }
+    if (db.n_big) {
+      check_hip(launch_lds_batched(trace, true, db.grid_big, db.lds_big, desc, adj,
+                                   q + db.n_reg + db.n_lds, db.n_big, cnt + 4, gstack,
+                                   db.big_stack_words, recs, colors, s),
+                "big-tier launch");
+      ++db.launches;
+    }
+  }
+  check_hip(hipEventRecord(ctx->ev[1], s), "event");
+}
+
+void device_fetch(DeviceBatch& db, std::vector<DevRecord>& recs, std::vector<int8_t>& colors) {
+  mpld_context* ctx = db.ctx;
+  hipStream_t s = ctx->stream;
+  check_hip(hipStreamSynchronize(s), "search");
+  float ms = 0.f;
+  check_hip(hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[1]), "event time");
+  db.last_search_ms = ms;
+  db.last_total_ms = ms;
+  recs.resize((size_t)db.num_comps);
+  colors.resize((size_t)db.total_nodes);
+  if (db.num_comps)
+    check_hip(hipMemcpyAsync(recs.data(), db.recs.p, sizeof(DevRecord) * recs.size(),
+                             hipMemcpyDeviceToHost, s), "download records");
+  if (db.total_nodes)
+    check_hip(hipMemcpyAsync(colors.data(), db.colors.p, colors.size(), hipMemcpyDeviceToHost, s),
+              "download colors");
+  check_hip(hipStreamSynchronize(s), "download");
+  for (const auto& r : recs)
+    if (r.status < 0 || r.status > MPLD_BUDGET_EXHAUSTED)
+      fail(MPLD_E_INTERNAL, "search reported a broken state");
+}
+
+}  // namespace mpld
+
+void* mpld_context::dev_alloc(size_t bytes) {
+  void* p = nullptr;
+  if (has_alloc) {
+    p = alloc.alloc(bytes, alloc.user);
+    if (!p) mpld::fail(MPLD_E_NOMEM, "device allocator returned NULL for " + std::to_string(bytes) + " bytes");
+  } else {
+    mpld::check_hip(hipMalloc(&p, bytes), "hipMalloc");
+  }
+  return p;
+}
+
+void mpld_context::dev_free(void* p) {
+  if (!p) return;
+  if (has_alloc)
+    alloc.free(p, alloc.user);
+  else
+    (void)hipFree(p);
+}

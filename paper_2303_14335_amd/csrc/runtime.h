@@ -1,0 +1,137 @@
+// runtime.h - device context, device buffers, packed batches and kernel
+// launchers of the decomposer library (host side).
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+
+#include <memory>
+#include <vector>
+
+#include "device_types.h"
+#include "internal.h"
+
+namespace mpld {
+
+// kernel launchers (defined with the kernels)
+hipError_t launch_reg_batched(bool trace, int grid, const DevDesc* descs, const uint64_t* masks,
+                              const int32_t* queue, int32_t qlen, int32_t* counters,
+                              DevRecord* recs, int8_t* colors, hipStream_t s);
+hipError_t launch_reg_single(bool trace, const DevDesc* descs, const uint64_t* masks, int32_t comp,
+                             DevRecord* recs, int8_t* colors, hipStream_t s);
+int reg_batched_blocks_per_cu(bool trace);
+hipError_t launch_lds_batched(bool trace, bool big, int grid, int lds_bytes, const DevDesc* descs,
+                              const uint32_t* adj32, const int32_t* queue, int32_t qlen,
+                              int32_t* counters, uint64_t* gstack, uint64_t stack_words,
+                              DevRecord* recs, int8_t* colors, hipStream_t s);
+hipError_t launch_lds_single(bool trace, bool big, int lds_bytes, const DevDesc* descs,
+                             const uint32_t* adj32, int32_t comp, uint64_t* gstack,
+                             DevRecord* recs, int8_t* colors, hipStream_t s);
+// LDS bytes of one LDS-tier component (adj_words = n + 1 + 2m) and the
+// global stack words of a big one.
+int64_t lds_bytes_for(int32_t n, int32_t k, int64_t adj_words, int32_t max_deg, bool big);
+int64_t lds_stack_words(int32_t n, int32_t max_deg);
+
+void check_hip(hipError_t e, const char* what);
+
+}  // namespace mpld
+
+struct mpld_context {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  mpld_allocator alloc{};
+  bool has_alloc = false;
+  int num_cus = 0;
+  int reg_blocks_per_cu = 1;
+  int lds_per_block = 0;
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+
+  void* dev_alloc(size_t bytes);
+  void dev_free(void* p);
+};
+
+namespace mpld {
+
+// Device memory owned through the context's allocator.
+struct DevBuf {
+  mpld_context* ctx = nullptr;
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() { release(); }
+  void release() {
+    if (p && ctx) ctx->dev_free(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  void alloc(mpld_context* c, size_t n) {
+    release();
+    ctx = c;
+    bytes = n ? n : 256;
+    p = c->dev_alloc(bytes);
+  }
+  template <class T>
+  T* as() const { return static_cast<T*>(p); }
+};
+
+// Host-side packed exact-cover image of a set of components.
+struct Image {
+  std::vector<DevDesc> desc;
+  std::vector<uint64_t> masks;     // register tier: one neighbour mask per node
+  std::vector<uint32_t> adj32;     // LDS tiers: row offsets, ids, max degree
+  std::vector<int32_t> q_reg, q_lds, q_big;   // component ids per tier
+  int32_t total_nodes = 0;
+  int32_t max_size = 0;
+  int64_t core_edges = 0;
+  int64_t lds_bytes_small = 0;     // largest footprint on the LDS tier
+  int64_t lds_bytes_big = 0;       // largest footprint on the big tier
+  int64_t big_stack_words = 0;     // largest global stack of the big tier
+};
+
+// LDS byte limit for a component to keep its lists and stack in LDS.
+constexpr int64_t kLdsSmallLimit = 64 * 1024;
+
+// Adds one component (local numbering, pairs i < j or j < i) to the image.
+// Throws MPLD_E_UNSUPPORTED when a forced tier cannot take it or it does
+// not fit any tier.
+void image_add(Image& im, mpld_context* ctx, int32_t n, const int32_t* pairs, int64_t m,
+               int32_t k, int64_t budget, uint32_t flags);
+// Sorts each tier's queue by descending size (then id).
+void image_finish(Image& im);
+
+// Device copy of an image plus its outputs and queue counters.
+struct DeviceBatch {
+  mpld_context* ctx = nullptr;
+  DevBuf desc, masks, adj32, queues, counters, recs, colors, gstack;
+  int32_t n_reg = 0, n_lds = 0, n_big = 0;
+  int32_t num_comps = 0, total_nodes = 0;
+  int grid_reg = 1, grid_lds = 1, grid_big = 1;
+  int lds_small = 0, lds_big = 0;
+  uint64_t big_stack_words = 0;
+  float last_search_ms = 0.f, last_total_ms = 0.f;
+  int32_t launches = 0;
+  hipGraphExec_t graph = nullptr;
+  uint32_t graph_flags = 0xffffffffu;
+  std::vector<int32_t> host_queue;  // all queues, in launch order (for the plain solver)
+  ~DeviceBatch();
+};
+
+void device_upload(mpld_context* ctx, const Image& im, DeviceBatch& db);
+// Enqueues the search of every component on the context stream (no wait).
+void device_solve(DeviceBatch& db, uint32_t flags);
+// Waits, then copies records and colors back.
+void device_fetch(DeviceBatch& db, std::vector<DevRecord>& recs, std::vector<int8_t>& colors);
+
+}  // namespace mpld
+
+struct mpld_batch {
+  mpld_context* ctx = nullptr;
+  mpld::Graph g;
+  mpld::Split s;
+  mpld_options opt{};
+  mpld::Image im;
+  mpld::DeviceBatch db;
+  bool solved = false;
+};

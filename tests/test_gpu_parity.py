@@ -1,0 +1,195 @@
+"""GPU parity: the HIP search (through the C ABI) against the oracle.
+
+The bar is bit-exact: per component status, search-node count, trace hash,
+depth at stop, colors; per node colors and component ids after recovery;
+the Eq. 1 tallies.  Every case prints what names it before it runs.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workload
+from algx_literal import complete, cycle, grotzsch, petersen, random_graph, wheel
+from workload.configs import CONFIGS
+
+pytestmark = pytest.mark.gpu
+
+TRACE = 1 << 1
+SIMPLIFY = 1 << 0
+FORCE = {"wave": 1 << 3, "lds": 1 << 4, "global": 1 << 5}
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+def compare_decomposition(got, ref):
+    assert np.array_equal(got.component_of, ref.comp_of)
+    rc = ref.comps
+    gc = got.components
+    assert len(gc) == len(rc)
+    for f in ("size", "status", "nodes", "trace_hash", "depth_at_stop", "stitches",
+              "first_node", "num_edges"):
+        assert np.array_equal(gc[f], rc[f]), f
+    assert np.array_equal(got.colors, ref.colors)
+    assert (got.stitches, got.conflicts, got.uncolored) == (ref.stitches, ref.conflicts,
+                                                             ref.uncolored)
+
+
+def graph_of(cfg, n_rects=None):
+    w = CONFIGS[cfg]
+    rects, _ = workload.generate(n_rects or w.n_rects, w.side_nm, w.seed)
+    return w, rects
+
+
+@pytest.mark.parametrize("cfg", [0, 1])
+def test_config_parity(ctx, cfg):
+    import paper_2303_14335_amd as mp
+    w, rects = graph_of(cfg)
+    say("config", cfg, w.name)
+    g = mp.mpld_build_graph(rects, w.dmin_nm, w.split_len_nm)
+    ref = oracle.decompose(oracle.Graph(g.num_nodes, g.ce, g.se), w.k, w.budget)
+    got = mp.mpld_decompose(ctx, g, w.k, w.budget, SIMPLIFY | TRACE)
+    compare_decomposition(got, ref)
+
+
+def test_config2_parity_stitches(ctx):
+    import paper_2303_14335_amd as mp
+    w, rects = graph_of(2)
+    say("config 2", w.name)
+    g = mp.mpld_build_graph(rects, w.dmin_nm, w.split_len_nm)
+    ref = oracle.decompose(oracle.Graph(g.num_nodes, g.ce, g.se), w.k, w.budget)
+    got = mp.mpld_decompose(ctx, g, w.k, w.budget, SIMPLIFY | TRACE)
+    compare_decomposition(got, ref)
+    assert got.stitches > 0
+
+
+def test_config3_giant_parity(ctx):
+    import paper_2303_14335_amd as mp
+    w, rects = graph_of(3)
+    say("config 3", w.name)
+    g = mp.mpld_build_graph(rects, w.dmin_nm, w.split_len_nm)
+    ref = oracle.decompose(oracle.Graph(g.num_nodes, g.ce, g.se), w.k, w.budget)
+    got = mp.mpld_decompose(ctx, g, w.k, w.budget, SIMPLIFY | TRACE)
+    compare_decomposition(got, ref)
+    assert got.components["size"].max() > 30000
+
+
+def solve_both(ctx, comps, k, budget, flags):
+    import paper_2303_14335_amd as mp
+    recs, colors = mp.mpld_solve_components(ctx, comps, k, budget, flags | TRACE)
+    for (n, e), r, c in zip(comps, recs, colors):
+        s = oracle.solve_component(n, e, k, budget)
+        assert (int(r["status"]), int(r["nodes"]), int(r["trace_hash"]),
+                int(r["depth_at_stop"])) == (s.status, s.nodes, s.trace_hash,
+                                             s.depth_at_stop), (n, e, k, budget)
+        assert np.array_equal(c, s.colors)
+
+
+@pytest.mark.parametrize("tier", ["auto", "lds", "global"])
+def test_known_graphs_every_tier(ctx, tier):
+    say("known graphs, tier", tier)
+    flags = 0 if tier == "auto" else FORCE[tier]
+    cases = [(4, complete(4), 3), (4, complete(4), 4), (5, complete(5), 4), (3, complete(3), 2),
+             (7, cycle(7), 2), (8, cycle(8), 2), petersen() + (3,), grotzsch() + (3,),
+             wheel(5) + (3,), wheel(6) + (3,), (1, [], 3), (0, [], 3)]
+    for n, e, k in cases:
+        solve_both(ctx, [(n, e)], k, 10**6, flags)
+
+
+@pytest.mark.parametrize("k", [2, 3, 4, 5, 8])
+def test_random_components_vs_oracle(ctx, k):
+    rng = np.random.default_rng(1000 + k)
+    comps = []
+    for _ in range(300):
+        n = int(rng.integers(1, 65))
+        # near the k-colorability threshold so that the search backtracks
+        p = min(0.95, float(rng.uniform(0.5, 1.6)) * 2.0 * k / max(n, 1))
+        comps.append((n, random_graph(rng, n, p)))
+    say("random components k", k, "count", len(comps))
+    solve_both(ctx, comps, k, 20000, 0)
+
+
+def test_lane_and_tier_boundaries(ctx):
+    rng = np.random.default_rng(5)
+    comps = []
+    for n in (63, 64, 65, 127, 128, 129, 200):
+        comps.append((n, random_graph(rng, n, 4.5 / n)))
+        comps.append((n, cycle(n)))
+    say("boundary sizes")
+    for flags in (0, FORCE["lds"], FORCE["global"]):
+        solve_both(ctx, [c for c in comps if c[0] <= 64 or flags != 0 or True], 3, 50000, flags)
+
+
+def test_budget_sweep(ctx):
+    rng = np.random.default_rng(9)
+    comps = [(12, random_graph(rng, 12, 0.42)) for _ in range(6)]
+    say("budget sweep")
+    for b in list(range(1, 40)) + [100, 1000]:
+        solve_both(ctx, comps, 3, b, 0)
+        solve_both(ctx, comps, 3, b, FORCE["lds"])
+
+
+def test_larger_components_lds_tiers(ctx):
+    rng = np.random.default_rng(21)
+    comps = []
+    for n in (80, 150, 300, 600, 1200):
+        comps.append((n, random_graph(rng, n, 4.6 / n)))
+    say("larger components")
+    for flags in (0, FORCE["global"]):
+        solve_both(ctx, comps, 3, 30000, flags)
+
+
+def test_plain_equals_batched_and_trace_off(ctx):
+    import paper_2303_14335_amd as mp
+    w, rects = graph_of(2, 40000)
+    say("plain vs batched, 40k rects of config 2")
+    g = mp.mpld_build_graph(rects, w.dmin_nm, w.split_len_nm)
+    b = mp.Batch(ctx, g, w.k, 20000, SIMPLIFY | TRACE)
+    b.solve(plain=False)
+    r1 = b.result()
+    b.solve(plain=True)
+    r2 = b.result()
+    b.close()
+    for f in r1.components.dtype.names:
+        assert np.array_equal(r1.components[f], r2.components[f]), f
+    assert np.array_equal(r1.colors, r2.colors)
+    b = mp.Batch(ctx, g, w.k, 20000, SIMPLIFY)
+    b.solve()
+    r3 = b.result()
+    b.solve()   # a replay of the same batch gives the same result
+    r4 = b.result()
+    b.close()
+    for r in (r3, r4):
+        assert np.array_equal(r.colors, r1.colors)
+        assert np.array_equal(r.components["nodes"], r1.components["nodes"])
+        assert np.array_equal(r.components["status"], r1.components["status"])
+
+
+def test_simplify_off_isolated_nodes(ctx):
+    import paper_2303_14335_amd as mp
+    say("simplify off")
+    g = mp.Graph(6, np.array([[0, 1], [1, 2], [0, 2]]), np.zeros((0, 2), np.int32))
+    got = mp.mpld_decompose(ctx, g, 3, 1000, TRACE)
+    ref = oracle.decompose(oracle.Graph(6, g.ce, g.se), 3, 1000, simplify=False)
+    compare_decomposition(got, ref)
+    g0 = mp.Graph(0, np.zeros((0, 2), np.int32), np.zeros((0, 2), np.int32))
+    r0 = mp.mpld_decompose(ctx, g0, 3, 1000, SIMPLIFY)
+    assert len(r0.colors) == 0 and len(r0.components) == 0
+
+
+def test_invalid_arguments(ctx):
+    import paper_2303_14335_amd as mp
+    say("invalid arguments")
+    g = mp.Graph(3, np.array([[0, 3]]), np.zeros((0, 2), np.int32))
+    with pytest.raises(mp.MpldError) as e:
+        mp.mpld_decompose(ctx, g, 3, 10)
+    assert e.value.code == -1
+    g = mp.Graph(3, np.array([[0, 1]]), np.zeros((0, 2), np.int32))
+    for k, budget in ((1, 10), (9, 10), (3, 0)):
+        with pytest.raises(mp.MpldError) as e:
+            mp.mpld_decompose(ctx, g, k, budget)
+        assert e.value.code == -1
+    with pytest.raises(mp.MpldError) as e:
+        mp.mpld_solve_components(ctx, [(70, cycle(70))], 3, 10, FORCE["wave"])
+    assert e.value.code == -7
