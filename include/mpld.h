@@ -85,7 +85,9 @@ enum {
   MPLD_PLAIN = 1u << 2,        /* one kernel launch per component (comparison) */
   MPLD_FORCE_WAVE = 1u << 3,   /* force the register tier (n <= 64)           */
   MPLD_FORCE_LDS = 1u << 4,    /* force the LDS tier                          */
-  MPLD_FORCE_GLOBAL = 1u << 5  /* force the global-memory tier                */
+  MPLD_FORCE_GLOBAL = 1u << 5, /* force the global-memory tier                */
+  MPLD_DIRECT = 1u << 6        /* batched solve: launch the kernels directly
+                                  instead of replaying the captured HIP graph */
 };
 
 typedef struct { int32_t x0, y0, x1, y1; } mpld_rect;  /* nm, closed box */
@@ -180,18 +182,20 @@ int32_t mpld_decompose(mpld_context* ctx, const mpld_graph* g,
  * mpld_batch_create runs the host front-end (simplification, sub-graphs,
  * exact-cover packing) and uploads the packed image to device memory.
  * mpld_batch_solve enqueues the whole device search on the context stream
- * (queue reset, tiered persistent search or, with MPLD_PLAIN in `flags`,
- * one launch per component; per-component results stay on the device); it
- * does not wait.  mpld_batch_result waits, copies the results back and runs
+ * and does not wait: by default the tiered persistent kernels, captured
+ * once into a HIP graph and replayed (MPLD_DIRECT in `flags` launches them
+ * directly); with MPLD_PLAIN one launch per component.  Queue counters
+ * reset themselves at the end of each launch, so no memset is enqueued.
+ * Per-component results stay on the device.  mpld_batch_result waits, copies the results back and runs
  * recovery and the Eq. 1 tallies. */
 int32_t mpld_batch_create(mpld_context* ctx, const mpld_graph* g,
                           const mpld_options* opt, mpld_batch** out);
 int32_t mpld_batch_solve(mpld_batch* b, uint32_t flags);
 int32_t mpld_batch_result(mpld_batch* b, mpld_result** out);
 /* Batch statistics: components per tier, core nodes, image bytes, and the
- * device time (ms) of the last solve's search kernels measured with HIP
- * events on the context stream (valid after mpld_batch_result or a stream
- * synchronisation). */
+ * device time (ms) of the last solve's search launches measured with HIP
+ * events recorded on the context stream right around them (read after
+ * mpld_batch_result or once the stream has drained; 0 before). */
 typedef struct {
   int32_t num_components;
   int32_t num_wave;          /* components on the register tier (n <= 64) */

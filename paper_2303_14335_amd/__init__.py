@@ -109,20 +109,25 @@ class _TorchAllocator:
 
 
 class Context:
-    """One device, one stream (torch's current stream by default)."""
+    """One device and one stream.  With use_torch the device memory comes
+    from torch's caching allocator and the work runs on ``self.stream``, a
+    torch stream of default priority (give it to torch.cuda.Event.record to
+    time the library's launches)."""
 
     def __init__(self, device: int = 0, use_torch: bool = True):
         self.handle = ctypes.c_void_p()
         self._alloc = None
-        stream = None
+        self.stream = None
+        handle = None
         alloc_ptr = None
         if use_torch:
             import torch
             dev = torch.device("cuda", device)
             self._alloc = _TorchAllocator(dev)
             alloc_ptr = ctypes.byref(self._alloc.struct)
-            stream = ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
-        _check(_lib.mpld_context_create(device, alloc_ptr, stream, ctypes.byref(self.handle)),
+            self.stream = torch.cuda.Stream(dev)
+            handle = ctypes.c_void_p(self.stream.cuda_stream)
+        _check(_lib.mpld_context_create(device, alloc_ptr, handle, ctypes.byref(self.handle)),
                "mpld_context_create")
 
     def close(self):
@@ -201,8 +206,9 @@ class Batch:
         _check(_lib.mpld_batch_create(ctx.handle, ctypes.byref(view), ctypes.byref(opt),
                                       ctypes.byref(self.handle)), "mpld_batch_create")
 
-    def solve(self, plain: bool = False) -> None:
-        _check(_lib.mpld_batch_solve(self.handle, MPLD_PLAIN if plain else 0), "mpld_batch_solve")
+    def solve(self, plain: bool = False, direct: bool = False) -> None:
+        flags = (MPLD_PLAIN if plain else 0) | (_ffi.MPLD_DIRECT if direct else 0)
+        _check(_lib.mpld_batch_solve(self.handle, flags), "mpld_batch_solve")
 
     def result(self) -> Result:
         h = ctypes.c_void_p()
@@ -231,8 +237,8 @@ def mpld_batch_create(ctx: Context, g: Graph, k: int, budget: int,
     return Batch(ctx, g, k, budget, flags)
 
 
-def mpld_batch_solve(b: Batch, plain: bool = False) -> None:
-    b.solve(plain)
+def mpld_batch_solve(b: Batch, plain: bool = False, direct: bool = False) -> None:
+    b.solve(plain, direct)
 
 
 def mpld_batch_result(b: Batch) -> Result:

@@ -196,6 +196,7 @@ int32_t mpld_context_create(int32_t device, const mpld_allocator* alloc, void* h
       }
       for (auto& e : ctx->ev) check_hip(hipEventCreate(&e), "event");
       ctx->reg_blocks_per_cu = reg_batched_blocks_per_cu(false);
+      lds_configure(ctx->lds_per_block);
     } catch (...) {
       mpld_context_destroy(ctx);
       throw;
@@ -236,7 +237,8 @@ int32_t mpld_batch_solve(mpld_batch* b, uint32_t flags) {
   return guard([&] {
     if (!b) fail(MPLD_E_INVALID, "batch is NULL");
     use_device(b->ctx);
-    device_solve(b->db, (b->opt.flags & ~MPLD_PLAIN) | (flags & MPLD_PLAIN));
+    const uint32_t how = MPLD_PLAIN | MPLD_DIRECT;
+    device_solve(b->db, (b->opt.flags & ~how) | (flags & how));
     b->solved = true;
   });
 }
@@ -261,6 +263,8 @@ int32_t mpld_batch_result(mpld_batch* b, mpld_result** out) {
 int32_t mpld_batch_get_info(mpld_batch* b, mpld_batch_info* info) {
   return guard([&] {
     if (!b || !info) fail(MPLD_E_INVALID, "NULL argument");
+    use_device(b->ctx);
+    device_time(b->db);
     std::memset(info, 0, sizeof(*info));
     info->num_components = b->db.num_comps;
     info->num_wave = b->db.n_reg;
@@ -268,8 +272,7 @@ int32_t mpld_batch_get_info(mpld_batch* b, mpld_batch_info* info) {
     info->num_global = b->db.n_big;
     info->core_nodes = b->im.total_nodes;
     info->max_size = b->im.max_size;
-    info->image_bytes = (int64_t)(b->db.desc.bytes + b->db.masks.bytes + b->db.adj32.bytes +
-                                  b->db.queues.bytes);
+    info->image_bytes = (int64_t)(b->db.desc.bytes + b->db.masks.bytes + b->db.adj32.bytes);
     info->core_edges = b->im.core_edges;
     info->last_search_ms = b->db.last_search_ms;
     info->last_total_ms = b->db.last_total_ms;
@@ -294,7 +297,7 @@ int32_t mpld_decompose(mpld_context* ctx, const mpld_graph* g, const mpld_option
     use_device(ctx);
     mpld_batch b;
     batch_build(ctx, g, opt, &b);
-    device_solve(b.db, opt->flags);
+    device_solve(b.db, opt->flags | MPLD_DIRECT);   // one-shot: no graph to capture
     b.solved = true;
     auto* r = new mpld_result();
     try {
@@ -342,7 +345,7 @@ int32_t mpld_solve_components(mpld_context* ctx, const mpld_component* comps, in
     image_finish(im);
     DeviceBatch db;
     device_upload(ctx, im, db);
-    device_solve(db, opt->flags);
+    device_solve(db, opt->flags | MPLD_DIRECT);
     std::vector<DevRecord> recs;
     std::vector<int8_t> lcol;
     device_fetch(db, recs, lcol);

@@ -8,7 +8,9 @@ namespace mpld {
 
 enum Tier : int32_t { kTierReg = 0, kTierLds = 1, kTierGlobal = 2 };
 
-// One descriptor per component (32 bytes).
+// One descriptor per component (32 bytes).  On the device the descriptors
+// of each tier are stored contiguously in that tier's launch order (largest
+// component first), so a wave's work item indexes them directly.
 //   register tier: nbr_off indexes `masks` (one uint64 neighbour mask per
 //                  local node, bit u set iff u is a conflict neighbour).
 //   LDS / global tier: nbr_off indexes `adj32`: n+1 row offsets (relative to
@@ -19,7 +21,7 @@ struct DevDesc {
   int64_t budget;   // search-node budget
   int64_t nbr_off;
   int32_t out_off;  // first entry of the component in the colors output
-  int32_t tier;
+  int32_t comp;     // component id: index of its record
 };
 static_assert(sizeof(DevDesc) == 32, "descriptor is 32 bytes");
 

@@ -28,10 +28,10 @@ void image_add(Image& im, mpld_context* ctx, int32_t n, const int32_t* pairs, in
   d.budget = budget;
   d.out_off = im.total_nodes;
   const int32_t id = (int32_t)im.desc.size();
+  d.comp = id;
   const bool force_lds = flags & MPLD_FORCE_LDS, force_glb = flags & MPLD_FORCE_GLOBAL,
              force_reg = flags & MPLD_FORCE_WAVE;
   if (n <= 64 && !force_lds && !force_glb) {
-    d.tier = kTierReg;
     d.nbr_off = (int64_t)im.masks.size();
     im.masks.resize(im.masks.size() + (size_t)n, 0ull);
     uint64_t* mk = im.masks.data() + d.nbr_off;
@@ -69,11 +69,9 @@ void image_add(Image& im, mpld_context* ctx, int32_t n, const int32_t* pairs, in
     const int64_t big = lds_bytes_for(n, k, adj_words, (int32_t)maxdeg, true);
     const int64_t limit = std::min<int64_t>(kLdsSmallLimit, ctx->lds_per_block);
     if (!force_glb && small <= limit) {
-      d.tier = kTierLds;
       im.lds_bytes_small = std::max(im.lds_bytes_small, small);
       im.q_lds.push_back(id);
     } else if (big <= ctx->lds_per_block) {
-      d.tier = kTierGlobal;
       im.lds_bytes_big = std::max(im.lds_bytes_big, big);
       im.big_stack_words = std::max(im.big_stack_words, lds_stack_words(n, (int32_t)maxdeg));
       im.q_big.push_back(id);
@@ -115,6 +113,7 @@ static int blocks_for_lds(mpld_context* ctx, int lds_bytes) {
 
 void device_upload(mpld_context* ctx, const Image& im, DeviceBatch& db) {
   db.ctx = ctx;
+  db.k = im.desc.empty() ? 3 : im.desc[0].k;
   db.num_comps = (int32_t)im.desc.size();
   db.total_nodes = im.total_nodes;
   db.n_reg = (int32_t)im.q_reg.size();
@@ -132,91 +131,140 @@ void device_upload(mpld_context* ctx, const Image& im, DeviceBatch& db) {
   db.host_queue.insert(db.host_queue.end(), im.q_lds.begin(), im.q_lds.end());
   db.host_queue.insert(db.host_queue.end(), im.q_big.begin(), im.q_big.end());
 
-  db.desc.alloc(ctx, sizeof(DevDesc) * im.desc.size());
+  std::vector<DevDesc> ordered;
+  ordered.reserve(db.host_queue.size());
+  for (int32_t c : db.host_queue) ordered.push_back(im.desc[c]);
+
+  db.desc.alloc(ctx, sizeof(DevDesc) * ordered.size());
   db.masks.alloc(ctx, sizeof(uint64_t) * im.masks.size());
   db.adj32.alloc(ctx, sizeof(uint32_t) * im.adj32.size());
-  db.queues.alloc(ctx, sizeof(int32_t) * db.host_queue.size());
   db.counters.alloc(ctx, sizeof(int32_t) * 8);
   db.recs.alloc(ctx, sizeof(DevRecord) * im.desc.size());
   db.colors.alloc(ctx, (size_t)im.total_nodes);
   if (db.n_big) db.gstack.alloc(ctx, sizeof(uint64_t) * db.big_stack_words * (size_t)db.grid_big);
 
   hipStream_t s = ctx->stream;
-  check_hip(hipMemcpyAsync(db.desc.p, im.desc.data(), sizeof(DevDesc) * im.desc.size(),
-                           hipMemcpyHostToDevice, s), "upload descriptors");
+  if (!ordered.empty())
+    check_hip(hipMemcpyAsync(db.desc.p, ordered.data(), sizeof(DevDesc) * ordered.size(),
+                             hipMemcpyHostToDevice, s), "upload descriptors");
   if (!im.masks.empty())
     check_hip(hipMemcpyAsync(db.masks.p, im.masks.data(), sizeof(uint64_t) * im.masks.size(),
                              hipMemcpyHostToDevice, s), "upload masks");
   if (!im.adj32.empty())
     check_hip(hipMemcpyAsync(db.adj32.p, im.adj32.data(), sizeof(uint32_t) * im.adj32.size(),
                              hipMemcpyHostToDevice, s), "upload adjacency");
-  if (!db.host_queue.empty())
-    check_hip(hipMemcpyAsync(db.queues.p, db.host_queue.data(),
-                             sizeof(int32_t) * db.host_queue.size(), hipMemcpyHostToDevice, s),
-              "upload queues");
   check_hip(hipMemsetAsync(db.counters.p, 0, sizeof(int32_t) * 8, s), "clear counters");
   check_hip(hipStreamSynchronize(s), "upload");
+}
+
+static void enqueue_batched(DeviceBatch& db, bool trace, hipStream_t s) {
+  const auto* desc = db.desc.as<DevDesc>();
+  const auto* masks = db.masks.as<uint64_t>();
+  const auto* adj = db.adj32.as<uint32_t>();
+  auto* cnt = db.counters.as<int32_t>();
+  auto* recs = db.recs.as<DevRecord>();
+  auto* colors = db.colors.as<int8_t>();
+  auto* gstack = db.gstack.as<uint64_t>();
+  db.launches = 0;
+  if (db.n_reg) {
+    check_hip(launch_reg_batched(trace, db.k, db.grid_reg, desc, masks, db.n_reg, cnt, recs, colors, s),
+              "register-tier launch");
+    ++db.launches;
+  }
+  if (db.n_lds) {
+    check_hip(launch_lds_batched(trace, false, db.grid_lds, db.lds_small, desc + db.n_reg, adj,
+                                 db.n_lds, cnt + 1, nullptr, 0, recs, colors, s),
+              "LDS-tier launch");
+    ++db.launches;
+  }
+  if (db.n_big) {
+    check_hip(launch_lds_batched(trace, true, db.grid_big, db.lds_big, desc + db.n_reg + db.n_lds,
+                                 adj, db.n_big, cnt + 2, gstack, db.big_stack_words, recs, colors,
+                                 s),
+              "big-tier launch");
+    ++db.launches;
+  }
 }
 
 void device_solve(DeviceBatch& db, uint32_t flags) {
   mpld_context* ctx = db.ctx;
   hipStream_t s = ctx->stream;
   const bool trace = flags & MPLD_TRACE_HASH;
-  const auto* desc = db.desc.as<DevDesc>();
-  const auto* masks = db.masks.as<uint64_t>();
-  const auto* adj = db.adj32.as<uint32_t>();
-  const auto* q = db.queues.as<int32_t>();
-  auto* cnt = db.counters.as<int32_t>();
-  auto* recs = db.recs.as<DevRecord>();
-  auto* colors = db.colors.as<int8_t>();
-  auto* gstack = db.gstack.as<uint64_t>();
-  db.launches = 0;
-  check_hip(hipEventRecord(ctx->ev[0], s), "event");
+  db.timed = false;
   if (flags & MPLD_PLAIN) {
     // one launch per component, same search code
+    const auto* desc = db.desc.as<DevDesc>();
+    const auto* masks = db.masks.as<uint64_t>();
+    const auto* adj = db.adj32.as<uint32_t>();
+    auto* recs = db.recs.as<DevRecord>();
+    auto* colors = db.colors.as<int8_t>();
+    auto* gstack = db.gstack.as<uint64_t>();
+    db.launches = 0;
+    check_hip(hipEventRecord(ctx->ev[0], s), "event");
     for (int32_t i = 0; i < (int32_t)db.host_queue.size(); ++i) {
-      const int32_t comp = db.host_queue[i];
       hipError_t e;
       if (i < db.n_reg)
-        e = launch_reg_single(trace, desc, masks, comp, recs, colors, s);
+        e = launch_reg_single(trace, db.k, desc, masks, i, recs, colors, s);
       else if (i < db.n_reg + db.n_lds)
-        e = launch_lds_single(trace, false, db.lds_small, desc, adj, comp, nullptr, recs, colors, s);
+        e = launch_lds_single(trace, false, db.lds_small, desc, adj, i, nullptr, recs, colors, s);
       else
-        e = launch_lds_single(trace, true, db.lds_big, desc, adj, comp, gstack, recs, colors, s);
+        e = launch_lds_single(trace, true, db.lds_big, desc, adj, i, gstack, recs, colors, s);
       check_hip(e, "plain launch");
       ++db.launches;
     }
+    check_hip(hipEventRecord(ctx->ev[1], s), "event");
+  } else if (flags & MPLD_DIRECT) {
+    check_hip(hipEventRecord(ctx->ev[0], s), "event");
+    enqueue_batched(db, trace, s);
+    check_hip(hipEventRecord(ctx->ev[1], s), "event");
   } else {
-    if (db.n_reg) {
-      check_hip(launch_reg_batched(trace, db.grid_reg, desc, masks, q, db.n_reg, cnt, recs, colors, s),
-                "register-tier launch");
-      ++db.launches;
+    // capture the tiered launches once, replay the graph afterwards
+    const uint32_t key = trace ? 1u : 0u;
+    if (!db.graph || db.graph_flags != key) {
+      if (db.graph) {
+        check_hip(hipGraphExecDestroy(db.graph), "graph destroy");
+        db.graph = nullptr;
+      }
+      hipGraph_t g = nullptr;
+      check_hip(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed), "begin capture");
+      try {
+        enqueue_batched(db, trace, s);
+      } catch (...) {
+        (void)hipStreamEndCapture(s, &g);
+        if (g) (void)hipGraphDestroy(g);
+        throw;
+      }
+      check_hip(hipStreamEndCapture(s, &g), "end capture");
+      hipError_t e = hipGraphInstantiate(&db.graph, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      check_hip(e, "graph instantiate");
+      db.graph_flags = key;
     }
-    if (db.n_lds) {
-      check_hip(launch_lds_batched(trace, false, db.grid_lds, db.lds_small, desc, adj, q + db.n_reg,
-                                   db.n_lds, cnt + 2, nullptr, 0, recs, colors, s),
-                "LDS-tier launch");
-      ++db.launches;
-    }
-    if (db.n_big) {
-      check_hip(launch_lds_batched(trace, true, db.grid_big, db.lds_big, desc, adj,
-                                   q + db.n_reg + db.n_lds, db.n_big, cnt + 4, gstack,
-                                   db.big_stack_words, recs, colors, s),
-                "big-tier launch");
-      ++db.launches;
-    }
+    check_hip(hipEventRecord(ctx->ev[0], s), "event");
+    check_hip(hipGraphLaunch(db.graph, s), "graph launch");
+    check_hip(hipEventRecord(ctx->ev[1], s), "event");
   }
-  check_hip(hipEventRecord(ctx->ev[1], s), "event");
+  db.timed = true;
+}
+
+bool device_time(DeviceBatch& db) {
+  if (!db.timed) return false;
+  float ms = 0.f;
+  const hipError_t e = hipEventElapsedTime(&ms, db.ctx->ev[0], db.ctx->ev[1]);
+  if (e == hipErrorNotReady) return false;
+  check_hip(e, "event time");
+  db.last_search_ms = ms;
+  db.last_total_ms = ms;
+  db.timed = false;
+  return true;
 }
 
 void device_fetch(DeviceBatch& db, std::vector<DevRecord>& recs, std::vector<int8_t>& colors) {
   mpld_context* ctx = db.ctx;
   hipStream_t s = ctx->stream;
+  (void)ctx;
   check_hip(hipStreamSynchronize(s), "search");
-  float ms = 0.f;
-  check_hip(hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[1]), "event time");
-  db.last_search_ms = ms;
-  db.last_total_ms = ms;
+  device_time(db);
   recs.resize((size_t)db.num_comps);
   colors.resize((size_t)db.total_nodes);
   if (db.num_comps)

@@ -13,23 +13,26 @@
 namespace mpld {
 
 // kernel launchers (defined with the kernels)
-hipError_t launch_reg_batched(bool trace, int grid, const DevDesc* descs, const uint64_t* masks,
-                              const int32_t* queue, int32_t qlen, int32_t* counters,
+// k: the batch's mask count (every component of a batch shares it).
+hipError_t launch_reg_batched(bool trace, int k, int grid, const DevDesc* descs,
+                              const uint64_t* masks, int32_t qlen, int32_t* counter,
                               DevRecord* recs, int8_t* colors, hipStream_t s);
-hipError_t launch_reg_single(bool trace, const DevDesc* descs, const uint64_t* masks, int32_t comp,
-                             DevRecord* recs, int8_t* colors, hipStream_t s);
+hipError_t launch_reg_single(bool trace, int k, const DevDesc* descs, const uint64_t* masks,
+                             int32_t item, DevRecord* recs, int8_t* colors, hipStream_t s);
 int reg_batched_blocks_per_cu(bool trace);
 hipError_t launch_lds_batched(bool trace, bool big, int grid, int lds_bytes, const DevDesc* descs,
-                              const uint32_t* adj32, const int32_t* queue, int32_t qlen,
-                              int32_t* counters, uint64_t* gstack, uint64_t stack_words,
-                              DevRecord* recs, int8_t* colors, hipStream_t s);
+                              const uint32_t* adj32, int32_t qlen, int32_t* counter,
+                              uint64_t* gstack, uint64_t stack_words, DevRecord* recs,
+                              int8_t* colors, hipStream_t s);
 hipError_t launch_lds_single(bool trace, bool big, int lds_bytes, const DevDesc* descs,
-                             const uint32_t* adj32, int32_t comp, uint64_t* gstack,
+                             const uint32_t* adj32, int32_t item, uint64_t* gstack,
                              DevRecord* recs, int8_t* colors, hipStream_t s);
 // LDS bytes of one LDS-tier component (adj_words = n + 1 + 2m) and the
 // global stack words of a big one.
 int64_t lds_bytes_for(int32_t n, int32_t k, int64_t adj_words, int32_t max_deg, bool big);
 int64_t lds_stack_words(int32_t n, int32_t max_deg);
+// Allows every LDS-tier kernel up to `bytes` of dynamic LDS (once per context).
+void lds_configure(int bytes);
 
 void check_hip(hipError_t e, const char* what);
 
@@ -78,7 +81,7 @@ struct DevBuf {
 
 // Host-side packed exact-cover image of a set of components.
 struct Image {
-  std::vector<DevDesc> desc;
+  std::vector<DevDesc> desc;       // by component id
   std::vector<uint64_t> masks;     // register tier: one neighbour mask per node
   std::vector<uint32_t> adj32;     // LDS tiers: row offsets, ids, max degree
   std::vector<int32_t> q_reg, q_lds, q_big;   // component ids per tier
@@ -104,9 +107,10 @@ void image_finish(Image& im);
 // Device copy of an image plus its outputs and queue counters.
 struct DeviceBatch {
   mpld_context* ctx = nullptr;
-  DevBuf desc, masks, adj32, queues, counters, recs, colors, gstack;
+  DevBuf desc, masks, adj32, counters, recs, colors, gstack;  // desc in launch order
   int32_t n_reg = 0, n_lds = 0, n_big = 0;
   int32_t num_comps = 0, total_nodes = 0;
+  int32_t k = 3;
   int grid_reg = 1, grid_lds = 1, grid_big = 1;
   int lds_small = 0, lds_big = 0;
   uint64_t big_stack_words = 0;
@@ -114,13 +118,16 @@ struct DeviceBatch {
   int32_t launches = 0;
   hipGraphExec_t graph = nullptr;
   uint32_t graph_flags = 0xffffffffu;
-  std::vector<int32_t> host_queue;  // all queues, in launch order (for the plain solver)
+  bool timed = false;               // events of the last solve not read yet
+  std::vector<int32_t> host_queue;  // component ids in launch order (all tiers)
   ~DeviceBatch();
 };
 
 void device_upload(mpld_context* ctx, const Image& im, DeviceBatch& db);
 // Enqueues the search of every component on the context stream (no wait).
 void device_solve(DeviceBatch& db, uint32_t flags);
+// Reads the last solve's event time if the stream has passed it.
+bool device_time(DeviceBatch& db);
 // Waits, then copies records and colors back.
 void device_fetch(DeviceBatch& db, std::vector<DevRecord>& recs, std::vector<int8_t>& colors);
 

@@ -291,44 +291,39 @@ done:
   __syncthreads();
 }
 
-// Persistent kernel, one wave per workgroup: pops components until the
-// queue is empty.  counters[0] = queue head, counters[1] = finished waves;
-// the last wave to finish resets both, so the kernel can be replayed.
+// Persistent kernel, one wave per workgroup; work distribution as in the
+// register tier: static first item, then atomic pops, the last pop resets
+// the counter.
 template <bool TRACE, bool BIG>
 __global__ __launch_bounds__(64) void lds_batched_kernel(
-    const DevDesc* __restrict__ descs, const uint32_t* __restrict__ adj32,
-    const int32_t* __restrict__ queue, int32_t qlen, int32_t* __restrict__ counters,
-    int32_t total_waves, uint64_t* gstack, uint64_t stack_words_per_wave,
+    const DevDesc* __restrict__ descs, const uint32_t* __restrict__ adj32, int32_t qlen,
+    int32_t* __restrict__ counter, uint64_t* gstack, uint64_t stack_words_per_wave,
     DevRecord* __restrict__ recs, int8_t* __restrict__ colors) {
   extern __shared__ __align__(16) char lds[];
   uint64_t* my_stack = BIG ? gstack + (uint64_t)blockIdx.x * stack_words_per_wave : nullptr;
-  for (;;) {
-    int32_t item = 0;
-    if (__lane_id() == 0) item = atomicAdd(&counters[0], 1);
-    item = (int32_t)uni((uint32_t)item);
-    if (item >= qlen) break;
-    const int32_t comp = (int32_t)uni((uint32_t)queue[item]);
-    const DevDesc d = descs[comp];
-    solve_lds<TRACE, BIG>(d, adj32 + d.nbr_off, lds, my_stack, colors + d.out_off, recs + comp);
-  }
-  if (__lane_id() == 0) {
-    const int32_t done = atomicAdd(&counters[1], 1);
-    if (done == total_waves - 1) {
-      atomicExch(&counters[0], 0);
-      atomicExch(&counters[1], 0);
-    }
+  const int32_t gw = (int32_t)gridDim.x;
+  int32_t item = (int32_t)uni(blockIdx.x);
+  while (item < qlen) {
+    const DevDesc d = descs[item];
+    solve_lds<TRACE, BIG>(d, adj32 + d.nbr_off, lds, my_stack, colors + d.out_off, recs + d.comp);
+    if (gw >= qlen) break;
+    int32_t r = 0;
+    if (__lane_id() == 0) r = atomicAdd(counter, 1);
+    r = (int32_t)uni((uint32_t)r);
+    item = gw + r;
+    if (r == qlen - 1) atomicExch(counter, 0);
   }
 }
 
 template <bool TRACE, bool BIG>
 __global__ __launch_bounds__(64) void lds_single_kernel(const DevDesc* __restrict__ descs,
                                                         const uint32_t* __restrict__ adj32,
-                                                        int32_t comp, uint64_t* gstack,
+                                                        int32_t item, uint64_t* gstack,
                                                         DevRecord* __restrict__ recs,
                                                         int8_t* __restrict__ colors) {
   extern __shared__ __align__(16) char lds[];
-  const DevDesc d = descs[comp];
-  solve_lds<TRACE, BIG>(d, adj32 + d.nbr_off, lds, gstack, colors + d.out_off, recs + comp);
+  const DevDesc d = descs[item];
+  solve_lds<TRACE, BIG>(d, adj32 + d.nbr_off, lds, gstack, colors + d.out_off, recs + d.comp);
 }
 
 // ---- host side --------------------------------------------------------------
@@ -343,52 +338,64 @@ int64_t lds_stack_words(int32_t n, int32_t max_deg) {
 }
 
 template <bool TRACE, bool BIG>
+static void lds_attr(int bytes) {
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&lds_batched_kernel<TRACE, BIG>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&lds_single_kernel<TRACE, BIG>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+}
+
+void lds_configure(int bytes) {
+  lds_attr<true, true>(bytes);
+  lds_attr<true, false>(bytes);
+  lds_attr<false, true>(bytes);
+  lds_attr<false, false>(bytes);
+  (void)hipGetLastError();
+}
+
+template <bool TRACE, bool BIG>
 static hipError_t lds_batched_t(int grid, int lds_bytes, const DevDesc* descs,
-                                const uint32_t* adj32, const int32_t* queue, int32_t qlen,
-                                int32_t* counters, uint64_t* gstack, uint64_t stack_words,
-                                DevRecord* recs, int8_t* colors, hipStream_t s) {
-  hipFuncSetAttribute(reinterpret_cast<const void*>(&lds_batched_kernel<TRACE, BIG>),
-                      hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
+                                const uint32_t* adj32, int32_t qlen, int32_t* counter,
+                                uint64_t* gstack, uint64_t stack_words, DevRecord* recs,
+                                int8_t* colors, hipStream_t s) {
   hipLaunchKernelGGL((lds_batched_kernel<TRACE, BIG>), dim3(grid), dim3(64), (size_t)lds_bytes, s,
-                     descs, adj32, queue, qlen, counters, grid, gstack, stack_words, recs, colors);
+                     descs, adj32, qlen, counter, gstack, stack_words, recs, colors);
   return hipGetLastError();
 }
 
 hipError_t launch_lds_batched(bool trace, bool big, int grid, int lds_bytes, const DevDesc* descs,
-                              const uint32_t* adj32, const int32_t* queue, int32_t qlen,
-                              int32_t* counters, uint64_t* gstack, uint64_t stack_words,
-                              DevRecord* recs, int8_t* colors, hipStream_t s) {
+                              const uint32_t* adj32, int32_t qlen, int32_t* counter,
+                              uint64_t* gstack, uint64_t stack_words, DevRecord* recs,
+                              int8_t* colors, hipStream_t s) {
   if (qlen <= 0) return hipSuccess;
   if (trace)
-    return big ? lds_batched_t<true, true>(grid, lds_bytes, descs, adj32, queue, qlen, counters,
-                                           gstack, stack_words, recs, colors, s)
-               : lds_batched_t<true, false>(grid, lds_bytes, descs, adj32, queue, qlen, counters,
-                                            gstack, stack_words, recs, colors, s);
-  return big ? lds_batched_t<false, true>(grid, lds_bytes, descs, adj32, queue, qlen, counters,
-                                          gstack, stack_words, recs, colors, s)
-             : lds_batched_t<false, false>(grid, lds_bytes, descs, adj32, queue, qlen, counters,
-                                           gstack, stack_words, recs, colors, s);
+    return big ? lds_batched_t<true, true>(grid, lds_bytes, descs, adj32, qlen, counter, gstack,
+                                           stack_words, recs, colors, s)
+               : lds_batched_t<true, false>(grid, lds_bytes, descs, adj32, qlen, counter, gstack,
+                                            stack_words, recs, colors, s);
+  return big ? lds_batched_t<false, true>(grid, lds_bytes, descs, adj32, qlen, counter, gstack,
+                                          stack_words, recs, colors, s)
+             : lds_batched_t<false, false>(grid, lds_bytes, descs, adj32, qlen, counter, gstack,
+                                           stack_words, recs, colors, s);
 }
 
 template <bool TRACE, bool BIG>
 static hipError_t lds_single_t(int lds_bytes, const DevDesc* descs, const uint32_t* adj32,
-                               int32_t comp, uint64_t* gstack, DevRecord* recs, int8_t* colors,
+                               int32_t item, uint64_t* gstack, DevRecord* recs, int8_t* colors,
                                hipStream_t s) {
-  hipFuncSetAttribute(reinterpret_cast<const void*>(&lds_single_kernel<TRACE, BIG>),
-                      hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
   hipLaunchKernelGGL((lds_single_kernel<TRACE, BIG>), dim3(1), dim3(64), (size_t)lds_bytes, s,
-                     descs, adj32, comp, gstack, recs, colors);
+                     descs, adj32, item, gstack, recs, colors);
   return hipGetLastError();
 }
 
 hipError_t launch_lds_single(bool trace, bool big, int lds_bytes, const DevDesc* descs,
-                             const uint32_t* adj32, int32_t comp, uint64_t* gstack,
+                             const uint32_t* adj32, int32_t item, uint64_t* gstack,
                              DevRecord* recs, int8_t* colors, hipStream_t s) {
   if (trace)
-    return big ? lds_single_t<true, true>(lds_bytes, descs, adj32, comp, gstack, recs, colors, s)
-               : lds_single_t<true, false>(lds_bytes, descs, adj32, comp, gstack, recs, colors, s);
-  return big ? lds_single_t<false, true>(lds_bytes, descs, adj32, comp, gstack, recs, colors, s)
-             : lds_single_t<false, false>(lds_bytes, descs, adj32, comp, gstack, recs, colors, s);
+    return big ? lds_single_t<true, true>(lds_bytes, descs, adj32, item, gstack, recs, colors, s)
+               : lds_single_t<true, false>(lds_bytes, descs, adj32, item, gstack, recs, colors, s);
+  return big ? lds_single_t<false, true>(lds_bytes, descs, adj32, item, gstack, recs, colors, s)
+             : lds_single_t<false, false>(lds_bytes, descs, adj32, item, gstack, recs, colors, s);
 }
 
 }  // namespace mpld

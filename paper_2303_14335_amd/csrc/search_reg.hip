@@ -51,8 +51,15 @@ __device__ __forceinline__ uint32_t uniform(uint32_t x) {
   return (uint32_t)__builtin_amdgcn_readfirstlane((int)x);
 }
 
-// Searches one component; every lane of the wave must call it.
-template <bool TRACE>
+// Searches one component; every lane of the wave must call it.  NB = bits
+// of a row count (k < 2^NB).
+//   rm   (VGPR)      open colors of the lane's node (k-bit row mask)
+//   nb   (VGPR pair) the lane's neighbour mask
+//   lost (VGPR pair) bit d set iff this lane's node lost a color when the
+//                    row at depth d was taken (the undo record)
+//   st   (VGPR)      lane d holds frame d: v | c << 8
+//   P, depth, nodes, hash: wave-uniform (SGPRs)
+template <bool TRACE, int NB>
 __device__ __forceinline__ void solve_reg(const int32_t n, const int32_t k, const uint64_t budget,
                                           const uint64_t* __restrict__ nbmask,
                                           int8_t* __restrict__ colors,
@@ -61,13 +68,14 @@ __device__ __forceinline__ void solve_reg(const int32_t n, const int32_t k, cons
   const uint64_t nb = lane < (uint32_t)n ? nbmask[lane] : 0ull;
   uint32_t rm = lane < (uint32_t)n ? ((1u << k) - 1u) : 0u;
   uint64_t P = n >= 64 ? ~0ull : ((1ull << n) - 1ull);
-  uint32_t st_vc = 0, st_lo = 0, st_hi = 0;
+  uint64_t lost = 0;
+  uint32_t st = 0;
   uint32_t depth = 0;
   uint64_t nodes = 0;
   uint64_t h = kFnvOffset;
   uint32_t row_in = kNone;
-  int32_t status;
-  for (;;) {
+  int32_t status = -1;
+  while (status < 0) {
     // ---- one search node
     if (nodes == budget) { status = MPLD_BUDGET_EXHAUSTED; break; }
     ++nodes;
@@ -76,52 +84,52 @@ __device__ __forceinline__ void solve_reg(const int32_t n, const int32_t k, cons
       status = MPLD_FEASIBLE;
       break;
     }
+    // column choice without branches: narrow the open columns to those of
+    // the smallest row count one count bit at a time (most significant
+    // first); the lowest survivor is the lowest index of that count
     const uint32_t cnt = __popc(rm);
-    uint64_t sel = 0;
-    uint32_t size = 0;
-    for (uint32_t t = 0; t <= (uint32_t)k; ++t) {
-      sel = __ballot(cnt == t) & P;
-      if (sel) { size = t; break; }
+    uint64_t cand = P;
+#pragma unroll
+    for (int j = NB - 1; j >= 0; --j) {
+      const uint64_t one = __ballot((cnt >> j) & 1u);
+      const uint64_t zero = cand & ~one;
+      cand = zero ? zero : cand;
     }
-    if (sel == 0) { status = 3; break; }   // cannot happen while P != 0; reported as a bug
-    uint32_t v = (uint32_t)__ffsll((unsigned long long)sel) - 1u;
-    uint32_t c;
+    uint32_t v = (uint32_t)__ffsll((unsigned long long)cand) - 1u;
+    const uint32_t size = rdlane(cnt, v);
     if (TRACE) h = trace_node(h, depth, row_in, v, size);
+    uint32_t c;
     if (size != 0) {
       // cover column v, take its first open row
       P &= ~(1ull << v);
       c = (uint32_t)__ffs(rdlane(rm, v)) - 1u;
     } else {
-      // dead end: uncover rows and columns until a column has a next row
-      for (;;) {
-        if (depth == 0) { status = MPLD_INFEASIBLE; goto done; }
+      // dead end: undo rows and uncover columns until one has a next row
+      uint32_t next = 0;
+      while (depth != 0) {
         --depth;
-        const uint32_t vc = rdlane(st_vc, depth);
-        const uint64_t rem = ((uint64_t)rdlane(st_hi, depth) << 32) | rdlane(st_lo, depth);
+        const uint32_t vc = rdlane(st, depth);
         v = vc & 0xffu;
         const uint32_t cp = vc >> 8;
-        rm |= (uint32_t)((rem >> lane) & 1ull) << cp;
-        const uint32_t next = rdlane(rm, v) & ~((2u << cp) - 1u);
-        if (next) { c = (uint32_t)__ffs(next) - 1u; break; }
+        rm |= (uint32_t)((lost >> depth) & 1ull) << cp;
+        lost &= ~(1ull << depth);
+        next = rdlane(rm, v) & (0xfffffffeu << cp);
+        if (next) break;
         P |= 1ull << v;
       }
+      if (!next) { status = MPLD_INFEASIBLE; break; }
+      c = (uint32_t)__ffs(next) - 1u;
     }
-    // ---- include row (v, c): close color c at the open neighbours of v
-    {
-      const bool hit = ((nb >> v) & 1ull) && ((rm >> c) & 1u);
-      const uint64_t rem = __ballot(hit);
-      rm &= ~((uint32_t)hit << c);
-      const bool mine = lane == depth;   // frame `depth` lives in lane `depth`
-      st_vc = mine ? (v | (c << 8)) : st_vc;
-      st_lo = mine ? (uint32_t)rem : st_lo;
-      st_hi = mine ? (uint32_t)(rem >> 32) : st_hi;
-      ++depth;
-      row_in = v * (uint32_t)k + c;
-    }
+    // ---- include row (v, c): close color c at v's neighbours that have it
+    const uint32_t hit = (uint32_t)(nb >> v) & (rm >> c) & 1u;
+    rm &= ~(hit << c);
+    lost |= (uint64_t)hit << depth;
+    st = lane == depth ? (v | (c << 8)) : st;
+    ++depth;
+    row_in = v * (uint32_t)k + c;
   }
-done:
   if (status == MPLD_FEASIBLE) {
-    if (lane < depth && (st_vc & 0xffu) < (uint32_t)n) colors[st_vc & 0xffu] = (int8_t)(st_vc >> 8);
+    if (lane < depth && (st & 0xffu) < (uint32_t)n) colors[st & 0xffu] = (int8_t)(st >> 8);
   } else if (lane < (uint32_t)n) {
     colors[lane] = -1;
   }
@@ -134,43 +142,40 @@ done:
   rec->hash = h;
 }
 
-// Persistent batched kernel: every wave pops component ids from the queue
-// until it is empty.  counters[0] = queue head, counters[1] = finished
-// waves; both are 0 at launch and the last wave to finish resets them, so
-// the same launch (or a graph holding it) can be replayed.
-template <bool TRACE>
+// Persistent batched kernel.  Wave w first takes item w of its tier's
+// descriptor list (no atomic); while the grid has fewer waves than items,
+// waves then pop item gw + atomicAdd(counter, 1).  Every wave fails exactly
+// one pop, so the pop that returns qlen - 1 is the last one: it resets the
+// counter to 0 and the launch (or the graph holding it) can be replayed with
+// no memset.
+template <bool TRACE, int NB>
 __global__ __launch_bounds__(256) void reg_batched_kernel(
-    const DevDesc* __restrict__ descs, const uint64_t* __restrict__ masks,
-    const int32_t* __restrict__ queue, int32_t qlen, int32_t* __restrict__ counters,
-    int32_t total_waves, DevRecord* __restrict__ recs, int8_t* __restrict__ colors) {
-  for (;;) {
-    int32_t item = 0;
-    if (__lane_id() == 0) item = atomicAdd(&counters[0], 1);
-    item = (int32_t)uniform((uint32_t)item);
-    if (item >= qlen) break;
-    const int32_t comp = (int32_t)uniform((uint32_t)queue[item]);
-    const DevDesc d = descs[comp];
-    solve_reg<TRACE>(d.n, d.k, (uint64_t)d.budget, masks + d.nbr_off, colors + d.out_off,
-                     recs + comp);
-  }
-  if (__lane_id() == 0) {
-    const int32_t done = atomicAdd(&counters[1], 1);
-    if (done == total_waves - 1) {
-      atomicExch(&counters[0], 0);
-      atomicExch(&counters[1], 0);
-    }
+    const DevDesc* __restrict__ descs, const uint64_t* __restrict__ masks, int32_t qlen,
+    int32_t* __restrict__ counter, DevRecord* __restrict__ recs, int8_t* __restrict__ colors) {
+  const int32_t gw = (int32_t)gridDim.x * 4;
+  int32_t item = (int32_t)uniform(blockIdx.x * 4u + (threadIdx.x >> 6));
+  while (item < qlen) {
+    const DevDesc d = descs[item];
+    solve_reg<TRACE, NB>(d.n, d.k, (uint64_t)d.budget, masks + d.nbr_off, colors + d.out_off,
+                         recs + d.comp);
+    if (gw >= qlen) break;   // every item was handed out statically
+    int32_t r = 0;
+    if (__lane_id() == 0) r = atomicAdd(counter, 1);
+    r = (int32_t)uniform((uint32_t)r);
+    item = gw + r;
+    if (r == qlen - 1) atomicExch(counter, 0);   // the last pop of this launch
   }
 }
 
 // One component per launch (the plain solver): a single wave.
-template <bool TRACE>
+template <bool TRACE, int NB>
 __global__ __launch_bounds__(64) void reg_single_kernel(const DevDesc* __restrict__ descs,
                                                         const uint64_t* __restrict__ masks,
-                                                        int32_t comp, DevRecord* __restrict__ recs,
+                                                        int32_t item, DevRecord* __restrict__ recs,
                                                         int8_t* __restrict__ colors) {
-  const DevDesc d = descs[comp];
-  solve_reg<TRACE>(d.n, d.k, (uint64_t)d.budget, masks + d.nbr_off, colors + d.out_off,
-                   recs + comp);
+  const DevDesc d = descs[item];
+  solve_reg<TRACE, NB>(d.n, d.k, (uint64_t)d.budget, masks + d.nbr_off, colors + d.out_off,
+                       recs + d.comp);
 }
 
 __global__ void fill_i32_kernel(int32_t* __restrict__ p, int32_t count, int32_t value) {
@@ -186,37 +191,57 @@ hipError_t launch_fill_i32(int32_t* p, int32_t count, int32_t value, hipStream_t
   return hipGetLastError();
 }
 
-hipError_t launch_reg_batched(bool trace, int grid, const DevDesc* descs, const uint64_t* masks,
-                              const int32_t* queue, int32_t qlen, int32_t* counters,
+// Row counts of k colors need count_bits(k) bits.
+static int count_bits(int k) { return k < 4 ? 2 : (k < 8 ? 3 : 4); }
+
+template <bool TRACE, int NB>
+static void reg_batched_t(int grid, const DevDesc* descs, const uint64_t* masks, int32_t qlen,
+                          int32_t* counter, DevRecord* recs, int8_t* colors, hipStream_t s) {
+  hipLaunchKernelGGL((reg_batched_kernel<TRACE, NB>), dim3(grid), dim3(256), 0, s, descs, masks,
+                     qlen, counter, recs, colors);
+}
+
+template <bool TRACE, int NB>
+static void reg_single_t(const DevDesc* descs, const uint64_t* masks, int32_t item,
+                         DevRecord* recs, int8_t* colors, hipStream_t s) {
+  hipLaunchKernelGGL((reg_single_kernel<TRACE, NB>), dim3(1), dim3(64), 0, s, descs, masks, item,
+                     recs, colors);
+}
+
+hipError_t launch_reg_batched(bool trace, int k, int grid, const DevDesc* descs,
+                              const uint64_t* masks, int32_t qlen, int32_t* counter,
                               DevRecord* recs, int8_t* colors, hipStream_t s) {
   if (qlen <= 0) return hipSuccess;
-  const int32_t waves = grid * 4;
-  if (trace)
-    hipLaunchKernelGGL(reg_batched_kernel<true>, dim3(grid), dim3(256), 0, s, descs, masks, queue,
-                       qlen, counters, waves, recs, colors);
-  else
-    hipLaunchKernelGGL(reg_batched_kernel<false>, dim3(grid), dim3(256), 0, s, descs, masks, queue,
-                       qlen, counters, waves, recs, colors);
+  switch (count_bits(k) + (trace ? 8 : 0)) {
+    case 2: reg_batched_t<false, 2>(grid, descs, masks, qlen, counter, recs, colors, s); break;
+    case 3: reg_batched_t<false, 3>(grid, descs, masks, qlen, counter, recs, colors, s); break;
+    case 4: reg_batched_t<false, 4>(grid, descs, masks, qlen, counter, recs, colors, s); break;
+    case 10: reg_batched_t<true, 2>(grid, descs, masks, qlen, counter, recs, colors, s); break;
+    case 11: reg_batched_t<true, 3>(grid, descs, masks, qlen, counter, recs, colors, s); break;
+    default: reg_batched_t<true, 4>(grid, descs, masks, qlen, counter, recs, colors, s); break;
+  }
   return hipGetLastError();
 }
 
-hipError_t launch_reg_single(bool trace, const DevDesc* descs, const uint64_t* masks, int32_t comp,
-                             DevRecord* recs, int8_t* colors, hipStream_t s) {
-  if (trace)
-    hipLaunchKernelGGL(reg_single_kernel<true>, dim3(1), dim3(64), 0, s, descs, masks, comp, recs,
-                       colors);
-  else
-    hipLaunchKernelGGL(reg_single_kernel<false>, dim3(1), dim3(64), 0, s, descs, masks, comp, recs,
-                       colors);
+hipError_t launch_reg_single(bool trace, int k, const DevDesc* descs, const uint64_t* masks,
+                             int32_t item, DevRecord* recs, int8_t* colors, hipStream_t s) {
+  switch (count_bits(k) + (trace ? 8 : 0)) {
+    case 2: reg_single_t<false, 2>(descs, masks, item, recs, colors, s); break;
+    case 3: reg_single_t<false, 3>(descs, masks, item, recs, colors, s); break;
+    case 4: reg_single_t<false, 4>(descs, masks, item, recs, colors, s); break;
+    case 10: reg_single_t<true, 2>(descs, masks, item, recs, colors, s); break;
+    case 11: reg_single_t<true, 3>(descs, masks, item, recs, colors, s); break;
+    default: reg_single_t<true, 4>(descs, masks, item, recs, colors, s); break;
+  }
   return hipGetLastError();
 }
 
 int reg_batched_blocks_per_cu(bool trace) {
   int blocks = 0;
   hipError_t e = trace ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                             &blocks, reg_batched_kernel<true>, 256, 0)
+                             &blocks, reg_batched_kernel<true, 4>, 256, 0)
                        : hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                             &blocks, reg_batched_kernel<false>, 256, 0);
+                             &blocks, reg_batched_kernel<false, 4>, 256, 0);
   return e == hipSuccess && blocks > 0 ? blocks : 1;
 }
 
