@@ -84,6 +84,62 @@ def cpu_baseline(rects, w, seconds: float):
             "components_per_s": passes * len(sizes) / el}
 
 
+def serve_leg(mp, ctx, count: int, seed: int):
+    """Serving workload: `count` layout requests with Poisson arrivals at the
+    configured rate, feature counts log-uniform in [100, 50000], window side
+    scaled to the small workload's density; each is decomposed through the
+    continuous-batching server.  Latency = finished result - arrival."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import numpy as np
+
+    import workload
+    from workload.configs import SERVE
+    t = workload.request_trace(seed, count, rate=SERVE["rate"], n_min=SERVE["n_min"],
+                               n_max=SERVE["n_max"], base_side=SERVE["base_side"],
+                               base_n=SERVE["base_n"])
+
+    def gen(i):
+        return workload.generate(int(t["n_rects"][i]), int(t["side_nm"][i]), int(t["seed"][i]))[0]
+
+    with ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+        rects = list(ex.map(gen, range(count)))
+    srv = mp.Server(ctx)
+    lags = np.zeros(count)
+    tickets = []
+    start = time.perf_counter()
+    for i in range(count):
+        target = start + float(t["arrival_s"][i])
+        now = time.perf_counter()
+        if target > now:
+            time.sleep(target - now)
+        lags[i] = max(0.0, time.perf_counter() - target)
+        tickets.append(srv.submit_layout(rects[i], SERVE["dmin_nm"], 0, SERVE["k"], SERVE["budget"]))
+    lat = np.zeros(count)
+    queue = np.zeros(count)
+    nodes = 0
+    for i, tk in enumerate(tickets):
+        r = srv.wait(tk)
+        lat[i] = lags[i] * 1e6 + r.total_us
+        queue[i] = r.queue_us
+        nodes += int(r.components["nodes"].sum())
+    end = time.perf_counter()
+    st = srv.stats()
+    srv.close()
+    feats = int(np.sum(t["n_rects"]))
+    return {"requests": count, "rate_per_s": SERVE["rate"], "seed": seed,
+            "p50_ms": float(np.percentile(lat, 50)) / 1e3,
+            "p99_ms": float(np.percentile(lat, 99)) / 1e3,
+            "mean_ms": float(lat.mean()) / 1e3,
+            "p99_queue_ms": float(np.percentile(queue, 99)) / 1e3,
+            "max_client_lag_ms": float(lags.max()) * 1e3,
+            "requests_per_s": count / (end - start),
+            "features_per_s": feats / (end - start),
+            "search_nodes_per_s": nodes / (end - start),
+            "ticks": st["ticks"], "device_ms": st["device_ms"],
+            "admission_waits": st["admission_waits"], "peak_device_bytes": st["peak_bytes"]}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -97,6 +153,8 @@ def main() -> int:
                     help="direct launches timed one by one for the kernel duration")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=1000,
+                    help="serving leg: requests of the serving workload (0 = skip)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run one device copy of this size (counter scaling probe)")
     args = ap.parse_args()
@@ -253,6 +311,11 @@ def main() -> int:
                      "budget": int(np.sum(comps["status"] == 2))},
         "stitches": res.stitches, "uncolored": res.uncolored,
     }
+    if args.serve_requests:
+        log(f"serving leg: {args.serve_requests} requests")
+        out["serving"] = serve_leg(mp, ctx, args.serve_requests, 0)
+        out["p50_latency_ms"] = out["serving"]["p50_ms"]
+        out["p99_latency_ms"] = out["serving"]["p99_ms"]
     if not args.no_cpu_baseline:
         log("timing the CPU oracle")
         out["cpu_baseline"] = cpu_baseline(rects, w, args.cpu_seconds)

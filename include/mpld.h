@@ -86,8 +86,12 @@ enum {
   MPLD_FORCE_WAVE = 1u << 3,   /* force the register tier (n <= 64)           */
   MPLD_FORCE_LDS = 1u << 4,    /* force the LDS tier                          */
   MPLD_FORCE_GLOBAL = 1u << 5, /* force the global-memory tier                */
-  MPLD_DIRECT = 1u << 6        /* batched solve: launch the kernels directly
+  MPLD_DIRECT = 1u << 6,       /* batched solve: launch the kernels directly
                                   instead of replaying the captured HIP graph */
+  MPLD_FORCE_DEVICE = 1u << 7  /* force the device-wide tier: one component at a
+                                  time over every CU, columns split across
+                                  workgroups, a device-wide min-count reduction
+                                  per search node                              */
 };
 
 typedef struct { int32_t x0, y0, x1, y1; } mpld_rect;  /* nm, closed box */
@@ -208,10 +212,41 @@ typedef struct {
   float last_search_ms;      /* search kernels of the last solve          */
   float last_total_ms;       /* whole enqueued solve of the last solve    */
   int32_t launches;          /* kernel launches of the last solve         */
-  int32_t reserved;
+  int32_t num_device;        /* components on the device-wide tier        */
 } mpld_batch_info;
 int32_t mpld_batch_get_info(mpld_batch* b, mpld_batch_info* info);
 void mpld_batch_free(mpld_batch* b);
+
+/* ---- launch parameters and the autotuner --------------------------------
+ * The tiered launch schedule of a batch: register-tier workgroup size (in
+ * waves of 64 lanes) and grid cap, queue order, HIP-graph replay, and whether
+ * components of at least giant_min_nodes nodes use the device-wide tier.
+ * mpld_batch_autotune times candidate schedules on the batch with HIP
+ * events (median of `reps` solves; one solve each for batches whose solve
+ * takes over 5 ms, which then only vary the order and the giant tier),
+ * checks that every candidate reproduces the default's records and colors
+ * (MPLD_E_INTERNAL otherwise), adopts the fastest and, when cache_path (or
+ * $MPLD_TUNE_CACHE) names a file, appends it as one JSON line keyed by the
+ * device architecture, CU count, k, trace flag and the batch's component
+ * count and size (powers of two).  mpld_batch_create applies the last
+ * matching cache line.  The schedule never changes a result. */
+typedef struct {
+  uint32_t struct_size;      /* sizeof(mpld_tune)                              */
+  int32_t waves_per_block;   /* 1, 2 or 4                                      */
+  int32_t max_blocks;        /* register-tier grid cap; 0 = a wave per component */
+  int32_t use_graph;         /* replay a captured HIP graph                    */
+  int32_t order;             /* 0 largest component first, 1 smallest first    */
+  int32_t giant_device;      /* giants on the device-wide tier                 */
+  int32_t giant_min_nodes;   /* what a giant is (>= 65)                        */
+  float best_ms;             /* autotune: median device ms of the chosen one   */
+  float default_ms;          /* autotune: the same for the default schedule    */
+  int32_t candidates;        /* autotune: schedules timed                      */
+  int32_t from_cache;        /* get: the schedule came from the cache          */
+} mpld_tune;
+int32_t mpld_batch_autotune(mpld_batch* b, int32_t reps, const char* cache_path, mpld_tune* out);
+int32_t mpld_batch_get_tune(mpld_batch* b, mpld_tune* out);
+/* Re-packs and re-uploads the batch with the given schedule. */
+int32_t mpld_batch_set_tune(mpld_batch* b, const mpld_tune* t);
 
 /* ---- components directly (no simplification, no renumbering) -----------
  * Solves `count` components given in local numbering.  out: count records;
@@ -221,6 +256,58 @@ int32_t mpld_solve_components(mpld_context* ctx, const mpld_component* comps,
                               int32_t count, const mpld_options* opt,
                               mpld_comp_record* out, int8_t* colors_out);
 
+/* ---- serving: continuous batching of whole-layout requests --------------
+ * A server owns a context's stream from a scheduler thread.  Requests are
+ * copied at submit and run through the host front-end on worker threads;
+ * the scheduler then admits them in arrival order as soon as their packed
+ * image fits the device arena and enough component slots are free (admission
+ * by device bytes).  Every tick advances every resident register-tier
+ * component by at most `slice_nodes` search nodes from the state it keeps in
+ * device memory (larger components run to completion in the tick that
+ * admits them), so requests that arrive while others are on the device join
+ * at the next tick and their work shares the same launches.  A request's
+ * result depends only on its graph and options - not on arrival time, the
+ * mix or the slice.  While a server exists its context must not be used
+ * elsewhere.  A request larger than the whole arena (or than all slots)
+ * completes with MPLD_E_NOMEM instead of waiting. */
+typedef struct mpld_server mpld_server;
+typedef struct {
+  uint32_t struct_size;    /* sizeof(mpld_server_options)                   */
+  int32_t max_components;  /* component slots resident at once; 0 = 65536   */
+  int64_t arena_bytes;     /* device bytes for request images; 0 = 256 MiB, at most 2 GiB */
+  int64_t slice_nodes;     /* search nodes per component per tick; 0 = 4096 */
+  int32_t host_threads;    /* front-end threads; 0 = min(16, host cores)    */
+  int32_t reserved;
+} mpld_server_options;
+typedef struct {
+  int64_t submitted, completed, failed, ticks;
+  int64_t resident_bytes, resident_components, peak_bytes;
+  int64_t search_nodes;     /* of completed requests                       */
+  int64_t admission_waits;  /* ticks in which the next request did not fit */
+  double device_ms;         /* summed device time of the ticks (HIP events) */
+} mpld_server_stats;
+
+int32_t mpld_server_create(mpld_context* ctx, const mpld_server_options* opt,
+                           mpld_server** out);
+/* Submit a layout graph (copied) or a rectangle layout (copied; the layout
+ * graph is built on a worker thread, as mpld_build_graph).  Returns a
+ * ticket at once. */
+int32_t mpld_server_submit(mpld_server* s, const mpld_graph* g, const mpld_options* opt,
+                           uint64_t* ticket);
+int32_t mpld_server_submit_layout(mpld_server* s, const mpld_rect* rects, int32_t n,
+                                  int32_t dmin_nm, int32_t split_len_nm,
+                                  const mpld_options* opt, uint64_t* ticket);
+/* The finished result of a ticket (the ticket is consumed), MPLD_E_NOT_READY
+ * while it runs, the request's own error code if it failed, MPLD_E_INVALID
+ * for an unknown ticket.  wait blocks up to timeout_us (< 0: no limit). */
+int32_t mpld_server_poll(mpld_server* s, uint64_t ticket, mpld_result** out);
+int32_t mpld_server_wait(mpld_server* s, uint64_t ticket, int64_t timeout_us,
+                         mpld_result** out);
+int32_t mpld_server_get_stats(mpld_server* s, mpld_server_stats* out);
+/* Stops the scheduler after its current tick; requests not finished by then
+ * complete with MPLD_E_CANCELLED (their results cannot be fetched). */
+int32_t mpld_server_destroy(mpld_server* s);
+
 /* ---- results ------------------------------------------------------------ */
 const int8_t* mpld_result_colors(const mpld_result* r, int32_t* num_nodes);
 const int32_t* mpld_result_component_of(const mpld_result* r); /* -1 = removed */
@@ -228,6 +315,9 @@ int32_t mpld_result_num_components(const mpld_result* r);
 const mpld_comp_record* mpld_result_components(const mpld_result* r);
 void mpld_result_totals(const mpld_result* r, int64_t* stitches,
                         int64_t* conflicts, int64_t* uncolored);
+/* Serving results: microseconds from submit to admission on the device and
+ * from submit to the finished result (0 for results of other calls). */
+void mpld_result_timing(const mpld_result* r, double* queue_us, double* total_us);
 void mpld_result_free(mpld_result* r);
 
 #ifdef __cplusplus

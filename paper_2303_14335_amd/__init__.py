@@ -15,9 +15,9 @@ from dataclasses import dataclass
 import numpy as np
 
 from . import _ffi
-from ._ffi import (MPLD_BUDGET_EXHAUSTED, MPLD_FEASIBLE, MPLD_FORCE_GLOBAL,  # noqa: F401
-                   MPLD_FORCE_LDS, MPLD_FORCE_WAVE, MPLD_INFEASIBLE, MPLD_PLAIN,
-                   MPLD_SIMPLIFY, MPLD_TRACE_HASH)
+from ._ffi import (MPLD_BUDGET_EXHAUSTED, MPLD_FEASIBLE, MPLD_FORCE_DEVICE,  # noqa: F401
+                   MPLD_FORCE_GLOBAL, MPLD_FORCE_LDS, MPLD_FORCE_WAVE, MPLD_INFEASIBLE,
+                   MPLD_PLAIN, MPLD_SIMPLIFY, MPLD_TRACE_HASH)
 
 _lib = _ffi.load()
 
@@ -160,6 +160,8 @@ class Result:
     stitches: int
     conflicts: int
     uncolored: int
+    queue_us: float = 0.0     # serving: submit -> admission on the device
+    total_us: float = 0.0     # serving: submit -> finished result
 
 
 def _take_result(h) -> Result:
@@ -180,7 +182,9 @@ def _take_result(h) -> Result:
             comps = np.zeros(0, RECORD_DTYPE)
         st, cn, un = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
         _lib.mpld_result_totals(h, ctypes.byref(st), ctypes.byref(cn), ctypes.byref(un))
-        return Result(colors, comp_of, comps, st.value, cn.value, un.value)
+        q, t = ctypes.c_double(), ctypes.c_double()
+        _lib.mpld_result_timing(h, ctypes.byref(q), ctypes.byref(t))
+        return Result(colors, comp_of, comps, st.value, cn.value, un.value, q.value, t.value)
     finally:
         _lib.mpld_result_free(h)
 
@@ -218,7 +222,26 @@ class Batch:
     def info(self) -> dict:
         i = _ffi.mpld_batch_info()
         _check(_lib.mpld_batch_get_info(self.handle, ctypes.byref(i)), "mpld_batch_get_info")
-        return {name: getattr(i, name) for name, _ in i._fields_ if name != "reserved"}
+        return {name: getattr(i, name) for name, _ in i._fields_}
+
+    def autotune(self, reps: int = 5, cache_path: str | None = None) -> dict:
+        t = _ffi.mpld_tune(ctypes.sizeof(_ffi.mpld_tune))
+        _check(_lib.mpld_batch_autotune(self.handle, reps,
+                                        cache_path.encode() if cache_path else None,
+                                        ctypes.byref(t)), "mpld_batch_autotune")
+        return {name: getattr(t, name) for name, _ in t._fields_ if name != "struct_size"}
+
+    def get_tune(self) -> dict:
+        t = _ffi.mpld_tune(ctypes.sizeof(_ffi.mpld_tune))
+        _check(_lib.mpld_batch_get_tune(self.handle, ctypes.byref(t)), "mpld_batch_get_tune")
+        return {name: getattr(t, name) for name, _ in t._fields_ if name != "struct_size"}
+
+    def set_tune(self, **kw) -> None:
+        t = _ffi.mpld_tune(ctypes.sizeof(_ffi.mpld_tune))
+        _check(_lib.mpld_batch_get_tune(self.handle, ctypes.byref(t)), "mpld_batch_get_tune")
+        for name, val in kw.items():
+            setattr(t, name, val)
+        _check(_lib.mpld_batch_set_tune(self.handle, ctypes.byref(t)), "mpld_batch_set_tune")
 
     def close(self):
         if self.handle:
@@ -253,6 +276,18 @@ def mpld_batch_free(b: Batch) -> None:
     b.close()
 
 
+def mpld_batch_autotune(b: Batch, reps: int = 5, cache_path: str | None = None) -> dict:
+    return b.autotune(reps, cache_path)
+
+
+def mpld_batch_get_tune(b: Batch) -> dict:
+    return b.get_tune()
+
+
+def mpld_batch_set_tune(b: Batch, **kw) -> None:
+    b.set_tune(**kw)
+
+
 def mpld_solve_components(ctx: Context, comps, k: int, budget: int, flags: int = 0):
     """comps: list of (n, edges [m, 2]) in local numbering.  Returns
     (records RECORD_DTYPE[count], list of per-component int8 colors)."""
@@ -275,3 +310,97 @@ def mpld_solve_components(ctx: Context, comps, k: int, budget: int, flags: int =
         per.append(colors[off: off + n].copy())
         off += n
     return out, per
+
+
+# ---- serving ----------------------------------------------------------------
+
+class Server:
+    """Continuous-batching server on a context (see include/mpld.h)."""
+
+    def __init__(self, ctx: Context, max_components: int = 0, arena_bytes: int = 0,
+                 slice_nodes: int = 0, host_threads: int = 0):
+        self.ctx = ctx
+        self.handle = ctypes.c_void_p()
+        o = _ffi.mpld_server_options(ctypes.sizeof(_ffi.mpld_server_options), max_components,
+                                     arena_bytes, slice_nodes, host_threads, 0)
+        _check(_lib.mpld_server_create(ctx.handle, ctypes.byref(o), ctypes.byref(self.handle)),
+               "mpld_server_create")
+
+    def submit_layout(self, rects: np.ndarray, dmin_nm: int, split_len_nm: int, k: int,
+                      budget: int, flags: int = MPLD_SIMPLIFY) -> int:
+        r = np.ascontiguousarray(rects, dtype=np.int32).reshape(-1, 4)
+        opt = options(k, budget, flags)
+        t = ctypes.c_uint64()
+        _check(_lib.mpld_server_submit_layout(self.handle, r.ctypes.data, len(r), dmin_nm,
+                                              split_len_nm, ctypes.byref(opt), ctypes.byref(t)),
+               "mpld_server_submit_layout")
+        return t.value
+
+    def submit(self, g: Graph, k: int, budget: int, flags: int = MPLD_SIMPLIFY) -> int:
+        opt = options(k, budget, flags)
+        view = g.view()
+        t = ctypes.c_uint64()
+        _check(_lib.mpld_server_submit(self.handle, ctypes.byref(view), ctypes.byref(opt),
+                                       ctypes.byref(t)), "mpld_server_submit")
+        return t.value
+
+    def poll(self, ticket: int):
+        h = ctypes.c_void_p()
+        rc = _lib.mpld_server_poll(self.handle, ticket, ctypes.byref(h))
+        if rc == _ffi.MPLD_E_NOT_READY:
+            return None
+        _check(rc, "mpld_server_poll")
+        return _take_result(h)
+
+    def wait(self, ticket: int, timeout_us: int = -1):
+        h = ctypes.c_void_p()
+        rc = _lib.mpld_server_wait(self.handle, ticket, timeout_us, ctypes.byref(h))
+        if rc == _ffi.MPLD_E_NOT_READY:
+            return None
+        _check(rc, "mpld_server_wait")
+        return _take_result(h)
+
+    def stats(self) -> dict:
+        st = _ffi.mpld_server_stats()
+        _check(_lib.mpld_server_get_stats(self.handle, ctypes.byref(st)), "mpld_server_get_stats")
+        return {name: getattr(st, name) for name, _ in st._fields_}
+
+    def close(self):
+        if self.handle:
+            _lib.mpld_server_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def mpld_server_create(ctx: Context, **kw) -> Server:
+    return Server(ctx, **kw)
+
+
+def mpld_server_submit_layout(s: Server, rects, dmin_nm: int, split_len_nm: int, k: int,
+                              budget: int, flags: int = MPLD_SIMPLIFY) -> int:
+    return s.submit_layout(rects, dmin_nm, split_len_nm, k, budget, flags)
+
+
+def mpld_server_submit(s: Server, g: Graph, k: int, budget: int, flags: int = MPLD_SIMPLIFY) -> int:
+    return s.submit(g, k, budget, flags)
+
+
+def mpld_server_poll(s: Server, ticket: int):
+    return s.poll(ticket)
+
+
+def mpld_server_wait(s: Server, ticket: int, timeout_us: int = -1):
+    return s.wait(ticket, timeout_us)
+
+
+def mpld_server_get_stats(s: Server) -> dict:
+    return s.stats()
+
+
+def mpld_server_destroy(s: Server) -> None:
+    s.close()

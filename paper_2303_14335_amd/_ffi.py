@@ -25,6 +25,7 @@ MPLD_FORCE_WAVE = 1 << 3
 MPLD_FORCE_LDS = 1 << 4
 MPLD_FORCE_GLOBAL = 1 << 5
 MPLD_DIRECT = 1 << 6
+MPLD_FORCE_DEVICE = 1 << 7
 
 c_i32, c_i64, c_u32, c_u64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint64
 vp = ctypes.c_void_p
@@ -66,7 +67,26 @@ class mpld_batch_info(ctypes.Structure):
     _fields_ = [("num_components", c_i32), ("num_wave", c_i32), ("num_lds", c_i32),
                 ("num_global", c_i32), ("core_nodes", c_i32), ("max_size", c_i32),
                 ("image_bytes", c_i64), ("core_edges", c_i64), ("last_search_ms", ctypes.c_float),
-                ("last_total_ms", ctypes.c_float), ("launches", c_i32), ("reserved", c_i32)]
+                ("last_total_ms", ctypes.c_float), ("launches", c_i32), ("num_device", c_i32)]
+
+
+class mpld_tune(ctypes.Structure):
+    _fields_ = [("struct_size", c_u32), ("waves_per_block", c_i32), ("max_blocks", c_i32),
+                ("use_graph", c_i32), ("order", c_i32), ("giant_device", c_i32),
+                ("giant_min_nodes", c_i32), ("best_ms", ctypes.c_float),
+                ("default_ms", ctypes.c_float), ("candidates", c_i32), ("from_cache", c_i32)]
+
+
+class mpld_server_options(ctypes.Structure):
+    _fields_ = [("struct_size", c_u32), ("max_components", c_i32), ("arena_bytes", c_i64),
+                ("slice_nodes", c_i64), ("host_threads", c_i32), ("reserved", c_i32)]
+
+
+class mpld_server_stats(ctypes.Structure):
+    _fields_ = [("submitted", c_i64), ("completed", c_i64), ("failed", c_i64), ("ticks", c_i64),
+                ("resident_bytes", c_i64), ("resident_components", c_i64),
+                ("peak_bytes", c_i64), ("search_nodes", c_i64), ("admission_waits", c_i64),
+                ("device_ms", ctypes.c_double)]
 
 
 P = ctypes.POINTER
@@ -87,6 +107,9 @@ SIGNATURES = {
     "mpld_batch_result": (c_i32, [vp, P(vp)]),
     "mpld_batch_get_info": (c_i32, [vp, P(mpld_batch_info)]),
     "mpld_batch_free": (None, [vp]),
+    "mpld_batch_autotune": (c_i32, [vp, c_i32, ctypes.c_char_p, P(mpld_tune)]),
+    "mpld_batch_get_tune": (c_i32, [vp, P(mpld_tune)]),
+    "mpld_batch_set_tune": (c_i32, [vp, P(mpld_tune)]),
     "mpld_solve_components": (c_i32, [vp, P(mpld_component), c_i32, P(mpld_options),
                                       P(mpld_comp_record), vp]),
     "mpld_result_colors": (vp, [vp, P(c_i32)]),
@@ -94,7 +117,16 @@ SIGNATURES = {
     "mpld_result_num_components": (c_i32, [vp]),
     "mpld_result_components": (vp, [vp]),
     "mpld_result_totals": (None, [vp, P(c_i64), P(c_i64), P(c_i64)]),
+    "mpld_result_timing": (None, [vp, P(ctypes.c_double), P(ctypes.c_double)]),
     "mpld_result_free": (None, [vp]),
+    "mpld_server_create": (c_i32, [vp, P(mpld_server_options), P(vp)]),
+    "mpld_server_submit": (c_i32, [vp, P(mpld_graph), P(mpld_options), P(c_u64)]),
+    "mpld_server_submit_layout": (c_i32, [vp, vp, c_i32, c_i32, c_i32, P(mpld_options),
+                                          P(c_u64)]),
+    "mpld_server_poll": (c_i32, [vp, c_u64, P(vp)]),
+    "mpld_server_wait": (c_i32, [vp, c_u64, c_i64, P(vp)]),
+    "mpld_server_get_stats": (c_i32, [vp, P(mpld_server_stats)]),
+    "mpld_server_destroy": (c_i32, [vp]),
 }
 
 _lib = None

@@ -44,7 +44,8 @@ void check_options(const mpld_options* opt) {
     fail(MPLD_E_INVALID, "options.struct_size does not match this library's mpld_options");
   if (opt->k < 2 || opt->k > MPLD_MAX_K) fail(MPLD_E_INVALID, "k must be in [2, 8]");
   if (opt->node_budget < 1) fail(MPLD_E_INVALID, "node_budget must be >= 1");
-  const uint32_t forced = opt->flags & (MPLD_FORCE_WAVE | MPLD_FORCE_LDS | MPLD_FORCE_GLOBAL);
+  const uint32_t forced =
+      opt->flags & (MPLD_FORCE_WAVE | MPLD_FORCE_LDS | MPLD_FORCE_GLOBAL | MPLD_FORCE_DEVICE);
   if (forced & (forced - 1)) fail(MPLD_E_INVALID, "at most one MPLD_FORCE_* flag");
 }
 
@@ -53,7 +54,8 @@ void use_device(mpld_context* ctx) {
   check_hip(hipSetDevice(ctx->device), "hipSetDevice");
 }
 
-// Builds the batch: front-end, packing, upload.
+// Builds the batch: front-end, then packing and upload with the batch's
+// launch parameters (from the tuning cache when one is configured).
 void batch_build(mpld_context* ctx, const mpld_graph* g, const mpld_options* opt, mpld_batch* b) {
   if (!g) fail(MPLD_E_INVALID, "graph is NULL");
   check_options(opt);
@@ -61,55 +63,16 @@ void batch_build(mpld_context* ctx, const mpld_graph* g, const mpld_options* opt
   b->opt = *opt;
   b->g = make_graph(*g);
   b->s = simplify_and_split(b->g, opt->k, opt->flags & MPLD_SIMPLIFY);
-  const int32_t nc = (int32_t)b->s.comp_ptr.size() - 1;
-  std::vector<int32_t> pairs;
-  for (int32_t c = 0; c < nc; ++c) {
-    local_edges(b->g, b->s, c, pairs);
-    const int32_t n = b->s.comp_ptr[c + 1] - b->s.comp_ptr[c];
-    image_add(b->im, ctx, n, pairs.data(), (int64_t)pairs.size() / 2, opt->k, opt->node_budget,
-              opt->flags);
-  }
-  image_finish(b->im);
-  device_upload(ctx, b->im, b->db);
+  Tune t;
+  tune_from_cache(b, nullptr, &t);
+  batch_pack(b, t);
 }
 
 void batch_collect(mpld_batch* b, mpld_result* r) {
   std::vector<DevRecord> recs;
   std::vector<int8_t> lcol;
   device_fetch(b->db, recs, lcol);
-  const Graph& g = b->g;
-  const Split& s = b->s;
-  const bool trace = b->opt.flags & MPLD_TRACE_HASH;
-  r->colors.assign((size_t)g.n, -1);
-  r->comp_of = s.comp_of;
-  const int32_t nc = (int32_t)s.comp_ptr.size() - 1;
-  r->comps.resize((size_t)nc);
-  for (int32_t c = 0; c < nc; ++c) {
-    const DevDesc& d = b->im.desc[c];
-    for (int32_t i = 0; i < d.n; ++i) r->colors[s.order[s.comp_ptr[c] + i]] = lcol[d.out_off + i];
-  }
-  for (int32_t c = 0; c < nc; ++c) {
-    const DevDesc& d = b->im.desc[c];
-    mpld_comp_record& rec = r->comps[c];
-    rec.size = d.n;
-    rec.status = recs[c].status;
-    rec.nodes = (int64_t)recs[c].nodes;
-    rec.trace_hash = trace ? recs[c].hash : 0;
-    rec.depth_at_stop = recs[c].depth;
-    rec.first_node = s.order[s.comp_ptr[c]];
-    int64_t edges2 = 0;
-    int32_t st = 0;
-    for (int32_t p = s.comp_ptr[c]; p < s.comp_ptr[c + 1]; ++p) {
-      const int32_t x = s.order[p];
-      for (int64_t t = g.ptr[x]; t < g.ptr[x + 1]; ++t) edges2 += s.comp_of[g.adj[t]] == c;
-      const int32_t q = g.partner[x];
-      if (q > x && s.comp_of[q] == c && r->colors[q] != r->colors[x]) ++st;
-    }
-    rec.num_edges = (int32_t)(edges2 / 2);
-    rec.stitches = rec.status == MPLD_FEASIBLE ? st : -1;
-  }
-  if (b->opt.flags & MPLD_SIMPLIFY) recover(g, s, b->opt.k, r->colors);
-  tallies(g, r->colors, &r->stitches, &r->conflicts, &r->uncolored);
+  assemble_result(b->g, b->s, b->im, b->opt, recs, lcol, r);
 }
 
 }  // namespace
@@ -277,6 +240,7 @@ int32_t mpld_batch_get_info(mpld_batch* b, mpld_batch_info* info) {
     info->last_search_ms = b->db.last_search_ms;
     info->last_total_ms = b->db.last_total_ms;
     info->launches = b->db.launches;
+    info->num_device = b->db.n_dev;
   });
 }
 
@@ -389,6 +353,12 @@ void mpld_result_totals(const mpld_result* r, int64_t* stitches, int64_t* confli
   if (stitches) *stitches = r->stitches;
   if (conflicts) *conflicts = r->conflicts;
   if (uncolored) *uncolored = r->uncolored;
+}
+
+void mpld_result_timing(const mpld_result* r, double* queue_us, double* total_us) {
+  if (!r) return;
+  if (queue_us) *queue_us = r->queue_us;
+  if (total_us) *total_us = r->total_us;
 }
 
 void mpld_result_free(mpld_result* r) { delete r; }

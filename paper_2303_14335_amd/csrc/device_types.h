@@ -6,7 +6,7 @@
 
 namespace mpld {
 
-enum Tier : int32_t { kTierReg = 0, kTierLds = 1, kTierGlobal = 2 };
+enum Tier : int32_t { kTierReg = 0, kTierLds = 1, kTierGlobal = 2, kTierDevice = 3 };
 
 // One descriptor per component (32 bytes).  On the device the descriptors
 // of each tier are stored contiguously in that tier's launch order (largest
@@ -33,5 +33,10 @@ struct DevRecord {
   uint64_t hash;    // FNV-1a trace hash (offset basis when tracing is off)
 };
 static_assert(sizeof(DevRecord) == 24, "record is 24 bytes");
+
+// Device bytes of the resumable register-tier search state of one
+// component (serving): a 64-byte uniform head, then 64 lanes x (u32 open
+// colors, u32 frame, u64 undo bits).
+constexpr uint64_t kRegStateBytes = 64 + 64 * (4 + 4 + 8);
 
 }  // namespace mpld

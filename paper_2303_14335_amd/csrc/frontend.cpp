@@ -189,7 +189,7 @@ void tallies(const Graph& g, const std::vector<int8_t>& colors, int64_t* stitche
 // 3x3 cells around a node hold its possible conflict partners.
 
 void build_layout_graph(const mpld_rect* rects, int32_t n, int32_t dmin,
-                        int32_t split_len, OwnedGraph& out) {
+                        int32_t split_len, OwnedGraph& out, int threads) {
   if (n < 0 || dmin < 0 || split_len < 0) fail(MPLD_E_INVALID, "negative size, dmin or split length");
   if (n > 0 && !rects) fail(MPLD_E_INVALID, "null rectangle array");
   std::vector<mpld_rect> nd;
@@ -247,7 +247,7 @@ void build_layout_graph(const mpld_rect* rects, int32_t n, int32_t dmin,
     for (int32_t i = 0; i < nn; ++i) sorted[fill[cell_of[i]]++] = i;  // ascending id per cell
   }
   const int64_t d2 = (int64_t)dmin * dmin;
-  const int T = std::min(host_threads(), std::max(1, nn / 4096));
+  const int T = std::min(threads > 0 ? threads : host_threads(), std::max(1, nn / 4096));
   std::vector<std::vector<int32_t>> part((size_t)T);
   auto work = [&](int t) {
     const int32_t lo = (int32_t)((int64_t)nn * t / T), hi = (int32_t)((int64_t)nn * (t + 1) / T);

@@ -60,8 +60,9 @@ struct OwnedGraph {
   std::vector<int32_t> ce;   // pairs u < v, sorted
   std::vector<int32_t> se;   // pairs
 };
+// threads = 0: host_threads().
 void build_layout_graph(const mpld_rect* rects, int32_t n, int32_t dmin,
-                        int32_t split_len, OwnedGraph& out);
+                        int32_t split_len, OwnedGraph& out, int threads = 0);
 
 int host_threads();
 
@@ -76,4 +77,5 @@ struct mpld_result {
   std::vector<int32_t> comp_of;
   std::vector<mpld_comp_record> comps;
   int64_t stitches = 0, conflicts = 0, uncolored = 0;
+  double queue_us = 0, total_us = 0;   // serving timing
 };

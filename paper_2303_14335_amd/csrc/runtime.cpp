@@ -30,8 +30,8 @@ void image_add(Image& im, mpld_context* ctx, int32_t n, const int32_t* pairs, in
   const int32_t id = (int32_t)im.desc.size();
   d.comp = id;
   const bool force_lds = flags & MPLD_FORCE_LDS, force_glb = flags & MPLD_FORCE_GLOBAL,
-             force_reg = flags & MPLD_FORCE_WAVE;
-  if (n <= 64 && !force_lds && !force_glb) {
+             force_reg = flags & MPLD_FORCE_WAVE, force_dev = flags & MPLD_FORCE_DEVICE;
+  if (n <= 64 && !force_lds && !force_glb && !force_dev) {
     d.nbr_off = (int64_t)im.masks.size();
     im.masks.resize(im.masks.size() + (size_t)n, 0ull);
     uint64_t* mk = im.masks.data() + d.nbr_off;
@@ -68,7 +68,11 @@ void image_add(Image& im, mpld_context* ctx, int32_t n, const int32_t* pairs, in
     const int64_t small = lds_bytes_for(n, k, adj_words, (int32_t)maxdeg, false);
     const int64_t big = lds_bytes_for(n, k, adj_words, (int32_t)maxdeg, true);
     const int64_t limit = std::min<int64_t>(kLdsSmallLimit, ctx->lds_per_block);
-    if (!force_glb && small <= limit) {
+    if (force_dev) {
+      im.dev_stack_words = std::max(im.dev_stack_words, device_tier_stack_words(n, (int32_t)maxdeg));
+      im.dev_max_n = std::max(im.dev_max_n, n);
+      im.q_dev.push_back(id);
+    } else if (!force_glb && small <= limit) {
       im.lds_bytes_small = std::max(im.lds_bytes_small, small);
       im.q_lds.push_back(id);
     } else if (big <= ctx->lds_per_block) {
@@ -87,14 +91,16 @@ void image_add(Image& im, mpld_context* ctx, int32_t n, const int32_t* pairs, in
   im.core_edges += m;
 }
 
-void image_finish(Image& im) {
+void image_finish(Image& im, int order) {
   auto by_size = [&](int32_t a, int32_t b) {
-    if (im.desc[a].n != im.desc[b].n) return im.desc[a].n > im.desc[b].n;
+    if (im.desc[a].n != im.desc[b].n)
+      return order == 1 ? im.desc[a].n < im.desc[b].n : im.desc[a].n > im.desc[b].n;
     return a < b;
   };
   std::sort(im.q_reg.begin(), im.q_reg.end(), by_size);
   std::sort(im.q_lds.begin(), im.q_lds.end(), by_size);
   std::sort(im.q_big.begin(), im.q_big.end(), by_size);
+  std::sort(im.q_dev.begin(), im.q_dev.end(), by_size);
 }
 
 // ---------------------------------------------------------------------------
@@ -111,18 +117,31 @@ static int blocks_for_lds(mpld_context* ctx, int lds_bytes) {
   return by_lds * ctx->num_cus;
 }
 
-void device_upload(mpld_context* ctx, const Image& im, DeviceBatch& db) {
+void device_upload(mpld_context* ctx, const Image& im, DeviceBatch& db, const Tune& tune) {
   db.ctx = ctx;
+  db.tune = tune;
+  if (db.graph) {
+    (void)hipGraphExecDestroy(db.graph);
+    db.graph = nullptr;
+    db.graph_flags = 0xffffffffu;
+  }
   db.k = im.desc.empty() ? 3 : im.desc[0].k;
   db.num_comps = (int32_t)im.desc.size();
   db.total_nodes = im.total_nodes;
   db.n_reg = (int32_t)im.q_reg.size();
   db.n_lds = (int32_t)im.q_lds.size();
   db.n_big = (int32_t)im.q_big.size();
+  db.n_dev = (int32_t)im.q_dev.size();
+  db.grid_dev = ctx->num_cus;
+  db.lds_dev = device_tier_lds_bytes(std::max(1, im.dev_max_n), db.grid_dev);
   db.lds_small = (int)im.lds_bytes_small;
   db.lds_big = (int)im.lds_bytes_big;
   db.big_stack_words = (uint64_t)im.big_stack_words;
-  db.grid_reg = std::max(1, std::min((db.n_reg + 3) / 4, ctx->num_cus * ctx->reg_blocks_per_cu));
+  {
+    const int wpb = std::max(1, std::min(4, tune.waves_per_block));
+    const int cap = tune.max_blocks > 0 ? tune.max_blocks : ctx->num_cus * ctx->reg_blocks_per_cu * (4 / wpb);
+    db.grid_reg = std::max(1, std::min((db.n_reg + wpb - 1) / wpb, cap));
+  }
   db.grid_lds = std::max(1, std::min(db.n_lds, blocks_for_lds(ctx, db.lds_small)));
   db.grid_big = std::max(1, std::min(db.n_big, blocks_for_lds(ctx, db.lds_big)));
 
@@ -130,6 +149,7 @@ void device_upload(mpld_context* ctx, const Image& im, DeviceBatch& db) {
   db.host_queue.insert(db.host_queue.end(), im.q_reg.begin(), im.q_reg.end());
   db.host_queue.insert(db.host_queue.end(), im.q_lds.begin(), im.q_lds.end());
   db.host_queue.insert(db.host_queue.end(), im.q_big.begin(), im.q_big.end());
+  db.host_queue.insert(db.host_queue.end(), im.q_dev.begin(), im.q_dev.end());
 
   std::vector<DevDesc> ordered;
   ordered.reserve(db.host_queue.size());
@@ -141,7 +161,14 @@ void device_upload(mpld_context* ctx, const Image& im, DeviceBatch& db) {
   db.counters.alloc(ctx, sizeof(int32_t) * 8);
   db.recs.alloc(ctx, sizeof(DevRecord) * im.desc.size());
   db.colors.alloc(ctx, (size_t)im.total_nodes);
+  db.gstack.release();
+  db.dev_keys.release();
+  db.dev_stacks.release();
   if (db.n_big) db.gstack.alloc(ctx, sizeof(uint64_t) * db.big_stack_words * (size_t)db.grid_big);
+  if (db.n_dev) {
+    db.dev_keys.alloc(ctx, sizeof(uint64_t) * 4);
+    db.dev_stacks.alloc(ctx, sizeof(uint64_t) * (size_t)im.dev_stack_words * (size_t)db.grid_dev);
+  }
 
   hipStream_t s = ctx->stream;
   if (!ordered.empty())
@@ -154,6 +181,8 @@ void device_upload(mpld_context* ctx, const Image& im, DeviceBatch& db) {
     check_hip(hipMemcpyAsync(db.adj32.p, im.adj32.data(), sizeof(uint32_t) * im.adj32.size(),
                              hipMemcpyHostToDevice, s), "upload adjacency");
   check_hip(hipMemsetAsync(db.counters.p, 0, sizeof(int32_t) * 8, s), "clear counters");
+  if (db.n_dev)
+    check_hip(hipMemsetAsync(db.dev_keys.p, 0xff, sizeof(uint64_t) * 4, s), "clear keys");
   check_hip(hipStreamSynchronize(s), "upload");
 }
 
@@ -167,7 +196,8 @@ static void enqueue_batched(DeviceBatch& db, bool trace, hipStream_t s) {
   auto* gstack = db.gstack.as<uint64_t>();
   db.launches = 0;
   if (db.n_reg) {
-    check_hip(launch_reg_batched(trace, db.k, db.grid_reg, desc, masks, db.n_reg, cnt, recs, colors, s),
+    check_hip(launch_reg_batched(trace, db.k, db.grid_reg, db.tune.waves_per_block, desc, masks,
+                                 db.n_reg, cnt, recs, colors, s),
               "register-tier launch");
     ++db.launches;
   }
@@ -182,6 +212,13 @@ static void enqueue_batched(DeviceBatch& db, bool trace, hipStream_t s) {
                                  adj, db.n_big, cnt + 2, gstack, db.big_stack_words, recs, colors,
                                  s),
               "big-tier launch");
+    ++db.launches;
+  }
+  for (int32_t i = 0; i < db.n_dev; ++i) {   // one cooperative launch per giant
+    check_hip(launch_device_tier(trace, db.grid_dev, db.lds_dev, desc + db.n_reg + db.n_lds + db.n_big + i,
+                                 adj, db.dev_keys.as<unsigned long long>(),
+                                 db.dev_stacks.as<uint64_t>(), recs, colors, s),
+              "device-tier launch");
     ++db.launches;
   }
 }
@@ -207,13 +244,18 @@ void device_solve(DeviceBatch& db, uint32_t flags) {
         e = launch_reg_single(trace, db.k, desc, masks, i, recs, colors, s);
       else if (i < db.n_reg + db.n_lds)
         e = launch_lds_single(trace, false, db.lds_small, desc, adj, i, nullptr, recs, colors, s);
-      else
+      else if (i < db.n_reg + db.n_lds + db.n_big)
         e = launch_lds_single(trace, true, db.lds_big, desc, adj, i, gstack, recs, colors, s);
+      else
+        e = launch_device_tier(trace, db.grid_dev, db.lds_dev, desc + i, adj,
+                               db.dev_keys.as<unsigned long long>(), db.dev_stacks.as<uint64_t>(),
+                               recs, colors, s);
       check_hip(e, "plain launch");
       ++db.launches;
     }
     check_hip(hipEventRecord(ctx->ev[1], s), "event");
-  } else if (flags & MPLD_DIRECT) {
+  } else if ((flags & MPLD_DIRECT) || !db.tune.use_graph || db.n_dev) {
+    // direct launches (cooperative launches stay out of graphs)
     check_hip(hipEventRecord(ctx->ev[0], s), "event");
     enqueue_batched(db, trace, s);
     check_hip(hipEventRecord(ctx->ev[1], s), "event");
@@ -277,6 +319,42 @@ void device_fetch(DeviceBatch& db, std::vector<DevRecord>& recs, std::vector<int
   for (const auto& r : recs)
     if (r.status < 0 || r.status > MPLD_BUDGET_EXHAUSTED)
       fail(MPLD_E_INTERNAL, "search reported a broken state");
+}
+
+void assemble_result(const Graph& g, const Split& s, const Image& im, const mpld_options& opt,
+                     const std::vector<DevRecord>& recs, const std::vector<int8_t>& lcol,
+                     mpld_result* r) {
+  const bool trace = opt.flags & MPLD_TRACE_HASH;
+  r->colors.assign((size_t)g.n, -1);
+  r->comp_of = s.comp_of;
+  const int32_t nc = (int32_t)s.comp_ptr.size() - 1;
+  r->comps.resize((size_t)nc);
+  for (int32_t c = 0; c < nc; ++c) {
+    const DevDesc& d = im.desc[c];
+    for (int32_t i = 0; i < d.n; ++i) r->colors[s.order[s.comp_ptr[c] + i]] = lcol[d.out_off + i];
+  }
+  for (int32_t c = 0; c < nc; ++c) {
+    const DevDesc& d = im.desc[c];
+    mpld_comp_record& rec = r->comps[c];
+    rec.size = d.n;
+    rec.status = recs[c].status;
+    rec.nodes = (int64_t)recs[c].nodes;
+    rec.trace_hash = trace ? recs[c].hash : 0;
+    rec.depth_at_stop = recs[c].depth;
+    rec.first_node = s.order[s.comp_ptr[c]];
+    int64_t edges2 = 0;
+    int32_t st = 0;
+    for (int32_t p = s.comp_ptr[c]; p < s.comp_ptr[c + 1]; ++p) {
+      const int32_t x = s.order[p];
+      for (int64_t t = g.ptr[x]; t < g.ptr[x + 1]; ++t) edges2 += s.comp_of[g.adj[t]] == c;
+      const int32_t q = g.partner[x];
+      if (q > x && s.comp_of[q] == c && r->colors[q] != r->colors[x]) ++st;
+    }
+    rec.num_edges = (int32_t)(edges2 / 2);
+    rec.stitches = rec.status == MPLD_FEASIBLE ? st : -1;
+  }
+  if (opt.flags & MPLD_SIMPLIFY) recover(g, s, opt.k, r->colors);
+  tallies(g, r->colors, &r->stitches, &r->conflicts, &r->uncolored);
 }
 
 }  // namespace mpld

@@ -14,12 +14,18 @@ namespace mpld {
 
 // kernel launchers (defined with the kernels)
 // k: the batch's mask count (every component of a batch shares it).
-hipError_t launch_reg_batched(bool trace, int k, int grid, const DevDesc* descs,
+// wpb: waves per workgroup (1..4).
+hipError_t launch_reg_batched(bool trace, int k, int grid, int wpb, const DevDesc* descs,
                               const uint64_t* masks, int32_t qlen, int32_t* counter,
                               DevRecord* recs, int8_t* colors, hipStream_t s);
 hipError_t launch_reg_single(bool trace, int k, const DevDesc* descs, const uint64_t* masks,
                              int32_t item, DevRecord* recs, int8_t* colors, hipStream_t s);
 int reg_batched_blocks_per_cu(bool trace);
+// Serving tick over register-tier components (see the kernel).
+hipError_t launch_reg_tick(bool trace, int k, int grid, const int32_t* list, int32_t len,
+                           int32_t* counter, const DevDesc* slot_desc, uint8_t* slot_state,
+                           DevRecord* slot_rec, const uint64_t* arena64, int8_t* arena8,
+                           uint64_t slice, DevRecord* tick_out, hipStream_t s);
 hipError_t launch_lds_batched(bool trace, bool big, int grid, int lds_bytes, const DevDesc* descs,
                               const uint32_t* adj32, int32_t qlen, int32_t* counter,
                               uint64_t* gstack, uint64_t stack_words, DevRecord* recs,
@@ -31,6 +37,12 @@ hipError_t launch_lds_single(bool trace, bool big, int lds_bytes, const DevDesc*
 // global stack words of a big one.
 int64_t lds_bytes_for(int32_t n, int32_t k, int64_t adj_words, int32_t max_deg, bool big);
 int64_t lds_stack_words(int32_t n, int32_t max_deg);
+// Device-wide tier (cooperative launch over `grid` workgroups, one per CU).
+hipError_t launch_device_tier(bool trace, int grid, int lds_bytes, const DevDesc* desc,
+                              const uint32_t* adj32, unsigned long long* keys, uint64_t* stacks,
+                              DevRecord* recs, int8_t* colors, hipStream_t s);
+int device_tier_lds_bytes(int32_t n, int grid);
+int64_t device_tier_stack_words(int32_t n, int32_t max_deg);
 // Allows every LDS-tier kernel up to `bytes` of dynamic LDS (once per context).
 void lds_configure(int bytes);
 
@@ -84,31 +96,47 @@ struct Image {
   std::vector<DevDesc> desc;       // by component id
   std::vector<uint64_t> masks;     // register tier: one neighbour mask per node
   std::vector<uint32_t> adj32;     // LDS tiers: row offsets, ids, max degree
-  std::vector<int32_t> q_reg, q_lds, q_big;   // component ids per tier
+  std::vector<int32_t> q_reg, q_lds, q_big, q_dev;   // component ids per tier
   int32_t total_nodes = 0;
   int32_t max_size = 0;
   int64_t core_edges = 0;
   int64_t lds_bytes_small = 0;     // largest footprint on the LDS tier
   int64_t lds_bytes_big = 0;       // largest footprint on the big tier
   int64_t big_stack_words = 0;     // largest global stack of the big tier
+  int64_t dev_stack_words = 0;     // largest per-workgroup stack of the device tier
+  int32_t dev_max_n = 0;
 };
 
 // LDS byte limit for a component to keep its lists and stack in LDS.
 constexpr int64_t kLdsSmallLimit = 64 * 1024;
+
+// Launch parameters of a batch (chosen by the autotuner or defaults).
+struct Tune {
+  int32_t waves_per_block = 4;   // register tier workgroup = 64 * waves
+  int32_t max_blocks = 0;        // register tier grid cap; 0 = one wave per component
+  int32_t use_graph = 1;         // replay a captured HIP graph
+  int32_t order = 0;             // 0 largest first, 1 smallest first
+  int32_t giant_device = 0;      // giants on the device-wide tier instead of the big tier
+  int32_t giant_min_nodes = 4096;
+};
 
 // Adds one component (local numbering, pairs i < j or j < i) to the image.
 // Throws MPLD_E_UNSUPPORTED when a forced tier cannot take it or it does
 // not fit any tier.
 void image_add(Image& im, mpld_context* ctx, int32_t n, const int32_t* pairs, int64_t m,
                int32_t k, int64_t budget, uint32_t flags);
-// Sorts each tier's queue by descending size (then id).
-void image_finish(Image& im);
+// Sorts each tier's queue by size (descending, or ascending when order = 1),
+// ties by id.
+void image_finish(Image& im, int order = 0);
 
 // Device copy of an image plus its outputs and queue counters.
 struct DeviceBatch {
   mpld_context* ctx = nullptr;
   DevBuf desc, masks, adj32, counters, recs, colors, gstack;  // desc in launch order
-  int32_t n_reg = 0, n_lds = 0, n_big = 0;
+  DevBuf dev_keys, dev_stacks;      // device-wide tier
+  Tune tune;
+  int32_t n_reg = 0, n_lds = 0, n_big = 0, n_dev = 0;
+  int grid_dev = 1, lds_dev = 0;
   int32_t num_comps = 0, total_nodes = 0;
   int32_t k = 3;
   int grid_reg = 1, grid_lds = 1, grid_big = 1;
@@ -123,9 +151,16 @@ struct DeviceBatch {
   ~DeviceBatch();
 };
 
-void device_upload(mpld_context* ctx, const Image& im, DeviceBatch& db);
+void device_upload(mpld_context* ctx, const Image& im, DeviceBatch& db, const Tune& tune = Tune());
 // Enqueues the search of every component on the context stream (no wait).
 void device_solve(DeviceBatch& db, uint32_t flags);
+// Result of a decomposition from the device records and local colors: maps
+// local colors to nodes, fills the component records, recovers the removed
+// nodes and computes the Eq. 1 tallies.
+void assemble_result(const Graph& g, const Split& s, const Image& im, const mpld_options& opt,
+                     const std::vector<DevRecord>& recs, const std::vector<int8_t>& lcol,
+                     mpld_result* r);
+
 // Reads the last solve's event time if the stream has passed it.
 bool device_time(DeviceBatch& db);
 // Waits, then copies records and colors back.
@@ -141,4 +176,14 @@ struct mpld_batch {
   mpld::Image im;
   mpld::DeviceBatch db;
   bool solved = false;
+  bool tuned_from_cache = false;
 };
+
+namespace mpld {
+// Packs the batch's components with tune `t` (tier of giants, queue order)
+// and uploads them (launch geometry).
+void batch_pack(mpld_batch* b, const Tune& t);
+// Looks the batch's shape up in the tuning cache (path, else $MPLD_TUNE_CACHE);
+// true and *t filled on a hit.
+bool tune_from_cache(mpld_batch* b, const char* path, Tune* t);
+}  // namespace mpld

@@ -51,33 +51,51 @@ __device__ __forceinline__ uint32_t uniform(uint32_t x) {
   return (uint32_t)__builtin_amdgcn_readfirstlane((int)x);
 }
 
-// Searches one component; every lane of the wave must call it.  NB = bits
-// of a row count (k < 2^NB).
-//   rm   (VGPR)      open colors of the lane's node (k-bit row mask)
-//   nb   (VGPR pair) the lane's neighbour mask
-//   lost (VGPR pair) bit d set iff this lane's node lost a color when the
-//                    row at depth d was taken (the undo record)
-//   st   (VGPR)      lane d holds frame d: v | c << 8
-//   P, depth, nodes, hash: wave-uniform (SGPRs)
-template <bool TRACE, int NB>
-__device__ __forceinline__ void solve_reg(const int32_t n, const int32_t k, const uint64_t budget,
-                                          const uint64_t* __restrict__ nbmask,
-                                          int8_t* __restrict__ colors,
-                                          DevRecord* __restrict__ rec) {
+// Search state of one component.  Per lane (VGPRs):
+//   rm    open colors of the lane's node (k-bit row mask)
+//   lost  bit d set iff this lane's node lost a color when the row at depth
+//         d was taken (the undo record)
+//   st    lane d holds frame d: v | c << 8
+// Wave-uniform (SGPRs): P (uncovered columns), depth, nodes, hash, entering
+// row, status (-1 while the search runs or is paused).
+struct RegState {
+  uint32_t rm, st;
+  uint64_t lost;
+  uint64_t P, nodes, h;
+  uint32_t depth, row_in;
+  int32_t status;
+};
+
+__device__ __forceinline__ void reg_init(RegState& s, int32_t n, int32_t k) {
   const uint32_t lane = __lane_id();
-  const uint64_t nb = lane < (uint32_t)n ? nbmask[lane] : 0ull;
-  uint32_t rm = lane < (uint32_t)n ? ((1u << k) - 1u) : 0u;
-  uint64_t P = n >= 64 ? ~0ull : ((1ull << n) - 1ull);
-  uint64_t lost = 0;
-  uint32_t st = 0;
-  uint32_t depth = 0;
-  uint64_t nodes = 0;
-  uint64_t h = kFnvOffset;
-  uint32_t row_in = kNone;
+  s.rm = lane < (uint32_t)n ? ((1u << k) - 1u) : 0u;
+  s.st = 0;
+  s.lost = 0;
+  s.P = n >= 64 ? ~0ull : ((1ull << n) - 1ull);
+  s.nodes = 0;
+  s.h = kFnvOffset;
+  s.depth = 0;
+  s.row_in = kNone;
+  s.status = -1;
+}
+
+// Runs the search until it ends or `nodes` reaches stop_at (<= budget); a
+// stop short of the budget leaves status -1 and the state resumable at a
+// node boundary.  NB = bits of a row count (k < 2^NB).  Every lane of the
+// wave must call it.
+template <bool TRACE, int NB>
+__device__ __forceinline__ void reg_run(RegState& s, const uint64_t nb, const int32_t k,
+                                        const uint64_t budget, const uint64_t stop_at) {
+  const uint32_t lane = __lane_id();
+  uint32_t rm = s.rm, st = s.st, depth = s.depth, row_in = s.row_in;
+  uint64_t lost = s.lost, P = s.P, nodes = s.nodes, h = s.h;
   int32_t status = -1;
-  while (status < 0) {
+  for (;;) {
     // ---- one search node
-    if (nodes == budget) { status = MPLD_BUDGET_EXHAUSTED; break; }
+    if (nodes == stop_at) {
+      if (nodes == budget) status = MPLD_BUDGET_EXHAUSTED;
+      break;
+    }
     ++nodes;
     if (P == 0) {
       if (TRACE) h = trace_node(h, depth, row_in, kNone, 0);
@@ -128,18 +146,76 @@ __device__ __forceinline__ void solve_reg(const int32_t n, const int32_t k, cons
     ++depth;
     row_in = v * (uint32_t)k + c;
   }
-  if (status == MPLD_FEASIBLE) {
-    if (lane < depth && (st & 0xffu) < (uint32_t)n) colors[st & 0xffu] = (int8_t)(st >> 8);
+  s.rm = rm; s.st = st; s.depth = depth; s.row_in = row_in;
+  s.lost = lost; s.P = P; s.nodes = nodes; s.h = h;
+  s.status = status;
+}
+
+// Writes the colors (the chosen row of every column on a solution, -1
+// otherwise) and the record of a finished search.
+__device__ __forceinline__ void reg_finish(const RegState& s, int32_t n, int8_t* __restrict__ colors,
+                                           DevRecord* __restrict__ rec) {
+  const uint32_t lane = __lane_id();
+  if (s.status == MPLD_FEASIBLE) {
+    if (lane < s.depth && (s.st & 0xffu) < (uint32_t)n) colors[s.st & 0xffu] = (int8_t)(s.st >> 8);
   } else if (lane < (uint32_t)n) {
     colors[lane] = -1;
   }
   // Every lane stores the same (uniform) record: no branch here may share
   // the queue pop's "lane 0" condition, or the compiler can thread the two
   // across the loop back-edge and split the wave at the pop.
-  rec->status = status;
-  rec->depth = status == MPLD_INFEASIBLE ? 0 : (int32_t)depth;
-  rec->nodes = nodes;
-  rec->hash = h;
+  rec->status = s.status;
+  rec->depth = s.status == MPLD_INFEASIBLE ? 0 : (int32_t)s.depth;
+  rec->nodes = s.nodes;
+  rec->hash = s.h;
+}
+
+template <bool TRACE, int NB>
+__device__ __forceinline__ void solve_reg(const int32_t n, const int32_t k, const uint64_t budget,
+                                          const uint64_t* __restrict__ nbmask,
+                                          int8_t* __restrict__ colors,
+                                          DevRecord* __restrict__ rec) {
+  const uint32_t lane = __lane_id();
+  const uint64_t nb = lane < (uint32_t)n ? nbmask[lane] : 0ull;
+  RegState s;
+  reg_init(s, n, k);
+  reg_run<TRACE, NB>(s, nb, k, budget, budget);
+  reg_finish(s, n, colors, rec);
+}
+
+// Resumable state in device memory (kRegStateBytes per component): the
+// uniform part first, then the three lane arrays.
+struct RegStateHead {
+  uint64_t P, nodes, h;
+  uint32_t depth, row_in;
+};
+static_assert(sizeof(RegStateHead) == 32, "state head is 32 bytes");
+
+__device__ __forceinline__ void reg_save(const RegState& s, uint8_t* base) {
+  const uint32_t lane = __lane_id();
+  RegStateHead* hd = reinterpret_cast<RegStateHead*>(base);
+  hd->P = s.P;   // same value from every lane
+  hd->nodes = s.nodes;
+  hd->h = s.h;
+  hd->depth = s.depth;
+  hd->row_in = s.row_in;
+  reinterpret_cast<uint32_t*>(base + 64)[lane] = s.rm;
+  reinterpret_cast<uint32_t*>(base + 64 + 256)[lane] = s.st;
+  reinterpret_cast<uint64_t*>(base + 64 + 512)[lane] = s.lost;
+}
+
+__device__ __forceinline__ void reg_load(RegState& s, const uint8_t* base) {
+  const uint32_t lane = __lane_id();
+  const RegStateHead* hd = reinterpret_cast<const RegStateHead*>(base);
+  s.P = ((uint64_t)uniform((uint32_t)(hd->P >> 32)) << 32) | uniform((uint32_t)hd->P);
+  s.nodes = ((uint64_t)uniform((uint32_t)(hd->nodes >> 32)) << 32) | uniform((uint32_t)hd->nodes);
+  s.h = ((uint64_t)uniform((uint32_t)(hd->h >> 32)) << 32) | uniform((uint32_t)hd->h);
+  s.depth = uniform(hd->depth);
+  s.row_in = uniform(hd->row_in);
+  s.rm = reinterpret_cast<const uint32_t*>(base + 64)[lane];
+  s.st = reinterpret_cast<const uint32_t*>(base + 64 + 256)[lane];
+  s.lost = reinterpret_cast<const uint64_t*>(base + 64 + 512)[lane];
+  s.status = -1;
 }
 
 // Persistent batched kernel.  Wave w first takes item w of its tier's
@@ -152,8 +228,9 @@ template <bool TRACE, int NB>
 __global__ __launch_bounds__(256) void reg_batched_kernel(
     const DevDesc* __restrict__ descs, const uint64_t* __restrict__ masks, int32_t qlen,
     int32_t* __restrict__ counter, DevRecord* __restrict__ recs, int8_t* __restrict__ colors) {
-  const int32_t gw = (int32_t)gridDim.x * 4;
-  int32_t item = (int32_t)uniform(blockIdx.x * 4u + (threadIdx.x >> 6));
+  const uint32_t wpb = blockDim.x >> 6;   // waves per workgroup
+  const int32_t gw = (int32_t)(gridDim.x * wpb);
+  int32_t item = (int32_t)uniform(blockIdx.x * wpb + (threadIdx.x >> 6));
   while (item < qlen) {
     const DevDesc d = descs[item];
     solve_reg<TRACE, NB>(d.n, d.k, (uint64_t)d.budget, masks + d.nbr_off, colors + d.out_off,
@@ -178,6 +255,52 @@ __global__ __launch_bounds__(64) void reg_single_kernel(const DevDesc* __restric
                        recs + d.comp);
 }
 
+// Serving tick: every listed component advances by at most `slice` search
+// nodes from its saved state (entries with bit 31 set start fresh).  A
+// finished search writes its colors and record; a paused one saves its
+// state.  tick_out[i] receives the record of list entry i (status -1 while
+// the search is still running).  Work distribution as in the batched kernel.
+template <bool TRACE, int NB>
+__global__ __launch_bounds__(256) void reg_tick_kernel(
+    const int32_t* __restrict__ list, int32_t len, int32_t* __restrict__ counter,
+    const DevDesc* __restrict__ slot_desc, uint8_t* slot_state, DevRecord* __restrict__ slot_rec,
+    const uint64_t* __restrict__ arena64, int8_t* __restrict__ arena8, uint64_t slice,
+    DevRecord* __restrict__ tick_out) {
+  const int32_t gw = (int32_t)gridDim.x * 4;
+  int32_t item = (int32_t)uniform(blockIdx.x * 4u + (threadIdx.x >> 6));
+  while (item < len) {
+    const uint32_t entry = uniform((uint32_t)list[item]);
+    const int32_t slot = (int32_t)(entry & 0x7fffffffu);
+    const DevDesc d = slot_desc[slot];
+    const uint32_t lane = __lane_id();
+    const uint64_t nb = lane < (uint32_t)d.n ? arena64[d.nbr_off + lane] : 0ull;
+    uint8_t* base = slot_state + (uint64_t)slot * kRegStateBytes;
+    RegState s;
+    if (entry >> 31)
+      reg_init(s, d.n, d.k);
+    else
+      reg_load(s, base);
+    const uint64_t budget = (uint64_t)d.budget;
+    const uint64_t stop = budget - s.nodes > slice ? s.nodes + slice : budget;
+    reg_run<TRACE, NB>(s, nb, d.k, budget, stop);
+    if (s.status >= 0)
+      reg_finish(s, d.n, arena8 + d.out_off, slot_rec + slot);
+    else
+      reg_save(s, base);
+    DevRecord* o = tick_out + item;
+    o->status = s.status;
+    o->depth = (int32_t)s.depth;
+    o->nodes = s.nodes;
+    o->hash = s.h;
+    if (gw >= len) break;
+    int32_t r = 0;
+    if (__lane_id() == 0) r = atomicAdd(counter, 1);
+    r = (int32_t)uniform((uint32_t)r);
+    item = gw + r;
+    if (r == len - 1) atomicExch(counter, 0);
+  }
+}
+
 __global__ void fill_i32_kernel(int32_t* __restrict__ p, int32_t count, int32_t value) {
   const int32_t i = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
   if (i < count) p[i] = value;
@@ -195,10 +318,11 @@ hipError_t launch_fill_i32(int32_t* p, int32_t count, int32_t value, hipStream_t
 static int count_bits(int k) { return k < 4 ? 2 : (k < 8 ? 3 : 4); }
 
 template <bool TRACE, int NB>
-static void reg_batched_t(int grid, const DevDesc* descs, const uint64_t* masks, int32_t qlen,
-                          int32_t* counter, DevRecord* recs, int8_t* colors, hipStream_t s) {
-  hipLaunchKernelGGL((reg_batched_kernel<TRACE, NB>), dim3(grid), dim3(256), 0, s, descs, masks,
-                     qlen, counter, recs, colors);
+static void reg_batched_t(int grid, int wpb, const DevDesc* descs, const uint64_t* masks,
+                          int32_t qlen, int32_t* counter, DevRecord* recs, int8_t* colors,
+                          hipStream_t s) {
+  hipLaunchKernelGGL((reg_batched_kernel<TRACE, NB>), dim3(grid), dim3(64 * wpb), 0, s, descs,
+                     masks, qlen, counter, recs, colors);
 }
 
 template <bool TRACE, int NB>
@@ -208,17 +332,18 @@ static void reg_single_t(const DevDesc* descs, const uint64_t* masks, int32_t it
                      recs, colors);
 }
 
-hipError_t launch_reg_batched(bool trace, int k, int grid, const DevDesc* descs,
+hipError_t launch_reg_batched(bool trace, int k, int grid, int wpb, const DevDesc* descs,
                               const uint64_t* masks, int32_t qlen, int32_t* counter,
                               DevRecord* recs, int8_t* colors, hipStream_t s) {
   if (qlen <= 0) return hipSuccess;
+  if (wpb < 1 || wpb > 4) return hipErrorInvalidValue;
   switch (count_bits(k) + (trace ? 8 : 0)) {
-    case 2: reg_batched_t<false, 2>(grid, descs, masks, qlen, counter, recs, colors, s); break;
-    case 3: reg_batched_t<false, 3>(grid, descs, masks, qlen, counter, recs, colors, s); break;
-    case 4: reg_batched_t<false, 4>(grid, descs, masks, qlen, counter, recs, colors, s); break;
-    case 10: reg_batched_t<true, 2>(grid, descs, masks, qlen, counter, recs, colors, s); break;
-    case 11: reg_batched_t<true, 3>(grid, descs, masks, qlen, counter, recs, colors, s); break;
-    default: reg_batched_t<true, 4>(grid, descs, masks, qlen, counter, recs, colors, s); break;
+    case 2: reg_batched_t<false, 2>(grid, wpb, descs, masks, qlen, counter, recs, colors, s); break;
+    case 3: reg_batched_t<false, 3>(grid, wpb, descs, masks, qlen, counter, recs, colors, s); break;
+    case 4: reg_batched_t<false, 4>(grid, wpb, descs, masks, qlen, counter, recs, colors, s); break;
+    case 10: reg_batched_t<true, 2>(grid, wpb, descs, masks, qlen, counter, recs, colors, s); break;
+    case 11: reg_batched_t<true, 3>(grid, wpb, descs, masks, qlen, counter, recs, colors, s); break;
+    default: reg_batched_t<true, 4>(grid, wpb, descs, masks, qlen, counter, recs, colors, s); break;
   }
   return hipGetLastError();
 }
@@ -232,6 +357,31 @@ hipError_t launch_reg_single(bool trace, int k, const DevDesc* descs, const uint
     case 10: reg_single_t<true, 2>(descs, masks, item, recs, colors, s); break;
     case 11: reg_single_t<true, 3>(descs, masks, item, recs, colors, s); break;
     default: reg_single_t<true, 4>(descs, masks, item, recs, colors, s); break;
+  }
+  return hipGetLastError();
+}
+
+template <bool TRACE, int NB>
+static void reg_tick_t(int grid, const int32_t* list, int32_t len, int32_t* counter,
+                       const DevDesc* slot_desc, uint8_t* slot_state, DevRecord* slot_rec,
+                       const uint64_t* arena64, int8_t* arena8, uint64_t slice,
+                       DevRecord* tick_out, hipStream_t s) {
+  hipLaunchKernelGGL((reg_tick_kernel<TRACE, NB>), dim3(grid), dim3(256), 0, s, list, len, counter,
+                     slot_desc, slot_state, slot_rec, arena64, arena8, slice, tick_out);
+}
+
+hipError_t launch_reg_tick(bool trace, int k, int grid, const int32_t* list, int32_t len,
+                           int32_t* counter, const DevDesc* slot_desc, uint8_t* slot_state,
+                           DevRecord* slot_rec, const uint64_t* arena64, int8_t* arena8,
+                           uint64_t slice, DevRecord* tick_out, hipStream_t s) {
+  if (len <= 0) return hipSuccess;
+  switch (count_bits(k) + (trace ? 8 : 0)) {
+    case 2: reg_tick_t<false, 2>(grid, list, len, counter, slot_desc, slot_state, slot_rec, arena64, arena8, slice, tick_out, s); break;
+    case 3: reg_tick_t<false, 3>(grid, list, len, counter, slot_desc, slot_state, slot_rec, arena64, arena8, slice, tick_out, s); break;
+    case 4: reg_tick_t<false, 4>(grid, list, len, counter, slot_desc, slot_state, slot_rec, arena64, arena8, slice, tick_out, s); break;
+    case 10: reg_tick_t<true, 2>(grid, list, len, counter, slot_desc, slot_state, slot_rec, arena64, arena8, slice, tick_out, s); break;
+    case 11: reg_tick_t<true, 3>(grid, list, len, counter, slot_desc, slot_state, slot_rec, arena64, arena8, slice, tick_out, s); break;
+    default: reg_tick_t<true, 4>(grid, list, len, counter, slot_desc, slot_state, slot_rec, arena64, arena8, slice, tick_out, s); break;
   }
   return hipGetLastError();
 }

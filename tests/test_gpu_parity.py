@@ -16,7 +16,7 @@ pytestmark = pytest.mark.gpu
 
 TRACE = 1 << 1
 SIMPLIFY = 1 << 0
-FORCE = {"wave": 1 << 3, "lds": 1 << 4, "global": 1 << 5}
+FORCE = {"wave": 1 << 3, "lds": 1 << 4, "global": 1 << 5, "device": 1 << 7}
 
 
 def say(*a):
@@ -86,7 +86,7 @@ def solve_both(ctx, comps, k, budget, flags):
         assert np.array_equal(c, s.colors)
 
 
-@pytest.mark.parametrize("tier", ["auto", "lds", "global"])
+@pytest.mark.parametrize("tier", ["auto", "lds", "global", "device"])
 def test_known_graphs_every_tier(ctx, tier):
     say("known graphs, tier", tier)
     flags = 0 if tier == "auto" else FORCE[tier]
@@ -138,6 +138,18 @@ def test_larger_components_lds_tiers(ctx):
     say("larger components")
     for flags in (0, FORCE["global"]):
         solve_both(ctx, comps, 3, 30000, flags)
+    say("larger components, device-wide tier")
+    solve_both(ctx, comps[:3], 3, 3000, FORCE["device"])
+
+
+def test_config3_giant_device_tier(ctx):
+    import paper_2303_14335_amd as mp
+    w, rects = graph_of(3)
+    say("config 3 on the device-wide tier")
+    g = mp.mpld_build_graph(rects, w.dmin_nm, w.split_len_nm)
+    ref = oracle.decompose(oracle.Graph(g.num_nodes, g.ce, g.se), w.k, w.budget)
+    got = mp.mpld_decompose(ctx, g, w.k, w.budget, SIMPLIFY | TRACE | FORCE["device"])
+    compare_decomposition(got, ref)
 
 
 def test_plain_equals_batched_and_trace_off(ctx):
@@ -193,3 +205,41 @@ def test_invalid_arguments(ctx):
     with pytest.raises(mp.MpldError) as e:
         mp.mpld_solve_components(ctx, [(70, cycle(70))], 3, 10, FORCE["wave"])
     assert e.value.code == -7
+
+
+def test_autotune_keeps_results_and_caches(ctx, tmp_path):
+    import paper_2303_14335_amd as mp
+    w, rects = graph_of(2, 30000)
+    say("autotune on 30k rects of config 2")
+    g = mp.mpld_build_graph(rects, w.dmin_nm, w.split_len_nm)
+    b = mp.Batch(ctx, g, w.k, 20000, SIMPLIFY)
+    b.solve()
+    ref = b.result()
+    cache = str(tmp_path / "tune.jsonl")
+    t = b.autotune(reps=3, cache_path=cache)
+    assert t["candidates"] > 1 and t["best_ms"] <= t["default_ms"] * 1.0001
+    b.solve()
+    got = b.result()
+    assert np.array_equal(got.colors, ref.colors)
+    assert np.array_equal(got.components["nodes"], ref.components["nodes"])
+    # every schedule gives the same answer
+    for wpb in (1, 2):
+        for order in (0, 1):
+            b.set_tune(waves_per_block=wpb, order=order, use_graph=0, max_blocks=64)
+            b.solve()
+            r = b.result()
+            assert np.array_equal(r.colors, ref.colors)
+            assert np.array_equal(r.components["status"], ref.components["status"])
+    b.close()
+    # a new batch of the same shape picks the cached schedule up
+    import os
+    os.environ["MPLD_TUNE_CACHE"] = cache
+    try:
+        b2 = mp.Batch(ctx, g, w.k, 20000, SIMPLIFY)
+        t2 = b2.get_tune()
+        b2.close()
+    finally:
+        del os.environ["MPLD_TUNE_CACHE"]
+    assert t2["from_cache"] == 1
+    assert (t2["waves_per_block"], t2["order"], t2["use_graph"]) == (
+        t["waves_per_block"], t["order"], t["use_graph"])

@@ -1,0 +1,150 @@
+"""GPU tests of the continuous-batching server.
+
+A request's result must be a function of its graph and options only: the
+same alone (one-shot decomposition) as in a mix of concurrent requests,
+for any per-tick slice of search nodes, with admission forced to wait by a
+small device arena; an oversize request fails with MPLD_E_NOMEM instead of
+waiting; traced requests keep their trace hash.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workload
+
+pytestmark = pytest.mark.gpu
+
+SIMPLIFY, TRACE = 1, 2
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+def same(a, b):
+    assert np.array_equal(a.colors, b.colors)
+    assert np.array_equal(a.component_of, b.component_of)
+    for f in a.components.dtype.names:
+        assert np.array_equal(a.components[f], b.components[f]), f
+    assert (a.stitches, a.conflicts, a.uncolored) == (b.stitches, b.conflicts, b.uncolored)
+
+
+def requests(count, seed, n_max=6000, k=3, dmin=80, split=0):
+    t = workload.request_trace(seed, count, n_min=100, n_max=n_max)
+    out = []
+    for i in range(count):
+        rects, _ = workload.generate(int(t["n_rects"][i]), int(t["side_nm"][i]), int(t["seed"][i]))
+        out.append(dict(rects=rects, dmin=dmin, split=split, k=k))
+    return out
+
+
+def alone(ctx, req, budget, flags):
+    import paper_2303_14335_amd as mp
+    g = mp.mpld_build_graph(req["rects"], req["dmin"], req["split"])
+    return mp.mpld_decompose(ctx, g, req["k"], budget, flags)
+
+
+@pytest.mark.parametrize("slice_nodes", [1, 7, 4096])
+def test_mix_equals_alone(ctx, slice_nodes):
+    import paper_2303_14335_amd as mp
+    reqs = requests(40, seed=slice_nodes)
+    say("serve mix, slice", slice_nodes, "requests", len(reqs))
+    srv = mp.Server(ctx, slice_nodes=slice_nodes, max_components=4096, arena_bytes=32 << 20)
+    tickets = [srv.submit_layout(r["rects"], r["dmin"], r["split"], r["k"], 10**6, SIMPLIFY | TRACE)
+               for r in reqs]
+    results = [srv.wait(t, 60_000_000) for t in tickets]
+    st = srv.stats()
+    srv.close()
+    assert st["completed"] == len(reqs) and st["failed"] == 0
+    for r, got in zip(reqs, results):
+        assert got is not None
+        same(got, alone(ctx, r, 10**6, SIMPLIFY | TRACE))
+        assert got.total_us >= got.queue_us >= 0
+
+
+def test_stitched_k4_heavy_components_sliced(ctx):
+    import paper_2303_14335_amd as mp
+    reqs = requests(12, seed=77, n_max=20000, k=4, dmin=120, split=120)
+    say("serve k=4 stitched, slice 5")
+    srv = mp.Server(ctx, slice_nodes=5, max_components=8192)
+    tickets = [srv.submit_layout(r["rects"], r["dmin"], r["split"], r["k"], 20000, SIMPLIFY)
+               for r in reqs]
+    results = [srv.wait(t, 60_000_000) for t in tickets]
+    ticks = srv.stats()["ticks"]
+    srv.close()
+    for r, got in zip(reqs, results):
+        same(got, alone(ctx, r, 20000, SIMPLIFY))
+    assert ticks > 5   # heavy components took several ticks
+    # and one of them against the oracle directly
+    r = reqs[0]
+    ref = oracle.decompose(oracle.build_graph(r["rects"], r["dmin"], r["split"]), 4, 20000)
+    assert np.array_equal(results[0].colors, ref.colors)
+
+
+def test_admission_waits_for_device_bytes(ctx):
+    import paper_2303_14335_amd as mp
+    reqs = requests(16, seed=5, n_max=3000)
+    say("serve tiny arena")
+    srv = mp.Server(ctx, arena_bytes=96 << 10, max_components=2048, slice_nodes=3)
+    tickets = [srv.submit_layout(r["rects"], r["dmin"], r["split"], r["k"], 10**6) for r in reqs]
+    results = [srv.wait(t, 60_000_000) for t in tickets]
+    st = srv.stats()
+    srv.close()
+    assert st["completed"] == len(reqs)
+    assert st["admission_waits"] > 0
+    assert st["peak_bytes"] <= 96 << 10
+    for r, got in zip(reqs, results):
+        same(got, alone(ctx, r, 10**6, SIMPLIFY))
+
+
+def test_oversize_request_is_nomem_not_a_hang(ctx):
+    import paper_2303_14335_amd as mp
+    say("serve oversize")
+    srv = mp.Server(ctx, arena_bytes=4096, max_components=64)
+    rects, _ = workload.generate(20000, 8000, 3)
+    t = srv.submit_layout(rects, 80, 0, 3, 1000)
+    small, _ = workload.generate(50, 3000, 4)
+    t2 = srv.submit_layout(small, 80, 0, 3, 1000)
+    with pytest.raises(mp.MpldError) as e:
+        srv.wait(t, 60_000_000)
+    assert e.value.code == -2
+    assert srv.wait(t2, 60_000_000) is not None     # later requests still run
+    srv.close()
+
+
+def test_bad_graph_and_unknown_ticket(ctx):
+    import paper_2303_14335_amd as mp
+    say("serve errors")
+    srv = mp.Server(ctx)
+    g = mp.Graph(3, np.array([[0, 5]]), np.zeros((0, 2), np.int32))
+    t = srv.submit(g, 3, 100)
+    with pytest.raises(mp.MpldError) as e:
+        srv.wait(t, 60_000_000)
+    assert e.value.code == -1
+    with pytest.raises(mp.MpldError):
+        srv.poll(123456789)
+    srv.close()
+
+
+def test_lds_tier_components_in_the_mix(ctx):
+    import paper_2303_14335_amd as mp
+    from algx_literal import random_graph
+    rng = np.random.default_rng(8)
+    graphs = []
+    for n in (90, 150, 300):
+        e = np.array(random_graph(rng, n, 5.0 / n), dtype=np.int32).reshape(-1, 2)
+        graphs.append(mp.Graph(n, e, np.zeros((0, 2), np.int32)))
+    say("serve LDS-tier components")
+    srv = mp.Server(ctx, slice_nodes=11)
+    tickets = [srv.submit(g, 3, 5000, SIMPLIFY | TRACE) for g in graphs]
+    small = requests(6, seed=9)
+    tickets += [srv.submit_layout(r["rects"], r["dmin"], 0, 3, 5000, SIMPLIFY | TRACE) for r in small]
+    results = [srv.wait(t, 60_000_000) for t in tickets]
+    srv.close()
+    for g, got in zip(graphs, results[:3]):
+        ref = oracle.decompose(oracle.Graph(g.num_nodes, g.ce, g.se), 3, 5000)
+        assert np.array_equal(got.colors, ref.colors)
+        assert np.array_equal(got.components["nodes"], ref.comps["nodes"])
+        assert np.array_equal(got.components["trace_hash"], ref.comps["trace_hash"])
+    for r, got in zip(small, results[3:]):
+        same(got, alone(ctx, r, 5000, SIMPLIFY | TRACE))
