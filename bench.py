@@ -147,6 +147,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--config", type=int, default=1, help="workload (workload/configs.py)")
     ap.add_argument("--plain-steps", type=int, default=10)
+    ap.add_argument("--split", action="store_true",
+                    help="search heavy components as parallel subtrees (exact sequential counts)")
     ap.add_argument("--launch", choices=["graph", "direct"], default="graph",
                     help="batched solve: replay the captured HIP graph or launch directly")
     ap.add_argument("--kernel-reps", type=int, default=50,
@@ -186,7 +188,7 @@ def main() -> int:
     t1 = time.perf_counter()
     b = mp.Batch(ctx, g, w.k, w.budget, mp.MPLD_SIMPLIFY)
     t2 = time.perf_counter()
-    b.solve()
+    b.solve(split=args.split)
     res = b.result()
     t3 = time.perf_counter()
     info = b.info()
@@ -198,15 +200,16 @@ def main() -> int:
 
     # ---- batched: K back-to-back solves (graph replays or direct launches)
     direct = args.launch == "direct"
+    split = args.split
     for _ in range(args.warmup):
-        b.solve(direct=direct)
+        b.solve(direct=direct, split=split)
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     ts = time.perf_counter()
     e0.record(stream)
     for _ in range(args.steps):
-        b.solve(direct=direct)
+        b.solve(direct=direct, split=split)
     e1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - ts
@@ -299,6 +302,7 @@ def main() -> int:
         "components_per_s": ncomp * args.steps / wall,
         "device_ms_per_step": dev_ms / args.steps,
         "launch": args.launch,
+        "split_heavy": args.split,
         "plain": {"ms_per_step": plain_ms, "search_nodes_per_s": total_nodes / (plain_ms * 1e-3),
                   "components_per_s": ncomp / (plain_ms * 1e-3), "launches": ncomp,
                   "same_result": same},

@@ -88,10 +88,18 @@ enum {
   MPLD_FORCE_GLOBAL = 1u << 5, /* force the global-memory tier                */
   MPLD_DIRECT = 1u << 6,       /* batched solve: launch the kernels directly
                                   instead of replaying the captured HIP graph */
-  MPLD_FORCE_DEVICE = 1u << 7  /* force the device-wide tier: one component at a
+  MPLD_FORCE_DEVICE = 1u << 7, /* force the device-wide tier: one component at a
                                   time over every CU, columns split across
                                   workgroups, a device-wide min-count reduction
                                   per search node                              */
+  MPLD_SPLIT_HEAVY = 1u << 8   /* register-tier components still searching after
+                                  a first capped pass are searched in parallel
+                                  subtrees by many wavefronts; the sequential
+                                  status, node count, depth and colors are
+                                  recomputed exactly from the subtrees' counts
+                                  in search order (not with MPLD_TRACE_HASH; a
+                                  component cut by its budget is re-run
+                                  sequentially).  Makes mpld_batch_solve wait. */
 };
 
 typedef struct { int32_t x0, y0, x1, y1; } mpld_rect;  /* nm, closed box */

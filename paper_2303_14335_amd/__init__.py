@@ -17,7 +17,7 @@ import numpy as np
 from . import _ffi
 from ._ffi import (MPLD_BUDGET_EXHAUSTED, MPLD_FEASIBLE, MPLD_FORCE_DEVICE,  # noqa: F401
                    MPLD_FORCE_GLOBAL, MPLD_FORCE_LDS, MPLD_FORCE_WAVE, MPLD_INFEASIBLE,
-                   MPLD_PLAIN, MPLD_SIMPLIFY, MPLD_TRACE_HASH)
+                   MPLD_PLAIN, MPLD_SIMPLIFY, MPLD_SPLIT_HEAVY, MPLD_TRACE_HASH)
 
 _lib = _ffi.load()
 
@@ -210,8 +210,9 @@ class Batch:
         _check(_lib.mpld_batch_create(ctx.handle, ctypes.byref(view), ctypes.byref(opt),
                                       ctypes.byref(self.handle)), "mpld_batch_create")
 
-    def solve(self, plain: bool = False, direct: bool = False) -> None:
-        flags = (MPLD_PLAIN if plain else 0) | (_ffi.MPLD_DIRECT if direct else 0)
+    def solve(self, plain: bool = False, direct: bool = False, split: bool = False) -> None:
+        flags = ((MPLD_PLAIN if plain else 0) | (_ffi.MPLD_DIRECT if direct else 0)
+                 | (MPLD_SPLIT_HEAVY if split else 0))
         _check(_lib.mpld_batch_solve(self.handle, flags), "mpld_batch_solve")
 
     def result(self) -> Result:
@@ -260,8 +261,9 @@ def mpld_batch_create(ctx: Context, g: Graph, k: int, budget: int,
     return Batch(ctx, g, k, budget, flags)
 
 
-def mpld_batch_solve(b: Batch, plain: bool = False, direct: bool = False) -> None:
-    b.solve(plain, direct)
+def mpld_batch_solve(b: Batch, plain: bool = False, direct: bool = False,
+                     split: bool = False) -> None:
+    b.solve(plain, direct, split)
 
 
 def mpld_batch_result(b: Batch) -> Result:

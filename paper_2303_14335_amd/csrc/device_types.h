@@ -34,6 +34,34 @@ struct DevRecord {
 };
 static_assert(sizeof(DevRecord) == 24, "record is 24 bytes");
 
+// Heavy-component engine (parallel subtree search).  A task is the subtree
+// of the node reached from a component's root by taking `depth` rows
+// (v | c << 8 each).
+struct SplitTask {
+  int32_t item;        // launch-ordered descriptor index of the component
+  int32_t depth;       // depth of the subtree root (rows on the path)
+  uint16_t rows[64];
+};
+static_assert(sizeof(SplitTask) == 136, "task is 136 bytes");
+// Result of exploring one task with a node cap.
+struct SplitResult {
+  int32_t status;      // MPLD_FEASIBLE, MPLD_INFEASIBLE (subtree exhausted) or -1 (cap hit)
+  int32_t nitems;      // split items written when the cap was hit
+  uint64_t nodes;      // nodes explored (the subtree's own count when finished)
+};
+static_assert(sizeof(SplitResult) == 16, "result is 16 bytes");
+// One item of the split of a capped task, in depth-first order: `seg` nodes
+// of the task's top levels are visited, then (kind 0) the subtree of the
+// node reached by rows[0..levels-1] below the task root, or (kind 1) the
+// task ends, or (kind 2) the last of the seg nodes was a solution.
+struct SplitItem {
+  uint32_t seg;
+  uint32_t kind;
+  uint16_t rows[4];
+};
+static_assert(sizeof(SplitItem) == 16, "item is 16 bytes");
+constexpr int kSplitMaxLevels = 4;
+
 // Device bytes of the resumable register-tier search state of one
 // component (serving): a 64-byte uniform head, then 64 lanes x (u32 open
 // colors, u32 frame, u64 undo bits).

@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <cstring>
+#include <unordered_map>
 
 namespace mpld {
 
@@ -151,7 +152,8 @@ void device_upload(mpld_context* ctx, const Image& im, DeviceBatch& db, const Tu
   db.host_queue.insert(db.host_queue.end(), im.q_big.begin(), im.q_big.end());
   db.host_queue.insert(db.host_queue.end(), im.q_dev.begin(), im.q_dev.end());
 
-  std::vector<DevDesc> ordered;
+  std::vector<DevDesc>& ordered = db.host_desc;
+  ordered.clear();
   ordered.reserve(db.host_queue.size());
   for (int32_t c : db.host_queue) ordered.push_back(im.desc[c]);
 
@@ -186,7 +188,7 @@ void device_upload(mpld_context* ctx, const Image& im, DeviceBatch& db, const Tu
   check_hip(hipStreamSynchronize(s), "upload");
 }
 
-static void enqueue_batched(DeviceBatch& db, bool trace, hipStream_t s) {
+static void enqueue_batched(DeviceBatch& db, bool trace, uint64_t cap, hipStream_t s) {
   const auto* desc = db.desc.as<DevDesc>();
   const auto* masks = db.masks.as<uint64_t>();
   const auto* adj = db.adj32.as<uint32_t>();
@@ -197,7 +199,7 @@ static void enqueue_batched(DeviceBatch& db, bool trace, hipStream_t s) {
   db.launches = 0;
   if (db.n_reg) {
     check_hip(launch_reg_batched(trace, db.k, db.grid_reg, db.tune.waves_per_block, desc, masks,
-                                 db.n_reg, cnt, recs, colors, s),
+                                 db.n_reg, cnt, recs, colors, cap, s),
               "register-tier launch");
     ++db.launches;
   }
@@ -223,10 +225,245 @@ static void enqueue_batched(DeviceBatch& db, bool trace, hipStream_t s) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Heavy-component engine.  Register-tier components still running after the
+// capped first pass are searched as ordered sequences of items: node counts
+// (visited in the top levels of a split) and subtree tasks.  Each round runs
+// every pending task with a node cap on its own wave; a task that finishes
+// reports its exact node count (and its solution), a capped task is split a
+// few levels further down into subtasks in search order.  Scanning a
+// component's items in order reproduces the sequential search: counts add
+// up until the first subtree holding a solution (FEASIBLE, nodes = the sum
+// through it) or to the end (INFEASIBLE); a sum passing the budget means the
+// sequential search was cut inside, and that component is re-run
+// sequentially to get its exact stopping point.
+
+namespace {
+
+constexpr uint64_t kHeavyFirstCap = 4096;   // nodes before a component counts as heavy
+constexpr uint64_t kHeavyRoundCap = 2048;   // nodes per task and round
+constexpr int32_t kHeavyMaxTasks = 16384;   // tasks per round
+
+struct HTask {
+  int32_t hc;            // heavy component index
+  int32_t depth;
+  uint16_t rows[64];
+  int32_t status = -2;   // -2 not run yet, -1 capped (being replaced), else final
+  uint64_t nodes = 0;
+  int8_t sol[64];
+};
+struct HItem {
+  int32_t task;          // -1: a node count
+  uint64_t count;
+};
+struct HComp {
+  int32_t item;          // launch-ordered descriptor index
+  std::vector<HItem> seq;
+  bool done = false, rerun = false;
+  DevRecord rec{};
+  std::vector<int8_t> colors;
+};
+
+int split_levels(int k) { return k <= 3 ? 4 : (k == 4 ? 3 : 2); }
+
+// Scans a component's items; true once its sequential result is known.
+bool resolve(HComp& hc, const DevDesc& d, const std::vector<HTask>& tasks) {
+  const uint64_t budget = (uint64_t)d.budget;
+  uint64_t acc = 0;
+  for (const HItem& it : hc.seq) {
+    if (it.task < 0) {
+      if (acc + it.count > budget) { hc.rerun = true; return true; }
+      acc += it.count;
+      continue;
+    }
+    const HTask& t = tasks[it.task];
+    if (t.status < 0) return false;
+    if (acc + t.nodes > budget) { hc.rerun = true; return true; }
+    acc += t.nodes;
+    if (t.status == MPLD_FEASIBLE) {
+      hc.rec.status = MPLD_FEASIBLE;
+      hc.rec.depth = d.n;
+      hc.rec.nodes = acc;
+      hc.rec.hash = 0xcbf29ce484222325ull;
+      hc.colors.assign(t.sol, t.sol + d.n);
+      return true;
+    }
+  }
+  hc.rec.status = MPLD_INFEASIBLE;
+  hc.rec.depth = 0;
+  hc.rec.nodes = acc;
+  hc.rec.hash = 0xcbf29ce484222325ull;
+  hc.colors.assign((size_t)d.n, -1);
+  return true;
+}
+
+}  // namespace
+
+static void heavy_engine(DeviceBatch& db) {
+  mpld_context* ctx = db.ctx;
+  hipStream_t s = ctx->stream;
+  db.sp_rounds = db.sp_tasks_run = db.sp_heavy = db.sp_reruns = 0;
+  // which register-tier components stopped at the first cap
+  std::vector<DevRecord> recs((size_t)db.num_comps);
+  check_hip(hipMemcpyAsync(recs.data(), db.recs.p, sizeof(DevRecord) * recs.size(),
+                           hipMemcpyDeviceToHost, s), "heavy: records");
+  check_hip(hipStreamSynchronize(s), "heavy: first pass");
+  std::vector<HComp> hcs;
+  std::vector<HTask> tasks;
+  for (int32_t i = 0; i < db.n_reg; ++i) {
+    if (recs[db.host_desc[i].comp].status >= 0) continue;
+    HComp hc;
+    hc.item = i;
+    HTask root;
+    root.hc = (int32_t)hcs.size();
+    root.depth = 0;
+    tasks.push_back(root);
+    hc.seq.push_back({(int32_t)tasks.size() - 1, 0});
+    hcs.push_back(std::move(hc));
+  }
+  if (hcs.empty()) return;
+  db.sp_heavy = (int64_t)hcs.size();
+  const int levels = split_levels(db.k);
+  int32_t max_items = 2;   // k^levels subtasks, an end item, a solution item
+  {
+    int64_t kp = 1;
+    for (int l = 0; l < levels; ++l) kp *= db.k;
+    max_items = (int32_t)kp + 2;
+  }
+  if (!db.sp_tasks.p) {
+    db.sp_tasks.alloc(ctx, sizeof(SplitTask) * kHeavyMaxTasks);
+    db.sp_results.alloc(ctx, sizeof(SplitResult) * kHeavyMaxTasks);
+    db.sp_items.alloc(ctx, sizeof(SplitItem) * (size_t)kHeavyMaxTasks * (size_t)max_items);
+    db.sp_sols.alloc(ctx, 64 * (size_t)kHeavyMaxTasks);
+  }
+  std::vector<SplitTask> up;
+  std::vector<SplitResult> res;
+  std::vector<SplitItem> items;
+  std::vector<int8_t> sols;
+  std::vector<int32_t> run;
+  for (;;) {
+    run.clear();
+    for (HComp& hc : hcs) {
+      if (hc.done) continue;
+      for (const HItem& it : hc.seq)
+        if (it.task >= 0 && tasks[it.task].status == -2 && (int32_t)run.size() < kHeavyMaxTasks)
+          run.push_back(it.task);
+    }
+    if (run.empty()) break;
+    const int32_t nt = (int32_t)run.size();
+    up.resize((size_t)nt);
+    for (int32_t i = 0; i < nt; ++i) {
+      const HTask& t = tasks[run[i]];
+      up[i].item = hcs[t.hc].item;
+      up[i].depth = t.depth;
+      std::memcpy(up[i].rows, t.rows, sizeof(up[i].rows));
+    }
+    check_hip(hipMemcpyAsync(db.sp_tasks.p, up.data(), sizeof(SplitTask) * nt, hipMemcpyHostToDevice, s),
+              "heavy: tasks");
+    const int grid = std::max(1, std::min((nt + 3) / 4, ctx->num_cus * ctx->reg_blocks_per_cu));
+    check_hip(launch_reg_split(db.k, grid, db.sp_tasks.as<SplitTask>(), nt, db.counters.as<int32_t>() + 6,
+                               db.desc.as<DevDesc>(), db.masks.as<uint64_t>(), kHeavyRoundCap,
+                               (uint32_t)levels, max_items, db.sp_results.as<SplitResult>(),
+                               db.sp_items.as<SplitItem>(), db.sp_sols.as<int8_t>(), s),
+              "heavy: split launch");
+    res.resize((size_t)nt);
+    items.resize((size_t)nt * (size_t)max_items);
+    sols.resize((size_t)nt * 64);
+    check_hip(hipMemcpyAsync(res.data(), db.sp_results.p, sizeof(SplitResult) * nt, hipMemcpyDeviceToHost, s),
+              "heavy: results");
+    check_hip(hipMemcpyAsync(items.data(), db.sp_items.p, sizeof(SplitItem) * items.size(),
+                             hipMemcpyDeviceToHost, s), "heavy: items");
+    check_hip(hipMemcpyAsync(sols.data(), db.sp_sols.p, sols.size(), hipMemcpyDeviceToHost, s),
+              "heavy: solutions");
+    check_hip(hipStreamSynchronize(s), "heavy: round");
+    ++db.sp_rounds;
+    db.sp_tasks_run += nt;
+    // finished tasks take their counts; capped ones are replaced by their split
+    std::vector<std::vector<HItem>> repl((size_t)nt);
+    std::vector<char> touched(hcs.size(), 0);
+    for (int32_t i = 0; i < nt; ++i) {
+      HTask& t = tasks[run[i]];
+      const SplitResult& r = res[i];
+      if (r.status == MPLD_FEASIBLE || r.status == MPLD_INFEASIBLE) {
+        t.status = r.status;
+        t.nodes = r.nodes;
+        if (r.status == MPLD_FEASIBLE) std::memcpy(t.sol, &sols[(size_t)i * 64], 64);
+        continue;
+      }
+      if (r.status != -1 || r.nitems < 1 || r.nitems > max_items)
+        fail(MPLD_E_INTERNAL, "heavy-component engine: bad task result");
+      t.status = -1;
+      touched[t.hc] = 1;
+      const SplitItem* its = &items[(size_t)i * (size_t)max_items];
+      for (int32_t j = 0; j < r.nitems; ++j) {
+        if (its[j].seg) repl[i].push_back({-1, its[j].seg});
+        if (its[j].kind == 1) break;
+        HTask ch;
+        ch.hc = t.hc;
+        if (its[j].kind == 0) {
+          ch.depth = t.depth + levels;
+          if (ch.depth > 64) fail(MPLD_E_INTERNAL, "heavy-component engine: task too deep");
+          std::memcpy(ch.rows, t.rows, sizeof(ch.rows));
+          for (int l = 0; l < levels; ++l) ch.rows[t.depth + l] = its[j].rows[l];
+        } else {   // kind 2: a solution among the split's top levels (already counted)
+          ch.depth = t.depth;
+          ch.status = MPLD_FEASIBLE;
+          ch.nodes = 0;
+          std::memcpy(ch.sol, &sols[(size_t)i * 64], 64);
+        }
+        tasks.push_back(ch);
+        repl[i].push_back({(int32_t)tasks.size() - 1, 0});
+        if (its[j].kind == 2) break;
+      }
+    }
+    // splice replacements into their components' sequences
+    std::unordered_map<int32_t, int32_t> where;
+    for (int32_t i = 0; i < nt; ++i)
+      if (tasks[run[i]].status == -1) where[run[i]] = i;
+    for (size_t h = 0; h < hcs.size(); ++h) {
+      HComp& hc = hcs[h];
+      if (hc.done) continue;
+      if (touched[h]) {
+        std::vector<HItem> seq;
+        seq.reserve(hc.seq.size() * 2);
+        for (const HItem& it : hc.seq) {
+          auto f = it.task >= 0 ? where.find(it.task) : where.end();
+          if (f == where.end()) {
+            seq.push_back(it);
+          } else {
+            for (const HItem& x : repl[f->second]) seq.push_back(x);
+          }
+        }
+        hc.seq.swap(seq);
+      }
+      hc.done = resolve(hc, db.host_desc[hc.item], tasks);
+    }
+  }
+  // write the results back where the first pass left its records
+  for (HComp& hc : hcs) {
+    const DevDesc& d = db.host_desc[hc.item];
+    if (hc.rerun) {
+      ++db.sp_reruns;
+      check_hip(launch_reg_single(false, db.k, db.desc.as<DevDesc>(), db.masks.as<uint64_t>(),
+                                  hc.item, db.recs.as<DevRecord>(), db.colors.as<int8_t>(), s),
+                "heavy: sequential re-run");
+      continue;
+    }
+    if (!hc.done) fail(MPLD_E_INTERNAL, "heavy-component engine ended unresolved");
+    check_hip(hipMemcpyAsync(db.recs.as<DevRecord>() + d.comp, &hc.rec, sizeof(DevRecord),
+                             hipMemcpyHostToDevice, s), "heavy: record");
+    check_hip(hipMemcpyAsync(db.colors.as<int8_t>() + d.out_off, hc.colors.data(), (size_t)d.n,
+                             hipMemcpyHostToDevice, s), "heavy: colors");
+  }
+  check_hip(hipStreamSynchronize(s), "heavy: write back");
+}
+
 void device_solve(DeviceBatch& db, uint32_t flags) {
   mpld_context* ctx = db.ctx;
   hipStream_t s = ctx->stream;
   const bool trace = flags & MPLD_TRACE_HASH;
+  const bool split = (flags & MPLD_SPLIT_HEAVY) && !trace && !(flags & MPLD_PLAIN) && db.n_reg > 0;
+  const uint64_t cap = split ? kHeavyFirstCap : ~0ull;
   db.timed = false;
   if (flags & MPLD_PLAIN) {
     // one launch per component, same search code
@@ -257,11 +494,12 @@ void device_solve(DeviceBatch& db, uint32_t flags) {
   } else if ((flags & MPLD_DIRECT) || !db.tune.use_graph || db.n_dev) {
     // direct launches (cooperative launches stay out of graphs)
     check_hip(hipEventRecord(ctx->ev[0], s), "event");
-    enqueue_batched(db, trace, s);
+    enqueue_batched(db, trace, cap, s);
+    if (split) heavy_engine(db);
     check_hip(hipEventRecord(ctx->ev[1], s), "event");
   } else {
     // capture the tiered launches once, replay the graph afterwards
-    const uint32_t key = trace ? 1u : 0u;
+    const uint32_t key = (trace ? 1u : 0u) | (split ? 2u : 0u);
     if (!db.graph || db.graph_flags != key) {
       if (db.graph) {
         check_hip(hipGraphExecDestroy(db.graph), "graph destroy");
@@ -270,7 +508,7 @@ void device_solve(DeviceBatch& db, uint32_t flags) {
       hipGraph_t g = nullptr;
       check_hip(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed), "begin capture");
       try {
-        enqueue_batched(db, trace, s);
+        enqueue_batched(db, trace, cap, s);
       } catch (...) {
         (void)hipStreamEndCapture(s, &g);
         if (g) (void)hipGraphDestroy(g);
@@ -284,6 +522,7 @@ void device_solve(DeviceBatch& db, uint32_t flags) {
     }
     check_hip(hipEventRecord(ctx->ev[0], s), "event");
     check_hip(hipGraphLaunch(db.graph, s), "graph launch");
+    if (split) heavy_engine(db);
     check_hip(hipEventRecord(ctx->ev[1], s), "event");
   }
   db.timed = true;

@@ -81,11 +81,14 @@ __device__ __forceinline__ void reg_init(RegState& s, int32_t n, int32_t k) {
 
 // Runs the search until it ends or `nodes` reaches stop_at (<= budget); a
 // stop short of the budget leaves status -1 and the state resumable at a
-// node boundary.  NB = bits of a row count (k < 2^NB).  Every lane of the
-// wave must call it.
+// node boundary.  With floor > 0 the search is confined to the subtree of
+// the node at depth `floor` (backtracking never pops below it; exhausting
+// the subtree reports MPLD_INFEASIBLE).  NB = bits of a row count
+// (k < 2^NB).  Every lane of the wave must call it.
 template <bool TRACE, int NB>
 __device__ __forceinline__ void reg_run(RegState& s, const uint64_t nb, const int32_t k,
-                                        const uint64_t budget, const uint64_t stop_at) {
+                                        const uint64_t budget, const uint64_t stop_at,
+                                        const uint32_t floor = 0) {
   const uint32_t lane = __lane_id();
   uint32_t rm = s.rm, st = s.st, depth = s.depth, row_in = s.row_in;
   uint64_t lost = s.lost, P = s.P, nodes = s.nodes, h = s.h;
@@ -124,7 +127,7 @@ __device__ __forceinline__ void reg_run(RegState& s, const uint64_t nb, const in
     } else {
       // dead end: undo rows and uncover columns until one has a next row
       uint32_t next = 0;
-      while (depth != 0) {
+      while (depth != floor) {
         --depth;
         const uint32_t vc = rdlane(st, depth);
         v = vc & 0xffu;
@@ -170,16 +173,19 @@ __device__ __forceinline__ void reg_finish(const RegState& s, int32_t n, int8_t*
   rec->hash = s.h;
 }
 
+// cap < budget stops the search after `cap` nodes (status -1 in the record:
+// the component is left to the heavy-component engine).
 template <bool TRACE, int NB>
 __device__ __forceinline__ void solve_reg(const int32_t n, const int32_t k, const uint64_t budget,
                                           const uint64_t* __restrict__ nbmask,
                                           int8_t* __restrict__ colors,
-                                          DevRecord* __restrict__ rec) {
+                                          DevRecord* __restrict__ rec,
+                                          const uint64_t cap = ~0ull) {
   const uint32_t lane = __lane_id();
   const uint64_t nb = lane < (uint32_t)n ? nbmask[lane] : 0ull;
   RegState s;
   reg_init(s, n, k);
-  reg_run<TRACE, NB>(s, nb, k, budget, budget);
+  reg_run<TRACE, NB>(s, nb, k, budget, cap < budget ? cap : budget);
   reg_finish(s, n, colors, rec);
 }
 
@@ -227,14 +233,15 @@ __device__ __forceinline__ void reg_load(RegState& s, const uint8_t* base) {
 template <bool TRACE, int NB>
 __global__ __launch_bounds__(256) void reg_batched_kernel(
     const DevDesc* __restrict__ descs, const uint64_t* __restrict__ masks, int32_t qlen,
-    int32_t* __restrict__ counter, DevRecord* __restrict__ recs, int8_t* __restrict__ colors) {
+    int32_t* __restrict__ counter, DevRecord* __restrict__ recs, int8_t* __restrict__ colors,
+    uint64_t cap) {
   const uint32_t wpb = blockDim.x >> 6;   // waves per workgroup
   const int32_t gw = (int32_t)(gridDim.x * wpb);
   int32_t item = (int32_t)uniform(blockIdx.x * wpb + (threadIdx.x >> 6));
   while (item < qlen) {
     const DevDesc d = descs[item];
     solve_reg<TRACE, NB>(d.n, d.k, (uint64_t)d.budget, masks + d.nbr_off, colors + d.out_off,
-                         recs + d.comp);
+                         recs + d.comp, cap);
     if (gw >= qlen) break;   // every item was handed out statically
     int32_t r = 0;
     if (__lane_id() == 0) r = atomicAdd(counter, 1);
@@ -301,6 +308,166 @@ __global__ __launch_bounds__(256) void reg_tick_kernel(
   }
 }
 
+// ---- heavy-component engine: subtree tasks --------------------------------
+
+// Rebuilds the search state at the end of a path of rows from the root:
+// cover each row's column and take the row, in order (the same applies the
+// sequential search made on the way down).
+__device__ __forceinline__ void reg_replay(RegState& s, const uint64_t nb, const int32_t k,
+                                           const uint16_t* __restrict__ rows, uint32_t d) {
+  const uint32_t lane = __lane_id();
+  for (uint32_t j = 0; j < d; ++j) {
+    const uint32_t vc = uniform(rows[j]);
+    const uint32_t v = vc & 0xffu, c = vc >> 8;
+    s.P &= ~(1ull << v);
+    const uint32_t hit = (uint32_t)(nb >> v) & (s.rm >> c) & 1u;
+    s.rm &= ~(hit << c);
+    s.lost |= (uint64_t)hit << j;
+    s.st = lane == j ? vc : s.st;
+    s.row_in = v * (uint32_t)k + c;
+  }
+  s.depth = d;
+}
+
+// Enumerates the top `levels` levels of the subtree rooted at depth d in
+// search order: counts their nodes, and emits a kind-0 item for every node
+// at depth d + levels (not counted here: its own task counts it), a kind-2
+// item when a solution is met (writing its colors) or a kind-1 item at the
+// end.  Returns the number of items.
+template <int NB>
+__device__ __forceinline__ int32_t reg_enumerate(RegState& s, const uint64_t nb, const int32_t k,
+                                                 const int32_t n, const uint32_t d,
+                                                 const uint32_t levels, SplitItem* __restrict__ out,
+                                                 int8_t* __restrict__ sol) {
+  const uint32_t lane = __lane_id();
+  const uint32_t limit = d + levels;
+  uint32_t rm = s.rm, st = s.st, depth = s.depth;
+  uint64_t lost = s.lost, P = s.P;
+  uint32_t seg = 0;
+  int32_t items = 0;
+  auto emit = [&](uint32_t kind) {
+    const uint32_t r0 = kind == 0 ? rdlane(st, d) : 0u;
+    const uint32_t r1 = kind == 0 && levels > 1 ? rdlane(st, d + 1) : 0u;
+    const uint32_t r2 = kind == 0 && levels > 2 ? rdlane(st, d + 2) : 0u;
+    const uint32_t r3 = kind == 0 && levels > 3 ? rdlane(st, d + 3) : 0u;
+    if (lane == ((uint32_t)items & 63u)) {   // one owner lane per item
+      SplitItem it;
+      it.seg = seg;
+      it.kind = kind;
+      it.rows[0] = (uint16_t)r0;
+      it.rows[1] = (uint16_t)r1;
+      it.rows[2] = (uint16_t)r2;
+      it.rows[3] = (uint16_t)r3;
+      out[items] = it;
+    }
+    ++items;
+    seg = 0;
+  };
+  for (;;) {
+    bool back;
+    uint32_t v = 0, c = 0;
+    if (depth == limit) {
+      emit(0);        // a subtask root: leave it to its own task
+      back = true;
+    } else {
+      ++seg;
+      if (P == 0) {   // a solution among the top levels
+        if (lane < depth && (st & 0xffu) < (uint32_t)n) sol[st & 0xffu] = (int8_t)(st >> 8);
+        emit(2);
+        break;
+      }
+      const uint32_t cnt = __popc(rm);
+      uint64_t cand = P;
+#pragma unroll
+      for (int j = NB - 1; j >= 0; --j) {
+        const uint64_t one = __ballot((cnt >> j) & 1u);
+        const uint64_t zero = cand & ~one;
+        cand = zero ? zero : cand;
+      }
+      v = (uint32_t)__ffsll((unsigned long long)cand) - 1u;
+      if (rdlane(cnt, v) != 0) {
+        P &= ~(1ull << v);
+        c = (uint32_t)__ffs(rdlane(rm, v)) - 1u;
+        back = false;
+      } else {
+        back = true;
+      }
+    }
+    if (back) {
+      uint32_t next = 0;
+      while (depth != d) {
+        --depth;
+        const uint32_t vc = rdlane(st, depth);
+        v = vc & 0xffu;
+        const uint32_t cp = vc >> 8;
+        rm |= (uint32_t)((lost >> depth) & 1ull) << cp;
+        lost &= ~(1ull << depth);
+        next = rdlane(rm, v) & (0xfffffffeu << cp);
+        if (next) break;
+        P |= 1ull << v;
+      }
+      if (!next) {
+        emit(1);
+        break;
+      }
+      c = (uint32_t)__ffs(next) - 1u;
+    }
+    const uint32_t hit = (uint32_t)(nb >> v) & (rm >> c) & 1u;
+    rm &= ~(hit << c);
+    lost |= (uint64_t)hit << depth;
+    st = lane == depth ? (v | (c << 8)) : st;
+    ++depth;
+  }
+  return items;
+}
+
+// One wave per task: explore the task's subtree up to `cap` nodes; if the
+// cap is hit, split the task `levels` levels down instead.
+template <int NB>
+__global__ __launch_bounds__(256) void reg_split_kernel(
+    const SplitTask* __restrict__ tasks, int32_t ntasks, int32_t* __restrict__ counter,
+    const DevDesc* __restrict__ descs, const uint64_t* __restrict__ masks, uint64_t cap,
+    uint32_t levels, int32_t max_items, SplitResult* __restrict__ results,
+    SplitItem* __restrict__ items, int8_t* __restrict__ sols) {
+  const uint32_t wpb = blockDim.x >> 6;
+  const int32_t gw = (int32_t)(gridDim.x * wpb);
+  int32_t t = (int32_t)uniform(blockIdx.x * wpb + (threadIdx.x >> 6));
+  const uint32_t lane = __lane_id();
+  while (t < ntasks) {
+    const SplitTask* task = tasks + t;
+    const int32_t it = (int32_t)uniform((uint32_t)task->item);
+    const uint32_t d = uniform((uint32_t)task->depth);
+    const DevDesc dd = descs[it];
+    const uint64_t nb = lane < (uint32_t)dd.n ? masks[dd.nbr_off + lane] : 0ull;
+    int8_t* sol = sols + (uint64_t)t * 64;
+    RegState s;
+    reg_init(s, dd.n, dd.k);
+    reg_replay(s, nb, dd.k, task->rows, d);
+    reg_run<false, NB>(s, nb, dd.k, ~0ull, cap, d);
+    int32_t nitems = 0;
+    if (s.status == MPLD_FEASIBLE) {
+      if (lane < s.depth && (s.st & 0xffu) < (uint32_t)dd.n) sol[s.st & 0xffu] = (int8_t)(s.st >> 8);
+    } else if (s.status < 0) {
+      RegState r;
+      reg_init(r, dd.n, dd.k);
+      reg_replay(r, nb, dd.k, task->rows, d);
+      nitems = reg_enumerate<NB>(r, nb, dd.k, dd.n, d, levels,
+                                 items + (uint64_t)t * (uint64_t)max_items, sol);
+    }
+    SplitResult res;
+    res.status = s.status;
+    res.nitems = nitems;
+    res.nodes = s.nodes;
+    results[t] = res;   // same value from every lane
+    if (gw >= ntasks) break;
+    int32_t r = 0;
+    if (__lane_id() == 0) r = atomicAdd(counter, 1);
+    r = (int32_t)uniform((uint32_t)r);
+    t = gw + r;
+    if (r == ntasks - 1) atomicExch(counter, 0);
+  }
+}
+
 __global__ void fill_i32_kernel(int32_t* __restrict__ p, int32_t count, int32_t value) {
   const int32_t i = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
   if (i < count) p[i] = value;
@@ -320,9 +487,9 @@ static int count_bits(int k) { return k < 4 ? 2 : (k < 8 ? 3 : 4); }
 template <bool TRACE, int NB>
 static void reg_batched_t(int grid, int wpb, const DevDesc* descs, const uint64_t* masks,
                           int32_t qlen, int32_t* counter, DevRecord* recs, int8_t* colors,
-                          hipStream_t s) {
+                          uint64_t cap, hipStream_t s) {
   hipLaunchKernelGGL((reg_batched_kernel<TRACE, NB>), dim3(grid), dim3(64 * wpb), 0, s, descs,
-                     masks, qlen, counter, recs, colors);
+                     masks, qlen, counter, recs, colors, cap);
 }
 
 template <bool TRACE, int NB>
@@ -334,16 +501,16 @@ static void reg_single_t(const DevDesc* descs, const uint64_t* masks, int32_t it
 
 hipError_t launch_reg_batched(bool trace, int k, int grid, int wpb, const DevDesc* descs,
                               const uint64_t* masks, int32_t qlen, int32_t* counter,
-                              DevRecord* recs, int8_t* colors, hipStream_t s) {
+                              DevRecord* recs, int8_t* colors, uint64_t cap, hipStream_t s) {
   if (qlen <= 0) return hipSuccess;
   if (wpb < 1 || wpb > 4) return hipErrorInvalidValue;
   switch (count_bits(k) + (trace ? 8 : 0)) {
-    case 2: reg_batched_t<false, 2>(grid, wpb, descs, masks, qlen, counter, recs, colors, s); break;
-    case 3: reg_batched_t<false, 3>(grid, wpb, descs, masks, qlen, counter, recs, colors, s); break;
-    case 4: reg_batched_t<false, 4>(grid, wpb, descs, masks, qlen, counter, recs, colors, s); break;
-    case 10: reg_batched_t<true, 2>(grid, wpb, descs, masks, qlen, counter, recs, colors, s); break;
-    case 11: reg_batched_t<true, 3>(grid, wpb, descs, masks, qlen, counter, recs, colors, s); break;
-    default: reg_batched_t<true, 4>(grid, wpb, descs, masks, qlen, counter, recs, colors, s); break;
+    case 2: reg_batched_t<false, 2>(grid, wpb, descs, masks, qlen, counter, recs, colors, cap, s); break;
+    case 3: reg_batched_t<false, 3>(grid, wpb, descs, masks, qlen, counter, recs, colors, cap, s); break;
+    case 4: reg_batched_t<false, 4>(grid, wpb, descs, masks, qlen, counter, recs, colors, cap, s); break;
+    case 10: reg_batched_t<true, 2>(grid, wpb, descs, masks, qlen, counter, recs, colors, cap, s); break;
+    case 11: reg_batched_t<true, 3>(grid, wpb, descs, masks, qlen, counter, recs, colors, cap, s); break;
+    default: reg_batched_t<true, 4>(grid, wpb, descs, masks, qlen, counter, recs, colors, cap, s); break;
   }
   return hipGetLastError();
 }
@@ -382,6 +549,29 @@ hipError_t launch_reg_tick(bool trace, int k, int grid, const int32_t* list, int
     case 10: reg_tick_t<true, 2>(grid, list, len, counter, slot_desc, slot_state, slot_rec, arena64, arena8, slice, tick_out, s); break;
     case 11: reg_tick_t<true, 3>(grid, list, len, counter, slot_desc, slot_state, slot_rec, arena64, arena8, slice, tick_out, s); break;
     default: reg_tick_t<true, 4>(grid, list, len, counter, slot_desc, slot_state, slot_rec, arena64, arena8, slice, tick_out, s); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_reg_split(int k, int grid, const SplitTask* tasks, int32_t ntasks,
+                            int32_t* counter, const DevDesc* descs, const uint64_t* masks,
+                            uint64_t cap, uint32_t levels, int32_t max_items,
+                            SplitResult* results, SplitItem* items, int8_t* sols, hipStream_t s) {
+  if (ntasks <= 0) return hipSuccess;
+  if (levels < 1 || levels > (uint32_t)kSplitMaxLevels) return hipErrorInvalidValue;
+  switch (count_bits(k)) {
+    case 2:
+      hipLaunchKernelGGL((reg_split_kernel<2>), dim3(grid), dim3(256), 0, s, tasks, ntasks, counter,
+                         descs, masks, cap, levels, max_items, results, items, sols);
+      break;
+    case 3:
+      hipLaunchKernelGGL((reg_split_kernel<3>), dim3(grid), dim3(256), 0, s, tasks, ntasks, counter,
+                         descs, masks, cap, levels, max_items, results, items, sols);
+      break;
+    default:
+      hipLaunchKernelGGL((reg_split_kernel<4>), dim3(grid), dim3(256), 0, s, tasks, ntasks, counter,
+                         descs, masks, cap, levels, max_items, results, items, sols);
+      break;
   }
   return hipGetLastError();
 }

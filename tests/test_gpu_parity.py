@@ -243,3 +243,43 @@ def test_autotune_keeps_results_and_caches(ctx, tmp_path):
     assert t2["from_cache"] == 1
     assert (t2["waves_per_block"], t2["order"], t2["use_graph"]) == (
         t["waves_per_block"], t["order"], t["use_graph"])
+
+
+SPLIT = 1 << 8
+
+
+def test_split_heavy_config2_matches_oracle(ctx):
+    import paper_2303_14335_amd as mp
+    w, rects = graph_of(2)
+    say("config 2 with the heavy-component engine")
+    g = mp.mpld_build_graph(rects, w.dmin_nm, w.split_len_nm)
+    ref = oracle.decompose(oracle.Graph(g.num_nodes, g.ce, g.se), w.k, w.budget)
+    got = mp.mpld_decompose(ctx, g, w.k, w.budget, SIMPLIFY | SPLIT)
+    for f in ("size", "status", "nodes", "depth_at_stop", "stitches", "first_node"):
+        assert np.array_equal(got.components[f], ref.comps[f]), f
+    assert np.array_equal(got.colors, ref.colors)
+    assert got.components["nodes"].max() > 100000   # a heavy component was split
+
+
+def heavy_graphs(seed, count, n_lo, n_hi, deg):
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(count):
+        n = int(rng.integers(n_lo, n_hi + 1))
+        out.append((n, random_graph(rng, n, deg / n)))
+    return out
+
+
+@pytest.mark.parametrize("k,deg,budget", [(3, 4.6, 300000), (4, 8.4, 300000), (3, 4.6, 20000)])
+def test_split_heavy_random_components(ctx, k, deg, budget):
+    import paper_2303_14335_amd as mp
+    comps = heavy_graphs(k * 100 + int(deg), 40, 40, 64, deg)
+    say("heavy random components k", k, "budget", budget)
+    # the batch path: components through mpld_decompose with simplification off
+    for n, e in comps:
+        g = mp.Graph(n, np.asarray(e, np.int32).reshape(-1, 2), np.zeros((0, 2), np.int32))
+        got = mp.mpld_decompose(ctx, g, k, budget, SPLIT)
+        ref = oracle.decompose(oracle.Graph(n, g.ce, g.se), k, budget, simplify=False)
+        for f in ("status", "nodes", "depth_at_stop"):
+            assert np.array_equal(got.components[f], ref.comps[f]), (f, n, k, budget)
+        assert np.array_equal(got.colors, ref.colors)
