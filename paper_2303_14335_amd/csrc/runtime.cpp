@@ -382,17 +382,19 @@ static void heavy_engine(DeviceBatch& db) {
     std::vector<std::vector<HItem>> repl((size_t)nt);
     std::vector<char> touched(hcs.size(), 0);
     for (int32_t i = 0; i < nt; ++i) {
-      HTask& t = tasks[run[i]];
       const SplitResult& r = res[i];
       if (r.status == MPLD_FEASIBLE || r.status == MPLD_INFEASIBLE) {
-        t.status = r.status;
-        t.nodes = r.nodes;
-        if (r.status == MPLD_FEASIBLE) std::memcpy(t.sol, &sols[(size_t)i * 64], 64);
+        HTask& done = tasks[run[i]];
+        done.status = r.status;
+        done.nodes = r.nodes;
+        if (r.status == MPLD_FEASIBLE) std::memcpy(done.sol, &sols[(size_t)i * 64], 64);
         continue;
       }
       if (r.status != -1 || r.nitems < 1 || r.nitems > max_items)
         fail(MPLD_E_INTERNAL, "heavy-component engine: bad task result");
-      t.status = -1;
+      tasks[run[i]].status = -1;
+      // a copy: pushing the children below may move `tasks`
+      const HTask t = tasks[run[i]];
       touched[t.hc] = 1;
       const SplitItem* its = &items[(size_t)i * (size_t)max_items];
       for (int32_t j = 0; j < r.nitems; ++j) {

@@ -83,16 +83,22 @@ def test_stitched_k4_heavy_components_sliced(ctx):
 
 def test_admission_waits_for_device_bytes(ctx):
     import paper_2303_14335_amd as mp
-    reqs = requests(16, seed=5, n_max=3000)
+    # sixteen 2000-rectangle windows at the small workload's density: each
+    # packed image is about 2 KB, so a 6 KB arena holds only a few of them,
+    # and one-node slices keep every admitted request resident for many ticks
+    reqs = []
+    for i in range(16):
+        rects, _ = workload.generate(2000, 7746, 1000 + i)
+        reqs.append(dict(rects=rects, dmin=80, split=0, k=3))
     say("serve tiny arena")
-    srv = mp.Server(ctx, arena_bytes=96 << 10, max_components=2048, slice_nodes=3)
+    srv = mp.Server(ctx, arena_bytes=6 << 10, max_components=2048, slice_nodes=1)
     tickets = [srv.submit_layout(r["rects"], r["dmin"], r["split"], r["k"], 10**6) for r in reqs]
     results = [srv.wait(t, 60_000_000) for t in tickets]
     st = srv.stats()
     srv.close()
     assert st["completed"] == len(reqs)
     assert st["admission_waits"] > 0
-    assert st["peak_bytes"] <= 96 << 10
+    assert st["peak_bytes"] <= 6 << 10
     for r, got in zip(reqs, results):
         same(got, alone(ctx, r, 10**6, SIMPLIFY))
 
