@@ -36,9 +36,11 @@ def log(*a):
 
 
 def kernel_source_hash() -> str:
+    """Hash of the search kernels' sources and of the build script (flags)."""
     h = hashlib.sha256()
-    for f in ("search_reg.hip", "search_lds.hip"):
-        with open(os.path.join(ROOT, "paper_2303_14335_amd", "csrc", f), "rb") as fh:
+    pkg = os.path.join(ROOT, "paper_2303_14335_amd")
+    for f in ("csrc/search_reg.hip", "csrc/search_lds.hip", "csrc/device_types.h", "build.py"):
+        with open(os.path.join(pkg, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
@@ -202,14 +204,14 @@ def main() -> int:
     direct = args.launch == "direct"
     split = args.split
     for _ in range(args.warmup):
-        b.solve(direct=direct, split=split)
+        b.solve(direct=direct, split=split, timed=False)
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     ts = time.perf_counter()
     e0.record(stream)
     for _ in range(args.steps):
-        b.solve(direct=direct, split=split)
+        b.solve(direct=direct, split=split, timed=False)
     e1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - ts
@@ -221,7 +223,7 @@ def main() -> int:
     # ---- the dominant kernel alone: direct launches, HIP events around it
     kms = []
     for _ in range(args.kernel_reps):
-        b.solve(direct=True)
+        b.solve(direct=True, split=split)
         torch.cuda.synchronize()
         kms.append(b.info()["last_search_ms"])
     kernel_ms = float(np.mean(kms))

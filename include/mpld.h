@@ -92,7 +92,7 @@ enum {
                                   time over every CU, columns split across
                                   workgroups, a device-wide min-count reduction
                                   per search node                              */
-  MPLD_SPLIT_HEAVY = 1u << 8   /* register-tier components still searching after
+  MPLD_SPLIT_HEAVY = 1u << 8,  /* register-tier components still searching after
                                   a first capped pass are searched in parallel
                                   subtrees by many wavefronts; the sequential
                                   status, node count, depth and colors are
@@ -100,6 +100,10 @@ enum {
                                   in search order (not with MPLD_TRACE_HASH; a
                                   component cut by its budget is re-run
                                   sequentially).  Makes mpld_batch_solve wait. */
+  MPLD_UNTIMED = 1u << 9       /* mpld_batch_solve: record no HIP events around
+                                  the search (last_search_ms keeps the value of
+                                  the last timed solve); for callers timing
+                                  many back-to-back solves themselves */
 };
 
 typedef struct { int32_t x0, y0, x1, y1; } mpld_rect;  /* nm, closed box */

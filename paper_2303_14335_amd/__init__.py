@@ -210,9 +210,10 @@ class Batch:
         _check(_lib.mpld_batch_create(ctx.handle, ctypes.byref(view), ctypes.byref(opt),
                                       ctypes.byref(self.handle)), "mpld_batch_create")
 
-    def solve(self, plain: bool = False, direct: bool = False, split: bool = False) -> None:
+    def solve(self, plain: bool = False, direct: bool = False, split: bool = False,
+              timed: bool = True) -> None:
         flags = ((MPLD_PLAIN if plain else 0) | (_ffi.MPLD_DIRECT if direct else 0)
-                 | (MPLD_SPLIT_HEAVY if split else 0))
+                 | (MPLD_SPLIT_HEAVY if split else 0) | (0 if timed else _ffi.MPLD_UNTIMED))
         _check(_lib.mpld_batch_solve(self.handle, flags), "mpld_batch_solve")
 
     def result(self) -> Result:
@@ -262,8 +263,8 @@ def mpld_batch_create(ctx: Context, g: Graph, k: int, budget: int,
 
 
 def mpld_batch_solve(b: Batch, plain: bool = False, direct: bool = False,
-                     split: bool = False) -> None:
-    b.solve(plain, direct, split)
+                     split: bool = False, timed: bool = True) -> None:
+    b.solve(plain, direct, split, timed)
 
 
 def mpld_batch_result(b: Batch) -> Result:

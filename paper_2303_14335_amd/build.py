@@ -22,9 +22,15 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
           "-packed-fp32-ops", "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 
 
+# Per-source flags.  The register tier's search loop branches only on
+# wave-uniform values; leaving those regions unstructurized keeps the
+# branches as scalar branches instead of exec-mask flow blocks.
+EXTRA = {"search_reg.hip": ["-mllvm", "-structurizecfg-skip-uniform-regions"]}
+
+
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC] + COMMON
+    cmd = [HIPCC] + COMMON + EXTRA.get(src, [])
     if src.endswith(".hip"):
         cmd += ["-x", "hip"]
     cmd += ["-c", os.path.join(CSRC, src), "-o", obj]

@@ -201,7 +201,7 @@ int32_t mpld_batch_solve(mpld_batch* b, uint32_t flags) {
     if (!b) fail(MPLD_E_INVALID, "batch is NULL");
     use_device(b->ctx);
     const uint32_t how = MPLD_PLAIN | MPLD_DIRECT;
-    device_solve(b->db, (b->opt.flags & ~how) | (flags & (how | MPLD_SPLIT_HEAVY)));
+    device_solve(b->db, (b->opt.flags & ~how) | (flags & (how | MPLD_SPLIT_HEAVY | MPLD_UNTIMED)));
     b->solved = true;
   });
 }

@@ -63,8 +63,8 @@ static_assert(sizeof(SplitItem) == 16, "item is 16 bytes");
 constexpr int kSplitMaxLevels = 4;
 
 // Device bytes of the resumable register-tier search state of one
-// component (serving): a 64-byte uniform head, then 64 lanes x (u32 open
-// colors, u32 frame, u64 undo bits).
-constexpr uint64_t kRegStateBytes = 64 + 64 * (4 + 4 + 8);
+// component (serving): a 128-byte uniform head (counters, then up to eight
+// 64-bit color planes), then 64 lanes x (u32 frame, u32 + u32 undo set).
+constexpr uint64_t kRegStateBytes = 128 + 64 * (4 + 4 + 4);
 
 }  // namespace mpld

@@ -466,6 +466,7 @@ void device_solve(DeviceBatch& db, uint32_t flags) {
   const bool trace = flags & MPLD_TRACE_HASH;
   const bool split = (flags & MPLD_SPLIT_HEAVY) && !trace && !(flags & MPLD_PLAIN) && db.n_reg > 0;
   const uint64_t cap = split ? kHeavyFirstCap : ~0ull;
+  const bool timed = !(flags & MPLD_UNTIMED) || (flags & MPLD_PLAIN);
   db.timed = false;
   if (flags & MPLD_PLAIN) {
     // one launch per component, same search code
@@ -495,10 +496,10 @@ void device_solve(DeviceBatch& db, uint32_t flags) {
     check_hip(hipEventRecord(ctx->ev[1], s), "event");
   } else if ((flags & MPLD_DIRECT) || !db.tune.use_graph || db.n_dev) {
     // direct launches (cooperative launches stay out of graphs)
-    check_hip(hipEventRecord(ctx->ev[0], s), "event");
+    if (timed) check_hip(hipEventRecord(ctx->ev[0], s), "event");
     enqueue_batched(db, trace, cap, s);
     if (split) heavy_engine(db);
-    check_hip(hipEventRecord(ctx->ev[1], s), "event");
+    if (timed) check_hip(hipEventRecord(ctx->ev[1], s), "event");
   } else {
     // capture the tiered launches once, replay the graph afterwards
     const uint32_t key = (trace ? 1u : 0u) | (split ? 2u : 0u);
@@ -522,12 +523,12 @@ void device_solve(DeviceBatch& db, uint32_t flags) {
       check_hip(e, "graph instantiate");
       db.graph_flags = key;
     }
-    check_hip(hipEventRecord(ctx->ev[0], s), "event");
+    if (timed) check_hip(hipEventRecord(ctx->ev[0], s), "event");
     check_hip(hipGraphLaunch(db.graph, s), "graph launch");
     if (split) heavy_engine(db);
-    check_hip(hipEventRecord(ctx->ev[1], s), "event");
+    if (timed) check_hip(hipEventRecord(ctx->ev[1], s), "event");
   }
-  db.timed = true;
+  db.timed = timed;
 }
 
 bool device_time(DeviceBatch& db) {

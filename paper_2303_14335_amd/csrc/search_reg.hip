@@ -5,18 +5,28 @@
 // primary column per node, a secondary column per (conflict edge, color).
 // Row (v, c) stays in the matrix while v is uncovered and no conflict
 // neighbour of v has taken row (u, c); so the rows of primary column v are
-// the colors still open to v, and the dancing-links state reduces to
-//   rm[v]  - a k-bit mask of v's open colors, one lane per node (VGPR);
-//   P      - the 64-bit set of uncovered primary columns (SGPR pair).
-// Column choice (Algorithm 1): per lane count = popcount(rm); a wave ballot
-// of count == t, masked with P, for t = 0, 1, ... gives the columns of the
-// smallest count, and its lowest set bit is the lowest local index.
-// Cover of row (v, c) (Eq. 2 "cover"): lanes u with v in N(u) and color c
-// open clear bit c; the ballot of those lanes is the undo record.  Uncover
-// (Eq. 2 "uncover") ORs the recorded lanes back.  The recursion of
-// Algorithm 1 becomes an explicit stack held in three VGPRs, lane d holding
-// frame d: (v | c << 8, removed-mask low, removed-mask high).
+// the colors still open to v.  With at most 64 nodes the whole
+// dancing-links state is a handful of 64-bit words, kept wave-uniform in
+// scalar registers:
+//   O[c] - color plane c: the nodes for which color c is still open;
+//   P    - the uncovered primary columns.
+// Column choice (Algorithm 1): the row count of column v is the number of
+// planes holding v.  A column with no rows shows as an uncovered node
+// missing from every plane (a dead end, chosen first).  Otherwise a
+// bit-sliced adder over the planes gives the counts of all 64 columns at
+// once as count-bit planes; narrowing P from the most significant count bit
+// down keeps the columns of smallest count, and the lowest set bit is the
+// lowest local index.
+// Cover of row (v, c) (Eq. 2 "cover"): v's conflict neighbours lose color
+// c, lost = O[c] & N(v) and O[c] &= ~N(v); uncover ORs lost back.  Taking a
+// row also covers column v (clears it from P).
+// The recursion of Algorithm 1 is an explicit stack in three VGPRs, lane d
+// holding frame d: v | c << 8 and the 64-bit `lost` set.  The
+// neighbour sets N(v) sit one per lane (lane v) and are read with
+// v_readlane when v is chosen.
 #include <hip/hip_runtime.h>
+
+#include <type_traits>
 
 #include "device_types.h"
 #include "mpld.h"
@@ -47,120 +57,240 @@ __device__ __forceinline__ uint64_t trace_node(uint64_t h, uint32_t depth, uint3
 __device__ __forceinline__ uint32_t rdlane(uint32_t x, uint32_t lane) {
   return (uint32_t)__builtin_amdgcn_readlane((int)x, (int)lane);
 }
+__device__ __forceinline__ uint64_t rdlane64(uint32_t lo, uint32_t hi, uint32_t lane) {
+  return (uint64_t)rdlane(lo, lane) | ((uint64_t)rdlane(hi, lane) << 32);
+}
+// v_writelane: `old` with lane `lane` replaced by the uniform `val`.
+__device__ int mpld_writelane(int val, int lane, int old) __asm("llvm.amdgcn.writelane.i32");
+__device__ __forceinline__ uint32_t wrlane(uint32_t old, uint32_t lane, uint32_t val) {
+  return (uint32_t)mpld_writelane((int)val, (int)lane, (int)old);
+}
+// Index of the lowest set bit of a nonzero 64-bit mask.
+__device__ __forceinline__ uint32_t low_bit(uint64_t x) { return (uint32_t)__builtin_ctzll(x); }
 __device__ __forceinline__ uint32_t uniform(uint32_t x) {
   return (uint32_t)__builtin_amdgcn_readfirstlane((int)x);
 }
+__device__ __forceinline__ uint64_t uniform64(uint64_t x) {
+  return (uint64_t)uniform((uint32_t)x) | ((uint64_t)uniform((uint32_t)(x >> 32)) << 32);
+}
 
-// Search state of one component.  Per lane (VGPRs):
-//   rm    open colors of the lane's node (k-bit row mask)
-//   lost  bit d set iff this lane's node lost a color when the row at depth
-//         d was taken (the undo record)
-//   st    lane d holds frame d: v | c << 8
-// Wave-uniform (SGPRs): P (uncovered columns), depth, nodes, hash, entering
-// row, status (-1 while the search runs or is paused).
+constexpr int bit_width(int x) { return x == 0 ? 0 : 1 + bit_width(x >> 1); }
+
+// Search state of one component, K color planes (K >= k; planes k..K-1 stay
+// empty).  Wave-uniform: the planes, P, counters, depth, hash, entering row,
+// status (-1 while the search runs or is paused).  Per lane: frame `fr` and
+// undo set `ll`/`lh` of depth = lane.
+template <int K>
+using Planes = uint64_t __attribute__((ext_vector_type(K)));
+
+template <int K>
 struct RegState {
-  uint32_t rm, st;
-  uint64_t lost;
+  Planes<K> O;
   uint64_t P, nodes, h;
   uint32_t depth, row_in;
   int32_t status;
+  uint32_t fr, ll, lh;
 };
 
-__device__ __forceinline__ void reg_init(RegState& s, int32_t n, int32_t k) {
-  const uint32_t lane = __lane_id();
-  s.rm = lane < (uint32_t)n ? ((1u << k) - 1u) : 0u;
-  s.st = 0;
-  s.lost = 0;
-  s.P = n >= 64 ? ~0ull : ((1ull << n) - 1ull);
+template <int K>
+__device__ __forceinline__ void reg_init(RegState<K>& s, int32_t n, int32_t k) {
+  const uint64_t all = n >= 64 ? ~0ull : ((1ull << n) - 1ull);
+#pragma unroll
+  for (int c = 0; c < K; ++c) s.O[c] = c < k ? all : 0ull;
+  s.P = all;
   s.nodes = 0;
   s.h = kFnvOffset;
   s.depth = 0;
   s.row_in = kNone;
   s.status = -1;
+  s.fr = 0;
+  s.ll = 0;
+  s.lh = 0;
+}
+
+// c == j ? a : b on uniform 64-bit words (one compare, one 64-bit select).
+__device__ __forceinline__ uint64_t sel_eq(uint32_t c, int j, uint64_t a, uint64_t b) {
+  uint64_t r;
+  asm("s_cmp_eq_u32 %1, %2\n\ts_cselect_b64 %0, %3, %4" : "=s"(r) : "s"(c), "i"(j), "s"(a), "s"(b) : "scc");
+  return r;
+}
+
+// Plane c (c < K), as a select chain: no indexed register access.
+template <int K>
+__device__ __forceinline__ uint64_t plane(const Planes<K>& O, uint32_t c) {
+  uint64_t r = O[0];
+#pragma unroll
+  for (int j = 1; j < K; ++j) r = sel_eq(c, j, O[j], r);
+  return r;
+}
+
+// Plane c := x.
+template <int K>
+__device__ __forceinline__ void set_plane(Planes<K>& O, uint32_t c, uint64_t x) {
+#pragma unroll
+  for (int j = 0; j < K; ++j) O[j] = sel_eq(c, j, x, O[j]);
+}
+
+// Open colors of node v (the rows of column v), bit c for color c.
+template <int K>
+__device__ __forceinline__ uint32_t rows_of(const Planes<K>& O, uint32_t v) {
+  uint32_t R = 0;
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    uint32_t b;
+    asm("s_bitcmp1_b64 %1, %2\n\ts_cselect_b32 %0, %3, 0" : "=s"(b) : "s"(O[j]), "s"(v), "i"(1 << j) : "scc");
+    R |= b;
+  }
+  return R;
+}
+
+// Keeps the columns of `cand` whose count bit `bits` is clear, unless none
+// is: one s_andn2 (which sets SCC to "result nonzero") and one 64-bit select.
+__device__ __forceinline__ uint64_t narrow(uint64_t cand, uint64_t bits) {
+  uint64_t r;
+  asm("s_andn2_b64 %0, %1, %2\n\ts_cselect_b64 %0, %0, %1" : "=&s"(r) : "s"(cand), "s"(bits) : "scc");
+  return r;
+}
+
+// Count-bit planes of the row counts: cnt[b] holds bit b of every column's
+// count (the number of color planes holding it).
+template <int K>
+__device__ __forceinline__ void count_planes(const Planes<K>& O, uint64_t (&cnt)[bit_width(K)]) {
+  constexpr int NB = bit_width(K);
+#pragma unroll
+  for (int b = 0; b < NB; ++b) cnt[b] = 0;
+#pragma unroll
+  for (int c = 0; c < K; ++c) {
+    // add plane c; afterwards a count is at most c + 1, so only
+    // bit_width(c + 1) bits can change
+    uint64_t carry = O[c];
+#pragma unroll
+    for (int b = 0; b < bit_width(c + 1); ++b) {
+      const uint64_t t = cnt[b] & carry;
+      cnt[b] ^= carry;
+      carry = t;
+    }
+  }
+}
+
+// Uncovered columns of the smallest row count (all of P has count >= 1).
+template <int K>
+__device__ __forceinline__ uint64_t min_count_columns(const Planes<K>& O, const uint64_t P) {
+  constexpr int NB = bit_width(K);
+  uint64_t cnt[NB];
+  count_planes(O, cnt);
+  uint64_t cand = P;
+#pragma unroll
+  for (int b = NB - 1; b >= 0; --b) cand = narrow(cand, cnt[b]);
+  return cand;
+}
+
+// Lowest open color of node v (v has at least one): s_bitcmp1 tests bit v
+// of a plane into SCC, s_cselect keeps the lower color.
+template <int K>
+__device__ __forceinline__ uint32_t first_color(const Planes<K>& O, const uint32_t v) {
+  uint32_t c = K - 1;
+#pragma unroll
+  for (int j = K - 2; j >= 0; --j)
+    asm("s_bitcmp1_b64 %1, %2\n\ts_cselect_b32 %0, %3, %0" : "+s"(c) : "s"(O[j]), "s"(v), "i"(j) : "scc");
+  return c;
+}
+
+// Takes row (v, c) at the current depth: v's neighbours lose color c; the
+// frame and the undo set go to lane `depth`.
+template <int K>
+__device__ __forceinline__ void take_row(RegState<K>& s, const uint64_t nbv, const uint32_t v,
+                                         const uint32_t c) {
+  const uint64_t oc = plane(s.O, c);
+  const uint64_t lost = oc & nbv;
+  set_plane(s.O, c, oc & ~nbv);
+  s.fr = wrlane(s.fr, s.depth, v | (c << 8));
+  s.ll = wrlane(s.ll, s.depth, (uint32_t)lost);
+  s.lh = wrlane(s.lh, s.depth, (uint32_t)(lost >> 32));
+  ++s.depth;
+}
+
+// Pops frames down to `floor` until one has a next row, restoring the
+// planes and uncovering columns on the way.  Returns the next color (v set
+// to that frame's column, depth to its depth), or kNone when the subtree
+// is exhausted.  After a frame's undo set is restored the planes are as
+// they were when its column was chosen, so the untried rows of that column
+// are its open colors above the row taken.
+template <int K>
+__device__ __forceinline__ uint32_t backtrack(RegState<K>& s, uint32_t& v, const uint32_t floor) {
+  while (s.depth != floor) {
+    --s.depth;
+    const uint32_t f = rdlane(s.fr, s.depth);
+    const uint64_t lost = rdlane64(s.ll, s.lh, s.depth);
+    v = f & 0xffu;
+    const uint32_t cp = f >> 8;
+    set_plane(s.O, cp, plane(s.O, cp) | lost);
+    const uint32_t next = rows_of(s.O, v) & (0xfffffffeu << cp);
+    if (next) return (uint32_t)__builtin_ctz(next);
+    s.P |= 1ull << v;
+  }
+  return kNone;
 }
 
 // Runs the search until it ends or `nodes` reaches stop_at (<= budget); a
 // stop short of the budget leaves status -1 and the state resumable at a
 // node boundary.  With floor > 0 the search is confined to the subtree of
 // the node at depth `floor` (backtracking never pops below it; exhausting
-// the subtree reports MPLD_INFEASIBLE).  NB = bits of a row count
-// (k < 2^NB).  Every lane of the wave must call it.
-template <bool TRACE, int NB>
-__device__ __forceinline__ void reg_run(RegState& s, const uint64_t nb, const int32_t k,
-                                        const uint64_t budget, const uint64_t stop_at,
-                                        const uint32_t floor = 0) {
-  const uint32_t lane = __lane_id();
-  uint32_t rm = s.rm, st = s.st, depth = s.depth, row_in = s.row_in;
-  uint64_t lost = s.lost, P = s.P, nodes = s.nodes, h = s.h;
+// the subtree reports MPLD_INFEASIBLE).  nb_lo/nb_hi: lane v holds N(v).
+// Every lane of the wave must call it.
+template <bool TRACE, int K>
+__device__ __forceinline__ void reg_run(RegState<K>& s, const uint32_t nb_lo, const uint32_t nb_hi,
+                                        const int32_t k, const uint64_t budget,
+                                        const uint64_t stop_at, const uint32_t floor = 0) {
   int32_t status = -1;
   for (;;) {
     // ---- one search node
-    if (nodes == stop_at) {
-      if (nodes == budget) status = MPLD_BUDGET_EXHAUSTED;
+    if (s.nodes == stop_at) {
+      if (s.nodes == budget) status = MPLD_BUDGET_EXHAUSTED;
       break;
     }
-    ++nodes;
-    if (P == 0) {
-      if (TRACE) h = trace_node(h, depth, row_in, kNone, 0);
+    ++s.nodes;
+    if (s.P == 0) {
+      if (TRACE) s.h = trace_node(s.h, s.depth, s.row_in, kNone, 0);
       status = MPLD_FEASIBLE;
       break;
     }
-    // column choice without branches: narrow the open columns to those of
-    // the smallest row count one count bit at a time (most significant
-    // first); the lowest survivor is the lowest index of that count
-    const uint32_t cnt = __popc(rm);
-    uint64_t cand = P;
+    uint64_t any = s.O[0];
 #pragma unroll
-    for (int j = NB - 1; j >= 0; --j) {
-      const uint64_t one = __ballot((cnt >> j) & 1u);
-      const uint64_t zero = cand & ~one;
-      cand = zero ? zero : cand;
-    }
-    uint32_t v = (uint32_t)__ffsll((unsigned long long)cand) - 1u;
-    const uint32_t size = rdlane(cnt, v);
-    if (TRACE) h = trace_node(h, depth, row_in, v, size);
-    uint32_t c;
-    if (size != 0) {
-      // cover column v, take its first open row
-      P &= ~(1ull << v);
-      c = (uint32_t)__ffs(rdlane(rm, v)) - 1u;
+    for (int j = 1; j < K; ++j) any |= s.O[j];
+    const uint64_t zero = s.P & ~any;
+    uint32_t v, c;
+    if (__builtin_expect(zero == 0, 1)) {
+      // every uncovered column has rows: cover the one of fewest rows and
+      // take its first row
+      v = low_bit(min_count_columns(s.O, s.P));
+      if (TRACE) s.h = trace_node(s.h, s.depth, s.row_in, v, (uint32_t)__popc(rows_of(s.O, v)));
+      c = first_color(s.O, v);
+      asm("s_bitset0_b64 %0, %1" : "+s"(s.P) : "s"(v));   // cover column v
     } else {
-      // dead end: undo rows and uncover columns until one has a next row
-      uint32_t next = 0;
-      while (depth != floor) {
-        --depth;
-        const uint32_t vc = rdlane(st, depth);
-        v = vc & 0xffu;
-        const uint32_t cp = vc >> 8;
-        rm |= (uint32_t)((lost >> depth) & 1ull) << cp;
-        lost &= ~(1ull << depth);
-        next = rdlane(rm, v) & (0xfffffffeu << cp);
-        if (next) break;
-        P |= 1ull << v;
-      }
-      if (!next) { status = MPLD_INFEASIBLE; break; }
-      c = (uint32_t)__ffs(next) - 1u;
+      // a column without rows (the first by index is the one chosen): dead end
+      if (TRACE)
+        s.h = trace_node(s.h, s.depth, s.row_in, low_bit(zero), 0);
+      c = backtrack(s, v, floor);
+      if (c == kNone) { status = MPLD_INFEASIBLE; break; }
     }
-    // ---- include row (v, c): close color c at v's neighbours that have it
-    const uint32_t hit = (uint32_t)(nb >> v) & (rm >> c) & 1u;
-    rm &= ~(hit << c);
-    lost |= (uint64_t)hit << depth;
-    st = lane == depth ? (v | (c << 8)) : st;
-    ++depth;
-    row_in = v * (uint32_t)k + c;
+    // ---- include row (v, c)
+    take_row(s, rdlane64(nb_lo, nb_hi, v), v, c);
+    s.row_in = v * (uint32_t)k + c;
   }
-  s.rm = rm; s.st = st; s.depth = depth; s.row_in = row_in;
-  s.lost = lost; s.P = P; s.nodes = nodes; s.h = h;
   s.status = status;
 }
 
 // Writes the colors (the chosen row of every column on a solution, -1
 // otherwise) and the record of a finished search.
-__device__ __forceinline__ void reg_finish(const RegState& s, int32_t n, int8_t* __restrict__ colors,
+template <int K>
+__device__ __forceinline__ void reg_finish(const RegState<K>& s, int32_t n,
+                                           int8_t* __restrict__ colors,
                                            DevRecord* __restrict__ rec) {
   const uint32_t lane = __lane_id();
   if (s.status == MPLD_FEASIBLE) {
-    if (lane < s.depth && (s.st & 0xffu) < (uint32_t)n) colors[s.st & 0xffu] = (int8_t)(s.st >> 8);
+    if (lane < s.depth && (s.fr & 0xffu) < (uint32_t)n)
+      colors[s.fr & 0xffu] = (int8_t)((s.fr >> 8) & 0xffu);
   } else if (lane < (uint32_t)n) {
     colors[lane] = -1;
   }
@@ -175,7 +305,7 @@ __device__ __forceinline__ void reg_finish(const RegState& s, int32_t n, int8_t*
 
 // cap < budget stops the search after `cap` nodes (status -1 in the record:
 // the component is left to the heavy-component engine).
-template <bool TRACE, int NB>
+template <bool TRACE, int K>
 __device__ __forceinline__ void solve_reg(const int32_t n, const int32_t k, const uint64_t budget,
                                           const uint64_t* __restrict__ nbmask,
                                           int8_t* __restrict__ colors,
@@ -183,21 +313,23 @@ __device__ __forceinline__ void solve_reg(const int32_t n, const int32_t k, cons
                                           const uint64_t cap = ~0ull) {
   const uint32_t lane = __lane_id();
   const uint64_t nb = lane < (uint32_t)n ? nbmask[lane] : 0ull;
-  RegState s;
+  RegState<K> s;
   reg_init(s, n, k);
-  reg_run<TRACE, NB>(s, nb, k, budget, cap < budget ? cap : budget);
+  reg_run<TRACE, K>(s, (uint32_t)nb, (uint32_t)(nb >> 32), k, budget, cap < budget ? cap : budget);
   reg_finish(s, n, colors, rec);
 }
 
 // Resumable state in device memory (kRegStateBytes per component): the
-// uniform part first, then the three lane arrays.
+// uniform head (counters at 0, planes at 32), then the three lane arrays.
 struct RegStateHead {
   uint64_t P, nodes, h;
   uint32_t depth, row_in;
 };
 static_assert(sizeof(RegStateHead) == 32, "state head is 32 bytes");
+static_assert(kRegStateBytes >= 128 + 64 * 12, "state layout");
 
-__device__ __forceinline__ void reg_save(const RegState& s, uint8_t* base) {
+template <int K>
+__device__ __forceinline__ void reg_save(const RegState<K>& s, uint8_t* base) {
   const uint32_t lane = __lane_id();
   RegStateHead* hd = reinterpret_cast<RegStateHead*>(base);
   hd->P = s.P;   // same value from every lane
@@ -205,22 +337,29 @@ __device__ __forceinline__ void reg_save(const RegState& s, uint8_t* base) {
   hd->h = s.h;
   hd->depth = s.depth;
   hd->row_in = s.row_in;
-  reinterpret_cast<uint32_t*>(base + 64)[lane] = s.rm;
-  reinterpret_cast<uint32_t*>(base + 64 + 256)[lane] = s.st;
-  reinterpret_cast<uint64_t*>(base + 64 + 512)[lane] = s.lost;
+  uint64_t* planes = reinterpret_cast<uint64_t*>(base + 32);
+#pragma unroll
+  for (int c = 0; c < K; ++c) planes[c] = s.O[c];
+  reinterpret_cast<uint32_t*>(base + 128)[lane] = s.fr;
+  reinterpret_cast<uint32_t*>(base + 128 + 256)[lane] = s.ll;
+  reinterpret_cast<uint32_t*>(base + 128 + 512)[lane] = s.lh;
 }
 
-__device__ __forceinline__ void reg_load(RegState& s, const uint8_t* base) {
+template <int K>
+__device__ __forceinline__ void reg_load(RegState<K>& s, const uint8_t* base) {
   const uint32_t lane = __lane_id();
   const RegStateHead* hd = reinterpret_cast<const RegStateHead*>(base);
-  s.P = ((uint64_t)uniform((uint32_t)(hd->P >> 32)) << 32) | uniform((uint32_t)hd->P);
-  s.nodes = ((uint64_t)uniform((uint32_t)(hd->nodes >> 32)) << 32) | uniform((uint32_t)hd->nodes);
-  s.h = ((uint64_t)uniform((uint32_t)(hd->h >> 32)) << 32) | uniform((uint32_t)hd->h);
+  s.P = uniform64(hd->P);
+  s.nodes = uniform64(hd->nodes);
+  s.h = uniform64(hd->h);
   s.depth = uniform(hd->depth);
   s.row_in = uniform(hd->row_in);
-  s.rm = reinterpret_cast<const uint32_t*>(base + 64)[lane];
-  s.st = reinterpret_cast<const uint32_t*>(base + 64 + 256)[lane];
-  s.lost = reinterpret_cast<const uint64_t*>(base + 64 + 512)[lane];
+  const uint64_t* planes = reinterpret_cast<const uint64_t*>(base + 32);
+#pragma unroll
+  for (int c = 0; c < K; ++c) s.O[c] = uniform64(planes[c]);
+  s.fr = reinterpret_cast<const uint32_t*>(base + 128)[lane];
+  s.ll = reinterpret_cast<const uint32_t*>(base + 128 + 256)[lane];
+  s.lh = reinterpret_cast<const uint32_t*>(base + 128 + 512)[lane];
   s.status = -1;
 }
 
@@ -230,7 +369,7 @@ __device__ __forceinline__ void reg_load(RegState& s, const uint8_t* base) {
 // one pop, so the pop that returns qlen - 1 is the last one: it resets the
 // counter to 0 and the launch (or the graph holding it) can be replayed with
 // no memset.
-template <bool TRACE, int NB>
+template <bool TRACE, int K>
 __global__ __launch_bounds__(256) void reg_batched_kernel(
     const DevDesc* __restrict__ descs, const uint64_t* __restrict__ masks, int32_t qlen,
     int32_t* __restrict__ counter, DevRecord* __restrict__ recs, int8_t* __restrict__ colors,
@@ -240,8 +379,8 @@ __global__ __launch_bounds__(256) void reg_batched_kernel(
   int32_t item = (int32_t)uniform(blockIdx.x * wpb + (threadIdx.x >> 6));
   while (item < qlen) {
     const DevDesc d = descs[item];
-    solve_reg<TRACE, NB>(d.n, d.k, (uint64_t)d.budget, masks + d.nbr_off, colors + d.out_off,
-                         recs + d.comp, cap);
+    solve_reg<TRACE, K>(d.n, d.k, (uint64_t)d.budget, masks + d.nbr_off, colors + d.out_off,
+                        recs + d.comp, cap);
     if (gw >= qlen) break;   // every item was handed out statically
     int32_t r = 0;
     if (__lane_id() == 0) r = atomicAdd(counter, 1);
@@ -252,14 +391,14 @@ __global__ __launch_bounds__(256) void reg_batched_kernel(
 }
 
 // One component per launch (the plain solver): a single wave.
-template <bool TRACE, int NB>
+template <bool TRACE, int K>
 __global__ __launch_bounds__(64) void reg_single_kernel(const DevDesc* __restrict__ descs,
                                                         const uint64_t* __restrict__ masks,
                                                         int32_t item, DevRecord* __restrict__ recs,
                                                         int8_t* __restrict__ colors) {
   const DevDesc d = descs[item];
-  solve_reg<TRACE, NB>(d.n, d.k, (uint64_t)d.budget, masks + d.nbr_off, colors + d.out_off,
-                       recs + d.comp);
+  solve_reg<TRACE, K>(d.n, d.k, (uint64_t)d.budget, masks + d.nbr_off, colors + d.out_off,
+                      recs + d.comp);
 }
 
 // Serving tick: every listed component advances by at most `slice` search
@@ -267,7 +406,7 @@ __global__ __launch_bounds__(64) void reg_single_kernel(const DevDesc* __restric
 // finished search writes its colors and record; a paused one saves its
 // state.  tick_out[i] receives the record of list entry i (status -1 while
 // the search is still running).  Work distribution as in the batched kernel.
-template <bool TRACE, int NB>
+template <bool TRACE, int K>
 __global__ __launch_bounds__(256) void reg_tick_kernel(
     const int32_t* __restrict__ list, int32_t len, int32_t* __restrict__ counter,
     const DevDesc* __restrict__ slot_desc, uint8_t* slot_state, DevRecord* __restrict__ slot_rec,
@@ -282,14 +421,14 @@ __global__ __launch_bounds__(256) void reg_tick_kernel(
     const uint32_t lane = __lane_id();
     const uint64_t nb = lane < (uint32_t)d.n ? arena64[d.nbr_off + lane] : 0ull;
     uint8_t* base = slot_state + (uint64_t)slot * kRegStateBytes;
-    RegState s;
+    RegState<K> s;
     if (entry >> 31)
       reg_init(s, d.n, d.k);
     else
       reg_load(s, base);
     const uint64_t budget = (uint64_t)d.budget;
     const uint64_t stop = budget - s.nodes > slice ? s.nodes + slice : budget;
-    reg_run<TRACE, NB>(s, nb, d.k, budget, stop);
+    reg_run<TRACE, K>(s, (uint32_t)nb, (uint32_t)(nb >> 32), d.k, budget, stop);
     if (s.status >= 0)
       reg_finish(s, d.n, arena8 + d.out_off, slot_rec + slot);
     else
@@ -311,22 +450,19 @@ __global__ __launch_bounds__(256) void reg_tick_kernel(
 // ---- heavy-component engine: subtree tasks --------------------------------
 
 // Rebuilds the search state at the end of a path of rows from the root:
-// cover each row's column and take the row, in order (the same applies the
-// sequential search made on the way down).
-__device__ __forceinline__ void reg_replay(RegState& s, const uint64_t nb, const int32_t k,
+// cover each row's column and take the row, in order (the same steps the
+// sequential search made on the way down, so the planes and frames match).
+template <int K>
+__device__ __forceinline__ void reg_replay(RegState<K>& s, const uint32_t nb_lo,
+                                           const uint32_t nb_hi, const int32_t k,
                                            const uint16_t* __restrict__ rows, uint32_t d) {
-  const uint32_t lane = __lane_id();
   for (uint32_t j = 0; j < d; ++j) {
     const uint32_t vc = uniform(rows[j]);
     const uint32_t v = vc & 0xffu, c = vc >> 8;
     s.P &= ~(1ull << v);
-    const uint32_t hit = (uint32_t)(nb >> v) & (s.rm >> c) & 1u;
-    s.rm &= ~(hit << c);
-    s.lost |= (uint64_t)hit << j;
-    s.st = lane == j ? vc : s.st;
+    take_row(s, rdlane64(nb_lo, nb_hi, v), v, c);
     s.row_in = v * (uint32_t)k + c;
   }
-  s.depth = d;
 }
 
 // Enumerates the top `levels` levels of the subtree rooted at depth d in
@@ -334,96 +470,73 @@ __device__ __forceinline__ void reg_replay(RegState& s, const uint64_t nb, const
 // at depth d + levels (not counted here: its own task counts it), a kind-2
 // item when a solution is met (writing its colors) or a kind-1 item at the
 // end.  Returns the number of items.
-template <int NB>
-__device__ __forceinline__ int32_t reg_enumerate(RegState& s, const uint64_t nb, const int32_t k,
-                                                 const int32_t n, const uint32_t d,
-                                                 const uint32_t levels, SplitItem* __restrict__ out,
+template <int K>
+__device__ __forceinline__ int32_t reg_enumerate(RegState<K>& s, const uint32_t nb_lo,
+                                                 const uint32_t nb_hi, const int32_t n,
+                                                 const uint32_t d, const uint32_t levels,
+                                                 SplitItem* __restrict__ out,
                                                  int8_t* __restrict__ sol) {
   const uint32_t lane = __lane_id();
   const uint32_t limit = d + levels;
-  uint32_t rm = s.rm, st = s.st, depth = s.depth;
-  uint64_t lost = s.lost, P = s.P;
   uint32_t seg = 0;
   int32_t items = 0;
   auto emit = [&](uint32_t kind) {
-    const uint32_t r0 = kind == 0 ? rdlane(st, d) : 0u;
-    const uint32_t r1 = kind == 0 && levels > 1 ? rdlane(st, d + 1) : 0u;
-    const uint32_t r2 = kind == 0 && levels > 2 ? rdlane(st, d + 2) : 0u;
-    const uint32_t r3 = kind == 0 && levels > 3 ? rdlane(st, d + 3) : 0u;
+    const uint32_t r0 = kind == 0 ? rdlane(s.fr, d) : 0u;
+    const uint32_t r1 = kind == 0 && levels > 1 ? rdlane(s.fr, d + 1) : 0u;
+    const uint32_t r2 = kind == 0 && levels > 2 ? rdlane(s.fr, d + 2) : 0u;
+    const uint32_t r3 = kind == 0 && levels > 3 ? rdlane(s.fr, d + 3) : 0u;
     if (lane == ((uint32_t)items & 63u)) {   // one owner lane per item
       SplitItem it;
       it.seg = seg;
       it.kind = kind;
-      it.rows[0] = (uint16_t)r0;
-      it.rows[1] = (uint16_t)r1;
-      it.rows[2] = (uint16_t)r2;
-      it.rows[3] = (uint16_t)r3;
+      it.rows[0] = (uint16_t)(r0 & 0xffffu);
+      it.rows[1] = (uint16_t)(r1 & 0xffffu);
+      it.rows[2] = (uint16_t)(r2 & 0xffffu);
+      it.rows[3] = (uint16_t)(r3 & 0xffffu);
       out[items] = it;
     }
     ++items;
     seg = 0;
   };
   for (;;) {
-    bool back;
     uint32_t v = 0, c = 0;
-    if (depth == limit) {
+    bool back;
+    if (s.depth == limit) {
       emit(0);        // a subtask root: leave it to its own task
       back = true;
     } else {
       ++seg;
-      if (P == 0) {   // a solution among the top levels
-        if (lane < depth && (st & 0xffu) < (uint32_t)n) sol[st & 0xffu] = (int8_t)(st >> 8);
+      if (s.P == 0) {   // a solution among the top levels
+        if (lane < s.depth && (s.fr & 0xffu) < (uint32_t)n)
+          sol[s.fr & 0xffu] = (int8_t)((s.fr >> 8) & 0xffu);
         emit(2);
         break;
       }
-      const uint32_t cnt = __popc(rm);
-      uint64_t cand = P;
+      uint64_t any = s.O[0];
 #pragma unroll
-      for (int j = NB - 1; j >= 0; --j) {
-        const uint64_t one = __ballot((cnt >> j) & 1u);
-        const uint64_t zero = cand & ~one;
-        cand = zero ? zero : cand;
-      }
-      v = (uint32_t)__ffsll((unsigned long long)cand) - 1u;
-      if (rdlane(cnt, v) != 0) {
-        P &= ~(1ull << v);
-        c = (uint32_t)__ffs(rdlane(rm, v)) - 1u;
-        back = false;
-      } else {
-        back = true;
+      for (int j = 1; j < K; ++j) any |= s.O[j];
+      back = (s.P & ~any) != 0;
+      if (!back) {
+        v = low_bit(min_count_columns(s.O, s.P));
+        c = first_color(s.O, v);
+        s.P &= ~(1ull << v);
       }
     }
     if (back) {
-      uint32_t next = 0;
-      while (depth != d) {
-        --depth;
-        const uint32_t vc = rdlane(st, depth);
-        v = vc & 0xffu;
-        const uint32_t cp = vc >> 8;
-        rm |= (uint32_t)((lost >> depth) & 1ull) << cp;
-        lost &= ~(1ull << depth);
-        next = rdlane(rm, v) & (0xfffffffeu << cp);
-        if (next) break;
-        P |= 1ull << v;
-      }
-      if (!next) {
+      c = backtrack(s, v, d);
+      if (c == kNone) {
         emit(1);
         break;
       }
-      c = (uint32_t)__ffs(next) - 1u;
     }
-    const uint32_t hit = (uint32_t)(nb >> v) & (rm >> c) & 1u;
-    rm &= ~(hit << c);
-    lost |= (uint64_t)hit << depth;
-    st = lane == depth ? (v | (c << 8)) : st;
-    ++depth;
+    take_row(s, rdlane64(nb_lo, nb_hi, v), v, c);
   }
   return items;
 }
 
 // One wave per task: explore the task's subtree up to `cap` nodes; if the
 // cap is hit, split the task `levels` levels down instead.
-template <int NB>
+template <int K>
 __global__ __launch_bounds__(256) void reg_split_kernel(
     const SplitTask* __restrict__ tasks, int32_t ntasks, int32_t* __restrict__ counter,
     const DevDesc* __restrict__ descs, const uint64_t* __restrict__ masks, uint64_t cap,
@@ -439,20 +552,22 @@ __global__ __launch_bounds__(256) void reg_split_kernel(
     const uint32_t d = uniform((uint32_t)task->depth);
     const DevDesc dd = descs[it];
     const uint64_t nb = lane < (uint32_t)dd.n ? masks[dd.nbr_off + lane] : 0ull;
+    const uint32_t nb_lo = (uint32_t)nb, nb_hi = (uint32_t)(nb >> 32);
     int8_t* sol = sols + (uint64_t)t * 64;
-    RegState s;
+    RegState<K> s;
     reg_init(s, dd.n, dd.k);
-    reg_replay(s, nb, dd.k, task->rows, d);
-    reg_run<false, NB>(s, nb, dd.k, ~0ull, cap, d);
+    reg_replay(s, nb_lo, nb_hi, dd.k, task->rows, d);
+    reg_run<false, K>(s, nb_lo, nb_hi, dd.k, ~0ull, cap, d);
     int32_t nitems = 0;
     if (s.status == MPLD_FEASIBLE) {
-      if (lane < s.depth && (s.st & 0xffu) < (uint32_t)dd.n) sol[s.st & 0xffu] = (int8_t)(s.st >> 8);
+      if (lane < s.depth && (s.fr & 0xffu) < (uint32_t)dd.n)
+        sol[s.fr & 0xffu] = (int8_t)((s.fr >> 8) & 0xffu);
     } else if (s.status < 0) {
-      RegState r;
+      RegState<K> r;
       reg_init(r, dd.n, dd.k);
-      reg_replay(r, nb, dd.k, task->rows, d);
-      nitems = reg_enumerate<NB>(r, nb, dd.k, dd.n, d, levels,
-                                 items + (uint64_t)t * (uint64_t)max_items, sol);
+      reg_replay(r, nb_lo, nb_hi, dd.k, task->rows, d);
+      nitems = reg_enumerate(r, nb_lo, nb_hi, dd.n, d, levels,
+                             items + (uint64_t)t * (uint64_t)max_items, sol);
     }
     SplitResult res;
     res.status = s.status;
@@ -481,22 +596,19 @@ hipError_t launch_fill_i32(int32_t* p, int32_t count, int32_t value, hipStream_t
   return hipGetLastError();
 }
 
-// Row counts of k colors need count_bits(k) bits.
-static int count_bits(int k) { return k < 4 ? 2 : (k < 8 ? 3 : 4); }
+// Number of color planes compiled for k colors: 2, 3 and 4 exactly, 8 for
+// k = 5..8 (the planes past k stay empty).
+static int planes_for(int k) { return k <= 4 ? k : 8; }
 
-template <bool TRACE, int NB>
-static void reg_batched_t(int grid, int wpb, const DevDesc* descs, const uint64_t* masks,
-                          int32_t qlen, int32_t* counter, DevRecord* recs, int8_t* colors,
-                          uint64_t cap, hipStream_t s) {
-  hipLaunchKernelGGL((reg_batched_kernel<TRACE, NB>), dim3(grid), dim3(64 * wpb), 0, s, descs,
-                     masks, qlen, counter, recs, colors, cap);
-}
-
-template <bool TRACE, int NB>
-static void reg_single_t(const DevDesc* descs, const uint64_t* masks, int32_t item,
-                         DevRecord* recs, int8_t* colors, hipStream_t s) {
-  hipLaunchKernelGGL((reg_single_kernel<TRACE, NB>), dim3(1), dim3(64), 0, s, descs, masks, item,
-                     recs, colors);
+// Calls f(std::integral_constant<int, K>) for the plane count of k.
+template <class F>
+static void with_planes(int k, F&& f) {
+  switch (planes_for(k)) {
+    case 2: f(std::integral_constant<int, 2>()); break;
+    case 3: f(std::integral_constant<int, 3>()); break;
+    case 4: f(std::integral_constant<int, 4>()); break;
+    default: f(std::integral_constant<int, 8>()); break;
+  }
 }
 
 hipError_t launch_reg_batched(bool trace, int k, int grid, int wpb, const DevDesc* descs,
@@ -504,37 +616,30 @@ hipError_t launch_reg_batched(bool trace, int k, int grid, int wpb, const DevDes
                               DevRecord* recs, int8_t* colors, uint64_t cap, hipStream_t s) {
   if (qlen <= 0) return hipSuccess;
   if (wpb < 1 || wpb > 4) return hipErrorInvalidValue;
-  switch (count_bits(k) + (trace ? 8 : 0)) {
-    case 2: reg_batched_t<false, 2>(grid, wpb, descs, masks, qlen, counter, recs, colors, cap, s); break;
-    case 3: reg_batched_t<false, 3>(grid, wpb, descs, masks, qlen, counter, recs, colors, cap, s); break;
-    case 4: reg_batched_t<false, 4>(grid, wpb, descs, masks, qlen, counter, recs, colors, cap, s); break;
-    case 10: reg_batched_t<true, 2>(grid, wpb, descs, masks, qlen, counter, recs, colors, cap, s); break;
-    case 11: reg_batched_t<true, 3>(grid, wpb, descs, masks, qlen, counter, recs, colors, cap, s); break;
-    default: reg_batched_t<true, 4>(grid, wpb, descs, masks, qlen, counter, recs, colors, cap, s); break;
-  }
+  with_planes(k, [&](auto kp) {
+    constexpr int K = decltype(kp)::value;
+    if (trace)
+      hipLaunchKernelGGL((reg_batched_kernel<true, K>), dim3(grid), dim3(64 * wpb), 0, s, descs,
+                         masks, qlen, counter, recs, colors, cap);
+    else
+      hipLaunchKernelGGL((reg_batched_kernel<false, K>), dim3(grid), dim3(64 * wpb), 0, s, descs,
+                         masks, qlen, counter, recs, colors, cap);
+  });
   return hipGetLastError();
 }
 
 hipError_t launch_reg_single(bool trace, int k, const DevDesc* descs, const uint64_t* masks,
                              int32_t item, DevRecord* recs, int8_t* colors, hipStream_t s) {
-  switch (count_bits(k) + (trace ? 8 : 0)) {
-    case 2: reg_single_t<false, 2>(descs, masks, item, recs, colors, s); break;
-    case 3: reg_single_t<false, 3>(descs, masks, item, recs, colors, s); break;
-    case 4: reg_single_t<false, 4>(descs, masks, item, recs, colors, s); break;
-    case 10: reg_single_t<true, 2>(descs, masks, item, recs, colors, s); break;
-    case 11: reg_single_t<true, 3>(descs, masks, item, recs, colors, s); break;
-    default: reg_single_t<true, 4>(descs, masks, item, recs, colors, s); break;
-  }
+  with_planes(k, [&](auto kp) {
+    constexpr int K = decltype(kp)::value;
+    if (trace)
+      hipLaunchKernelGGL((reg_single_kernel<true, K>), dim3(1), dim3(64), 0, s, descs, masks,
+                         item, recs, colors);
+    else
+      hipLaunchKernelGGL((reg_single_kernel<false, K>), dim3(1), dim3(64), 0, s, descs, masks,
+                         item, recs, colors);
+  });
   return hipGetLastError();
-}
-
-template <bool TRACE, int NB>
-static void reg_tick_t(int grid, const int32_t* list, int32_t len, int32_t* counter,
-                       const DevDesc* slot_desc, uint8_t* slot_state, DevRecord* slot_rec,
-                       const uint64_t* arena64, int8_t* arena8, uint64_t slice,
-                       DevRecord* tick_out, hipStream_t s) {
-  hipLaunchKernelGGL((reg_tick_kernel<TRACE, NB>), dim3(grid), dim3(256), 0, s, list, len, counter,
-                     slot_desc, slot_state, slot_rec, arena64, arena8, slice, tick_out);
 }
 
 hipError_t launch_reg_tick(bool trace, int k, int grid, const int32_t* list, int32_t len,
@@ -542,14 +647,15 @@ hipError_t launch_reg_tick(bool trace, int k, int grid, const int32_t* list, int
                            DevRecord* slot_rec, const uint64_t* arena64, int8_t* arena8,
                            uint64_t slice, DevRecord* tick_out, hipStream_t s) {
   if (len <= 0) return hipSuccess;
-  switch (count_bits(k) + (trace ? 8 : 0)) {
-    case 2: reg_tick_t<false, 2>(grid, list, len, counter, slot_desc, slot_state, slot_rec, arena64, arena8, slice, tick_out, s); break;
-    case 3: reg_tick_t<false, 3>(grid, list, len, counter, slot_desc, slot_state, slot_rec, arena64, arena8, slice, tick_out, s); break;
-    case 4: reg_tick_t<false, 4>(grid, list, len, counter, slot_desc, slot_state, slot_rec, arena64, arena8, slice, tick_out, s); break;
-    case 10: reg_tick_t<true, 2>(grid, list, len, counter, slot_desc, slot_state, slot_rec, arena64, arena8, slice, tick_out, s); break;
-    case 11: reg_tick_t<true, 3>(grid, list, len, counter, slot_desc, slot_state, slot_rec, arena64, arena8, slice, tick_out, s); break;
-    default: reg_tick_t<true, 4>(grid, list, len, counter, slot_desc, slot_state, slot_rec, arena64, arena8, slice, tick_out, s); break;
-  }
+  with_planes(k, [&](auto kp) {
+    constexpr int K = decltype(kp)::value;
+    if (trace)
+      hipLaunchKernelGGL((reg_tick_kernel<true, K>), dim3(grid), dim3(256), 0, s, list, len,
+                         counter, slot_desc, slot_state, slot_rec, arena64, arena8, slice, tick_out);
+    else
+      hipLaunchKernelGGL((reg_tick_kernel<false, K>), dim3(grid), dim3(256), 0, s, list, len,
+                         counter, slot_desc, slot_state, slot_rec, arena64, arena8, slice, tick_out);
+  });
   return hipGetLastError();
 }
 
@@ -559,29 +665,20 @@ hipError_t launch_reg_split(int k, int grid, const SplitTask* tasks, int32_t nta
                             SplitResult* results, SplitItem* items, int8_t* sols, hipStream_t s) {
   if (ntasks <= 0) return hipSuccess;
   if (levels < 1 || levels > (uint32_t)kSplitMaxLevels) return hipErrorInvalidValue;
-  switch (count_bits(k)) {
-    case 2:
-      hipLaunchKernelGGL((reg_split_kernel<2>), dim3(grid), dim3(256), 0, s, tasks, ntasks, counter,
-                         descs, masks, cap, levels, max_items, results, items, sols);
-      break;
-    case 3:
-      hipLaunchKernelGGL((reg_split_kernel<3>), dim3(grid), dim3(256), 0, s, tasks, ntasks, counter,
-                         descs, masks, cap, levels, max_items, results, items, sols);
-      break;
-    default:
-      hipLaunchKernelGGL((reg_split_kernel<4>), dim3(grid), dim3(256), 0, s, tasks, ntasks, counter,
-                         descs, masks, cap, levels, max_items, results, items, sols);
-      break;
-  }
+  with_planes(k, [&](auto kp) {
+    constexpr int K = decltype(kp)::value;
+    hipLaunchKernelGGL((reg_split_kernel<K>), dim3(grid), dim3(256), 0, s, tasks, ntasks, counter,
+                       descs, masks, cap, levels, max_items, results, items, sols);
+  });
   return hipGetLastError();
 }
 
 int reg_batched_blocks_per_cu(bool trace) {
   int blocks = 0;
   hipError_t e = trace ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                             &blocks, reg_batched_kernel<true, 4>, 256, 0)
+                             &blocks, reg_batched_kernel<true, 8>, 256, 0)
                        : hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                             &blocks, reg_batched_kernel<false, 4>, 256, 0);
+                             &blocks, reg_batched_kernel<false, 8>, 256, 0);
   return e == hipSuccess && blocks > 0 ? blocks : 1;
 }
 
