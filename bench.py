@@ -142,6 +142,38 @@ def serve_leg(mp, ctx, count: int, seed: int):
             "admission_waits": st["admission_waits"], "peak_device_bytes": st["peak_bytes"]}
 
 
+# Per-node latency probes (labelled as probes, not workloads): one connected
+# random component per tier, run to its node budget on a single wave (or
+# the whole device), so launch and setup costs vanish in the per-node time.
+# The instances were picked so that the search runs to the budget.
+PROBES = [
+    # name, n, k, average degree, seed, budget, tier flag name
+    ("register_k3_n64", 64, 3, 4.4, 26, 200000, "MPLD_FORCE_WAVE"),
+    ("register_k4_n64", 64, 4, 8.4, 0, 200000, "MPLD_FORCE_WAVE"),
+    ("lds_k3_n10000", 10000, 3, 4.6, 0, 20000, "MPLD_FORCE_GLOBAL"),
+    ("device_k3_n10000", 10000, 3, 4.6, 0, 2000, "MPLD_FORCE_DEVICE"),
+]
+
+
+def latency_probe(mp, ctx, reps=3):
+    import numpy as np
+    import workload
+    out = {}
+    for name, n, k, deg, seed, budget, flag in PROBES:
+        e = workload.random_component(n, deg, seed)
+        g = mp.Graph(n, e, np.zeros((0, 2), np.int32))
+        b = mp.Batch(ctx, g, k, budget, getattr(mp, flag))
+        ms = []
+        for _ in range(reps):
+            b.solve(direct=True)
+            ms.append(b.info()["last_search_ms"])
+        nodes = int(b.result().components["nodes"].sum())
+        b.close()
+        out[name] = {"n": n, "k": k, "avg_degree": deg, "seed": seed, "nodes": nodes,
+                     "ms": round(min(ms), 4), "ns_per_node": round(1e6 * min(ms) / max(nodes, 1), 2)}
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -151,12 +183,15 @@ def main() -> int:
     ap.add_argument("--plain-steps", type=int, default=10)
     ap.add_argument("--split", action="store_true",
                     help="search heavy components as parallel subtrees (exact sequential counts)")
+    ap.add_argument("--heavy-caps", type=str, default="",
+                    help="with --split: first-pass cap,round cap[,levels] of the heavy engine")
     ap.add_argument("--launch", choices=["graph", "direct"], default="graph",
                     help="batched solve: replay the captured HIP graph or launch directly")
     ap.add_argument("--kernel-reps", type=int, default=50,
                     help="direct launches timed one by one for the kernel duration")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-latency-probe", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=1000,
                     help="serving leg: requests of the serving workload (0 = skip)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -189,6 +224,10 @@ def main() -> int:
     g = mp.mpld_build_graph(rects, w.dmin_nm, w.split_len_nm)
     t1 = time.perf_counter()
     b = mp.Batch(ctx, g, w.k, w.budget, mp.MPLD_SIMPLIFY)
+    if args.heavy_caps:
+        caps = [int(x) for x in args.heavy_caps.split(",")]
+        b.set_tune(heavy_first_cap=caps[0], heavy_round_cap=caps[1],
+                   heavy_levels=caps[2] if len(caps) > 2 else 0)
     t2 = time.perf_counter()
     b.solve(split=args.split)
     res = b.result()
@@ -227,6 +266,8 @@ def main() -> int:
         torch.cuda.synchronize()
         kms.append(b.info()["last_search_ms"])
     kernel_ms = float(np.mean(kms))
+    info_split = b.info()
+    tune = b.get_tune()
     assert info["launches"] >= 1
 
     # ---- plain solver: one launch per component on the same batch
@@ -305,6 +346,11 @@ def main() -> int:
         "device_ms_per_step": dev_ms / args.steps,
         "launch": args.launch,
         "split_heavy": args.split,
+        "heavy_engine": ({"tune": {x: tune[x] for x in ("heavy_first_cap", "heavy_round_cap",
+                                                         "heavy_levels")},
+                          "components": info_split["heavy_components"],
+                          "rounds": info_split["split_rounds"], "tasks": info_split["split_tasks"],
+                          "reruns": info_split["split_reruns"]} if args.split else None),
         "plain": {"ms_per_step": plain_ms, "search_nodes_per_s": total_nodes / (plain_ms * 1e-3),
                   "components_per_s": ncomp / (plain_ms * 1e-3), "launches": ncomp,
                   "same_result": same},
@@ -317,6 +363,9 @@ def main() -> int:
                      "budget": int(np.sum(comps["status"] == 2))},
         "stitches": res.stitches, "uncolored": res.uncolored,
     }
+    if not args.no_latency_probe:
+        log("latency probes")
+        out["latency_probe"] = latency_probe(mp, ctx)
     if args.serve_requests:
         log(f"serving leg: {args.serve_requests} requests")
         out["serving"] = serve_leg(mp, ctx, args.serve_requests, 0)

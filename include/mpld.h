@@ -225,6 +225,11 @@ typedef struct {
   float last_total_ms;       /* whole enqueued solve of the last solve    */
   int32_t launches;          /* kernel launches of the last solve         */
   int32_t num_device;        /* components on the device-wide tier        */
+  int32_t heavy_components;  /* MPLD_SPLIT_HEAVY, last solve: components past
+                                the first-pass cap                          */
+  int32_t split_rounds;      /* ... task rounds                              */
+  int32_t split_tasks;       /* ... subtree tasks run                        */
+  int32_t split_reruns;      /* ... components re-run sequentially (budget)  */
 } mpld_batch_info;
 int32_t mpld_batch_get_info(mpld_batch* b, mpld_batch_info* info);
 void mpld_batch_free(mpld_batch* b);
@@ -254,6 +259,12 @@ typedef struct {
   float default_ms;          /* autotune: the same for the default schedule    */
   int32_t candidates;        /* autotune: schedules timed                      */
   int32_t from_cache;        /* get: the schedule came from the cache          */
+  int32_t heavy_first_cap;   /* MPLD_SPLIT_HEAVY: first-pass node cap (>= 64)  */
+  int32_t heavy_round_cap;   /* MPLD_SPLIT_HEAVY: nodes per subtree task and
+                                round (>= 16)                                   */
+  int32_t heavy_levels;      /* MPLD_SPLIT_HEAVY: search levels enumerated when
+                                a capped task splits (1..4; 0 = 4, 3 or 2 for
+                                k <= 3, k = 4, k >= 5)                          */
 } mpld_tune;
 int32_t mpld_batch_autotune(mpld_batch* b, int32_t reps, const char* cache_path, mpld_tune* out);
 int32_t mpld_batch_get_tune(mpld_batch* b, mpld_tune* out);

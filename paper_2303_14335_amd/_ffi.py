@@ -69,14 +69,17 @@ class mpld_batch_info(ctypes.Structure):
     _fields_ = [("num_components", c_i32), ("num_wave", c_i32), ("num_lds", c_i32),
                 ("num_global", c_i32), ("core_nodes", c_i32), ("max_size", c_i32),
                 ("image_bytes", c_i64), ("core_edges", c_i64), ("last_search_ms", ctypes.c_float),
-                ("last_total_ms", ctypes.c_float), ("launches", c_i32), ("num_device", c_i32)]
+                ("last_total_ms", ctypes.c_float), ("launches", c_i32), ("num_device", c_i32),
+                ("heavy_components", c_i32), ("split_rounds", c_i32), ("split_tasks", c_i32),
+                ("split_reruns", c_i32)]
 
 
 class mpld_tune(ctypes.Structure):
     _fields_ = [("struct_size", c_u32), ("waves_per_block", c_i32), ("max_blocks", c_i32),
                 ("use_graph", c_i32), ("order", c_i32), ("giant_device", c_i32),
                 ("giant_min_nodes", c_i32), ("best_ms", ctypes.c_float),
-                ("default_ms", ctypes.c_float), ("candidates", c_i32), ("from_cache", c_i32)]
+                ("default_ms", ctypes.c_float), ("candidates", c_i32), ("from_cache", c_i32),
+                ("heavy_first_cap", c_i32), ("heavy_round_cap", c_i32), ("heavy_levels", c_i32)]
 
 
 class mpld_server_options(ctypes.Structure):

@@ -241,6 +241,10 @@ int32_t mpld_batch_get_info(mpld_batch* b, mpld_batch_info* info) {
     info->last_total_ms = b->db.last_total_ms;
     info->launches = b->db.launches;
     info->num_device = b->db.n_dev;
+    info->heavy_components = (int32_t)b->db.sp_heavy;
+    info->split_rounds = (int32_t)b->db.sp_rounds;
+    info->split_tasks = (int32_t)b->db.sp_tasks_run;
+    info->split_reruns = (int32_t)b->db.sp_reruns;
   });
 }
 

@@ -100,6 +100,10 @@ bool tune_from_cache(mpld_batch* b, const char* path, Tune* t) {
   if (field(hit, "order", &v)) t->order = v ? 1 : 0;
   if (field(hit, "giant_device", &v)) t->giant_device = v ? 1 : 0;
   if (field(hit, "giant_min_nodes", &v)) t->giant_min_nodes = (int32_t)std::max(65L, v);
+  if (field(hit, "heavy_first_cap", &v)) t->heavy_first_cap = (int32_t)std::max(64L, v);
+  if (field(hit, "heavy_round_cap", &v)) t->heavy_round_cap = (int32_t)std::max(16L, v);
+  if (field(hit, "heavy_levels", &v))
+    t->heavy_levels = (int32_t)std::max(0L, std::min((long)kSplitMaxLevels, v));
   b->tuned_from_cache = true;
   return true;
 }
@@ -147,6 +151,9 @@ static void to_abi(const Tune& t, mpld_tune* o) {
   o->order = t.order;
   o->giant_device = t.giant_device;
   o->giant_min_nodes = t.giant_min_nodes;
+  o->heavy_first_cap = t.heavy_first_cap;
+  o->heavy_round_cap = t.heavy_round_cap;
+  o->heavy_levels = t.heavy_levels;
 }
 
 extern "C" {
@@ -169,6 +176,9 @@ int32_t mpld_batch_set_tune(mpld_batch* b, const mpld_tune* in) {
     t.order = in->order ? 1 : 0;
     t.giant_device = in->giant_device ? 1 : 0;
     t.giant_min_nodes = std::max(65, in->giant_min_nodes);
+    t.heavy_first_cap = std::max(64, in->heavy_first_cap);
+    t.heavy_round_cap = std::max(16, in->heavy_round_cap);
+    t.heavy_levels = std::max(0, std::min(kSplitMaxLevels, in->heavy_levels));
     batch_pack(b, t);
     b->solved = false;
     set_last_error("");
@@ -240,7 +250,10 @@ int32_t mpld_batch_autotune(mpld_batch* b, int32_t reps, const char* cache_path,
         f << "{\"key\": \"" << shape_key(b) << "\", \"waves_per_block\": " << best.waves_per_block
           << ", \"max_blocks\": " << best.max_blocks << ", \"use_graph\": " << best.use_graph
           << ", \"order\": " << best.order << ", \"giant_device\": " << best.giant_device
-          << ", \"giant_min_nodes\": " << best.giant_min_nodes << ", \"best_ms\": " << best_ms
+          << ", \"giant_min_nodes\": " << best.giant_min_nodes
+          << ", \"heavy_first_cap\": " << best.heavy_first_cap
+          << ", \"heavy_round_cap\": " << best.heavy_round_cap
+          << ", \"heavy_levels\": " << best.heavy_levels << ", \"best_ms\": " << best_ms
           << ", \"default_ms\": " << base_ms << "}\n";
       }
     }

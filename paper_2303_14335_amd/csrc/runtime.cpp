@@ -240,8 +240,6 @@ static void enqueue_batched(DeviceBatch& db, bool trace, uint64_t cap, hipStream
 
 namespace {
 
-constexpr uint64_t kHeavyFirstCap = 4096;   // nodes before a component counts as heavy
-constexpr uint64_t kHeavyRoundCap = 2048;   // nodes per task and round
 constexpr int32_t kHeavyMaxTasks = 16384;   // tasks per round
 
 struct HTask {
@@ -323,19 +321,23 @@ static void heavy_engine(DeviceBatch& db) {
   }
   if (hcs.empty()) return;
   db.sp_heavy = (int64_t)hcs.size();
-  const int levels = split_levels(db.k);
-  int32_t max_items = 2;   // k^levels subtasks, an end item, a solution item
-  {
-    int64_t kp = 1;
-    for (int l = 0; l < levels; ++l) kp *= db.k;
-    max_items = (int32_t)kp + 2;
+  int levels = db.tune.heavy_levels > 0 ? db.tune.heavy_levels : split_levels(db.k);
+  int64_t kp = 1;   // at most k^levels subtasks per split
+  for (int l = 0; l < levels; ++l) kp *= db.k;
+  while (levels > 1 && kp > 512) {   // keep the item area bounded
+    kp /= db.k;
+    --levels;
   }
+  const int32_t max_items = (int32_t)kp + 2;   // subtasks, an end item, a solution item
   if (!db.sp_tasks.p) {
     db.sp_tasks.alloc(ctx, sizeof(SplitTask) * kHeavyMaxTasks);
     db.sp_results.alloc(ctx, sizeof(SplitResult) * kHeavyMaxTasks);
-    db.sp_items.alloc(ctx, sizeof(SplitItem) * (size_t)kHeavyMaxTasks * (size_t)max_items);
     db.sp_sols.alloc(ctx, 64 * (size_t)kHeavyMaxTasks);
   }
+  // the item area depends on k and the split depth, which a new schedule
+  // may change: grow it when it is too small for this solve
+  const size_t item_bytes = sizeof(SplitItem) * (size_t)kHeavyMaxTasks * (size_t)max_items;
+  if (db.sp_items.bytes < item_bytes) db.sp_items.alloc(ctx, item_bytes);
   std::vector<SplitTask> up;
   std::vector<SplitResult> res;
   std::vector<SplitItem> items;
@@ -362,7 +364,7 @@ static void heavy_engine(DeviceBatch& db) {
               "heavy: tasks");
     const int grid = std::max(1, std::min((nt + 3) / 4, ctx->num_cus * ctx->reg_blocks_per_cu));
     check_hip(launch_reg_split(db.k, grid, db.sp_tasks.as<SplitTask>(), nt, db.counters.as<int32_t>() + 6,
-                               db.desc.as<DevDesc>(), db.masks.as<uint64_t>(), kHeavyRoundCap,
+                               db.desc.as<DevDesc>(), db.masks.as<uint64_t>(), (uint64_t)db.tune.heavy_round_cap,
                                (uint32_t)levels, max_items, db.sp_results.as<SplitResult>(),
                                db.sp_items.as<SplitItem>(), db.sp_sols.as<int8_t>(), s),
               "heavy: split launch");
@@ -465,7 +467,7 @@ void device_solve(DeviceBatch& db, uint32_t flags) {
   hipStream_t s = ctx->stream;
   const bool trace = flags & MPLD_TRACE_HASH;
   const bool split = (flags & MPLD_SPLIT_HEAVY) && !trace && !(flags & MPLD_PLAIN) && db.n_reg > 0;
-  const uint64_t cap = split ? kHeavyFirstCap : ~0ull;
+  const uint64_t cap = split ? (uint64_t)db.tune.heavy_first_cap : ~0ull;
   const bool timed = !(flags & MPLD_UNTIMED) || (flags & MPLD_PLAIN);
   db.timed = false;
   if (flags & MPLD_PLAIN) {

@@ -94,3 +94,17 @@ def request_trace(seed: int, count: int, rate: float = 500.0, n_min: int = 100,
     if rc != 0:
         raise ValueError(f"lg_request_trace failed with {rc}")
     return {"arrival_s": arr, "n_rects": nr, "side_nm": sd, "seed": ls}
+
+
+def random_component(n: int, avg_degree: float, seed: int) -> np.ndarray:
+    """Connected random graph for latency probes: the path 0-1-...-(n-1) plus
+    uniformly random extra pairs (numpy PCG64, `seed`) until n*avg_degree/2
+    distinct pairs.  Returns int32 [m, 2] pairs (u < v), sorted."""
+    rng = np.random.default_rng(seed)
+    m = int(n * avg_degree / 2)
+    e = set((i, i + 1) for i in range(n - 1))
+    while len(e) < m:
+        a, b = rng.integers(0, n, 2)
+        if a != b:
+            e.add((int(min(a, b)), int(max(a, b))))
+    return np.array(sorted(e), dtype=np.int32).reshape(-1, 2)
