@@ -157,6 +157,7 @@ PROBES = [
 
 def latency_probe(mp, ctx, reps=3):
     import numpy as np
+    import torch
     import workload
     out = {}
     for name, n, k, deg, seed, budget, flag in PROBES:
@@ -166,6 +167,7 @@ def latency_probe(mp, ctx, reps=3):
         ms = []
         for _ in range(reps):
             b.solve(direct=True)
+            torch.cuda.synchronize()
             ms.append(b.info()["last_search_ms"])
         nodes = int(b.result().components["nodes"].sum())
         b.close()

@@ -64,7 +64,8 @@ constexpr int kSplitMaxLevels = 4;
 
 // Device bytes of the resumable register-tier search state of one
 // component (serving): a 128-byte uniform head (counters, then up to eight
-// 64-bit color planes), then 64 lanes x (u32 frame, u32 + u32 undo set).
-constexpr uint64_t kRegStateBytes = 128 + 64 * (4 + 4 + 4);
+// 64-bit color planes), then 64 lanes x (u32 frame, u64 P snapshot, up to
+// eight u64 plane snapshots).
+constexpr uint64_t kRegStateBytes = 128 + 64 * 4 * (3 + 2 * 8);
 
 }  // namespace mpld

@@ -124,8 +124,8 @@ struct Tune {
   int32_t order = 0;             // 0 largest first, 1 smallest first
   int32_t giant_device = 0;      // giants on the device-wide tier instead of the big tier
   int32_t giant_min_nodes = 4096;
-  int32_t heavy_first_cap = 4096;  // heavy-component engine: first-pass node cap
-  int32_t heavy_round_cap = 2048;  // nodes per subtree task and round
+  int32_t heavy_first_cap = 2048;  // heavy-component engine: first-pass node cap
+  int32_t heavy_round_cap = 1024;  // nodes per subtree task and round
   int32_t heavy_levels = 0;        // levels per split; 0 = by k (4, 3 or 2)
 };
 

@@ -18,11 +18,14 @@
 // down keeps the columns of smallest count, and the lowest set bit is the
 // lowest local index.
 // Cover of row (v, c) (Eq. 2 "cover"): v's conflict neighbours lose color
-// c, lost = O[c] & N(v) and O[c] &= ~N(v); uncover ORs lost back.  Taking a
-// row also covers column v (clears it from P).
-// The recursion of Algorithm 1 is an explicit stack in three VGPRs, lane d
-// holding frame d: v | c << 8 and the 64-bit `lost` set.  The
-// neighbour sets N(v) sit one per lane (lane v) and are read with
+// c, O[c] &= ~N(v), and column v leaves P.
+// The recursion of Algorithm 1 is an explicit stack in VGPRs, lane d
+// holding frame d: v | c << 8 and a snapshot of P and the planes from
+// right before row (v, c) was taken.  Uncover (Eq. 2 "uncover") of all the
+// rows above a frame is restoring that frame's snapshot, so a dead end
+// jumps straight to the deepest frame whose column has untried rows (a
+// uniform bit set of such depths) instead of popping frame by frame.
+// The neighbour sets N(v) sit one per lane (lane v) and are read with
 // v_readlane when v is chosen.
 #include <hip/hip_runtime.h>
 
@@ -77,19 +80,26 @@ __device__ __forceinline__ uint64_t uniform64(uint64_t x) {
 constexpr int bit_width(int x) { return x == 0 ? 0 : 1 + bit_width(x >> 1); }
 
 // Search state of one component, K color planes (K >= k; planes k..K-1 stay
-// empty).  Wave-uniform: the planes, P, counters, depth, hash, entering row,
-// status (-1 while the search runs or is paused).  Per lane: frame `fr` and
-// undo set `ll`/`lh` of depth = lane.
+// empty).  Wave-uniform: the planes O, the uncovered set P, the set A of
+// stack depths whose column still has untried rows, counters, depth, hash,
+// entering row, status (-1 while the search runs or is paused).  Per lane
+// d (the stack): the frame fr = v | c << 8 of depth d and a snapshot of the
+// state right before its row was taken (P with v already covered, and the
+// K planes), so that a dead end restores the deepest frame with untried
+// rows in one step, whatever the number of frames above it.
 template <int K>
 using Planes = uint64_t __attribute__((ext_vector_type(K)));
+template <int K>
+using LaneWords = uint32_t __attribute__((ext_vector_type(K)));
 
 template <int K>
 struct RegState {
   Planes<K> O;
-  uint64_t P, nodes, h;
+  uint64_t P, A, nodes, h;
   uint32_t depth, row_in;
   int32_t status;
-  uint32_t fr, ll, lh;
+  uint32_t fr, sp_lo, sp_hi;
+  LaneWords<K> so_lo, so_hi;
 };
 
 template <int K>
@@ -98,14 +108,20 @@ __device__ __forceinline__ void reg_init(RegState<K>& s, int32_t n, int32_t k) {
 #pragma unroll
   for (int c = 0; c < K; ++c) s.O[c] = c < k ? all : 0ull;
   s.P = all;
+  s.A = 0;
   s.nodes = 0;
   s.h = kFnvOffset;
   s.depth = 0;
   s.row_in = kNone;
   s.status = -1;
   s.fr = 0;
-  s.ll = 0;
-  s.lh = 0;
+  s.sp_lo = 0;
+  s.sp_hi = 0;
+#pragma unroll
+  for (int c = 0; c < K; ++c) {
+    s.so_lo[c] = 0;
+    s.so_hi[c] = 0;
+  }
 }
 
 // c == j ? a : b on uniform 64-bit words (one compare, one 64-bit select).
@@ -113,22 +129,6 @@ __device__ __forceinline__ uint64_t sel_eq(uint32_t c, int j, uint64_t a, uint64
   uint64_t r;
   asm("s_cmp_eq_u32 %1, %2\n\ts_cselect_b64 %0, %3, %4" : "=s"(r) : "s"(c), "i"(j), "s"(a), "s"(b) : "scc");
   return r;
-}
-
-// Plane c (c < K), as a select chain: no indexed register access.
-template <int K>
-__device__ __forceinline__ uint64_t plane(const Planes<K>& O, uint32_t c) {
-  uint64_t r = O[0];
-#pragma unroll
-  for (int j = 1; j < K; ++j) r = sel_eq(c, j, O[j], r);
-  return r;
-}
-
-// Plane c := x.
-template <int K>
-__device__ __forceinline__ void set_plane(Planes<K>& O, uint32_t c, uint64_t x) {
-#pragma unroll
-  for (int j = 0; j < K; ++j) O[j] = sel_eq(c, j, x, O[j]);
 }
 
 // Open colors of node v (the rows of column v), bit c for color c.
@@ -152,11 +152,14 @@ __device__ __forceinline__ uint64_t narrow(uint64_t cand, uint64_t bits) {
   return r;
 }
 
-// Count-bit planes of the row counts: cnt[b] holds bit b of every column's
-// count (the number of color planes holding it).
+// Uncovered columns of the smallest row count (every column of P has at
+// least one row).  ge2 receives the columns with two rows or more.  The row
+// counts are added bit-sliced: cnt[b] holds bit b of every column's count.
 template <int K>
-__device__ __forceinline__ void count_planes(const Planes<K>& O, uint64_t (&cnt)[bit_width(K)]) {
+__device__ __forceinline__ uint64_t min_count_columns(const Planes<K>& O, const uint64_t P,
+                                                      uint64_t& ge2) {
   constexpr int NB = bit_width(K);
+  uint64_t cnt[NB];
 #pragma unroll
   for (int b = 0; b < NB; ++b) cnt[b] = 0;
 #pragma unroll
@@ -171,14 +174,9 @@ __device__ __forceinline__ void count_planes(const Planes<K>& O, uint64_t (&cnt)
       carry = t;
     }
   }
-}
-
-// Uncovered columns of the smallest row count (all of P has count >= 1).
-template <int K>
-__device__ __forceinline__ uint64_t min_count_columns(const Planes<K>& O, const uint64_t P) {
-  constexpr int NB = bit_width(K);
-  uint64_t cnt[NB];
-  count_planes(O, cnt);
+  ge2 = 0;
+#pragma unroll
+  for (int b = 1; b < NB; ++b) ge2 |= cnt[b];
   uint64_t cand = P;
 #pragma unroll
   for (int b = NB - 1; b >= 0; --b) cand = narrow(cand, cnt[b]);
@@ -196,86 +194,119 @@ __device__ __forceinline__ uint32_t first_color(const Planes<K>& O, const uint32
   return c;
 }
 
-// Takes row (v, c) at the current depth: v's neighbours lose color c; the
-// frame and the undo set go to lane `depth`.
+// Cover of row (v, c) on the planes: v's neighbours lose color c.
 template <int K>
-__device__ __forceinline__ void take_row(RegState<K>& s, const uint64_t nbv, const uint32_t v,
-                                         const uint32_t c) {
-  const uint64_t oc = plane(s.O, c);
-  const uint64_t lost = oc & nbv;
-  set_plane(s.O, c, oc & ~nbv);
-  s.fr = wrlane(s.fr, s.depth, v | (c << 8));
-  s.ll = wrlane(s.ll, s.depth, (uint32_t)lost);
-  s.lh = wrlane(s.lh, s.depth, (uint32_t)(lost >> 32));
-  ++s.depth;
+__device__ __forceinline__ void cover(Planes<K>& O, const uint32_t c, const uint64_t nbv) {
+#pragma unroll
+  for (int j = 0; j < K; ++j) O[j] = sel_eq(c, j, O[j] & ~nbv, O[j]);
 }
 
-// Pops frames down to `floor` until one has a next row, restoring the
-// planes and uncovering columns on the way.  Returns the next color (v set
-// to that frame's column, depth to its depth), or kNone when the subtree
-// is exhausted.  After a frame's undo set is restored the planes are as
-// they were when its column was chosen, so the untried rows of that column
-// are its open colors above the row taken.
+// Bits 0 .. d-1 (d <= 64).
+__device__ __forceinline__ uint64_t below(uint32_t d) { return d >= 64u ? ~0ull : (1ull << d) - 1ull; }
+
+// Sets bit d of A to `on` (0 or 1), without a branch.
+__device__ __forceinline__ uint64_t with_bit(uint64_t A, uint32_t d, uint64_t on) {
+  return (A & ~(1ull << d)) | (on << d);
+}
+
+// Takes row (v, c) at the current depth (column v already removed from P):
+// snapshot of P and the planes and the frame to lane `depth`, then the
+// cover; `alt` says whether column v has rows after c.
 template <int K>
-__device__ __forceinline__ uint32_t backtrack(RegState<K>& s, uint32_t& v, const uint32_t floor) {
-  while (s.depth != floor) {
-    --s.depth;
-    const uint32_t f = rdlane(s.fr, s.depth);
-    const uint64_t lost = rdlane64(s.ll, s.lh, s.depth);
-    v = f & 0xffu;
-    const uint32_t cp = f >> 8;
-    set_plane(s.O, cp, plane(s.O, cp) | lost);
-    const uint32_t next = rows_of(s.O, v) & (0xfffffffeu << cp);
-    if (next) return (uint32_t)__builtin_ctz(next);
-    s.P |= 1ull << v;
+__device__ __forceinline__ void take_row(RegState<K>& s, const uint64_t nbv, const uint32_t v,
+                                         const uint32_t c, const uint64_t alt) {
+  const uint32_t d = s.depth;
+  s.sp_lo = wrlane(s.sp_lo, d, (uint32_t)s.P);
+  s.sp_hi = wrlane(s.sp_hi, d, (uint32_t)(s.P >> 32));
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    s.so_lo[j] = wrlane(s.so_lo[j], d, (uint32_t)s.O[j]);
+    s.so_hi[j] = wrlane(s.so_hi[j], d, (uint32_t)(s.O[j] >> 32));
   }
-  return kNone;
+  s.fr = wrlane(s.fr, d, v | (c << 8));
+  cover(s.O, c, nbv);
+  s.A = with_bit(s.A, d, alt);
+  s.depth = d + 1;
+}
+
+// Dead end: returns to the deepest frame above `floor` whose column has
+// untried rows and restores the state from before its row was taken (its
+// snapshot; the frames above it are dropped, which undoes their rows and
+// uncovers their columns).  Sets v, c to that column and its next row and
+// `alt` to whether more rows follow (1 or 0); returns false when no such
+// frame exists (the subtree below `floor` is exhausted).
+template <int K>
+__device__ __forceinline__ bool retreat(RegState<K>& s, const uint32_t floor, uint32_t& v,
+                                        uint32_t& c, uint64_t& alt) {
+  const uint64_t open = s.A & below(s.depth) & ~below(floor);
+  if (open == 0) {   // exhausted: every frame above the floor is dropped
+    s.depth = floor;
+    return false;
+  }
+  const uint32_t d = 63u - (uint32_t)__builtin_clzll(open);
+  const uint32_t f = rdlane(s.fr, d);
+  s.P = rdlane64(s.sp_lo, s.sp_hi, d);
+#pragma unroll
+  for (int j = 0; j < K; ++j) s.O[j] = rdlane64(s.so_lo[j], s.so_hi[j], d);
+  v = f & 0xffu;
+  const uint32_t cp = f >> 8;
+  const uint32_t R = rows_of(s.O, v);   // the rows of v when it was chosen
+  const uint32_t next = R & (0xfffffffeu << cp);
+  c = (uint32_t)__builtin_ctz(next);
+  alt = (next & (next - 1u)) != 0 ? 1ull : 0ull;
+  s.depth = d;
+  return true;
 }
 
 // Runs the search until it ends or `nodes` reaches stop_at (<= budget); a
 // stop short of the budget leaves status -1 and the state resumable at a
 // node boundary.  With floor > 0 the search is confined to the subtree of
-// the node at depth `floor` (backtracking never pops below it; exhausting
-// the subtree reports MPLD_INFEASIBLE).  nb_lo/nb_hi: lane v holds N(v).
-// Every lane of the wave must call it.
+// the node at depth `floor` (backtracking never returns above it;
+// exhausting the subtree reports MPLD_INFEASIBLE).  nb_lo/nb_hi: lane v
+// holds N(v).  Every lane of the wave must call it.
 template <bool TRACE, int K>
 __device__ __forceinline__ void reg_run(RegState<K>& s, const uint32_t nb_lo, const uint32_t nb_hi,
                                         const int32_t k, const uint64_t budget,
                                         const uint64_t stop_at, const uint32_t floor = 0) {
   int32_t status = -1;
-  for (;;) {
+  while (status < 0) {
     // ---- one search node
     if (s.nodes == stop_at) {
-      if (s.nodes == budget) status = MPLD_BUDGET_EXHAUSTED;
-      break;
+      if (s.nodes != budget) break;   // paused: resumable here
+      status = MPLD_BUDGET_EXHAUSTED;
+      continue;
     }
     ++s.nodes;
     if (s.P == 0) {
       if (TRACE) s.h = trace_node(s.h, s.depth, s.row_in, kNone, 0);
       status = MPLD_FEASIBLE;
-      break;
+      continue;
     }
     uint64_t any = s.O[0];
 #pragma unroll
     for (int j = 1; j < K; ++j) any |= s.O[j];
     const uint64_t zero = s.P & ~any;
     uint32_t v, c;
+    uint64_t alt;
     if (__builtin_expect(zero == 0, 1)) {
       // every uncovered column has rows: cover the one of fewest rows and
       // take its first row
-      v = low_bit(min_count_columns(s.O, s.P));
+      uint64_t ge2;
+      v = low_bit(min_count_columns(s.O, s.P, ge2));
       if (TRACE) s.h = trace_node(s.h, s.depth, s.row_in, v, (uint32_t)__popc(rows_of(s.O, v)));
       c = first_color(s.O, v);
+      alt = (ge2 >> v) & 1ull;
       asm("s_bitset0_b64 %0, %1" : "+s"(s.P) : "s"(v));   // cover column v
     } else {
       // a column without rows (the first by index is the one chosen): dead end
-      if (TRACE)
-        s.h = trace_node(s.h, s.depth, s.row_in, low_bit(zero), 0);
-      c = backtrack(s, v, floor);
-      if (c == kNone) { status = MPLD_INFEASIBLE; break; }
+      if (TRACE) s.h = trace_node(s.h, s.depth, s.row_in, low_bit(zero), 0);
+      if (!retreat(s, floor, v, c, alt)) {
+        status = MPLD_INFEASIBLE;
+        continue;
+      }
     }
     // ---- include row (v, c)
-    take_row(s, rdlane64(nb_lo, nb_hi, v), v, c);
+    take_row(s, rdlane64(nb_lo, nb_hi, v), v, c, alt);
     s.row_in = v * (uint32_t)k + c;
   }
   s.status = status;
@@ -288,8 +319,9 @@ __device__ __forceinline__ void reg_finish(const RegState<K>& s, int32_t n,
                                            int8_t* __restrict__ colors,
                                            DevRecord* __restrict__ rec) {
   const uint32_t lane = __lane_id();
+  const uint32_t depth = uniform(s.depth);
   if (s.status == MPLD_FEASIBLE) {
-    if (lane < s.depth && (s.fr & 0xffu) < (uint32_t)n)
+    if (lane < depth && (s.fr & 0xffu) < (uint32_t)n)
       colors[s.fr & 0xffu] = (int8_t)((s.fr >> 8) & 0xffu);
   } else if (lane < (uint32_t)n) {
     colors[lane] = -1;
@@ -298,7 +330,7 @@ __device__ __forceinline__ void reg_finish(const RegState<K>& s, int32_t n,
   // the queue pop's "lane 0" condition, or the compiler can thread the two
   // across the loop back-edge and split the wave at the pop.
   rec->status = s.status;
-  rec->depth = s.status == MPLD_INFEASIBLE ? 0 : (int32_t)s.depth;
+  rec->depth = s.status == MPLD_INFEASIBLE ? 0 : (int32_t)depth;
   rec->nodes = s.nodes;
   rec->hash = s.h;
 }
@@ -320,29 +352,37 @@ __device__ __forceinline__ void solve_reg(const int32_t n, const int32_t k, cons
 }
 
 // Resumable state in device memory (kRegStateBytes per component): the
-// uniform head (counters at 0, planes at 32), then the three lane arrays.
+// uniform head (counters at 0, planes at 64), then 64-lane arrays of u32:
+// frames, P snapshot (low, high), then per plane its snapshot (low, high).
 struct RegStateHead {
-  uint64_t P, nodes, h;
+  uint64_t P, A, nodes, h;
   uint32_t depth, row_in;
 };
-static_assert(sizeof(RegStateHead) == 32, "state head is 32 bytes");
-static_assert(kRegStateBytes >= 128 + 64 * 12, "state layout");
+static_assert(sizeof(RegStateHead) == 40, "state head is 40 bytes");
+static_assert(kRegStateBytes >= 128 + 256 * (3 + 2 * 8), "state layout");
 
 template <int K>
 __device__ __forceinline__ void reg_save(const RegState<K>& s, uint8_t* base) {
   const uint32_t lane = __lane_id();
   RegStateHead* hd = reinterpret_cast<RegStateHead*>(base);
   hd->P = s.P;   // same value from every lane
+  hd->A = s.A;
   hd->nodes = s.nodes;
   hd->h = s.h;
   hd->depth = s.depth;
   hd->row_in = s.row_in;
-  uint64_t* planes = reinterpret_cast<uint64_t*>(base + 32);
+  uint64_t* planes = reinterpret_cast<uint64_t*>(base + 64);
 #pragma unroll
   for (int c = 0; c < K; ++c) planes[c] = s.O[c];
-  reinterpret_cast<uint32_t*>(base + 128)[lane] = s.fr;
-  reinterpret_cast<uint32_t*>(base + 128 + 256)[lane] = s.ll;
-  reinterpret_cast<uint32_t*>(base + 128 + 512)[lane] = s.lh;
+  uint32_t* lanes = reinterpret_cast<uint32_t*>(base + 128);
+  lanes[lane] = s.fr;
+  lanes[64 + lane] = s.sp_lo;
+  lanes[128 + lane] = s.sp_hi;
+#pragma unroll
+  for (int c = 0; c < K; ++c) {
+    lanes[(3 + 2 * c) * 64 + lane] = s.so_lo[c];
+    lanes[(4 + 2 * c) * 64 + lane] = s.so_hi[c];
+  }
 }
 
 template <int K>
@@ -350,16 +390,23 @@ __device__ __forceinline__ void reg_load(RegState<K>& s, const uint8_t* base) {
   const uint32_t lane = __lane_id();
   const RegStateHead* hd = reinterpret_cast<const RegStateHead*>(base);
   s.P = uniform64(hd->P);
+  s.A = uniform64(hd->A);
   s.nodes = uniform64(hd->nodes);
   s.h = uniform64(hd->h);
   s.depth = uniform(hd->depth);
   s.row_in = uniform(hd->row_in);
-  const uint64_t* planes = reinterpret_cast<const uint64_t*>(base + 32);
+  const uint64_t* planes = reinterpret_cast<const uint64_t*>(base + 64);
 #pragma unroll
   for (int c = 0; c < K; ++c) s.O[c] = uniform64(planes[c]);
-  s.fr = reinterpret_cast<const uint32_t*>(base + 128)[lane];
-  s.ll = reinterpret_cast<const uint32_t*>(base + 128 + 256)[lane];
-  s.lh = reinterpret_cast<const uint32_t*>(base + 128 + 512)[lane];
+  const uint32_t* lanes = reinterpret_cast<const uint32_t*>(base + 128);
+  s.fr = lanes[lane];
+  s.sp_lo = lanes[64 + lane];
+  s.sp_hi = lanes[128 + lane];
+#pragma unroll
+  for (int c = 0; c < K; ++c) {
+    s.so_lo[c] = lanes[(3 + 2 * c) * 64 + lane];
+    s.so_hi[c] = lanes[(4 + 2 * c) * 64 + lane];
+  }
   s.status = -1;
 }
 
@@ -451,7 +498,8 @@ __global__ __launch_bounds__(256) void reg_tick_kernel(
 
 // Rebuilds the search state at the end of a path of rows from the root:
 // cover each row's column and take the row, in order (the same steps the
-// sequential search made on the way down, so the planes and frames match).
+// sequential search made on the way down, so planes, snapshots and the
+// untried-rows set match).
 template <int K>
 __device__ __forceinline__ void reg_replay(RegState<K>& s, const uint32_t nb_lo,
                                            const uint32_t nb_hi, const int32_t k,
@@ -459,8 +507,9 @@ __device__ __forceinline__ void reg_replay(RegState<K>& s, const uint32_t nb_lo,
   for (uint32_t j = 0; j < d; ++j) {
     const uint32_t vc = uniform(rows[j]);
     const uint32_t v = vc & 0xffu, c = vc >> 8;
+    const uint32_t R = rows_of(s.O, v);
     s.P &= ~(1ull << v);
-    take_row(s, rdlane64(nb_lo, nb_hi, v), v, c);
+    take_row(s, rdlane64(nb_lo, nb_hi, v), v, c, (R & (0xfffffffeu << c)) != 0 ? 1ull : 0ull);
     s.row_in = v * (uint32_t)k + c;
   }
 }
@@ -500,6 +549,7 @@ __device__ __forceinline__ int32_t reg_enumerate(RegState<K>& s, const uint32_t 
   };
   for (;;) {
     uint32_t v = 0, c = 0;
+    uint64_t alt = 0;
     bool back;
     if (s.depth == limit) {
       emit(0);        // a subtask root: leave it to its own task
@@ -517,19 +567,18 @@ __device__ __forceinline__ int32_t reg_enumerate(RegState<K>& s, const uint32_t 
       for (int j = 1; j < K; ++j) any |= s.O[j];
       back = (s.P & ~any) != 0;
       if (!back) {
-        v = low_bit(min_count_columns(s.O, s.P));
+        uint64_t ge2;
+        v = low_bit(min_count_columns(s.O, s.P, ge2));
         c = first_color(s.O, v);
+        alt = (ge2 >> v) & 1ull;
         s.P &= ~(1ull << v);
       }
     }
-    if (back) {
-      c = backtrack(s, v, d);
-      if (c == kNone) {
-        emit(1);
-        break;
-      }
+    if (back && !retreat(s, d, v, c, alt)) {
+      emit(1);
+      break;
     }
-    take_row(s, rdlane64(nb_lo, nb_hi, v), v, c);
+    take_row(s, rdlane64(nb_lo, nb_hi, v), v, c, alt);
   }
   return items;
 }
@@ -596,17 +645,16 @@ hipError_t launch_fill_i32(int32_t* p, int32_t count, int32_t value, hipStream_t
   return hipGetLastError();
 }
 
-// Number of color planes compiled for k colors: 2, 3 and 4 exactly, 8 for
-// k = 5..8 (the planes past k stay empty).
-static int planes_for(int k) { return k <= 4 ? k : 8; }
-
-// Calls f(std::integral_constant<int, K>) for the plane count of k.
+// Calls f(std::integral_constant<int, K>) with K = k color planes.
 template <class F>
 static void with_planes(int k, F&& f) {
-  switch (planes_for(k)) {
+  switch (k) {
     case 2: f(std::integral_constant<int, 2>()); break;
     case 3: f(std::integral_constant<int, 3>()); break;
     case 4: f(std::integral_constant<int, 4>()); break;
+    case 5: f(std::integral_constant<int, 5>()); break;
+    case 6: f(std::integral_constant<int, 6>()); break;
+    case 7: f(std::integral_constant<int, 7>()); break;
     default: f(std::integral_constant<int, 8>()); break;
   }
 }
