@@ -187,7 +187,7 @@ def main() -> int:
                     help="search heavy components as parallel subtrees (exact sequential counts)")
     ap.add_argument("--heavy-caps", type=str, default="",
                     help="with --split: first-pass cap,round cap[,levels] of the heavy engine")
-    ap.add_argument("--launch", choices=["graph", "direct"], default="graph",
+    ap.add_argument("--launch", choices=["graph", "direct"], default="direct",
                     help="batched solve: replay the captured HIP graph or launch directly")
     ap.add_argument("--kernel-reps", type=int, default=50,
                     help="direct launches timed one by one for the kernel duration")
@@ -301,7 +301,7 @@ def main() -> int:
                   + 4 * int(np.sum((comps["size"] + 2 + 2 * comps["num_edges"])[comps["size"] > 64])))
     achieved = algo_bytes / (kernel_ms * 1e-3) / 1e9
     traffic = None
-    prof = os.path.join(ROOT, "profiles", f"traffic_{w.name}.json")
+    prof = os.path.join(ROOT, "profiles", f"reg_batched_kernel_{w.name}_traffic.json")
     if os.path.exists(prof):
         with open(prof) as fh:
             t = json.load(fh)

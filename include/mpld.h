@@ -198,8 +198,9 @@ int32_t mpld_decompose(mpld_context* ctx, const mpld_graph* g,
  * mpld_batch_create runs the host front-end (simplification, sub-graphs,
  * exact-cover packing) and uploads the packed image to device memory.
  * mpld_batch_solve enqueues the whole device search on the context stream
- * and does not wait: by default the tiered persistent kernels, captured
- * once into a HIP graph and replayed (MPLD_DIRECT in `flags` launches them
+ * and does not wait: the tiered persistent kernels, launched directly or,
+ * when the batch's schedule says so (mpld_tune.use_graph), captured once
+ * into a HIP graph and replayed (MPLD_DIRECT in `flags` always launches
  * directly); with MPLD_PLAIN one launch per component.  Queue counters
  * reset themselves at the end of each launch, so no memset is enqueued.
  * Per-component results stay on the device.  mpld_batch_result waits, copies the results back and runs

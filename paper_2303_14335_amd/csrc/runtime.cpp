@@ -156,6 +156,16 @@ void device_upload(mpld_context* ctx, const Image& im, DeviceBatch& db, const Tu
   ordered.clear();
   ordered.reserve(db.host_queue.size());
   for (int32_t c : db.host_queue) ordered.push_back(im.desc[c]);
+  // register-tier masks in launch order too, so that neighbouring items
+  // (handled by the same XCD) read neighbouring cache lines
+  std::vector<uint64_t> qmasks;
+  qmasks.reserve(im.masks.size());
+  for (int32_t i = 0; i < db.n_reg; ++i) {
+    DevDesc& d = ordered[(size_t)i];
+    const int64_t from = d.nbr_off;
+    d.nbr_off = (int64_t)qmasks.size();
+    qmasks.insert(qmasks.end(), im.masks.begin() + from, im.masks.begin() + from + d.n);
+  }
 
   db.desc.alloc(ctx, sizeof(DevDesc) * ordered.size());
   db.masks.alloc(ctx, sizeof(uint64_t) * im.masks.size());
@@ -176,8 +186,8 @@ void device_upload(mpld_context* ctx, const Image& im, DeviceBatch& db, const Tu
   if (!ordered.empty())
     check_hip(hipMemcpyAsync(db.desc.p, ordered.data(), sizeof(DevDesc) * ordered.size(),
                              hipMemcpyHostToDevice, s), "upload descriptors");
-  if (!im.masks.empty())
-    check_hip(hipMemcpyAsync(db.masks.p, im.masks.data(), sizeof(uint64_t) * im.masks.size(),
+  if (!qmasks.empty())
+    check_hip(hipMemcpyAsync(db.masks.p, qmasks.data(), sizeof(uint64_t) * qmasks.size(),
                              hipMemcpyHostToDevice, s), "upload masks");
   if (!im.adj32.empty())
     check_hip(hipMemcpyAsync(db.adj32.p, im.adj32.data(), sizeof(uint32_t) * im.adj32.size(),

@@ -120,7 +120,7 @@ constexpr int64_t kLdsSmallLimit = 64 * 1024;
 struct Tune {
   int32_t waves_per_block = 4;   // register tier workgroup = 64 * waves
   int32_t max_blocks = 0;        // register tier grid cap; 0 = one wave per component
-  int32_t use_graph = 1;         // replay a captured HIP graph
+  int32_t use_graph = 0;         // replay a captured HIP graph (off: direct launches are cheaper for the usual one or two kernels)
   int32_t order = 0;             // 0 largest first, 1 smallest first
   int32_t giant_device = 0;      // giants on the device-wide tier instead of the big tier
   int32_t giant_min_nodes = 4096;

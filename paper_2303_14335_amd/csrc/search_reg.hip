@@ -410,6 +410,17 @@ __device__ __forceinline__ void reg_load(RegState<K>& s, const uint8_t* base) {
   s.status = -1;
 }
 
+// The hardware deals workgroups to the eight XCDs round-robin (block b to
+// XCD b % 8), and each XCD has its own L2.  Neighbouring items' descriptors
+// and masks share cache lines, so blocks are renumbered to give each XCD one
+// contiguous range of items (a bijection on 0 .. gridDim.x - 1).
+__device__ __forceinline__ uint32_t xcd_block() {
+  constexpr uint32_t kXcds = 8;
+  const uint32_t G = gridDim.x, b = blockIdx.x;
+  const uint32_t x = b % kXcds, i = b / kXcds, q = G / kXcds, r = G % kXcds;
+  return x * q + (x < r ? x : r) + i;
+}
+
 // Persistent batched kernel.  Wave w first takes item w of its tier's
 // descriptor list (no atomic); while the grid has fewer waves than items,
 // waves then pop item gw + atomicAdd(counter, 1).  Every wave fails exactly
@@ -423,7 +434,7 @@ __global__ __launch_bounds__(256) void reg_batched_kernel(
     uint64_t cap) {
   const uint32_t wpb = blockDim.x >> 6;   // waves per workgroup
   const int32_t gw = (int32_t)(gridDim.x * wpb);
-  int32_t item = (int32_t)uniform(blockIdx.x * wpb + (threadIdx.x >> 6));
+  int32_t item = (int32_t)uniform(xcd_block() * wpb + (threadIdx.x >> 6));
   while (item < qlen) {
     const DevDesc d = descs[item];
     solve_reg<TRACE, K>(d.n, d.k, (uint64_t)d.budget, masks + d.nbr_off, colors + d.out_off,
@@ -460,7 +471,7 @@ __global__ __launch_bounds__(256) void reg_tick_kernel(
     const uint64_t* __restrict__ arena64, int8_t* __restrict__ arena8, uint64_t slice,
     DevRecord* __restrict__ tick_out) {
   const int32_t gw = (int32_t)gridDim.x * 4;
-  int32_t item = (int32_t)uniform(blockIdx.x * 4u + (threadIdx.x >> 6));
+  int32_t item = (int32_t)uniform(xcd_block() * 4u + (threadIdx.x >> 6));
   while (item < len) {
     const uint32_t entry = uniform((uint32_t)list[item]);
     const int32_t slot = (int32_t)(entry & 0x7fffffffu);
@@ -593,7 +604,7 @@ __global__ __launch_bounds__(256) void reg_split_kernel(
     SplitItem* __restrict__ items, int8_t* __restrict__ sols) {
   const uint32_t wpb = blockDim.x >> 6;
   const int32_t gw = (int32_t)(gridDim.x * wpb);
-  int32_t t = (int32_t)uniform(blockIdx.x * wpb + (threadIdx.x >> 6));
+  int32_t t = (int32_t)uniform(xcd_block() * wpb + (threadIdx.x >> 6));
   const uint32_t lane = __lane_id();
   while (t < ntasks) {
     const SplitTask* task = tasks + t;

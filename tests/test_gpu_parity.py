@@ -152,6 +152,26 @@ def test_config3_giant_device_tier(ctx):
     compare_decomposition(got, ref)
 
 
+def test_graph_replays_match_direct(ctx):
+    """The captured HIP graph (schedule use_graph = 1), replayed several times
+    with results read back in between, gives the direct launches' result."""
+    import paper_2303_14335_amd as mp
+    w, rects = graph_of(2, 40000)
+    say("graph replays, 40k rects of config 2")
+    g = mp.mpld_build_graph(rects, w.dmin_nm, w.split_len_nm)
+    b = mp.Batch(ctx, g, w.k, 20000, SIMPLIFY | TRACE)
+    b.solve(direct=True)
+    ref = b.result()
+    b.set_tune(use_graph=1)
+    for rep in range(4):
+        b.solve()
+        got = b.result()
+        for f in ref.components.dtype.names:
+            assert np.array_equal(got.components[f], ref.components[f]), (rep, f)
+        assert np.array_equal(got.colors, ref.colors), rep
+    b.close()
+
+
 def test_plain_equals_batched_and_trace_off(ctx):
     import paper_2303_14335_amd as mp
     w, rects = graph_of(2, 40000)
