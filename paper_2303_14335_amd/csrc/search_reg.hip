@@ -271,13 +271,13 @@ __device__ __forceinline__ void reg_run(RegState<K>& s, const uint32_t nb_lo, co
   int32_t status = -1;
   while (status < 0) {
     // ---- one search node
-    if (s.nodes == stop_at) {
+    if (__builtin_expect(s.nodes == stop_at, 0)) {
       if (s.nodes != budget) break;   // paused: resumable here
       status = MPLD_BUDGET_EXHAUSTED;
       continue;
     }
     ++s.nodes;
-    if (s.P == 0) {
+    if (__builtin_expect(s.P == 0, 0)) {
       if (TRACE) s.h = trace_node(s.h, s.depth, s.row_in, kNone, 0);
       status = MPLD_FEASIBLE;
       continue;
