@@ -235,7 +235,7 @@ int32_t mpld_batch_get_info(mpld_batch* b, mpld_batch_info* info) {
     info->num_global = b->db.n_big;
     info->core_nodes = b->im.total_nodes;
     info->max_size = b->im.max_size;
-    info->image_bytes = (int64_t)(b->db.desc.bytes + b->db.masks.bytes + b->db.adj32.bytes);
+    info->image_bytes = (int64_t)(b->db.desc.bytes + b->db.regitems.bytes + b->db.adj32.bytes);
     info->core_edges = b->im.core_edges;
     info->last_search_ms = b->db.last_search_ms;
     info->last_total_ms = b->db.last_total_ms;

@@ -25,6 +25,16 @@ struct DevDesc {
 };
 static_assert(sizeof(DevDesc) == 32, "descriptor is 32 bytes");
 
+// Register-tier work item (n <= 64): the descriptor and the neighbour masks
+// in one 544-byte record, stored in launch order (mask v = the conflict
+// neighbours of local node v; zero past n).  A wave issues the loads of
+// both at once instead of reading the descriptor to find the masks.
+struct RegItem {
+  DevDesc d;
+  uint64_t nb[64];
+};
+static_assert(sizeof(RegItem) == 544, "register item is 544 bytes");
+
 // One record per component (24 bytes), written by the search.
 struct DevRecord {
   int32_t status;   // MPLD_FEASIBLE / MPLD_INFEASIBLE / MPLD_BUDGET_EXHAUSTED

@@ -156,19 +156,17 @@ void device_upload(mpld_context* ctx, const Image& im, DeviceBatch& db, const Tu
   ordered.clear();
   ordered.reserve(db.host_queue.size());
   for (int32_t c : db.host_queue) ordered.push_back(im.desc[c]);
-  // register-tier masks in launch order too, so that neighbouring items
-  // (handled by the same XCD) read neighbouring cache lines
-  std::vector<uint64_t> qmasks;
-  qmasks.reserve(im.masks.size());
+  // register-tier items: descriptor and masks together, in launch order
+  std::vector<RegItem> items((size_t)db.n_reg);
   for (int32_t i = 0; i < db.n_reg; ++i) {
-    DevDesc& d = ordered[(size_t)i];
-    const int64_t from = d.nbr_off;
-    d.nbr_off = (int64_t)qmasks.size();
-    qmasks.insert(qmasks.end(), im.masks.begin() + from, im.masks.begin() + from + d.n);
+    RegItem& it = items[(size_t)i];
+    it.d = ordered[(size_t)i];
+    std::memset(it.nb, 0, sizeof(it.nb));
+    std::memcpy(it.nb, im.masks.data() + it.d.nbr_off, sizeof(uint64_t) * (size_t)it.d.n);
   }
 
   db.desc.alloc(ctx, sizeof(DevDesc) * ordered.size());
-  db.masks.alloc(ctx, sizeof(uint64_t) * im.masks.size());
+  db.regitems.alloc(ctx, sizeof(RegItem) * items.size());
   db.adj32.alloc(ctx, sizeof(uint32_t) * im.adj32.size());
   db.counters.alloc(ctx, sizeof(int32_t) * 8);
   db.recs.alloc(ctx, sizeof(DevRecord) * im.desc.size());
@@ -186,9 +184,9 @@ void device_upload(mpld_context* ctx, const Image& im, DeviceBatch& db, const Tu
   if (!ordered.empty())
     check_hip(hipMemcpyAsync(db.desc.p, ordered.data(), sizeof(DevDesc) * ordered.size(),
                              hipMemcpyHostToDevice, s), "upload descriptors");
-  if (!qmasks.empty())
-    check_hip(hipMemcpyAsync(db.masks.p, qmasks.data(), sizeof(uint64_t) * qmasks.size(),
-                             hipMemcpyHostToDevice, s), "upload masks");
+  if (!items.empty())
+    check_hip(hipMemcpyAsync(db.regitems.p, items.data(), sizeof(RegItem) * items.size(),
+                             hipMemcpyHostToDevice, s), "upload register items");
   if (!im.adj32.empty())
     check_hip(hipMemcpyAsync(db.adj32.p, im.adj32.data(), sizeof(uint32_t) * im.adj32.size(),
                              hipMemcpyHostToDevice, s), "upload adjacency");
@@ -200,7 +198,7 @@ void device_upload(mpld_context* ctx, const Image& im, DeviceBatch& db, const Tu
 
 static void enqueue_batched(DeviceBatch& db, bool trace, uint64_t cap, hipStream_t s) {
   const auto* desc = db.desc.as<DevDesc>();
-  const auto* masks = db.masks.as<uint64_t>();
+  const auto* items = db.regitems.as<RegItem>();
   const auto* adj = db.adj32.as<uint32_t>();
   auto* cnt = db.counters.as<int32_t>();
   auto* recs = db.recs.as<DevRecord>();
@@ -208,7 +206,7 @@ static void enqueue_batched(DeviceBatch& db, bool trace, uint64_t cap, hipStream
   auto* gstack = db.gstack.as<uint64_t>();
   db.launches = 0;
   if (db.n_reg) {
-    check_hip(launch_reg_batched(trace, db.k, db.grid_reg, db.tune.waves_per_block, desc, masks,
+    check_hip(launch_reg_batched(trace, db.k, db.grid_reg, db.tune.waves_per_block, items,
                                  db.n_reg, cnt, recs, colors, cap, s),
               "register-tier launch");
     ++db.launches;
@@ -374,7 +372,7 @@ static void heavy_engine(DeviceBatch& db) {
               "heavy: tasks");
     const int grid = std::max(1, std::min((nt + 3) / 4, ctx->num_cus * ctx->reg_blocks_per_cu));
     check_hip(launch_reg_split(db.k, grid, db.sp_tasks.as<SplitTask>(), nt, db.counters.as<int32_t>() + 6,
-                               db.desc.as<DevDesc>(), db.masks.as<uint64_t>(), (uint64_t)db.tune.heavy_round_cap,
+                               db.regitems.as<RegItem>(), (uint64_t)db.tune.heavy_round_cap,
                                (uint32_t)levels, max_items, db.sp_results.as<SplitResult>(),
                                db.sp_items.as<SplitItem>(), db.sp_sols.as<int8_t>(), s),
               "heavy: split launch");
@@ -458,7 +456,7 @@ static void heavy_engine(DeviceBatch& db) {
     const DevDesc& d = db.host_desc[hc.item];
     if (hc.rerun) {
       ++db.sp_reruns;
-      check_hip(launch_reg_single(false, db.k, db.desc.as<DevDesc>(), db.masks.as<uint64_t>(),
+      check_hip(launch_reg_single(false, db.k, db.regitems.as<RegItem>(),
                                   hc.item, db.recs.as<DevRecord>(), db.colors.as<int8_t>(), s),
                 "heavy: sequential re-run");
       continue;
@@ -483,7 +481,7 @@ void device_solve(DeviceBatch& db, uint32_t flags) {
   if (flags & MPLD_PLAIN) {
     // one launch per component, same search code
     const auto* desc = db.desc.as<DevDesc>();
-    const auto* masks = db.masks.as<uint64_t>();
+    const auto* items = db.regitems.as<RegItem>();
     const auto* adj = db.adj32.as<uint32_t>();
     auto* recs = db.recs.as<DevRecord>();
     auto* colors = db.colors.as<int8_t>();
@@ -493,7 +491,7 @@ void device_solve(DeviceBatch& db, uint32_t flags) {
     for (int32_t i = 0; i < (int32_t)db.host_queue.size(); ++i) {
       hipError_t e;
       if (i < db.n_reg)
-        e = launch_reg_single(trace, db.k, desc, masks, i, recs, colors, s);
+        e = launch_reg_single(trace, db.k, items, i, recs, colors, s);
       else if (i < db.n_reg + db.n_lds)
         e = launch_lds_single(trace, false, db.lds_small, desc, adj, i, nullptr, recs, colors, s);
       else if (i < db.n_reg + db.n_lds + db.n_big)

@@ -16,16 +16,16 @@ namespace mpld {
 // k: the batch's mask count (every component of a batch shares it).
 // wpb: waves per workgroup (1..4); cap < budget stops components after cap
 // nodes (status -1, for the heavy-component engine).
-hipError_t launch_reg_batched(bool trace, int k, int grid, int wpb, const DevDesc* descs,
-                              const uint64_t* masks, int32_t qlen, int32_t* counter,
-                              DevRecord* recs, int8_t* colors, uint64_t cap, hipStream_t s);
+hipError_t launch_reg_batched(bool trace, int k, int grid, int wpb, const RegItem* items,
+                              int32_t qlen, int32_t* counter, DevRecord* recs, int8_t* colors,
+                              uint64_t cap, hipStream_t s);
 // Heavy-component engine: explore / split subtree tasks.
 hipError_t launch_reg_split(int k, int grid, const SplitTask* tasks, int32_t ntasks,
-                            int32_t* counter, const DevDesc* descs, const uint64_t* masks,
+                            int32_t* counter, const RegItem* regitems,
                             uint64_t cap, uint32_t levels, int32_t max_items,
                             SplitResult* results, SplitItem* items, int8_t* sols, hipStream_t s);
-hipError_t launch_reg_single(bool trace, int k, const DevDesc* descs, const uint64_t* masks,
-                             int32_t item, DevRecord* recs, int8_t* colors, hipStream_t s);
+hipError_t launch_reg_single(bool trace, int k, const RegItem* items, int32_t item,
+                             DevRecord* recs, int8_t* colors, hipStream_t s);
 int reg_batched_blocks_per_cu(bool trace);
 // Serving tick over register-tier components (see the kernel).
 hipError_t launch_reg_tick(bool trace, int k, int grid, const int32_t* list, int32_t len,
@@ -141,7 +141,7 @@ void image_finish(Image& im, int order = 0);
 // Device copy of an image plus its outputs and queue counters.
 struct DeviceBatch {
   mpld_context* ctx = nullptr;
-  DevBuf desc, masks, adj32, counters, recs, colors, gstack;  // desc in launch order
+  DevBuf desc, regitems, adj32, counters, recs, colors, gstack;  // desc in launch order
   DevBuf dev_keys, dev_stacks;      // device-wide tier
   DevBuf sp_tasks, sp_results, sp_items, sp_sols;   // heavy-component engine
   int64_t sp_rounds = 0, sp_tasks_run = 0, sp_heavy = 0, sp_reruns = 0;  // last solve's stats

@@ -335,20 +335,24 @@ __device__ __forceinline__ void reg_finish(const RegState<K>& s, int32_t n,
   rec->hash = s.h;
 }
 
-// cap < budget stops the search after `cap` nodes (status -1 in the record:
-// the component is left to the heavy-component engine).
+// Solves one register-tier item.  The descriptor (scalar loads) and the
+// lane's neighbour mask (a vector load) come from one record, so both
+// loads are in flight together.  cap < budget stops the search after `cap`
+// nodes (status -1 in the record: the component is left to the
+// heavy-component engine).
 template <bool TRACE, int K>
-__device__ __forceinline__ void solve_reg(const int32_t n, const int32_t k, const uint64_t budget,
-                                          const uint64_t* __restrict__ nbmask,
-                                          int8_t* __restrict__ colors,
-                                          DevRecord* __restrict__ rec,
+__device__ __forceinline__ void solve_reg(const RegItem* __restrict__ it,
+                                          int8_t* __restrict__ colors_base,
+                                          DevRecord* __restrict__ recs,
                                           const uint64_t cap = ~0ull) {
   const uint32_t lane = __lane_id();
-  const uint64_t nb = lane < (uint32_t)n ? nbmask[lane] : 0ull;
+  const uint64_t nb = it->nb[lane];   // zero past n
+  const DevDesc d = it->d;
+  const uint64_t budget = (uint64_t)d.budget;
   RegState<K> s;
-  reg_init(s, n, k);
-  reg_run<TRACE, K>(s, (uint32_t)nb, (uint32_t)(nb >> 32), k, budget, cap < budget ? cap : budget);
-  reg_finish(s, n, colors, rec);
+  reg_init(s, d.n, d.k);
+  reg_run<TRACE, K>(s, (uint32_t)nb, (uint32_t)(nb >> 32), d.k, budget, cap < budget ? cap : budget);
+  reg_finish(s, d.n, colors_base + d.out_off, recs + d.comp);
 }
 
 // Resumable state in device memory (kRegStateBytes per component): the
@@ -429,16 +433,13 @@ __device__ __forceinline__ uint32_t xcd_block() {
 // no memset.
 template <bool TRACE, int K>
 __global__ __launch_bounds__(256) void reg_batched_kernel(
-    const DevDesc* __restrict__ descs, const uint64_t* __restrict__ masks, int32_t qlen,
-    int32_t* __restrict__ counter, DevRecord* __restrict__ recs, int8_t* __restrict__ colors,
-    uint64_t cap) {
+    const RegItem* __restrict__ items, int32_t qlen, int32_t* __restrict__ counter,
+    DevRecord* __restrict__ recs, int8_t* __restrict__ colors, uint64_t cap) {
   const uint32_t wpb = blockDim.x >> 6;   // waves per workgroup
   const int32_t gw = (int32_t)(gridDim.x * wpb);
   int32_t item = (int32_t)uniform(xcd_block() * wpb + (threadIdx.x >> 6));
   while (item < qlen) {
-    const DevDesc d = descs[item];
-    solve_reg<TRACE, K>(d.n, d.k, (uint64_t)d.budget, masks + d.nbr_off, colors + d.out_off,
-                        recs + d.comp, cap);
+    solve_reg<TRACE, K>(items + item, colors, recs, cap);
     if (gw >= qlen) break;   // every item was handed out statically
     int32_t r = 0;
     if (__lane_id() == 0) r = atomicAdd(counter, 1);
@@ -450,13 +451,10 @@ __global__ __launch_bounds__(256) void reg_batched_kernel(
 
 // One component per launch (the plain solver): a single wave.
 template <bool TRACE, int K>
-__global__ __launch_bounds__(64) void reg_single_kernel(const DevDesc* __restrict__ descs,
-                                                        const uint64_t* __restrict__ masks,
+__global__ __launch_bounds__(64) void reg_single_kernel(const RegItem* __restrict__ items,
                                                         int32_t item, DevRecord* __restrict__ recs,
                                                         int8_t* __restrict__ colors) {
-  const DevDesc d = descs[item];
-  solve_reg<TRACE, K>(d.n, d.k, (uint64_t)d.budget, masks + d.nbr_off, colors + d.out_off,
-                      recs + d.comp);
+  solve_reg<TRACE, K>(items + item, colors, recs);
 }
 
 // Serving tick: every listed component advances by at most `slice` search
@@ -599,7 +597,7 @@ __device__ __forceinline__ int32_t reg_enumerate(RegState<K>& s, const uint32_t 
 template <int K>
 __global__ __launch_bounds__(256) void reg_split_kernel(
     const SplitTask* __restrict__ tasks, int32_t ntasks, int32_t* __restrict__ counter,
-    const DevDesc* __restrict__ descs, const uint64_t* __restrict__ masks, uint64_t cap,
+    const RegItem* __restrict__ regitems, uint64_t cap,
     uint32_t levels, int32_t max_items, SplitResult* __restrict__ results,
     SplitItem* __restrict__ items, int8_t* __restrict__ sols) {
   const uint32_t wpb = blockDim.x >> 6;
@@ -610,8 +608,8 @@ __global__ __launch_bounds__(256) void reg_split_kernel(
     const SplitTask* task = tasks + t;
     const int32_t it = (int32_t)uniform((uint32_t)task->item);
     const uint32_t d = uniform((uint32_t)task->depth);
-    const DevDesc dd = descs[it];
-    const uint64_t nb = lane < (uint32_t)dd.n ? masks[dd.nbr_off + lane] : 0ull;
+    const DevDesc dd = regitems[it].d;
+    const uint64_t nb = regitems[it].nb[lane];
     const uint32_t nb_lo = (uint32_t)nb, nb_hi = (uint32_t)(nb >> 32);
     int8_t* sol = sols + (uint64_t)t * 64;
     RegState<K> s;
@@ -670,33 +668,33 @@ static void with_planes(int k, F&& f) {
   }
 }
 
-hipError_t launch_reg_batched(bool trace, int k, int grid, int wpb, const DevDesc* descs,
-                              const uint64_t* masks, int32_t qlen, int32_t* counter,
-                              DevRecord* recs, int8_t* colors, uint64_t cap, hipStream_t s) {
+hipError_t launch_reg_batched(bool trace, int k, int grid, int wpb, const RegItem* items,
+                              int32_t qlen, int32_t* counter, DevRecord* recs, int8_t* colors,
+                              uint64_t cap, hipStream_t s) {
   if (qlen <= 0) return hipSuccess;
   if (wpb < 1 || wpb > 4) return hipErrorInvalidValue;
   with_planes(k, [&](auto kp) {
     constexpr int K = decltype(kp)::value;
     if (trace)
-      hipLaunchKernelGGL((reg_batched_kernel<true, K>), dim3(grid), dim3(64 * wpb), 0, s, descs,
-                         masks, qlen, counter, recs, colors, cap);
+      hipLaunchKernelGGL((reg_batched_kernel<true, K>), dim3(grid), dim3(64 * wpb), 0, s, items,
+                         qlen, counter, recs, colors, cap);
     else
-      hipLaunchKernelGGL((reg_batched_kernel<false, K>), dim3(grid), dim3(64 * wpb), 0, s, descs,
-                         masks, qlen, counter, recs, colors, cap);
+      hipLaunchKernelGGL((reg_batched_kernel<false, K>), dim3(grid), dim3(64 * wpb), 0, s, items,
+                         qlen, counter, recs, colors, cap);
   });
   return hipGetLastError();
 }
 
-hipError_t launch_reg_single(bool trace, int k, const DevDesc* descs, const uint64_t* masks,
-                             int32_t item, DevRecord* recs, int8_t* colors, hipStream_t s) {
+hipError_t launch_reg_single(bool trace, int k, const RegItem* items, int32_t item,
+                             DevRecord* recs, int8_t* colors, hipStream_t s) {
   with_planes(k, [&](auto kp) {
     constexpr int K = decltype(kp)::value;
     if (trace)
-      hipLaunchKernelGGL((reg_single_kernel<true, K>), dim3(1), dim3(64), 0, s, descs, masks,
-                         item, recs, colors);
+      hipLaunchKernelGGL((reg_single_kernel<true, K>), dim3(1), dim3(64), 0, s, items, item, recs,
+                         colors);
     else
-      hipLaunchKernelGGL((reg_single_kernel<false, K>), dim3(1), dim3(64), 0, s, descs, masks,
-                         item, recs, colors);
+      hipLaunchKernelGGL((reg_single_kernel<false, K>), dim3(1), dim3(64), 0, s, items, item, recs,
+                         colors);
   });
   return hipGetLastError();
 }
@@ -719,7 +717,7 @@ hipError_t launch_reg_tick(bool trace, int k, int grid, const int32_t* list, int
 }
 
 hipError_t launch_reg_split(int k, int grid, const SplitTask* tasks, int32_t ntasks,
-                            int32_t* counter, const DevDesc* descs, const uint64_t* masks,
+                            int32_t* counter, const RegItem* regitems,
                             uint64_t cap, uint32_t levels, int32_t max_items,
                             SplitResult* results, SplitItem* items, int8_t* sols, hipStream_t s) {
   if (ntasks <= 0) return hipSuccess;
@@ -727,7 +725,7 @@ hipError_t launch_reg_split(int k, int grid, const SplitTask* tasks, int32_t nta
   with_planes(k, [&](auto kp) {
     constexpr int K = decltype(kp)::value;
     hipLaunchKernelGGL((reg_split_kernel<K>), dim3(grid), dim3(256), 0, s, tasks, ntasks, counter,
-                       descs, masks, cap, levels, max_items, results, items, sols);
+                       regitems, cap, levels, max_items, results, items, sols);
   });
   return hipGetLastError();
 }
