@@ -235,6 +235,9 @@ void build_layout_graph(const mpld_rect* rects, int32_t n, int32_t dmin,
     gx = (maxx - minx) / cell + 1;
     gy = (maxy - miny) / cell + 1;
   }
+  // counting sort of the nodes by cell (ascending id within a cell), with a
+  // copy of their boxes in that order so that the 3x3 neighbourhood scans
+  // below read contiguous memory
   std::vector<int32_t> cell_of((size_t)nn), start((size_t)(gx * gy + 1), 0), sorted((size_t)nn);
   for (int32_t i = 0; i < nn; ++i) {
     const int64_t cx = (nd[i].x0 - minx) / cell, cy = (nd[i].y0 - miny) / cell;
@@ -244,35 +247,53 @@ void build_layout_graph(const mpld_rect* rects, int32_t n, int32_t dmin,
   for (int64_t c = 0; c < gx * gy; ++c) start[c + 1] += start[c];
   {
     std::vector<int32_t> fill(start.begin(), start.end() - 1);
-    for (int32_t i = 0; i < nn; ++i) sorted[fill[cell_of[i]]++] = i;  // ascending id per cell
+    for (int32_t i = 0; i < nn; ++i) sorted[fill[cell_of[i]]++] = i;
+  }
+  std::vector<mpld_rect> box((size_t)nn);
+  std::vector<int32_t> mate((size_t)nn);   // stitch partner of the node at sorted position p
+  for (int32_t p = 0; p < nn; ++p) {
+    box[p] = nd[sorted[p]];
+    mate[p] = partner[sorted[p]];
   }
   const int64_t d2 = (int64_t)dmin * dmin;
+  const int64_t ncell = gx * gy;
   const int T = std::min(threads > 0 ? threads : host_threads(), std::max(1, nn / 4096));
-  std::vector<std::vector<int32_t>> part((size_t)T);
+  // Thread t scans cell rows [gy*t/T, gy*(t+1)/T).  Every unordered pair is
+  // tested once: a node against the later nodes of its own cell and every
+  // node of the four forward neighbour cells (right; below-left, below,
+  // below-right).  Pairs are emitted as (min id, max id).
+  std::vector<std::vector<uint64_t>> part((size_t)T);
   auto work = [&](int t) {
-    const int32_t lo = (int32_t)((int64_t)nn * t / T), hi = (int32_t)((int64_t)nn * (t + 1) / T);
-    std::vector<int32_t>& e = part[t];
-    std::vector<int32_t> nbr;
-    for (int32_t a = lo; a < hi; ++a) {
-      const mpld_rect& ra = nd[a];
-      const int64_t cx = cell_of[a] % gx, cy = cell_of[a] / gx;
-      nbr.clear();
-      for (int64_t yy = std::max<int64_t>(0, cy - 1); yy <= std::min(gy - 1, cy + 1); ++yy)
-        for (int64_t xx = std::max<int64_t>(0, cx - 1); xx <= std::min(gx - 1, cx + 1); ++xx) {
-          const int64_t c = yy * gx + xx;
-          for (int32_t p = start[c]; p < start[c + 1]; ++p) {
-            const int32_t b = sorted[p];
-            if (b <= a || partner[a] == b) continue;
-            const mpld_rect& rb = nd[b];
-            const int64_t dx = std::max<int64_t>({0, (int64_t)rb.x0 - ra.x1, (int64_t)ra.x0 - rb.x1});
-            const int64_t dy = std::max<int64_t>({0, (int64_t)rb.y0 - ra.y1, (int64_t)ra.y0 - rb.y1});
-            if (dx * dx + dy * dy < d2) nbr.push_back(b);
+    const int64_t ylo = gy * t / T, yhi = gy * (t + 1) / T;
+    std::vector<uint64_t>& e = part[t];
+    auto test = [&](int32_t pa, const mpld_rect& ra, int32_t pb) {
+      const mpld_rect& rb = box[pb];
+      const int64_t dx = std::max<int64_t>({0, (int64_t)rb.x0 - ra.x1, (int64_t)ra.x0 - rb.x1});
+      const int64_t dy = std::max<int64_t>({0, (int64_t)rb.y0 - ra.y1, (int64_t)ra.y0 - rb.y1});
+      if (dx * dx + dy * dy < d2) {
+        const int32_t a = sorted[pa], b = sorted[pb];
+        if (mate[pa] == b) return;   // the two halves of a split feature
+        const uint32_t lo = (uint32_t)std::min(a, b), hi = (uint32_t)std::max(a, b);
+        e.push_back(((uint64_t)lo << 32) | hi);
+      }
+    };
+    for (int64_t cy = ylo; cy < yhi; ++cy)
+      for (int64_t cx = 0; cx < gx; ++cx) {
+        const int64_t c = cy * gx + cx;
+        for (int32_t pa = start[c]; pa < start[c + 1]; ++pa) {
+          const mpld_rect ra = box[pa];
+          for (int32_t pb = pa + 1; pb < start[c + 1]; ++pb) test(pa, ra, pb);
+          if (cx + 1 < gx)
+            for (int32_t pb = start[c + 1]; pb < start[c + 2]; ++pb) test(pa, ra, pb);
+          if (cy + 1 < gy) {
+            const int64_t c0 = (cy + 1) * gx + std::max<int64_t>(0, cx - 1);
+            const int64_t c1 = (cy + 1) * gx + std::min(gx - 1, cx + 1);
+            for (int32_t pb = start[c0]; pb < start[c1 + 1]; ++pb) test(pa, ra, pb);
           }
         }
-      std::sort(nbr.begin(), nbr.end());
-      for (int32_t b : nbr) { e.push_back(a); e.push_back(b); }
-    }
+      }
   };
+  (void)ncell;
   if (T == 1) {
     work(0);
   } else {
@@ -280,10 +301,27 @@ void build_layout_graph(const mpld_rect* rects, int32_t n, int32_t dmin,
     for (int t = 0; t < T; ++t) th.emplace_back(work, t);
     for (auto& x : th) x.join();
   }
+  // pairs sorted by (a, b): counting sort by a, then each a's few b ascending
   size_t total = 0;
-  for (auto& p : part) total += p.size();
-  out.ce.reserve(total);
-  for (auto& p : part) out.ce.insert(out.ce.end(), p.begin(), p.end());
+  for (auto& q : part) total += q.size();
+  std::vector<int64_t> off((size_t)nn + 1, 0);
+  for (auto& q : part)
+    for (uint64_t x : q) ++off[(x >> 32) + 1];
+  for (int32_t i = 0; i < nn; ++i) off[i + 1] += off[i];
+  std::vector<int32_t> nb(total);
+  {
+    std::vector<int64_t> fill(off.begin(), off.end() - 1);
+    for (auto& q : part)
+      for (uint64_t x : q) nb[(size_t)fill[x >> 32]++] = (int32_t)(uint32_t)x;
+  }
+  out.ce.resize(2 * total);
+  for (int32_t a = 0; a < nn; ++a) {
+    std::sort(nb.begin() + off[a], nb.begin() + off[a + 1]);
+    for (int64_t j = off[a]; j < off[a + 1]; ++j) {
+      out.ce[2 * j] = a;
+      out.ce[2 * j + 1] = nb[(size_t)j];
+    }
+  }
 }
 
 }  // namespace mpld

@@ -121,7 +121,10 @@ void mpld_server::front_end(Request* r) {
   try {
     if (r->layout) {
       OwnedGraph og;
-      build_layout_graph(r->rects.data(), (int32_t)r->rects.size(), r->dmin, r->split, og, 1);
+      // large layouts build their graph on a few threads (the host is mostly
+      // idle between requests); small ones on this worker alone
+      const int32_t nr = (int32_t)r->rects.size();
+      build_layout_graph(r->rects.data(), nr, r->dmin, r->split, og, std::max(1, std::min(4, nr / 12500)));
       r->num_nodes = og.num_nodes;
       r->ce.swap(og.ce);
       r->se.swap(og.se);
