@@ -71,6 +71,26 @@ struct SplitItem {
 };
 static_assert(sizeof(SplitItem) == 16, "item is 16 bytes");
 constexpr int kSplitMaxLevels = 4;
+// Output block of one task in a split round, all of a round's blocks in one
+// buffer so that the host reads them back with a single copy: the result,
+// the solution (colors by local node, when the task found one), then up to
+// max_items split items.
+constexpr uint32_t kSplitSolOffset = 16;
+constexpr uint32_t kSplitItemsOffset = 80;
+constexpr uint32_t split_block_bytes(int32_t max_items) {
+  return kSplitItemsOffset + 16u * (uint32_t)max_items;
+}
+// A resolved heavy component written back by the device: its record and
+// colors, scattered to their places by one small kernel.
+struct HeavyWrite {
+  int32_t comp;        // record index
+  int32_t out_off;     // first color entry
+  int32_t n;
+  int32_t pad;
+  DevRecord rec;
+  int8_t colors[64];
+};
+static_assert(sizeof(HeavyWrite) == 104, "write-back entry is 104 bytes");
 
 // Device bytes of the resumable register-tier search state of one
 // component (serving): a 128-byte uniform head (counters, then up to eight

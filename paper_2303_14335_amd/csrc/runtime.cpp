@@ -310,8 +310,10 @@ static void heavy_engine(DeviceBatch& db) {
   hipStream_t s = ctx->stream;
   db.sp_rounds = db.sp_tasks_run = db.sp_heavy = db.sp_reruns = 0;
   // which register-tier components stopped at the first cap
-  std::vector<DevRecord> recs((size_t)db.num_comps);
-  check_hip(hipMemcpyAsync(recs.data(), db.recs.p, sizeof(DevRecord) * recs.size(),
+  if (!db.sp_host_recs.reserve(sizeof(DevRecord) * (size_t)std::max(1, db.num_comps)))
+    fail(MPLD_E_NOMEM, "heavy-component engine: pinned host memory");
+  DevRecord* recs = db.sp_host_recs.as<DevRecord>();
+  check_hip(hipMemcpyAsync(recs, db.recs.p, sizeof(DevRecord) * (size_t)db.num_comps,
                            hipMemcpyDeviceToHost, s), "heavy: records");
   check_hip(hipStreamSynchronize(s), "heavy: first pass");
   std::vector<HComp> hcs;
@@ -337,19 +339,16 @@ static void heavy_engine(DeviceBatch& db) {
     --levels;
   }
   const int32_t max_items = (int32_t)kp + 2;   // subtasks, an end item, a solution item
-  if (!db.sp_tasks.p) {
-    db.sp_tasks.alloc(ctx, sizeof(SplitTask) * kHeavyMaxTasks);
-    db.sp_results.alloc(ctx, sizeof(SplitResult) * kHeavyMaxTasks);
-    db.sp_sols.alloc(ctx, 64 * (size_t)kHeavyMaxTasks);
-  }
-  // the item area depends on k and the split depth, which a new schedule
-  // may change: grow it when it is too small for this solve
-  const size_t item_bytes = sizeof(SplitItem) * (size_t)kHeavyMaxTasks * (size_t)max_items;
-  if (db.sp_items.bytes < item_bytes) db.sp_items.alloc(ctx, item_bytes);
-  std::vector<SplitTask> up;
-  std::vector<SplitResult> res;
-  std::vector<SplitItem> items;
-  std::vector<int8_t> sols;
+  if (!db.sp_tasks.p) db.sp_tasks.alloc(ctx, sizeof(SplitTask) * kHeavyMaxTasks);
+  // per-task output blocks; their size depends on k and the split depth,
+  // which a new schedule may change: grow the areas when too small
+  const size_t block = split_block_bytes(max_items);
+  if (db.sp_out.bytes < block * kHeavyMaxTasks) db.sp_out.alloc(ctx, block * kHeavyMaxTasks);
+  if (!db.sp_host_tasks.reserve(sizeof(SplitTask) * kHeavyMaxTasks) ||
+      !db.sp_host_out.reserve(block * kHeavyMaxTasks))
+    fail(MPLD_E_NOMEM, "heavy-component engine: pinned host memory");
+  SplitTask* up = db.sp_host_tasks.as<SplitTask>();
+  const uint8_t* hout = db.sp_host_out.as<uint8_t>();
   std::vector<int32_t> run;
   for (;;) {
     run.clear();
@@ -361,30 +360,21 @@ static void heavy_engine(DeviceBatch& db) {
     }
     if (run.empty()) break;
     const int32_t nt = (int32_t)run.size();
-    up.resize((size_t)nt);
     for (int32_t i = 0; i < nt; ++i) {
       const HTask& t = tasks[run[i]];
       up[i].item = hcs[t.hc].item;
       up[i].depth = t.depth;
       std::memcpy(up[i].rows, t.rows, sizeof(up[i].rows));
     }
-    check_hip(hipMemcpyAsync(db.sp_tasks.p, up.data(), sizeof(SplitTask) * nt, hipMemcpyHostToDevice, s),
+    check_hip(hipMemcpyAsync(db.sp_tasks.p, up, sizeof(SplitTask) * nt, hipMemcpyHostToDevice, s),
               "heavy: tasks");
     const int grid = std::max(1, std::min((nt + 3) / 4, ctx->num_cus * ctx->reg_blocks_per_cu));
     check_hip(launch_reg_split(db.k, grid, db.sp_tasks.as<SplitTask>(), nt, db.counters.as<int32_t>() + 6,
                                db.regitems.as<RegItem>(), (uint64_t)db.tune.heavy_round_cap,
-                               (uint32_t)levels, max_items, db.sp_results.as<SplitResult>(),
-                               db.sp_items.as<SplitItem>(), db.sp_sols.as<int8_t>(), s),
+                               (uint32_t)levels, max_items, db.sp_out.as<uint8_t>(), s),
               "heavy: split launch");
-    res.resize((size_t)nt);
-    items.resize((size_t)nt * (size_t)max_items);
-    sols.resize((size_t)nt * 64);
-    check_hip(hipMemcpyAsync(res.data(), db.sp_results.p, sizeof(SplitResult) * nt, hipMemcpyDeviceToHost, s),
-              "heavy: results");
-    check_hip(hipMemcpyAsync(items.data(), db.sp_items.p, sizeof(SplitItem) * items.size(),
-                             hipMemcpyDeviceToHost, s), "heavy: items");
-    check_hip(hipMemcpyAsync(sols.data(), db.sp_sols.p, sols.size(), hipMemcpyDeviceToHost, s),
-              "heavy: solutions");
+    check_hip(hipMemcpyAsync(db.sp_host_out.p, db.sp_out.p, block * (size_t)nt, hipMemcpyDeviceToHost, s),
+              "heavy: task outputs");
     check_hip(hipStreamSynchronize(s), "heavy: round");
     ++db.sp_rounds;
     db.sp_tasks_run += nt;
@@ -392,12 +382,15 @@ static void heavy_engine(DeviceBatch& db) {
     std::vector<std::vector<HItem>> repl((size_t)nt);
     std::vector<char> touched(hcs.size(), 0);
     for (int32_t i = 0; i < nt; ++i) {
-      const SplitResult& r = res[i];
+      const uint8_t* blk = hout + block * (size_t)i;
+      SplitResult r;
+      std::memcpy(&r, blk, sizeof(r));
+      const int8_t* sol = reinterpret_cast<const int8_t*>(blk + kSplitSolOffset);
       if (r.status == MPLD_FEASIBLE || r.status == MPLD_INFEASIBLE) {
         HTask& done = tasks[run[i]];
         done.status = r.status;
         done.nodes = r.nodes;
-        if (r.status == MPLD_FEASIBLE) std::memcpy(done.sol, &sols[(size_t)i * 64], 64);
+        if (r.status == MPLD_FEASIBLE) std::memcpy(done.sol, sol, 64);
         continue;
       }
       if (r.status != -1 || r.nitems < 1 || r.nitems > max_items)
@@ -406,7 +399,8 @@ static void heavy_engine(DeviceBatch& db) {
       // a copy: pushing the children below may move `tasks`
       const HTask t = tasks[run[i]];
       touched[t.hc] = 1;
-      const SplitItem* its = &items[(size_t)i * (size_t)max_items];
+      std::vector<SplitItem> its((size_t)r.nitems);
+      std::memcpy(its.data(), blk + kSplitItemsOffset, sizeof(SplitItem) * (size_t)r.nitems);
       for (int32_t j = 0; j < r.nitems; ++j) {
         if (its[j].seg) repl[i].push_back({-1, its[j].seg});
         if (its[j].kind == 1) break;
@@ -421,7 +415,7 @@ static void heavy_engine(DeviceBatch& db) {
           ch.depth = t.depth;
           ch.status = MPLD_FEASIBLE;
           ch.nodes = 0;
-          std::memcpy(ch.sol, &sols[(size_t)i * 64], 64);
+          std::memcpy(ch.sol, sol, 64);
         }
         tasks.push_back(ch);
         repl[i].push_back({(int32_t)tasks.size() - 1, 0});
@@ -451,7 +445,9 @@ static void heavy_engine(DeviceBatch& db) {
       hc.done = resolve(hc, db.host_desc[hc.item], tasks);
     }
   }
-  // write the results back where the first pass left its records
+  // write the results back where the first pass left its records: one
+  // staged copy and one scatter kernel for all resolved components
+  std::vector<HeavyWrite> wb;
   for (HComp& hc : hcs) {
     const DevDesc& d = db.host_desc[hc.item];
     if (hc.rerun) {
@@ -462,10 +458,25 @@ static void heavy_engine(DeviceBatch& db) {
       continue;
     }
     if (!hc.done) fail(MPLD_E_INTERNAL, "heavy-component engine ended unresolved");
-    check_hip(hipMemcpyAsync(db.recs.as<DevRecord>() + d.comp, &hc.rec, sizeof(DevRecord),
-                             hipMemcpyHostToDevice, s), "heavy: record");
-    check_hip(hipMemcpyAsync(db.colors.as<int8_t>() + d.out_off, hc.colors.data(), (size_t)d.n,
-                             hipMemcpyHostToDevice, s), "heavy: colors");
+    HeavyWrite w{};
+    w.comp = d.comp;
+    w.out_off = d.out_off;
+    w.n = d.n;
+    w.rec = hc.rec;
+    std::memcpy(w.colors, hc.colors.data(), (size_t)d.n);
+    wb.push_back(w);
+  }
+  if (!wb.empty()) {
+    if (!db.sp_host_writes.reserve(sizeof(HeavyWrite) * wb.size()))
+      fail(MPLD_E_NOMEM, "heavy-component engine: pinned host memory");
+    if (db.sp_writes.bytes < sizeof(HeavyWrite) * wb.size())
+      db.sp_writes.alloc(ctx, sizeof(HeavyWrite) * wb.size());
+    std::memcpy(db.sp_host_writes.p, wb.data(), sizeof(HeavyWrite) * wb.size());
+    check_hip(hipMemcpyAsync(db.sp_writes.p, db.sp_host_writes.p, sizeof(HeavyWrite) * wb.size(),
+                             hipMemcpyHostToDevice, s), "heavy: write-back upload");
+    check_hip(launch_heavy_writeback(db.sp_writes.as<HeavyWrite>(), (int32_t)wb.size(),
+                                     db.recs.as<DevRecord>(), db.colors.as<int8_t>(), s),
+              "heavy: write-back");
   }
   check_hip(hipStreamSynchronize(s), "heavy: write back");
 }

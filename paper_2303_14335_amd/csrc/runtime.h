@@ -20,10 +20,14 @@ hipError_t launch_reg_batched(bool trace, int k, int grid, int wpb, const RegIte
                               int32_t qlen, int32_t* counter, DevRecord* recs, int8_t* colors,
                               uint64_t cap, hipStream_t s);
 // Heavy-component engine: explore / split subtree tasks.
+// Task t writes its output block at out + t * split_block_bytes(max_items).
 hipError_t launch_reg_split(int k, int grid, const SplitTask* tasks, int32_t ntasks,
                             int32_t* counter, const RegItem* regitems,
-                            uint64_t cap, uint32_t levels, int32_t max_items,
-                            SplitResult* results, SplitItem* items, int8_t* sols, hipStream_t s);
+                            uint64_t cap, uint32_t levels, int32_t max_items, uint8_t* out,
+                            hipStream_t s);
+// Scatters `count` resolved heavy components (records and colors).
+hipError_t launch_heavy_writeback(const HeavyWrite* w, int32_t count, DevRecord* recs,
+                                  int8_t* colors, hipStream_t s);
 hipError_t launch_reg_single(bool trace, int k, const RegItem* items, int32_t item,
                              DevRecord* recs, int8_t* colors, hipStream_t s);
 int reg_batched_blocks_per_cu(bool trace);
@@ -97,6 +101,35 @@ struct DevBuf {
   T* as() const { return static_cast<T*>(p); }
 };
 
+// Page-locked host memory (hipHostMalloc), for small transfers that the
+// host waits on.
+struct PinnedBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  PinnedBuf() = default;
+  PinnedBuf(const PinnedBuf&) = delete;
+  PinnedBuf& operator=(const PinnedBuf&) = delete;
+  ~PinnedBuf() { release(); }
+  void release() {
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  // grows (never shrinks); false if the allocation failed
+  bool reserve(size_t n) {
+    if (n <= bytes) return true;
+    release();
+    if (hipHostMalloc(&p, n, hipHostMallocDefault) != hipSuccess) {
+      p = nullptr;
+      return false;
+    }
+    bytes = n;
+    return true;
+  }
+  template <class T>
+  T* as() const { return static_cast<T*>(p); }
+};
+
 // Host-side packed exact-cover image of a set of components.
 struct Image {
   std::vector<DevDesc> desc;       // by component id
@@ -124,8 +157,8 @@ struct Tune {
   int32_t order = 0;             // 0 largest first, 1 smallest first
   int32_t giant_device = 0;      // giants on the device-wide tier instead of the big tier
   int32_t giant_min_nodes = 4096;
-  int32_t heavy_first_cap = 2048;  // heavy-component engine: first-pass node cap
-  int32_t heavy_round_cap = 1024;  // nodes per subtree task and round
+  int32_t heavy_first_cap = 512;   // heavy-component engine: first-pass node cap
+  int32_t heavy_round_cap = 256;   // nodes per subtree task and round
   int32_t heavy_levels = 0;        // levels per split; 0 = by k (4, 3 or 2)
 };
 
@@ -143,7 +176,8 @@ struct DeviceBatch {
   mpld_context* ctx = nullptr;
   DevBuf desc, regitems, adj32, counters, recs, colors, gstack;  // desc in launch order
   DevBuf dev_keys, dev_stacks;      // device-wide tier
-  DevBuf sp_tasks, sp_results, sp_items, sp_sols;   // heavy-component engine
+  DevBuf sp_tasks, sp_out, sp_writes;               // heavy-component engine
+  PinnedBuf sp_host_tasks, sp_host_out, sp_host_writes, sp_host_recs;
   int64_t sp_rounds = 0, sp_tasks_run = 0, sp_heavy = 0, sp_reruns = 0;  // last solve's stats
   Tune tune;
   int32_t n_reg = 0, n_lds = 0, n_big = 0, n_dev = 0;

@@ -598,8 +598,7 @@ template <int K>
 __global__ __launch_bounds__(256) void reg_split_kernel(
     const SplitTask* __restrict__ tasks, int32_t ntasks, int32_t* __restrict__ counter,
     const RegItem* __restrict__ regitems, uint64_t cap,
-    uint32_t levels, int32_t max_items, SplitResult* __restrict__ results,
-    SplitItem* __restrict__ items, int8_t* __restrict__ sols) {
+    uint32_t levels, int32_t max_items, uint8_t* __restrict__ out) {
   const uint32_t wpb = blockDim.x >> 6;
   const int32_t gw = (int32_t)(gridDim.x * wpb);
   int32_t t = (int32_t)uniform(xcd_block() * wpb + (threadIdx.x >> 6));
@@ -611,7 +610,8 @@ __global__ __launch_bounds__(256) void reg_split_kernel(
     const DevDesc dd = regitems[it].d;
     const uint64_t nb = regitems[it].nb[lane];
     const uint32_t nb_lo = (uint32_t)nb, nb_hi = (uint32_t)(nb >> 32);
-    int8_t* sol = sols + (uint64_t)t * 64;
+    uint8_t* block = out + (uint64_t)t * split_block_bytes(max_items);
+    int8_t* sol = reinterpret_cast<int8_t*>(block + kSplitSolOffset);
     RegState<K> s;
     reg_init(s, dd.n, dd.k);
     reg_replay(s, nb_lo, nb_hi, dd.k, task->rows, d);
@@ -625,13 +625,13 @@ __global__ __launch_bounds__(256) void reg_split_kernel(
       reg_init(r, dd.n, dd.k);
       reg_replay(r, nb_lo, nb_hi, dd.k, task->rows, d);
       nitems = reg_enumerate(r, nb_lo, nb_hi, dd.n, d, levels,
-                             items + (uint64_t)t * (uint64_t)max_items, sol);
+                             reinterpret_cast<SplitItem*>(block + kSplitItemsOffset), sol);
     }
     SplitResult res;
     res.status = s.status;
     res.nitems = nitems;
     res.nodes = s.nodes;
-    results[t] = res;   // same value from every lane
+    *reinterpret_cast<SplitResult*>(block) = res;   // same value from every lane
     if (gw >= ntasks) break;
     int32_t r = 0;
     if (__lane_id() == 0) r = atomicAdd(counter, 1);
@@ -718,15 +718,32 @@ hipError_t launch_reg_tick(bool trace, int k, int grid, const int32_t* list, int
 
 hipError_t launch_reg_split(int k, int grid, const SplitTask* tasks, int32_t ntasks,
                             int32_t* counter, const RegItem* regitems,
-                            uint64_t cap, uint32_t levels, int32_t max_items,
-                            SplitResult* results, SplitItem* items, int8_t* sols, hipStream_t s) {
+                            uint64_t cap, uint32_t levels, int32_t max_items, uint8_t* out,
+                            hipStream_t s) {
   if (ntasks <= 0) return hipSuccess;
   if (levels < 1 || levels > (uint32_t)kSplitMaxLevels) return hipErrorInvalidValue;
   with_planes(k, [&](auto kp) {
     constexpr int K = decltype(kp)::value;
     hipLaunchKernelGGL((reg_split_kernel<K>), dim3(grid), dim3(256), 0, s, tasks, ntasks, counter,
-                       regitems, cap, levels, max_items, results, items, sols);
+                       regitems, cap, levels, max_items, out);
   });
+  return hipGetLastError();
+}
+
+// One wave per entry: the record by one lane, the colors one per lane.
+__global__ __launch_bounds__(64) void heavy_writeback_kernel(const HeavyWrite* __restrict__ w,
+                                                             DevRecord* __restrict__ recs,
+                                                             int8_t* __restrict__ colors) {
+  const HeavyWrite& e = w[blockIdx.x];
+  const uint32_t lane = threadIdx.x;
+  if (lane < (uint32_t)e.n) colors[e.out_off + (int32_t)lane] = e.colors[lane];
+  if (lane == 0) recs[e.comp] = e.rec;
+}
+
+hipError_t launch_heavy_writeback(const HeavyWrite* w, int32_t count, DevRecord* recs,
+                                  int8_t* colors, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(heavy_writeback_kernel, dim3(count), dim3(64), 0, s, w, recs, colors);
   return hipGetLastError();
 }
 
