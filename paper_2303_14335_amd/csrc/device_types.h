@@ -58,8 +58,10 @@ struct SplitResult {
   int32_t status;      // MPLD_FEASIBLE, MPLD_INFEASIBLE (subtree exhausted) or -1 (cap hit)
   int32_t nitems;      // split items written when the cap was hit
   uint64_t nodes;      // nodes explored (the subtree's own count when finished)
+  uint32_t item_off;   // first of the task's items in the round's item pool
+  uint32_t pad;
 };
-static_assert(sizeof(SplitResult) == 16, "result is 16 bytes");
+static_assert(sizeof(SplitResult) == 24, "result is 24 bytes");
 // One item of the split of a capped task, in depth-first order: `seg` nodes
 // of the task's top levels are visited, then (kind 0) the subtree of the
 // node reached by rows[0..levels-1] below the task root, or (kind 1) the
@@ -71,15 +73,13 @@ struct SplitItem {
 };
 static_assert(sizeof(SplitItem) == 16, "item is 16 bytes");
 constexpr int kSplitMaxLevels = 4;
-// Output block of one task in a split round, all of a round's blocks in one
-// buffer so that the host reads them back with a single copy: the result,
-// the solution (colors by local node, when the task found one), then up to
-// max_items split items.
-constexpr uint32_t kSplitSolOffset = 16;
-constexpr uint32_t kSplitItemsOffset = 80;
-constexpr uint32_t split_block_bytes(int32_t max_items) {
-  return kSplitItemsOffset + 16u * (uint32_t)max_items;
-}
+// Output block of one task in a split round (all of a round's blocks in one
+// buffer, read back with one copy): the result, then the solution (colors by
+// local node, when the task found one).  A capped task's split items go to
+// a pool shared by the round, at an offset taken with one atomic, so only
+// the items that exist are read back.
+constexpr uint32_t kSplitSolOffset = 24;
+constexpr uint32_t kSplitBlockBytes = 88;
 // A resolved heavy component written back by the device: its record and
 // colors, scattered to their places by one small kernel.
 struct HeavyWrite {

@@ -340,15 +340,19 @@ static void heavy_engine(DeviceBatch& db) {
   }
   const int32_t max_items = (int32_t)kp + 2;   // subtasks, an end item, a solution item
   if (!db.sp_tasks.p) db.sp_tasks.alloc(ctx, sizeof(SplitTask) * kHeavyMaxTasks);
-  // per-task output blocks; their size depends on k and the split depth,
-  // which a new schedule may change: grow the areas when too small
-  const size_t block = split_block_bytes(max_items);
-  if (db.sp_out.bytes < block * kHeavyMaxTasks) db.sp_out.alloc(ctx, block * kHeavyMaxTasks);
+  if (!db.sp_out.p) db.sp_out.alloc(ctx, (size_t)kSplitBlockBytes * kHeavyMaxTasks);
+  // the item pool depends on k and the split depth, which a new schedule
+  // may change: grow it when too small
+  const size_t pool_bytes = sizeof(SplitItem) * (size_t)max_items * kHeavyMaxTasks;
+  if (db.sp_pool.bytes < pool_bytes) db.sp_pool.alloc(ctx, pool_bytes);
+  const size_t count_at = (size_t)kSplitBlockBytes * kHeavyMaxTasks;   // pool count copy
   if (!db.sp_host_tasks.reserve(sizeof(SplitTask) * kHeavyMaxTasks) ||
-      !db.sp_host_out.reserve(block * kHeavyMaxTasks))
+      !db.sp_host_out.reserve(count_at + 64) || !db.sp_host_pool.reserve(pool_bytes))
     fail(MPLD_E_NOMEM, "heavy-component engine: pinned host memory");
   SplitTask* up = db.sp_host_tasks.as<SplitTask>();
   const uint8_t* hout = db.sp_host_out.as<uint8_t>();
+  const SplitItem* hpool = db.sp_host_pool.as<SplitItem>();
+  int32_t* pool_count = db.counters.as<int32_t>() + 7;
   std::vector<int32_t> run;
   for (;;) {
     run.clear();
@@ -369,20 +373,33 @@ static void heavy_engine(DeviceBatch& db) {
     check_hip(hipMemcpyAsync(db.sp_tasks.p, up, sizeof(SplitTask) * nt, hipMemcpyHostToDevice, s),
               "heavy: tasks");
     const int grid = std::max(1, std::min((nt + 3) / 4, ctx->num_cus * ctx->reg_blocks_per_cu));
+    check_hip(hipMemsetAsync(pool_count, 0, sizeof(int32_t), s), "heavy: pool count");
     check_hip(launch_reg_split(db.k, grid, db.sp_tasks.as<SplitTask>(), nt, db.counters.as<int32_t>() + 6,
                                db.regitems.as<RegItem>(), (uint64_t)db.tune.heavy_round_cap,
-                               (uint32_t)levels, max_items, db.sp_out.as<uint8_t>(), s),
+                               (uint32_t)levels, db.sp_out.as<uint8_t>(), db.sp_pool.as<SplitItem>(),
+                               pool_count, s),
               "heavy: split launch");
-    check_hip(hipMemcpyAsync(db.sp_host_out.p, db.sp_out.p, block * (size_t)nt, hipMemcpyDeviceToHost, s),
-              "heavy: task outputs");
+    check_hip(hipMemcpyAsync(db.sp_host_out.p, db.sp_out.p, (size_t)kSplitBlockBytes * nt,
+                             hipMemcpyDeviceToHost, s), "heavy: task outputs");
+    check_hip(hipMemcpyAsync(db.sp_host_out.as<uint8_t>() + count_at, pool_count, sizeof(int32_t),
+                             hipMemcpyDeviceToHost, s), "heavy: pool count");
     check_hip(hipStreamSynchronize(s), "heavy: round");
+    int32_t pooled = 0;
+    std::memcpy(&pooled, hout + count_at, sizeof(pooled));
+    if (pooled < 0 || (size_t)pooled * sizeof(SplitItem) > pool_bytes)
+      fail(MPLD_E_INTERNAL, "heavy-component engine: bad item count");
+    if (pooled > 0) {
+      check_hip(hipMemcpyAsync(db.sp_host_pool.p, db.sp_pool.p, sizeof(SplitItem) * (size_t)pooled,
+                               hipMemcpyDeviceToHost, s), "heavy: items");
+      check_hip(hipStreamSynchronize(s), "heavy: items");
+    }
     ++db.sp_rounds;
     db.sp_tasks_run += nt;
     // finished tasks take their counts; capped ones are replaced by their split
     std::vector<std::vector<HItem>> repl((size_t)nt);
     std::vector<char> touched(hcs.size(), 0);
     for (int32_t i = 0; i < nt; ++i) {
-      const uint8_t* blk = hout + block * (size_t)i;
+      const uint8_t* blk = hout + (size_t)kSplitBlockBytes * i;
       SplitResult r;
       std::memcpy(&r, blk, sizeof(r));
       const int8_t* sol = reinterpret_cast<const int8_t*>(blk + kSplitSolOffset);
@@ -393,14 +410,14 @@ static void heavy_engine(DeviceBatch& db) {
         if (r.status == MPLD_FEASIBLE) std::memcpy(done.sol, sol, 64);
         continue;
       }
-      if (r.status != -1 || r.nitems < 1 || r.nitems > max_items)
+      if (r.status != -1 || r.nitems < 1 || r.nitems > max_items ||
+          (int64_t)r.item_off + r.nitems > (int64_t)pooled)
         fail(MPLD_E_INTERNAL, "heavy-component engine: bad task result");
       tasks[run[i]].status = -1;
       // a copy: pushing the children below may move `tasks`
       const HTask t = tasks[run[i]];
       touched[t.hc] = 1;
-      std::vector<SplitItem> its((size_t)r.nitems);
-      std::memcpy(its.data(), blk + kSplitItemsOffset, sizeof(SplitItem) * (size_t)r.nitems);
+      const SplitItem* its = hpool + r.item_off;
       for (int32_t j = 0; j < r.nitems; ++j) {
         if (its[j].seg) repl[i].push_back({-1, its[j].seg});
         if (its[j].kind == 1) break;

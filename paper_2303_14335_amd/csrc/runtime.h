@@ -20,11 +20,13 @@ hipError_t launch_reg_batched(bool trace, int k, int grid, int wpb, const RegIte
                               int32_t qlen, int32_t* counter, DevRecord* recs, int8_t* colors,
                               uint64_t cap, hipStream_t s);
 // Heavy-component engine: explore / split subtree tasks.
-// Task t writes its output block at out + t * split_block_bytes(max_items).
+// Task t writes its output block at out + t * kSplitBlockBytes and its
+// split items to pool at an offset taken from *pool_count (zero before the
+// launch).
 hipError_t launch_reg_split(int k, int grid, const SplitTask* tasks, int32_t ntasks,
-                            int32_t* counter, const RegItem* regitems,
-                            uint64_t cap, uint32_t levels, int32_t max_items, uint8_t* out,
-                            hipStream_t s);
+                            int32_t* counter, const RegItem* regitems, uint64_t cap,
+                            uint32_t levels, uint8_t* out, SplitItem* pool,
+                            int32_t* pool_count, hipStream_t s);
 // Scatters `count` resolved heavy components (records and colors).
 hipError_t launch_heavy_writeback(const HeavyWrite* w, int32_t count, DevRecord* recs,
                                   int8_t* colors, hipStream_t s);
@@ -176,8 +178,8 @@ struct DeviceBatch {
   mpld_context* ctx = nullptr;
   DevBuf desc, regitems, adj32, counters, recs, colors, gstack;  // desc in launch order
   DevBuf dev_keys, dev_stacks;      // device-wide tier
-  DevBuf sp_tasks, sp_out, sp_writes;               // heavy-component engine
-  PinnedBuf sp_host_tasks, sp_host_out, sp_host_writes, sp_host_recs;
+  DevBuf sp_tasks, sp_out, sp_pool, sp_writes;      // heavy-component engine
+  PinnedBuf sp_host_tasks, sp_host_out, sp_host_pool, sp_host_writes, sp_host_recs;
   int64_t sp_rounds = 0, sp_tasks_run = 0, sp_heavy = 0, sp_reruns = 0;  // last solve's stats
   Tune tune;
   int32_t n_reg = 0, n_lds = 0, n_big = 0, n_dev = 0;

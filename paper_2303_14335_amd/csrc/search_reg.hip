@@ -527,7 +527,7 @@ __device__ __forceinline__ void reg_replay(RegState<K>& s, const uint32_t nb_lo,
 // search order: counts their nodes, and emits a kind-0 item for every node
 // at depth d + levels (not counted here: its own task counts it), a kind-2
 // item when a solution is met (writing its colors) or a kind-1 item at the
-// end.  Returns the number of items.
+// end.  Returns the number of items; with out == nullptr it only counts.
 template <int K>
 __device__ __forceinline__ int32_t reg_enumerate(RegState<K>& s, const uint32_t nb_lo,
                                                  const uint32_t nb_hi, const int32_t n,
@@ -543,7 +543,7 @@ __device__ __forceinline__ int32_t reg_enumerate(RegState<K>& s, const uint32_t 
     const uint32_t r1 = kind == 0 && levels > 1 ? rdlane(s.fr, d + 1) : 0u;
     const uint32_t r2 = kind == 0 && levels > 2 ? rdlane(s.fr, d + 2) : 0u;
     const uint32_t r3 = kind == 0 && levels > 3 ? rdlane(s.fr, d + 3) : 0u;
-    if (lane == ((uint32_t)items & 63u)) {   // one owner lane per item
+    if (out != nullptr && lane == ((uint32_t)items & 63u)) {   // one owner lane per item
       SplitItem it;
       it.seg = seg;
       it.kind = kind;
@@ -598,7 +598,8 @@ template <int K>
 __global__ __launch_bounds__(256) void reg_split_kernel(
     const SplitTask* __restrict__ tasks, int32_t ntasks, int32_t* __restrict__ counter,
     const RegItem* __restrict__ regitems, uint64_t cap,
-    uint32_t levels, int32_t max_items, uint8_t* __restrict__ out) {
+    uint32_t levels, uint8_t* __restrict__ out, SplitItem* __restrict__ pool,
+    int32_t* __restrict__ pool_count) {
   const uint32_t wpb = blockDim.x >> 6;
   const int32_t gw = (int32_t)(gridDim.x * wpb);
   int32_t t = (int32_t)uniform(xcd_block() * wpb + (threadIdx.x >> 6));
@@ -610,27 +611,39 @@ __global__ __launch_bounds__(256) void reg_split_kernel(
     const DevDesc dd = regitems[it].d;
     const uint64_t nb = regitems[it].nb[lane];
     const uint32_t nb_lo = (uint32_t)nb, nb_hi = (uint32_t)(nb >> 32);
-    uint8_t* block = out + (uint64_t)t * split_block_bytes(max_items);
+    uint8_t* block = out + (uint64_t)t * kSplitBlockBytes;
     int8_t* sol = reinterpret_cast<int8_t*>(block + kSplitSolOffset);
     RegState<K> s;
     reg_init(s, dd.n, dd.k);
     reg_replay(s, nb_lo, nb_hi, dd.k, task->rows, d);
     reg_run<false, K>(s, nb_lo, nb_hi, dd.k, ~0ull, cap, d);
     int32_t nitems = 0;
+    uint32_t item_off = 0;
     if (s.status == MPLD_FEASIBLE) {
       if (lane < s.depth && (s.fr & 0xffu) < (uint32_t)dd.n)
         sol[s.fr & 0xffu] = (int8_t)((s.fr >> 8) & 0xffu);
     } else if (s.status < 0) {
+      // count the split's items, reserve their range of the pool, then
+      // enumerate again writing them (the top levels are cheap to walk)
       RegState<K> r;
       reg_init(r, dd.n, dd.k);
       reg_replay(r, nb_lo, nb_hi, dd.k, task->rows, d);
-      nitems = reg_enumerate(r, nb_lo, nb_hi, dd.n, d, levels,
-                             reinterpret_cast<SplitItem*>(block + kSplitItemsOffset), sol);
+      nitems = reg_enumerate(r, nb_lo, nb_hi, dd.n, d, levels, nullptr, sol);
+      // lane 63 takes the reservation: a lane-0 branch here could be merged
+      // with the queue pop's and split the wave across the loop
+      uint32_t o = 0;
+      if (lane == 63u) o = (uint32_t)atomicAdd(pool_count, nitems);
+      item_off = (uint32_t)__builtin_amdgcn_readlane((int)o, 63);
+      reg_init(r, dd.n, dd.k);
+      reg_replay(r, nb_lo, nb_hi, dd.k, task->rows, d);
+      reg_enumerate(r, nb_lo, nb_hi, dd.n, d, levels, pool + item_off, sol);
     }
     SplitResult res;
     res.status = s.status;
     res.nitems = nitems;
     res.nodes = s.nodes;
+    res.item_off = item_off;
+    res.pad = 0;
     *reinterpret_cast<SplitResult*>(block) = res;   // same value from every lane
     if (gw >= ntasks) break;
     int32_t r = 0;
@@ -717,15 +730,15 @@ hipError_t launch_reg_tick(bool trace, int k, int grid, const int32_t* list, int
 }
 
 hipError_t launch_reg_split(int k, int grid, const SplitTask* tasks, int32_t ntasks,
-                            int32_t* counter, const RegItem* regitems,
-                            uint64_t cap, uint32_t levels, int32_t max_items, uint8_t* out,
-                            hipStream_t s) {
+                            int32_t* counter, const RegItem* regitems, uint64_t cap,
+                            uint32_t levels, uint8_t* out, SplitItem* pool,
+                            int32_t* pool_count, hipStream_t s) {
   if (ntasks <= 0) return hipSuccess;
   if (levels < 1 || levels > (uint32_t)kSplitMaxLevels) return hipErrorInvalidValue;
   with_planes(k, [&](auto kp) {
     constexpr int K = decltype(kp)::value;
     hipLaunchKernelGGL((reg_split_kernel<K>), dim3(grid), dim3(256), 0, s, tasks, ntasks, counter,
-                       regitems, cap, levels, max_items, out);
+                       regitems, cap, levels, out, pool, pool_count);
   });
   return hipGetLastError();
 }
