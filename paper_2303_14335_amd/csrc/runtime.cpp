@@ -6,7 +6,6 @@
 
 #include <algorithm>
 #include <cstring>
-#include <unordered_map>
 
 namespace mpld {
 
@@ -265,6 +264,8 @@ struct HItem {
 struct HComp {
   int32_t item;          // launch-ordered descriptor index
   std::vector<HItem> seq;
+  size_t pos = 0;        // seq[0 .. pos) is final and sums to acc
+  uint64_t acc = 0;
   bool done = false, rerun = false;
   DevRecord rec{};
   std::vector<int8_t> colors;
@@ -272,11 +273,14 @@ struct HComp {
 
 int split_levels(int k) { return k <= 3 ? 4 : (k == 4 ? 3 : 2); }
 
-// Scans a component's items; true once its sequential result is known.
+// Scans a component's items from its first unresolved one (everything
+// before it is final and already summed); true once its sequential result
+// is known.
 bool resolve(HComp& hc, const DevDesc& d, const std::vector<HTask>& tasks) {
   const uint64_t budget = (uint64_t)d.budget;
-  uint64_t acc = 0;
-  for (const HItem& it : hc.seq) {
+  uint64_t& acc = hc.acc;
+  for (; hc.pos < hc.seq.size(); ++hc.pos) {
+    const HItem& it = hc.seq[hc.pos];
     if (it.task < 0) {
       if (acc + it.count > budget) { hc.rerun = true; return true; }
       acc += it.count;
@@ -318,6 +322,7 @@ static void heavy_engine(DeviceBatch& db) {
   check_hip(hipStreamSynchronize(s), "heavy: first pass");
   std::vector<HComp> hcs;
   std::vector<HTask> tasks;
+  std::vector<int32_t> pending;   // tasks not run yet, in creation order
   for (int32_t i = 0; i < db.n_reg; ++i) {
     if (recs[db.host_desc[i].comp].status >= 0) continue;
     HComp hc;
@@ -326,6 +331,7 @@ static void heavy_engine(DeviceBatch& db) {
     root.hc = (int32_t)hcs.size();
     root.depth = 0;
     tasks.push_back(root);
+    pending.push_back((int32_t)tasks.size() - 1);
     hc.seq.push_back({(int32_t)tasks.size() - 1, 0});
     hcs.push_back(std::move(hc));
   }
@@ -339,29 +345,35 @@ static void heavy_engine(DeviceBatch& db) {
     --levels;
   }
   const int32_t max_items = (int32_t)kp + 2;   // subtasks, an end item, a solution item
-  if (!db.sp_tasks.p) db.sp_tasks.alloc(ctx, sizeof(SplitTask) * kHeavyMaxTasks);
+  // task area: the round's item-pool count first (zeroed by the same upload
+  // that brings the tasks), the tasks from byte 64 on
+  constexpr size_t kTasksAt = 64;
+  if (!db.sp_tasks.p) db.sp_tasks.alloc(ctx, kTasksAt + sizeof(SplitTask) * kHeavyMaxTasks);
   if (!db.sp_out.p) db.sp_out.alloc(ctx, (size_t)kSplitBlockBytes * kHeavyMaxTasks);
   // the item pool depends on k and the split depth, which a new schedule
   // may change: grow it when too small
   const size_t pool_bytes = sizeof(SplitItem) * (size_t)max_items * kHeavyMaxTasks;
   if (db.sp_pool.bytes < pool_bytes) db.sp_pool.alloc(ctx, pool_bytes);
   const size_t count_at = (size_t)kSplitBlockBytes * kHeavyMaxTasks;   // pool count copy
-  if (!db.sp_host_tasks.reserve(sizeof(SplitTask) * kHeavyMaxTasks) ||
+  if (!db.sp_host_tasks.reserve(kTasksAt + sizeof(SplitTask) * kHeavyMaxTasks) ||
       !db.sp_host_out.reserve(count_at + 64) || !db.sp_host_pool.reserve(pool_bytes))
     fail(MPLD_E_NOMEM, "heavy-component engine: pinned host memory");
-  SplitTask* up = db.sp_host_tasks.as<SplitTask>();
+  SplitTask* up = reinterpret_cast<SplitTask*>(db.sp_host_tasks.as<uint8_t>() + kTasksAt);
   const uint8_t* hout = db.sp_host_out.as<uint8_t>();
   const SplitItem* hpool = db.sp_host_pool.as<SplitItem>();
-  int32_t* pool_count = db.counters.as<int32_t>() + 7;
-  std::vector<int32_t> run;
+  int32_t* pool_count = db.sp_tasks.as<int32_t>();
+  const SplitTask* dtasks = reinterpret_cast<const SplitTask*>(db.sp_tasks.as<uint8_t>() + kTasksAt);
+  std::vector<int32_t> run, rest, where;
   for (;;) {
+    // this round: pending tasks of unresolved components, oldest first
     run.clear();
-    for (HComp& hc : hcs) {
-      if (hc.done) continue;
-      for (const HItem& it : hc.seq)
-        if (it.task >= 0 && tasks[it.task].status == -2 && (int32_t)run.size() < kHeavyMaxTasks)
-          run.push_back(it.task);
+    rest.clear();
+    for (int32_t id : pending) {
+      if (hcs[tasks[id].hc].done) continue;
+      if ((int32_t)run.size() < kHeavyMaxTasks) run.push_back(id);
+      else rest.push_back(id);
     }
+    pending.swap(rest);
     if (run.empty()) break;
     const int32_t nt = (int32_t)run.size();
     for (int32_t i = 0; i < nt; ++i) {
@@ -370,11 +382,11 @@ static void heavy_engine(DeviceBatch& db) {
       up[i].depth = t.depth;
       std::memcpy(up[i].rows, t.rows, sizeof(up[i].rows));
     }
-    check_hip(hipMemcpyAsync(db.sp_tasks.p, up, sizeof(SplitTask) * nt, hipMemcpyHostToDevice, s),
-              "heavy: tasks");
+    *db.sp_host_tasks.as<int32_t>() = 0;   // the pool count
+    check_hip(hipMemcpyAsync(db.sp_tasks.p, db.sp_host_tasks.p, kTasksAt + sizeof(SplitTask) * nt,
+                             hipMemcpyHostToDevice, s), "heavy: tasks");
     const int grid = std::max(1, std::min((nt + 3) / 4, ctx->num_cus * ctx->reg_blocks_per_cu));
-    check_hip(hipMemsetAsync(pool_count, 0, sizeof(int32_t), s), "heavy: pool count");
-    check_hip(launch_reg_split(db.k, grid, db.sp_tasks.as<SplitTask>(), nt, db.counters.as<int32_t>() + 6,
+    check_hip(launch_reg_split(db.k, grid, dtasks, nt, db.counters.as<int32_t>() + 6,
                                db.regitems.as<RegItem>(), (uint64_t)db.tune.heavy_round_cap,
                                (uint32_t)levels, db.sp_out.as<uint8_t>(), db.sp_pool.as<SplitItem>(),
                                pool_count, s),
@@ -435,29 +447,33 @@ static void heavy_engine(DeviceBatch& db) {
           std::memcpy(ch.sol, sol, 64);
         }
         tasks.push_back(ch);
+        if (ch.status == -2) pending.push_back((int32_t)tasks.size() - 1);
         repl[i].push_back({(int32_t)tasks.size() - 1, 0});
         if (its[j].kind == 2) break;
       }
     }
-    // splice replacements into their components' sequences
-    std::unordered_map<int32_t, int32_t> where;
+    // splice replacements into their components' sequences (only past the
+    // resolved prefix: a capped task was not final)
+    where.assign(tasks.size(), -1);
     for (int32_t i = 0; i < nt; ++i)
       if (tasks[run[i]].status == -1) where[run[i]] = i;
     for (size_t h = 0; h < hcs.size(); ++h) {
       HComp& hc = hcs[h];
       if (hc.done) continue;
       if (touched[h]) {
-        std::vector<HItem> seq;
-        seq.reserve(hc.seq.size() * 2);
-        for (const HItem& it : hc.seq) {
-          auto f = it.task >= 0 ? where.find(it.task) : where.end();
-          if (f == where.end()) {
-            seq.push_back(it);
+        std::vector<HItem> tail;
+        tail.reserve((hc.seq.size() - hc.pos) * 2);
+        for (size_t j = hc.pos; j < hc.seq.size(); ++j) {
+          const HItem& it = hc.seq[j];
+          const int32_t f = it.task >= 0 ? where[it.task] : -1;
+          if (f < 0) {
+            tail.push_back(it);
           } else {
-            for (const HItem& x : repl[f->second]) seq.push_back(x);
+            for (const HItem& x : repl[f]) tail.push_back(x);
           }
         }
-        hc.seq.swap(seq);
+        hc.seq.resize(hc.pos);
+        hc.seq.insert(hc.seq.end(), tail.begin(), tail.end());
       }
       hc.done = resolve(hc, db.host_desc[hc.item], tasks);
     }
