@@ -45,7 +45,11 @@ def test_abi_version_and_error_strings():
 
 
 @pytest.mark.parametrize("n,side,dmin,split,seed", [(300, 3000, 80, 0, 0), (3000, 9000, 120, 120, 1),
-                                                    (5000, 6000, 100, 0, 2), (20000, 30000, 80, 0, 3)])
+                                                    (5000, 6000, 100, 0, 2), (20000, 30000, 80, 0, 3),
+                                                    # sparse: the grid cells grow; dense: crowded cells
+                                                    (2000, 400000, 80, 0, 4), (6000, 4500, 150, 100, 5),
+                                                    # several scan threads and stitch pairs
+                                                    (40000, 40000, 100, 90, 6)])
 def test_front_end_graph_matches_oracle(n, side, dmin, split, seed):
     import paper_2303_14335_amd as mp
     rects, _ = workload.generate(n, side, seed)
