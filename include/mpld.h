@@ -266,6 +266,10 @@ typedef struct {
   int32_t heavy_levels;      /* MPLD_SPLIT_HEAVY: search levels enumerated when
                                 a capped task splits (1..4; 0 = 4, 3 or 2 for
                                 k <= 3, k = 4, k >= 5)                          */
+  int32_t heavy_device;      /* MPLD_SPLIT_HEAVY: 1 chains the rounds on the
+                                device (subtasks written by the kernel, the
+                                host resolves once at the end); 0 drives every
+                                round from the host                             */
 } mpld_tune;
 int32_t mpld_batch_autotune(mpld_batch* b, int32_t reps, const char* cache_path, mpld_tune* out);
 int32_t mpld_batch_get_tune(mpld_batch* b, mpld_tune* out);

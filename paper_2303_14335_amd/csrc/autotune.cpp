@@ -102,6 +102,7 @@ bool tune_from_cache(mpld_batch* b, const char* path, Tune* t) {
   if (field(hit, "giant_min_nodes", &v)) t->giant_min_nodes = (int32_t)std::max(65L, v);
   if (field(hit, "heavy_first_cap", &v)) t->heavy_first_cap = (int32_t)std::max(64L, v);
   if (field(hit, "heavy_round_cap", &v)) t->heavy_round_cap = (int32_t)std::max(16L, v);
+  if (field(hit, "heavy_device", &v)) t->heavy_device = v ? 1 : 0;
   if (field(hit, "heavy_levels", &v))
     t->heavy_levels = (int32_t)std::max(0L, std::min((long)kSplitMaxLevels, v));
   b->tuned_from_cache = true;
@@ -154,6 +155,7 @@ static void to_abi(const Tune& t, mpld_tune* o) {
   o->heavy_first_cap = t.heavy_first_cap;
   o->heavy_round_cap = t.heavy_round_cap;
   o->heavy_levels = t.heavy_levels;
+  o->heavy_device = t.heavy_device;
 }
 
 extern "C" {
@@ -179,6 +181,7 @@ int32_t mpld_batch_set_tune(mpld_batch* b, const mpld_tune* in) {
     t.heavy_first_cap = std::max(64, in->heavy_first_cap);
     t.heavy_round_cap = std::max(16, in->heavy_round_cap);
     t.heavy_levels = std::max(0, std::min(kSplitMaxLevels, in->heavy_levels));
+    t.heavy_device = in->heavy_device ? 1 : 0;
     batch_pack(b, t);
     b->solved = false;
     set_last_error("");
@@ -253,7 +256,8 @@ int32_t mpld_batch_autotune(mpld_batch* b, int32_t reps, const char* cache_path,
           << ", \"giant_min_nodes\": " << best.giant_min_nodes
           << ", \"heavy_first_cap\": " << best.heavy_first_cap
           << ", \"heavy_round_cap\": " << best.heavy_round_cap
-          << ", \"heavy_levels\": " << best.heavy_levels << ", \"best_ms\": " << best_ms
+          << ", \"heavy_levels\": " << best.heavy_levels
+          << ", \"heavy_device\": " << best.heavy_device << ", \"best_ms\": " << best_ms
           << ", \"default_ms\": " << base_ms << "}\n";
       }
     }

@@ -80,6 +80,39 @@ constexpr int kSplitMaxLevels = 4;
 // the items that exist are read back.
 constexpr uint32_t kSplitSolOffset = 24;
 constexpr uint32_t kSplitBlockBytes = 88;
+// Device-resident heavy-component engine.  Tasks of every round live in one
+// array: round r runs the tasks [begin, end) and appends the subtasks of
+// its capped tasks at `alloc`; a one-thread kernel between rounds moves the
+// window on.  Capped tasks put their items in one pool at `pool`.
+struct EngineHead {
+  int32_t begin, end;   // tasks of the current round
+  int32_t alloc;        // next free task slot (may pass the capacity)
+  int32_t pool;         // next free item slot (may pass the capacity)
+  int32_t pop;          // work counter of the current round
+  int32_t rounds;       // rounds started
+  int32_t overflow;     // an allocation did not fit (the host re-runs)
+  int32_t pad[9];
+};
+static_assert(sizeof(EngineHead) == 64, "engine head is 64 bytes");
+struct EngineTask {
+  int32_t item;         // launch-ordered index of the component's register item
+  int32_t depth;        // rows on the path from the root
+  int32_t hc;           // heavy-component index
+  int32_t skip;         // nonzero: a slot whose subtask could not be stored
+  uint16_t rows[64];    // the path: v | c << 8 per depth
+};
+static_assert(sizeof(EngineTask) == 144, "engine task is 144 bytes");
+// One item of a capped task's split (as SplitItem, with the subtask's task
+// index instead of its rows).
+struct EngineItem {
+  uint32_t seg;
+  uint32_t kind;        // 0 subtask, 1 end, 2 solution
+  int32_t child;        // kind 0: task index of the subtask
+  uint32_t pad;
+};
+static_assert(sizeof(EngineItem) == 16, "engine item is 16 bytes");
+constexpr int32_t kEngineSkipped = -3;   // task status: not run (skip slot) or not split (budget or space)
+
 // A resolved heavy component written back by the device: its record and
 // colors, scattered to their places by one small kernel.
 struct HeavyWrite {

@@ -309,7 +309,201 @@ bool resolve(HComp& hc, const DevDesc& d, const std::vector<HTask>& tasks) {
 
 }  // namespace
 
+// Device-resident rounds.  Capacities bound the engine's memory; a split
+// that does not fit (or a component whose explored nodes pass twice its
+// budget) leaves that component to a sequential re-run, which is exact.
+constexpr int32_t kEngineTaskCap = 1 << 18;   // tasks (144 B + an 88 B result block each)
+constexpr int32_t kEnginePoolCap = 1 << 21;   // split items (16 B each)
+constexpr int32_t kEngineMaxRounds = 96;      // depth <= 64: far more than needed
+constexpr int32_t kEngineRoundsPerCheck = 3;  // rounds enqueued between looks at the head
+
+static void heavy_engine_device(DeviceBatch& db) {
+  mpld_context* ctx = db.ctx;
+  hipStream_t s = ctx->stream;
+  db.sp_rounds = db.sp_tasks_run = db.sp_heavy = db.sp_reruns = 0;
+  // which register-tier components stopped at the first cap
+  if (!db.sp_host_recs.reserve(sizeof(DevRecord) * (size_t)std::max(1, db.num_comps)))
+    fail(MPLD_E_NOMEM, "heavy-component engine: pinned host memory");
+  const DevRecord* recs = db.sp_host_recs.as<DevRecord>();
+  check_hip(hipMemcpyAsync(db.sp_host_recs.p, db.recs.p, sizeof(DevRecord) * (size_t)db.num_comps,
+                           hipMemcpyDeviceToHost, s), "heavy: records");
+  check_hip(hipStreamSynchronize(s), "heavy: first pass");
+  std::vector<int32_t> heavy;   // launch-order register items
+  for (int32_t i = 0; i < db.n_reg; ++i)
+    if (recs[db.host_desc[i].comp].status < 0) heavy.push_back(i);
+  if (heavy.empty()) return;
+  const int32_t H = (int32_t)heavy.size();
+  if (H > kEngineTaskCap) fail(MPLD_E_INTERNAL, "heavy-component engine: too many heavy components");
+  db.sp_heavy = H;
+  int levels = db.tune.heavy_levels > 0 ? db.tune.heavy_levels : split_levels(db.k);
+  int64_t kp = 1;
+  for (int l = 0; l < levels; ++l) kp *= db.k;
+  while (levels > 1 && kp > 512) {
+    kp /= db.k;
+    --levels;
+  }
+  // device areas: head + per-component explored nodes and limits; tasks,
+  // result blocks, item pool
+  const size_t meta_bytes = sizeof(EngineHead) + 16 * (size_t)H;
+  if (db.en_meta.bytes < meta_bytes) db.en_meta.alloc(ctx, meta_bytes);
+  if (!db.en_tasks.p) {
+    db.en_tasks.alloc(ctx, sizeof(EngineTask) * (size_t)kEngineTaskCap);
+    db.en_blocks.alloc(ctx, (size_t)kSplitBlockBytes * kEngineTaskCap);
+    db.en_pool.alloc(ctx, sizeof(EngineItem) * (size_t)kEnginePoolCap);
+  }
+  auto* head = db.en_meta.as<EngineHead>();
+  auto* hc_nodes = reinterpret_cast<unsigned long long*>(db.en_meta.as<uint8_t>() + sizeof(EngineHead));
+  auto* hc_limit = reinterpret_cast<uint64_t*>(db.en_meta.as<uint8_t>() + sizeof(EngineHead) + 8 * (size_t)H);
+  // staging: the meta area, then the root tasks
+  const size_t roots_at = (meta_bytes + 255) / 256 * 256;
+  const size_t stage_bytes = roots_at + sizeof(EngineTask) * (size_t)H;
+  if (!db.sp_host_tasks.reserve(stage_bytes)) fail(MPLD_E_NOMEM, "heavy-component engine: pinned host memory");
+  uint8_t* st = db.sp_host_tasks.as<uint8_t>();
+  std::memset(st, 0, stage_bytes);
+  EngineHead* h0 = reinterpret_cast<EngineHead*>(st);
+  h0->alloc = H;
+  uint64_t* lim = reinterpret_cast<uint64_t*>(st + sizeof(EngineHead) + 8 * (size_t)H);
+  EngineTask* roots = reinterpret_cast<EngineTask*>(st + roots_at);
+  for (int32_t h = 0; h < H; ++h) {
+    const uint64_t budget = (uint64_t)db.host_desc[heavy[h]].budget;
+    lim[h] = budget > (UINT64_MAX / 4) ? UINT64_MAX : 2 * budget + (uint64_t)db.tune.heavy_round_cap;
+    roots[h].item = heavy[h];
+    roots[h].depth = 0;
+    roots[h].hc = h;
+    roots[h].skip = 0;
+  }
+  check_hip(hipMemcpyAsync(db.en_meta.p, st, meta_bytes, hipMemcpyHostToDevice, s), "heavy: engine head");
+  check_hip(hipMemcpyAsync(db.en_tasks.p, roots, sizeof(EngineTask) * (size_t)H, hipMemcpyHostToDevice, s),
+            "heavy: root tasks");
+  const int grid = std::max(1, ctx->num_cus * ctx->reg_blocks_per_cu);
+  auto* tasks = db.en_tasks.as<EngineTask>();
+  auto* blocks = db.en_blocks.as<uint8_t>();
+  auto* pool = db.en_pool.as<EngineItem>();
+  // head read back into the result staging area
+  if (!db.sp_host_out.reserve(sizeof(EngineHead))) fail(MPLD_E_NOMEM, "heavy-component engine: pinned host memory");
+  EngineHead hh{};
+  for (int32_t r = 0;;) {
+    for (int i = 0; i < kEngineRoundsPerCheck; ++i, ++r) {
+      check_hip(launch_engine_advance(head, kEngineTaskCap, s), "heavy: advance");
+      check_hip(launch_engine_round(db.k, grid, head, tasks, kEngineTaskCap, blocks, pool, kEnginePoolCap,
+                                    db.regitems.as<RegItem>(), hc_nodes, hc_limit,
+                                    (uint64_t)db.tune.heavy_round_cap, (uint32_t)levels, s),
+                "heavy: round");
+    }
+    check_hip(hipMemcpyAsync(db.sp_host_out.p, head, sizeof(EngineHead), hipMemcpyDeviceToHost, s),
+              "heavy: engine head");
+    check_hip(hipStreamSynchronize(s), "heavy: rounds");
+    std::memcpy(&hh, db.sp_host_out.p, sizeof(hh));
+    if (std::min(hh.alloc, kEngineTaskCap) == hh.end) break;   // the last round added no task
+    if (r >= kEngineMaxRounds) fail(MPLD_E_INTERNAL, "heavy-component engine: too many rounds");
+  }
+  const int32_t ntasks = std::min(hh.alloc, kEngineTaskCap);
+  const int32_t nitems = std::min(hh.pool, kEnginePoolCap);
+  db.sp_rounds = hh.rounds;
+  db.sp_tasks_run = ntasks;
+  const size_t blocks_bytes = (size_t)kSplitBlockBytes * (size_t)ntasks;
+  const size_t items_at = (blocks_bytes + 255) / 256 * 256;
+  if (!db.sp_host_out.reserve(items_at + sizeof(EngineItem) * (size_t)nitems))
+    fail(MPLD_E_NOMEM, "heavy-component engine: pinned host memory");
+  check_hip(hipMemcpyAsync(db.sp_host_out.p, blocks, blocks_bytes, hipMemcpyDeviceToHost, s),
+            "heavy: result blocks");
+  if (nitems > 0)
+    check_hip(hipMemcpyAsync(db.sp_host_out.as<uint8_t>() + items_at, pool, sizeof(EngineItem) * (size_t)nitems,
+                             hipMemcpyDeviceToHost, s), "heavy: items");
+  check_hip(hipStreamSynchronize(s), "heavy: results");
+  // one sequential copy out of the page-locked staging area: the walk
+  // below reads the blocks and items in tree order, and scattered reads of
+  // page-locked memory cost several times more than of ordinary memory
+  db.sp_host_copy.resize(items_at + sizeof(EngineItem) * (size_t)nitems);
+  std::memcpy(db.sp_host_copy.data(), db.sp_host_out.p, db.sp_host_copy.size());
+  const uint8_t* hb = db.sp_host_copy.data();
+  const EngineItem* hi = reinterpret_cast<const EngineItem*>(hb + items_at);
+  auto result = [&](int32_t t) {
+    SplitResult r;
+    std::memcpy(&r, hb + (size_t)kSplitBlockBytes * (size_t)t, sizeof(r));
+    return r;
+  };
+  auto solution = [&](int32_t t) { return reinterpret_cast<const int8_t*>(hb + (size_t)kSplitBlockBytes * t + kSplitSolOffset); };
+  // each component in search order: a depth-first walk of its task tree
+  std::vector<HeavyWrite> wb;
+  std::vector<int32_t> rerun;
+  struct Walk { int32_t task, next; };
+  std::vector<Walk> stack;
+  for (int32_t h = 0; h < H; ++h) {
+    const DevDesc& d = db.host_desc[heavy[h]];
+    const uint64_t budget = (uint64_t)d.budget;
+    uint64_t acc = 0;
+    bool redo = false, found = false;
+    const int8_t* sol = nullptr;
+    stack.clear();
+    stack.push_back({h, -1});
+    while (!stack.empty() && !redo && !found) {
+      Walk& w = stack.back();
+      const SplitResult r = result(w.task);
+      if (w.next < 0) {   // first visit
+        if (r.status == MPLD_INFEASIBLE || r.status == MPLD_FEASIBLE) {
+          acc += r.nodes;
+          if (acc > budget) { redo = true; break; }
+          if (r.status == MPLD_FEASIBLE) { found = true; sol = solution(w.task); break; }
+          stack.pop_back();
+          continue;
+        }
+        if (r.status != -1) { redo = true; break; }   // not split: budget or space
+        if (r.nitems < 1 || (int64_t)r.item_off + r.nitems > nitems)
+          fail(MPLD_E_INTERNAL, "heavy-component engine: bad task result");
+        w.next = 0;
+      }
+      if (w.next >= r.nitems) { stack.pop_back(); continue; }
+      const EngineItem it = hi[r.item_off + (uint32_t)w.next++];
+      acc += it.seg;
+      if (acc > budget) { redo = true; break; }
+      if (it.kind == 1) { stack.pop_back(); continue; }
+      if (it.kind == 2) { found = true; sol = solution(w.task); break; }
+      if (it.child < 0 || it.child >= ntasks) fail(MPLD_E_INTERNAL, "heavy-component engine: bad subtask");
+      const int32_t child = it.child;
+      stack.push_back({child, -1});   // invalidates w
+    }
+    if (redo) { rerun.push_back(heavy[h]); continue; }
+    HeavyWrite e{};
+    e.comp = d.comp;
+    e.out_off = d.out_off;
+    e.n = d.n;
+    e.rec.status = found ? MPLD_FEASIBLE : MPLD_INFEASIBLE;
+    e.rec.depth = found ? d.n : 0;
+    e.rec.nodes = acc;
+    e.rec.hash = 0xcbf29ce484222325ull;
+    if (found) std::memcpy(e.colors, sol, (size_t)d.n);
+    else std::memset(e.colors, -1, (size_t)d.n);
+    wb.push_back(e);
+  }
+  for (int32_t item : rerun) {
+    ++db.sp_reruns;
+    check_hip(launch_reg_single(false, db.k, db.regitems.as<RegItem>(), item, db.recs.as<DevRecord>(),
+                                db.colors.as<int8_t>(), s), "heavy: sequential re-run");
+  }
+  if (!wb.empty()) {
+    if (!db.sp_host_writes.reserve(sizeof(HeavyWrite) * wb.size()))
+      fail(MPLD_E_NOMEM, "heavy-component engine: pinned host memory");
+    if (db.sp_writes.bytes < sizeof(HeavyWrite) * wb.size())
+      db.sp_writes.alloc(ctx, sizeof(HeavyWrite) * wb.size());
+    std::memcpy(db.sp_host_writes.p, wb.data(), sizeof(HeavyWrite) * wb.size());
+    check_hip(hipMemcpyAsync(db.sp_writes.p, db.sp_host_writes.p, sizeof(HeavyWrite) * wb.size(),
+                             hipMemcpyHostToDevice, s), "heavy: write-back upload");
+    check_hip(launch_heavy_writeback(db.sp_writes.as<HeavyWrite>(), (int32_t)wb.size(),
+                                     db.recs.as<DevRecord>(), db.colors.as<int8_t>(), s),
+              "heavy: write-back");
+  }
+  check_hip(hipStreamSynchronize(s), "heavy: write back");
+}
+
+static void heavy_engine_host(DeviceBatch& db);
+
 static void heavy_engine(DeviceBatch& db) {
+  if (db.tune.heavy_device) heavy_engine_device(db);
+  else heavy_engine_host(db);
+}
+
+static void heavy_engine_host(DeviceBatch& db) {
   mpld_context* ctx = db.ctx;
   hipStream_t s = ctx->stream;
   db.sp_rounds = db.sp_tasks_run = db.sp_heavy = db.sp_reruns = 0;

@@ -27,6 +27,16 @@ hipError_t launch_reg_split(int k, int grid, const SplitTask* tasks, int32_t nta
                             int32_t* counter, const RegItem* regitems, uint64_t cap,
                             uint32_t levels, uint8_t* out, SplitItem* pool,
                             int32_t* pool_count, hipStream_t s);
+// Device-resident heavy engine: move the round window on (one thread), and
+// run the current round's tasks (persistent grid; the window comes from
+// head).  hc_nodes / hc_limit: per heavy component, explored nodes and the
+// limit past which its tasks stop splitting.
+hipError_t launch_engine_advance(EngineHead* head, int32_t task_cap, hipStream_t s);
+hipError_t launch_engine_round(int k, int grid, EngineHead* head, EngineTask* tasks,
+                               int32_t task_cap, uint8_t* blocks, EngineItem* pool,
+                               int32_t pool_cap, const RegItem* regitems,
+                               unsigned long long* hc_nodes, const uint64_t* hc_limit,
+                               uint64_t cap, uint32_t levels, hipStream_t s);
 // Scatters `count` resolved heavy components (records and colors).
 hipError_t launch_heavy_writeback(const HeavyWrite* w, int32_t count, DevRecord* recs,
                                   int8_t* colors, hipStream_t s);
@@ -162,6 +172,7 @@ struct Tune {
   int32_t heavy_first_cap = 512;   // heavy-component engine: first-pass node cap
   int32_t heavy_round_cap = 256;   // nodes per subtree task and round
   int32_t heavy_levels = 0;        // levels per split; 0 = by k (4, 3 or 2)
+  int32_t heavy_device = 1;        // 1: rounds chained on the device; 0: host-driven rounds
 };
 
 // Adds one component (local numbering, pairs i < j or j < i) to the image.
@@ -180,6 +191,8 @@ struct DeviceBatch {
   DevBuf dev_keys, dev_stacks;      // device-wide tier
   DevBuf sp_tasks, sp_out, sp_pool, sp_writes;      // heavy-component engine
   PinnedBuf sp_host_tasks, sp_host_out, sp_host_pool, sp_host_writes, sp_host_recs;
+  DevBuf en_meta, en_tasks, en_blocks, en_pool;     // device-resident rounds
+  std::vector<uint8_t> sp_host_copy;                // engine results in ordinary memory
   int64_t sp_rounds = 0, sp_tasks_run = 0, sp_heavy = 0, sp_reruns = 0;  // last solve's stats
   Tune tune;
   int32_t n_reg = 0, n_lds = 0, n_big = 0, n_dev = 0;

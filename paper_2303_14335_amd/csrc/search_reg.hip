@@ -125,9 +125,12 @@ __device__ __forceinline__ void reg_init(RegState<K>& s, int32_t n, int32_t k) {
 }
 
 // c == j ? a : b on uniform 64-bit words (one compare, one 64-bit select).
+// The 32-bit scalar operands of these inline-asm helpers go through
+// readfirstlane: free for a value already in an SGPR, and it keeps a value
+// the compiler's divergence analysis lost track of out of a VGPR operand.
 __device__ __forceinline__ uint64_t sel_eq(uint32_t c, int j, uint64_t a, uint64_t b) {
   uint64_t r;
-  asm("s_cmp_eq_u32 %1, %2\n\ts_cselect_b64 %0, %3, %4" : "=s"(r) : "s"(c), "i"(j), "s"(a), "s"(b) : "scc");
+  asm("s_cmp_eq_u32 %1, %2\n\ts_cselect_b64 %0, %3, %4" : "=s"(r) : "s"(uniform(c)), "i"(j), "s"(a), "s"(b) : "scc");
   return r;
 }
 
@@ -138,7 +141,7 @@ __device__ __forceinline__ uint32_t rows_of(const Planes<K>& O, uint32_t v) {
 #pragma unroll
   for (int j = 0; j < K; ++j) {
     uint32_t b;
-    asm("s_bitcmp1_b64 %1, %2\n\ts_cselect_b32 %0, %3, 0" : "=s"(b) : "s"(O[j]), "s"(v), "i"(1 << j) : "scc");
+    asm("s_bitcmp1_b64 %1, %2\n\ts_cselect_b32 %0, %3, 0" : "=s"(b) : "s"(O[j]), "s"(uniform(v)), "i"(1 << j) : "scc");
     R |= b;
   }
   return R;
@@ -190,7 +193,7 @@ __device__ __forceinline__ uint32_t first_color(const Planes<K>& O, const uint32
   uint32_t c = K - 1;
 #pragma unroll
   for (int j = K - 2; j >= 0; --j)
-    asm("s_bitcmp1_b64 %1, %2\n\ts_cselect_b32 %0, %3, %0" : "+s"(c) : "s"(O[j]), "s"(v), "i"(j) : "scc");
+    asm("s_bitcmp1_b64 %1, %2\n\ts_cselect_b32 %0, %3, %0" : "+s"(c) : "s"(O[j]), "s"(uniform(v)), "i"(j) : "scc");
   return c;
 }
 
@@ -296,7 +299,7 @@ __device__ __forceinline__ void reg_run(RegState<K>& s, const uint32_t nb_lo, co
       if (TRACE) s.h = trace_node(s.h, s.depth, s.row_in, v, (uint32_t)__popc(rows_of(s.O, v)));
       c = first_color(s.O, v);
       alt = (ge2 >> v) & 1ull;
-      asm("s_bitset0_b64 %0, %1" : "+s"(s.P) : "s"(v));   // cover column v
+      asm("s_bitset0_b64 %0, %1" : "+s"(s.P) : "s"(uniform(v)));   // cover column v
     } else {
       // a column without rows (the first by index is the one chosen): dead end
       if (TRACE) s.h = trace_node(s.h, s.depth, s.row_in, low_bit(zero), 0);
@@ -739,6 +742,228 @@ hipError_t launch_reg_split(int k, int grid, const SplitTask* tasks, int32_t nta
     constexpr int K = decltype(kp)::value;
     hipLaunchKernelGGL((reg_split_kernel<K>), dim3(grid), dim3(256), 0, s, tasks, ntasks, counter,
                        regitems, cap, levels, out, pool, pool_count);
+  });
+  return hipGetLastError();
+}
+
+// ---- device-resident heavy engine ------------------------------------------
+
+// Enumerates the top `levels` levels of the subtree at depth d (as
+// reg_enumerate).  With items == nullptr it only counts; returns the items
+// and sets nchild to the kind-0 items.  Otherwise item j goes to items[j]
+// and the i-th subtask becomes task children_base + i: its path is this
+// task's path plus the rows down to depth d + levels, which sit in lanes
+// 0 .. d + levels - 1 of the frame register.
+template <int K>
+__device__ __forceinline__ int32_t engine_enumerate(RegState<K>& s, const uint32_t nb_lo,
+                                                    const uint32_t nb_hi, const int32_t n,
+                                                    const uint32_t d, const uint32_t levels,
+                                                    EngineItem* __restrict__ items,
+                                                    EngineTask* __restrict__ tasks,
+                                                    const int32_t children_base,
+                                                    const int32_t item_idx, const int32_t hc,
+                                                    int8_t* __restrict__ sol, int32_t& nchild) {
+  const uint32_t lane = __lane_id();
+  const uint32_t limit = d + levels;
+  uint32_t seg = 0;
+  int32_t count = 0;
+  nchild = 0;
+  auto emit = [&](uint32_t kind) {
+    if (items != nullptr) {
+      if (kind == 0) {   // the subtask: every lane writes its row, same header
+        EngineTask* ch = tasks + children_base + nchild;
+        ch->rows[lane] = lane < limit ? (uint16_t)(s.fr & 0xffffu) : (uint16_t)0;
+        ch->item = item_idx;
+        ch->depth = (int32_t)limit;
+        ch->hc = hc;
+        ch->skip = 0;
+      }
+      if (lane == ((uint32_t)count & 63u)) {   // one owner lane per item
+        EngineItem it;
+        it.seg = seg;
+        it.kind = kind;
+        it.child = kind == 0 ? children_base + nchild : -1;
+        it.pad = 0;
+        items[count] = it;
+      }
+    }
+    if (kind == 0) ++nchild;
+    ++count;
+    seg = 0;
+  };
+  for (;;) {
+    uint32_t v = 0, c = 0;
+    uint64_t alt = 0;
+    bool back;
+    if (s.depth == limit) {
+      emit(0);        // a subtask root: leave it to its own task
+      back = true;
+    } else {
+      ++seg;
+      if (s.P == 0) {   // a solution among the top levels
+        if (lane < s.depth && (s.fr & 0xffu) < (uint32_t)n)
+          sol[s.fr & 0xffu] = (int8_t)((s.fr >> 8) & 0xffu);
+        emit(2);
+        break;
+      }
+      uint64_t any = s.O[0];
+#pragma unroll
+      for (int j = 1; j < K; ++j) any |= s.O[j];
+      back = (s.P & ~any) != 0;
+      if (!back) {
+        uint64_t ge2;
+        v = low_bit(min_count_columns(s.O, s.P, ge2));
+        c = first_color(s.O, v);
+        alt = (ge2 >> v) & 1ull;
+        s.P &= ~(1ull << v);
+      }
+    }
+    if (back && !retreat(s, d, v, c, alt)) {
+      emit(1);
+      break;
+    }
+    take_row(s, rdlane64(nb_lo, nb_hi, v), v, c, alt);
+  }
+  return count;
+}
+
+// Moves the round window on: the subtasks appended by the last round are
+// the next round's tasks.
+__global__ void engine_advance_kernel(EngineHead* head, int32_t task_cap) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    head->begin = head->end;
+    head->end = head->alloc < task_cap ? head->alloc : task_cap;
+    head->pop = 0;
+    head->rounds += 1;
+  }
+}
+
+// One round: every task of the window explores its subtree up to `cap`
+// nodes (result block g at blocks + g * kSplitBlockBytes); a capped task
+// reserves item and task space with atomics and appends its split.  A
+// component whose explored nodes pass its limit, or a split that does not
+// fit, is not split (status kEngineSkipped; its reserved task slots that
+// exist are marked skip) and the host re-runs that component sequentially.
+template <int K>
+__global__ __launch_bounds__(256) void engine_round_kernel(
+    EngineHead* __restrict__ head, EngineTask* __restrict__ tasks, int32_t task_cap,
+    uint8_t* __restrict__ blocks, EngineItem* __restrict__ pool, int32_t pool_cap,
+    const RegItem* __restrict__ regitems, unsigned long long* __restrict__ hc_nodes,
+    const uint64_t* __restrict__ hc_limit, uint64_t cap, uint32_t levels) {
+  const uint32_t wpb = blockDim.x >> 6;
+  const int32_t gw = (int32_t)(gridDim.x * wpb);
+  const uint32_t lane = __lane_id();
+  const int32_t begin = (int32_t)uniform((uint32_t)head->begin);
+  const int32_t nt = (int32_t)uniform((uint32_t)head->end) - begin;
+  // the grid is fixed and usually much larger than the round: plain block
+  // order deals the first tasks to all eight XCDs (the XCD-range renumbering
+  // of the other kernels would put them all on the first XCD)
+  int32_t t = (int32_t)uniform(blockIdx.x * wpb + (threadIdx.x >> 6));
+  while (t < nt) {
+    const int32_t g = begin + t;
+    const EngineTask* task = tasks + g;
+    uint8_t* block = blocks + (uint64_t)g * kSplitBlockBytes;
+    int8_t* sol = reinterpret_cast<int8_t*>(block + kSplitSolOffset);
+    SplitResult res;
+    res.status = kEngineSkipped;
+    res.nitems = 0;
+    res.nodes = 0;
+    res.item_off = 0;
+    res.pad = 0;
+    if (uniform((uint32_t)task->skip) == 0) {
+      const int32_t it = (int32_t)uniform((uint32_t)task->item);
+      const uint32_t d = uniform((uint32_t)task->depth);
+      const int32_t hc = (int32_t)uniform((uint32_t)task->hc);
+      const DevDesc dd = regitems[it].d;
+      const uint64_t nb = regitems[it].nb[lane];
+      const uint32_t nb_lo = (uint32_t)nb, nb_hi = (uint32_t)(nb >> 32);
+      RegState<K> s;
+      reg_init(s, dd.n, dd.k);
+      reg_replay(s, nb_lo, nb_hi, dd.k, task->rows, d);
+      reg_run<false, K>(s, nb_lo, nb_hi, dd.k, ~0ull, cap, d);
+      res.nodes = s.nodes;
+      if (s.status == MPLD_FEASIBLE) {
+        if (lane < s.depth && (s.fr & 0xffu) < (uint32_t)dd.n)
+          sol[s.fr & 0xffu] = (int8_t)((s.fr >> 8) & 0xffu);
+        res.status = MPLD_FEASIBLE;
+      } else if (s.status == MPLD_INFEASIBLE) {
+        res.status = MPLD_INFEASIBLE;
+      } else {
+        // capped: count the split, then reserve space for it.  All of the
+        // atomics are taken by lane 63 in one branch (a lane-0 branch here
+        // could be merged with the queue pop's and split the wave).
+        RegState<K> r;
+        reg_init(r, dd.n, dd.k);
+        reg_replay(r, nb_lo, nb_hi, dd.k, task->rows, d);
+        int32_t nchild = 0;
+        const int32_t nitems = engine_enumerate(r, nb_lo, nb_hi, dd.n, d, levels, nullptr, nullptr,
+                                                0, it, hc, sol, nchild);
+        // the component's explored nodes: the guard reads the total as of
+        // the previous round (a plain load), and the add does not wait for
+        // its result, so the reservations are the only round trips
+        uint32_t io = 0xffffffffu, cb = 0xffffffffu;
+        if (lane == 63u) {
+          const unsigned long long seen = __hip_atomic_load(hc_nodes + hc, __ATOMIC_RELAXED,
+                                                            __HIP_MEMORY_SCOPE_AGENT);
+          __hip_atomic_fetch_add(hc_nodes + hc, (unsigned long long)s.nodes, __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_AGENT);
+          if (seen + s.nodes <= hc_limit[hc]) {
+            io = (uint32_t)atomicAdd(&head->pool, nitems);
+            cb = (uint32_t)atomicAdd(&head->alloc, nchild);
+          }
+        }
+        io = (uint32_t)__builtin_amdgcn_readlane((int)io, 63);
+        cb = (uint32_t)__builtin_amdgcn_readlane((int)cb, 63);
+        const bool limited = io == 0xffffffffu;
+        const bool fits = !limited && (int64_t)io + nitems <= pool_cap &&
+                          (int64_t)cb + nchild <= task_cap;
+        if (fits) {
+          reg_init(r, dd.n, dd.k);
+          reg_replay(r, nb_lo, nb_hi, dd.k, task->rows, d);
+          int32_t nc2 = 0;
+          engine_enumerate(r, nb_lo, nb_hi, dd.n, d, levels, pool + io, tasks, (int32_t)cb, it, hc,
+                           sol, nc2);
+          res.status = -1;
+          res.nitems = nitems;
+          res.item_off = io;
+        } else {
+          if (!limited) {
+            // reserved slots that exist must not be run as tasks (a loop
+            // with a uniform trip count: every branch here stays uniform)
+            for (int32_t j0 = 0; j0 < nchild; j0 += 64) {
+              const int32_t j = j0 + (int32_t)lane;
+              if (j < nchild && (int64_t)cb + j < task_cap) tasks[cb + j].skip = 1;
+            }
+            if (lane == 63u) atomicExch(&head->overflow, 1);
+          }
+          res.status = kEngineSkipped;
+        }
+      }
+    }
+    *reinterpret_cast<SplitResult*>(block) = res;   // same value from every lane
+    if (gw >= nt) break;
+    int32_t q = 0;
+    if (lane == 0) q = atomicAdd(&head->pop, 1);
+    q = (int32_t)uniform((uint32_t)q);
+    t = gw + q;
+  }
+}
+
+hipError_t launch_engine_advance(EngineHead* head, int32_t task_cap, hipStream_t s) {
+  hipLaunchKernelGGL(engine_advance_kernel, dim3(1), dim3(64), 0, s, head, task_cap);
+  return hipGetLastError();
+}
+
+hipError_t launch_engine_round(int k, int grid, EngineHead* head, EngineTask* tasks,
+                               int32_t task_cap, uint8_t* blocks, EngineItem* pool,
+                               int32_t pool_cap, const RegItem* regitems,
+                               unsigned long long* hc_nodes, const uint64_t* hc_limit,
+                               uint64_t cap, uint32_t levels, hipStream_t s) {
+  if (levels < 1 || levels > (uint32_t)kSplitMaxLevels) return hipErrorInvalidValue;
+  with_planes(k, [&](auto kp) {
+    constexpr int K = decltype(kp)::value;
+    hipLaunchKernelGGL((engine_round_kernel<K>), dim3(grid), dim3(256), 0, s, head, tasks, task_cap,
+                       blocks, pool, pool_cap, regitems, hc_nodes, hc_limit, cap, levels);
   });
   return hipGetLastError();
 }

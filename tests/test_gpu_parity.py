@@ -281,6 +281,27 @@ def test_split_heavy_config2_matches_oracle(ctx):
     assert got.components["nodes"].max() > 100000   # a heavy component was split
 
 
+@pytest.mark.parametrize("device_rounds", [0, 1])
+def test_split_heavy_engines_agree(ctx, device_rounds):
+    """Both heavy-component engines (rounds driven by the host, or chained on
+    the device with the host resolving once) give the sequential result."""
+    import paper_2303_14335_amd as mp
+    w, rects = graph_of(2)
+    say("config 2, heavy engine with device rounds =", device_rounds)
+    g = mp.mpld_build_graph(rects, w.dmin_nm, w.split_len_nm)
+    ref = oracle.decompose(oracle.Graph(g.num_nodes, g.ce, g.se), w.k, w.budget)
+    b = mp.Batch(ctx, g, w.k, w.budget, SIMPLIFY)
+    b.set_tune(heavy_device=device_rounds, heavy_first_cap=256, heavy_round_cap=128)
+    for rep in range(2):
+        b.solve(split=True)
+        got = b.result()
+        for f in ("status", "nodes", "depth_at_stop"):
+            assert np.array_equal(got.components[f], ref.comps[f]), (f, rep)
+        assert np.array_equal(got.colors, ref.colors), rep
+    assert b.info()["split_rounds"] >= 3
+    b.close()
+
+
 def heavy_graphs(seed, count, n_lo, n_hi, deg):
     rng = np.random.default_rng(seed)
     out = []
