@@ -72,12 +72,12 @@ void image_add(Image& im, mpld_context* ctx, int32_t n, const int32_t* pairs, in
       im.dev_stack_words = std::max(im.dev_stack_words, device_tier_stack_words(n, (int32_t)maxdeg));
       im.dev_max_n = std::max(im.dev_max_n, n);
       im.q_dev.push_back(id);
-    } else if (!force_glb && small <= limit) {
+    } else if (!force_glb && small <= limit && (n + 63) / 64 <= 64) {
       im.lds_bytes_small = std::max(im.lds_bytes_small, small);
       im.q_lds.push_back(id);
     } else if (big <= ctx->lds_per_block) {
       im.lds_bytes_big = std::max(im.lds_bytes_big, big);
-      im.big_stack_words = std::max(im.big_stack_words, lds_stack_words(n, (int32_t)maxdeg));
+      im.big_stack_words = std::max(im.big_stack_words, lds_stack_words(n, k, adj_words));
       im.q_big.push_back(id);
     } else {
       fail(MPLD_E_UNSUPPORTED, "component of " + std::to_string(n) + " nodes needs " +

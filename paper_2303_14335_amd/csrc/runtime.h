@@ -58,7 +58,7 @@ hipError_t launch_lds_single(bool trace, bool big, int lds_bytes, const DevDesc*
 // LDS bytes of one LDS-tier component (adj_words = n + 1 + 2m) and the
 // global stack words of a big one.
 int64_t lds_bytes_for(int32_t n, int32_t k, int64_t adj_words, int32_t max_deg, bool big);
-int64_t lds_stack_words(int32_t n, int32_t max_deg);
+int64_t lds_stack_words(int32_t n, int32_t k, int64_t adj_words);
 // Device-wide tier (cooperative launch over `grid` workgroups, one per CU).
 hipError_t launch_device_tier(bool trace, int grid, int lds_bytes, const DevDesc* desc,
                               const uint32_t* adj32, unsigned long long* keys, uint64_t* stacks,

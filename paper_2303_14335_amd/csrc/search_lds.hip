@@ -2,24 +2,30 @@
 // than 64 nodes), one 64-lane wavefront per component.
 //
 // Same matrix and rules as the register tier (Sec. 2.3, Algorithm 1), with
-// state that scales past one lane per node:
-//   rm[v]    open colors of node v (one byte; 0 once v's column is covered);
-//   B[t]     bitset of uncovered nodes whose column has exactly t rows,
-//            t = 0..k (W = ceil(n/64) words each);
-//   S[t]     summary of B[t]: bit w set whenever word w of B[t] may be
-//            nonzero (set on every insert, cleared lazily at selection).
-// Column choice: for t = 0..k, the lowest set summary bit leads to the
-// lowest nonzero word of B[t] and its lowest bit is the lowest index with t
-// rows - the min-count, lowest-index column, without scanning all columns.
-// Cover of row (v, c) walks v's neighbour list, one neighbour per lane:
-// lanes whose neighbour still has color c open clear it and move the
-// neighbour from B[t] to B[t-1] (LDS atomics, several lanes may share a
-// word); the ballot of those lanes is the undo record (Eq. 2 uncover ORs
-// them back, moving each neighbour up one bucket).
+// the state spread over W = ceil(n/64) words per bit-plane:
+//   PL[c][w]  (c < k) color plane: bit v set while color c is open at v,
+//             i.e. while row (v, c) is active;
+//   PL[k][w]  uncovered primary columns P.
+// Column choice (count + select): lane l takes words l, l+64, ...; a
+// bit-sliced adder over the k planes gives per-word count-bit planes,
+// narrowing P from the top count bit leaves the lowest-count columns of the
+// word, and the key (count << 24 | index) of its lowest one goes into a
+// DPP min-reduction over the wave: the global minimum is the fewest-rows,
+// lowest-index column.  All-ones means P is empty (a solution).
+// Cover of row (v, c) (Eq. 2): P loses v, and each neighbour u of v loses
+// color c through an LDS atomic AND that returns the old word, so a lane
+// knows whether it removed an active row; those rows go to an undo log of
+// 32-bit entries (plane << 26 | node), after one entry for v's P bit.
+// Uncover (Eq. 2) ORs entries back.  Because OR commutes and the removed
+// bits of different levels are disjoint, a backtrack over several levels is
+// one lane-parallel pass over the log suffix: a per-depth bit set marks
+// levels whose column still has untried rows, and the deepest such level
+// is found with a word scan instead of popping level by level.
 //
-// Placement: rm, B, S always in LDS.  Small components also keep their
-// neighbour lists and search stack in LDS; "big" components keep them in
-// global memory (stack in a per-worker scratch area).
+// Placement: the planes and the per-depth bit set always live in LDS.
+// Small components also keep their neighbour lists, level headers and undo
+// log in LDS; "big" components keep those in global memory (header and log
+// in a per-worker scratch area).
 #include <hip/hip_runtime.h>
 
 #include "device_types.h"
@@ -30,7 +36,8 @@ namespace mpld {
 static constexpr uint64_t kFnvOffsetL = 0xcbf29ce484222325ull;
 static constexpr uint64_t kFnvPrimeL = 0x100000001b3ull;
 static constexpr uint32_t kNoneL = 0xffffffffu;
-static constexpr int32_t kStatusBroken = 3;   // reported to the host as an internal error
+static constexpr uint32_t kNoKey = 0xffffffffu;
+static constexpr uint32_t kEntryNodeBits = 26;   // undo entry: plane << 26 | node
 
 __device__ __forceinline__ uint64_t fnv_u32_l(uint64_t h, uint32_t v) {
 #pragma unroll
@@ -55,231 +62,269 @@ __device__ __forceinline__ uint32_t uni(uint32_t x) {
 __device__ __forceinline__ uint64_t uni64(uint64_t x) {
   return ((uint64_t)uni((uint32_t)(x >> 32)) << 32) | uni((uint32_t)x);
 }
-__device__ __forceinline__ uint64_t rdlane64(uint64_t x, uint32_t lane) {
-  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, (int)lane);
-  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), (int)lane);
-  return ((uint64_t)hi << 32) | lo;
+
+constexpr int bits_for(int x) { return x == 0 ? 0 : 1 + bits_for(x >> 1); }
+
+// Minimum over the wave: row_shr 1, 2, 4, 8 leave each row's minimum in its
+// lane 15; row_bcast 15 and 31 fold the four rows into lane 63.  A lane
+// with no source in a step reads all-ones, the identity of min.
+__device__ __forceinline__ uint32_t wave_min(uint32_t m) {
+  m = min(m, (uint32_t)__builtin_amdgcn_update_dpp(-1, (int)m, 0x111, 0xf, 0xf, false));
+  m = min(m, (uint32_t)__builtin_amdgcn_update_dpp(-1, (int)m, 0x112, 0xf, 0xf, false));
+  m = min(m, (uint32_t)__builtin_amdgcn_update_dpp(-1, (int)m, 0x114, 0xf, 0xf, false));
+  m = min(m, (uint32_t)__builtin_amdgcn_update_dpp(-1, (int)m, 0x118, 0xf, 0xf, false));
+  m = min(m, (uint32_t)__builtin_amdgcn_update_dpp(-1, (int)m, 0x142, 0xa, 0xf, false));
+  m = min(m, (uint32_t)__builtin_amdgcn_update_dpp(-1, (int)m, 0x143, 0xc, 0xf, false));
+  return (uint32_t)__builtin_amdgcn_readlane((int)m, 63);
+}
+
+// Key of the lowest-count, lowest-index uncovered column in word w:
+// (count << 24) | (64 w + bit), or kNoKey when the word has none.
+template <int K>
+__device__ __forceinline__ uint32_t word_key(const uint64_t* PL, uint32_t W, uint32_t w) {
+  constexpr int NB = bits_for(K);
+  uint64_t a[K];
+#pragma unroll
+  for (int c = 0; c < K; ++c) a[c] = PL[(uint32_t)c * W + w];
+  const uint64_t p = PL[(uint32_t)K * W + w];
+  uint64_t cnt[NB];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) cnt[b] = 0;
+#pragma unroll
+  for (int c = 0; c < K; ++c) {
+    uint64_t carry = a[c];
+#pragma unroll
+    for (int b = 0; b < bits_for(c + 1); ++b) {
+      const uint64_t t = cnt[b] & carry;
+      cnt[b] ^= carry;
+      carry = t;
+    }
+  }
+  uint64_t cand = p;
+  uint32_t t = 0;
+#pragma unroll
+  for (int b = NB - 1; b >= 0; --b) {
+    const uint64_t x = cand & ~cnt[b];
+    if (x) cand = x;
+    else t |= 1u << b;
+  }
+  const uint32_t key = (t << 24) | (w << 6) | (uint32_t)__builtin_ctzll(cand | (1ull << 63));
+  return p ? key : kNoKey;
 }
 
 // Byte layout of the LDS area of one component.
 struct LdsLayout {
-  uint32_t W, SW, frame_words, rm_off, b_off, s_off, adj_off, stk_off, total;
+  uint32_t W, E, pl_off, a_off, adj_off, hdr_off, ent_off, total;
 };
 
-__host__ __device__ inline LdsLayout lds_layout(int32_t n, int32_t k, int64_t adj_words,
-                                                int32_t max_deg, bool big) {
+// Undo-log capacity: one entry per level (its P bit) plus the removed rows,
+// at most one per (neighbour, color) pair and at most one per incidence.
+__host__ __device__ inline uint32_t lds_log_entries(int32_t n, int32_t k, int64_t adj_words) {
+  const int64_t incid = adj_words - n - 1;   // 2m
+  const int64_t nk = (int64_t)n * k;
+  return (uint32_t)(n + (incid < nk ? incid : nk));
+}
+
+__host__ __device__ inline LdsLayout lds_layout(int32_t n, int32_t k, int64_t adj_words, bool big) {
   LdsLayout L;
   L.W = (uint32_t)((n + 63) / 64);
-  L.SW = (L.W + 63) / 64;
-  L.frame_words = 1u + (uint32_t)((max_deg + 63) / 64);   // u64: header + removed masks
+  L.E = lds_log_entries(n, k, adj_words);
   uint32_t off = 0;
-  L.rm_off = off;
-  off += ((uint32_t)n + 7u) & ~7u;
-  L.b_off = off;
+  L.pl_off = off;
   off += 8u * (uint32_t)(k + 1) * L.W;
-  L.s_off = off;
-  off += 8u * (uint32_t)(k + 1) * L.SW;
+  L.a_off = off;
+  off += 8u * L.W;   // one bit per depth 0 .. n-1
   L.adj_off = off;
   if (!big) off += 4u * (uint32_t)adj_words;
   off = (off + 7u) & ~7u;
-  L.stk_off = off;
-  if (!big) off += 8u * L.frame_words * (uint32_t)n;
-  L.total = off;
+  L.hdr_off = off;
+  if (!big) off += 8u * (uint32_t)n;
+  L.ent_off = off;
+  if (!big) off += 4u * L.E;
+  L.total = (off + 7u) & ~7u;
   return L;
 }
 
-template <bool TRACE, bool BIG>
+// Level header: v | c << 24 | rows << 28 | log start << 36.
+__device__ __forceinline__ uint64_t make_hdr(uint32_t v, uint32_t c, uint32_t rows, uint32_t est) {
+  return (uint64_t)v | ((uint64_t)c << 24) | ((uint64_t)rows << 28) | ((uint64_t)est << 36);
+}
+
+template <bool TRACE, bool BIG, int K>
 __device__ void solve_lds(const DevDesc& d, const uint32_t* __restrict__ gadj, char* lds,
                           uint64_t* gstack, int8_t* __restrict__ colors,
                           DevRecord* __restrict__ rec) {
   const uint32_t lane = __lane_id();
-  const int32_t n = d.n, k = d.k;
-  // adjacency block: [0..n] row offsets, [n+1 ..] neighbour ids; the host
-  // stores the largest degree right after the ids.
-  const uint32_t adj_words = uni(gadj[n]) + (uint32_t)n + 1u;
-  const uint32_t mdeg = uni(gadj[adj_words]);
-  const LdsLayout L = lds_layout(n, k, adj_words, (int32_t)mdeg, BIG);
-  uint8_t* rm = reinterpret_cast<uint8_t*>(lds + L.rm_off);
-  uint64_t* B = reinterpret_cast<uint64_t*>(lds + L.b_off);
-  uint64_t* S = reinterpret_cast<uint64_t*>(lds + L.s_off);
+  const uint32_t n = (uint32_t)d.n;
+  // adjacency block: [0..n] row offsets, [n+1 ..] neighbour ids
+  const uint32_t adj_words = uni(gadj[n]) + n + 1u;
+  const LdsLayout L = lds_layout((int32_t)n, K, adj_words, BIG);
+  const uint32_t W = L.W;
+  uint64_t* PL = reinterpret_cast<uint64_t*>(lds + L.pl_off);
+  uint64_t* A = reinterpret_cast<uint64_t*>(lds + L.a_off);
   const uint32_t* adj;
-  uint64_t* stk;
+  uint64_t* hdr;
+  uint32_t* ent;
   if (BIG) {
     adj = gadj;
-    stk = gstack;
+    hdr = gstack;
+    ent = reinterpret_cast<uint32_t*>(gstack + n);
   } else {
     uint32_t* la = reinterpret_cast<uint32_t*>(lds + L.adj_off);
     for (uint32_t i = lane; i < adj_words; i += 64) la[i] = gadj[i];
     adj = la;
-    stk = reinterpret_cast<uint64_t*>(lds + L.stk_off);
+    hdr = reinterpret_cast<uint64_t*>(lds + L.hdr_off);
+    ent = reinterpret_cast<uint32_t*>(lds + L.ent_off);
   }
   const uint32_t* ids = adj + n + 1;
-  const uint32_t W = L.W, SW = L.SW, FW = L.frame_words;
   // initial state: every node uncovered with all k colors open
-  const uint8_t full = (uint8_t)((1u << k) - 1u);
-  for (uint32_t v = lane; v < (uint32_t)n; v += 64) rm[v] = full;
-  for (uint32_t i = lane; i < (uint32_t)(k + 1) * W; i += 64) {
-    const uint32_t t = i / W, w = i % W;
-    uint64_t val = 0;
-    if (t == (uint32_t)k) {
-      const uint32_t lo = w * 64u;
-      const uint32_t cnt = (uint32_t)n - lo >= 64u ? 64u : (uint32_t)n - lo;
-      val = cnt == 64u ? ~0ull : ((1ull << cnt) - 1ull);
-    }
-    B[i] = val;
+  for (uint32_t w = lane; w < W; w += 64) {
+    const uint32_t cnt = n - w * 64u >= 64u ? 64u : n - w * 64u;
+    const uint64_t val = cnt == 64u ? ~0ull : ((1ull << cnt) - 1ull);
+#pragma unroll
+    for (int c = 0; c <= K; ++c) PL[(uint32_t)c * W + w] = val;
+    if (BIG) A[w] = 0ull;
   }
-  for (uint32_t i = lane; i < (uint32_t)(k + 1) * SW; i += 64) {
-    const uint32_t t = i / SW, j = i % SW;
-    uint64_t val = 0;
-    if (t == (uint32_t)k) {
-      const uint32_t lo = j * 64u;
-      const uint32_t cnt = W - lo >= 64u ? 64u : W - lo;
-      val = cnt == 64u ? ~0ull : ((1ull << cnt) - 1ull);
-    }
-    S[i] = val;
-  }
+  // Small components (the host admits at most 64 words) keep the per-depth
+  // bit set in registers, word l in lane l; big ones keep it in LDS.
+  uint64_t areg = 0;
   __syncthreads();
 
-  uint32_t depth = 0, open = (uint32_t)n, row_in = kNoneL;
+  uint32_t depth = 0, row_in = kNoneL, esp = 0;
   uint64_t nodes = 0, h = kFnvOffsetL;
-  int32_t status;
+  int32_t status = -1;
   const uint64_t budget = (uint64_t)d.budget;
 
-  auto move_up = [&](uint32_t w, uint32_t t) {  // node w: bucket t -> t+1
-    const uint32_t word = w >> 6;
-    const uint64_t bit = 1ull << (w & 63u);
-    atomicAnd(reinterpret_cast<unsigned long long*>(&B[t * W + word]), ~bit);
-    atomicOr(reinterpret_cast<unsigned long long*>(&B[(t + 1) * W + word]), bit);
-    atomicOr(reinterpret_cast<unsigned long long*>(&S[(t + 1) * SW + (word >> 6)]),
-             1ull << (word & 63u));
-  };
-  auto move_down = [&](uint32_t w, uint32_t t) {  // node w: bucket t -> t-1
-    const uint32_t word = w >> 6;
-    const uint64_t bit = 1ull << (w & 63u);
-    atomicAnd(reinterpret_cast<unsigned long long*>(&B[t * W + word]), ~bit);
-    atomicOr(reinterpret_cast<unsigned long long*>(&B[(t - 1) * W + word]), bit);
-    atomicOr(reinterpret_cast<unsigned long long*>(&S[(t - 1) * SW + (word >> 6)]),
-             1ull << (word & 63u));
-  };
-
-  for (;;) {
+  while (status < 0) {
     // ---- one search node
     if (nodes == budget) { status = MPLD_BUDGET_EXHAUSTED; break; }
     ++nodes;
-    if (open == 0) {
+    uint32_t key = kNoKey;
+    for (uint32_t w = lane; w < W; w += 64) key = min(key, word_key<K>(PL, W, w));
+    key = wave_min(key);
+    if (key == kNoKey) {   // no uncovered column: the levels hold a solution
       if (TRACE) h = trace_node_l(h, depth, row_in, kNoneL, 0);
       status = MPLD_FEASIBLE;
       break;
     }
-    // column choice: smallest t with a nonzero bucket, lowest index in it
-    uint32_t v = 0, size = 0;
-    bool any = false;
-    for (uint32_t t = 0; t <= (uint32_t)k; ++t) {
-      uint64_t s = lane < SW ? S[t * SW + lane] : 0ull;
-      bool found = false;
-      for (;;) {
-        const uint64_t bal = __ballot(s != 0ull);
-        if (bal == 0ull) break;
-        const uint32_t j = (uint32_t)__ffsll((unsigned long long)bal) - 1u;
-        const uint64_t sj = rdlane64(s, j);
-        const uint32_t b = (uint32_t)__ffsll((unsigned long long)sj) - 1u;
-        const uint32_t w = j * 64u + b;
-        const uint64_t word = uni64(B[t * W + w]);
-        if (word) {
-          v = w * 64u + (uint32_t)__ffsll((unsigned long long)word) - 1u;
-          size = t;
-          found = true;
-          break;
-        }
-        // stale summary bit: drop it and look again (lane j owns word j)
-        if (lane == j) {
-          s &= ~(1ull << b);
-          S[t * SW + j] = s;
-        }
-      }
-      if (found) { any = true; break; }
-    }
-    if (!any) { status = kStatusBroken; break; }   // open > 0 but no bucket: a bug
+    uint32_t v = key & 0xffffffu;
+    const uint32_t size = key >> 24;
     if (TRACE) h = trace_node_l(h, depth, row_in, v, size);
-    uint32_t c, rows;
+    uint32_t c, rows, est, beg, deg, u0;
     if (size != 0) {
-      // cover column v
-      rows = uni(rm[v]);
-      if (lane == (v & 63u)) {   // one owner lane; see the note at the record store
-        rm[v] = 0;
-        atomicAnd(reinterpret_cast<unsigned long long*>(&B[size * W + (v >> 6)]),
+      // rows of v and its neighbour list, loaded together
+      const uint32_t b0 = adj[v], b1 = adj[v + 1];
+      uint32_t r = 0;
+#pragma unroll
+      for (int j = 0; j < K; ++j) r |= (uint32_t)((PL[(uint32_t)j * W + (v >> 6)] >> (v & 63u)) & 1ull) << j;
+      beg = uni(b0);
+      deg = uni(b1) - beg;
+      u0 = lane < deg ? ids[beg + lane] : 0u;
+      rows = uni(r);
+      c = (uint32_t)__builtin_ctz(rows);
+      // cover column v: its P bit becomes the first entry of the level
+      est = esp;
+      if (lane == 63u) {
+        ent[est] = ((uint32_t)K << kEntryNodeBits) | v;
+        atomicAnd(reinterpret_cast<unsigned long long*>(&PL[(uint32_t)K * W + (v >> 6)]),
                   ~(1ull << (v & 63u)));
       }
-      --open;
-      c = (uint32_t)__ffs(rows) - 1u;
+      esp = est + 1u;
     } else {
-      // dead end: undo rows and columns until one has a next row
-      for (;;) {
-        if (depth == 0) { status = MPLD_INFEASIBLE; goto done; }
-        --depth;
-        const uint64_t hdr = uni64(stk[(uint64_t)depth * FW]);
-        v = (uint32_t)hdr;
-        const uint32_t cp = (uint32_t)(hdr >> 32) & 0xffu;
-        rows = (uint32_t)(hdr >> 40) & 0xffu;
-        const uint32_t beg = uni(adj[v]), deg = uni(adj[v + 1]) - beg;
-        for (uint32_t ch = 0; ch * 64u < deg; ++ch) {
-          const uint64_t rem = uni64(stk[(uint64_t)depth * FW + 1 + ch]);
-          if ((rem >> lane) & 1ull) {
-            const uint32_t w = ids[beg + ch * 64u + lane];
-            const uint32_t r = rm[w];
-            rm[w] = (uint8_t)(r | (1u << cp));
-            move_up(w, (uint32_t)__popc(r));
+      // dead end: back to the deepest level whose column has an untried row
+      uint32_t f = kNoneL;
+      if (depth != 0) {
+        const uint32_t d1 = depth - 1u, dw = d1 >> 6;
+        const uint64_t below = ~0ull >> (63u - (d1 & 63u));
+        if (BIG) {
+          uint32_t aw = dw;
+          uint64_t bits = uni64(A[aw]) & below;
+          while (bits == 0ull && aw != 0u) bits = uni64(A[--aw]);
+          if (bits) f = aw * 64u + 63u - (uint32_t)__builtin_clzll(bits);
+        } else {
+          const uint64_t m = lane < dw ? areg : (lane == dw ? areg & below : 0ull);
+          const uint64_t bal = __ballot(m != 0ull);
+          if (bal) {
+            const uint32_t l = 63u - (uint32_t)__builtin_clzll(bal);
+            const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)m, (int)l);
+            const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(m >> 32), (int)l);
+            const uint64_t bits = ((uint64_t)hi << 32) | lo;
+            f = l * 64u + 63u - (uint32_t)__builtin_clzll(bits);
           }
         }
-        __syncthreads();   // lanes' LDS updates visible to every lane
-        const uint32_t next = rows & ~((2u << cp) - 1u);
-        if (next) { c = (uint32_t)__ffs(next) - 1u; break; }
-        // uncover column v
-        if (lane == (v & 63u)) {
-          rm[v] = (uint8_t)rows;
-          const uint32_t t = (uint32_t)__popc(rows);
-          atomicOr(reinterpret_cast<unsigned long long*>(&B[t * W + (v >> 6)]), 1ull << (v & 63u));
-          atomicOr(reinterpret_cast<unsigned long long*>(&S[t * SW + (v >> 12)]),
-                   1ull << ((v >> 6) & 63u));
-        }
-        __syncthreads();
-        ++open;
       }
+      if (f == kNoneL) { status = MPLD_INFEASIBLE; break; }
+      const uint64_t hd = uni64(hdr[f]);
+      v = (uint32_t)hd & 0xffffffu;
+      const uint32_t cp = (uint32_t)(hd >> 24) & 0xfu;
+      rows = (uint32_t)(hd >> 28) & 0xffu;
+      est = (uint32_t)(hd >> 36);
+      beg = uni(adj[v]);
+      deg = uni(adj[v + 1]) - beg;
+      u0 = lane < deg ? ids[beg + lane] : 0u;
+      // uncover every level above f, and the rows level f removed; v stays covered
+      for (uint32_t i = est + 1u + lane; i < esp; i += 64) {
+        const uint32_t e = ent[i];
+        const uint32_t u = e & ((1u << kEntryNodeBits) - 1u);
+        atomicOr(reinterpret_cast<unsigned long long*>(&PL[(e >> kEntryNodeBits) * W + (u >> 6)]),
+                 1ull << (u & 63u));
+      }
+      c = (uint32_t)__builtin_ctz(rows & ~((2u << cp) - 1u));
+      depth = f;
+      esp = est + 1u;
     }
-    // ---- include row (v, c): close color c at v's open neighbours
+    // ---- include row (v, c) at this depth: record the level, then v's
+    // neighbours lose color c
     {
-      const uint32_t beg = uni(adj[v]), deg = uni(adj[v + 1]) - beg;
-      if (lane == (depth & 63u))
-        stk[(uint64_t)depth * FW] = (uint64_t)v | ((uint64_t)c << 32) | ((uint64_t)rows << 40);
-      for (uint32_t ch = 0; ch * 64u < deg; ++ch) {
-        bool hit = false;
-        const uint32_t j = ch * 64u + lane;
-        if (j < deg) {
-          const uint32_t w = ids[beg + j];
-          const uint32_t r = rm[w];
-          if ((r >> c) & 1u) {
-            hit = true;
-            rm[w] = (uint8_t)(r & ~(1u << c));
-            move_down(w, (uint32_t)__popc(r));
-          }
-        }
-        const uint64_t rem = __ballot(hit);
-        if (lane == ((depth + 1u + ch) & 63u)) stk[(uint64_t)depth * FW + 1 + ch] = rem;
+      const bool more = (rows >> (c + 1u)) != 0u;
+      const uint64_t bit = 1ull << (depth & 63u);
+      if (!BIG) {
+        const uint64_t set = more ? areg | bit : areg & ~bit;
+        areg = lane == (depth >> 6) ? set : areg;
       }
-      __syncthreads();
-      ++depth;
-      row_in = v * (uint32_t)k + c;
+      if (lane == 63u) {
+        hdr[depth] = make_hdr(v, c, rows, est);
+        if (BIG) {
+          if (more) atomicOr(reinterpret_cast<unsigned long long*>(&A[depth >> 6]), bit);
+          else atomicAnd(reinterpret_cast<unsigned long long*>(&A[depth >> 6]), ~bit);
+        }
+      }
     }
+    {
+      unsigned long long* plane = reinterpret_cast<unsigned long long*>(PL + c * W);
+      uint32_t u = u0;
+      for (uint32_t ch = 0; ch < deg; ch += 64u) {
+        if (ch != 0u) u = ch + lane < deg ? ids[beg + ch + lane] : 0u;
+        bool hit = false;
+        if (ch + lane < deg) {
+          const uint64_t bit = 1ull << (u & 63u);
+          hit = (atomicAnd(&plane[u >> 6], ~bit) & bit) != 0ull;
+        }
+        const uint64_t bal = __ballot(hit);
+        if (hit) {
+          const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
+                                                          __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+          ent[esp + rank] = (c << kEntryNodeBits) | u;
+        }
+        esp += (uint32_t)__popcll(bal);
+      }
+    }
+    // One wave executes its LDS operations in order, so the next node's
+    // loads see these writes; this only keeps the compiler from caching
+    // LDS values across the loop.
+    if (BIG) __syncthreads();
+    else asm volatile("" ::: "memory");
+    ++depth;
+    row_in = v * (uint32_t)K + c;
   }
-done:
   __syncthreads();
   if (status == MPLD_FEASIBLE) {
     for (uint32_t f = lane; f < depth; f += 64) {
-      const uint64_t hdr = stk[(uint64_t)f * FW];
-      colors[(uint32_t)hdr] = (int8_t)((hdr >> 32) & 0xffu);
+      const uint64_t hd = hdr[f];
+      colors[(uint32_t)hd & 0xffffffu] = (int8_t)((hd >> 24) & 0xfu);
     }
   } else {
-    for (uint32_t v = lane; v < (uint32_t)n; v += 64) colors[v] = -1;
+    for (uint32_t v = lane; v < n; v += 64) colors[v] = -1;
   }
   // Every lane stores the same (uniform) record: no branch in the loop may
   // share the queue pop's "lane 0" condition, or the compiler can thread the
@@ -289,6 +334,20 @@ done:
   rec->nodes = nodes;
   rec->hash = h;
   __syncthreads();
+}
+
+template <bool TRACE, bool BIG>
+__device__ __forceinline__ void solve_lds_k(const DevDesc& d, const uint32_t* gadj, char* lds,
+                                            uint64_t* gstack, int8_t* colors, DevRecord* rec) {
+  switch (d.k) {
+    case 2: solve_lds<TRACE, BIG, 2>(d, gadj, lds, gstack, colors, rec); break;
+    case 3: solve_lds<TRACE, BIG, 3>(d, gadj, lds, gstack, colors, rec); break;
+    case 4: solve_lds<TRACE, BIG, 4>(d, gadj, lds, gstack, colors, rec); break;
+    case 5: solve_lds<TRACE, BIG, 5>(d, gadj, lds, gstack, colors, rec); break;
+    case 6: solve_lds<TRACE, BIG, 6>(d, gadj, lds, gstack, colors, rec); break;
+    case 7: solve_lds<TRACE, BIG, 7>(d, gadj, lds, gstack, colors, rec); break;
+    default: solve_lds<TRACE, BIG, 8>(d, gadj, lds, gstack, colors, rec); break;
+  }
 }
 
 // Persistent kernel, one wave per workgroup; work distribution as in the
@@ -305,7 +364,7 @@ __global__ __launch_bounds__(64) void lds_batched_kernel(
   int32_t item = (int32_t)uni(blockIdx.x);
   while (item < qlen) {
     const DevDesc d = descs[item];
-    solve_lds<TRACE, BIG>(d, adj32 + d.nbr_off, lds, my_stack, colors + d.out_off, recs + d.comp);
+    solve_lds_k<TRACE, BIG>(d, adj32 + d.nbr_off, lds, my_stack, colors + d.out_off, recs + d.comp);
     if (gw >= qlen) break;
     int32_t r = 0;
     if (__lane_id() == 0) r = atomicAdd(counter, 1);
@@ -323,20 +382,21 @@ __global__ __launch_bounds__(64) void lds_single_kernel(const DevDesc* __restric
                                                         int8_t* __restrict__ colors) {
   extern __shared__ __align__(16) char lds[];
   const DevDesc d = descs[item];
-  solve_lds<TRACE, BIG>(d, adj32 + d.nbr_off, lds, gstack, colors + d.out_off, recs + d.comp);
+  solve_lds_k<TRACE, BIG>(d, adj32 + d.nbr_off, lds, gstack, colors + d.out_off, recs + d.comp);
 }
 
 // ---- host side --------------------------------------------------------------
 
 int64_t lds_bytes_for(int32_t n, int32_t k, int64_t adj_words, int32_t max_deg, bool big) {
   // adj_words: row offsets + neighbour ids (n + 1 + 2m)
-  return (int64_t)lds_layout(n, k, adj_words, max_deg, big).total;
+  (void)max_deg;
+  return (int64_t)lds_layout(n, k, adj_words, big).total;
 }
 
-int64_t lds_stack_words(int32_t n, int32_t max_deg) {
-  return (int64_t)n * (1 + (max_deg + 63) / 64);
+int64_t lds_stack_words(int32_t n, int32_t k, int64_t adj_words) {
+  // level headers (one u64 per depth) and the undo log (u32 entries)
+  return (int64_t)n + ((int64_t)lds_log_entries(n, k, adj_words) + 1) / 2;
 }
-
 template <bool TRACE, bool BIG>
 static void lds_attr(int bytes) {
   (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&lds_batched_kernel<TRACE, BIG>),

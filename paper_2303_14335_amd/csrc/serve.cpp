@@ -307,7 +307,7 @@ void mpld_server::tick(std::vector<Request*>& admitted) {
       } else {
         lds_big.push_back({r, c});
         lds_big_bytes = std::max<int>(lds_big_bytes, (int)lds_bytes_for(hd.n, hd.k, adj_words, maxdeg, true));
-        big_words = std::max<int64_t>(big_words, lds_stack_words(hd.n, maxdeg));
+        big_words = std::max<int64_t>(big_words, lds_stack_words(hd.n, hd.k, adj_words));
       }
     }
   }

@@ -142,6 +142,27 @@ def test_larger_components_lds_tiers(ctx):
     solve_both(ctx, comps[:3], 3, 3000, FORCE["device"])
 
 
+@pytest.mark.parametrize("k", [2, 4, 5, 8])
+def test_lds_tiers_backtracking_every_k(ctx, k):
+    """LDS and global tiers near the colorability threshold (deep
+    backtracking, per-depth bit sets over several words), plus hub nodes of
+    degree above 64 and 128 so that a cover takes several lane chunks."""
+    rng = np.random.default_rng(2000 + k)
+    comps = []
+    for _ in range(24):
+        n = int(rng.integers(1, 260))
+        p = min(0.95, float(rng.uniform(0.6, 1.4)) * 2.0 * k / max(n, 1))
+        comps.append((n, random_graph(rng, n, p)))
+    for n, hub_deg in ((150, 70), (300, 140)):
+        e = set(map(tuple, random_graph(rng, n, 1.5 * k / n)))
+        for u in rng.choice(np.arange(1, n), size=hub_deg, replace=False):
+            e.add((0, int(u)))
+        comps.append((n, sorted(e)))
+    say("LDS tiers, backtracking, k", k, "count", len(comps))
+    for flags in (FORCE["lds"], FORCE["global"]):
+        solve_both(ctx, comps, k, 20000, flags)
+
+
 def test_config3_giant_device_tier(ctx):
     import paper_2303_14335_amd as mp
     w, rects = graph_of(3)
