@@ -36,10 +36,11 @@ def log(*a):
 
 
 def kernel_source_hash() -> str:
-    """Hash of the search kernels' sources and of the build script (flags)."""
+    """Hash of the register-tier kernel's sources and of the build script
+    (flags): the stored traffic counters belong to that kernel."""
     h = hashlib.sha256()
     pkg = os.path.join(ROOT, "paper_2303_14335_amd")
-    for f in ("csrc/search_reg.hip", "csrc/search_lds.hip", "csrc/device_types.h", "build.py"):
+    for f in ("csrc/search_reg.hip", "csrc/device_types.h", "build.py"):
         with open(os.path.join(pkg, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

@@ -25,15 +25,20 @@ struct DevDesc {
 };
 static_assert(sizeof(DevDesc) == 32, "descriptor is 32 bytes");
 
-// Register-tier work item (n <= 64): the descriptor and the neighbour masks
-// in one 544-byte record, stored in launch order (mask v = the conflict
-// neighbours of local node v; zero past n).  A wave issues the loads of
-// both at once instead of reading the descriptor to find the masks.
-struct RegItem {
-  DevDesc d;
-  uint64_t nb[64];
+// Register-tier work items (n <= 64), stored in launch order.  Item i is a
+// 32-byte descriptor followed by `width` neighbour masks (mask v = the
+// conflict neighbours of local node v; zero past n) at byte offset
+// i * stride, stride = 32 + 8 * width.  One width per batch (the largest n
+// of its items) keeps the address a function of the index, so a wave
+// issues the descriptor and mask loads at once, and lanes at or past
+// `width` load nothing.
+struct RegItems {
+  const uint8_t* base;
+  uint32_t width;    // 1 .. 64
+  uint32_t stride;   // 32 + 8 * width bytes
 };
-static_assert(sizeof(RegItem) == 544, "register item is 544 bytes");
+constexpr uint32_t kRegItemHead = 32;
+inline uint32_t reg_item_width(int32_t max_n) { return max_n < 1 ? 1u : (uint32_t)max_n; }
 
 // One record per component (24 bytes), written by the search.
 struct DevRecord {

@@ -156,16 +156,20 @@ void device_upload(mpld_context* ctx, const Image& im, DeviceBatch& db, const Tu
   ordered.reserve(db.host_queue.size());
   for (int32_t c : db.host_queue) ordered.push_back(im.desc[c]);
   // register-tier items: descriptor and masks together, in launch order
-  std::vector<RegItem> items((size_t)db.n_reg);
+  int32_t max_reg_n = 0;
+  for (int32_t i = 0; i < db.n_reg; ++i) max_reg_n = std::max(max_reg_n, ordered[(size_t)i].n);
+  db.reg_width = reg_item_width(max_reg_n);
+  const size_t stride = kRegItemHead + 8u * db.reg_width;
+  std::vector<uint8_t> items(stride * (size_t)db.n_reg, 0);
   for (int32_t i = 0; i < db.n_reg; ++i) {
-    RegItem& it = items[(size_t)i];
-    it.d = ordered[(size_t)i];
-    std::memset(it.nb, 0, sizeof(it.nb));
-    std::memcpy(it.nb, im.masks.data() + it.d.nbr_off, sizeof(uint64_t) * (size_t)it.d.n);
+    uint8_t* it = items.data() + stride * (size_t)i;
+    const DevDesc& d = ordered[(size_t)i];
+    std::memcpy(it, &d, sizeof(DevDesc));
+    std::memcpy(it + kRegItemHead, im.masks.data() + d.nbr_off, sizeof(uint64_t) * (size_t)d.n);
   }
 
   db.desc.alloc(ctx, sizeof(DevDesc) * ordered.size());
-  db.regitems.alloc(ctx, sizeof(RegItem) * items.size());
+  db.regitems.alloc(ctx, items.size());
   db.adj32.alloc(ctx, sizeof(uint32_t) * im.adj32.size());
   db.counters.alloc(ctx, sizeof(int32_t) * 8);
   db.recs.alloc(ctx, sizeof(DevRecord) * im.desc.size());
@@ -184,7 +188,7 @@ void device_upload(mpld_context* ctx, const Image& im, DeviceBatch& db, const Tu
     check_hip(hipMemcpyAsync(db.desc.p, ordered.data(), sizeof(DevDesc) * ordered.size(),
                              hipMemcpyHostToDevice, s), "upload descriptors");
   if (!items.empty())
-    check_hip(hipMemcpyAsync(db.regitems.p, items.data(), sizeof(RegItem) * items.size(),
+    check_hip(hipMemcpyAsync(db.regitems.p, items.data(), items.size(),
                              hipMemcpyHostToDevice, s), "upload register items");
   if (!im.adj32.empty())
     check_hip(hipMemcpyAsync(db.adj32.p, im.adj32.data(), sizeof(uint32_t) * im.adj32.size(),
@@ -197,7 +201,7 @@ void device_upload(mpld_context* ctx, const Image& im, DeviceBatch& db, const Tu
 
 static void enqueue_batched(DeviceBatch& db, bool trace, uint64_t cap, hipStream_t s) {
   const auto* desc = db.desc.as<DevDesc>();
-  const auto* items = db.regitems.as<RegItem>();
+  const RegItems items = db.reg_items();
   const auto* adj = db.adj32.as<uint32_t>();
   auto* cnt = db.counters.as<int32_t>();
   auto* recs = db.recs.as<DevRecord>();
@@ -386,7 +390,7 @@ static void heavy_engine_device(DeviceBatch& db) {
     for (int i = 0; i < kEngineRoundsPerCheck; ++i, ++r) {
       check_hip(launch_engine_advance(head, kEngineTaskCap, s), "heavy: advance");
       check_hip(launch_engine_round(db.k, grid, head, tasks, kEngineTaskCap, blocks, pool, kEnginePoolCap,
-                                    db.regitems.as<RegItem>(), hc_nodes, hc_limit,
+                                    db.reg_items(), hc_nodes, hc_limit,
                                     (uint64_t)db.tune.heavy_round_cap, (uint32_t)levels, s),
                 "heavy: round");
     }
@@ -478,7 +482,7 @@ static void heavy_engine_device(DeviceBatch& db) {
   }
   for (int32_t item : rerun) {
     ++db.sp_reruns;
-    check_hip(launch_reg_single(false, db.k, db.regitems.as<RegItem>(), item, db.recs.as<DevRecord>(),
+    check_hip(launch_reg_single(false, db.k, db.reg_items(), item, db.recs.as<DevRecord>(),
                                 db.colors.as<int8_t>(), s), "heavy: sequential re-run");
   }
   if (!wb.empty()) {
@@ -581,7 +585,7 @@ static void heavy_engine_host(DeviceBatch& db) {
                              hipMemcpyHostToDevice, s), "heavy: tasks");
     const int grid = std::max(1, std::min((nt + 3) / 4, ctx->num_cus * ctx->reg_blocks_per_cu));
     check_hip(launch_reg_split(db.k, grid, dtasks, nt, db.counters.as<int32_t>() + 6,
-                               db.regitems.as<RegItem>(), (uint64_t)db.tune.heavy_round_cap,
+                               db.reg_items(), (uint64_t)db.tune.heavy_round_cap,
                                (uint32_t)levels, db.sp_out.as<uint8_t>(), db.sp_pool.as<SplitItem>(),
                                pool_count, s),
               "heavy: split launch");
@@ -679,7 +683,7 @@ static void heavy_engine_host(DeviceBatch& db) {
     const DevDesc& d = db.host_desc[hc.item];
     if (hc.rerun) {
       ++db.sp_reruns;
-      check_hip(launch_reg_single(false, db.k, db.regitems.as<RegItem>(),
+      check_hip(launch_reg_single(false, db.k, db.reg_items(),
                                   hc.item, db.recs.as<DevRecord>(), db.colors.as<int8_t>(), s),
                 "heavy: sequential re-run");
       continue;
@@ -719,7 +723,7 @@ void device_solve(DeviceBatch& db, uint32_t flags) {
   if (flags & MPLD_PLAIN) {
     // one launch per component, same search code
     const auto* desc = db.desc.as<DevDesc>();
-    const auto* items = db.regitems.as<RegItem>();
+    const RegItems items = db.reg_items();
     const auto* adj = db.adj32.as<uint32_t>();
     auto* recs = db.recs.as<DevRecord>();
     auto* colors = db.colors.as<int8_t>();

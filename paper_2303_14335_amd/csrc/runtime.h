@@ -16,7 +16,7 @@ namespace mpld {
 // k: the batch's mask count (every component of a batch shares it).
 // wpb: waves per workgroup (1..4); cap < budget stops components after cap
 // nodes (status -1, for the heavy-component engine).
-hipError_t launch_reg_batched(bool trace, int k, int grid, int wpb, const RegItem* items,
+hipError_t launch_reg_batched(bool trace, int k, int grid, int wpb, RegItems items,
                               int32_t qlen, int32_t* counter, DevRecord* recs, int8_t* colors,
                               uint64_t cap, hipStream_t s);
 // Heavy-component engine: explore / split subtree tasks.
@@ -24,7 +24,7 @@ hipError_t launch_reg_batched(bool trace, int k, int grid, int wpb, const RegIte
 // split items to pool at an offset taken from *pool_count (zero before the
 // launch).
 hipError_t launch_reg_split(int k, int grid, const SplitTask* tasks, int32_t ntasks,
-                            int32_t* counter, const RegItem* regitems, uint64_t cap,
+                            int32_t* counter, RegItems regitems, uint64_t cap,
                             uint32_t levels, uint8_t* out, SplitItem* pool,
                             int32_t* pool_count, hipStream_t s);
 // Device-resident heavy engine: move the round window on (one thread), and
@@ -34,13 +34,13 @@ hipError_t launch_reg_split(int k, int grid, const SplitTask* tasks, int32_t nta
 hipError_t launch_engine_advance(EngineHead* head, int32_t task_cap, hipStream_t s);
 hipError_t launch_engine_round(int k, int grid, EngineHead* head, EngineTask* tasks,
                                int32_t task_cap, uint8_t* blocks, EngineItem* pool,
-                               int32_t pool_cap, const RegItem* regitems,
+                               int32_t pool_cap, RegItems regitems,
                                unsigned long long* hc_nodes, const uint64_t* hc_limit,
                                uint64_t cap, uint32_t levels, hipStream_t s);
 // Scatters `count` resolved heavy components (records and colors).
 hipError_t launch_heavy_writeback(const HeavyWrite* w, int32_t count, DevRecord* recs,
                                   int8_t* colors, hipStream_t s);
-hipError_t launch_reg_single(bool trace, int k, const RegItem* items, int32_t item,
+hipError_t launch_reg_single(bool trace, int k, RegItems items, int32_t item,
                              DevRecord* recs, int8_t* colors, hipStream_t s);
 int reg_batched_blocks_per_cu(bool trace);
 // Serving tick over register-tier components (see the kernel).
@@ -188,6 +188,10 @@ void image_finish(Image& im, int order = 0);
 struct DeviceBatch {
   mpld_context* ctx = nullptr;
   DevBuf desc, regitems, adj32, counters, recs, colors, gstack;  // desc in launch order
+  uint32_t reg_width = 1;   // masks per register-tier item
+  RegItems reg_items() const {
+    return RegItems{regitems.as<uint8_t>(), reg_width, kRegItemHead + 8u * reg_width};
+  }
   DevBuf dev_keys, dev_stacks;      // device-wide tier
   DevBuf sp_tasks, sp_out, sp_pool, sp_writes;      // heavy-component engine
   PinnedBuf sp_host_tasks, sp_host_out, sp_host_pool, sp_host_writes, sp_host_recs;

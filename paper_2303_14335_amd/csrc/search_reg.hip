@@ -343,14 +343,22 @@ __device__ __forceinline__ void reg_finish(const RegState<K>& s, int32_t n,
 // loads are in flight together.  cap < budget stops the search after `cap`
 // nodes (status -1 in the record: the component is left to the
 // heavy-component engine).
+__device__ __forceinline__ const DevDesc& item_desc(const RegItems& R, int32_t i) {
+  return *reinterpret_cast<const DevDesc*>(R.base + (uint64_t)i * R.stride);
+}
+__device__ __forceinline__ uint64_t item_mask(const RegItems& R, int32_t i, uint32_t lane) {
+  const uint64_t* m = reinterpret_cast<const uint64_t*>(R.base + (uint64_t)i * R.stride + kRegItemHead);
+  return lane < R.width ? m[lane] : 0ull;   // zero past n
+}
+
 template <bool TRACE, int K>
-__device__ __forceinline__ void solve_reg(const RegItem* __restrict__ it,
+__device__ __forceinline__ void solve_reg(const RegItems& items, int32_t item,
                                           int8_t* __restrict__ colors_base,
                                           DevRecord* __restrict__ recs,
                                           const uint64_t cap = ~0ull) {
   const uint32_t lane = __lane_id();
-  const uint64_t nb = it->nb[lane];   // zero past n
-  const DevDesc d = it->d;
+  const uint64_t nb = item_mask(items, item, lane);
+  const DevDesc d = item_desc(items, item);
   const uint64_t budget = (uint64_t)d.budget;
   RegState<K> s;
   reg_init(s, d.n, d.k);
@@ -436,13 +444,13 @@ __device__ __forceinline__ uint32_t xcd_block() {
 // no memset.
 template <bool TRACE, int K>
 __global__ __launch_bounds__(256) void reg_batched_kernel(
-    const RegItem* __restrict__ items, int32_t qlen, int32_t* __restrict__ counter,
+    const RegItems items, int32_t qlen, int32_t* __restrict__ counter,
     DevRecord* __restrict__ recs, int8_t* __restrict__ colors, uint64_t cap) {
   const uint32_t wpb = blockDim.x >> 6;   // waves per workgroup
   const int32_t gw = (int32_t)(gridDim.x * wpb);
   int32_t item = (int32_t)uniform(xcd_block() * wpb + (threadIdx.x >> 6));
   while (item < qlen) {
-    solve_reg<TRACE, K>(items + item, colors, recs, cap);
+    solve_reg<TRACE, K>(items, item, colors, recs, cap);
     if (gw >= qlen) break;   // every item was handed out statically
     int32_t r = 0;
     if (__lane_id() == 0) r = atomicAdd(counter, 1);
@@ -454,10 +462,10 @@ __global__ __launch_bounds__(256) void reg_batched_kernel(
 
 // One component per launch (the plain solver): a single wave.
 template <bool TRACE, int K>
-__global__ __launch_bounds__(64) void reg_single_kernel(const RegItem* __restrict__ items,
+__global__ __launch_bounds__(64) void reg_single_kernel(const RegItems items,
                                                         int32_t item, DevRecord* __restrict__ recs,
                                                         int8_t* __restrict__ colors) {
-  solve_reg<TRACE, K>(items + item, colors, recs);
+  solve_reg<TRACE, K>(items, item, colors, recs);
 }
 
 // Serving tick: every listed component advances by at most `slice` search
@@ -600,7 +608,7 @@ __device__ __forceinline__ int32_t reg_enumerate(RegState<K>& s, const uint32_t 
 template <int K>
 __global__ __launch_bounds__(256) void reg_split_kernel(
     const SplitTask* __restrict__ tasks, int32_t ntasks, int32_t* __restrict__ counter,
-    const RegItem* __restrict__ regitems, uint64_t cap,
+    const RegItems regitems, uint64_t cap,
     uint32_t levels, uint8_t* __restrict__ out, SplitItem* __restrict__ pool,
     int32_t* __restrict__ pool_count) {
   const uint32_t wpb = blockDim.x >> 6;
@@ -611,8 +619,8 @@ __global__ __launch_bounds__(256) void reg_split_kernel(
     const SplitTask* task = tasks + t;
     const int32_t it = (int32_t)uniform((uint32_t)task->item);
     const uint32_t d = uniform((uint32_t)task->depth);
-    const DevDesc dd = regitems[it].d;
-    const uint64_t nb = regitems[it].nb[lane];
+    const DevDesc dd = item_desc(regitems, it);
+    const uint64_t nb = item_mask(regitems, it, lane);
     const uint32_t nb_lo = (uint32_t)nb, nb_hi = (uint32_t)(nb >> 32);
     uint8_t* block = out + (uint64_t)t * kSplitBlockBytes;
     int8_t* sol = reinterpret_cast<int8_t*>(block + kSplitSolOffset);
@@ -684,7 +692,7 @@ static void with_planes(int k, F&& f) {
   }
 }
 
-hipError_t launch_reg_batched(bool trace, int k, int grid, int wpb, const RegItem* items,
+hipError_t launch_reg_batched(bool trace, int k, int grid, int wpb, RegItems items,
                               int32_t qlen, int32_t* counter, DevRecord* recs, int8_t* colors,
                               uint64_t cap, hipStream_t s) {
   if (qlen <= 0) return hipSuccess;
@@ -701,7 +709,7 @@ hipError_t launch_reg_batched(bool trace, int k, int grid, int wpb, const RegIte
   return hipGetLastError();
 }
 
-hipError_t launch_reg_single(bool trace, int k, const RegItem* items, int32_t item,
+hipError_t launch_reg_single(bool trace, int k, RegItems items, int32_t item,
                              DevRecord* recs, int8_t* colors, hipStream_t s) {
   with_planes(k, [&](auto kp) {
     constexpr int K = decltype(kp)::value;
@@ -733,7 +741,7 @@ hipError_t launch_reg_tick(bool trace, int k, int grid, const int32_t* list, int
 }
 
 hipError_t launch_reg_split(int k, int grid, const SplitTask* tasks, int32_t ntasks,
-                            int32_t* counter, const RegItem* regitems, uint64_t cap,
+                            int32_t* counter, RegItems regitems, uint64_t cap,
                             uint32_t levels, uint8_t* out, SplitItem* pool,
                             int32_t* pool_count, hipStream_t s) {
   if (ntasks <= 0) return hipSuccess;
@@ -848,7 +856,7 @@ template <int K>
 __global__ __launch_bounds__(256) void engine_round_kernel(
     EngineHead* __restrict__ head, EngineTask* __restrict__ tasks, int32_t task_cap,
     uint8_t* __restrict__ blocks, EngineItem* __restrict__ pool, int32_t pool_cap,
-    const RegItem* __restrict__ regitems, unsigned long long* __restrict__ hc_nodes,
+    const RegItems regitems, unsigned long long* __restrict__ hc_nodes,
     const uint64_t* __restrict__ hc_limit, uint64_t cap, uint32_t levels) {
   const uint32_t wpb = blockDim.x >> 6;
   const int32_t gw = (int32_t)(gridDim.x * wpb);
@@ -874,8 +882,8 @@ __global__ __launch_bounds__(256) void engine_round_kernel(
       const int32_t it = (int32_t)uniform((uint32_t)task->item);
       const uint32_t d = uniform((uint32_t)task->depth);
       const int32_t hc = (int32_t)uniform((uint32_t)task->hc);
-      const DevDesc dd = regitems[it].d;
-      const uint64_t nb = regitems[it].nb[lane];
+      const DevDesc dd = item_desc(regitems, it);
+      const uint64_t nb = item_mask(regitems, it, lane);
       const uint32_t nb_lo = (uint32_t)nb, nb_hi = (uint32_t)(nb >> 32);
       RegState<K> s;
       reg_init(s, dd.n, dd.k);
@@ -956,7 +964,7 @@ hipError_t launch_engine_advance(EngineHead* head, int32_t task_cap, hipStream_t
 
 hipError_t launch_engine_round(int k, int grid, EngineHead* head, EngineTask* tasks,
                                int32_t task_cap, uint8_t* blocks, EngineItem* pool,
-                               int32_t pool_cap, const RegItem* regitems,
+                               int32_t pool_cap, RegItems regitems,
                                unsigned long long* hc_nodes, const uint64_t* hc_limit,
                                uint64_t cap, uint32_t levels, hipStream_t s) {
   if (levels < 1 || levels > (uint32_t)kSplitMaxLevels) return hipErrorInvalidValue;
