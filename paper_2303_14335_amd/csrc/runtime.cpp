@@ -78,6 +78,7 @@ void image_add(Image& im, mpld_context* ctx, int32_t n, const int32_t* pairs, in
     } else if (big <= ctx->lds_per_block) {
       im.lds_bytes_big = std::max(im.lds_bytes_big, big);
       im.big_stack_words = std::max(im.big_stack_words, lds_stack_words(n, k, adj_words));
+      im.big_max_n = std::max(im.big_max_n, n);
       im.q_big.push_back(id);
     } else {
       fail(MPLD_E_UNSUPPORTED, "component of " + std::to_string(n) + " nodes needs " +
@@ -136,6 +137,7 @@ void device_upload(mpld_context* ctx, const Image& im, DeviceBatch& db, const Tu
   db.lds_dev = device_tier_lds_bytes(std::max(1, im.dev_max_n), db.grid_dev);
   db.lds_small = (int)im.lds_bytes_small;
   db.lds_big = (int)im.lds_bytes_big;
+  db.big_waves = lds_big_waves(im.big_max_n);
   db.big_stack_words = (uint64_t)im.big_stack_words;
   {
     const int wpb = std::max(1, std::min(4, tune.waves_per_block));
@@ -215,13 +217,13 @@ static void enqueue_batched(DeviceBatch& db, bool trace, uint64_t cap, hipStream
     ++db.launches;
   }
   if (db.n_lds) {
-    check_hip(launch_lds_batched(trace, false, db.grid_lds, db.lds_small, desc + db.n_reg, adj,
+    check_hip(launch_lds_batched(trace, false, 1, db.grid_lds, db.lds_small, desc + db.n_reg, adj,
                                  db.n_lds, cnt + 1, nullptr, 0, recs, colors, s),
               "LDS-tier launch");
     ++db.launches;
   }
   if (db.n_big) {
-    check_hip(launch_lds_batched(trace, true, db.grid_big, db.lds_big, desc + db.n_reg + db.n_lds,
+    check_hip(launch_lds_batched(trace, true, db.big_waves, db.grid_big, db.lds_big, desc + db.n_reg + db.n_lds,
                                  adj, db.n_big, cnt + 2, gstack, db.big_stack_words, recs, colors,
                                  s),
               "big-tier launch");
@@ -735,9 +737,9 @@ void device_solve(DeviceBatch& db, uint32_t flags) {
       if (i < db.n_reg)
         e = launch_reg_single(trace, db.k, items, i, recs, colors, s);
       else if (i < db.n_reg + db.n_lds)
-        e = launch_lds_single(trace, false, db.lds_small, desc, adj, i, nullptr, recs, colors, s);
+        e = launch_lds_single(trace, false, 1, db.lds_small, desc, adj, i, nullptr, recs, colors, s);
       else if (i < db.n_reg + db.n_lds + db.n_big)
-        e = launch_lds_single(trace, true, db.lds_big, desc, adj, i, gstack, recs, colors, s);
+        e = launch_lds_single(trace, true, db.big_waves, db.lds_big, desc, adj, i, gstack, recs, colors, s);
       else
         e = launch_device_tier(trace, db.grid_dev, db.lds_dev, desc + i, adj,
                                db.dev_keys.as<unsigned long long>(), db.dev_stacks.as<uint64_t>(),

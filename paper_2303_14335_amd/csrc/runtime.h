@@ -48,13 +48,15 @@ hipError_t launch_reg_tick(bool trace, int k, int grid, const int32_t* list, int
                            int32_t* counter, const DevDesc* slot_desc, uint8_t* slot_state,
                            DevRecord* slot_rec, const uint64_t* arena64, int8_t* arena8,
                            uint64_t slice, DevRecord* tick_out, hipStream_t s);
-hipError_t launch_lds_batched(bool trace, bool big, int grid, int lds_bytes, const DevDesc* descs,
-                              const uint32_t* adj32, int32_t qlen, int32_t* counter,
-                              uint64_t* gstack, uint64_t stack_words, DevRecord* recs,
-                              int8_t* colors, hipStream_t s);
-hipError_t launch_lds_single(bool trace, bool big, int lds_bytes, const DevDesc* descs,
+hipError_t launch_lds_batched(bool trace, bool big, int waves, int grid, int lds_bytes,
+                              const DevDesc* descs, const uint32_t* adj32, int32_t qlen,
+                              int32_t* counter, uint64_t* gstack, uint64_t stack_words,
+                              DevRecord* recs, int8_t* colors, hipStream_t s);
+hipError_t launch_lds_single(bool trace, bool big, int waves, int lds_bytes, const DevDesc* descs,
                              const uint32_t* adj32, int32_t item, uint64_t* gstack,
                              DevRecord* recs, int8_t* colors, hipStream_t s);
+// Waves per workgroup for big LDS-tier components of at most max_n nodes.
+int lds_big_waves(int32_t max_n);
 // LDS bytes of one LDS-tier component (adj_words = n + 1 + 2m) and the
 // global stack words of a big one.
 int64_t lds_bytes_for(int32_t n, int32_t k, int64_t adj_words, int32_t max_deg, bool big);
@@ -154,6 +156,7 @@ struct Image {
   int64_t lds_bytes_small = 0;     // largest footprint on the LDS tier
   int64_t lds_bytes_big = 0;       // largest footprint on the big tier
   int64_t big_stack_words = 0;     // largest global stack of the big tier
+  int32_t big_max_n = 0;           // largest component of the big tier
   int64_t dev_stack_words = 0;     // largest per-workgroup stack of the device tier
   int32_t dev_max_n = 0;
 };
@@ -205,6 +208,7 @@ struct DeviceBatch {
   int32_t k = 3;
   int grid_reg = 1, grid_lds = 1, grid_big = 1;
   int lds_small = 0, lds_big = 0;
+  int big_waves = 1;   // waves per workgroup on the big tier
   uint64_t big_stack_words = 0;
   float last_search_ms = 0.f, last_total_ms = 0.f;
   int32_t launches = 0;

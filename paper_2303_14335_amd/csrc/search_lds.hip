@@ -22,10 +22,12 @@
 // levels whose column still has untried rows, and the deepest such level
 // is found with a word scan instead of popping level by level.
 //
-// Placement: the planes and the per-depth bit set always live in LDS.
-// Small components also keep their neighbour lists, level headers and undo
-// log in LDS; "big" components keep those in global memory (header and log
-// in a per-worker scratch area).
+// Placement: the planes always live in LDS.  Small components run on one
+// wave and also keep their neighbour lists, level headers and undo log in
+// LDS (the per-depth bit set in lane registers); "big" components run on a
+// workgroup of up to 16 waves that share the column scan, and keep the
+// per-depth bit set in LDS and the rest in global memory (header and log in
+// a per-worker scratch area).
 #include <hip/hip_runtime.h>
 
 #include "device_types.h"
@@ -114,7 +116,7 @@ __device__ __forceinline__ uint32_t word_key(const uint64_t* PL, uint32_t W, uin
 
 // Byte layout of the LDS area of one component.
 struct LdsLayout {
-  uint32_t W, E, pl_off, a_off, adj_off, hdr_off, ent_off, total;
+  uint32_t W, E, pl_off, a_off, adj_off, hdr_off, ent_off, ctl_off, total;
 };
 
 // Undo-log capacity: one entry per level (its P bit) plus the removed rows,
@@ -129,11 +131,13 @@ __host__ __device__ inline LdsLayout lds_layout(int32_t n, int32_t k, int64_t ad
   LdsLayout L;
   L.W = (uint32_t)((n + 63) / 64);
   L.E = lds_log_entries(n, k, adj_words);
-  uint32_t off = 0;
+  uint32_t off = big ? 16u : 0u;   // big: the workgroup's queue pop result first
   L.pl_off = off;
   off += 8u * (uint32_t)(k + 1) * L.W;
   L.a_off = off;
-  off += 8u * L.W;   // one bit per depth 0 .. n-1
+  if (big) off += 8u * L.W;   // one bit per depth 0 .. n-1 (small: in registers)
+  L.ctl_off = off;
+  if (big) off += 128u;       // per-wave minima, loop status, final depth
   L.adj_off = off;
   if (!big) off += 4u * (uint32_t)adj_words;
   off = (off + 7u) & ~7u;
@@ -150,32 +154,24 @@ __device__ __forceinline__ uint64_t make_hdr(uint32_t v, uint32_t c, uint32_t ro
   return (uint64_t)v | ((uint64_t)c << 24) | ((uint64_t)rows << 28) | ((uint64_t)est << 36);
 }
 
-template <bool TRACE, bool BIG, int K>
+// Small components: one wave; neighbour lists, level headers and the undo
+// log in LDS, the per-depth bit set in lane registers (word l in lane l; the
+// host admits at most 64 words).
+template <bool TRACE, int K>
 __device__ void solve_lds(const DevDesc& d, const uint32_t* __restrict__ gadj, char* lds,
-                          uint64_t* gstack, int8_t* __restrict__ colors,
-                          DevRecord* __restrict__ rec) {
+                          int8_t* __restrict__ colors, DevRecord* __restrict__ rec) {
   const uint32_t lane = __lane_id();
   const uint32_t n = (uint32_t)d.n;
   // adjacency block: [0..n] row offsets, [n+1 ..] neighbour ids
   const uint32_t adj_words = uni(gadj[n]) + n + 1u;
-  const LdsLayout L = lds_layout((int32_t)n, K, adj_words, BIG);
+  const LdsLayout L = lds_layout((int32_t)n, K, adj_words, false);
   const uint32_t W = L.W;
   uint64_t* PL = reinterpret_cast<uint64_t*>(lds + L.pl_off);
-  uint64_t* A = reinterpret_cast<uint64_t*>(lds + L.a_off);
-  const uint32_t* adj;
-  uint64_t* hdr;
-  uint32_t* ent;
-  if (BIG) {
-    adj = gadj;
-    hdr = gstack;
-    ent = reinterpret_cast<uint32_t*>(gstack + n);
-  } else {
-    uint32_t* la = reinterpret_cast<uint32_t*>(lds + L.adj_off);
-    for (uint32_t i = lane; i < adj_words; i += 64) la[i] = gadj[i];
-    adj = la;
-    hdr = reinterpret_cast<uint64_t*>(lds + L.hdr_off);
-    ent = reinterpret_cast<uint32_t*>(lds + L.ent_off);
-  }
+  uint32_t* la = reinterpret_cast<uint32_t*>(lds + L.adj_off);
+  for (uint32_t i = lane; i < adj_words; i += 64) la[i] = gadj[i];
+  const uint32_t* adj = la;
+  uint64_t* hdr = reinterpret_cast<uint64_t*>(lds + L.hdr_off);
+  uint32_t* ent = reinterpret_cast<uint32_t*>(lds + L.ent_off);
   const uint32_t* ids = adj + n + 1;
   // initial state: every node uncovered with all k colors open
   for (uint32_t w = lane; w < W; w += 64) {
@@ -183,11 +179,8 @@ __device__ void solve_lds(const DevDesc& d, const uint32_t* __restrict__ gadj, c
     const uint64_t val = cnt == 64u ? ~0ull : ((1ull << cnt) - 1ull);
 #pragma unroll
     for (int c = 0; c <= K; ++c) PL[(uint32_t)c * W + w] = val;
-    if (BIG) A[w] = 0ull;
   }
-  // Small components (the host admits at most 64 words) keep the per-depth
-  // bit set in registers, word l in lane l; big ones keep it in LDS.
-  uint64_t areg = 0;
+  uint64_t areg = 0;   // per-depth bit set, word `lane`
   __syncthreads();
 
   uint32_t depth = 0, row_in = kNoneL, esp = 0;
@@ -236,21 +229,14 @@ __device__ void solve_lds(const DevDesc& d, const uint32_t* __restrict__ gadj, c
       if (depth != 0) {
         const uint32_t d1 = depth - 1u, dw = d1 >> 6;
         const uint64_t below = ~0ull >> (63u - (d1 & 63u));
-        if (BIG) {
-          uint32_t aw = dw;
-          uint64_t bits = uni64(A[aw]) & below;
-          while (bits == 0ull && aw != 0u) bits = uni64(A[--aw]);
-          if (bits) f = aw * 64u + 63u - (uint32_t)__builtin_clzll(bits);
-        } else {
-          const uint64_t m = lane < dw ? areg : (lane == dw ? areg & below : 0ull);
-          const uint64_t bal = __ballot(m != 0ull);
-          if (bal) {
-            const uint32_t l = 63u - (uint32_t)__builtin_clzll(bal);
-            const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)m, (int)l);
-            const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(m >> 32), (int)l);
-            const uint64_t bits = ((uint64_t)hi << 32) | lo;
-            f = l * 64u + 63u - (uint32_t)__builtin_clzll(bits);
-          }
+        const uint64_t m = lane < dw ? areg : (lane == dw ? areg & below : 0ull);
+        const uint64_t bal = __ballot(m != 0ull);
+        if (bal) {
+          const uint32_t l = 63u - (uint32_t)__builtin_clzll(bal);
+          const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)m, (int)l);
+          const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(m >> 32), (int)l);
+          const uint64_t bits = ((uint64_t)hi << 32) | lo;
+          f = l * 64u + 63u - (uint32_t)__builtin_clzll(bits);
         }
       }
       if (f == kNoneL) { status = MPLD_INFEASIBLE; break; }
@@ -278,17 +264,9 @@ __device__ void solve_lds(const DevDesc& d, const uint32_t* __restrict__ gadj, c
     {
       const bool more = (rows >> (c + 1u)) != 0u;
       const uint64_t bit = 1ull << (depth & 63u);
-      if (!BIG) {
-        const uint64_t set = more ? areg | bit : areg & ~bit;
-        areg = lane == (depth >> 6) ? set : areg;
-      }
-      if (lane == 63u) {
-        hdr[depth] = make_hdr(v, c, rows, est);
-        if (BIG) {
-          if (more) atomicOr(reinterpret_cast<unsigned long long*>(&A[depth >> 6]), bit);
-          else atomicAnd(reinterpret_cast<unsigned long long*>(&A[depth >> 6]), ~bit);
-        }
-      }
+      const uint64_t set = more ? areg | bit : areg & ~bit;
+      areg = lane == (depth >> 6) ? set : areg;
+      if (lane == 63u) hdr[depth] = make_hdr(v, c, rows, est);
     }
     {
       unsigned long long* plane = reinterpret_cast<unsigned long long*>(PL + c * W);
@@ -312,8 +290,7 @@ __device__ void solve_lds(const DevDesc& d, const uint32_t* __restrict__ gadj, c
     // One wave executes its LDS operations in order, so the next node's
     // loads see these writes; this only keeps the compiler from caching
     // LDS values across the loop.
-    if (BIG) __syncthreads();
-    else asm volatile("" ::: "memory");
+    asm volatile("" ::: "memory");
     ++depth;
     row_in = v * (uint32_t)K + c;
   }
@@ -336,25 +313,199 @@ __device__ void solve_lds(const DevDesc& d, const uint32_t* __restrict__ gadj, c
   __syncthreads();
 }
 
+// Big components: one workgroup of nw waves (nw = blockDim.x / 64).  Every
+// wave scans its share of the plane words; the per-wave minima meet in LDS
+// and each wave folds them, so all waves hold the same column choice.  The
+// rest of the node (cover, backtrack, bookkeeping) is a few lanes of work
+// and runs on wave 0 alone; a barrier ends the node, and wave 0 publishes
+// the loop status (and the final depth) in LDS for the others.  Adjacency,
+// level headers and the undo log are in global memory.
+template <bool TRACE, int K>
+__device__ void solve_lds_wg(const DevDesc& d, const uint32_t* __restrict__ adj, char* lds,
+                             uint64_t* gstack, int8_t* __restrict__ colors,
+                             DevRecord* __restrict__ rec) {
+  const uint32_t tid = threadIdx.x, lane = __lane_id(), nthr = blockDim.x;
+  const uint32_t wid = uni(tid >> 6), nw = nthr >> 6;
+  const uint32_t n = (uint32_t)d.n;
+  const uint32_t adj_words = uni(adj[n]) + n + 1u;
+  const LdsLayout L = lds_layout((int32_t)n, K, adj_words, true);
+  const uint32_t W = L.W;
+  uint64_t* PL = reinterpret_cast<uint64_t*>(lds + L.pl_off);
+  uint64_t* A = reinterpret_cast<uint64_t*>(lds + L.a_off);
+  uint32_t* red = reinterpret_cast<uint32_t*>(lds + L.ctl_off);   // per-wave minima
+  int32_t* ctl = reinterpret_cast<int32_t*>(lds + L.ctl_off + 64);  // status, depth
+  uint64_t* hdr = gstack;
+  uint32_t* ent = reinterpret_cast<uint32_t*>(gstack + n);
+  const uint32_t* ids = adj + n + 1;
+  for (uint32_t w = tid; w < W; w += nthr) {
+    const uint32_t cnt = n - w * 64u >= 64u ? 64u : n - w * 64u;
+    const uint64_t val = cnt == 64u ? ~0ull : ((1ull << cnt) - 1ull);
+#pragma unroll
+    for (int c = 0; c <= K; ++c) PL[(uint32_t)c * W + w] = val;
+    A[w] = 0ull;
+  }
+  if (tid == 0) ctl[0] = -1;   // budget >= 1: the root always counts
+  __syncthreads();
+
+  // search state, kept by wave 0
+  uint32_t depth = 0, row_in = kNoneL, esp = 0;
+  uint64_t nodes = 1, h = kFnvOffsetL;
+  int32_t status = -1;
+  const uint64_t budget = (uint64_t)d.budget;
+
+  while (ctl[0] < 0) {
+    uint32_t key = kNoKey;
+    for (uint32_t w = tid; w < W; w += nthr) key = min(key, word_key<K>(PL, W, w));
+    key = wave_min(key);
+    if (nw > 1u) {
+      if (lane == 63u) red[wid] = key;
+      __syncthreads();
+      key = wave_min(lane < nw ? red[lane] : kNoKey);
+    }
+    if (wid == 0u) {
+      if (key == kNoKey) {   // no uncovered column: the levels hold a solution
+        if (TRACE) h = trace_node_l(h, depth, row_in, kNoneL, 0);
+        status = MPLD_FEASIBLE;
+      } else {
+        uint32_t v = key & 0xffffffu;
+        const uint32_t size = key >> 24;
+        if (TRACE) h = trace_node_l(h, depth, row_in, v, size);
+        uint32_t c = 0, rows = 0, est = 0, beg = 0, deg = 0;
+        if (size != 0) {
+          const uint32_t b0 = adj[v], b1 = adj[v + 1];
+          uint32_t r = 0;
+#pragma unroll
+          for (int j = 0; j < K; ++j) r |= (uint32_t)((PL[(uint32_t)j * W + (v >> 6)] >> (v & 63u)) & 1ull) << j;
+          beg = uni(b0);
+          deg = uni(b1) - beg;
+          rows = uni(r);
+          c = (uint32_t)__builtin_ctz(rows);
+          est = esp;
+          if (lane == 63u) {
+            ent[est] = ((uint32_t)K << kEntryNodeBits) | v;
+            atomicAnd(reinterpret_cast<unsigned long long*>(&PL[(uint32_t)K * W + (v >> 6)]),
+                      ~(1ull << (v & 63u)));
+          }
+          esp = est + 1u;
+        } else {
+          // dead end: back to the deepest level whose column has an untried row
+          uint32_t f = kNoneL;
+          if (depth != 0) {
+            const uint32_t d1 = depth - 1u;
+            uint32_t aw = d1 >> 6;
+            uint64_t bits = uni64(A[aw]) & (~0ull >> (63u - (d1 & 63u)));
+            while (bits == 0ull && aw != 0u) bits = uni64(A[--aw]);
+            if (bits) f = aw * 64u + 63u - (uint32_t)__builtin_clzll(bits);
+          }
+          if (f == kNoneL) {
+            status = MPLD_INFEASIBLE;
+          } else {
+            const uint64_t hd = uni64(hdr[f]);
+            v = (uint32_t)hd & 0xffffffu;
+            const uint32_t cp = (uint32_t)(hd >> 24) & 0xfu;
+            rows = (uint32_t)(hd >> 28) & 0xffu;
+            est = (uint32_t)(hd >> 36);
+            beg = uni(adj[v]);
+            deg = uni(adj[v + 1]) - beg;
+            // uncover every level above f, and the rows level f removed
+            for (uint32_t i = est + 1u + lane; i < esp; i += 64) {
+              const uint32_t e = ent[i];
+              const uint32_t u = e & ((1u << kEntryNodeBits) - 1u);
+              atomicOr(reinterpret_cast<unsigned long long*>(&PL[(e >> kEntryNodeBits) * W + (u >> 6)]),
+                       1ull << (u & 63u));
+            }
+            c = (uint32_t)__builtin_ctz(rows & ~((2u << cp) - 1u));
+            depth = f;
+            esp = est + 1u;
+          }
+        }
+        if (status < 0) {
+          // include row (v, c) at this depth
+          if (lane == 63u) {
+            hdr[depth] = make_hdr(v, c, rows, est);
+            const uint64_t bit = 1ull << (depth & 63u);
+            if (rows >> (c + 1u)) atomicOr(reinterpret_cast<unsigned long long*>(&A[depth >> 6]), bit);
+            else atomicAnd(reinterpret_cast<unsigned long long*>(&A[depth >> 6]), ~bit);
+          }
+          unsigned long long* plane = reinterpret_cast<unsigned long long*>(PL + c * W);
+          for (uint32_t ch = 0; ch < deg; ch += 64u) {
+            bool hit = false;
+            uint32_t u = 0;
+            if (ch + lane < deg) {
+              u = ids[beg + ch + lane];
+              const uint64_t bit = 1ull << (u & 63u);
+              hit = (atomicAnd(&plane[u >> 6], ~bit) & bit) != 0ull;
+            }
+            const uint64_t bal = __ballot(hit);
+            if (hit) {
+              const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
+                                                              __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+              ent[esp + rank] = (c << kEntryNodeBits) | u;
+            }
+            esp += (uint32_t)__popcll(bal);
+          }
+          ++depth;
+          row_in = v * (uint32_t)K + c;
+          // the next node, if the budget allows it
+          if (nodes == budget) status = MPLD_BUDGET_EXHAUSTED;
+          else ++nodes;
+        }
+      }
+      if (lane == 63u) {
+        ctl[0] = status;
+        ctl[1] = (int32_t)depth;
+      }
+    }
+    __syncthreads();
+  }
+  const int32_t fin = ctl[0];
+  const uint32_t fdepth = (uint32_t)ctl[1];
+  if (fin == MPLD_FEASIBLE) {
+    for (uint32_t f = tid; f < fdepth; f += nthr) {
+      const uint64_t hd = hdr[f];
+      colors[(uint32_t)hd & 0xffffffu] = (int8_t)((hd >> 24) & 0xfu);
+    }
+  } else {
+    for (uint32_t v = tid; v < n; v += nthr) colors[v] = -1;
+  }
+  if (wid == 0u) {   // uniform record from every lane of wave 0
+    rec->status = status;
+    rec->depth = status == MPLD_INFEASIBLE ? 0 : (int32_t)depth;
+    rec->nodes = nodes;
+    rec->hash = h;
+  }
+  __syncthreads();
+}
+
 template <bool TRACE, bool BIG>
 __device__ __forceinline__ void solve_lds_k(const DevDesc& d, const uint32_t* gadj, char* lds,
                                             uint64_t* gstack, int8_t* colors, DevRecord* rec) {
+#define MPLD_LDS_CASE(KK)                                             \
+  case KK:                                                            \
+    if (BIG) solve_lds_wg<TRACE, KK>(d, gadj, lds, gstack, colors, rec); \
+    else solve_lds<TRACE, KK>(d, gadj, lds, colors, rec);             \
+    break;
   switch (d.k) {
-    case 2: solve_lds<TRACE, BIG, 2>(d, gadj, lds, gstack, colors, rec); break;
-    case 3: solve_lds<TRACE, BIG, 3>(d, gadj, lds, gstack, colors, rec); break;
-    case 4: solve_lds<TRACE, BIG, 4>(d, gadj, lds, gstack, colors, rec); break;
-    case 5: solve_lds<TRACE, BIG, 5>(d, gadj, lds, gstack, colors, rec); break;
-    case 6: solve_lds<TRACE, BIG, 6>(d, gadj, lds, gstack, colors, rec); break;
-    case 7: solve_lds<TRACE, BIG, 7>(d, gadj, lds, gstack, colors, rec); break;
-    default: solve_lds<TRACE, BIG, 8>(d, gadj, lds, gstack, colors, rec); break;
+    MPLD_LDS_CASE(2)
+    MPLD_LDS_CASE(3)
+    MPLD_LDS_CASE(4)
+    MPLD_LDS_CASE(5)
+    MPLD_LDS_CASE(6)
+    MPLD_LDS_CASE(7)
+    default:
+      if (BIG) solve_lds_wg<TRACE, 8>(d, gadj, lds, gstack, colors, rec);
+      else solve_lds<TRACE, 8>(d, gadj, lds, colors, rec);
+      break;
   }
+#undef MPLD_LDS_CASE
 }
 
-// Persistent kernel, one wave per workgroup; work distribution as in the
-// register tier: static first item, then atomic pops, the last pop resets
-// the counter.
+// Persistent kernel, one workgroup per component (one wave for small
+// components, nw waves for big ones); work distribution as in the register
+// tier: static first item, then atomic pops by one thread, the last pop
+// resets the counter.
 template <bool TRACE, bool BIG>
-__global__ __launch_bounds__(64) void lds_batched_kernel(
+__global__ __launch_bounds__(BIG ? 1024 : 64) void lds_batched_kernel(
     const DevDesc* __restrict__ descs, const uint32_t* __restrict__ adj32, int32_t qlen,
     int32_t* __restrict__ counter, uint64_t* gstack, uint64_t stack_words_per_wave,
     DevRecord* __restrict__ recs, int8_t* __restrict__ colors) {
@@ -367,19 +518,25 @@ __global__ __launch_bounds__(64) void lds_batched_kernel(
     solve_lds_k<TRACE, BIG>(d, adj32 + d.nbr_off, lds, my_stack, colors + d.out_off, recs + d.comp);
     if (gw >= qlen) break;
     int32_t r = 0;
-    if (__lane_id() == 0) r = atomicAdd(counter, 1);
-    r = (int32_t)uni((uint32_t)r);
+    if constexpr (BIG) {   // one pop per workgroup, shared through LDS
+      int32_t* popped = reinterpret_cast<int32_t*>(lds);
+      if (threadIdx.x == 0) *popped = atomicAdd(counter, 1);
+      __syncthreads();
+      r = (int32_t)uni((uint32_t)*popped);
+      __syncthreads();
+    } else {
+      if (__lane_id() == 0) r = atomicAdd(counter, 1);
+      r = (int32_t)uni((uint32_t)r);
+    }
     item = gw + r;
-    if (r == qlen - 1) atomicExch(counter, 0);
+    if (r == qlen - 1 && threadIdx.x == 0) atomicExch(counter, 0);
   }
 }
 
 template <bool TRACE, bool BIG>
-__global__ __launch_bounds__(64) void lds_single_kernel(const DevDesc* __restrict__ descs,
-                                                        const uint32_t* __restrict__ adj32,
-                                                        int32_t item, uint64_t* gstack,
-                                                        DevRecord* __restrict__ recs,
-                                                        int8_t* __restrict__ colors) {
+__global__ __launch_bounds__(BIG ? 1024 : 64) void lds_single_kernel(
+    const DevDesc* __restrict__ descs, const uint32_t* __restrict__ adj32, int32_t item,
+    uint64_t* gstack, DevRecord* __restrict__ recs, int8_t* __restrict__ colors) {
   extern __shared__ __align__(16) char lds[];
   const DevDesc d = descs[item];
   solve_lds_k<TRACE, BIG>(d, adj32 + d.nbr_off, lds, gstack, colors + d.out_off, recs + d.comp);
@@ -413,49 +570,63 @@ void lds_configure(int bytes) {
   (void)hipGetLastError();
 }
 
+int lds_big_waves(int32_t max_n) {
+  // one plane word per lane of the workgroup, at most 16 waves
+  const int32_t words = (max_n + 63) / 64;
+  const int32_t w = (words + 63) / 64;
+  return w < 1 ? 1 : (w > 16 ? 16 : w);
+}
+
 template <bool TRACE, bool BIG>
-static hipError_t lds_batched_t(int grid, int lds_bytes, const DevDesc* descs,
+static hipError_t lds_batched_t(int waves, int grid, int lds_bytes, const DevDesc* descs,
                                 const uint32_t* adj32, int32_t qlen, int32_t* counter,
                                 uint64_t* gstack, uint64_t stack_words, DevRecord* recs,
                                 int8_t* colors, hipStream_t s) {
-  hipLaunchKernelGGL((lds_batched_kernel<TRACE, BIG>), dim3(grid), dim3(64), (size_t)lds_bytes, s,
-                     descs, adj32, qlen, counter, gstack, stack_words, recs, colors);
+  hipLaunchKernelGGL((lds_batched_kernel<TRACE, BIG>), dim3(grid), dim3(64 * waves),
+                     (size_t)lds_bytes, s, descs, adj32, qlen, counter, gstack, stack_words, recs,
+                     colors);
   return hipGetLastError();
 }
 
-hipError_t launch_lds_batched(bool trace, bool big, int grid, int lds_bytes, const DevDesc* descs,
-                              const uint32_t* adj32, int32_t qlen, int32_t* counter,
-                              uint64_t* gstack, uint64_t stack_words, DevRecord* recs,
-                              int8_t* colors, hipStream_t s) {
+hipError_t launch_lds_batched(bool trace, bool big, int waves, int grid, int lds_bytes,
+                              const DevDesc* descs, const uint32_t* adj32, int32_t qlen,
+                              int32_t* counter, uint64_t* gstack, uint64_t stack_words,
+                              DevRecord* recs, int8_t* colors, hipStream_t s) {
   if (qlen <= 0) return hipSuccess;
+  if (waves < 1 || waves > 16 || (!big && waves != 1)) return hipErrorInvalidValue;
   if (trace)
-    return big ? lds_batched_t<true, true>(grid, lds_bytes, descs, adj32, qlen, counter, gstack,
-                                           stack_words, recs, colors, s)
-               : lds_batched_t<true, false>(grid, lds_bytes, descs, adj32, qlen, counter, gstack,
-                                            stack_words, recs, colors, s);
-  return big ? lds_batched_t<false, true>(grid, lds_bytes, descs, adj32, qlen, counter, gstack,
-                                          stack_words, recs, colors, s)
-             : lds_batched_t<false, false>(grid, lds_bytes, descs, adj32, qlen, counter, gstack,
-                                           stack_words, recs, colors, s);
+    return big ? lds_batched_t<true, true>(waves, grid, lds_bytes, descs, adj32, qlen, counter,
+                                           gstack, stack_words, recs, colors, s)
+               : lds_batched_t<true, false>(1, grid, lds_bytes, descs, adj32, qlen, counter,
+                                            gstack, stack_words, recs, colors, s);
+  return big ? lds_batched_t<false, true>(waves, grid, lds_bytes, descs, adj32, qlen, counter,
+                                          gstack, stack_words, recs, colors, s)
+             : lds_batched_t<false, false>(1, grid, lds_bytes, descs, adj32, qlen, counter,
+                                           gstack, stack_words, recs, colors, s);
 }
 
 template <bool TRACE, bool BIG>
-static hipError_t lds_single_t(int lds_bytes, const DevDesc* descs, const uint32_t* adj32,
-                               int32_t item, uint64_t* gstack, DevRecord* recs, int8_t* colors,
-                               hipStream_t s) {
-  hipLaunchKernelGGL((lds_single_kernel<TRACE, BIG>), dim3(1), dim3(64), (size_t)lds_bytes, s,
-                     descs, adj32, item, gstack, recs, colors);
+static hipError_t lds_single_t(int waves, int lds_bytes, const DevDesc* descs,
+                               const uint32_t* adj32, int32_t item, uint64_t* gstack,
+                               DevRecord* recs, int8_t* colors, hipStream_t s) {
+  hipLaunchKernelGGL((lds_single_kernel<TRACE, BIG>), dim3(1), dim3(64 * waves),
+                     (size_t)lds_bytes, s, descs, adj32, item, gstack, recs, colors);
   return hipGetLastError();
 }
 
-hipError_t launch_lds_single(bool trace, bool big, int lds_bytes, const DevDesc* descs,
+hipError_t launch_lds_single(bool trace, bool big, int waves, int lds_bytes, const DevDesc* descs,
                              const uint32_t* adj32, int32_t item, uint64_t* gstack,
                              DevRecord* recs, int8_t* colors, hipStream_t s) {
+  if (waves < 1 || waves > 16 || (!big && waves != 1)) return hipErrorInvalidValue;
   if (trace)
-    return big ? lds_single_t<true, true>(lds_bytes, descs, adj32, item, gstack, recs, colors, s)
-               : lds_single_t<true, false>(lds_bytes, descs, adj32, item, gstack, recs, colors, s);
-  return big ? lds_single_t<false, true>(lds_bytes, descs, adj32, item, gstack, recs, colors, s)
-             : lds_single_t<false, false>(lds_bytes, descs, adj32, item, gstack, recs, colors, s);
+    return big ? lds_single_t<true, true>(waves, lds_bytes, descs, adj32, item, gstack, recs,
+                                          colors, s)
+               : lds_single_t<true, false>(1, lds_bytes, descs, adj32, item, gstack, recs,
+                                           colors, s);
+  return big ? lds_single_t<false, true>(waves, lds_bytes, descs, adj32, item, gstack, recs,
+                                         colors, s)
+             : lds_single_t<false, false>(1, lds_bytes, descs, adj32, item, gstack, recs,
+                                          colors, s);
 }
 
 }  // namespace mpld

@@ -290,6 +290,7 @@ void mpld_server::tick(std::vector<Request*>& admitted) {
   std::vector<DevDesc> lds_d;
   int lds_small_bytes = 0, lds_big_bytes = 0;
   int64_t big_words = 0;
+  int32_t big_max_n = 0;
   for (Request* r : admitted) {
     const int32_t nc = (int32_t)r->recs.size();
     for (int32_t c = 0; c < nc; ++c) {
@@ -308,6 +309,7 @@ void mpld_server::tick(std::vector<Request*>& admitted) {
         lds_big.push_back({r, c});
         lds_big_bytes = std::max<int>(lds_big_bytes, (int)lds_bytes_for(hd.n, hd.k, adj_words, maxdeg, true));
         big_words = std::max<int64_t>(big_words, lds_stack_words(hd.n, hd.k, adj_words));
+        big_max_n = std::max(big_max_n, hd.n);
       }
     }
   }
@@ -376,7 +378,8 @@ void mpld_server::tick(std::vector<Request*>& admitted) {
       while (b < first + count && lds_trace[b] == lds_trace[a]) ++b;
       const int per_cu = std::max(1, std::min(32, (160 * 1024) / std::max(bytes, 1)));
       const int grid = std::max(1, std::min((int)(b - a), ctx->num_cus * per_cu));
-      check_hip(launch_lds_batched(lds_trace[a] != 0, big, grid, bytes, lds_desc.as<DevDesc>() + a,
+      check_hip(launch_lds_batched(lds_trace[a] != 0, big, big ? lds_big_waves(big_max_n) : 1, grid,
+                                   bytes, lds_desc.as<DevDesc>() + a,
                                    arena.as<uint32_t>(), (int32_t)(b - a), counter.as<int32_t>() + 1,
                                    big ? gstack.as<uint64_t>() : nullptr, (uint64_t)big_words,
                                    lds_out.as<DevRecord>(), arena8, s),
