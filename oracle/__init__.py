@@ -19,14 +19,15 @@ _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 FEASIBLE, INFEASIBLE, BUDGET = 0, 1, 2
-SIMPLIFY = 1
+SIMPLIFY, MARK = 1, 2
 
 
 class OrcComp(ctypes.Structure):
     _fields_ = [("size", ctypes.c_int32), ("status", ctypes.c_int32),
                 ("nodes", ctypes.c_int64), ("trace_hash", ctypes.c_uint64),
                 ("depth_at_stop", ctypes.c_int32), ("stitches", ctypes.c_int32),
-                ("first_node", ctypes.c_int32), ("num_edges", ctypes.c_int32)]
+                ("first_node", ctypes.c_int32), ("num_edges", ctypes.c_int32),
+                ("conflicts", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 def build() -> str:
@@ -69,6 +70,9 @@ def _load():
                                             _p(ctypes.c_int64),
                                             _p(ctypes.c_uint64),
                                             _p(ctypes.c_int32)]
+        lib.orc_mark_conflicts.restype = ctypes.c_int32
+        lib.orc_mark_conflicts.argtypes = [ctypes.c_int32, ctypes.c_int64, vp,
+                                           ctypes.c_int32, vp]
         lib.orc_solve_many.restype = ctypes.c_int32
         lib.orc_solve_many.argtypes = [ctypes.c_int32, vp, vp, vp,
                                        ctypes.c_int32, ctypes.c_int64,
@@ -137,10 +141,14 @@ class Decomposition:
 COMP_DTYPE = np.dtype([("size", np.int32), ("status", np.int32),
                        ("nodes", np.int64), ("trace_hash", np.uint64),
                        ("depth_at_stop", np.int32), ("stitches", np.int32),
-                       ("first_node", np.int32), ("num_edges", np.int32)])
+                       ("first_node", np.int32), ("num_edges", np.int32),
+                       ("conflicts", np.int32), ("reserved", np.int32)])
 
 
-def decompose(g: Graph, k: int, budget: int, simplify: bool = True) -> Decomposition:
+def decompose(g: Graph, k: int, budget: int, simplify: bool = True,
+              mark: bool = False) -> Decomposition:
+    """Whole flow; mark=True colors the components left without a solution
+    by the conflict-marking descent (mark_conflicts)."""
     lib = _load()
     n = g.num_nodes
     ce = np.ascontiguousarray(g.ce, dtype=np.int32).reshape(-1, 2)
@@ -153,7 +161,7 @@ def decompose(g: Graph, k: int, budget: int, simplify: bool = True) -> Decomposi
     cn = ctypes.c_int64()
     un = ctypes.c_int64()
     rc = lib.orc_decompose(n, len(ce), ce.ctypes.data, len(se), se.ctypes.data,
-                           k, budget, SIMPLIFY if simplify else 0,
+                           k, budget, (SIMPLIFY if simplify else 0) | (MARK if mark else 0),
                            colors.ctypes.data, comp_of.ctypes.data,
                            ctypes.byref(nc), ctypes.byref(pcs),
                            ctypes.byref(st), ctypes.byref(cn), ctypes.byref(un))
@@ -189,6 +197,19 @@ def solve_component(n: int, edges, k: int, budget: int) -> Solve:
     if rc != 0:
         raise ValueError(f"orc_solve_component failed: {rc}")
     return Solve(status.value, nodes.value, h.value, d.value, colors[:n].copy())
+
+
+def mark_conflicts(n: int, edges, k: int) -> np.ndarray:
+    """Conflict marking of Algorithm 1 on one component (local numbering):
+    the no-backtracking descent whose empty columns take their last removed
+    row.  Returns int8 colors, every node colored."""
+    lib = _load()
+    e = np.ascontiguousarray(np.asarray(edges, dtype=np.int32).reshape(-1, 2))
+    colors = np.zeros(max(n, 1), dtype=np.int8)
+    rc = lib.orc_mark_conflicts(n, len(e), e.ctypes.data, k, colors.ctypes.data)
+    if rc != 0:
+        raise ValueError(f"orc_mark_conflicts failed: {rc}")
+    return colors[:n].copy()
 
 
 def solve_many(sizes, edge_lists, k: int, budget: int, threads: int):

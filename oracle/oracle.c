@@ -306,6 +306,61 @@ static void dlx_search(orc_dlx* x, int32_t depth, int32_t row_in) {
   dlx_uncover(x, c);
 }
 
+/* Links the matrix (CSR over rows rp/ci) into x's arrays: root, headers
+ * (primaries on the root ring in index order, secondaries self-linked),
+ * then every 1 into its row ring and, rows ascending, its column. */
+static void dlx_link(orc_dlx* x, int32_t n, int32_t ncols, int64_t rows, const int64_t* rp,
+                     const int32_t* ci) {
+  /* root and headers */
+  for (int32_t h = 0; h <= ncols; ++h) {
+    x->U[h] = x->D[h] = h;
+    x->col[h] = h;
+    x->row[h] = -1;
+    x->L[h] = x->R[h] = h;
+  }
+  x->nprim = n;
+  for (int32_t h = 1; h <= n; ++h) {  /* primary ring: root, 1, 2, ..., n */
+    x->L[h] = h - 1;
+    x->R[h - 1] = h;
+  }
+  if (n > 0) { x->R[n] = 0; x->L[0] = n; }
+  /* rows, ascending */
+  int32_t next = ncols + 1;
+  for (int64_t r = 0; r < rows; ++r) {
+    int32_t first = -1;
+    for (int64_t p = rp[r]; p < rp[r + 1]; ++p) {
+      const int32_t h = ci[p] + 1;
+      const int32_t nd = next++;
+      x->col[nd] = h;
+      x->row[nd] = (int32_t)r;
+      x->U[nd] = x->U[h]; x->D[nd] = h;
+      x->D[x->U[h]] = nd; x->U[h] = nd;
+      x->size[h]++;
+      if (first < 0) { first = nd; x->L[nd] = x->R[nd] = nd; }
+      else { x->L[nd] = x->L[first]; x->R[nd] = first; x->R[x->L[first]] = nd; x->L[first] = nd; }
+    }
+  }
+}
+
+/* Allocates the link arrays for `total` nodes and n rows of solution. */
+static int32_t dlx_alloc(orc_dlx* x, int64_t total, int32_t n) {
+  memset(x, 0, sizeof(*x));
+  x->L = (int32_t*)malloc(sizeof(int32_t) * (size_t)total);
+  x->R = (int32_t*)malloc(sizeof(int32_t) * (size_t)total);
+  x->U = (int32_t*)malloc(sizeof(int32_t) * (size_t)total);
+  x->D = (int32_t*)malloc(sizeof(int32_t) * (size_t)total);
+  x->col = (int32_t*)malloc(sizeof(int32_t) * (size_t)total);
+  x->row = (int32_t*)malloc(sizeof(int32_t) * (size_t)total);
+  x->size = (int32_t*)calloc((size_t)total, sizeof(int32_t));
+  x->sol = (int32_t*)malloc(sizeof(int32_t) * ((size_t)n + 1));
+  return (x->L && x->R && x->U && x->D && x->col && x->row && x->size && x->sol) ? 0 : -2;
+}
+
+static void dlx_free(orc_dlx* x) {
+  free(x->L); free(x->R); free(x->U); free(x->D); free(x->col); free(x->row);
+  free(x->size); free(x->sol);
+}
+
 int32_t orc_solve_component(int32_t n, int64_t m, const int32_t* edges,
                             int32_t k, int64_t budget, int8_t* colors,
                             int32_t* status, int64_t* nodes,
@@ -324,48 +379,11 @@ int32_t orc_solve_component(int32_t n, int64_t m, const int32_t* edges,
   const int64_t ones = rp[rows];
   const int64_t total = 1 + (int64_t)ncols + ones;
   orc_dlx x;
-  memset(&x, 0, sizeof(x));
-  x.L = (int32_t*)malloc(sizeof(int32_t) * (size_t)total);
-  x.R = (int32_t*)malloc(sizeof(int32_t) * (size_t)total);
-  x.U = (int32_t*)malloc(sizeof(int32_t) * (size_t)total);
-  x.D = (int32_t*)malloc(sizeof(int32_t) * (size_t)total);
-  x.col = (int32_t*)malloc(sizeof(int32_t) * (size_t)total);
-  x.row = (int32_t*)malloc(sizeof(int32_t) * (size_t)total);
-  x.size = (int32_t*)calloc((size_t)total, sizeof(int32_t));
-  x.sol = (int32_t*)malloc(sizeof(int32_t) * ((size_t)n + 1));
-  if (!x.L || !x.R || !x.U || !x.D || !x.col || !x.row || !x.size || !x.sol) {
+  if (dlx_alloc(&x, total, n)) {
     rc = -2;
     goto done;
   }
-  /* root and headers */
-  for (int32_t h = 0; h <= ncols; ++h) {
-    x.U[h] = x.D[h] = h;
-    x.col[h] = h;
-    x.row[h] = -1;
-    x.L[h] = x.R[h] = h;
-  }
-  x.nprim = n;
-  for (int32_t h = 1; h <= n; ++h) {  /* primary ring: root, 1, 2, ..., n */
-    x.L[h] = h - 1;
-    x.R[h - 1] = h;
-  }
-  if (n > 0) { x.R[n] = 0; x.L[0] = n; }
-  /* rows, ascending */
-  int32_t next = ncols + 1;
-  for (int64_t r = 0; r < rows; ++r) {
-    int32_t first = -1;
-    for (int64_t p = rp[r]; p < rp[r + 1]; ++p) {
-      const int32_t h = ci[p] + 1;
-      const int32_t nd = next++;
-      x.col[nd] = h;
-      x.row[nd] = (int32_t)r;
-      x.U[nd] = x.U[h]; x.D[nd] = h;
-      x.D[x.U[h]] = nd; x.U[h] = nd;
-      x.size[h]++;
-      if (first < 0) { first = nd; x.L[nd] = x.R[nd] = nd; }
-      else { x.L[nd] = x.L[first]; x.R[nd] = first; x.R[x.L[first]] = nd; x.L[first] = nd; }
-    }
-  }
+  dlx_link(&x, n, ncols, rows, rp, ci);
   x.budget = budget;
   x.nodes = 0;
   x.hash = 0xcbf29ce484222325ULL;
@@ -383,8 +401,88 @@ int32_t orc_solve_component(int32_t n, int64_t m, const int32_t* edges,
   if (depth_at_stop) *depth_at_stop = x.status == ORC_INFEASIBLE ? 0 : x.depth_at_stop;
   rc = 0;
 done:
-  free(x.L); free(x.R); free(x.U); free(x.D); free(x.col); free(x.row);
-  free(x.size); free(x.sol);
+  dlx_free(&x);
+  free(rp); free(ci);
+  free_comp_graph(&g);
+  return rc;
+}
+
+/* ------------------------------------------------------------------------
+ * Conflict marking (Algorithm 1: a column left with no related row is
+ * marked as a conflict candidate (cl, cl'), cl' being the column whose cover
+ * removed cl's final row).  Reading: a component whose search ends without
+ * a solution is still colored, by one descent of the same search that never
+ * backtracks.  The column is chosen by the search's rule and its first
+ * remaining row is included; a column with no row left is a conflict
+ * candidate and takes its final removed row anyway: the column and those of
+ * the row's secondary columns that are still uncovered are covered, and the
+ * covered ones are the marked conflicts.  Every primary column ends covered,
+ * so every node gets a color; the conflicts are the conflict edges whose
+ * ends share a color (Eq. 1).
+ * ---------------------------------------------------------------------- */
+
+/* Eq. 2 cover that also records, for every primary column that loses a row,
+ * the row it lost last. */
+static void dlx_cover_track(orc_dlx* x, int32_t c, int32_t* last_row) {
+  x->L[x->R[c]] = x->L[c];
+  x->R[x->L[c]] = x->R[c];
+  for (int32_t i = x->D[c]; i != c; i = x->D[i])
+    for (int32_t j = x->R[i]; j != i; j = x->R[j]) {
+      x->U[x->D[j]] = x->U[j];
+      x->D[x->U[j]] = x->D[j];
+      x->size[x->col[j]]--;
+      if (x->col[j] <= x->nprim) last_row[x->col[j]] = x->row[j];
+    }
+}
+
+int32_t orc_mark_conflicts(int32_t n, int64_t m, const int32_t* edges, int32_t k,
+                           int8_t* colors) {
+  if (n < 0 || m < 0 || k < 1 || k > 127) return -1;
+  if (m > 0 && !edges) return -1;
+  orc_comp_graph g;
+  int32_t rc = make_comp_graph(n, m, edges, k, &g);
+  if (rc) { free_comp_graph(&g); return rc; }
+  int64_t* rp = NULL;
+  int32_t* ci = NULL;
+  rc = orc_ec_matrix(n, m, g.edges, k, &rp, &ci);
+  if (rc) { free_comp_graph(&g); return rc; }
+  const int32_t ncols = (int32_t)(n + m * k);
+  const int64_t rows = (int64_t)n * k;
+  const int64_t total = 1 + (int64_t)ncols + rp[rows];
+  orc_dlx x;
+  int32_t* last_row = (int32_t*)malloc(sizeof(int32_t) * ((size_t)ncols + 1));
+  int32_t* row_node = (int32_t*)malloc(sizeof(int32_t) * ((size_t)rows + 1));
+  char* covered = (char*)calloc((size_t)ncols + 1, 1);
+  if (dlx_alloc(&x, total, n) || !last_row || !row_node || !covered) {
+    rc = -2;
+    goto done;
+  }
+  dlx_link(&x, n, ncols, rows, rp, ci);
+  for (int32_t h = 0; h <= ncols; ++h) last_row[h] = -1;
+  for (int64_t nd = ncols + 1; nd < total; ++nd)   /* each row's node in its primary column */
+    if (x.col[nd] <= n) row_node[x.row[nd]] = (int32_t)nd;
+  for (int32_t v = 0; v < n; ++v) colors[v] = -1;
+  while (x.R[0] != 0) {
+    int32_t c = x.R[0];
+    for (int32_t j = x.R[c]; j != 0 && x.size[c] > 0; j = x.R[j])
+      if (x.size[j] < x.size[c]) c = j;
+    /* the first remaining row, or for a conflict candidate the final one removed */
+    const int32_t rw = x.size[c] > 0 ? x.row[x.D[c]] : last_row[c];
+    if (rw < 0) { rc = -6; goto done; }   /* impossible: every column starts with k rows */
+    const int32_t nd = row_node[rw];
+    dlx_cover_track(&x, c, last_row);
+    covered[c] = 1;
+    for (int32_t j = x.R[nd]; j != nd; j = x.R[j])
+      if (!covered[x.col[j]]) {
+        dlx_cover_track(&x, x.col[j], last_row);
+        covered[x.col[j]] = 1;
+      }
+    colors[rw / k] = (int8_t)(rw % k);
+  }
+  rc = 0;
+done:
+  dlx_free(&x);
+  free(last_row); free(row_node); free(covered);
   free(rp); free(ci);
   free_comp_graph(&g);
   return rc;
@@ -572,13 +670,23 @@ int32_t orc_decompose(int32_t num_nodes, int64_t num_ce, const int32_t* ce,
     rc = orc_solve_component(size, lm, ledges, k, budget, lcolors, &r->status,
                              &r->nodes, &r->trace_hash, &r->depth_at_stop);
     if (rc) goto out;
+    const int marked = r->status != ORC_FEASIBLE && (flags & ORC_MARK);
+    if (marked) {
+      rc = orc_mark_conflicts(size, lm, ledges, k, lcolors);
+      if (rc) goto out;
+    }
     for (int32_t i = 0; i < size; ++i) colors[nodes[i]] = lcolors[i];
     r->stitches = 0;
     for (int32_t i = 0; i < size; ++i) {
       const int32_t x = nodes[i], p = partner[x];
       if (p > x && comp_of[p] == c && colors[p] != colors[x]) r->stitches++;
     }
-    if (r->status != ORC_FEASIBLE) r->stitches = -1;
+    if (r->status != ORC_FEASIBLE && !marked) r->stitches = -1;
+    r->conflicts = 0;
+    for (int64_t e = 0; e < lm; ++e)
+      if (lcolors[ledges[2 * e]] >= 0 && lcolors[ledges[2 * e]] == lcolors[ledges[2 * e + 1]])
+        r->conflicts++;
+    r->reserved = 0;
   }
 
   /* recovery, reverse removal order */

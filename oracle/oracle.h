@@ -26,7 +26,7 @@ extern "C" {
 #endif
 
 enum { ORC_FEASIBLE = 0, ORC_INFEASIBLE = 1, ORC_BUDGET = 2 };
-enum { ORC_SIMPLIFY = 1 };
+enum { ORC_SIMPLIFY = 1, ORC_MARK = 2 };
 
 typedef struct { int32_t x0, y0, x1, y1; } orc_rect;
 
@@ -37,9 +37,11 @@ typedef struct {
   int64_t nodes;         /* search nodes counted                       */
   uint64_t trace_hash;   /* FNV-1a 64 over the node trace              */
   int32_t depth_at_stop; /* rows in the partial solution at the stop   */
-  int32_t stitches;      /* SE pairs inside, colored differently; -1 unless feasible */
+  int32_t stitches;      /* SE pairs inside, colored differently; -1 unless colored */
   int32_t first_node;    /* smallest original node id                  */
   int32_t num_edges;     /* conflict edges inside                      */
+  int32_t conflicts;     /* conflict edges inside whose ends share a color */
+  int32_t reserved;
 } orc_comp;
 
 /* Builds the node list and conflict/stitch edges of a rectangle layout.
@@ -53,7 +55,9 @@ int32_t orc_build_graph(const orc_rect* rects, int32_t n, int32_t dmin,
                         int64_t* num_ce, int32_t** ce, int64_t* num_se,
                         int32_t** se);
 
-/* Full decomposition of a graph.  colors (num_nodes, -1 = uncolored) and
+/* Full decomposition of a graph.  flags: ORC_SIMPLIFY, ORC_MARK (components
+ * the search leaves without a solution are colored by orc_mark_conflicts).
+ * colors (num_nodes, -1 = uncolored) and
  * comp_of (num_nodes, -1 = removed by simplification) are caller-allocated;
  * *comps is malloc'ed (free with orc_free).  Totals may be NULL. */
 int32_t orc_decompose(int32_t num_nodes, int64_t num_ce, const int32_t* ce,
@@ -78,6 +82,13 @@ int32_t orc_solve_component(int32_t n, int64_t m, const int32_t* edges,
                             int32_t k, int64_t budget, int8_t* colors,
                             int32_t* status, int64_t* nodes,
                             uint64_t* trace_hash, int32_t* depth_at_stop);
+
+/* Conflict marking of Algorithm 1 for one component in local numbering:
+ * the no-backtracking descent of the search in which a column left with
+ * no row takes the row it lost last (a marked conflict).  colors (n) are
+ * caller-allocated; every node is colored. */
+int32_t orc_mark_conflicts(int32_t n, int64_t m, const int32_t* edges, int32_t k,
+                           int8_t* colors);
 
 /* Solves many components (concatenated local edge lists) on `threads`
  * threads, each component independently with orc_solve_component's

@@ -8,7 +8,12 @@
   ascending order; first solution stops; budget tested before counting) and
   the same node trace hash, so status, node count, hash and colors must
   agree with the oracle's dancing-links search exactly.
-* ``brute_force_colorable`` - exhaustive k-coloring test for tiny graphs.
+* ``mark_sets`` - the conflict-marking descent (Algorithm 1's conflict
+  candidates) on the same set representation: no backtracking, a column
+  with no row left takes the row it lost last.  Must give the oracle's
+  colors exactly.
+* ``brute_force_colorable`` / ``min_conflicts`` - exhaustive k-colorings
+  for tiny graphs.
 """
 from __future__ import annotations
 
@@ -101,6 +106,58 @@ def algx_sets(n: int, edges, k: int, budget: int):
             colors[r // k] = r % k
     depth = 0 if status == INFEASIBLE else st["depth"]
     return status, st["nodes"], st["hash"], depth, colors
+
+
+def mark_sets(n: int, edges, k: int):
+    """Conflict-marking descent on sets.  Columns as in algx_sets; every
+    row deleted from a primary column is remembered as that column's last
+    lost row.  Repeatedly take the fewest-rows primary column (lowest index
+    on ties); include its lowest row, or, when it has none (a conflict
+    candidate), the row it lost last.  Including a row deletes its columns
+    that are still present, with every row that has a 1 in them."""
+    edges = sorted((min(u, w), max(u, w)) for u, w in edges)
+    rows = {}
+    for v in range(n):
+        inc = [e for e, (a, b) in enumerate(edges) if v in (a, b)]
+        for c in range(k):
+            rows[v * k + c] = [("p", v)] + [("s", e, c) for e in inc]
+    cols = {}
+    for r, cl in rows.items():
+        for col in cl:
+            cols.setdefault(col, set()).add(r)
+    for v in range(n):
+        cols.setdefault(("p", v), set())
+    last = {}
+    colors = np.full(n, -1, dtype=np.int8)
+    while True:
+        open_prim = [v for v in range(n) if ("p", v) in cols]
+        if not open_prim:
+            break
+        best = min(open_prim, key=lambda v: (len(cols[("p", v)]), v))
+        members = cols[("p", best)]
+        r = min(members) if members else last[best]
+        for col in rows[r]:
+            if col not in cols:
+                continue            # already covered: a marked conflict
+            for other in cols.pop(col):
+                for col2 in rows[other]:
+                    if col2 != col and col2 in cols and other in cols[col2]:
+                        cols[col2].discard(other)
+                        if col2[0] == "p":
+                            last[col2[1]] = other
+        colors[r // k] = r % k
+    return colors
+
+
+def min_conflicts(n: int, edges, k: int) -> int:
+    """Fewest monochromatic edges over all k-colorings (tiny graphs)."""
+    e = np.asarray(list(edges), dtype=np.int64).reshape(-1, 2)
+    if n == 0 or len(e) == 0:
+        return 0
+    best = len(e)
+    for chunk in _colorings(n, k):
+        best = min(best, int((chunk[:, e[:, 0]] == chunk[:, e[:, 1]]).sum(axis=1).min()))
+    return best
 
 
 def brute_force_colorable(n: int, edges, k: int) -> bool:
