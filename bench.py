@@ -225,6 +225,8 @@ def main() -> int:
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-latency-probe", action="store_true")
+    ap.add_argument("--no-mark", action="store_true",
+                    help="skip the conflict-marking leg (MPLD_MARK_CONFLICTS on the same workload)")
     ap.add_argument("--serve-requests", type=int, default=1000,
                     help="serving leg: requests of the serving workload (0 = skip)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -323,6 +325,30 @@ def main() -> int:
                 and np.array_equal(res_plain.colors, res.colors))
     log(f"plain: {plain_ms:.4f} ms/step")
 
+    # ---- conflict marking (Algorithm 1's conflict candidates): the same
+    # workload with MPLD_MARK_CONFLICTS, so that components left without a
+    # solution are colored by the no-backtracking descent; a separate leg,
+    # not the headline value
+    mark = None
+    if not args.no_mark:
+        bm = mp.Batch(ctx, g, w.k, w.budget, mp.MPLD_SIMPLIFY | mp.MPLD_MARK_CONFLICTS)
+        for _ in range(args.warmup):
+            bm.solve(direct=direct, split=split, timed=False)
+        torch.cuda.synchronize()
+        tm = time.perf_counter()
+        for _ in range(args.steps):
+            bm.solve(direct=direct, split=split, timed=False)
+        torch.cuda.synchronize()
+        mark_ms = 1000.0 * (time.perf_counter() - tm) / args.steps
+        rm = bm.result()
+        bm.close()
+        failed = int(np.sum(rm.components["status"] != 0))
+        mark = {"ms_per_step": mark_ms, "search_ms_per_step": ms_per_step,
+                "marked_components": failed, "conflicts": int(rm.conflicts),
+                "uncolored": int(rm.uncolored), "stitches": int(rm.stitches),
+                "same_search": bool(np.array_equal(rm.components["nodes"], comps["nodes"]))}
+        log(f"marking: {mark_ms:.4f} ms/step, {failed} components marked, {rm.conflicts} conflicts")
+
     if args.copy_probe_mib:
         src = torch.empty(args.copy_probe_mib << 20, dtype=torch.uint8, device="cuda")
         dst = torch.empty_like(src)
@@ -397,6 +423,7 @@ def main() -> int:
                   "components_per_s": ncomp / (plain_ms * 1e-3), "launches": ncomp,
                   "same_result": same},
         "batched_over_plain": plain_ms / ms_per_step,
+        "mark_conflicts": mark,
         "frontend_ms": {"graph": 1000 * (t1 - t0), "simplify_pack_upload": 1000 * (t2 - t1)},
         "e2e_ms": 1000 * (t3 - t0),
         "roofline": roofline,

@@ -61,7 +61,7 @@
 extern "C" {
 #endif
 
-#define MPLD_ABI_VERSION 1u
+#define MPLD_ABI_VERSION 2u
 #define MPLD_MAX_K 8
 
 enum {
@@ -100,10 +100,22 @@ enum {
                                   in search order (not with MPLD_TRACE_HASH; a
                                   component cut by its budget is re-run
                                   sequentially).  Makes mpld_batch_solve wait. */
-  MPLD_UNTIMED = 1u << 9       /* mpld_batch_solve: record no HIP events around
+  MPLD_UNTIMED = 1u << 9,      /* mpld_batch_solve: record no HIP events around
                                   the search (last_search_ms keeps the value of
                                   the last timed solve); for callers timing
                                   many back-to-back solves themselves */
+  MPLD_MARK_CONFLICTS = 1u << 10 /* conflict marking (Algorithm 1, a column
+                                  left with no related row is a conflict
+                                  candidate): a component whose search ends
+                                  INFEASIBLE or BUDGET_EXHAUSTED is still
+                                  colored, by one descent of the search that
+                                  never backtracks, in which such a column
+                                  takes the color of the row it lost last.
+                                  Status, node count, hash and depth stay the
+                                  search's; `conflicts` and `stitches` are
+                                  counted on the colors.  Decompose, batches
+                                  and mpld_solve_components only (a server
+                                  rejects it with MPLD_E_UNSUPPORTED). */
 };
 
 typedef struct { int32_t x0, y0, x1, y1; } mpld_rect;  /* nm, closed box */
@@ -129,16 +141,20 @@ typedef struct {
   int32_t reserved;
 } mpld_options;
 
-/* Per component record (40 bytes). */
+/* Per component record (48 bytes). */
 typedef struct {
   int32_t size;           /* nodes                                          */
   int32_t status;         /* MPLD_FEASIBLE / MPLD_INFEASIBLE / MPLD_BUDGET_EXHAUSTED */
   int64_t nodes;          /* search nodes                                   */
   uint64_t trace_hash;    /* FNV-1a trace hash (0 unless MPLD_TRACE_HASH)   */
   int32_t depth_at_stop;  /* rows in the partial solution when it stopped (0 if infeasible) */
-  int32_t stitches;       /* stitch pairs inside colored differently; -1 unless feasible */
+  int32_t stitches;       /* stitch pairs inside colored differently; -1 unless colored
+                             (feasible, or marked with MPLD_MARK_CONFLICTS) */
   int32_t first_node;     /* smallest original node id                      */
   int32_t num_edges;      /* conflict edges inside                          */
+  int32_t conflicts;      /* conflict edges inside whose ends share a color
+                             (0 unless MPLD_MARK_CONFLICTS marked it)        */
+  int32_t reserved;
 } mpld_comp_record;
 
 /* One component given directly in its local numbering (no simplification,

@@ -17,14 +17,16 @@ import numpy as np
 from . import _ffi
 from ._ffi import (MPLD_BUDGET_EXHAUSTED, MPLD_FEASIBLE, MPLD_FORCE_DEVICE,  # noqa: F401
                    MPLD_FORCE_GLOBAL, MPLD_FORCE_LDS, MPLD_FORCE_WAVE, MPLD_INFEASIBLE,
-                   MPLD_PLAIN, MPLD_SIMPLIFY, MPLD_SPLIT_HEAVY, MPLD_TRACE_HASH)
+                   MPLD_MARK_CONFLICTS, MPLD_PLAIN, MPLD_SIMPLIFY, MPLD_SPLIT_HEAVY,
+                   MPLD_TRACE_HASH)
 
 _lib = _ffi.load()
 
 RECORD_DTYPE = np.dtype([("size", np.int32), ("status", np.int32), ("nodes", np.int64),
                          ("trace_hash", np.uint64), ("depth_at_stop", np.int32),
                          ("stitches", np.int32), ("first_node", np.int32),
-                         ("num_edges", np.int32)])
+                         ("num_edges", np.int32), ("conflicts", np.int32),
+                         ("reserved", np.int32)])
 assert RECORD_DTYPE.itemsize == ctypes.sizeof(_ffi.mpld_comp_record)
 
 

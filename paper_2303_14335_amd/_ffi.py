@@ -28,6 +28,7 @@ MPLD_DIRECT = 1 << 6
 MPLD_FORCE_DEVICE = 1 << 7
 MPLD_SPLIT_HEAVY = 1 << 8
 MPLD_UNTIMED = 1 << 9
+MPLD_MARK_CONFLICTS = 1 << 10
 
 c_i32, c_i64, c_u32, c_u64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint64
 vp = ctypes.c_void_p
@@ -50,7 +51,7 @@ class mpld_options(ctypes.Structure):
 class mpld_comp_record(ctypes.Structure):
     _fields_ = [("size", c_i32), ("status", c_i32), ("nodes", c_i64), ("trace_hash", c_u64),
                 ("depth_at_stop", c_i32), ("stitches", c_i32), ("first_node", c_i32),
-                ("num_edges", c_i32)]
+                ("num_edges", c_i32), ("conflicts", c_i32), ("reserved", c_i32)]
 
 
 class mpld_component(ctypes.Structure):

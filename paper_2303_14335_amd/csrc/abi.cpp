@@ -325,9 +325,16 @@ int32_t mpld_solve_components(mpld_context* ctx, const mpld_component* comps, in
       r.nodes = (int64_t)recs[c].nodes;
       r.trace_hash = trace ? recs[c].hash : 0;
       r.depth_at_stop = recs[c].depth;
-      r.stitches = r.status == MPLD_FEASIBLE ? 0 : -1;
+      r.stitches = r.status == MPLD_FEASIBLE || (opt->flags & MPLD_MARK_CONFLICTS) ? 0 : -1;
       r.first_node = -1;
       r.num_edges = (int32_t)comps[c].m;
+      r.conflicts = 0;
+      r.reserved = 0;
+      const int8_t* cc = lcol.data() + im.desc[c].out_off;
+      for (int64_t e = 0; e < comps[c].m; ++e) {
+        const int8_t a = cc[comps[c].edges[2 * e]];
+        r.conflicts += a >= 0 && a == cc[comps[c].edges[2 * e + 1]];
+      }
     }
     if (!lcol.empty()) std::memcpy(colors_out, lcol.data(), lcol.size());
   });

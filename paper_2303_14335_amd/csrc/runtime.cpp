@@ -68,6 +68,7 @@ void image_add(Image& im, mpld_context* ctx, int32_t n, const int32_t* pairs, in
     const int64_t small = lds_bytes_for(n, k, adj_words, (int32_t)maxdeg, false);
     const int64_t big = lds_bytes_for(n, k, adj_words, (int32_t)maxdeg, true);
     const int64_t limit = std::min<int64_t>(kLdsSmallLimit, ctx->lds_per_block);
+    im.mark_lds = std::max(im.mark_lds, mark_lds_bytes(n, k));
     if (force_dev) {
       im.dev_stack_words = std::max(im.dev_stack_words, device_tier_stack_words(n, (int32_t)maxdeg));
       im.dev_max_n = std::max(im.dev_max_n, n);
@@ -138,6 +139,7 @@ void device_upload(mpld_context* ctx, const Image& im, DeviceBatch& db, const Tu
   db.lds_small = (int)im.lds_bytes_small;
   db.lds_big = (int)im.lds_bytes_big;
   db.big_waves = lds_big_waves(im.big_max_n);
+  db.mark_lds = im.mark_lds;
   db.big_stack_words = (uint64_t)im.big_stack_words;
   {
     const int wpb = std::max(1, std::min(4, tune.waves_per_block));
@@ -714,9 +716,31 @@ static void heavy_engine_host(DeviceBatch& db) {
   check_hip(hipStreamSynchronize(s), "heavy: write back");
 }
 
+// Conflict marking of every component whose record is not FEASIBLE (after
+// all search work of the batch, on the same stream).
+static void enqueue_mark(DeviceBatch& db, hipStream_t s) {
+  mpld_context* ctx = db.ctx;
+  auto* recs = db.recs.as<DevRecord>();
+  auto* colors = db.colors.as<int8_t>();
+  if (db.n_reg)
+    check_hip(launch_mark_reg(db.k, std::min(db.n_reg, ctx->num_cus * 8), db.reg_items(), db.n_reg,
+                              recs, colors, s),
+              "conflict marking (register tier)");
+  const int32_t ncsr = db.n_lds + db.n_big + db.n_dev;
+  if (ncsr)
+    check_hip(launch_mark_lds(std::min(ncsr, ctx->num_cus * 4), (int)db.mark_lds,
+                              db.desc.as<DevDesc>() + db.n_reg, db.adj32.as<uint32_t>(), ncsr, recs,
+                              colors, s),
+              "conflict marking (CSR components)");
+}
+
 void device_solve(DeviceBatch& db, uint32_t flags) {
   mpld_context* ctx = db.ctx;
   hipStream_t s = ctx->stream;
+  const bool mark = flags & MPLD_MARK_CONFLICTS;
+  if (mark && db.mark_lds > ctx->lds_per_block)
+    fail(MPLD_E_UNSUPPORTED, "a component is too large for conflict marking (" +
+                                 std::to_string(db.mark_lds) + " bytes of LDS)");
   const bool trace = flags & MPLD_TRACE_HASH;
   const bool split = (flags & MPLD_SPLIT_HEAVY) && !trace && !(flags & MPLD_PLAIN) && db.n_reg > 0;
   const uint64_t cap = split ? (uint64_t)db.tune.heavy_first_cap : ~0ull;
@@ -747,12 +771,14 @@ void device_solve(DeviceBatch& db, uint32_t flags) {
       check_hip(e, "plain launch");
       ++db.launches;
     }
+    if (mark) enqueue_mark(db, s);
     check_hip(hipEventRecord(ctx->ev[1], s), "event");
   } else if ((flags & MPLD_DIRECT) || !db.tune.use_graph || db.n_dev) {
     // direct launches (cooperative launches stay out of graphs)
     if (timed) check_hip(hipEventRecord(ctx->ev[0], s), "event");
     enqueue_batched(db, trace, cap, s);
     if (split) heavy_engine(db);
+    if (mark) enqueue_mark(db, s);
     if (timed) check_hip(hipEventRecord(ctx->ev[1], s), "event");
   } else {
     // capture the tiered launches once, replay the graph afterwards
@@ -780,6 +806,7 @@ void device_solve(DeviceBatch& db, uint32_t flags) {
     if (timed) check_hip(hipEventRecord(ctx->ev[0], s), "event");
     check_hip(hipGraphLaunch(db.graph, s), "graph launch");
     if (split) heavy_engine(db);
+    if (mark) enqueue_mark(db, s);
     if (timed) check_hip(hipEventRecord(ctx->ev[1], s), "event");
   }
   db.timed = timed;
@@ -838,16 +865,25 @@ void assemble_result(const Graph& g, const Split& s, const Image& im, const mpld
     rec.trace_hash = trace ? recs[c].hash : 0;
     rec.depth_at_stop = recs[c].depth;
     rec.first_node = s.order[s.comp_ptr[c]];
-    int64_t edges2 = 0;
+    int64_t edges2 = 0, same2 = 0;
     int32_t st = 0;
     for (int32_t p = s.comp_ptr[c]; p < s.comp_ptr[c + 1]; ++p) {
       const int32_t x = s.order[p];
-      for (int64_t t = g.ptr[x]; t < g.ptr[x + 1]; ++t) edges2 += s.comp_of[g.adj[t]] == c;
+      const int8_t cx = r->colors[x];
+      for (int64_t t = g.ptr[x]; t < g.ptr[x + 1]; ++t) {
+        const int32_t w = g.adj[t];
+        if (s.comp_of[w] != c) continue;
+        ++edges2;
+        same2 += cx >= 0 && r->colors[w] == cx;
+      }
       const int32_t q = g.partner[x];
-      if (q > x && s.comp_of[q] == c && r->colors[q] != r->colors[x]) ++st;
+      if (q > x && s.comp_of[q] == c && r->colors[q] != cx) ++st;
     }
     rec.num_edges = (int32_t)(edges2 / 2);
-    rec.stitches = rec.status == MPLD_FEASIBLE ? st : -1;
+    const bool colored = rec.status == MPLD_FEASIBLE || (opt.flags & MPLD_MARK_CONFLICTS);
+    rec.stitches = colored ? st : -1;
+    rec.conflicts = (int32_t)(same2 / 2);
+    rec.reserved = 0;
   }
   if (opt.flags & MPLD_SIMPLIFY) recover(g, s, opt.k, r->colors);
   tallies(g, r->colors, &r->stitches, &r->conflicts, &r->uncolored);

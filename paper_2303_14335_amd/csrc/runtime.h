@@ -57,6 +57,14 @@ hipError_t launch_lds_single(bool trace, bool big, int waves, int lds_bytes, con
                              DevRecord* recs, int8_t* colors, hipStream_t s);
 // Waves per workgroup for big LDS-tier components of at most max_n nodes.
 int lds_big_waves(int32_t max_n);
+// Conflict marking (MPLD_MARK_CONFLICTS) of the components whose record is
+// not FEASIBLE: register-tier items, and CSR components (LDS, big and
+// device-wide tiers, one wave each, mark_lds_bytes of LDS).
+hipError_t launch_mark_reg(int k, int grid, RegItems items, int32_t qlen, const DevRecord* recs,
+                           int8_t* colors, hipStream_t s);
+hipError_t launch_mark_lds(int grid, int lds_bytes, const DevDesc* descs, const uint32_t* adj32,
+                           int32_t qlen, const DevRecord* recs, int8_t* colors, hipStream_t s);
+int64_t mark_lds_bytes(int32_t n, int32_t k);
 // LDS bytes of one LDS-tier component (adj_words = n + 1 + 2m) and the
 // global stack words of a big one.
 int64_t lds_bytes_for(int32_t n, int32_t k, int64_t adj_words, int32_t max_deg, bool big);
@@ -157,6 +165,7 @@ struct Image {
   int64_t lds_bytes_big = 0;       // largest footprint on the big tier
   int64_t big_stack_words = 0;     // largest global stack of the big tier
   int32_t big_max_n = 0;           // largest component of the big tier
+  int64_t mark_lds = 0;            // LDS of the conflict marking of CSR components
   int64_t dev_stack_words = 0;     // largest per-workgroup stack of the device tier
   int32_t dev_max_n = 0;
 };
@@ -209,6 +218,7 @@ struct DeviceBatch {
   int grid_reg = 1, grid_lds = 1, grid_big = 1;
   int lds_small = 0, lds_big = 0;
   int big_waves = 1;   // waves per workgroup on the big tier
+  int64_t mark_lds = 0;   // LDS bytes of the CSR conflict marking
   uint64_t big_stack_words = 0;
   float last_search_ms = 0.f, last_total_ms = 0.f;
   int32_t launches = 0;

@@ -32,6 +32,7 @@
 
 #include "device_types.h"
 #include "mpld.h"
+#include "wave_ops.h"
 
 namespace mpld {
 
@@ -67,18 +68,7 @@ __device__ __forceinline__ uint64_t uni64(uint64_t x) {
 
 constexpr int bits_for(int x) { return x == 0 ? 0 : 1 + bits_for(x >> 1); }
 
-// Minimum over the wave: row_shr 1, 2, 4, 8 leave each row's minimum in its
-// lane 15; row_bcast 15 and 31 fold the four rows into lane 63.  A lane
-// with no source in a step reads all-ones, the identity of min.
-__device__ __forceinline__ uint32_t wave_min(uint32_t m) {
-  m = min(m, (uint32_t)__builtin_amdgcn_update_dpp(-1, (int)m, 0x111, 0xf, 0xf, false));
-  m = min(m, (uint32_t)__builtin_amdgcn_update_dpp(-1, (int)m, 0x112, 0xf, 0xf, false));
-  m = min(m, (uint32_t)__builtin_amdgcn_update_dpp(-1, (int)m, 0x114, 0xf, 0xf, false));
-  m = min(m, (uint32_t)__builtin_amdgcn_update_dpp(-1, (int)m, 0x118, 0xf, 0xf, false));
-  m = min(m, (uint32_t)__builtin_amdgcn_update_dpp(-1, (int)m, 0x142, 0xa, 0xf, false));
-  m = min(m, (uint32_t)__builtin_amdgcn_update_dpp(-1, (int)m, 0x143, 0xc, 0xf, false));
-  return (uint32_t)__builtin_amdgcn_readlane((int)m, 63);
-}
+__device__ __forceinline__ uint32_t wave_min(uint32_t m) { return wave_min_u32(m); }
 
 // Key of the lowest-count, lowest-index uncovered column in word w:
 // (count << 24) | (64 w + bit), or kNoKey when the word has none.
@@ -542,6 +532,87 @@ __global__ __launch_bounds__(BIG ? 1024 : 64) void lds_single_kernel(
   solve_lds_k<TRACE, BIG>(d, adj32 + d.nbr_off, lds, gstack, colors + d.out_off, recs + d.comp);
 }
 
+// Conflict marking (Algorithm 1: a column left with no related row is a
+// conflict candidate (cl, cl'), cl' the column whose cover removed cl's
+// final row) for a component whose search ended without a solution: one
+// descent of the search that never backtracks.  Same column rule and plane
+// scan as the search; the column takes its lowest open color, or, with no
+// row left, the color it lost last (last[u] in LDS, written by the lane
+// whose atomic AND removed u's row).  One wave; adjacency from global
+// memory; LDS holds the planes and last[].  Every node is colored.
+template <int K>
+__device__ void mark_csr(const DevDesc& d, const uint32_t* __restrict__ adj, char* lds,
+                         int8_t* __restrict__ colors) {
+  const uint32_t lane = __lane_id();
+  const uint32_t n = (uint32_t)d.n, W = (n + 63u) / 64u;
+  uint64_t* PL = reinterpret_cast<uint64_t*>(lds);
+  uint8_t* last = reinterpret_cast<uint8_t*>(PL + (uint32_t)(K + 1) * W);
+  const uint32_t* ids = adj + n + 1;
+  for (uint32_t w = lane; w < W; w += 64) {
+    const uint32_t cnt = n - w * 64u >= 64u ? 64u : n - w * 64u;
+    const uint64_t val = cnt == 64u ? ~0ull : ((1ull << cnt) - 1ull);
+#pragma unroll
+    for (int c = 0; c <= K; ++c) PL[(uint32_t)c * W + w] = val;
+  }
+  __syncthreads();
+  for (;;) {
+    uint32_t key = kNoKey;
+    for (uint32_t w = lane; w < W; w += 64) key = min(key, word_key<K>(PL, W, w));
+    key = wave_min(key);
+    if (key == kNoKey) break;
+    const uint32_t v = key & 0xffffffu;
+    uint32_t c;
+    if ((key >> 24) != 0u) {
+      uint32_t r = 0;
+#pragma unroll
+      for (int j = 0; j < K; ++j) r |= (uint32_t)((PL[(uint32_t)j * W + (v >> 6)] >> (v & 63u)) & 1ull) << j;
+      c = (uint32_t)__builtin_ctz(uni(r));
+    } else {
+      c = uni(last[v]);
+    }
+    if (lane == 63u) {
+      colors[v] = (int8_t)c;
+      atomicAnd(reinterpret_cast<unsigned long long*>(&PL[(uint32_t)K * W + (v >> 6)]),
+                ~(1ull << (v & 63u)));
+    }
+    const uint32_t beg = uni(adj[v]), deg = uni(adj[v + 1]) - beg;
+    unsigned long long* plane = reinterpret_cast<unsigned long long*>(PL + c * W);
+    for (uint32_t j = lane; j < deg; j += 64u) {
+      const uint32_t u = ids[beg + j];
+      const uint64_t bit = 1ull << (u & 63u);
+      if (atomicAnd(&plane[u >> 6], ~bit) & bit) last[u] = (uint8_t)c;
+    }
+    __syncthreads();
+  }
+  __syncthreads();
+}
+
+// One wave per workgroup over the components of the LDS, big and
+// device-wide tiers; components whose record is FEASIBLE keep the search's
+// colors.
+__global__ __launch_bounds__(64) void mark_lds_kernel(const DevDesc* __restrict__ descs,
+                                                      const uint32_t* __restrict__ adj32,
+                                                      int32_t qlen,
+                                                      const DevRecord* __restrict__ recs,
+                                                      int8_t* __restrict__ colors) {
+  extern __shared__ __align__(16) char lds[];
+  for (int32_t i = (int32_t)uni(blockIdx.x); i < qlen; i += (int32_t)gridDim.x) {
+    const DevDesc d = descs[i];
+    if ((int32_t)uni((uint32_t)recs[d.comp].status) == MPLD_FEASIBLE) continue;
+    const uint32_t* adj = adj32 + d.nbr_off;
+    int8_t* out = colors + d.out_off;
+    switch (d.k) {
+      case 2: mark_csr<2>(d, adj, lds, out); break;
+      case 3: mark_csr<3>(d, adj, lds, out); break;
+      case 4: mark_csr<4>(d, adj, lds, out); break;
+      case 5: mark_csr<5>(d, adj, lds, out); break;
+      case 6: mark_csr<6>(d, adj, lds, out); break;
+      case 7: mark_csr<7>(d, adj, lds, out); break;
+      default: mark_csr<8>(d, adj, lds, out); break;
+    }
+  }
+}
+
 // ---- host side --------------------------------------------------------------
 
 int64_t lds_bytes_for(int32_t n, int32_t k, int64_t adj_words, int32_t max_deg, bool big) {
@@ -562,7 +633,23 @@ static void lds_attr(int bytes) {
                             hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 
+int64_t mark_lds_bytes(int32_t n, int32_t k) {
+  // planes (k + 1 words of 64 nodes each) and one byte per node
+  const int64_t W = ((int64_t)n + 63) / 64;
+  return (8 * (int64_t)(k + 1) * W + (int64_t)n + 7) & ~(int64_t)7;
+}
+
+hipError_t launch_mark_lds(int grid, int lds_bytes, const DevDesc* descs, const uint32_t* adj32,
+                           int32_t qlen, const DevRecord* recs, int8_t* colors, hipStream_t s) {
+  if (qlen <= 0) return hipSuccess;
+  hipLaunchKernelGGL(mark_lds_kernel, dim3(grid), dim3(64), (size_t)lds_bytes, s, descs, adj32,
+                     qlen, recs, colors);
+  return hipGetLastError();
+}
+
 void lds_configure(int bytes) {
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&mark_lds_kernel),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
   lds_attr<true, true>(bytes);
   lds_attr<true, false>(bytes);
   lds_attr<false, true>(bytes);

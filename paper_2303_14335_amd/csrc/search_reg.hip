@@ -33,6 +33,7 @@
 
 #include "device_types.h"
 #include "mpld.h"
+#include "wave_ops.h"
 
 namespace mpld {
 
@@ -468,6 +469,69 @@ __global__ __launch_bounds__(64) void reg_single_kernel(const RegItems items,
   solve_reg<TRACE, K>(items, item, colors, recs);
 }
 
+// Conflict marking (Algorithm 1: a column left with no related row is a
+// conflict candidate (cl, cl'), cl' the column whose cover removed cl's
+// final row) for a component whose search ended without a solution: one
+// descent of the search that never backtracks.  The column is chosen by the
+// search's rule (fewest rows, lowest index) and takes its lowest open color;
+// a column with no row left takes the color of the row it lost last, which
+// conflicts with the neighbour that took that color.  Lane u holds N(u) and
+// the color u lost last; the planes are wave-uniform.  Every node is colored.
+template <int K>
+__device__ __forceinline__ void mark_reg(const RegItems& items, int32_t item,
+                                         int8_t* __restrict__ colors_base) {
+  const uint32_t lane = __lane_id();
+  const DevDesc d = item_desc(items, item);
+  const uint64_t nb = item_mask(items, item, lane);
+  const uint32_t n = uniform((uint32_t)d.n);
+  uint64_t P = n >= 64u ? ~0ull : ((1ull << n) - 1ull);
+  uint64_t O[K];
+#pragma unroll
+  for (int c = 0; c < K; ++c) O[c] = P;
+  uint32_t last = 0, color = 0;
+  while (P != 0ull) {
+    uint32_t cnt = 0;
+#pragma unroll
+    for (int c = 0; c < K; ++c) cnt += (uint32_t)((O[c] >> lane) & 1ull);
+    const uint32_t key = wave_min_u32(((P >> lane) & 1ull) ? (cnt << 8) | lane : ~0u);
+    const uint32_t v = key & 0xffu;
+    uint32_t c = (uint32_t)__builtin_amdgcn_readlane((int)last, (int)v);
+    if ((key >> 8) != 0u) {   // lowest open color of v
+      c = K - 1;
+#pragma unroll
+      for (int j = K - 2; j >= 0; --j)
+        if ((O[j] >> v) & 1ull) c = (uint32_t)j;
+    }
+    c = uniform(c);
+    P &= ~(1ull << v);
+    if (lane == v) color = c;
+    const uint64_t nv = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(nb >> 32), (int)v) << 32) |
+                        (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)nb, (int)v);
+    uint64_t removed = 0;
+#pragma unroll
+    for (int j = 0; j < K; ++j)
+      if ((uint32_t)j == c) {
+        removed = nv & O[j];
+        O[j] &= ~nv;
+      }
+    if ((removed >> lane) & 1ull) last = c;
+  }
+  if (lane < n) colors_base[d.out_off + lane] = (int8_t)color;
+}
+
+// One wave per workgroup over the register-tier items; components whose
+// record is FEASIBLE keep the search's colors.
+template <int K>
+__global__ __launch_bounds__(64) void mark_reg_kernel(const RegItems items, int32_t qlen,
+                                                      const DevRecord* __restrict__ recs,
+                                                      int8_t* __restrict__ colors) {
+  for (int32_t i = (int32_t)uniform(blockIdx.x); i < qlen; i += (int32_t)gridDim.x) {
+    const int32_t comp = (int32_t)uniform((uint32_t)item_desc(items, i).comp);
+    if ((int32_t)uniform((uint32_t)recs[comp].status) == MPLD_FEASIBLE) continue;
+    mark_reg<K>(items, i, colors);
+  }
+}
+
 // Serving tick: every listed component advances by at most `slice` search
 // nodes from its saved state (entries with bit 31 set start fresh).  A
 // finished search writes its colors and record; a paused one saves its
@@ -705,6 +769,16 @@ hipError_t launch_reg_batched(bool trace, int k, int grid, int wpb, RegItems ite
     else
       hipLaunchKernelGGL((reg_batched_kernel<false, K>), dim3(grid), dim3(64 * wpb), 0, s, items,
                          qlen, counter, recs, colors, cap);
+  });
+  return hipGetLastError();
+}
+
+hipError_t launch_mark_reg(int k, int grid, RegItems items, int32_t qlen, const DevRecord* recs,
+                           int8_t* colors, hipStream_t s) {
+  if (qlen <= 0) return hipSuccess;
+  with_planes(k, [&](auto kp) {
+    constexpr int K = decltype(kp)::value;
+    hipLaunchKernelGGL((mark_reg_kernel<K>), dim3(grid), dim3(64), 0, s, items, qlen, recs, colors);
   });
   return hipGetLastError();
 }

@@ -526,6 +526,8 @@ void check_opts(const mpld_options* o) {
   if (o->node_budget < 1) fail(MPLD_E_INVALID, "node_budget must be >= 1");
   if (o->flags & (MPLD_PLAIN | MPLD_FORCE_WAVE | MPLD_FORCE_LDS | MPLD_FORCE_GLOBAL | MPLD_FORCE_DEVICE))
     fail(MPLD_E_INVALID, "serving takes no PLAIN or FORCE_* flags");
+  if (o->flags & MPLD_MARK_CONFLICTS)
+    fail(MPLD_E_UNSUPPORTED, "serving does not mark conflicts (MPLD_MARK_CONFLICTS)");
 }
 
 int32_t submit_request(mpld_server* s, Request* r, uint64_t* ticket) {

@@ -37,7 +37,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_abi_version_and_error_strings():
     import paper_2303_14335_amd as mp
-    assert mp.mpld_abi_version() == 1
+    assert mp.mpld_abi_version() == 2
     lib = mp._lib
     for code in (0, -1, -2, -3, -4, -5, -6, -7):
         assert lib.mpld_error_string(code)
