@@ -193,6 +193,14 @@ const char* mpld_last_error(void);            /* thread-local detail */
  * x1 < x0 or y1 < y0. */
 int32_t mpld_build_graph(const mpld_rect* rects, int32_t n, int32_t dmin_nm,
                          int32_t split_len_nm, mpld_owned_graph** out);
+/* The same layout graph (identical pairs, stitch pairs and node count)
+ * built on the context's device: the host validates, splits and picks the
+ * search grid, the device sorts the nodes into grid cells and tests every
+ * node against its 3x3 cell neighbourhood.  For large layouts, where the
+ * host pair search dominates.  Synchronous on the context's stream.
+ * Errors as mpld_build_graph, plus MPLD_E_DEVICE / MPLD_E_NOMEM. */
+int32_t mpld_build_graph_device(mpld_context* ctx, const mpld_rect* rects, int32_t n,
+                                int32_t dmin_nm, int32_t split_len_nm, mpld_owned_graph** out);
 /* Borrowed view of an owned graph (valid until mpld_owned_graph_free). */
 int32_t mpld_owned_graph_view(const mpld_owned_graph* g, mpld_graph* view);
 void mpld_owned_graph_free(mpld_owned_graph* g);

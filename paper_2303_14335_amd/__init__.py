@@ -73,6 +73,21 @@ def mpld_build_graph(rects: np.ndarray, dmin_nm: int, split_len_nm: int = 0) -> 
     h = ctypes.c_void_p()
     _check(_lib.mpld_build_graph(r.ctypes.data, len(r), dmin_nm, split_len_nm,
                                  ctypes.byref(h)), "mpld_build_graph")
+    return _owned_graph(h)
+
+
+def mpld_build_graph_device(ctx: "Context", rects: np.ndarray, dmin_nm: int,
+                            split_len_nm: int = 0) -> Graph:
+    """The same layout graph built on the context's device."""
+    r = np.ascontiguousarray(rects, dtype=np.int32).reshape(-1, 4)
+    h = ctypes.c_void_p()
+    _check(_lib.mpld_build_graph_device(ctx.handle, r.ctypes.data, len(r), dmin_nm,
+                                        split_len_nm, ctypes.byref(h)),
+           "mpld_build_graph_device")
+    return _owned_graph(h)
+
+
+def _owned_graph(h) -> Graph:
     try:
         v = _ffi.mpld_graph()
         _check(_lib.mpld_owned_graph_view(h, ctypes.byref(v)), "mpld_owned_graph_view")

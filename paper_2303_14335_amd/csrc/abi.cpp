@@ -113,6 +113,30 @@ int32_t mpld_build_graph(const mpld_rect* rects, int32_t n, int32_t dmin_nm, int
   });
 }
 
+int32_t mpld_build_graph_device(mpld_context* ctx, const mpld_rect* rects, int32_t n,
+                                int32_t dmin_nm, int32_t split_len_nm, mpld_owned_graph** out) {
+  return guard([&] {
+    if (!out) fail(MPLD_E_INVALID, "out is NULL");
+    *out = nullptr;
+    use_device(ctx);
+    if (!ctx->graph_builder) ctx->graph_builder = graph_builder_create(ctx, false);
+    Graph g;
+    std::vector<int32_t> se;
+    build_layout_graph_device(*ctx->graph_builder, rects, n, dmin_nm, split_len_nm, g, &se);
+    auto* og = new mpld_owned_graph();
+    og->g.num_nodes = g.n;
+    og->g.se.swap(se);
+    og->g.ce.reserve((size_t)g.num_ce * 2);
+    for (int32_t a = 0; a < g.n; ++a)
+      for (int64_t t = g.ptr[a]; t < g.ptr[a + 1]; ++t)
+        if (g.adj[t] > a) {
+          og->g.ce.push_back(a);
+          og->g.ce.push_back(g.adj[t]);
+        }
+    *out = og;
+  });
+}
+
 int32_t mpld_owned_graph_view(const mpld_owned_graph* g, mpld_graph* view) {
   return guard([&] {
     if (!g || !view) fail(MPLD_E_INVALID, "NULL argument");
@@ -172,6 +196,7 @@ int32_t mpld_context_destroy(mpld_context* ctx) {
   if (!ctx) return MPLD_OK;
   (void)hipSetDevice(ctx->device);
   if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+  if (ctx->graph_builder) graph_builder_destroy(ctx->graph_builder);
   for (auto& e : ctx->ev)
     if (e) (void)hipEventDestroy(e);
   if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);

@@ -188,14 +188,16 @@ void tallies(const Graph& g, const std::vector<int8_t>& colors, int64_t* stitche
 // dmin have lower-left corners less than S apart on each axis, so only the
 // 3x3 cells around a node hold its possible conflict partners.
 
-void build_layout_graph(const mpld_rect* rects, int32_t n, int32_t dmin,
-                        int32_t split_len, OwnedGraph& out, int threads) {
+void prepare_layout(const mpld_rect* rects, int32_t n, int32_t dmin, int32_t split_len,
+                    LayoutPrep& lp) {
   if (n < 0 || dmin < 0 || split_len < 0) fail(MPLD_E_INVALID, "negative size, dmin or split length");
   if (n > 0 && !rects) fail(MPLD_E_INVALID, "null rectangle array");
-  std::vector<mpld_rect> nd;
-  std::vector<int32_t> partner;
+  std::vector<mpld_rect>& nd = lp.nd;
+  std::vector<int32_t>& partner = lp.partner;
+  nd.clear();
+  partner.clear();
+  lp.se.clear();
   nd.reserve((size_t)n * (split_len > 0 ? 2 : 1));
-  out.se.clear();
   for (int32_t i = 0; i < n; ++i) {
     const mpld_rect r = rects[i];
     if (r.x1 < r.x0 || r.y1 < r.y0) fail(MPLD_E_INVALID, "rectangle " + std::to_string(i) + " has x1 < x0 or y1 < y0");
@@ -205,8 +207,8 @@ void build_layout_graph(const mpld_rect* rects, int32_t n, int32_t dmin,
       if (w >= h) { a.x1 = r.x0 + len / 2; b.x0 = a.x1; }
       else { a.y1 = r.y0 + len / 2; b.y0 = a.y1; }
       const int32_t id = (int32_t)nd.size();
-      out.se.push_back(id);
-      out.se.push_back(id + 1);
+      lp.se.push_back(id);
+      lp.se.push_back(id + 1);
       nd.push_back(a);
       nd.push_back(b);
       partner.push_back(id + 1);
@@ -217,8 +219,9 @@ void build_layout_graph(const mpld_rect* rects, int32_t n, int32_t dmin,
     }
   }
   const int32_t nn = (int32_t)nd.size();
-  out.num_nodes = nn;
-  out.ce.clear();
+  lp.minx = lp.miny = 0;
+  lp.cell = 1;
+  lp.gx = lp.gy = 1;
   if (nn == 0) return;
   int64_t minx = INT64_MAX, miny = INT64_MAX, maxx = INT64_MIN, maxy = INT64_MIN, ext = 1;
   for (const auto& r : nd) {
@@ -228,6 +231,8 @@ void build_layout_graph(const mpld_rect* rects, int32_t n, int32_t dmin,
     maxy = std::max<int64_t>(maxy, r.y0);
     ext = std::max<int64_t>(ext, std::max<int64_t>((int64_t)r.x1 - r.x0, (int64_t)r.y1 - r.y0));
   }
+  // cells of side > largest extent + d_min: every conflict pair has its
+  // lower-left corners in the same or adjacent cells
   int64_t cell = ext + dmin + 1;
   int64_t gx = (maxx - minx) / cell + 1, gy = (maxy - miny) / cell + 1;
   while (gx * gy > 4 * (int64_t)nn + 1024) {   // keep the grid O(n)
@@ -235,6 +240,25 @@ void build_layout_graph(const mpld_rect* rects, int32_t n, int32_t dmin,
     gx = (maxx - minx) / cell + 1;
     gy = (maxy - miny) / cell + 1;
   }
+  lp.minx = minx;
+  lp.miny = miny;
+  lp.cell = cell;
+  lp.gx = gx;
+  lp.gy = gy;
+}
+
+void build_layout_graph(const mpld_rect* rects, int32_t n, int32_t dmin,
+                        int32_t split_len, OwnedGraph& out, int threads) {
+  LayoutPrep lp;
+  prepare_layout(rects, n, dmin, split_len, lp);
+  const std::vector<mpld_rect>& nd = lp.nd;
+  const std::vector<int32_t>& partner = lp.partner;
+  out.se = lp.se;
+  const int32_t nn = (int32_t)nd.size();
+  out.num_nodes = nn;
+  out.ce.clear();
+  if (nn == 0) return;
+  const int64_t minx = lp.minx, miny = lp.miny, cell = lp.cell, gx = lp.gx, gy = lp.gy;
   // counting sort of the nodes by cell (ascending id within a cell), with a
   // copy of their boxes in that order so that the 3x3 neighbourhood scans
   // below read contiguous memory

@@ -64,6 +64,20 @@ struct OwnedGraph {
 void build_layout_graph(const mpld_rect* rects, int32_t n, int32_t dmin,
                         int32_t split_len, OwnedGraph& out, int threads = 0);
 
+// Validation, midpoint stitch split and search grid of a layout, shared by
+// the host and the device graph builders: nd = node boxes (split halves
+// consecutive, lower/left first), partner[v] = stitch partner or -1, se =
+// stitch pairs; grid of gx x gy square cells of side `cell` from (minx,
+// miny), cell > largest box extent + d_min, so that every conflict pair has
+// its lower-left corners in the same or adjacent cells.
+struct LayoutPrep {
+  std::vector<mpld_rect> nd;
+  std::vector<int32_t> partner, se;
+  int64_t minx = 0, miny = 0, cell = 1, gx = 1, gy = 1;
+};
+void prepare_layout(const mpld_rect* rects, int32_t n, int32_t dmin, int32_t split_len,
+                    LayoutPrep& lp);
+
 int host_threads();
 
 }  // namespace mpld

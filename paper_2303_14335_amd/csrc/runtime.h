@@ -82,6 +82,10 @@ void check_hip(hipError_t e, const char* what);
 
 }  // namespace mpld
 
+namespace mpld {
+struct GraphBuilder;
+}
+
 struct mpld_context {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -92,6 +96,7 @@ struct mpld_context {
   int reg_blocks_per_cu = 1;
   int lds_per_block = 0;
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  mpld::GraphBuilder* graph_builder = nullptr;   // device layout-graph builder (lazy)
 
   void* dev_alloc(size_t bytes);
   void dev_free(void* p);
@@ -265,4 +270,13 @@ void batch_pack(mpld_batch* b, const Tune& t);
 // Looks the batch's shape up in the tuning cache (path, else $MPLD_TUNE_CACHE);
 // true and *t filled on a hit.
 bool tune_from_cache(mpld_batch* b, const char* path, Tune* t);
+// Device layout-graph builder (graph_device.hip).  own_stream: a stream of
+// its own (server front-end workers), else the context's stream.
+GraphBuilder* graph_builder_create(mpld_context* ctx, bool own_stream);
+void graph_builder_destroy(GraphBuilder* gb);
+// Builds the CSR layout graph of `rects` on the device (the host's
+// prepare_layout first); se receives the stitch pairs when not null.
+void build_layout_graph_device(GraphBuilder& gb, const mpld_rect* rects, int32_t n, int32_t dmin,
+                               int32_t split_len, Graph& g, std::vector<int32_t>* se);
+
 }  // namespace mpld

@@ -36,6 +36,11 @@ namespace {
 
 using Clock = std::chrono::steady_clock;
 
+// Layout requests of at least this many rectangles build their graph on the
+// device (a fixed cost of about ten launches and two transfers, against
+// about 50-90 ns per rectangle for the host's pair search).
+constexpr int32_t kDeviceGraphMinRects = 4096;
+
 struct Request {
   uint64_t ticket = 0;
   bool layout = false;
@@ -103,6 +108,8 @@ struct mpld_server {
   mpld_server_stats stats{};
   std::vector<std::thread> workers;
   std::thread scheduler;
+  // device layout-graph builder for large layout requests (its own stream)
+  GraphBuilder* gbuilder = nullptr;
 
   void worker_loop();
   void scheduler_loop();
@@ -119,20 +126,28 @@ struct mpld_server {
 
 void mpld_server::front_end(Request* r) {
   try {
+    bool built = false;
     if (r->layout) {
-      OwnedGraph og;
-      // large layouts build their graph on a few threads (the host is mostly
-      // idle between requests); small ones on this worker alone
       const int32_t nr = (int32_t)r->rects.size();
-      build_layout_graph(r->rects.data(), nr, r->dmin, r->split, og, std::max(1, std::min(4, nr / 12500)));
-      r->num_nodes = og.num_nodes;
-      r->ce.swap(og.ce);
-      r->se.swap(og.se);
+      if (nr >= kDeviceGraphMinRects && gbuilder) {
+        // large layouts: pair search on the device, CSR straight back (valid
+        // by construction, so no host validation pass)
+        build_layout_graph_device(*gbuilder, r->rects.data(), nr, r->dmin, r->split, r->g, nullptr);
+        built = true;
+      } else {
+        OwnedGraph og;
+        build_layout_graph(r->rects.data(), nr, r->dmin, r->split, og, 1);
+        r->num_nodes = og.num_nodes;
+        r->ce.swap(og.ce);
+        r->se.swap(og.se);
+      }
       std::vector<mpld_rect>().swap(r->rects);
     }
-    mpld_graph view{r->num_nodes, 0, (int64_t)r->ce.size() / 2, r->ce.data(),
-                    (int64_t)r->se.size() / 2, r->se.data()};
-    r->g = make_graph(view);
+    if (!built) {
+      mpld_graph view{r->num_nodes, 0, (int64_t)r->ce.size() / 2, r->ce.data(),
+                      (int64_t)r->se.size() / 2, r->se.data()};
+      r->g = make_graph(view);
+    }
     r->s = simplify_and_split(r->g, r->opt.k, r->opt.flags & MPLD_SIMPLIFY);
     const int32_t nc = (int32_t)r->s.comp_ptr.size() - 1;
     std::vector<int32_t> pairs;
@@ -580,9 +595,11 @@ int32_t mpld_server_create(mpld_context* ctx, const mpld_server_options* opt, mp
       s->lds_desc.alloc(ctx, sizeof(DevDesc) * (size_t)s->max_slots);
       s->lds_out.alloc(ctx, sizeof(DevRecord) * (size_t)s->max_slots);
       s->counter.alloc(ctx, sizeof(int32_t) * 4);
+      s->gbuilder = graph_builder_create(ctx, true);
       check_hip(hipMemsetAsync(s->counter.p, 0, sizeof(int32_t) * 4, ctx->stream), "serve: clear");
       check_hip(hipStreamSynchronize(ctx->stream), "serve: clear");
     } catch (...) {
+      if (s->gbuilder) graph_builder_destroy(s->gbuilder);
       delete s;
       throw;
     }
@@ -687,6 +704,7 @@ int32_t mpld_server_destroy(mpld_server* s) {
   // every request is either pending (not finished) or done (not fetched)
   for (auto& kv : s->pending) delete kv.second;
   for (auto& kv : s->done) delete kv.second;
+  if (s->gbuilder) graph_builder_destroy(s->gbuilder);
   delete s;
   return MPLD_OK;
 }
