@@ -294,6 +294,13 @@ typedef struct {
                                 device (subtasks written by the kernel, the
                                 host resolves once at the end); 0 drives every
                                 round from the host                             */
+  int32_t root_split;        /* 1: register-tier components of at least
+                                root_split_min_n nodes get a workgroup each,
+                                whose helper waves search the root's rows 1..3
+                                beside the owner (no trace hash, no
+                                MPLD_SPLIT_HEAVY); 0: off                      */
+  int32_t root_split_min_n;  /* smallest component that gets one (>= 2)        */
+  int32_t root_split_max;    /* most components that get one; 0 = all         */
 } mpld_tune;
 int32_t mpld_batch_autotune(mpld_batch* b, int32_t reps, const char* cache_path, mpld_tune* out);
 int32_t mpld_batch_get_tune(mpld_batch* b, mpld_tune* out);

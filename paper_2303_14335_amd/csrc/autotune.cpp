@@ -103,6 +103,9 @@ bool tune_from_cache(mpld_batch* b, const char* path, Tune* t) {
   if (field(hit, "heavy_first_cap", &v)) t->heavy_first_cap = (int32_t)std::max(64L, v);
   if (field(hit, "heavy_round_cap", &v)) t->heavy_round_cap = (int32_t)std::max(16L, v);
   if (field(hit, "heavy_device", &v)) t->heavy_device = v ? 1 : 0;
+  if (field(hit, "root_split", &v)) t->root_split = v ? 1 : 0;
+  if (field(hit, "root_split_min_n", &v)) t->root_split_min_n = (int32_t)std::max(2L, v);
+  if (field(hit, "root_split_max", &v)) t->root_split_max = (int32_t)std::max(0L, v);
   if (field(hit, "heavy_levels", &v))
     t->heavy_levels = (int32_t)std::max(0L, std::min((long)kSplitMaxLevels, v));
   b->tuned_from_cache = true;
@@ -156,6 +159,9 @@ static void to_abi(const Tune& t, mpld_tune* o) {
   o->heavy_round_cap = t.heavy_round_cap;
   o->heavy_levels = t.heavy_levels;
   o->heavy_device = t.heavy_device;
+  o->root_split = t.root_split;
+  o->root_split_min_n = t.root_split_min_n;
+  o->root_split_max = t.root_split_max;
 }
 
 extern "C" {
@@ -182,6 +188,9 @@ int32_t mpld_batch_set_tune(mpld_batch* b, const mpld_tune* in) {
     t.heavy_round_cap = std::max(16, in->heavy_round_cap);
     t.heavy_levels = std::max(0, std::min(kSplitMaxLevels, in->heavy_levels));
     t.heavy_device = in->heavy_device ? 1 : 0;
+    t.root_split = in->root_split ? 1 : 0;
+    t.root_split_min_n = std::max(2, in->root_split_min_n);
+    t.root_split_max = std::max(0, in->root_split_max);
     batch_pack(b, t);
     b->solved = false;
     set_last_error("");
@@ -257,7 +266,9 @@ int32_t mpld_batch_autotune(mpld_batch* b, int32_t reps, const char* cache_path,
           << ", \"heavy_first_cap\": " << best.heavy_first_cap
           << ", \"heavy_round_cap\": " << best.heavy_round_cap
           << ", \"heavy_levels\": " << best.heavy_levels
-          << ", \"heavy_device\": " << best.heavy_device << ", \"best_ms\": " << best_ms
+          << ", \"heavy_device\": " << best.heavy_device << ", \"root_split\": " << best.root_split
+          << ", \"root_split_min_n\": " << best.root_split_min_n
+          << ", \"root_split_max\": " << best.root_split_max << ", \"best_ms\": " << best_ms
           << ", \"default_ms\": " << base_ms << "}\n";
       }
     }

@@ -159,6 +159,16 @@ void device_upload(mpld_context* ctx, const Image& im, DeviceBatch& db, const Tu
   ordered.clear();
   ordered.reserve(db.host_queue.size());
   for (int32_t c : db.host_queue) ordered.push_back(im.desc[c]);
+  // root split: the largest register-tier items (a prefix of the launch
+  // order when it is largest first) get a workgroup each, at most
+  // root_split_max of them (0: every item of at least root_split_min_n nodes)
+  db.reg_heavy = 0;
+  if (db.tune.root_split && db.tune.order == 0 && db.tune.waves_per_block == 4) {
+    const int32_t most = db.tune.root_split_max > 0 ? db.tune.root_split_max : db.n_reg;
+    while (db.reg_heavy < std::min(most, db.n_reg) &&
+           ordered[(size_t)db.reg_heavy].n >= db.tune.root_split_min_n)
+      ++db.reg_heavy;
+  }
   // register-tier items: descriptor and masks together, in launch order
   int32_t max_reg_n = 0;
   for (int32_t i = 0; i < db.n_reg; ++i) max_reg_n = std::max(max_reg_n, ordered[(size_t)i].n);
@@ -213,8 +223,10 @@ static void enqueue_batched(DeviceBatch& db, bool trace, uint64_t cap, hipStream
   auto* gstack = db.gstack.as<uint64_t>();
   db.launches = 0;
   if (db.n_reg) {
-    check_hip(launch_reg_batched(trace, db.k, db.grid_reg, db.tune.waves_per_block, items,
-                                 db.n_reg, cnt, recs, colors, cap, s),
+    const int32_t heavy = (!trace && cap == ~0ull) ? db.reg_heavy : 0;
+    const int grid = heavy ? heavy + (db.n_reg - heavy + 3) / 4 : db.grid_reg;
+    check_hip(launch_reg_batched(trace, db.k, grid, db.tune.waves_per_block, items, db.n_reg, cnt,
+                                 recs, colors, cap, heavy, s),
               "register-tier launch");
     ++db.launches;
   }

@@ -16,9 +16,11 @@ namespace mpld {
 // k: the batch's mask count (every component of a batch shares it).
 // wpb: waves per workgroup (1..4); cap < budget stops components after cap
 // nodes (status -1, for the heavy-component engine).
+// heavy > 0: root split of items 0 .. heavy-1 (no trace, cap = ~0, wpb = 4,
+// grid >= heavy + ceil((qlen - heavy) / 4)).
 hipError_t launch_reg_batched(bool trace, int k, int grid, int wpb, RegItems items,
                               int32_t qlen, int32_t* counter, DevRecord* recs, int8_t* colors,
-                              uint64_t cap, hipStream_t s);
+                              uint64_t cap, int32_t heavy, hipStream_t s);
 // Heavy-component engine: explore / split subtree tasks.
 // Task t writes its output block at out + t * kSplitBlockBytes and its
 // split items to pool at an offset taken from *pool_count (zero before the
@@ -190,6 +192,9 @@ struct Tune {
   int32_t heavy_round_cap = 256;   // nodes per subtree task and round
   int32_t heavy_levels = 0;        // levels per split; 0 = by k (4, 3 or 2)
   int32_t heavy_device = 1;        // 1: rounds chained on the device; 0: host-driven rounds
+  int32_t root_split = 1;          // root split of the largest register-tier items
+  int32_t root_split_min_n = 4;    // smallest item that gets one
+  int32_t root_split_max = 0;      // most items that get one; 0 = all
 };
 
 // Adds one component (local numbering, pairs i < j or j < i) to the image.
@@ -223,6 +228,7 @@ struct DeviceBatch {
   int grid_reg = 1, grid_lds = 1, grid_big = 1;
   int lds_small = 0, lds_big = 0;
   int big_waves = 1;   // waves per workgroup on the big tier
+  int32_t reg_heavy = 0;   // register-tier items (a launch-order prefix) with a root split
   int64_t mark_lds = 0;   // LDS bytes of the CSR conflict marking
   uint64_t big_stack_words = 0;
   float last_search_ms = 0.f, last_total_ms = 0.f;

@@ -367,6 +367,136 @@ __device__ __forceinline__ void solve_reg(const RegItems& items, int32_t item,
   reg_finish(s, d.n, colors_base + d.out_off, recs + d.comp);
 }
 
+// Root split for the heaviest items (no trace hash, no cap): one
+// workgroup of four waves per item.  At the root every column has all k
+// rows, so the root column v0 is node 0 and its rows are the k colors.
+// Wave 0 (the owner) counts the root node and searches the subtree of row
+// 0; wave c = 1 .. min(k, 4) - 1 (a helper) searches the subtree of row c
+// from the same start, in chunks, and publishes its node count, status and
+// solution in LDS.  The owner takes the rows in order: for a helper's row it
+// waits for the helper and adds its count (an exhausted subtree: next row;
+// a solution: done), exactly as the sequential search would have counted
+// them; a helper that ran into the budget, or whose count would cross it,
+// is searched again by the owner.  The owner releases the helpers it no
+// longer needs.  Status, node count, depth and colors equal the sequential
+// search's.
+struct RootSplitLds {
+  uint32_t flag[4], stop[4];
+  uint64_t nodes[4];
+  int32_t status[4], depth[4];
+  int8_t colors[4][64];
+};
+
+constexpr uint64_t kHelperChunk = 4;   // helper nodes between stop checks
+
+template <int K>
+__device__ __forceinline__ void root_split(const RegItems& items, int32_t item, uint32_t wave,
+                                           int8_t* __restrict__ colors_base,
+                                           DevRecord* __restrict__ recs) {
+  __shared__ RootSplitLds L;
+  const uint32_t lane = __lane_id();
+  constexpr uint32_t kHelpers = (K < 4 ? K : 4) - 1;
+  if (wave == 0u && lane < 4u) {
+    L.flag[lane] = 0u;
+    L.stop[lane] = 0u;
+  }
+  __syncthreads();
+  const DevDesc d = item_desc(items, item);
+  const uint64_t nb = item_mask(items, item, lane);
+  const uint32_t nb_lo = (uint32_t)nb, nb_hi = (uint32_t)(nb >> 32);
+  const uint64_t budget = (uint64_t)d.budget;
+  RegState<K> s;
+  reg_init(s, d.n, d.k);
+  if (wave > kHelpers) return;
+  if (s.P == 0ull) {   // empty component: the root is a solution
+    if (wave == 0u) {
+      reg_run<false, K>(s, nb_lo, nb_hi, d.k, budget, budget);
+      reg_finish(s, d.n, colors_base + d.out_off, recs + d.comp);
+    }
+    return;
+  }
+  uint64_t ge2;
+  const uint32_t v0 = uniform(low_bit(min_count_columns(s.O, s.P, ge2)));
+  const uint32_t R0 = uniform(rows_of(s.O, v0));
+  s.P &= ~(1ull << v0);
+  const uint64_t nbv0 = rdlane64(nb_lo, nb_hi, v0);
+  if (wave != 0u) {
+    // ---- helper: the subtree of root row c
+    const uint32_t c = wave;
+    if (!((R0 >> c) & 1u)) return;   // the owner never asks for a missing row
+    take_row(s, nbv0, v0, c, 0ull);
+    s.row_in = v0 * (uint32_t)d.k + c;
+    for (;;) {
+      reg_run<false, K>(s, nb_lo, nb_hi, d.k, ~0ull, s.nodes + kHelperChunk, 1);
+      if (s.status >= 0) break;
+      if (__hip_atomic_load(&L.stop[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) != 0u)
+        return;   // no longer needed
+      if (s.nodes >= budget) {   // the owner re-searches it under its budget
+        s.status = -2;
+        break;
+      }
+    }
+    const uint32_t depth = uniform(s.depth);
+    if (s.status == MPLD_FEASIBLE && lane < depth) L.colors[c][s.fr & 0xffu] = (int8_t)(s.fr >> 8);
+    if (lane == 63u) {
+      L.status[c] = s.status;
+      L.nodes[c] = s.nodes;
+      L.depth[c] = (int32_t)depth;
+    }
+    __hip_atomic_store(&L.flag[c], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+    return;
+  }
+  // ---- owner: the root node, then the root rows in order
+  ++s.nodes;
+  const Planes<K> O0 = s.O;
+  const uint64_t P0 = s.P;
+  int32_t taken = -1;   // helper whose solution ends the search
+  int32_t status = MPLD_INFEASIBLE;
+  uint32_t rem = R0;
+  while (rem != 0u) {
+    const uint32_t c = uniform((uint32_t)__builtin_ctz(rem));
+    rem &= rem - 1u;
+    if (c >= 1u && c <= kHelpers) {
+      while (__hip_atomic_load(&L.flag[c], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) == 0u)
+        __builtin_amdgcn_s_sleep(1);
+      const int32_t hs = (int32_t)uniform((uint32_t)L.status[c]);
+      const uint64_t hn = uniform64(L.nodes[c]);
+      if (hs >= 0 && s.nodes + hn <= budget) {
+        s.nodes += hn;
+        if (hs == MPLD_FEASIBLE) {
+          status = MPLD_FEASIBLE;
+          taken = (int32_t)c;
+          break;
+        }
+        continue;   // the subtree is exhausted: next row
+      }
+    }
+    s.O = O0;
+    s.P = P0;
+    s.depth = 0;
+    take_row(s, nbv0, v0, c, rem != 0u ? 1ull : 0ull);
+    s.row_in = v0 * (uint32_t)d.k + c;
+    reg_run<false, K>(s, nb_lo, nb_hi, d.k, budget, budget, 1);
+    if (s.status != MPLD_INFEASIBLE) {
+      status = s.status;
+      break;
+    }
+  }
+  if (lane < 4u) __hip_atomic_store(&L.stop[lane], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  int8_t* colors = colors_base + d.out_off;
+  DevRecord* rec = recs + d.comp;
+  if (taken >= 0) {
+    if (lane < (uint32_t)d.n) colors[lane] = L.colors[taken][lane];
+    rec->status = MPLD_FEASIBLE;
+    rec->depth = (int32_t)uniform((uint32_t)L.depth[taken]);
+    rec->nodes = s.nodes;
+    rec->hash = s.h;
+    return;
+  }
+  s.status = status;
+  reg_finish(s, d.n, colors, rec);
+}
+
 // Resumable state in device memory (kRegStateBytes per component): the
 // uniform head (counters at 0, planes at 64), then 64-lane arrays of u32:
 // frames, P snapshot (low, high), then per plane its snapshot (low, high).
@@ -446,8 +576,21 @@ __device__ __forceinline__ uint32_t xcd_block() {
 template <bool TRACE, int K>
 __global__ __launch_bounds__(256) void reg_batched_kernel(
     const RegItems items, int32_t qlen, int32_t* __restrict__ counter,
-    DevRecord* __restrict__ recs, int8_t* __restrict__ colors, uint64_t cap) {
+    DevRecord* __restrict__ recs, int8_t* __restrict__ colors, uint64_t cap, int32_t heavy) {
   const uint32_t wpb = blockDim.x >> 6;   // waves per workgroup
+  if (!TRACE && heavy > 0) {
+    // root split: workgroups 0 .. heavy-1 take items 0 .. heavy-1 (four
+    // waves each), the rest one item per wave; the host sized the grid so
+    // that every item is handed out here
+    const uint32_t b = xcd_block(), wave = uniform(threadIdx.x >> 6);
+    if (b < (uint32_t)heavy) {
+      root_split<K>(items, (int32_t)b, wave, colors, recs);
+    } else {
+      const int32_t item = heavy + (int32_t)((b - (uint32_t)heavy) * wpb + wave);
+      if (item < qlen) solve_reg<false, K>(items, item, colors, recs, cap);
+    }
+    return;
+  }
   const int32_t gw = (int32_t)(gridDim.x * wpb);
   int32_t item = (int32_t)uniform(xcd_block() * wpb + (threadIdx.x >> 6));
   while (item < qlen) {
@@ -758,17 +901,23 @@ static void with_planes(int k, F&& f) {
 
 hipError_t launch_reg_batched(bool trace, int k, int grid, int wpb, RegItems items,
                               int32_t qlen, int32_t* counter, DevRecord* recs, int8_t* colors,
-                              uint64_t cap, hipStream_t s) {
+                              uint64_t cap, int32_t heavy, hipStream_t s) {
   if (qlen <= 0) return hipSuccess;
   if (wpb < 1 || wpb > 4) return hipErrorInvalidValue;
+  // the root split needs four waves per workgroup and a grid that hands
+  // out every item at once
+  if (heavy < 0 || heavy > qlen) return hipErrorInvalidValue;
+  if (heavy > 0 && (trace || wpb != 4 || cap != ~0ull ||
+                    (int64_t)grid < heavy + ((int64_t)qlen - heavy + wpb - 1) / wpb))
+    return hipErrorInvalidValue;
   with_planes(k, [&](auto kp) {
     constexpr int K = decltype(kp)::value;
     if (trace)
       hipLaunchKernelGGL((reg_batched_kernel<true, K>), dim3(grid), dim3(64 * wpb), 0, s, items,
-                         qlen, counter, recs, colors, cap);
+                         qlen, counter, recs, colors, cap, 0);
     else
       hipLaunchKernelGGL((reg_batched_kernel<false, K>), dim3(grid), dim3(64 * wpb), 0, s, items,
-                         qlen, counter, recs, colors, cap);
+                         qlen, counter, recs, colors, cap, heavy);
   });
   return hipGetLastError();
 }

@@ -345,3 +345,50 @@ def test_split_heavy_random_components(ctx, k, deg, budget):
         for f in ("status", "nodes", "depth_at_stop"):
             assert np.array_equal(got.components[f], ref.comps[f]), (f, n, k, budget)
         assert np.array_equal(got.colors, ref.colors)
+
+
+# ---- untraced solves: the root split (helper waves searching the root's
+# rows 1..3 of the largest register-tier components) must give the
+# sequential status, node count, depth and colors
+
+def solve_untraced(ctx, comps, k, budget):
+    import paper_2303_14335_amd as mp
+    recs, colors = mp.mpld_solve_components(ctx, comps, k, budget, 0)
+    for (n, e), r, c in zip(comps, recs, colors):
+        s = oracle.solve_component(n, e, k, budget)
+        assert (int(r["status"]), int(r["nodes"]), int(r["depth_at_stop"])) == (
+            s.status, s.nodes, s.depth_at_stop), (n, e, k, budget)
+        assert np.array_equal(c, s.colors)
+
+
+@pytest.mark.parametrize("cfg", [0, 1, 2])
+def test_config_parity_untraced(ctx, cfg):
+    import paper_2303_14335_amd as mp
+    w, rects = graph_of(cfg)
+    say("config", cfg, w.name, "untraced")
+    g = mp.mpld_build_graph(rects, w.dmin_nm, w.split_len_nm)
+    ref = oracle.decompose(oracle.Graph(g.num_nodes, g.ce, g.se), w.k, w.budget)
+    got = mp.mpld_decompose(ctx, g, w.k, w.budget, SIMPLIFY)
+    for f in ("size", "status", "nodes", "depth_at_stop", "stitches", "first_node", "num_edges"):
+        assert np.array_equal(got.components[f], ref.comps[f]), f
+    assert np.array_equal(got.colors, ref.colors)
+
+
+@pytest.mark.parametrize("k", [2, 3, 4, 5, 8])
+def test_root_split_random_components(ctx, k):
+    rng = np.random.default_rng(3000 + k)
+    comps = []
+    for _ in range(200):
+        n = int(rng.integers(1, 65))
+        p = min(0.95, float(rng.uniform(0.5, 1.6)) * 2.0 * k / max(n, 1))
+        comps.append((n, random_graph(rng, n, p)))
+    say("root split, random components, k", k)
+    solve_untraced(ctx, comps, k, 20000)
+
+
+def test_root_split_budget_cuts(ctx):
+    rng = np.random.default_rng(31)
+    comps = [(int(n), random_graph(rng, int(n), 0.4)) for n in rng.integers(8, 20, 40)]
+    say("root split, budget cuts")
+    for budget in (1, 2, 3, 7, 15, 40, 120, 1000):
+        solve_untraced(ctx, comps, 3, budget)
