@@ -301,6 +301,8 @@ typedef struct {
                                 MPLD_SPLIT_HEAVY); 0: off                      */
   int32_t root_split_min_n;  /* smallest component that gets one (>= 2)        */
   int32_t root_split_max;    /* most components that get one; 0 = all         */
+  int32_t root_split_chunk;  /* helper nodes between checks of the owner's
+                                release (>= 1)                                  */
 } mpld_tune;
 int32_t mpld_batch_autotune(mpld_batch* b, int32_t reps, const char* cache_path, mpld_tune* out);
 int32_t mpld_batch_get_tune(mpld_batch* b, mpld_tune* out);

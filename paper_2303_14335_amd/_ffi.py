@@ -82,7 +82,7 @@ class mpld_tune(ctypes.Structure):
                 ("default_ms", ctypes.c_float), ("candidates", c_i32), ("from_cache", c_i32),
                 ("heavy_first_cap", c_i32), ("heavy_round_cap", c_i32), ("heavy_levels", c_i32),
                 ("heavy_device", c_i32), ("root_split", c_i32), ("root_split_min_n", c_i32),
-                ("root_split_max", c_i32)]
+                ("root_split_max", c_i32), ("root_split_chunk", c_i32)]
 
 
 class mpld_server_options(ctypes.Structure):

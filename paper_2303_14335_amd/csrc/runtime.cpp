@@ -226,7 +226,7 @@ static void enqueue_batched(DeviceBatch& db, bool trace, uint64_t cap, hipStream
     const int32_t heavy = (!trace && cap == ~0ull) ? db.reg_heavy : 0;
     const int grid = heavy ? heavy + (db.n_reg - heavy + 3) / 4 : db.grid_reg;
     check_hip(launch_reg_batched(trace, db.k, grid, db.tune.waves_per_block, items, db.n_reg, cnt,
-                                 recs, colors, cap, heavy, s),
+                                 recs, colors, cap, heavy, (uint32_t)db.tune.root_split_chunk, s),
               "register-tier launch");
     ++db.launches;
   }

@@ -20,7 +20,7 @@ namespace mpld {
 // grid >= heavy + ceil((qlen - heavy) / 4)).
 hipError_t launch_reg_batched(bool trace, int k, int grid, int wpb, RegItems items,
                               int32_t qlen, int32_t* counter, DevRecord* recs, int8_t* colors,
-                              uint64_t cap, int32_t heavy, hipStream_t s);
+                              uint64_t cap, int32_t heavy, uint32_t chunk, hipStream_t s);
 // Heavy-component engine: explore / split subtree tasks.
 // Task t writes its output block at out + t * kSplitBlockBytes and its
 // split items to pool at an offset taken from *pool_count (zero before the
@@ -195,6 +195,7 @@ struct Tune {
   int32_t root_split = 1;          // root split of the largest register-tier items
   int32_t root_split_min_n = 4;    // smallest item that gets one
   int32_t root_split_max = 0;      // most items that get one; 0 = all
+  int32_t root_split_chunk = 16;   // helper nodes between release checks
 };
 
 // Adds one component (local numbering, pairs i < j or j < i) to the image.

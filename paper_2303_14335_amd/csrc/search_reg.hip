@@ -372,7 +372,8 @@ __device__ __forceinline__ void solve_reg(const RegItems& items, int32_t item,
 // rows, so the root column v0 is node 0 and its rows are the k colors.
 // Wave 0 (the owner) counts the root node and searches the subtree of row
 // 0; wave c = 1 .. min(k, 4) - 1 (a helper) searches the subtree of row c
-// from the same start, in chunks, and publishes its node count, status and
+// from the same start, in chunks of `chunk` nodes with a check of the
+// owner's release between them, and publishes its node count, status and
 // solution in LDS.  The owner takes the rows in order: for a helper's row it
 // waits for the helper and adds its count (an exhausted subtree: next row;
 // a solution: done), exactly as the sequential search would have counted
@@ -387,11 +388,9 @@ struct RootSplitLds {
   int8_t colors[4][64];
 };
 
-constexpr uint64_t kHelperChunk = 4;   // helper nodes between stop checks
-
 template <int K>
 __device__ __forceinline__ void root_split(const RegItems& items, int32_t item, uint32_t wave,
-                                           int8_t* __restrict__ colors_base,
+                                           uint32_t chunk, int8_t* __restrict__ colors_base,
                                            DevRecord* __restrict__ recs) {
   __shared__ RootSplitLds L;
   const uint32_t lane = __lane_id();
@@ -427,7 +426,7 @@ __device__ __forceinline__ void root_split(const RegItems& items, int32_t item, 
     take_row(s, nbv0, v0, c, 0ull);
     s.row_in = v0 * (uint32_t)d.k + c;
     for (;;) {
-      reg_run<false, K>(s, nb_lo, nb_hi, d.k, ~0ull, s.nodes + kHelperChunk, 1);
+      reg_run<false, K>(s, nb_lo, nb_hi, d.k, ~0ull, s.nodes + chunk, 1);
       if (s.status >= 0) break;
       if (__hip_atomic_load(&L.stop[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) != 0u)
         return;   // no longer needed
@@ -576,7 +575,8 @@ __device__ __forceinline__ uint32_t xcd_block() {
 template <bool TRACE, int K>
 __global__ __launch_bounds__(256) void reg_batched_kernel(
     const RegItems items, int32_t qlen, int32_t* __restrict__ counter,
-    DevRecord* __restrict__ recs, int8_t* __restrict__ colors, uint64_t cap, int32_t heavy) {
+    DevRecord* __restrict__ recs, int8_t* __restrict__ colors, uint64_t cap, int32_t heavy,
+    uint32_t chunk) {
   const uint32_t wpb = blockDim.x >> 6;   // waves per workgroup
   if (!TRACE && heavy > 0) {
     // root split: workgroups 0 .. heavy-1 take items 0 .. heavy-1 (four
@@ -584,7 +584,7 @@ __global__ __launch_bounds__(256) void reg_batched_kernel(
     // that every item is handed out here
     const uint32_t b = xcd_block(), wave = uniform(threadIdx.x >> 6);
     if (b < (uint32_t)heavy) {
-      root_split<K>(items, (int32_t)b, wave, colors, recs);
+      root_split<K>(items, (int32_t)b, wave, uniform(chunk), colors, recs);
     } else {
       const int32_t item = heavy + (int32_t)((b - (uint32_t)heavy) * wpb + wave);
       if (item < qlen) solve_reg<false, K>(items, item, colors, recs, cap);
@@ -901,12 +901,12 @@ static void with_planes(int k, F&& f) {
 
 hipError_t launch_reg_batched(bool trace, int k, int grid, int wpb, RegItems items,
                               int32_t qlen, int32_t* counter, DevRecord* recs, int8_t* colors,
-                              uint64_t cap, int32_t heavy, hipStream_t s) {
+                              uint64_t cap, int32_t heavy, uint32_t chunk, hipStream_t s) {
   if (qlen <= 0) return hipSuccess;
   if (wpb < 1 || wpb > 4) return hipErrorInvalidValue;
   // the root split needs four waves per workgroup and a grid that hands
   // out every item at once
-  if (heavy < 0 || heavy > qlen) return hipErrorInvalidValue;
+  if (heavy < 0 || heavy > qlen || chunk < 1) return hipErrorInvalidValue;
   if (heavy > 0 && (trace || wpb != 4 || cap != ~0ull ||
                     (int64_t)grid < heavy + ((int64_t)qlen - heavy + wpb - 1) / wpb))
     return hipErrorInvalidValue;
@@ -914,10 +914,10 @@ hipError_t launch_reg_batched(bool trace, int k, int grid, int wpb, RegItems ite
     constexpr int K = decltype(kp)::value;
     if (trace)
       hipLaunchKernelGGL((reg_batched_kernel<true, K>), dim3(grid), dim3(64 * wpb), 0, s, items,
-                         qlen, counter, recs, colors, cap, 0);
+                         qlen, counter, recs, colors, cap, 0, chunk);
     else
       hipLaunchKernelGGL((reg_batched_kernel<false, K>), dim3(grid), dim3(64 * wpb), 0, s, items,
-                         qlen, counter, recs, colors, cap, heavy);
+                         qlen, counter, recs, colors, cap, heavy, chunk);
   });
   return hipGetLastError();
 }
