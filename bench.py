@@ -178,23 +178,30 @@ def serve_leg(mp, ctx, count: int, seed: int):
 # the whole device), so launch and setup costs vanish in the per-node time.
 # The instances were picked so that the search runs to the budget.
 PROBES = [
-    # name, n, k, average degree, seed, budget, tier flag name
+    # name, n, k, average degree, seed, budget, tier flag name; the register
+    # probes run on one wave (root split off) and measure the per-node chain,
+    # "..._root_split" runs the same instance with the root split
     ("register_k3_n64", 64, 3, 4.4, 26, 200000, "MPLD_FORCE_WAVE"),
+    ("register_k3_n64_root_split", 64, 3, 4.4, 26, 200000, "MPLD_FORCE_WAVE"),
     ("register_k4_n64", 64, 4, 8.4, 0, 200000, "MPLD_FORCE_WAVE"),
+    ("lds_small_k3_n1000", 1000, 3, 4.6, 0, 20000, "MPLD_FORCE_LDS"),
     ("lds_k3_n10000", 10000, 3, 4.6, 0, 20000, "MPLD_FORCE_GLOBAL"),
     ("device_k3_n10000", 10000, 3, 4.6, 0, 2000, "MPLD_FORCE_DEVICE"),
 ]
 
 
-def latency_probe(mp, ctx, reps=3):
+def latency_probe(mp, ctx, reps=3, names=None):
     import numpy as np
     import torch
     import workload
     out = {}
     for name, n, k, deg, seed, budget, flag in PROBES:
+        if names and name not in names:
+            continue
         e = workload.random_component(n, deg, seed)
         g = mp.Graph(n, e, np.zeros((0, 2), np.int32))
         b = mp.Batch(ctx, g, k, budget, getattr(mp, flag))
+        b.set_tune(root_split=1 if name.endswith("_root_split") else 0)
         ms = []
         for _ in range(reps):
             b.solve(direct=True)
@@ -225,6 +232,10 @@ def main() -> int:
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-latency-probe", action="store_true")
+    ap.add_argument("--probe-only", action="store_true",
+                    help="run only the per-tier latency probes and print them as one JSON line")
+    ap.add_argument("--probes", type=str, default="",
+                    help="comma-separated probe names to run (default: all)")
     ap.add_argument("--no-mark", action="store_true",
                     help="skip the conflict-marking leg (MPLD_MARK_CONFLICTS on the same workload)")
     ap.add_argument("--serve-requests", type=int, default=1000,
@@ -246,6 +257,12 @@ def main() -> int:
     import paper_2303_14335_amd as mp
     import workload
     from workload.configs import CONFIGS
+
+    if args.probe_only:
+        ctx = mp.Context(0)
+        names = [x for x in args.probes.split(",") if x]
+        print(json.dumps({"latency_probe": latency_probe(mp, ctx, names=names)}), flush=True)
+        return 0
 
     w = CONFIGS[args.config]
     log(f"workload {w.name}: generating {w.n_rects} rectangles")
