@@ -19,7 +19,7 @@ _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 FEASIBLE, INFEASIBLE, BUDGET = 0, 1, 2
-SIMPLIFY, MARK = 1, 2
+SIMPLIFY, MARK, STITCH = 1, 2, 4
 
 
 class OrcComp(ctypes.Structure):
@@ -70,6 +70,11 @@ def _load():
                                             _p(ctypes.c_int64),
                                             _p(ctypes.c_uint64),
                                             _p(ctypes.c_int32)]
+        lib.orc_solve_component_stitch.restype = ctypes.c_int32
+        lib.orc_solve_component_stitch.argtypes = [ctypes.c_int32, ctypes.c_int64, vp,
+                                                   ctypes.c_int32, ctypes.c_int64, vp, vp,
+                                                   _p(ctypes.c_int32), _p(ctypes.c_int64),
+                                                   _p(ctypes.c_uint64), _p(ctypes.c_int32)]
         lib.orc_mark_conflicts.restype = ctypes.c_int32
         lib.orc_mark_conflicts.argtypes = [ctypes.c_int32, ctypes.c_int64, vp,
                                            ctypes.c_int32, vp]
@@ -146,9 +151,10 @@ COMP_DTYPE = np.dtype([("size", np.int32), ("status", np.int32),
 
 
 def decompose(g: Graph, k: int, budget: int, simplify: bool = True,
-              mark: bool = False) -> Decomposition:
+              mark: bool = False, stitch: bool = False) -> Decomposition:
     """Whole flow; mark=True colors the components left without a solution
-    by the conflict-marking descent (mark_conflicts)."""
+    by the conflict-marking descent (mark_conflicts); stitch=True searches
+    with the stitch-aware row order."""
     lib = _load()
     n = g.num_nodes
     ce = np.ascontiguousarray(g.ce, dtype=np.int32).reshape(-1, 2)
@@ -161,7 +167,8 @@ def decompose(g: Graph, k: int, budget: int, simplify: bool = True,
     cn = ctypes.c_int64()
     un = ctypes.c_int64()
     rc = lib.orc_decompose(n, len(ce), ce.ctypes.data, len(se), se.ctypes.data,
-                           k, budget, (SIMPLIFY if simplify else 0) | (MARK if mark else 0),
+                           k, budget, (SIMPLIFY if simplify else 0) | (MARK if mark else 0)
+                           | (STITCH if stitch else 0),
                            colors.ctypes.data, comp_of.ctypes.data,
                            ctypes.byref(nc), ctypes.byref(pcs),
                            ctypes.byref(st), ctypes.byref(cn), ctypes.byref(un))
@@ -182,7 +189,9 @@ class Solve:
     colors: np.ndarray
 
 
-def solve_component(n: int, edges, k: int, budget: int) -> Solve:
+def solve_component(n: int, edges, k: int, budget: int, partner=None) -> Solve:
+    """One component in local numbering; partner (n ints, -1 none) selects the
+    stitch-aware row order."""
     lib = _load()
     e = np.ascontiguousarray(np.asarray(edges, dtype=np.int32).reshape(-1, 2))
     colors = np.zeros(max(n, 1), dtype=np.int8)
@@ -190,10 +199,12 @@ def solve_component(n: int, edges, k: int, budget: int) -> Solve:
     nodes = ctypes.c_int64()
     h = ctypes.c_uint64()
     d = ctypes.c_int32()
-    rc = lib.orc_solve_component(n, len(e), e.ctypes.data, k, budget,
-                                 colors.ctypes.data, ctypes.byref(status),
-                                 ctypes.byref(nodes), ctypes.byref(h),
-                                 ctypes.byref(d))
+    part = None if partner is None else np.ascontiguousarray(np.asarray(partner, dtype=np.int32))
+    rc = lib.orc_solve_component_stitch(n, len(e), e.ctypes.data, k, budget,
+                                        None if part is None else part.ctypes.data,
+                                        colors.ctypes.data, ctypes.byref(status),
+                                        ctypes.byref(nodes), ctypes.byref(h),
+                                        ctypes.byref(d))
     if rc != 0:
         raise ValueError(f"orc_solve_component failed: {rc}")
     return Solve(status.value, nodes.value, h.value, d.value, colors[:n].copy())

@@ -221,6 +221,10 @@ typedef struct {
   int32_t status; /* -1 while running */
   int32_t depth_at_stop;
   int32_t* sol;   /* row chosen at each depth */
+  /* stitch-aware row order (NULL partner: rows ascending) */
+  int32_t k;
+  const int32_t* partner;   /* stitch partner of each node in the component, -1 none */
+  int8_t* color;            /* color of each node on the current path, -1 none */
 } orc_dlx;
 
 static void dlx_cover(orc_dlx* x, int32_t c) {
@@ -296,13 +300,27 @@ static void dlx_search(orc_dlx* x, int32_t depth, int32_t row_in) {
              (uint32_t)x->size[c]);
   if (x->size[c] == 0) return;
   dlx_cover(x, c);
-  for (int32_t r = x->D[c]; r != c; r = x->D[r]) {
-    x->sol[depth] = x->row[r];
-    for (int32_t j = x->R[r]; j != r; j = x->R[j]) dlx_cover(x, x->col[j]);
-    dlx_search(x, depth + 1, x->row[r]);
-    if (x->status >= 0) return;
-    for (int32_t j = x->L[r]; j != r; j = x->L[j]) dlx_uncover(x, x->col[j]);
+  /* Rows in ascending order; with the stitch-aware order the row of the
+   * color the column's stitch partner already has (if that row is still
+   * there) goes first (Eq. 1: a pair of halves colored alike is no stitch). */
+  int32_t first = -1;
+  if (x->partner) {
+    const int32_t v = c - 1, p = x->partner[v];
+    if (p >= 0 && x->color[p] >= 0)
+      for (int32_t r = x->D[c]; r != c; r = x->D[r])
+        if (x->row[r] == v * x->k + x->color[p]) first = r;
   }
+  for (int32_t pass = first >= 0 ? 0 : 1; pass < 2; ++pass)
+    for (int32_t r = pass == 0 ? first : x->D[c]; r != c; r = pass == 0 ? c : x->D[r]) {
+      if (pass == 1 && r == first) continue;
+      x->sol[depth] = x->row[r];
+      if (x->partner) x->color[x->row[r] / x->k] = (int8_t)(x->row[r] % x->k);
+      for (int32_t j = x->R[r]; j != r; j = x->R[j]) dlx_cover(x, x->col[j]);
+      dlx_search(x, depth + 1, x->row[r]);
+      if (x->status >= 0) return;
+      for (int32_t j = x->L[r]; j != r; j = x->L[j]) dlx_uncover(x, x->col[j]);
+      if (x->partner) x->color[x->row[r] / x->k] = -1;
+    }
   dlx_uncover(x, c);
 }
 
@@ -365,7 +383,19 @@ int32_t orc_solve_component(int32_t n, int64_t m, const int32_t* edges,
                             int32_t k, int64_t budget, int8_t* colors,
                             int32_t* status, int64_t* nodes,
                             uint64_t* trace_hash, int32_t* depth_at_stop) {
+  return orc_solve_component_stitch(n, m, edges, k, budget, NULL, colors, status, nodes,
+                                    trace_hash, depth_at_stop);
+}
+
+int32_t orc_solve_component_stitch(int32_t n, int64_t m, const int32_t* edges,
+                                   int32_t k, int64_t budget, const int32_t* partner,
+                                   int8_t* colors, int32_t* status, int64_t* nodes,
+                                   uint64_t* trace_hash, int32_t* depth_at_stop) {
   if (n < 0 || m < 0 || k < 1 || k > 127 || budget < 1) return -1;
+  if (partner)
+    for (int32_t v = 0; v < n; ++v)
+      if (partner[v] >= n || partner[v] == v || (partner[v] >= 0 && partner[partner[v]] != v))
+        return -1;
   if (m > 0 && !edges) return -1;
   orc_comp_graph g;
   int32_t rc = make_comp_graph(n, m, edges, k, &g);
@@ -384,6 +414,14 @@ int32_t orc_solve_component(int32_t n, int64_t m, const int32_t* edges,
     goto done;
   }
   dlx_link(&x, n, ncols, rows, rp, ci);
+  x.k = k;
+  x.partner = partner;
+  x.color = NULL;
+  if (partner) {
+    x.color = (int8_t*)malloc((size_t)n + 1);
+    if (!x.color) { rc = -2; goto done; }
+    for (int32_t v = 0; v < n; ++v) x.color[v] = -1;
+  }
   x.budget = budget;
   x.nodes = 0;
   x.hash = 0xcbf29ce484222325ULL;
@@ -401,6 +439,7 @@ int32_t orc_solve_component(int32_t n, int64_t m, const int32_t* edges,
   if (depth_at_stop) *depth_at_stop = x.status == ORC_INFEASIBLE ? 0 : x.depth_at_stop;
   rc = 0;
 done:
+  free(x.color);
   dlx_free(&x);
   free(rp); free(ci);
   free_comp_graph(&g);
@@ -634,10 +673,11 @@ int32_t orc_decompose(int32_t num_nodes, int64_t num_ce, const int32_t* ce,
   int32_t* local = (int32_t*)malloc(sizeof(int32_t) * ((size_t)n + 1));
   int32_t* ledges = (int32_t*)malloc(sizeof(int32_t) * 2 * (size_t)(num_ce + 1));
   int8_t* lcolors = (int8_t*)malloc((size_t)n + 1);
+  int32_t* lpartner = (int32_t*)malloc(sizeof(int32_t) * ((size_t)n + 1));
   orc_comp* cs = NULL;
   int32_t nrem = 0, nc = 0;
   if (!ap || !adj || !partner || !removal || !bfs || !comp_ptr || !local ||
-      !ledges || !lcolors) { rc = -2; goto out; }
+      !ledges || !lcolors || !lpartner) { rc = -2; goto out; }
   rc = build_adjacency(n, num_ce, ce, num_se, se, ap, adj, partner);
   if (rc) goto out;
   rc = simplify_split(n, ap, adj, k, flags, removal, &nrem, comp_of, bfs,
@@ -667,8 +707,14 @@ int32_t orc_decompose(int32_t num_nodes, int64_t num_ce, const int32_t* ce,
     r->size = size;
     r->first_node = nodes[0];
     r->num_edges = (int32_t)lm;
-    rc = orc_solve_component(size, lm, ledges, k, budget, lcolors, &r->status,
-                             &r->nodes, &r->trace_hash, &r->depth_at_stop);
+    if (flags & ORC_STITCH)   /* stitch partners inside the component, local ids */
+      for (int32_t i = 0; i < size; ++i) {
+        const int32_t p = partner[nodes[i]];
+        lpartner[i] = p >= 0 && comp_of[p] == c ? local[p] : -1;
+      }
+    rc = orc_solve_component_stitch(size, lm, ledges, k, budget,
+                                    (flags & ORC_STITCH) ? lpartner : NULL, lcolors,
+                                    &r->status, &r->nodes, &r->trace_hash, &r->depth_at_stop);
     if (rc) goto out;
     const int marked = r->status != ORC_FEASIBLE && (flags & ORC_MARK);
     if (marked) {
@@ -729,7 +775,7 @@ int32_t orc_decompose(int32_t num_nodes, int64_t num_ce, const int32_t* ce,
   cs = NULL;
 out:
   free(ap); free(adj); free(partner); free(removal); free(bfs); free(comp_ptr);
-  free(local); free(ledges); free(lcolors); free(cs);
+  free(local); free(ledges); free(lcolors); free(lpartner); free(cs);
   return rc;
 }
 

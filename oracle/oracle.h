@@ -26,7 +26,7 @@ extern "C" {
 #endif
 
 enum { ORC_FEASIBLE = 0, ORC_INFEASIBLE = 1, ORC_BUDGET = 2 };
-enum { ORC_SIMPLIFY = 1, ORC_MARK = 2 };
+enum { ORC_SIMPLIFY = 1, ORC_MARK = 2, ORC_STITCH = 4 };
 
 typedef struct { int32_t x0, y0, x1, y1; } orc_rect;
 
@@ -56,7 +56,9 @@ int32_t orc_build_graph(const orc_rect* rects, int32_t n, int32_t dmin,
                         int32_t** se);
 
 /* Full decomposition of a graph.  flags: ORC_SIMPLIFY, ORC_MARK (components
- * the search leaves without a solution are colored by orc_mark_conflicts).
+ * the search leaves without a solution are colored by orc_mark_conflicts),
+ * ORC_STITCH (stitch-aware row order, orc_solve_component_stitch, with each
+ * node's stitch partner when the partner is in the same component).
  * colors (num_nodes, -1 = uncolored) and
  * comp_of (num_nodes, -1 = removed by simplification) are caller-allocated;
  * *comps is malloc'ed (free with orc_free).  Totals may be NULL. */
@@ -82,6 +84,17 @@ int32_t orc_solve_component(int32_t n, int64_t m, const int32_t* edges,
                             int32_t k, int64_t budget, int8_t* colors,
                             int32_t* status, int64_t* nodes,
                             uint64_t* trace_hash, int32_t* depth_at_stop);
+
+/* The same search with a stitch-aware row order (Eq. 1 counts a stitch for
+ * each pair of split halves colored differently): when the chosen column's
+ * node has a stitch partner (partner[v], local id, -1 none; symmetric) that
+ * is already colored on the current path and the row of that color is
+ * still present, that row is tried first, the others follow in ascending
+ * order.  partner = NULL is orc_solve_component. */
+int32_t orc_solve_component_stitch(int32_t n, int64_t m, const int32_t* edges,
+                                   int32_t k, int64_t budget, const int32_t* partner,
+                                   int8_t* colors, int32_t* status, int64_t* nodes,
+                                   uint64_t* trace_hash, int32_t* depth_at_stop);
 
 /* Conflict marking of Algorithm 1 for one component in local numbering:
  * the no-backtracking descent of the search in which a column left with

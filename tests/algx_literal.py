@@ -36,7 +36,10 @@ def fnv1a_words(h: int, words) -> int:
     return h
 
 
-def algx_sets(n: int, edges, k: int, budget: int):
+def algx_sets(n: int, edges, k: int, budget: int, partner=None):
+    """partner (n ints, -1 none): stitch-aware row order - a column whose
+    node's partner is colored on the current path tries the row of that
+    color first (if present), then the rest ascending."""
     edges = sorted((min(u, w), max(u, w)) for u, w in edges)
     rows = {}
     for v in range(n):
@@ -89,7 +92,14 @@ def algx_sets(n: int, edges, k: int, budget: int):
         st["hash"] = fnv1a_words(st["hash"], [depth, row_in, best, size])
         if size == 0:
             return
-        for r in sorted(cols[("p", best)]):
+        order = sorted(cols[("p", best)])
+        if partner is not None and partner[best] >= 0:
+            colored = {row // k: row % k for row in solution}
+            pref = colored.get(int(partner[best]))
+            if pref is not None and best * k + pref in order:
+                order.remove(best * k + pref)
+                order.insert(0, best * k + pref)
+        for r in order:
             solution.append(r)
             undo = choose_row(r)
             search(depth + 1, r)
