@@ -104,7 +104,7 @@ enum {
                                   the search (last_search_ms keeps the value of
                                   the last timed solve); for callers timing
                                   many back-to-back solves themselves */
-  MPLD_MARK_CONFLICTS = 1u << 10 /* conflict marking (Algorithm 1, a column
+  MPLD_MARK_CONFLICTS = 1u << 10, /* conflict marking (Algorithm 1, a column
                                   left with no related row is a conflict
                                   candidate): a component whose search ends
                                   INFEASIBLE or BUDGET_EXHAUSTED is still
@@ -116,6 +116,17 @@ enum {
                                   counted on the colors.  Decompose, batches
                                   and mpld_solve_components only (a server
                                   rejects it with MPLD_E_UNSUPPORTED). */
+  MPLD_STITCH_ORDER = 1u << 11 /* stitch-aware row order (Eq. 1 counts a stitch
+                                  for each pair of split halves colored
+                                  differently): when the chosen column's node
+                                  has its stitch partner in the component and
+                                  already colored on the path, the row of the
+                                  partner's color (if open) is tried first,
+                                  the others follow ascending.  Register tier
+                                  only: components of more than 64 nodes or a
+                                  forced LDS/global/device tier give
+                                  MPLD_E_UNSUPPORTED; disables
+                                  MPLD_SPLIT_HEAVY; not with a server. */
 };
 
 typedef struct { int32_t x0, y0, x1, y1; } mpld_rect;  /* nm, closed box */

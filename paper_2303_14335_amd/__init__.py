@@ -17,7 +17,7 @@ import numpy as np
 from . import _ffi
 from ._ffi import (MPLD_BUDGET_EXHAUSTED, MPLD_FEASIBLE, MPLD_FORCE_DEVICE,  # noqa: F401
                    MPLD_FORCE_GLOBAL, MPLD_FORCE_LDS, MPLD_FORCE_WAVE, MPLD_INFEASIBLE,
-                   MPLD_MARK_CONFLICTS, MPLD_PLAIN, MPLD_SIMPLIFY, MPLD_SPLIT_HEAVY,
+                   MPLD_MARK_CONFLICTS, MPLD_PLAIN, MPLD_SIMPLIFY, MPLD_SPLIT_HEAVY, MPLD_STITCH_ORDER,
                    MPLD_TRACE_HASH)
 
 _lib = _ffi.load()

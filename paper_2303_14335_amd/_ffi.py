@@ -29,6 +29,7 @@ MPLD_FORCE_DEVICE = 1 << 7
 MPLD_SPLIT_HEAVY = 1 << 8
 MPLD_UNTIMED = 1 << 9
 MPLD_MARK_CONFLICTS = 1 << 10
+MPLD_STITCH_ORDER = 1 << 11
 
 c_i32, c_i64, c_u32, c_u64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint64
 vp = ctypes.c_void_p

@@ -28,14 +28,17 @@ static_assert(sizeof(DevDesc) == 32, "descriptor is 32 bytes");
 // Register-tier work items (n <= 64), stored in launch order.  Item i is a
 // 32-byte descriptor followed by `width` neighbour masks (mask v = the
 // conflict neighbours of local node v; zero past n) at byte offset
-// i * stride, stride = 32 + 8 * width.  One width per batch (the largest n
+// i * stride, stride = 32 + 8 * width (+ 8-byte-rounded partner bytes with
+// the stitch-aware order).  One width per batch (the largest n
 // of its items) keeps the address a function of the index, so a wave
 // issues the descriptor and mask loads at once, and lanes at or past
 // `width` load nothing.
 struct RegItems {
   const uint8_t* base;
-  uint32_t width;    // 1 .. 64
-  uint32_t stride;   // 32 + 8 * width bytes
+  uint32_t width;      // 1 .. 64
+  uint32_t stride;     // 32 + 8 * width bytes (+ the partner bytes)
+  uint32_t part_off;   // with the stitch-aware order: offset of `width` bytes
+                       // of local stitch partners (0xff none) in an item; 0 = none
 };
 constexpr uint32_t kRegItemHead = 32;
 inline uint32_t reg_item_width(int32_t max_n) { return max_n < 1 ? 1u : (uint32_t)max_n; }

@@ -21,7 +21,7 @@ void check_hip(hipError_t e, const char* what) {
 // LDS tiers: row offsets (n + 1), neighbour ids (2m), largest degree.
 
 void image_add(Image& im, mpld_context* ctx, int32_t n, const int32_t* pairs, int64_t m, int32_t k,
-               int64_t budget, uint32_t flags) {
+               int64_t budget, uint32_t flags, const int32_t* partner) {
   DevDesc d{};
   d.n = n;
   d.k = k;
@@ -31,9 +31,20 @@ void image_add(Image& im, mpld_context* ctx, int32_t n, const int32_t* pairs, in
   d.comp = id;
   const bool force_lds = flags & MPLD_FORCE_LDS, force_glb = flags & MPLD_FORCE_GLOBAL,
              force_reg = flags & MPLD_FORCE_WAVE, force_dev = flags & MPLD_FORCE_DEVICE;
+  const bool stitch = flags & MPLD_STITCH_ORDER;
+  if (stitch && (n > 64 || force_lds || force_glb || force_dev))
+    fail(MPLD_E_UNSUPPORTED, "the stitch-aware order runs on the register tier (components of at "
+                             "most 64 nodes); component has " + std::to_string(n));
   if (n <= 64 && !force_lds && !force_glb && !force_dev) {
     d.nbr_off = (int64_t)im.masks.size();
     im.masks.resize(im.masks.size() + (size_t)n, 0ull);
+    im.partner8.resize(im.masks.size(), 0xffu);
+    if (stitch) {
+      im.stitch = true;
+      if (partner)
+        for (int32_t v = 0; v < n; ++v)
+          if (partner[v] >= 0) im.partner8[(size_t)d.nbr_off + v] = (uint8_t)partner[v];
+    }
     uint64_t* mk = im.masks.data() + d.nbr_off;
     for (int64_t e = 0; e < m; ++e) {
       const int32_t a = pairs[2 * e], b = pairs[2 * e + 1];
@@ -173,13 +184,19 @@ void device_upload(mpld_context* ctx, const Image& im, DeviceBatch& db, const Tu
   int32_t max_reg_n = 0;
   for (int32_t i = 0; i < db.n_reg; ++i) max_reg_n = std::max(max_reg_n, ordered[(size_t)i].n);
   db.reg_width = reg_item_width(max_reg_n);
-  const size_t stride = kRegItemHead + 8u * db.reg_width;
+  db.reg_stitch = im.stitch;
+  const RegItems shape = db.reg_items();
+  const size_t stride = shape.stride;
   std::vector<uint8_t> items(stride * (size_t)db.n_reg, 0);
   for (int32_t i = 0; i < db.n_reg; ++i) {
     uint8_t* it = items.data() + stride * (size_t)i;
     const DevDesc& d = ordered[(size_t)i];
     std::memcpy(it, &d, sizeof(DevDesc));
     std::memcpy(it + kRegItemHead, im.masks.data() + d.nbr_off, sizeof(uint64_t) * (size_t)d.n);
+    if (shape.part_off) {
+      std::memset(it + shape.part_off, 0xff, db.reg_width);
+      std::memcpy(it + shape.part_off, im.partner8.data() + d.nbr_off, (size_t)d.n);
+    }
   }
 
   db.desc.alloc(ctx, sizeof(DevDesc) * ordered.size());
@@ -754,7 +771,8 @@ void device_solve(DeviceBatch& db, uint32_t flags) {
     fail(MPLD_E_UNSUPPORTED, "a component is too large for conflict marking (" +
                                  std::to_string(db.mark_lds) + " bytes of LDS)");
   const bool trace = flags & MPLD_TRACE_HASH;
-  const bool split = (flags & MPLD_SPLIT_HEAVY) && !trace && !(flags & MPLD_PLAIN) && db.n_reg > 0;
+  const bool split = (flags & MPLD_SPLIT_HEAVY) && !trace && !(flags & MPLD_PLAIN) && db.n_reg > 0 &&
+                     !db.reg_stitch;   // the subtree engine replays rows in ascending order
   const uint64_t cap = split ? (uint64_t)db.tune.heavy_first_cap : ~0ull;
   const bool timed = !(flags & MPLD_UNTIMED) || (flags & MPLD_PLAIN);
   db.timed = false;

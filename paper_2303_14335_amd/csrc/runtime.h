@@ -163,6 +163,8 @@ struct PinnedBuf {
 struct Image {
   std::vector<DevDesc> desc;       // by component id
   std::vector<uint64_t> masks;     // register tier: one neighbour mask per node
+  std::vector<uint8_t> partner8;   // register tier: local stitch partner per node (0xff none)
+  bool stitch = false;             // MPLD_STITCH_ORDER: items carry the partners
   std::vector<uint32_t> adj32;     // LDS tiers: row offsets, ids, max degree
   std::vector<int32_t> q_reg, q_lds, q_big, q_dev;   // component ids per tier
   int32_t total_nodes = 0;
@@ -201,8 +203,9 @@ struct Tune {
 // Adds one component (local numbering, pairs i < j or j < i) to the image.
 // Throws MPLD_E_UNSUPPORTED when a forced tier cannot take it or it does
 // not fit any tier.
+// partner: local stitch partner per node (-1 none), for MPLD_STITCH_ORDER.
 void image_add(Image& im, mpld_context* ctx, int32_t n, const int32_t* pairs, int64_t m,
-               int32_t k, int64_t budget, uint32_t flags);
+               int32_t k, int64_t budget, uint32_t flags, const int32_t* partner = nullptr);
 // Sorts each tier's queue by size (descending, or ascending when order = 1),
 // ties by id.
 void image_finish(Image& im, int order = 0);
@@ -212,8 +215,11 @@ struct DeviceBatch {
   mpld_context* ctx = nullptr;
   DevBuf desc, regitems, adj32, counters, recs, colors, gstack;  // desc in launch order
   uint32_t reg_width = 1;   // masks per register-tier item
+  bool reg_stitch = false;  // items carry stitch partners
   RegItems reg_items() const {
-    return RegItems{regitems.as<uint8_t>(), reg_width, kRegItemHead + 8u * reg_width};
+    const uint32_t pb = reg_stitch ? (reg_width + 7u) & ~7u : 0u;
+    return RegItems{regitems.as<uint8_t>(), reg_width, kRegItemHead + 8u * reg_width + pb,
+                    reg_stitch ? kRegItemHead + 8u * reg_width : 0u};
   }
   DevBuf dev_keys, dev_stacks;      // device-wide tier
   DevBuf sp_tasks, sp_out, sp_pool, sp_writes;      // heavy-component engine

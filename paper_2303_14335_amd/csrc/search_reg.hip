@@ -216,9 +216,10 @@ __device__ __forceinline__ uint64_t with_bit(uint64_t A, uint32_t d, uint64_t on
 // Takes row (v, c) at the current depth (column v already removed from P):
 // snapshot of P and the planes and the frame to lane `depth`, then the
 // cover; `alt` says whether column v has rows after c.
-template <int K>
+template <int K, bool STITCH = false>
 __device__ __forceinline__ void take_row(RegState<K>& s, const uint64_t nbv, const uint32_t v,
-                                         const uint32_t c, const uint64_t alt) {
+                                         const uint32_t c, const uint64_t alt,
+                                         const uint32_t tried = 0) {
   const uint32_t d = s.depth;
   s.sp_lo = wrlane(s.sp_lo, d, (uint32_t)s.P);
   s.sp_hi = wrlane(s.sp_hi, d, (uint32_t)(s.P >> 32));
@@ -227,7 +228,7 @@ __device__ __forceinline__ void take_row(RegState<K>& s, const uint64_t nbv, con
     s.so_lo[j] = wrlane(s.so_lo[j], d, (uint32_t)s.O[j]);
     s.so_hi[j] = wrlane(s.so_hi[j], d, (uint32_t)(s.O[j] >> 32));
   }
-  s.fr = wrlane(s.fr, d, v | (c << 8));
+  s.fr = wrlane(s.fr, d, STITCH ? (v | (c << 8) | (tried << 16)) : (v | (c << 8)));
   cover(s.O, c, nbv);
   s.A = with_bit(s.A, d, alt);
   s.depth = d + 1;
@@ -239,9 +240,9 @@ __device__ __forceinline__ void take_row(RegState<K>& s, const uint64_t nbv, con
 // uncovers their columns).  Sets v, c to that column and its next row and
 // `alt` to whether more rows follow (1 or 0); returns false when no such
 // frame exists (the subtree below `floor` is exhausted).
-template <int K>
+template <int K, bool STITCH = false>
 __device__ __forceinline__ bool retreat(RegState<K>& s, const uint32_t floor, uint32_t& v,
-                                        uint32_t& c, uint64_t& alt) {
+                                        uint32_t& c, uint64_t& alt, uint32_t& tried) {
   const uint64_t open = s.A & below(s.depth) & ~below(floor);
   if (open == 0) {   // exhausted: every frame above the floor is dropped
     s.depth = floor;
@@ -253,11 +254,13 @@ __device__ __forceinline__ bool retreat(RegState<K>& s, const uint32_t floor, ui
 #pragma unroll
   for (int j = 0; j < K; ++j) s.O[j] = rdlane64(s.so_lo[j], s.so_hi[j], d);
   v = f & 0xffu;
-  const uint32_t cp = f >> 8;
   const uint32_t R = rows_of(s.O, v);   // the rows of v when it was chosen
-  const uint32_t next = R & (0xfffffffeu << cp);
+  // rows not tried yet: above the last one in ascending order; with the
+  // stitch-aware order the frame keeps the set tried (bits 16..23)
+  const uint32_t next = STITCH ? R & ~(f >> 16) : R & (0xfffffffeu << (f >> 8));
   c = (uint32_t)__builtin_ctz(next);
   alt = (next & (next - 1u)) != 0 ? 1ull : 0ull;
+  if (STITCH) tried = (f >> 16) | (1u << c);
   s.depth = d;
   return true;
 }
@@ -268,10 +271,11 @@ __device__ __forceinline__ bool retreat(RegState<K>& s, const uint32_t floor, ui
 // the node at depth `floor` (backtracking never returns above it;
 // exhausting the subtree reports MPLD_INFEASIBLE).  nb_lo/nb_hi: lane v
 // holds N(v).  Every lane of the wave must call it.
-template <bool TRACE, int K>
+template <bool TRACE, int K, bool STITCH = false>
 __device__ __forceinline__ void reg_run(RegState<K>& s, const uint32_t nb_lo, const uint32_t nb_hi,
                                         const int32_t k, const uint64_t budget,
-                                        const uint64_t stop_at, const uint32_t floor = 0) {
+                                        const uint64_t stop_at, const uint32_t floor = 0,
+                                        const uint32_t* __restrict__ part = nullptr) {
   int32_t status = -1;
   while (status < 0) {
     // ---- one search node
@@ -290,7 +294,7 @@ __device__ __forceinline__ void reg_run(RegState<K>& s, const uint32_t nb_lo, co
 #pragma unroll
     for (int j = 1; j < K; ++j) any |= s.O[j];
     const uint64_t zero = s.P & ~any;
-    uint32_t v, c;
+    uint32_t v, c, tried = 0;
     uint64_t alt;
     if (__builtin_expect(zero == 0, 1)) {
       // every uncovered column has rows: cover the one of fewest rows and
@@ -300,17 +304,36 @@ __device__ __forceinline__ void reg_run(RegState<K>& s, const uint32_t nb_lo, co
       if (TRACE) s.h = trace_node(s.h, s.depth, s.row_in, v, (uint32_t)__popc(rows_of(s.O, v)));
       c = first_color(s.O, v);
       alt = (ge2 >> v) & 1ull;
+      if (STITCH) {
+        // stitch-aware order: the color of v's stitch partner first, when
+        // the partner is on the path (covered) and that row is still open
+        const uint32_t R = rows_of(s.O, v);
+        tried = R & ((2u << c) - 1u);
+        // v's partner id: a byte of the item's partner block, read at a
+        // wave-uniform address
+        const uint32_t p = uniform((part[v >> 2] >> ((v & 3u) * 8u)) & 0xffu);
+        // branch-free: the frame of the partner's column, if it is on the
+        // path, gives its color
+        const bool on_path = p < 64u && !((s.P >> (p & 63u)) & 1ull);
+        const uint64_t at =
+            __ballot(on_path && __lane_id() < s.depth && (s.fr & 0xffu) == p) | (1ull << 63);
+        const uint32_t cp =
+            uniform((rdlane(s.fr, (uint32_t)__builtin_ctzll(at)) >> 8) & 0x1fu);
+        const bool use = (at & ~(1ull << 63)) != 0ull && ((R >> cp) & 1u);
+        c = uniform(use ? cp : c);
+        tried = uniform(use ? 1u << cp : tried);
+      }
       asm("s_bitset0_b64 %0, %1" : "+s"(s.P) : "s"(uniform(v)));   // cover column v
     } else {
       // a column without rows (the first by index is the one chosen): dead end
       if (TRACE) s.h = trace_node(s.h, s.depth, s.row_in, low_bit(zero), 0);
-      if (!retreat(s, floor, v, c, alt)) {
+      if (!retreat<K, STITCH>(s, floor, v, c, alt, tried)) {
         status = MPLD_INFEASIBLE;
         continue;
       }
     }
     // ---- include row (v, c)
-    take_row(s, rdlane64(nb_lo, nb_hi, v), v, c, alt);
+    take_row<K, STITCH>(s, rdlane64(nb_lo, nb_hi, v), v, c, alt, tried);
     s.row_in = v * (uint32_t)k + c;
   }
   s.status = status;
@@ -351,19 +374,26 @@ __device__ __forceinline__ uint64_t item_mask(const RegItems& R, int32_t i, uint
   const uint64_t* m = reinterpret_cast<const uint64_t*>(R.base + (uint64_t)i * R.stride + kRegItemHead);
   return lane < R.width ? m[lane] : 0ull;   // zero past n
 }
+// The item's stitch partner block: byte v is the partner (local id) of node
+// v, 0xff for none; 8-byte aligned, so it is read as 32-bit words.
+__device__ __forceinline__ const uint32_t* item_partners(const RegItems& R, int32_t i) {
+  return reinterpret_cast<const uint32_t*>(R.base + (uint64_t)i * R.stride + R.part_off);
+}
 
-template <bool TRACE, int K>
+template <bool TRACE, int K, bool STITCH = false>
 __device__ __forceinline__ void solve_reg(const RegItems& items, int32_t item,
                                           int8_t* __restrict__ colors_base,
                                           DevRecord* __restrict__ recs,
                                           const uint64_t cap = ~0ull) {
   const uint32_t lane = __lane_id();
   const uint64_t nb = item_mask(items, item, lane);
+  const uint32_t* part = STITCH ? item_partners(items, item) : nullptr;
   const DevDesc d = item_desc(items, item);
   const uint64_t budget = (uint64_t)d.budget;
   RegState<K> s;
   reg_init(s, d.n, d.k);
-  reg_run<TRACE, K>(s, (uint32_t)nb, (uint32_t)(nb >> 32), d.k, budget, cap < budget ? cap : budget);
+  reg_run<TRACE, K, STITCH>(s, (uint32_t)nb, (uint32_t)(nb >> 32), d.k, budget,
+                            cap < budget ? cap : budget, 0, part);
   reg_finish(s, d.n, colors_base + d.out_off, recs + d.comp);
 }
 
@@ -388,7 +418,7 @@ struct RootSplitLds {
   int8_t colors[4][64];
 };
 
-template <int K>
+template <int K, bool STITCH>
 __device__ __forceinline__ void root_split(const RegItems& items, int32_t item, uint32_t wave,
                                            uint32_t chunk, int8_t* __restrict__ colors_base,
                                            DevRecord* __restrict__ recs) {
@@ -403,6 +433,7 @@ __device__ __forceinline__ void root_split(const RegItems& items, int32_t item, 
   const DevDesc d = item_desc(items, item);
   const uint64_t nb = item_mask(items, item, lane);
   const uint32_t nb_lo = (uint32_t)nb, nb_hi = (uint32_t)(nb >> 32);
+  const uint32_t* part = STITCH ? item_partners(items, item) : nullptr;
   const uint64_t budget = (uint64_t)d.budget;
   RegState<K> s;
   reg_init(s, d.n, d.k);
@@ -423,10 +454,10 @@ __device__ __forceinline__ void root_split(const RegItems& items, int32_t item, 
     // ---- helper: the subtree of root row c
     const uint32_t c = wave;
     if (!((R0 >> c) & 1u)) return;   // the owner never asks for a missing row
-    take_row(s, nbv0, v0, c, 0ull);
+    take_row<K, STITCH>(s, nbv0, v0, c, 0ull, R0 & ((2u << c) - 1u));
     s.row_in = v0 * (uint32_t)d.k + c;
     for (;;) {
-      reg_run<false, K>(s, nb_lo, nb_hi, d.k, ~0ull, s.nodes + chunk, 1);
+      reg_run<false, K, STITCH>(s, nb_lo, nb_hi, d.k, ~0ull, s.nodes + chunk, 1, part);
       if (s.status >= 0) break;
       if (__hip_atomic_load(&L.stop[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) != 0u)
         return;   // no longer needed
@@ -473,9 +504,9 @@ __device__ __forceinline__ void root_split(const RegItems& items, int32_t item, 
     s.O = O0;
     s.P = P0;
     s.depth = 0;
-    take_row(s, nbv0, v0, c, rem != 0u ? 1ull : 0ull);
+    take_row<K, STITCH>(s, nbv0, v0, c, rem != 0u ? 1ull : 0ull, R0 & ((2u << c) - 1u));
     s.row_in = v0 * (uint32_t)d.k + c;
-    reg_run<false, K>(s, nb_lo, nb_hi, d.k, budget, budget, 1);
+    reg_run<false, K, STITCH>(s, nb_lo, nb_hi, d.k, budget, budget, 1, part);
     if (s.status != MPLD_INFEASIBLE) {
       status = s.status;
       break;
@@ -572,7 +603,7 @@ __device__ __forceinline__ uint32_t xcd_block() {
 // one pop, so the pop that returns qlen - 1 is the last one: it resets the
 // counter to 0 and the launch (or the graph holding it) can be replayed with
 // no memset.
-template <bool TRACE, int K>
+template <bool TRACE, int K, bool STITCH>
 __global__ __launch_bounds__(256) void reg_batched_kernel(
     const RegItems items, int32_t qlen, int32_t* __restrict__ counter,
     DevRecord* __restrict__ recs, int8_t* __restrict__ colors, uint64_t cap, int32_t heavy,
@@ -584,17 +615,17 @@ __global__ __launch_bounds__(256) void reg_batched_kernel(
     // that every item is handed out here
     const uint32_t b = xcd_block(), wave = uniform(threadIdx.x >> 6);
     if (b < (uint32_t)heavy) {
-      root_split<K>(items, (int32_t)b, wave, uniform(chunk), colors, recs);
+      root_split<K, STITCH>(items, (int32_t)b, wave, uniform(chunk), colors, recs);
     } else {
       const int32_t item = heavy + (int32_t)((b - (uint32_t)heavy) * wpb + wave);
-      if (item < qlen) solve_reg<false, K>(items, item, colors, recs, cap);
+      if (item < qlen) solve_reg<false, K, STITCH>(items, item, colors, recs, cap);
     }
     return;
   }
   const int32_t gw = (int32_t)(gridDim.x * wpb);
   int32_t item = (int32_t)uniform(xcd_block() * wpb + (threadIdx.x >> 6));
   while (item < qlen) {
-    solve_reg<TRACE, K>(items, item, colors, recs, cap);
+    solve_reg<TRACE, K, STITCH>(items, item, colors, recs, cap);
     if (gw >= qlen) break;   // every item was handed out statically
     int32_t r = 0;
     if (__lane_id() == 0) r = atomicAdd(counter, 1);
@@ -605,11 +636,11 @@ __global__ __launch_bounds__(256) void reg_batched_kernel(
 }
 
 // One component per launch (the plain solver): a single wave.
-template <bool TRACE, int K>
+template <bool TRACE, int K, bool STITCH>
 __global__ __launch_bounds__(64) void reg_single_kernel(const RegItems items,
                                                         int32_t item, DevRecord* __restrict__ recs,
                                                         int8_t* __restrict__ colors) {
-  solve_reg<TRACE, K>(items, item, colors, recs);
+  solve_reg<TRACE, K, STITCH>(items, item, colors, recs);
 }
 
 // Conflict marking (Algorithm 1: a column left with no related row is a
@@ -801,7 +832,8 @@ __device__ __forceinline__ int32_t reg_enumerate(RegState<K>& s, const uint32_t 
         s.P &= ~(1ull << v);
       }
     }
-    if (back && !retreat(s, d, v, c, alt)) {
+    uint32_t tried_unused = 0;
+    if (back && !retreat(s, d, v, c, alt, tried_unused)) {
       emit(1);
       break;
     }
@@ -910,14 +942,22 @@ hipError_t launch_reg_batched(bool trace, int k, int grid, int wpb, RegItems ite
   if (heavy > 0 && (trace || wpb != 4 || cap != ~0ull ||
                     (int64_t)grid < heavy + ((int64_t)qlen - heavy + wpb - 1) / wpb))
     return hipErrorInvalidValue;
+  const bool stitch = items.part_off != 0;   // the items carry stitch partners
   with_planes(k, [&](auto kp) {
     constexpr int K = decltype(kp)::value;
-    if (trace)
-      hipLaunchKernelGGL((reg_batched_kernel<true, K>), dim3(grid), dim3(64 * wpb), 0, s, items,
-                         qlen, counter, recs, colors, cap, 0, chunk);
+    const dim3 g(grid), b(64 * wpb);
+    if (trace && stitch)
+      hipLaunchKernelGGL((reg_batched_kernel<true, K, true>), g, b, 0, s, items, qlen, counter, recs,
+                         colors, cap, 0, chunk);
+    else if (trace)
+      hipLaunchKernelGGL((reg_batched_kernel<true, K, false>), g, b, 0, s, items, qlen, counter,
+                         recs, colors, cap, 0, chunk);
+    else if (stitch)
+      hipLaunchKernelGGL((reg_batched_kernel<false, K, true>), g, b, 0, s, items, qlen, counter,
+                         recs, colors, cap, heavy, chunk);
     else
-      hipLaunchKernelGGL((reg_batched_kernel<false, K>), dim3(grid), dim3(64 * wpb), 0, s, items,
-                         qlen, counter, recs, colors, cap, heavy, chunk);
+      hipLaunchKernelGGL((reg_batched_kernel<false, K, false>), g, b, 0, s, items, qlen, counter,
+                         recs, colors, cap, heavy, chunk);
   });
   return hipGetLastError();
 }
@@ -934,14 +974,21 @@ hipError_t launch_mark_reg(int k, int grid, RegItems items, int32_t qlen, const 
 
 hipError_t launch_reg_single(bool trace, int k, RegItems items, int32_t item,
                              DevRecord* recs, int8_t* colors, hipStream_t s) {
+  const bool stitch = items.part_off != 0;
   with_planes(k, [&](auto kp) {
     constexpr int K = decltype(kp)::value;
-    if (trace)
-      hipLaunchKernelGGL((reg_single_kernel<true, K>), dim3(1), dim3(64), 0, s, items, item, recs,
-                         colors);
+    if (trace && stitch)
+      hipLaunchKernelGGL((reg_single_kernel<true, K, true>), dim3(1), dim3(64), 0, s, items, item,
+                         recs, colors);
+    else if (trace)
+      hipLaunchKernelGGL((reg_single_kernel<true, K, false>), dim3(1), dim3(64), 0, s, items, item,
+                         recs, colors);
+    else if (stitch)
+      hipLaunchKernelGGL((reg_single_kernel<false, K, true>), dim3(1), dim3(64), 0, s, items, item,
+                         recs, colors);
     else
-      hipLaunchKernelGGL((reg_single_kernel<false, K>), dim3(1), dim3(64), 0, s, items, item, recs,
-                         colors);
+      hipLaunchKernelGGL((reg_single_kernel<false, K, false>), dim3(1), dim3(64), 0, s, items, item,
+                         recs, colors);
   });
   return hipGetLastError();
 }
@@ -1049,7 +1096,8 @@ __device__ __forceinline__ int32_t engine_enumerate(RegState<K>& s, const uint32
         s.P &= ~(1ull << v);
       }
     }
-    if (back && !retreat(s, d, v, c, alt)) {
+    uint32_t tried_unused = 0;
+    if (back && !retreat(s, d, v, c, alt, tried_unused)) {
       emit(1);
       break;
     }
@@ -1219,9 +1267,9 @@ hipError_t launch_heavy_writeback(const HeavyWrite* w, int32_t count, DevRecord*
 int reg_batched_blocks_per_cu(bool trace) {
   int blocks = 0;
   hipError_t e = trace ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                             &blocks, reg_batched_kernel<true, 8>, 256, 0)
+                             &blocks, reg_batched_kernel<true, 8, false>, 256, 0)
                        : hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                             &blocks, reg_batched_kernel<false, 8>, 256, 0);
+                             &blocks, reg_batched_kernel<false, 8, false>, 256, 0);
   return e == hipSuccess && blocks > 0 ? blocks : 1;
 }
 

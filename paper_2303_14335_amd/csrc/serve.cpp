@@ -543,6 +543,8 @@ void check_opts(const mpld_options* o) {
     fail(MPLD_E_INVALID, "serving takes no PLAIN or FORCE_* flags");
   if (o->flags & MPLD_MARK_CONFLICTS)
     fail(MPLD_E_UNSUPPORTED, "serving does not mark conflicts (MPLD_MARK_CONFLICTS)");
+  if (o->flags & MPLD_STITCH_ORDER)
+    fail(MPLD_E_UNSUPPORTED, "serving keeps the ascending row order (MPLD_STITCH_ORDER)");
 }
 
 int32_t submit_request(mpld_server* s, Request* r, uint64_t* ticket) {
