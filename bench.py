@@ -240,6 +240,8 @@ def main() -> int:
                     help="skip the conflict-marking leg (MPLD_MARK_CONFLICTS on the same workload)")
     ap.add_argument("--serve-requests", type=int, default=1000,
                     help="serving leg: requests of the serving workload (0 = skip)")
+    ap.add_argument("--stitch-steps", type=int, default=5,
+                    help="steps of the stitch-order leg on the stitch workload (0: skip)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run one device copy of this size (counter scaling probe)")
     args = ap.parse_args()
@@ -366,6 +368,36 @@ def main() -> int:
                 "same_search": bool(np.array_equal(rm.components["nodes"], comps["nodes"]))}
         log(f"marking: {mark_ms:.4f} ms/step, {failed} components marked, {rm.conflicts} conflicts")
 
+    # ---- stitch-aware row order (Eq. 1's stitch term) on the stitch
+    # workload: the same batch searched in ascending row order and with
+    # MPLD_STITCH_ORDER; a separate leg, not the headline value
+    stitch = None
+    if args.stitch_steps:
+        ws = next(c for c in CONFIGS.values() if c.split_len_nm > 0)
+        rs, _ = workload.generate(ws.n_rects, ws.side_nm, ws.seed)
+        gs = mp.mpld_build_graph(rs, ws.dmin_nm, ws.split_len_nm)
+        legs = {}
+        for name, fl in (("ascending", 0), ("stitch_order", mp.MPLD_STITCH_ORDER)):
+            bs = mp.Batch(ctx, gs, ws.k, ws.budget, mp.MPLD_SIMPLIFY | fl)
+            bs.solve(direct=direct, timed=False)
+            torch.cuda.synchronize()
+            tq = time.perf_counter()
+            for _ in range(args.stitch_steps):
+                bs.solve(direct=direct, timed=False)
+            torch.cuda.synchronize()
+            rq = bs.result()
+            cs = rq.components["stitches"]
+            legs[name] = {"ms_per_step": 1000.0 * (time.perf_counter() - tq) / args.stitch_steps,
+                          "search_nodes": int(rq.components["nodes"].sum()),
+                          "stitches": int(rq.stitches),
+                          "stitches_in_searched_components": int(cs[cs >= 0].sum()),
+                          "uncolored": int(rq.uncolored)}
+            bs.close()
+        stitch = {"workload": ws.name, "steps": args.stitch_steps, **legs}
+        log(f"stitch order: {legs['ascending']['stitches_in_searched_components']} -> "
+            f"{legs['stitch_order']['stitches_in_searched_components']} stitches in searched "
+            f"components, {legs['stitch_order']['ms_per_step']:.3f} ms/step")
+
     if args.copy_probe_mib:
         src = torch.empty(args.copy_probe_mib << 20, dtype=torch.uint8, device="cuda")
         dst = torch.empty_like(src)
@@ -441,6 +473,7 @@ def main() -> int:
                   "same_result": same},
         "batched_over_plain": plain_ms / ms_per_step,
         "mark_conflicts": mark,
+        "stitch_order": stitch,
         "frontend_ms": {"graph": 1000 * (t1 - t0), "simplify_pack_upload": 1000 * (t2 - t1)},
         "e2e_ms": 1000 * (t3 - t0),
         "roofline": roofline,

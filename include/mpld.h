@@ -212,6 +212,24 @@ int32_t mpld_build_graph(const mpld_rect* rects, int32_t n, int32_t dmin_nm,
  * Errors as mpld_build_graph, plus MPLD_E_DEVICE / MPLD_E_NOMEM. */
 int32_t mpld_build_graph_device(mpld_context* ctx, const mpld_rect* rects, int32_t n,
                                 int32_t dmin_nm, int32_t split_len_nm, mpld_owned_graph** out);
+/* Simplification and sub-graph split (Sec. 2.2; Algorithm 1 splits the
+ * graph into sub-graphs) of a layout graph, computed on the context's
+ * device: FIFO removal of nodes of conflict degree < k (queue seeded in
+ * ascending id, a removed node's neighbours visited in ascending id),
+ * connected components of the rest ordered by smallest id, local numbering
+ * by BFS from that node with neighbours in ascending id.  flags:
+ * MPLD_SIMPLIFY or 0 (no removal).  Outputs are caller-allocated:
+ * removal_order (num_nodes; the first *num_removed are used), comp_of
+ * (num_nodes; -1 = removed), bfs_order (num_nodes; core nodes grouped by
+ * component, each in local order), comp_ptr (num_nodes + 1; component c is
+ * bfs_order[comp_ptr[c] .. comp_ptr[c + 1])).  One workgroup runs the whole
+ * split, so that its many short rounds are separated by barriers rather than
+ * launches.  Synchronous on the context's stream.  Errors: MPLD_E_INVALID
+ * for a bad graph (as mpld_decompose), k outside [2, MPLD_MAX_K] or a NULL
+ * output; MPLD_E_DEVICE / MPLD_E_NOMEM. */
+int32_t mpld_split_graph_device(mpld_context* ctx, const mpld_graph* g, int32_t k, uint32_t flags,
+                                int32_t* removal_order, int32_t* num_removed, int32_t* comp_of,
+                                int32_t* bfs_order, int32_t* comp_ptr, int32_t* num_comps);
 /* Borrowed view of an owned graph (valid until mpld_owned_graph_free). */
 int32_t mpld_owned_graph_view(const mpld_owned_graph* g, mpld_graph* view);
 void mpld_owned_graph_free(mpld_owned_graph* g);

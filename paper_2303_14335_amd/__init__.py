@@ -87,6 +87,25 @@ def mpld_build_graph_device(ctx: "Context", rects: np.ndarray, dmin_nm: int,
     return _owned_graph(h)
 
 
+def mpld_split_graph_device(ctx: "Context", g: Graph, k: int, simplify: bool = True):
+    """Simplification and sub-graph split on the context's device.  Returns
+    (removal_order, comp_of, [per-component global ids in local BFS order])."""
+    n = g.num_nodes
+    rem = np.zeros(max(n, 1), np.int32)
+    comp_of = np.zeros(max(n, 1), np.int32)
+    bfs = np.zeros(max(n, 1), np.int32)
+    ptr = np.zeros(n + 1, np.int32)
+    nrem, nc = ctypes.c_int32(), ctypes.c_int32()
+    v = g.view()
+    _check(_lib.mpld_split_graph_device(ctx.handle, ctypes.byref(v), k,
+                                        MPLD_SIMPLIFY if simplify else 0, rem.ctypes.data,
+                                        ctypes.byref(nrem), comp_of.ctypes.data, bfs.ctypes.data,
+                                        ptr.ctypes.data, ctypes.byref(nc)),
+           "mpld_split_graph_device")
+    comps = [bfs[ptr[c]:ptr[c + 1]].copy() for c in range(nc.value)]
+    return rem[: nrem.value].copy(), comp_of[:n].copy(), comps
+
+
 def _owned_graph(h) -> Graph:
     try:
         v = _ffi.mpld_graph()

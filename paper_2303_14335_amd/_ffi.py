@@ -107,6 +107,8 @@ SIGNATURES = {
     "mpld_last_error": (ctypes.c_char_p, []),
     "mpld_build_graph": (c_i32, [vp, c_i32, c_i32, c_i32, P(vp)]),
     "mpld_build_graph_device": (c_i32, [vp, vp, c_i32, c_i32, c_i32, P(vp)]),
+    "mpld_split_graph_device": (c_i32, [vp, P(mpld_graph), c_i32, c_u32, vp, P(c_i32), vp, vp,
+                                        vp, P(c_i32)]),
     "mpld_owned_graph_view": (c_i32, [vp, P(mpld_graph)]),
     "mpld_owned_graph_free": (None, [vp]),
     "mpld_context_create": (c_i32, [c_i32, P(mpld_allocator), vp, P(vp)]),

@@ -137,6 +137,27 @@ int32_t mpld_build_graph_device(mpld_context* ctx, const mpld_rect* rects, int32
   });
 }
 
+int32_t mpld_split_graph_device(mpld_context* ctx, const mpld_graph* g, int32_t k, uint32_t flags,
+                                int32_t* removal_order, int32_t* num_removed, int32_t* comp_of,
+                                int32_t* bfs_order, int32_t* comp_ptr, int32_t* num_comps) {
+  return guard([&] {
+    if (!g || !removal_order || !num_removed || !comp_of || !bfs_order || !comp_ptr || !num_comps)
+      fail(MPLD_E_INVALID, "NULL argument");
+    if (k < 2 || k > MPLD_MAX_K) fail(MPLD_E_INVALID, "k outside [2, MPLD_MAX_K]");
+    use_device(ctx);
+    if (!ctx->graph_builder) ctx->graph_builder = graph_builder_create(ctx, false);
+    const Graph gr = make_graph(*g);
+    Split s;
+    split_graph_device(*ctx->graph_builder, gr, k, flags & MPLD_SIMPLIFY, s);
+    std::copy(s.removal.begin(), s.removal.end(), removal_order);
+    *num_removed = (int32_t)s.removal.size();
+    std::copy(s.comp_of.begin(), s.comp_of.end(), comp_of);
+    std::copy(s.order.begin(), s.order.end(), bfs_order);
+    std::copy(s.comp_ptr.begin(), s.comp_ptr.end(), comp_ptr);
+    *num_comps = (int32_t)s.comp_ptr.size() - 1;
+  });
+}
+
 int32_t mpld_owned_graph_view(const mpld_owned_graph* g, mpld_graph* view) {
   return guard([&] {
     if (!g || !view) fail(MPLD_E_INVALID, "NULL argument");

@@ -18,6 +18,12 @@
 // ascending per node, symmetric, no self loops or duplicates by
 // construction.  Scans are three-phase (per-block sums, one block over the
 // sums, per-block scan plus offset).
+//
+// The simplification and sub-graph split that follow (Sec. 2.2; Algorithm 1
+// splits the graph into sub-graphs) can run here too, on the CSR while it is
+// still on the device: split_kernel reproduces the host's FIFO peeling order,
+// components ordered by smallest id and BFS local numbering exactly, level by
+// level (see the comment above it).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -200,6 +206,359 @@ __global__ __launch_bounds__(256) void neighbours_kernel(
   }
 }
 
+
+// ---- simplification and sub-graph split ------------------------------------
+//
+// One workgroup of 1024 threads does the whole split, so that its many short
+// rounds are separated by barriers instead of launches.  It reproduces the
+// sequential definitions exactly:
+//
+// FIFO peeling (nodes of conflict degree < k, queue seeded in ascending id;
+// a popped node lowers its neighbours' degrees in ascending id and queues
+// those that drop below k).  The queue falls into levels: level 0 is the
+// seed; level L+1 holds the nodes queued while level L is popped.  A node w
+// outside levels 0..L with deg0(w) = d is queued when its (d - k + 1)-th
+// neighbour is popped; if that neighbour (its trigger) is in level L, it is
+// the one of rank (d - k + 1 - before) among w's level-L neighbours by queue
+// position, `before` counting w's neighbours in earlier levels.  Level L+1 is
+// then ordered by (trigger's queue position, w's position in the trigger's
+// ascending list), i.e. one exclusive scan of per-trigger counts.
+//
+// Components: union-find with hooking of the larger root under the smaller
+// (so each root is its component's smallest id), numbered by root id.  BFS
+// local numbering from each root, neighbours in ascending id: a node of BFS
+// level d+1 is reached from its level-d neighbour of smallest local position,
+// and level d+1 is ordered per component by (parent's position, id) -- again
+// one scan of per-parent counts, with per-component bases.
+constexpr int kSplitThreads = 1024;
+
+struct SplitArgs {
+  int32_t n, k, simplify;
+  const int32_t* ptr;   // n + 1 CSR offsets
+  const int32_t* adj;   // ascending neighbour lists
+  // outputs
+  int32_t* counts;      // [0] removed, [1] components
+  int32_t* queue;       // n: removal order
+  int32_t* comp_of;     // n: component, -1 if removed
+  int32_t* order;       // n: core nodes by component, local order
+  int32_t* comp_ptr;    // n + 1
+  int32_t* local;       // n: local index, -1 if removed
+  // scratch, n each
+  int32_t *qpos, *lvl, *stamp, *trig, *cand, *parent, *fa, *fb, *gex, *cnt, *cbase, *tail, *rootof;
+};
+
+// Exclusive prefix of x over the workgroup (16 waves); `total` = the sum.
+__device__ __forceinline__ int32_t wg_excl_scan(int32_t x, int32_t* wsum, int32_t& total) {
+  const int32_t lane = (int32_t)(threadIdx.x & 63u), w = (int32_t)(threadIdx.x >> 6);
+  int32_t incl = x;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int32_t t = __shfl_up(incl, off, 64);
+    if (lane >= off) incl += t;
+  }
+  if (lane == 63) wsum[w] = incl;
+  __syncthreads();
+  int32_t before = 0, tot = 0;
+#pragma unroll
+  for (int i = 0; i < kSplitThreads / 64; ++i) {
+    const int32_t v = wsum[i];
+    before += i < w ? v : 0;
+    tot += v;
+  }
+  __syncthreads();   // wsum is reused by the next scan
+  total = tot;
+  return before + incl - x;
+}
+
+__device__ __forceinline__ int32_t ld_relaxed(const int32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Root of x with path halving (parent[x] < x for every non-root, so every
+// rewrite points x at one of its ancestors and the loop ends).
+__device__ int32_t uf_find(int32_t* parent, int32_t x) {
+  for (;;) {
+    const int32_t p = ld_relaxed(parent + x);
+    if (p == x) return x;
+    const int32_t g = ld_relaxed(parent + p);
+    if (g == p) return p;
+    __hip_atomic_store(parent + x, g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    x = g;
+  }
+}
+
+// Hooks the larger of the two roots under the smaller; a failed CAS means
+// that root was just hooked elsewhere: find again.
+__device__ void uf_unite(int32_t* parent, int32_t a, int32_t b) {
+  for (;;) {
+    const int32_t ra = uf_find(parent, a), rb = uf_find(parent, b);
+    if (ra == rb) return;
+    const int32_t hi = ra > rb ? ra : rb, lo = ra > rb ? rb : ra;
+    if (atomicCAS(parent + hi, hi, lo) == hi) return;
+  }
+}
+
+__global__ __launch_bounds__(kSplitThreads) void split_kernel(SplitArgs a) {
+  __shared__ int32_t wsum[kSplitThreads / 64];
+  __shared__ int32_t ncand;
+  const int32_t tid = (int32_t)threadIdx.x, T = kSplitThreads, n = a.n;
+  const int32_t* __restrict__ ptr = a.ptr;
+  const int32_t* __restrict__ adj = a.adj;
+  for (int32_t v = tid; v < n; v += T) {
+    a.qpos[v] = -1;
+    a.lvl[v] = -1;
+    a.stamp[v] = -1;
+    a.trig[v] = -1;
+    a.local[v] = -1;
+    a.comp_of[v] = -1;
+  }
+  __syncthreads();
+
+  // ---- FIFO peeling, level by level
+  int32_t qn = 0;
+  if (a.simplify) {
+    for (int32_t base = 0; base < n; base += T) {   // level 0: degree < k, ascending
+      const int32_t v = base + tid;
+      const int32_t f = v < n && ptr[v + 1] - ptr[v] < a.k ? 1 : 0;
+      int32_t total;
+      const int32_t ex = wg_excl_scan(f, wsum, total);
+      if (f) {
+        a.queue[qn + ex] = v;
+        a.qpos[v] = qn + ex;
+        a.lvl[v] = 0;
+      }
+      qn += total;
+    }
+  }
+  for (int32_t lo = 0, hi = qn, L = 0; lo < hi; ++L) {
+    // candidates: the unqueued neighbours of level L, each listed once
+    if (tid == 0) ncand = 0;
+    __syncthreads();
+    for (int32_t i = lo + tid; i < hi; i += T) {
+      const int32_t u = a.queue[i];
+      for (int32_t t = ptr[u]; t < ptr[u + 1]; ++t) {
+        const int32_t w = adj[t];
+        if (a.qpos[w] < 0 && atomicMax(a.stamp + w, L) < L) a.cand[atomicAdd(&ncand, 1)] = w;
+      }
+    }
+    __syncthreads();
+    const int32_t nc = ncand;
+    // trigger of each candidate in level L, or -1
+    for (int32_t j = tid; j < nc; j += T) {
+      const int32_t w = a.cand[j];
+      const int32_t t0 = ptr[w], t1 = ptr[w + 1];
+      const int32_t need = t1 - t0 - a.k + 1;
+      int32_t before = 0, at = 0;
+      for (int32_t t = t0; t < t1; ++t) {
+        const int32_t l = a.lvl[adj[t]];
+        before += l >= 0 && l < L ? 1 : 0;
+        at += l == L ? 1 : 0;
+      }
+      int32_t tr = -1;
+      if (before + at >= need) {
+        const int32_t rank = need - before - 1;   // among level-L neighbours by queue position
+        for (int32_t t = t0; t < t1 && tr < 0; ++t) {
+          const int32_t x = adj[t];
+          if (a.lvl[x] != L) continue;
+          const int32_t px = a.qpos[x];
+          int32_t r = 0;
+          for (int32_t q = t0; q < t1; ++q) {
+            const int32_t y = adj[q];
+            r += a.lvl[y] == L && a.qpos[y] < px ? 1 : 0;
+          }
+          if (r == rank) tr = x;
+        }
+      }
+      a.trig[w] = tr;
+    }
+    __syncthreads();
+    // level L+1: each level-L node in queue order appends the nodes it
+    // triggered, in its ascending list order
+    int32_t next = hi;
+    for (int32_t base = lo; base < hi; base += T) {
+      const int32_t i = base + tid;
+      const int32_t u = i < hi ? a.queue[i] : -1;
+      int32_t c = 0;
+      if (u >= 0)
+        for (int32_t t = ptr[u]; t < ptr[u + 1]; ++t) {
+          const int32_t w = adj[t];
+          c += a.qpos[w] < 0 && a.trig[w] == u ? 1 : 0;
+        }
+      int32_t total;
+      int32_t pos = next + wg_excl_scan(c, wsum, total);
+      if (c)
+        for (int32_t t = ptr[u]; t < ptr[u + 1]; ++t) {
+          const int32_t w = adj[t];
+          if (a.qpos[w] < 0 && a.trig[w] == u) {
+            a.queue[pos] = w;
+            a.qpos[w] = pos;
+            a.lvl[w] = L + 1;
+            ++pos;
+          }
+        }
+      next += total;
+    }
+    __syncthreads();
+    lo = hi;
+    hi = next;
+    qn = next;
+  }
+
+  // ---- components over the core (never queued): union-find
+  for (int32_t v = tid; v < n; v += T) a.parent[v] = a.lvl[v] < 0 ? v : -1;
+  __syncthreads();
+  for (int32_t v = tid; v < n; v += T) {
+    if (a.lvl[v] >= 0) continue;
+    for (int32_t t = ptr[v]; t < ptr[v + 1]; ++t) {
+      const int32_t w = adj[t];
+      if (w > v && a.lvl[w] < 0) uf_unite(a.parent, v, w);
+    }
+  }
+  __syncthreads();
+  // every core node's root, by read-only walks (a halving store here could
+  // overwrite a root just written with an older ancestor), then stored
+  for (int32_t v = tid; v < n; v += T)
+    if (a.lvl[v] < 0) {
+      int32_t r = v;
+      for (int32_t p = a.parent[r]; p != r; p = a.parent[r]) r = p;
+      a.fa[v] = r;
+    }
+  __syncthreads();
+  for (int32_t v = tid; v < n; v += T)
+    if (a.lvl[v] < 0) a.parent[v] = a.fa[v];
+  __syncthreads();
+  // numbered by root (= smallest id) ascending
+  int32_t ncomp = 0;
+  for (int32_t base = 0; base < n; base += T) {
+    const int32_t v = base + tid;
+    const int32_t f = v < n && a.lvl[v] < 0 && a.parent[v] == v ? 1 : 0;
+    int32_t total;
+    const int32_t ex = wg_excl_scan(f, wsum, total);
+    if (f) {
+      a.comp_of[v] = ncomp + ex;
+      a.rootof[ncomp + ex] = v;
+    }
+    ncomp += total;
+  }
+  for (int32_t c = tid; c < ncomp; c += T) a.tail[c] = 0;
+  __syncthreads();
+  for (int32_t v = tid; v < n; v += T) {
+    if (a.lvl[v] >= 0) continue;
+    const int32_t c = a.comp_of[a.parent[v]];
+    if (a.parent[v] != v) a.comp_of[v] = c;
+    atomicAdd(a.tail + c, 1);
+  }
+  __syncthreads();
+  int32_t core = 0;
+  for (int32_t base = 0; base < ncomp; base += T) {
+    const int32_t c = base + tid;
+    const int32_t sz = c < ncomp ? a.tail[c] : 0;
+    int32_t total;
+    const int32_t ex = wg_excl_scan(sz, wsum, total);
+    if (c < ncomp) a.comp_ptr[c] = core + ex;
+    core += total;
+  }
+  if (tid == 0) a.comp_ptr[ncomp] = core;
+  __syncthreads();
+
+  // ---- BFS local numbering, all components at once
+  for (int32_t v = tid; v < n; v += T) {
+    a.stamp[v] = -1;
+    a.trig[v] = -1;
+  }
+  for (int32_t c = tid; c < ncomp; c += T) {
+    const int32_t r = a.rootof[c];
+    a.fa[c] = r;
+    a.local[r] = 0;
+    a.order[a.comp_ptr[c]] = r;
+    a.tail[c] = 1;
+  }
+  __syncthreads();
+  int32_t* F = a.fa;
+  int32_t* NF = a.fb;
+  for (int32_t fn = ncomp, d = 0; fn > 0; ++d) {
+    if (tid == 0) ncand = 0;
+    __syncthreads();
+    for (int32_t i = tid; i < fn; i += T) {
+      const int32_t u = F[i];
+      for (int32_t t = ptr[u]; t < ptr[u + 1]; ++t) {
+        const int32_t w = adj[t];
+        if (a.lvl[w] < 0 && a.local[w] < 0 && atomicMax(a.stamp + w, d) < d)
+          a.cand[atomicAdd(&ncand, 1)] = w;
+      }
+    }
+    __syncthreads();
+    const int32_t nc = ncand;
+    // parent: the numbered neighbour of smallest local position (all of
+    // them are in level d)
+    for (int32_t j = tid; j < nc; j += T) {
+      const int32_t w = a.cand[j];
+      int32_t best = -1, bp = INT32_MAX;
+      for (int32_t t = ptr[w]; t < ptr[w + 1]; ++t) {
+        const int32_t x = adj[t];
+        const int32_t p = a.local[x];
+        if (a.lvl[x] < 0 && p >= 0 && p < bp) {
+          bp = p;
+          best = x;
+        }
+      }
+      a.trig[w] = best;
+    }
+    __syncthreads();
+    // children per frontier node; frontier is ordered by (component, position)
+    int32_t carry = 0;
+    for (int32_t base = 0; base < fn; base += T) {
+      const int32_t i = base + tid;
+      const int32_t u = i < fn ? F[i] : -1;
+      int32_t c = 0;
+      if (u >= 0)
+        for (int32_t t = ptr[u]; t < ptr[u + 1]; ++t) {
+          const int32_t w = adj[t];
+          c += a.lvl[w] < 0 && a.local[w] < 0 && a.trig[w] == u ? 1 : 0;
+        }
+      int32_t total;
+      const int32_t ex = carry + wg_excl_scan(c, wsum, total);
+      if (u >= 0) {
+        a.gex[i] = ex;
+        a.cnt[i] = c;
+        const int32_t cu = a.comp_of[u];
+        if (i == 0 || a.comp_of[F[i - 1]] != cu) a.cbase[cu] = ex;
+      }
+      carry += total;
+    }
+    __syncthreads();
+    for (int32_t i = tid; i < fn; i += T) {
+      const int32_t u = F[i], cu = a.comp_of[u];
+      int32_t p = a.tail[cu] + a.gex[i] - a.cbase[cu], g = a.gex[i];
+      if (a.cnt[i] == 0) continue;
+      for (int32_t t = ptr[u]; t < ptr[u + 1]; ++t) {
+        const int32_t w = adj[t];
+        if (a.lvl[w] < 0 && a.local[w] < 0 && a.trig[w] == u) {
+          a.local[w] = p;
+          a.order[a.comp_ptr[cu] + p] = w;
+          NF[g] = w;
+          ++p;
+          ++g;
+        }
+      }
+    }
+    __syncthreads();
+    for (int32_t i = tid; i < fn; i += T) {
+      const int32_t cu = a.comp_of[F[i]];
+      if (i == fn - 1 || a.comp_of[F[i + 1]] != cu) a.tail[cu] += a.gex[i] + a.cnt[i] - a.cbase[cu];
+    }
+    __syncthreads();
+    int32_t* tmp = F;
+    F = NF;
+    NF = tmp;
+    fn = carry;
+  }
+  if (tid == 0) {
+    a.counts[0] = qn;
+    a.counts[1] = ncomp;
+  }
+}
+
 // ---- host side --------------------------------------------------------------
 
 struct GraphBuilder {
@@ -208,6 +567,7 @@ struct GraphBuilder {
   bool own_stream = false;
   std::mutex mu;
   DevBuf box, partner, cell_of, cnt, start, fill, ids, sbox, smate, deg, ptr, adj, sums, offs;
+  DevBuf split_ws;   // split outputs then scratch (int32)
   PinnedBuf hin, hout;
   ~GraphBuilder() {
     if (own_stream && stream) (void)hipStreamDestroy(stream);
@@ -251,8 +611,98 @@ static void scan(GraphBuilder& gb, const int32_t* in, int64_t n, int32_t* out) {
   check_hip(hipGetLastError(), "graph builder: scan");
 }
 
+// split_ws layout (int32): counts (2), queue, comp_of, order (n each),
+// comp_ptr (n + 1), local (n) -- the part copied back, kSplitOut(n) words --
+// then 13 scratch arrays of n.
+static size_t split_out_words(int64_t n) { return 2 + 5 * (size_t)n + 1; }
+
+// Enqueues split_kernel on the CSR at dptr / dadj (device, int32).
+static void enqueue_split(GraphBuilder& gb, int32_t n, const int32_t* dptr, const int32_t* dadj,
+                          int32_t k, bool simplify) {
+  const size_t nn = (size_t)n;
+  grow(gb.split_ws, gb.ctx, sizeof(int32_t) * (split_out_words(n) + 13 * nn));
+  int32_t* w = gb.split_ws.as<int32_t>();
+  SplitArgs a{};
+  a.n = n;
+  a.k = k;
+  a.simplify = simplify ? 1 : 0;
+  a.ptr = dptr;
+  a.adj = dadj;
+  a.counts = w;
+  a.queue = w + 2;
+  a.comp_of = a.queue + nn;
+  a.order = a.comp_of + nn;
+  a.comp_ptr = a.order + nn;
+  a.local = a.comp_ptr + nn + 1;
+  int32_t* q = a.local + nn;
+  int32_t** scratch[] = {&a.qpos, &a.lvl, &a.stamp, &a.trig, &a.cand, &a.parent, &a.fa,
+                         &a.fb, &a.gex, &a.cnt, &a.cbase, &a.tail, &a.rootof};
+  for (int32_t** d : scratch) {
+    *d = q;
+    q += nn;
+  }
+  hipLaunchKernelGGL(split_kernel, dim3(1), dim3(kSplitThreads), 0, gb.stream, a);
+  check_hip(hipGetLastError(), "device split");
+}
+
+// Split from the copied-back words of split_ws.
+static void collect_split(const int32_t* h, int32_t n, Split& s) {
+  const size_t nn = (size_t)n;
+  const int32_t removed = h[0], ncomp = h[1];
+  const int32_t* queue = h + 2;
+  const int32_t* comp_of = queue + nn;
+  const int32_t* order = comp_of + nn;
+  const int32_t* comp_ptr = order + nn;
+  const int32_t* local = comp_ptr + nn + 1;
+  if (removed < 0 || removed > n || ncomp < 0 || ncomp > n)
+    fail(MPLD_E_INTERNAL, "device split returned bad counts");
+  s = Split();
+  s.removal.assign(queue, queue + removed);
+  s.comp_of.assign(comp_of, comp_of + nn);
+  s.comp_ptr.assign(comp_ptr, comp_ptr + ncomp + 1);
+  s.order.assign(order, order + s.comp_ptr.back());
+  s.local.assign(local, local + nn);
+}
+
+void split_graph_device(GraphBuilder& gb, const Graph& g, int32_t k, bool simplify, Split& s) {
+  const int32_t nn = g.n;
+  if (nn == 0) {
+    s = Split();
+    s.comp_ptr.push_back(0);
+    return;
+  }
+  const int64_t m2 = g.ptr[(size_t)nn];
+  if (m2 >= INT32_MAX) fail(MPLD_E_INVALID, "graph too large for the device split");
+  std::lock_guard<std::mutex> lk(gb.mu);
+  mpld_context* ctx = gb.ctx;
+  hipStream_t st = gb.stream;
+  check_hip(hipSetDevice(ctx->device), "hipSetDevice");
+  const size_t nb = (size_t)nn;
+  grow(gb.ptr, ctx, sizeof(int32_t) * (nb + 1));
+  grow(gb.adj, ctx, sizeof(int32_t) * (size_t)std::max<int64_t>(m2, 1));
+  const size_t in_bytes = sizeof(int32_t) * (nb + 1 + (size_t)m2);
+  if (!gb.hin.reserve(in_bytes)) fail(MPLD_E_NOMEM, "device split: pinned host memory");
+  int32_t* hp = gb.hin.as<int32_t>();
+  for (size_t i = 0; i <= nb; ++i) hp[i] = (int32_t)g.ptr[i];
+  std::memcpy(hp + nb + 1, g.adj.data(), sizeof(int32_t) * (size_t)m2);
+  check_hip(hipMemcpyAsync(gb.ptr.p, hp, sizeof(int32_t) * (nb + 1), hipMemcpyHostToDevice, st),
+            "device split: upload offsets");
+  if (m2)
+    check_hip(hipMemcpyAsync(gb.adj.p, hp + nb + 1, sizeof(int32_t) * (size_t)m2,
+                             hipMemcpyHostToDevice, st),
+              "device split: upload lists");
+  enqueue_split(gb, nn, gb.ptr.as<int32_t>(), gb.adj.as<int32_t>(), k, simplify);
+  const size_t out_bytes = sizeof(int32_t) * split_out_words(nn);
+  if (!gb.hout.reserve(out_bytes)) fail(MPLD_E_NOMEM, "device split: pinned host memory");
+  check_hip(hipMemcpyAsync(gb.hout.p, gb.split_ws.p, out_bytes, hipMemcpyDeviceToHost, st),
+            "device split: download");
+  check_hip(hipStreamSynchronize(st), "device split");
+  collect_split(gb.hout.as<int32_t>(), nn, s);
+}
+
 void build_layout_graph_device(GraphBuilder& gb, const mpld_rect* rects, int32_t n, int32_t dmin,
-                               int32_t split_len, Graph& g, std::vector<int32_t>* se) {
+                               int32_t split_len, Graph& g, std::vector<int32_t>* se, Split* split,
+                               int32_t k, bool simplify) {
   LayoutPrep lp;
   prepare_layout(rects, n, dmin, split_len, lp);
   const int32_t nn = (int32_t)lp.nd.size();
@@ -261,7 +711,13 @@ void build_layout_graph_device(GraphBuilder& gb, const mpld_rect* rects, int32_t
   g.partner = lp.partner;
   g.ptr.assign((size_t)nn + 1, 0);
   if (se) *se = lp.se;
-  if (nn == 0) return;
+  if (nn == 0) {
+    if (split) {
+      *split = Split();
+      split->comp_ptr.push_back(0);
+    }
+    return;
+  }
   const int64_t ncell = lp.gx * lp.gy;
   if (ncell >= INT32_MAX || 2 * (int64_t)nn >= INT32_MAX)
     fail(MPLD_E_INVALID, "layout too large for the device graph builder");
@@ -324,10 +780,17 @@ void build_layout_graph_device(GraphBuilder& gb, const mpld_rect* rects, int32_t
                      gb.ids.as<int32_t>(), gb.smate.as<int32_t>(), gb.start.as<int32_t>(), nn, gp,
                      d2, nullptr, gb.ptr.as<int32_t>(), gb.adj.as<int32_t>());
   check_hip(hipGetLastError(), "graph builder: neighbour lists");
-  const size_t out_bytes = sizeof(int32_t) * (nb + 1) + sizeof(int32_t) * (size_t)total;
+  if (split) enqueue_split(gb, nn, gb.ptr.as<int32_t>(), gb.adj.as<int32_t>(), k, simplify);
+  const size_t split_words = split ? split_out_words(nn) : 0;
+  const size_t out_bytes = sizeof(int32_t) * ((nb + 1) + (size_t)total + split_words);
   if (!gb.hout.reserve(out_bytes)) fail(MPLD_E_NOMEM, "graph builder: pinned host memory");
   int32_t* hptr = static_cast<int32_t*>(gb.hout.p);
   int32_t* hadj = hptr + nb + 1;
+  int32_t* hsplit = hadj + total;
+  if (split)
+    check_hip(hipMemcpyAsync(hsplit, gb.split_ws.p, sizeof(int32_t) * split_words,
+                             hipMemcpyDeviceToHost, s),
+              "graph builder: download split");
   check_hip(hipMemcpyAsync(hptr, gb.ptr.p, sizeof(int32_t) * (nb + 1), hipMemcpyDeviceToHost, s),
             "graph builder: download offsets");
   if (total)
@@ -338,6 +801,7 @@ void build_layout_graph_device(GraphBuilder& gb, const mpld_rect* rects, int32_t
   for (size_t i = 0; i <= nb; ++i) g.ptr[i] = hptr[i];
   g.adj.assign(hadj, hadj + total);
   g.num_ce = total / 2;
+  if (split) collect_split(hsplit, nn, *split);
 }
 
 }  // namespace mpld

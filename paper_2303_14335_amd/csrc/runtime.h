@@ -288,8 +288,14 @@ bool tune_from_cache(mpld_batch* b, const char* path, Tune* t);
 GraphBuilder* graph_builder_create(mpld_context* ctx, bool own_stream);
 void graph_builder_destroy(GraphBuilder* gb);
 // Builds the CSR layout graph of `rects` on the device (the host's
-// prepare_layout first); se receives the stitch pairs when not null.
+// prepare_layout first); se receives the stitch pairs when not null.  With
+// `split`, the simplification and sub-graph split (identical to
+// simplify_and_split(g, k, simplify)) run on the device too, before the
+// results come back.
 void build_layout_graph_device(GraphBuilder& gb, const mpld_rect* rects, int32_t n, int32_t dmin,
-                               int32_t split_len, Graph& g, std::vector<int32_t>* se);
+                               int32_t split_len, Graph& g, std::vector<int32_t>* se,
+                               Split* split = nullptr, int32_t k = 0, bool simplify = true);
+// simplify_and_split of a host graph, computed on the device.
+void split_graph_device(GraphBuilder& gb, const Graph& g, int32_t k, bool simplify, Split& s);
 
 }  // namespace mpld
