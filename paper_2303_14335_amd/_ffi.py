@@ -152,6 +152,13 @@ def load():
             raise ImportError(
                 f"{LIB_PATH} is missing: the HIP library must be built "
                 "(python -m paper_2303_14335_amd.build) - there is no CPU fallback")
+        # torch first: it ships its own HIP and HSA runtimes; with the
+        # library loaded before torch, context creation has reported no
+        # visible device
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         lib = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in SIGNATURES.items():
             fn = getattr(lib, name)

@@ -130,11 +130,9 @@ void mpld_server::front_end(Request* r) {
     if (r->layout) {
       const int32_t nr = (int32_t)r->rects.size();
       if (nr >= kDeviceGraphMinRects && gbuilder) {
-        // large layouts: pair search, simplification and sub-graph split on
-        // the device, CSR and split straight back (valid by construction, so
-        // no host validation pass)
-        build_layout_graph_device(*gbuilder, r->rects.data(), nr, r->dmin, r->split, r->g, nullptr,
-                                  &r->s, r->opt.k, r->opt.flags & MPLD_SIMPLIFY);
+        // large layouts: pair search on the device, CSR straight back (valid
+        // by construction, so no host validation pass)
+        build_layout_graph_device(*gbuilder, r->rects.data(), nr, r->dmin, r->split, r->g, nullptr);
         built = true;
       } else {
         OwnedGraph og;
@@ -150,7 +148,7 @@ void mpld_server::front_end(Request* r) {
                       (int64_t)r->se.size() / 2, r->se.data()};
       r->g = make_graph(view);
     }
-    if (!built) r->s = simplify_and_split(r->g, r->opt.k, r->opt.flags & MPLD_SIMPLIFY);
+    r->s = simplify_and_split(r->g, r->opt.k, r->opt.flags & MPLD_SIMPLIFY);
     const int32_t nc = (int32_t)r->s.comp_ptr.size() - 1;
     std::vector<int32_t> pairs;
     for (int32_t c = 0; c < nc; ++c) {
