@@ -46,6 +46,36 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
+# Instruction issue per CU and cycle: the scalar unit takes one SALU
+# instruction per cycle, and each of the four SIMDs one wave64 VALU
+# instruction per four cycles; 256 CUs at 2.4 GHz.
+CUS, CLOCK_HZ = 256, 2.4e9
+
+
+def issue_fractions(pmc_sq_txt: str, kernel_ms: float):
+    """SALU and VALU issue of reg_batched_kernel as fractions of the chip's
+    issue rates, from the SQ counters of the committed rocprofv3 summary (per
+    dispatch) over the live kernel duration; None without the summary."""
+    if not os.path.exists(pmc_sq_txt):
+        return None
+    per = {}
+    with open(pmc_sq_txt) as fh:
+        for line in fh:
+            if "reg_batched_kernel" not in line:
+                continue
+            for name in ("SQ_INSTS_SALU", "SQ_INSTS_VALU", "SQ_WAVES"):
+                if f" {name} " in line:
+                    per[name] = float(line.split()[-3])
+    if len(per) < 3:
+        return None
+    cycles = kernel_ms * 1e-3 * CLOCK_HZ
+    return {"salu_per_launch": per["SQ_INSTS_SALU"], "valu_per_launch": per["SQ_INSTS_VALU"],
+            "waves": per["SQ_WAVES"],
+            "salu_frac": per["SQ_INSTS_SALU"] / (cycles * CUS),
+            "valu_frac": per["SQ_INSTS_VALU"] / (cycles * CUS),
+            "source": os.path.relpath(pmc_sq_txt, ROOT)}
+
+
 def oracle_components(rects, w):
     """Components of the oracle's own front-end as local edge lists."""
     import numpy as np
@@ -413,12 +443,16 @@ def main() -> int:
                   + 4 * int(np.sum((comps["size"] + 2 + 2 * comps["num_edges"])[comps["size"] > 64])))
     achieved = algo_bytes / (kernel_ms * 1e-3) / 1e9
     traffic = None
+    issue = None
     prof = os.path.join(ROOT, "profiles", f"reg_batched_kernel_{w.name}_traffic.json")
     if os.path.exists(prof):
         with open(prof) as fh:
             t = json.load(fh)
         if t.get("kernel_source_hash") == kernel_source_hash():
             traffic = t.get("bytes_per_launch")
+            issue = issue_fractions(os.path.join(ROOT, "profiles",
+                                                 f"reg_batched_kernel_{w.name}_pmc_sq.txt"),
+                                    kernel_ms)
     roofline = {"bound": "hbm", "achieved": round(achieved, 3), "peak": HBM_PEAK_GBPS,
                 "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic,
                 "kernel": "reg_batched_kernel" if info["num_wave"] else "lds_batched_kernel",
@@ -426,6 +460,7 @@ def main() -> int:
                 "kernel_us_source": ("timed-region HIP events / steps" if one_kernel
                                      else "HIP events around single solves"),
                 "single_solve_us": round(single_ms * 1000.0, 3),
+                "issue": issue,
                 "algorithmic_bytes_per_launch": algo_bytes,
                 "ns_per_search_node_per_wave": None}
     # state-bytes model per search node (k+1 bitset planes scanned, cover /
