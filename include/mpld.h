@@ -367,7 +367,9 @@ typedef struct {
   int64_t arena_bytes;     /* device bytes for request images; 0 = 256 MiB, at most 2 GiB */
   int64_t slice_nodes;     /* search nodes per component per tick; 0 = 4096 */
   int32_t host_threads;    /* front-end threads; 0 = min(16, host cores)    */
-  int32_t reserved;
+  int32_t graph_builders;  /* device graph builders (own stream each) taken
+                              in turn by layout requests of >= 4096 rects;
+                              0 = 1, < 0 = none (the host builds every graph) */
 } mpld_server_options;
 typedef struct {
   int64_t submitted, completed, failed, ticks;

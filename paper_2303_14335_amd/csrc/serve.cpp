@@ -18,6 +18,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -108,8 +109,11 @@ struct mpld_server {
   mpld_server_stats stats{};
   std::vector<std::thread> workers;
   std::thread scheduler;
-  // device layout-graph builder for large layout requests (its own stream)
-  GraphBuilder* gbuilder = nullptr;
+  // device layout-graph builders for large layout requests (own stream
+  // each), taken in turn so that concurrent large requests do not queue on
+  // one builder's lock
+  std::vector<GraphBuilder*> gbuilders;
+  std::atomic<uint32_t> gb_next{0};
 
   void worker_loop();
   void scheduler_loop();
@@ -129,10 +133,11 @@ void mpld_server::front_end(Request* r) {
     bool built = false;
     if (r->layout) {
       const int32_t nr = (int32_t)r->rects.size();
-      if (nr >= kDeviceGraphMinRects && gbuilder) {
+      if (nr >= kDeviceGraphMinRects && !gbuilders.empty()) {
         // large layouts: pair search on the device, CSR straight back (valid
         // by construction, so no host validation pass)
-        build_layout_graph_device(*gbuilder, r->rects.data(), nr, r->dmin, r->split, r->g, nullptr);
+        GraphBuilder* gb = gbuilders[gb_next.fetch_add(1) % gbuilders.size()];
+        build_layout_graph_device(*gb, r->rects.data(), nr, r->dmin, r->split, r->g, nullptr);
         built = true;
       } else {
         OwnedGraph og;
@@ -597,11 +602,14 @@ int32_t mpld_server_create(mpld_context* ctx, const mpld_server_options* opt, mp
       s->lds_desc.alloc(ctx, sizeof(DevDesc) * (size_t)s->max_slots);
       s->lds_out.alloc(ctx, sizeof(DevRecord) * (size_t)s->max_slots);
       s->counter.alloc(ctx, sizeof(int32_t) * 4);
-      s->gbuilder = graph_builder_create(ctx, true);
+      // one builder by default: with four, p99 latency rose (their streams
+      // and the scheduler's compete for the device's hardware queues)
+      const int nb = o.graph_builders == 0 ? 1 : std::max(0, o.graph_builders);
+      for (int i = 0; i < nb; ++i) s->gbuilders.push_back(graph_builder_create(ctx, true));
       check_hip(hipMemsetAsync(s->counter.p, 0, sizeof(int32_t) * 4, ctx->stream), "serve: clear");
       check_hip(hipStreamSynchronize(ctx->stream), "serve: clear");
     } catch (...) {
-      if (s->gbuilder) graph_builder_destroy(s->gbuilder);
+      for (GraphBuilder* gb : s->gbuilders) graph_builder_destroy(gb);
       delete s;
       throw;
     }
@@ -706,7 +714,7 @@ int32_t mpld_server_destroy(mpld_server* s) {
   // every request is either pending (not finished) or done (not fetched)
   for (auto& kv : s->pending) delete kv.second;
   for (auto& kv : s->done) delete kv.second;
-  if (s->gbuilder) graph_builder_destroy(s->gbuilder);
+  for (GraphBuilder* gb : s->gbuilders) graph_builder_destroy(gb);
   delete s;
   return MPLD_OK;
 }
