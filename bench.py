@@ -147,7 +147,8 @@ def cpu_all_cores(rects, w, seconds: float):
                       f"{el:.2f} s"}
 
 
-def serve_leg(mp, ctx, count: int, seed: int, graph_builders: int = 0):
+def serve_leg(mp, ctx, count: int, seed: int, graph_builders: int = 0,
+              device_split: bool = True):
     """Serving workload: `count` layout requests with Poisson arrivals at the
     configured rate, feature counts log-uniform in [100, 50000], window side
     scaled to the small workload's density; each is decomposed through the
@@ -167,7 +168,7 @@ def serve_leg(mp, ctx, count: int, seed: int, graph_builders: int = 0):
 
     with ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
         rects = list(ex.map(gen, range(count)))
-    srv = mp.Server(ctx, graph_builders=graph_builders)
+    srv = mp.Server(ctx, graph_builders=graph_builders, device_split=device_split)
     lags = np.zeros(count)
     tickets = []
     start = time.perf_counter()

@@ -370,6 +370,11 @@ typedef struct {
   int32_t graph_builders;  /* device graph builders (own stream each) taken
                               in turn by layout requests of >= 4096 rects;
                               0 = 1, < 0 = none (the host builds every graph) */
+  int32_t device_split;    /* >= 0: device-built layouts are also simplified
+                              and split on the device (mpld_split_graph_device's
+                              kernels, behind the pair search; default);
+                              < 0: on the host */
+  int32_t reserved;
 } mpld_server_options;
 typedef struct {
   int64_t submitted, completed, failed, ticks;

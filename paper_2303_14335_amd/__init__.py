@@ -357,11 +357,13 @@ class Server:
     """Continuous-batching server on a context (see include/mpld.h)."""
 
     def __init__(self, ctx: Context, max_components: int = 0, arena_bytes: int = 0,
-                 slice_nodes: int = 0, host_threads: int = 0, graph_builders: int = 0):
+                 slice_nodes: int = 0, host_threads: int = 0, graph_builders: int = 0,
+                 device_split: bool = True):
         self.ctx = ctx
         self.handle = ctypes.c_void_p()
         o = _ffi.mpld_server_options(ctypes.sizeof(_ffi.mpld_server_options), max_components,
-                                     arena_bytes, slice_nodes, host_threads, graph_builders)
+                                     arena_bytes, slice_nodes, host_threads, graph_builders,
+                                     0 if device_split else -1, 0)
         _check(_lib.mpld_server_create(ctx.handle, ctypes.byref(o), ctypes.byref(self.handle)),
                "mpld_server_create")
 

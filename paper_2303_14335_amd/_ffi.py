@@ -88,7 +88,8 @@ class mpld_tune(ctypes.Structure):
 
 class mpld_server_options(ctypes.Structure):
     _fields_ = [("struct_size", c_u32), ("max_components", c_i32), ("arena_bytes", c_i64),
-                ("slice_nodes", c_i64), ("host_threads", c_i32), ("graph_builders", c_i32)]
+                ("slice_nodes", c_i64), ("host_threads", c_i32), ("graph_builders", c_i32),
+                ("device_split", c_i32), ("reserved", c_i32)]
 
 
 class mpld_server_stats(ctypes.Structure):

@@ -21,9 +21,9 @@
 //
 // The simplification and sub-graph split that follow (Sec. 2.2; Algorithm 1
 // splits the graph into sub-graphs) can run here too, on the CSR while it is
-// still on the device: split_kernel reproduces the host's FIFO peeling order,
-// components ordered by smallest id and BFS local numbering exactly, level by
-// level (see the comment above it).
+// still on the device: the split kernels reproduce the host's FIFO peeling
+// order, components ordered by smallest id and BFS local numbering exactly,
+// level by level (see the comment above them).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -209,43 +209,189 @@ __global__ __launch_bounds__(256) void neighbours_kernel(
 
 // ---- simplification and sub-graph split ------------------------------------
 //
-// One workgroup of 1024 threads does the whole split, so that its many short
-// rounds are separated by barriers instead of launches.  It reproduces the
-// sequential definitions exactly:
+// The sequential definitions (FIFO peeling of nodes of conflict degree < k,
+// queue seeded in ascending id, a popped node lowering its neighbours'
+// degrees in ascending id; components of the rest ordered by smallest id;
+// local numbering by BFS from that node, neighbours in ascending id) are
+// reproduced exactly, in level-synchronous form:
 //
-// FIFO peeling (nodes of conflict degree < k, queue seeded in ascending id;
-// a popped node lowers its neighbours' degrees in ascending id and queues
-// those that drop below k).  The queue falls into levels: level 0 is the
-// seed; level L+1 holds the nodes queued while level L is popped.  A node w
-// outside levels 0..L with deg0(w) = d is queued when its (d - k + 1)-th
-// neighbour is popped; if that neighbour (its trigger) is in level L, it is
-// the one of rank (d - k + 1 - before) among w's level-L neighbours by queue
-// position, `before` counting w's neighbours in earlier levels.  Level L+1 is
-// then ordered by (trigger's queue position, w's position in the trigger's
-// ascending list), i.e. one exclusive scan of per-trigger counts.
+// Peeling.  The queue falls into levels: level 0 is the seed; level L+1
+// holds the nodes queued while level L is popped (the rounds of synchronous
+// peeling).  A node w outside levels 0..L with deg0(w) = d is queued when
+// its (d - k + 1)-th neighbour is popped; if that neighbour (its trigger) is
+// in level L, it is the one of rank (d - k + 1 - before) among w's level-L
+// neighbours by queue position, `before` counting w's neighbours in earlier
+// levels.  Level L+1 is ordered by (trigger's queue position, w's place in
+// the trigger's ascending list): one exclusive scan of per-trigger counts.
+// Level 0 is ordered by id, so level 1's triggers need only the level-0
+// flags: the wide levels 0 and 1 run on the whole device; the rest, usually
+// small, on one workgroup whose rounds are separated by barriers.
 //
-// Components: union-find with hooking of the larger root under the smaller
-// (so each root is its component's smallest id), numbered by root id.  BFS
-// local numbering from each root, neighbours in ascending id: a node of BFS
-// level d+1 is reached from its level-d neighbour of smallest local position,
-// and level d+1 is ordered per component by (parent's position, id) -- again
-// one scan of per-parent counts, with per-component bases.
-constexpr int kSplitThreads = 1024;
+// Components: union-find over the whole device, the larger root hooked
+// under the smaller (so each root is its component's smallest id), numbered
+// by root id with a scan.  BFS: one wave per component of at most 64 nodes
+// (ranks by id, neighbour masks over the ranks, the queue kept in a lane
+// register); larger components on one workgroup, level by level, a node's
+// parent being its numbered neighbour of smallest local position.
+constexpr int kSplitThreads = 1024;   // the one-workgroup kernels
+constexpr int kSplitGrid = 2048;      // grid-stride kernels: blocks of 256
 
 struct SplitArgs {
   int32_t n, k, simplify;
   const int32_t* ptr;   // n + 1 CSR offsets
   const int32_t* adj;   // ascending neighbour lists
-  // outputs
+  // outputs (one contiguous region)
   int32_t* counts;      // [0] removed, [1] components
   int32_t* queue;       // n: removal order
   int32_t* comp_of;     // n: component, -1 if removed
   int32_t* order;       // n: core nodes by component, local order
   int32_t* comp_ptr;    // n + 1
   int32_t* local;       // n: local index, -1 if removed
-  // scratch, n each
-  int32_t *qpos, *lvl, *stamp, *trig, *cand, *parent, *fa, *fb, *gex, *cnt, *cbase, *tail, *rootof;
+  // scratch: n each, pos0 / off0 / cid n + 1
+  int32_t *f0, *pos0, *cnt0, *off0, *qpos, *lvl, *stamp, *trig, *cand, *parent, *root, *rflag,
+      *cid, *csize, *fill, *list, *rank, *fa, *fb, *gex, *cnt, *cbase, *tail, *cntA, *cntB, *offL;
+  int32_t* ctl;         // [2L], [2L+1]: queue range of level L (1 .. kWideLevels + 1)
 };
+
+// Peel levels 1 .. kWideLevels take their next level with device-wide
+// launches; the one-workgroup kernel goes on from level kWideLevels + 1.
+constexpr int kWideLevels = 4;
+
+#define SPLIT_FOR(v, n)                                                                 \
+  for (int32_t v = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x); v < (n);          \
+       v += (int32_t)(gridDim.x * blockDim.x))
+
+__global__ __launch_bounds__(256) void split_init_kernel(SplitArgs a) {
+  SPLIT_FOR(v, a.n) {
+    a.f0[v] = a.simplify && a.ptr[v + 1] - a.ptr[v] < a.k ? 1 : 0;
+    a.cnt0[v] = 0;
+    a.cntA[v] = 0;
+    a.cntB[v] = 0;
+    a.csize[v] = 0;
+    a.fill[v] = 0;
+    a.qpos[v] = -1;
+    a.lvl[v] = -1;
+    a.stamp[v] = -1;
+    a.trig[v] = -1;
+    a.local[v] = -1;
+    a.comp_of[v] = -1;
+  }
+}
+
+// Level 0 in id order, and each other node's level-1 trigger: the
+// (d - k + 1)-th level-0 neighbour in its ascending list (level-0 queue
+// order is id order), counted per trigger.
+__global__ __launch_bounds__(256) void split_level0_kernel(SplitArgs a) {
+  SPLIT_FOR(v, a.n) {
+    if (a.f0[v]) {
+      const int32_t p = a.pos0[v];
+      a.queue[p] = v;
+      a.qpos[v] = p;
+      a.lvl[v] = 0;
+    } else if (a.simplify) {
+      int32_t need = a.ptr[v + 1] - a.ptr[v] - a.k + 1;
+      for (int32_t t = a.ptr[v]; t < a.ptr[v + 1]; ++t) {
+        const int32_t x = a.adj[t];
+        if (a.f0[x] && --need == 0) {
+          a.trig[v] = x;
+          atomicAdd(a.cnt0 + a.pos0[x], 1);
+          break;
+        }
+      }
+    }
+  }
+}
+
+// Level 1: the children of level-0 node x go, in x's list order, at
+// |level 0| + off0[position of x].
+__global__ __launch_bounds__(256) void split_level1_kernel(SplitArgs a) {
+  const int32_t base = a.pos0[a.n];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    a.ctl[2] = base;
+    a.ctl[3] = base + a.off0[a.n];
+  }
+  SPLIT_FOR(w, a.n) {
+    const int32_t x = a.trig[w];
+    if (x < 0) continue;
+    int32_t r = 0;
+    for (int32_t t = a.ptr[x]; t < a.ptr[x + 1]; ++t) {
+      const int32_t y = a.adj[t];
+      if (y >= w) break;
+      r += !a.f0[y] && a.trig[y] == x ? 1 : 0;
+    }
+    const int32_t p = base + a.off0[a.qpos[x]] + r;
+    if (p >= a.n) continue;   // cannot happen: positions are a permutation
+    a.queue[p] = w;
+    a.qpos[w] = p;
+    a.lvl[w] = 1;
+  }
+}
+
+// Wide level L (>= 1): the trigger of every unqueued node next to level L,
+// counted per trigger at its position within the level.
+__global__ __launch_bounds__(256) void split_trig_kernel(SplitArgs a, int32_t L, int32_t* cnt) {
+  const int32_t lo = a.ctl[2 * L], hi = a.ctl[2 * L + 1];
+  if (lo >= hi) return;
+  SPLIT_FOR(w, a.n) {
+    if (a.qpos[w] >= 0) continue;
+    const int32_t t0 = a.ptr[w], t1 = a.ptr[w + 1];
+    int32_t before = 0, at = 0;
+    for (int32_t t = t0; t < t1; ++t) {
+      const int32_t l = a.lvl[a.adj[t]];
+      before += l >= 0 && l < L ? 1 : 0;
+      at += l == L ? 1 : 0;
+    }
+    if (at == 0) continue;   // not next to level L: its trigger stays -1
+    const int32_t need = t1 - t0 - a.k + 1;
+    int32_t tr = -1;
+    if (before + at >= need) {
+      const int32_t rank = need - before - 1;   // among level-L neighbours by queue position
+      for (int32_t t = t0; t < t1 && tr < 0; ++t) {
+        const int32_t x = a.adj[t];
+        if (a.lvl[x] != L) continue;
+        const int32_t px = a.qpos[x];
+        int32_t r = 0;
+        for (int32_t q = t0; q < t1; ++q) {
+          const int32_t y = a.adj[q];
+          r += a.lvl[y] == L && a.qpos[y] < px ? 1 : 0;
+        }
+        if (r == rank) tr = x;
+      }
+    }
+    a.trig[w] = tr;
+    if (tr >= 0) atomicAdd(cnt + (a.qpos[tr] - lo), 1);
+  }
+}
+
+// Wide level L: level L+1 in (trigger position, trigger's list order); the
+// range of level L+1 goes to ctl, the other count array is cleared for it.
+__global__ __launch_bounds__(256) void split_place_kernel(SplitArgs a, int32_t L,
+                                                          const int32_t* off, int32_t* cnt_next) {
+  const int32_t lo = a.ctl[2 * L], hi = a.ctl[2 * L + 1];
+  SPLIT_FOR(v, a.n) cnt_next[v] = 0;
+  const int32_t total = lo < hi ? off[a.n] : 0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    a.ctl[2 * L + 2] = hi;
+    a.ctl[2 * L + 3] = hi + total;
+  }
+  if (lo >= hi) return;
+  SPLIT_FOR(w, a.n) {
+    const int32_t x = a.trig[w];
+    if (x < 0 || a.qpos[w] >= 0 || a.lvl[x] != L) continue;
+    // x's children this level are exactly the y with trig[y] == x
+    int32_t r = 0;
+    for (int32_t t = a.ptr[x]; t < a.ptr[x + 1]; ++t) {
+      const int32_t y = a.adj[t];
+      if (y >= w) break;
+      r += a.trig[y] == x ? 1 : 0;
+    }
+    const int32_t p = hi + off[a.qpos[x] - lo] + r;
+    if (p >= a.n) continue;   // cannot happen: positions are a permutation
+    a.queue[p] = w;
+    a.qpos[w] = p;
+    a.lvl[w] = L + 1;
+  }
+}
 
 // Exclusive prefix of x over the workgroup (16 waves); `total` = the sum.
 __device__ __forceinline__ int32_t wg_excl_scan(int32_t x, int32_t* wsum, int32_t& total) {
@@ -270,67 +416,15 @@ __device__ __forceinline__ int32_t wg_excl_scan(int32_t x, int32_t* wsum, int32_
   return before + incl - x;
 }
 
-__device__ __forceinline__ int32_t ld_relaxed(const int32_t* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-}
-
-// Root of x with path halving (parent[x] < x for every non-root, so every
-// rewrite points x at one of its ancestors and the loop ends).
-__device__ int32_t uf_find(int32_t* parent, int32_t x) {
-  for (;;) {
-    const int32_t p = ld_relaxed(parent + x);
-    if (p == x) return x;
-    const int32_t g = ld_relaxed(parent + p);
-    if (g == p) return p;
-    __hip_atomic_store(parent + x, g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-    x = g;
-  }
-}
-
-// Hooks the larger of the two roots under the smaller; a failed CAS means
-// that root was just hooked elsewhere: find again.
-__device__ void uf_unite(int32_t* parent, int32_t a, int32_t b) {
-  for (;;) {
-    const int32_t ra = uf_find(parent, a), rb = uf_find(parent, b);
-    if (ra == rb) return;
-    const int32_t hi = ra > rb ? ra : rb, lo = ra > rb ? rb : ra;
-    if (atomicCAS(parent + hi, hi, lo) == hi) return;
-  }
-}
-
-__global__ __launch_bounds__(kSplitThreads) void split_kernel(SplitArgs a) {
+// The remaining levels on one workgroup, from level kWideLevels + 1.
+__global__ __launch_bounds__(kSplitThreads) void split_peel_kernel(SplitArgs a) {
   __shared__ int32_t wsum[kSplitThreads / 64];
   __shared__ int32_t ncand;
   const int32_t tid = (int32_t)threadIdx.x, T = kSplitThreads, n = a.n;
   const int32_t* __restrict__ ptr = a.ptr;
   const int32_t* __restrict__ adj = a.adj;
-  for (int32_t v = tid; v < n; v += T) {
-    a.qpos[v] = -1;
-    a.lvl[v] = -1;
-    a.stamp[v] = -1;
-    a.trig[v] = -1;
-    a.local[v] = -1;
-    a.comp_of[v] = -1;
-  }
-  __syncthreads();
-
-  // ---- FIFO peeling, level by level
-  int32_t qn = 0;
-  if (a.simplify) {
-    for (int32_t base = 0; base < n; base += T) {   // level 0: degree < k, ascending
-      const int32_t v = base + tid;
-      const int32_t f = v < n && ptr[v + 1] - ptr[v] < a.k ? 1 : 0;
-      int32_t total;
-      const int32_t ex = wg_excl_scan(f, wsum, total);
-      if (f) {
-        a.queue[qn + ex] = v;
-        a.qpos[v] = qn + ex;
-        a.lvl[v] = 0;
-      }
-      qn += total;
-    }
-  }
-  for (int32_t lo = 0, hi = qn, L = 0; lo < hi; ++L) {
+  int32_t lo = a.ctl[2 * (kWideLevels + 1)], hi = a.ctl[2 * (kWideLevels + 1) + 1];
+  for (int32_t L = kWideLevels + 1; lo < hi; ++L) {
     // candidates: the unqueued neighbours of level L, each listed once
     if (tid == 0) ncand = 0;
     __syncthreads();
@@ -389,7 +483,7 @@ __global__ __launch_bounds__(kSplitThreads) void split_kernel(SplitArgs a) {
       if (c)
         for (int32_t t = ptr[u]; t < ptr[u + 1]; ++t) {
           const int32_t w = adj[t];
-          if (a.qpos[w] < 0 && a.trig[w] == u) {
+          if (a.qpos[w] < 0 && a.trig[w] == u && pos < n) {
             a.queue[pos] = w;
             a.qpos[w] = pos;
             a.lvl[w] = L + 1;
@@ -401,82 +495,186 @@ __global__ __launch_bounds__(kSplitThreads) void split_kernel(SplitArgs a) {
     __syncthreads();
     lo = hi;
     hi = next;
-    qn = next;
   }
+  if (tid == 0) a.counts[0] = hi;
+}
 
-  // ---- components over the core (never queued): union-find
-  for (int32_t v = tid; v < n; v += T) a.parent[v] = a.lvl[v] < 0 ? v : -1;
-  __syncthreads();
-  for (int32_t v = tid; v < n; v += T) {
-    if (a.lvl[v] >= 0) continue;
-    for (int32_t t = ptr[v]; t < ptr[v + 1]; ++t) {
-      const int32_t w = adj[t];
-      if (w > v && a.lvl[w] < 0) uf_unite(a.parent, v, w);
-    }
-  }
-  __syncthreads();
-  // every core node's root, by read-only walks (a halving store here could
-  // overwrite a root just written with an older ancestor), then stored
-  for (int32_t v = tid; v < n; v += T)
-    if (a.lvl[v] < 0) {
-      int32_t r = v;
-      for (int32_t p = a.parent[r]; p != r; p = a.parent[r]) r = p;
-      a.fa[v] = r;
-    }
-  __syncthreads();
-  for (int32_t v = tid; v < n; v += T)
-    if (a.lvl[v] < 0) a.parent[v] = a.fa[v];
-  __syncthreads();
-  // numbered by root (= smallest id) ascending
-  int32_t ncomp = 0;
-  for (int32_t base = 0; base < n; base += T) {
-    const int32_t v = base + tid;
-    const int32_t f = v < n && a.lvl[v] < 0 && a.parent[v] == v ? 1 : 0;
-    int32_t total;
-    const int32_t ex = wg_excl_scan(f, wsum, total);
-    if (f) {
-      a.comp_of[v] = ncomp + ex;
-      a.rootof[ncomp + ex] = v;
-    }
-    ncomp += total;
-  }
-  for (int32_t c = tid; c < ncomp; c += T) a.tail[c] = 0;
-  __syncthreads();
-  for (int32_t v = tid; v < n; v += T) {
-    if (a.lvl[v] >= 0) continue;
-    const int32_t c = a.comp_of[a.parent[v]];
-    if (a.parent[v] != v) a.comp_of[v] = c;
-    atomicAdd(a.tail + c, 1);
-  }
-  __syncthreads();
-  int32_t core = 0;
-  for (int32_t base = 0; base < ncomp; base += T) {
-    const int32_t c = base + tid;
-    const int32_t sz = c < ncomp ? a.tail[c] : 0;
-    int32_t total;
-    const int32_t ex = wg_excl_scan(sz, wsum, total);
-    if (c < ncomp) a.comp_ptr[c] = core + ex;
-    core += total;
-  }
-  if (tid == 0) a.comp_ptr[ncomp] = core;
-  __syncthreads();
+__device__ __forceinline__ int32_t ld_agent(const int32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 
-  // ---- BFS local numbering, all components at once
-  for (int32_t v = tid; v < n; v += T) {
+// Root of x with path halving (parent[x] < x for every non-root, so every
+// rewrite points x at one of its ancestors and the loop ends).
+__device__ int32_t uf_find(int32_t* parent, int32_t x) {
+  for (;;) {
+    const int32_t p = ld_agent(parent + x);
+    if (p == x) return x;
+    const int32_t g = ld_agent(parent + p);
+    if (g == p) return p;
+    __hip_atomic_store(parent + x, g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    x = g;
+  }
+}
+
+// Union-find start; the candidate stamps and triggers of the peeling are
+// reset for the BFS of the big components.
+__global__ __launch_bounds__(256) void uf_init_kernel(SplitArgs a) {
+  SPLIT_FOR(v, a.n) {
+    a.parent[v] = a.lvl[v] < 0 ? v : -1;
     a.stamp[v] = -1;
     a.trig[v] = -1;
   }
-  for (int32_t c = tid; c < ncomp; c += T) {
-    const int32_t r = a.rootof[c];
-    a.fa[c] = r;
-    a.local[r] = 0;
-    a.order[a.comp_ptr[c]] = r;
-    a.tail[c] = 1;
+}
+
+// Hooks the larger of two roots under the smaller; a failed CAS means that
+// root was just hooked elsewhere: find again.
+__global__ __launch_bounds__(256) void uf_unite_kernel(SplitArgs a) {
+  SPLIT_FOR(v, a.n) {
+    if (a.lvl[v] >= 0) continue;
+    for (int32_t t = a.ptr[v]; t < a.ptr[v + 1]; ++t) {
+      const int32_t w = a.adj[t];
+      if (w < v || a.lvl[w] >= 0) continue;
+      for (;;) {
+        const int32_t ra = uf_find(a.parent, v), rb = uf_find(a.parent, w);
+        if (ra == rb) break;
+        const int32_t hi = ra > rb ? ra : rb, lo = ra > rb ? rb : ra;
+        if (atomicCAS(a.parent + hi, hi, lo) == hi) break;
+      }
+    }
   }
-  __syncthreads();
+}
+
+// Every core node's root (read-only walks: the forest is final here) and
+// the root flags to be numbered.
+__global__ __launch_bounds__(256) void uf_root_kernel(SplitArgs a) {
+  SPLIT_FOR(v, a.n) {
+    int32_t r = -1;
+    if (a.lvl[v] < 0) {
+      r = v;
+      for (int32_t p = a.parent[r]; p != r; p = a.parent[r]) r = p;
+    }
+    a.root[v] = r;
+    a.rflag[v] = r == v ? 1 : 0;
+  }
+}
+
+// Component of every core node (roots numbered in id order), its size, and
+// the root of every component.
+__global__ __launch_bounds__(256) void comp_kernel(SplitArgs a) {
+  SPLIT_FOR(v, a.n) {
+    const int32_t r = a.root[v];
+    if (r < 0) continue;
+    const int32_t c = a.cid[r];
+    a.comp_of[v] = c;
+    if (r == v) a.parent[c] = v;   // parent[] is free now: root of component c
+    atomicAdd(a.csize + c, 1);
+  }
+}
+
+// Core nodes listed per component (any order within it).
+__global__ __launch_bounds__(256) void comp_list_kernel(SplitArgs a) {
+  SPLIT_FOR(v, a.n) {
+    const int32_t c = a.comp_of[v];
+    if (c < 0) continue;
+    a.list[a.comp_ptr[c] + atomicAdd(a.fill + c, 1)] = v;
+  }
+}
+
+__device__ __forceinline__ uint64_t rdlane64(uint64_t x, uint32_t l) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, (int)l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), (int)l);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// BFS numbering of the components of at most 64 nodes, one wave each.
+// Lane i holds node x_i of the component; its rank by id is its index in
+// the neighbour masks (rank 0 is the smallest id: the root).
+__global__ __launch_bounds__(256) void bfs_small_kernel(SplitArgs a) {
+  const int32_t lane = (int32_t)(threadIdx.x & 63u);
+  const int32_t ncomp = a.cid[a.n];
+  const int32_t waves = (int32_t)(gridDim.x * (blockDim.x >> 6));
+  for (int32_t c = (int32_t)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)); c < ncomp;
+       c += waves) {
+    const int32_t base = a.comp_ptr[c], sz = a.comp_ptr[c + 1] - base;
+    if (sz > 64) continue;
+    const bool in = lane < sz;
+    const int32_t x = in ? a.list[base + lane] : INT32_MAX;
+    int32_t r = 0;
+    for (int32_t j = 0; j < sz; ++j) r += __builtin_amdgcn_readlane(x, j) < x ? 1 : 0;
+    if (in) a.rank[x] = r;
+    __threadfence_block();
+    uint64_t m = 0;
+    if (in)
+      for (int32_t t = a.ptr[x]; t < a.ptr[x + 1]; ++t) {
+        const int32_t w = a.adj[t];
+        if (a.comp_of[w] == c) m |= 1ull << a.rank[w];
+      }
+    // lane i's mask is indexed by its rank: mk[rank] via a lane shuffle
+    const int32_t src = [&] {
+      // the lane whose rank equals this lane's index
+      int32_t s = 0;
+      for (int32_t j = 0; j < sz; ++j)
+        if (__builtin_amdgcn_readlane(r, j) == lane) s = j;
+      return s;
+    }();
+    const uint32_t mlo = (uint32_t)__shfl((int)(uint32_t)m, src, 64);
+    const uint32_t mhi = (uint32_t)__shfl((int)(uint32_t)(m >> 32), src, 64);
+    const uint64_t mk = ((uint64_t)mhi << 32) | mlo;   // mask of rank `lane`
+    // sequential BFS over ranks; q: lane t holds the rank at queue position t
+    int32_t q = 0;
+    uint64_t seen = 1ull;
+    int32_t tail = 1;
+    for (int32_t head = 0; head < tail; ++head) {
+      const int32_t u = __builtin_amdgcn_readlane(q, head);
+      uint64_t nb = rdlane64(mk, (uint32_t)u) & ~seen;
+      seen |= nb;
+      while (nb) {
+        const int32_t b = (int32_t)__builtin_ctzll(nb);
+        nb &= nb - 1;
+        q = lane == tail ? b : q;
+        ++tail;
+      }
+    }
+    // the lane of rank q[t] is numbered t
+    int32_t pos = -1;
+    for (int32_t t = 0; t < sz; ++t)
+      if (__builtin_amdgcn_readlane(q, t) == r) pos = t;
+    if (in && pos >= 0) {
+      a.local[x] = pos;
+      a.order[base + pos] = x;
+    }
+  }
+}
+
+// BFS numbering of the components of more than 64 nodes, on one workgroup,
+// all of them at once; the frontier stays ordered by (component, position).
+__global__ __launch_bounds__(kSplitThreads) void bfs_big_kernel(SplitArgs a) {
+  __shared__ int32_t wsum[kSplitThreads / 64];
+  __shared__ int32_t ncand;
+  const int32_t tid = (int32_t)threadIdx.x, T = kSplitThreads;
+  const int32_t* __restrict__ ptr = a.ptr;
+  const int32_t* __restrict__ adj = a.adj;
+  const int32_t ncomp = a.cid[a.n];
   int32_t* F = a.fa;
   int32_t* NF = a.fb;
-  for (int32_t fn = ncomp, d = 0; fn > 0; ++d) {
+  // the roots of the big components, in component order
+  int32_t fn = 0;
+  for (int32_t base = 0; base < ncomp; base += T) {
+    const int32_t c = base + tid;
+    const int32_t big = c < ncomp && a.comp_ptr[c + 1] - a.comp_ptr[c] > 64 ? 1 : 0;
+    int32_t total;
+    const int32_t ex = wg_excl_scan(big, wsum, total);
+    if (big) {
+      const int32_t r = a.parent[c];
+      F[fn + ex] = r;
+      a.local[r] = 0;
+      a.order[a.comp_ptr[c]] = r;
+      a.tail[c] = 1;
+    }
+    fn += total;
+  }
+  __syncthreads();
+  for (int32_t d = 0; fn > 0; ++d) {
     if (tid == 0) ncand = 0;
     __syncthreads();
     for (int32_t i = tid; i < fn; i += T) {
@@ -505,7 +703,6 @@ __global__ __launch_bounds__(kSplitThreads) void split_kernel(SplitArgs a) {
       a.trig[w] = best;
     }
     __syncthreads();
-    // children per frontier node; frontier is ordered by (component, position)
     int32_t carry = 0;
     for (int32_t base = 0; base < fn; base += T) {
       const int32_t i = base + tid;
@@ -528,12 +725,13 @@ __global__ __launch_bounds__(kSplitThreads) void split_kernel(SplitArgs a) {
     }
     __syncthreads();
     for (int32_t i = tid; i < fn; i += T) {
+      if (a.cnt[i] == 0) continue;
       const int32_t u = F[i], cu = a.comp_of[u];
       int32_t p = a.tail[cu] + a.gex[i] - a.cbase[cu], g = a.gex[i];
-      if (a.cnt[i] == 0) continue;
       for (int32_t t = ptr[u]; t < ptr[u + 1]; ++t) {
         const int32_t w = adj[t];
-        if (a.lvl[w] < 0 && a.local[w] < 0 && a.trig[w] == u) {
+        if (a.lvl[w] < 0 && a.local[w] < 0 && a.trig[w] == u && g < a.n &&
+            a.comp_ptr[cu] + p < a.comp_ptr[cu + 1]) {
           a.local[w] = p;
           a.order[a.comp_ptr[cu] + p] = w;
           NF[g] = w;
@@ -553,10 +751,7 @@ __global__ __launch_bounds__(kSplitThreads) void split_kernel(SplitArgs a) {
     NF = tmp;
     fn = carry;
   }
-  if (tid == 0) {
-    a.counts[0] = qn;
-    a.counts[1] = ncomp;
-  }
+  if (tid == 0) a.counts[1] = ncomp;
 }
 
 // ---- host side --------------------------------------------------------------
@@ -612,15 +807,18 @@ static void scan(GraphBuilder& gb, const int32_t* in, int64_t n, int32_t* out) {
 }
 
 // split_ws layout (int32): counts (2), queue, comp_of, order (n each),
-// comp_ptr (n + 1), local (n) -- the part copied back, kSplitOut(n) words --
-// then 13 scratch arrays of n.
+// comp_ptr (n + 1), local (n) -- the part copied back, split_out_words(n)
+// words -- then the scratch arrays, n + 1 words each.
 static size_t split_out_words(int64_t n) { return 2 + 5 * (size_t)n + 1; }
+static constexpr int kSplitScratch = 27;
 
-// Enqueues split_kernel on the CSR at dptr / dadj (device, int32).
+// Enqueues the split of the CSR at dptr / dadj (device, int32); no host
+// synchronisation.
 static void enqueue_split(GraphBuilder& gb, int32_t n, const int32_t* dptr, const int32_t* dadj,
                           int32_t k, bool simplify) {
   const size_t nn = (size_t)n;
-  grow(gb.split_ws, gb.ctx, sizeof(int32_t) * (split_out_words(n) + 13 * nn));
+  const size_t stride = std::max<size_t>(nn + 1, 64);   // ctl needs 2 * (kWideLevels + 2)
+  grow(gb.split_ws, gb.ctx, sizeof(int32_t) * (split_out_words(n) + kSplitScratch * stride));
   int32_t* w = gb.split_ws.as<int32_t>();
   SplitArgs a{};
   a.n = n;
@@ -635,13 +833,42 @@ static void enqueue_split(GraphBuilder& gb, int32_t n, const int32_t* dptr, cons
   a.comp_ptr = a.order + nn;
   a.local = a.comp_ptr + nn + 1;
   int32_t* q = a.local + nn;
-  int32_t** scratch[] = {&a.qpos, &a.lvl, &a.stamp, &a.trig, &a.cand, &a.parent, &a.fa,
-                         &a.fb, &a.gex, &a.cnt, &a.cbase, &a.tail, &a.rootof};
+  int32_t** scratch[kSplitScratch] = {&a.f0,   &a.pos0,  &a.cnt0, &a.off0,  &a.qpos,  &a.lvl,
+                                      &a.stamp, &a.trig,  &a.cand, &a.parent, &a.root, &a.rflag,
+                                      &a.cid,  &a.csize, &a.fill, &a.list,  &a.rank,  &a.fa,
+                                      &a.fb,   &a.gex,   &a.cnt,  &a.cbase, &a.tail,
+                                      &a.cntA, &a.cntB,  &a.offL, &a.ctl};
   for (int32_t** d : scratch) {
     *d = q;
-    q += nn;
+    q += stride;
   }
-  hipLaunchKernelGGL(split_kernel, dim3(1), dim3(kSplitThreads), 0, gb.stream, a);
+  hipStream_t st = gb.stream;
+  const unsigned grid = (unsigned)std::min<int64_t>((n + 255) / 256, kSplitGrid);
+  auto wide = [&](void (*kern)(SplitArgs)) {
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(256), 0, st, a);
+  };
+  wide(split_init_kernel);
+  scan(gb, a.f0, n, a.pos0);            // level-0 positions; pos0[n] = |level 0|
+  wide(split_level0_kernel);
+  scan(gb, a.cnt0, n, a.off0);          // level-1 offsets per level-0 position
+  wide(split_level1_kernel);
+  for (int32_t L = 1; L <= kWideLevels; ++L) {
+    int32_t* cur = (L & 1) ? a.cntA : a.cntB;
+    int32_t* nxt = (L & 1) ? a.cntB : a.cntA;
+    hipLaunchKernelGGL(split_trig_kernel, dim3(grid), dim3(256), 0, st, a, L, cur);
+    scan(gb, cur, n, a.offL);
+    hipLaunchKernelGGL(split_place_kernel, dim3(grid), dim3(256), 0, st, a, L, a.offL, nxt);
+  }
+  hipLaunchKernelGGL(split_peel_kernel, dim3(1), dim3(kSplitThreads), 0, st, a);
+  wide(uf_init_kernel);
+  wide(uf_unite_kernel);
+  wide(uf_root_kernel);
+  scan(gb, a.rflag, n, a.cid);          // component ids; cid[n] = components
+  wide(comp_kernel);
+  scan(gb, a.csize, n, a.comp_ptr);
+  wide(comp_list_kernel);
+  wide(bfs_small_kernel);
+  hipLaunchKernelGGL(bfs_big_kernel, dim3(1), dim3(kSplitThreads), 0, st, a);
   check_hip(hipGetLastError(), "device split");
 }
 

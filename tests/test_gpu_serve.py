@@ -62,6 +62,24 @@ def test_mix_equals_alone(ctx, slice_nodes):
         assert got.total_us >= got.queue_us >= 0
 
 
+@pytest.mark.parametrize("simplify", [True, False])
+def test_device_split_equals_alone(ctx, simplify):
+    # layouts of >= 4096 rects are built, simplified and split on the device
+    import paper_2303_14335_amd as mp
+    reqs = requests(24, seed=31, n_max=12000)
+    reqs += requests(4, seed=32, n_max=9000, k=4, split=120)
+    flags = (SIMPLIFY if simplify else 0) | TRACE
+    say("serve with the device split, simplify", simplify, "requests", len(reqs))
+    srv = mp.Server(ctx, slice_nodes=64, device_split=True)
+    tickets = [srv.submit_layout(r["rects"], r["dmin"], r["split"], r["k"], 20000, flags)
+               for r in reqs]
+    results = [srv.wait(t, 60_000_000) for t in tickets]
+    srv.close()
+    assert sum(len(r["rects"]) >= 4096 for r in reqs) >= 5
+    for r, got in zip(reqs, results):
+        same(got, alone(ctx, r, 20000, flags))
+
+
 def test_stitched_k4_heavy_components_sliced(ctx):
     import paper_2303_14335_amd as mp
     reqs = requests(12, seed=77, n_max=20000, k=4, dmin=120, split=120)
