@@ -101,6 +101,10 @@ struct RegState {
   int32_t status;
   uint32_t fr, sp_lo, sp_hi;
   LaneWords<K> so_lo, so_hi;
+  // stitch-aware order only: lane u holds u's stitch partner (bits 8..15,
+  // 0xff none) and the color last given to that partner (bits 0..7, 0xff
+  // none); it is the partner's current color while the partner is covered
+  uint32_t pc;
 };
 
 template <int K>
@@ -229,6 +233,7 @@ __device__ __forceinline__ void take_row(RegState<K>& s, const uint64_t nbv, con
     s.so_hi[j] = wrlane(s.so_hi[j], d, (uint32_t)(s.O[j] >> 32));
   }
   s.fr = wrlane(s.fr, d, STITCH ? (v | (c << 8) | (tried << 16)) : (v | (c << 8)));
+  if (STITCH) s.pc = (s.pc >> 8) == v ? (s.pc & 0xff00u) | c : s.pc;   // v's partners see c
   cover(s.O, c, nbv);
   s.A = with_bit(s.A, d, alt);
   s.depth = d + 1;
@@ -274,8 +279,7 @@ __device__ __forceinline__ bool retreat(RegState<K>& s, const uint32_t floor, ui
 template <bool TRACE, int K, bool STITCH = false>
 __device__ __forceinline__ void reg_run(RegState<K>& s, const uint32_t nb_lo, const uint32_t nb_hi,
                                         const int32_t k, const uint64_t budget,
-                                        const uint64_t stop_at, const uint32_t floor = 0,
-                                        const uint32_t* __restrict__ part = nullptr) {
+                                        const uint64_t stop_at, const uint32_t floor = 0) {
   int32_t status = -1;
   while (status < 0) {
     // ---- one search node
@@ -309,17 +313,10 @@ __device__ __forceinline__ void reg_run(RegState<K>& s, const uint32_t nb_lo, co
         // the partner is on the path (covered) and that row is still open
         const uint32_t R = rows_of(s.O, v);
         tried = R & ((2u << c) - 1u);
-        // v's partner id: a byte of the item's partner block, read at a
-        // wave-uniform address
-        const uint32_t p = uniform((part[v >> 2] >> ((v & 3u) * 8u)) & 0xffu);
-        // branch-free: the frame of the partner's column, if it is on the
-        // path, gives its color
-        const bool on_path = p < 64u && !((s.P >> (p & 63u)) & 1ull);
-        const uint64_t at =
-            __ballot(on_path && __lane_id() < s.depth && (s.fr & 0xffu) == p) | (1ull << 63);
-        const uint32_t cp =
-            uniform((rdlane(s.fr, (uint32_t)__builtin_ctzll(at)) >> 8) & 0x1fu);
-        const bool use = (at & ~(1ull << 63)) != 0ull && ((R >> cp) & 1u);
+        // v's partner and the color it was last given, from v's lane
+        const uint32_t x = uniform(rdlane(s.pc, v));
+        const uint32_t p = x >> 8, cp = x & 0x1fu;
+        const bool use = p < 64u && !((s.P >> (p & 63u)) & 1ull) && ((R >> cp) & 1u);
         c = uniform(use ? cp : c);
         tried = uniform(use ? 1u << cp : tried);
       }
@@ -374,10 +371,14 @@ __device__ __forceinline__ uint64_t item_mask(const RegItems& R, int32_t i, uint
   const uint64_t* m = reinterpret_cast<const uint64_t*>(R.base + (uint64_t)i * R.stride + kRegItemHead);
   return lane < R.width ? m[lane] : 0ull;   // zero past n
 }
-// The item's stitch partner block: byte v is the partner (local id) of node
-// v, 0xff for none; 8-byte aligned, so it is read as 32-bit words.
-__device__ __forceinline__ const uint32_t* item_partners(const RegItems& R, int32_t i) {
-  return reinterpret_cast<const uint32_t*>(R.base + (uint64_t)i * R.stride + R.part_off);
+// Stitch partner (local id) of node `lane`, 0xff for none: byte `lane` of
+// the item's partner block, which is 8-byte aligned and padded, so it is
+// read as a 32-bit word.
+__device__ __forceinline__ uint32_t item_partner(const RegItems& R, int32_t i, uint32_t lane) {
+  const uint32_t* p = reinterpret_cast<const uint32_t*>(R.base + (uint64_t)i * R.stride + R.part_off);
+  const bool in = lane < R.width;
+  const uint32_t w = p[in ? lane >> 2 : 0u];   // word 0 always exists
+  return in ? (w >> ((lane & 3u) * 8u)) & 0xffu : 0xffu;
 }
 
 template <bool TRACE, int K, bool STITCH = false>
@@ -387,13 +388,13 @@ __device__ __forceinline__ void solve_reg(const RegItems& items, int32_t item,
                                           const uint64_t cap = ~0ull) {
   const uint32_t lane = __lane_id();
   const uint64_t nb = item_mask(items, item, lane);
-  const uint32_t* part = STITCH ? item_partners(items, item) : nullptr;
   const DevDesc d = item_desc(items, item);
   const uint64_t budget = (uint64_t)d.budget;
   RegState<K> s;
   reg_init(s, d.n, d.k);
+  if (STITCH) s.pc = (item_partner(items, item, lane) << 8) | 0xffu;
   reg_run<TRACE, K, STITCH>(s, (uint32_t)nb, (uint32_t)(nb >> 32), d.k, budget,
-                            cap < budget ? cap : budget, 0, part);
+                            cap < budget ? cap : budget, 0);
   reg_finish(s, d.n, colors_base + d.out_off, recs + d.comp);
 }
 
@@ -433,10 +434,10 @@ __device__ __forceinline__ void root_split(const RegItems& items, int32_t item, 
   const DevDesc d = item_desc(items, item);
   const uint64_t nb = item_mask(items, item, lane);
   const uint32_t nb_lo = (uint32_t)nb, nb_hi = (uint32_t)(nb >> 32);
-  const uint32_t* part = STITCH ? item_partners(items, item) : nullptr;
   const uint64_t budget = (uint64_t)d.budget;
   RegState<K> s;
   reg_init(s, d.n, d.k);
+  if (STITCH) s.pc = (item_partner(items, item, lane) << 8) | 0xffu;
   if (wave > kHelpers) return;
   if (s.P == 0ull) {   // empty component: the root is a solution
     if (wave == 0u) {
@@ -457,7 +458,7 @@ __device__ __forceinline__ void root_split(const RegItems& items, int32_t item, 
     take_row<K, STITCH>(s, nbv0, v0, c, 0ull, R0 & ((2u << c) - 1u));
     s.row_in = v0 * (uint32_t)d.k + c;
     for (;;) {
-      reg_run<false, K, STITCH>(s, nb_lo, nb_hi, d.k, ~0ull, s.nodes + chunk, 1, part);
+      reg_run<false, K, STITCH>(s, nb_lo, nb_hi, d.k, ~0ull, s.nodes + chunk, 1);
       if (s.status >= 0) break;
       if (__hip_atomic_load(&L.stop[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) != 0u)
         return;   // no longer needed
@@ -506,7 +507,7 @@ __device__ __forceinline__ void root_split(const RegItems& items, int32_t item, 
     s.depth = 0;
     take_row<K, STITCH>(s, nbv0, v0, c, rem != 0u ? 1ull : 0ull, R0 & ((2u << c) - 1u));
     s.row_in = v0 * (uint32_t)d.k + c;
-    reg_run<false, K, STITCH>(s, nb_lo, nb_hi, d.k, budget, budget, 1, part);
+    reg_run<false, K, STITCH>(s, nb_lo, nb_hi, d.k, budget, budget, 1);
     if (s.status != MPLD_INFEASIBLE) {
       status = s.status;
       break;
