@@ -946,7 +946,10 @@ hipError_t launch_reg_batched(bool trace, int k, int grid, int wpb, RegItems ite
   const bool stitch = items.part_off != 0;   // the items carry stitch partners
   with_planes(k, [&](auto kp) {
     constexpr int K = decltype(kp)::value;
-    const dim3 g(grid), b(64 * wpb);
+    // every item split: one workgroup per item and one wave per root row
+    // (three for k = 3), so that no idle fourth wave is dispatched
+    const int wg_waves = heavy == qlen ? (k < 4 ? k : 4) : wpb;
+    const dim3 g(grid), b(64 * wg_waves);
     if (trace && stitch)
       hipLaunchKernelGGL((reg_batched_kernel<true, K, true>), g, b, 0, s, items, qlen, counter, recs,
                          colors, cap, 0, chunk);
