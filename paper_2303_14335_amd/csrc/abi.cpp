@@ -49,6 +49,8 @@ void check_options(const mpld_options* opt) {
   if (forced & (forced - 1)) fail(MPLD_E_INVALID, "at most one MPLD_FORCE_* flag");
 }
 
+constexpr int32_t kDeviceSplitMinNodes = 32768;
+
 void use_device(mpld_context* ctx) {
   if (!ctx) fail(MPLD_E_INVALID, "context is NULL");
   check_hip(hipSetDevice(ctx->device), "hipSetDevice");
@@ -62,7 +64,14 @@ void batch_build(mpld_context* ctx, const mpld_graph* g, const mpld_options* opt
   b->ctx = ctx;
   b->opt = *opt;
   b->g = make_graph(*g);
-  b->s = simplify_and_split(b->g, opt->k, opt->flags & MPLD_SIMPLIFY);
+  // large sparse graphs are simplified and split on the device (identical
+  // result; at 50k nodes about half the host's time, at 5k nodes slower)
+  if (device_split_pays(b->g.n, b->g.ptr[(size_t)b->g.n], opt->k) && b->g.n >= kDeviceSplitMinNodes) {
+    if (!ctx->graph_builder) ctx->graph_builder = graph_builder_create(ctx, false);
+    split_graph_device(*ctx->graph_builder, b->g, opt->k, opt->flags & MPLD_SIMPLIFY, b->s);
+  } else {
+    b->s = simplify_and_split(b->g, opt->k, opt->flags & MPLD_SIMPLIFY);
+  }
   Tune t;
   tune_from_cache(b, nullptr, &t);
   batch_pack(b, t);

@@ -927,7 +927,7 @@ void split_graph_device(GraphBuilder& gb, const Graph& g, int32_t k, bool simpli
   collect_split(gb.hout.as<int32_t>(), nn, s);
 }
 
-void build_layout_graph_device(GraphBuilder& gb, const mpld_rect* rects, int32_t n, int32_t dmin,
+bool build_layout_graph_device(GraphBuilder& gb, const mpld_rect* rects, int32_t n, int32_t dmin,
                                int32_t split_len, Graph& g, std::vector<int32_t>* se, Split* split,
                                int32_t k, bool simplify) {
   LayoutPrep lp;
@@ -943,7 +943,7 @@ void build_layout_graph_device(GraphBuilder& gb, const mpld_rect* rects, int32_t
       *split = Split();
       split->comp_ptr.push_back(0);
     }
-    return;
+    return split != nullptr;
   }
   const int64_t ncell = lp.gx * lp.gy;
   if (ncell >= INT32_MAX || 2 * (int64_t)nn >= INT32_MAX)
@@ -1007,6 +1007,7 @@ void build_layout_graph_device(GraphBuilder& gb, const mpld_rect* rects, int32_t
                      gb.ids.as<int32_t>(), gb.smate.as<int32_t>(), gb.start.as<int32_t>(), nn, gp,
                      d2, nullptr, gb.ptr.as<int32_t>(), gb.adj.as<int32_t>());
   check_hip(hipGetLastError(), "graph builder: neighbour lists");
+  if (split && !device_split_pays(nn, total, k)) split = nullptr;   // the caller splits on the host
   if (split) enqueue_split(gb, nn, gb.ptr.as<int32_t>(), gb.adj.as<int32_t>(), k, simplify);
   const size_t split_words = split ? split_out_words(nn) : 0;
   const size_t out_bytes = sizeof(int32_t) * ((nb + 1) + (size_t)total + split_words);
@@ -1029,6 +1030,7 @@ void build_layout_graph_device(GraphBuilder& gb, const mpld_rect* rects, int32_t
   g.adj.assign(hadj, hadj + total);
   g.num_ce = total / 2;
   if (split) collect_split(hsplit, nn, *split);
+  return split != nullptr;
 }
 
 }  // namespace mpld

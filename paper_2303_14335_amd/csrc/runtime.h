@@ -290,12 +290,21 @@ void graph_builder_destroy(GraphBuilder* gb);
 // Builds the CSR layout graph of `rects` on the device (the host's
 // prepare_layout first); se receives the stitch pairs when not null.  With
 // `split`, the simplification and sub-graph split (identical to
-// simplify_and_split(g, k, simplify)) run on the device too, before the
-// results come back.
-void build_layout_graph_device(GraphBuilder& gb, const mpld_rect* rects, int32_t n, int32_t dmin,
+// simplify_and_split(g, k, simplify)) run on the device too when
+// device_split_pays for the graph; returns whether *split was filled.
+bool build_layout_graph_device(GraphBuilder& gb, const mpld_rect* rects, int32_t n, int32_t dmin,
                                int32_t split_len, Graph& g, std::vector<int32_t>* se,
                                Split* split = nullptr, int32_t k = 0, bool simplify = true);
 // simplify_and_split of a host graph, computed on the device.
 void split_graph_device(GraphBuilder& gb, const Graph& g, int32_t k, bool simplify, Split& s);
+// Whether the device split is worth it for a graph of n nodes with
+// `adj_entries` (= 2 |CE|) adjacency entries: with an average conflict degree
+// of at least k most nodes survive the peeling and the components can be
+// large, whose BFS runs level by level on one workgroup (a 40k-node
+// component: 13.6 ms, against a few ms on the host); below it the peeling
+// leaves small components and the device split is about twice as fast.
+inline bool device_split_pays(int64_t n, int64_t adj_entries, int32_t k) {
+  return adj_entries < (int64_t)k * n;
+}
 
 }  // namespace mpld

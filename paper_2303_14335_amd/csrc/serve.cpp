@@ -139,9 +139,9 @@ void mpld_server::front_end(Request* r) {
         // by construction, so no host validation pass)
         GraphBuilder* gb = gbuilders[gb_next.fetch_add(1) % gbuilders.size()];
         if (device_split) {   // simplification and split behind the pair search
-          build_layout_graph_device(*gb, r->rects.data(), nr, r->dmin, r->split, r->g, nullptr,
-                                    &r->s, r->opt.k, r->opt.flags & MPLD_SIMPLIFY);
-          split_done = true;
+          split_done = build_layout_graph_device(*gb, r->rects.data(), nr, r->dmin, r->split, r->g,
+                                                 nullptr, &r->s, r->opt.k,
+                                                 r->opt.flags & MPLD_SIMPLIFY);
         } else {
           build_layout_graph_device(*gb, r->rects.data(), nr, r->dmin, r->split, r->g, nullptr);
         }
