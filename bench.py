@@ -204,6 +204,35 @@ def serve_leg(mp, ctx, count: int, seed: int, graph_builders: int = 0,
             "admission_waits": st["admission_waits"], "peak_device_bytes": st["peak_bytes"]}
 
 
+def split_leg(mp, ctx, reps=5):
+    """Device simplification and sub-graph split (mpld_split_graph_device,
+    host validation, upload, kernels and download included) on a 50k-rect
+    request at the serving density and on config 1's graph; best of `reps`."""
+    import math
+
+    import workload
+    from workload.configs import CONFIGS, SERVE
+    out = {}
+    n = SERVE["n_max"]
+    side = round(SERVE["base_side"] * math.sqrt(n / SERVE["base_n"]))
+    cases = [(f"request {n} rects", workload.generate(n, side, 7)[0], SERVE["dmin_nm"], 0,
+              SERVE["k"])]
+    w = CONFIGS[1]
+    cases.append((w.name, workload.generate(w.n_rects, w.side_nm, w.seed)[0], w.dmin_nm,
+                  w.split_len_nm, w.k))
+    for name, rects, dmin, split, k in cases:
+        g = mp.mpld_build_graph(rects, dmin, split)
+        mp.mpld_split_graph_device(ctx, g, k)
+        ts = []
+        for _ in range(reps):
+            t = time.perf_counter()
+            rem, _, comps = mp.mpld_split_graph_device(ctx, g, k)
+            ts.append(time.perf_counter() - t)
+        out[name] = {"nodes": g.num_nodes, "removed": int(len(rem)), "components": len(comps),
+                     "ms": round(1000 * min(ts), 3)}
+    return out
+
+
 # Per-node latency probes (labelled as probes, not workloads): one connected
 # random component per tier, run to its node budget on a single wave (or
 # the whole device), so launch and setup costs vanish in the per-node time.
@@ -273,6 +302,8 @@ def main() -> int:
                     help="serving leg: requests of the serving workload (0 = skip)")
     ap.add_argument("--stitch-steps", type=int, default=5,
                     help="steps of the stitch-order leg on the stitch workload (0: skip)")
+    ap.add_argument("--split-only", action="store_true",
+                    help="only the device simplification/split leg (for profiling its kernels)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run one device copy of this size (counter scaling probe)")
     args = ap.parse_args()
@@ -290,6 +321,11 @@ def main() -> int:
     import paper_2303_14335_amd as mp
     import workload
     from workload.configs import CONFIGS
+
+    if args.split_only:
+        ctx = mp.Context(0)
+        print(json.dumps({"device_split": split_leg(mp, ctx)}), flush=True)
+        return 0
 
     if args.probe_only:
         ctx = mp.Context(0)
@@ -524,6 +560,8 @@ def main() -> int:
                      "budget": int(np.sum(comps["status"] == 2))},
         "stitches": res.stitches, "uncolored": res.uncolored,
     }
+    log("device split leg")
+    out["device_split"] = split_leg(mp, ctx)
     if not args.no_latency_probe:
         log("latency probes")
         out["latency_probe"] = latency_probe(mp, ctx)
