@@ -62,15 +62,20 @@ def test_mix_equals_alone(ctx, slice_nodes):
         assert got.total_us >= got.queue_us >= 0
 
 
-@pytest.mark.parametrize("simplify", [True, False])
-def test_device_split_equals_alone(ctx, simplify):
-    # layouts of >= 4096 rects are built, simplified and split on the device
+@pytest.mark.parametrize("simplify,builders,device_split",
+                         [(True, 0, True), (False, 0, True), (True, 2, True), (True, 0, False),
+                          (True, -1, True)])
+def test_device_front_end_equals_alone(ctx, simplify, builders, device_split):
+    # layouts of >= 4096 rects are built (and, with device_split, simplified
+    # and split) on the device, by one builder or a pool of two; builders < 0
+    # builds every graph on the host
     import paper_2303_14335_amd as mp
     reqs = requests(24, seed=31, n_max=12000)
     reqs += requests(4, seed=32, n_max=9000, k=4, split=120)
     flags = (SIMPLIFY if simplify else 0) | TRACE
-    say("serve with the device split, simplify", simplify, "requests", len(reqs))
-    srv = mp.Server(ctx, slice_nodes=64, device_split=True)
+    say("serve, simplify", simplify, "builders", builders, "device split", device_split,
+        "requests", len(reqs))
+    srv = mp.Server(ctx, slice_nodes=64, graph_builders=builders, device_split=device_split)
     tickets = [srv.submit_layout(r["rects"], r["dmin"], r["split"], r["k"], 20000, flags)
                for r in reqs]
     results = [srv.wait(t, 60_000_000) for t in tickets]
