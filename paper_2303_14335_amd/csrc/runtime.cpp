@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 
 namespace mpld {
@@ -145,7 +146,17 @@ void device_upload(mpld_context* ctx, const Image& im, DeviceBatch& db, const Tu
   db.n_lds = (int32_t)im.q_lds.size();
   db.n_big = (int32_t)im.q_big.size();
   db.n_dev = (int32_t)im.q_dev.size();
-  db.grid_dev = ctx->num_cus;
+  {
+    // device-wide tier: each search node costs two grid barriers, whose
+    // cost grows with the workgroups (about 3 us at 64, 12 us at 256),
+    // while the scan per node shrinks with them: about sqrt(n) / 12
+    // workgroups, at least 8 (per node on n = 10^4: 3.6 us at 8, 4.6 at 16,
+    // 5.9 at 32, 24.9 at 256), and enough that a block's slice fits in 48 KB
+    const int32_t n = std::max(1, im.dev_max_n);
+    int grid = std::max(8, (int)std::lround(std::sqrt((double)n) / 12.0));
+    while (grid < ctx->num_cus && device_tier_lds_bytes(n, grid) > 48 * 1024) grid *= 2;
+    db.grid_dev = std::min(grid, ctx->num_cus);
+  }
   db.lds_dev = device_tier_lds_bytes(std::max(1, im.dev_max_n), db.grid_dev);
   db.lds_small = (int)im.lds_bytes_small;
   db.lds_big = (int)im.lds_bytes_big;
