@@ -769,8 +769,13 @@ struct GraphBuilder {
   }
 };
 
+// Buffers grow geometrically: a reallocation (and, for pinned host memory,
+// hipHostMalloc) costs milliseconds, so it should happen rarely.
 static void grow(DevBuf& b, mpld_context* ctx, size_t bytes) {
-  if (b.bytes < bytes) b.alloc(ctx, bytes + bytes / 4);
+  if (b.bytes < bytes) b.alloc(ctx, std::max(bytes + bytes / 4, 2 * b.bytes));
+}
+static bool grow_pinned(PinnedBuf& b, size_t bytes) {
+  return bytes <= b.bytes || b.reserve(std::max(bytes + bytes / 4, 2 * b.bytes));
 }
 
 GraphBuilder* graph_builder_create(mpld_context* ctx, bool own_stream) {
@@ -791,6 +796,7 @@ GraphBuilder* graph_builder_create(mpld_context* ctx, bool own_stream) {
 }
 
 void graph_builder_destroy(GraphBuilder* gb) { delete gb; }
+
 
 static void scan(GraphBuilder& gb, const int32_t* in, int64_t n, int32_t* out) {
   const int64_t ntiles = (n + kScanTile - 1) / kScanTile;
@@ -891,6 +897,26 @@ static void collect_split(const int32_t* h, int32_t n, Split& s) {
   s.local.assign(local, local + nn);
 }
 
+void graph_builder_reserve(GraphBuilder& gb, int32_t nodes) {
+  // sizes as a build and split of `nodes` nodes with up to 8 adjacency
+  // entries and 4 grid cells per node would ask for
+  std::lock_guard<std::mutex> lk(gb.mu);
+  mpld_context* ctx = gb.ctx;
+  const size_t n = (size_t)std::max(nodes, 1), cells = 4 * n, adj = 8 * n;
+  for (DevBuf* b : {&gb.partner, &gb.cell_of, &gb.ids, &gb.smate}) grow(*b, ctx, 4 * n);
+  for (DevBuf* b : {&gb.box, &gb.sbox}) grow(*b, ctx, 16 * n);
+  for (DevBuf* b : {&gb.cnt, &gb.start, &gb.fill}) grow(*b, ctx, 4 * (cells + 1));
+  for (DevBuf* b : {&gb.deg, &gb.ptr}) grow(*b, ctx, 4 * (n + 1));
+  grow(gb.adj, ctx, 4 * adj);
+  const size_t tiles = (cells + kScanTile - 1) / kScanTile + 1;
+  grow(gb.sums, ctx, 4 * tiles);
+  grow(gb.offs, ctx, 4 * tiles);
+  grow(gb.split_ws, ctx, 4 * (split_out_words((int64_t)n) + kSplitScratch * std::max<size_t>(n + 1, 64)));
+  if (!grow_pinned(gb.hin, 20 * n + 4 * (n + 1 + adj)) ||
+      !grow_pinned(gb.hout, 4 * (n + 1 + adj + split_out_words((int64_t)n))))
+    fail(MPLD_E_NOMEM, "graph builder: pinned host memory");
+}
+
 void split_graph_device(GraphBuilder& gb, const Graph& g, int32_t k, bool simplify, Split& s) {
   const int32_t nn = g.n;
   if (nn == 0) {
@@ -908,7 +934,7 @@ void split_graph_device(GraphBuilder& gb, const Graph& g, int32_t k, bool simpli
   grow(gb.ptr, ctx, sizeof(int32_t) * (nb + 1));
   grow(gb.adj, ctx, sizeof(int32_t) * (size_t)std::max<int64_t>(m2, 1));
   const size_t in_bytes = sizeof(int32_t) * (nb + 1 + (size_t)m2);
-  if (!gb.hin.reserve(in_bytes)) fail(MPLD_E_NOMEM, "device split: pinned host memory");
+  if (!grow_pinned(gb.hin, in_bytes)) fail(MPLD_E_NOMEM, "device split: pinned host memory");
   int32_t* hp = gb.hin.as<int32_t>();
   for (size_t i = 0; i <= nb; ++i) hp[i] = (int32_t)g.ptr[i];
   std::memcpy(hp + nb + 1, g.adj.data(), sizeof(int32_t) * (size_t)m2);
@@ -920,7 +946,7 @@ void split_graph_device(GraphBuilder& gb, const Graph& g, int32_t k, bool simpli
               "device split: upload lists");
   enqueue_split(gb, nn, gb.ptr.as<int32_t>(), gb.adj.as<int32_t>(), k, simplify);
   const size_t out_bytes = sizeof(int32_t) * split_out_words(nn);
-  if (!gb.hout.reserve(out_bytes)) fail(MPLD_E_NOMEM, "device split: pinned host memory");
+  if (!grow_pinned(gb.hout, out_bytes)) fail(MPLD_E_NOMEM, "device split: pinned host memory");
   check_hip(hipMemcpyAsync(gb.hout.p, gb.split_ws.p, out_bytes, hipMemcpyDeviceToHost, st),
             "device split: download");
   check_hip(hipStreamSynchronize(st), "device split");
@@ -967,7 +993,7 @@ bool build_layout_graph_device(GraphBuilder& gb, const mpld_rect* rects, int32_t
   grow(gb.ptr, ctx, sizeof(int32_t) * (nb + 1));
   // boxes and partners in one pinned staging copy
   const size_t in_bytes = sizeof(int4) * nb + sizeof(int32_t) * nb;
-  if (!gb.hin.reserve(in_bytes)) fail(MPLD_E_NOMEM, "graph builder: pinned host memory");
+  if (!grow_pinned(gb.hin, in_bytes)) fail(MPLD_E_NOMEM, "graph builder: pinned host memory");
   std::memcpy(gb.hin.p, lp.nd.data(), sizeof(int4) * nb);
   std::memcpy(static_cast<char*>(gb.hin.p) + sizeof(int4) * nb, lp.partner.data(),
               sizeof(int32_t) * nb);
@@ -1011,7 +1037,7 @@ bool build_layout_graph_device(GraphBuilder& gb, const mpld_rect* rects, int32_t
   if (split) enqueue_split(gb, nn, gb.ptr.as<int32_t>(), gb.adj.as<int32_t>(), k, simplify);
   const size_t split_words = split ? split_out_words(nn) : 0;
   const size_t out_bytes = sizeof(int32_t) * ((nb + 1) + (size_t)total + split_words);
-  if (!gb.hout.reserve(out_bytes)) fail(MPLD_E_NOMEM, "graph builder: pinned host memory");
+  if (!grow_pinned(gb.hout, out_bytes)) fail(MPLD_E_NOMEM, "graph builder: pinned host memory");
   int32_t* hptr = static_cast<int32_t*>(gb.hout.p);
   int32_t* hadj = hptr + nb + 1;
   int32_t* hsplit = hadj + total;

@@ -287,6 +287,9 @@ bool tune_from_cache(mpld_batch* b, const char* path, Tune* t);
 // its own (server front-end workers), else the context's stream.
 GraphBuilder* graph_builder_create(mpld_context* ctx, bool own_stream);
 void graph_builder_destroy(GraphBuilder* gb);
+// Allocates the builder's device and pinned buffers for layouts of up to
+// about `nodes` nodes ahead of use (they still grow beyond).
+void graph_builder_reserve(GraphBuilder& gb, int32_t nodes);
 // Builds the CSR layout graph of `rects` on the device (the host's
 // prepare_layout first); se receives the stitch pairs when not null.  With
 // `split`, the simplification and sub-graph split (identical to

@@ -612,7 +612,12 @@ int32_t mpld_server_create(mpld_context* ctx, const mpld_server_options* opt, mp
       // one builder by default: with four, the measured p99 latency of a
       // Poisson mix of layout requests rose by about a third
       const int nb = o.graph_builders == 0 ? 1 : std::max(0, o.graph_builders);
-      for (int i = 0; i < nb; ++i) s->gbuilders.push_back(graph_builder_create(ctx, true));
+      for (int i = 0; i < nb; ++i) {
+        s->gbuilders.push_back(graph_builder_create(ctx, true));
+        // sized ahead for layouts of up to 64k nodes: growing a builder
+        // while requests wait behind it cost several milliseconds each time
+        graph_builder_reserve(*s->gbuilders.back(), 1 << 16);
+      }
       // device split by default: over three paired runs of 1,000 requests
       // it took p99 latency from 2.9-3.5 ms (host split) to 2.5-2.7 ms
       s->device_split = o.device_split >= 0;
