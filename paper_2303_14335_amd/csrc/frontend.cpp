@@ -169,13 +169,19 @@ void recover(const Graph& g, const Split& s, int32_t k, std::vector<int8_t>& col
 void tallies(const Graph& g, const std::vector<int8_t>& colors, int64_t* stitches,
              int64_t* conflicts, int64_t* uncolored) {
   int64_t st = 0, cn = 0, un = 0;
+  const int8_t* col = colors.data();
+  const int32_t* adj = g.adj.data();
   for (int32_t v = 0; v < g.n; ++v) {
-    const int8_t cv = colors[v];
+    const int8_t cv = col[v];
     if (cv < 0) { ++un; continue; }
     const int32_t p = g.partner[v];
-    if (p > v && colors[p] >= 0 && colors[p] != cv) ++st;
-    for (int64_t t = g.ptr[v]; t < g.ptr[v + 1]; ++t)
-      if (g.adj[t] > v && colors[g.adj[t]] == cv) ++cn;
+    if (p > v) st += col[p] >= 0 && col[p] != cv;
+    int64_t c = 0;   // branch-free: the pair test is unpredictable
+    for (int64_t t = g.ptr[v], e = g.ptr[v + 1]; t < e; ++t) {
+      const int32_t w = adj[t];
+      c += (w > v) & (col[w] == cv);
+    }
+    cn += c;
   }
   *stitches = st;
   *conflicts = cn;
