@@ -222,9 +222,11 @@ int32_t mpld_build_graph_device(mpld_context* ctx, const mpld_rect* rects, int32
  * removal_order (num_nodes; the first *num_removed are used), comp_of
  * (num_nodes; -1 = removed), bfs_order (num_nodes; core nodes grouped by
  * component, each in local order), comp_ptr (num_nodes + 1; component c is
- * bfs_order[comp_ptr[c] .. comp_ptr[c + 1])).  One workgroup runs the whole
- * split, so that its many short rounds are separated by barriers rather than
- * launches.  Synchronous on the context's stream.  Errors: MPLD_E_INVALID
+ * bfs_order[comp_ptr[c] .. comp_ptr[c + 1])).  Wide passes (the first peel
+ * levels, union-find, numbering) run over the whole device, the small tail
+ * of the peeling and the BFS of components above 64 nodes on one workgroup,
+ * the BFS of smaller components one wave each.  Synchronous on the
+ * context's stream.  Errors: MPLD_E_INVALID
  * for a bad graph (as mpld_decompose), k outside [2, MPLD_MAX_K] or a NULL
  * output; MPLD_E_DEVICE / MPLD_E_NOMEM. */
 int32_t mpld_split_graph_device(mpld_context* ctx, const mpld_graph* g, int32_t k, uint32_t flags,
@@ -370,10 +372,11 @@ typedef struct {
   int32_t graph_builders;  /* device graph builders (own stream each) taken
                               in turn by layout requests of >= 4096 rects;
                               0 = 1, < 0 = none (the host builds every graph) */
-  int32_t device_split;    /* >= 0: device-built layouts are also simplified
+  int32_t device_split;    /* >= 0: device-built layouts whose average
+                              conflict degree is below k are also simplified
                               and split on the device (mpld_split_graph_device's
                               kernels, behind the pair search; default);
-                              < 0: on the host */
+                              < 0: always on the host */
   int32_t reserved;
 } mpld_server_options;
 typedef struct {
