@@ -190,7 +190,7 @@ struct Tune {
   int32_t order = 0;             // 0 largest first, 1 smallest first
   int32_t giant_device = 0;      // giants on the device-wide tier instead of the big tier
   int32_t giant_min_nodes = 4096;
-  int32_t heavy_first_cap = 512;   // heavy-component engine: first-pass node cap
+  int32_t heavy_first_cap = 128;   // heavy-component engine: first-pass node cap
   int32_t heavy_round_cap = 256;   // nodes per subtree task and round
   int32_t heavy_levels = 0;        // levels per split; 0 = by k (4, 3 or 2)
   int32_t heavy_device = 1;        // 1: rounds chained on the device; 0: host-driven rounds
