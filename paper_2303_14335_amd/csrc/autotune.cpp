@@ -248,6 +248,17 @@ int32_t mpld_batch_autotune(mpld_batch* b, int32_t reps, const char* cache_path,
               t.giant_device = giant;
               cands.push_back(t);
             }
+    // root split of the register-tier items (four-wave workgroups, largest
+    // first): off, only for larger items, other helper chunks
+    if (!heavy && n_reg > 0) {
+      for (const int v : {0, 8, 16, -4, -64}) {
+        Tune t;
+        if (v == 0) t.root_split = 0;
+        else if (v > 0) t.root_split_min_n = v;
+        else t.root_split_chunk = -v;
+        cands.push_back(t);
+      }
+    }
     Tune best = base;
     float best_ms = base_ms;
     for (const Tune& t : cands) {

@@ -286,6 +286,25 @@ def test_autotune_keeps_results_and_caches(ctx, tmp_path):
         t["waves_per_block"], t["order"], t["use_graph"])
 
 
+def test_autotune_light_batch_root_split_candidates(ctx):
+    # a light batch (config 1) also tries the root split's settings; every
+    # candidate must reproduce the default's records and colors
+    import paper_2303_14335_amd as mp
+    w, rects = graph_of(1)
+    say("autotune on config 1")
+    g = mp.mpld_build_graph(rects, w.dmin_nm, w.split_len_nm)
+    b = mp.Batch(ctx, g, w.k, w.budget, SIMPLIFY)
+    b.solve()
+    ref = b.result()
+    t = b.autotune(reps=3)
+    assert t["candidates"] >= 6 and t["best_ms"] <= t["default_ms"] * 1.0001
+    b.solve()
+    got = b.result()
+    assert np.array_equal(got.colors, ref.colors)
+    assert np.array_equal(got.components["nodes"], ref.components["nodes"])
+    b.close()
+
+
 SPLIT = 1 << 8
 
 
