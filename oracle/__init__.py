@@ -81,7 +81,8 @@ def _load():
         lib.orc_solve_many.restype = ctypes.c_int32
         lib.orc_solve_many.argtypes = [ctypes.c_int32, vp, vp, vp,
                                        ctypes.c_int32, ctypes.c_int64,
-                                       ctypes.c_int32, vp, vp, vp, vp]
+                                       ctypes.c_int32, ctypes.c_int32, vp, vp, vp, vp,
+                                       _p(ctypes.c_int64)]
         lib.orc_ec_matrix.restype = ctypes.c_int32
         lib.orc_ec_matrix.argtypes = [ctypes.c_int32, ctypes.c_int64, vp,
                                       ctypes.c_int32, _p(vp), _p(vp)]
@@ -223,8 +224,11 @@ def mark_conflicts(n: int, edges, k: int) -> np.ndarray:
     return colors[:n].copy()
 
 
-def solve_many(sizes, edge_lists, k: int, budget: int, threads: int):
-    """Components solved over `threads` host threads; returns dict."""
+def solve_many(sizes, edge_lists, k: int, budget: int, threads: int, passes: int = 1):
+    """Components solved over `threads` host threads, the whole set repeated
+    `passes` times in one call; returns a dict with the first pass's
+    per-component status, nodes, trace_hash and concatenated local colors,
+    and total_nodes over every pass."""
     lib = _load()
     sizes = np.ascontiguousarray(sizes, dtype=np.int32)
     counts = np.array([len(e) for e in edge_lists], dtype=np.int64)
@@ -236,14 +240,16 @@ def solve_many(sizes, edge_lists, k: int, budget: int, threads: int):
     status = np.zeros(max(cnt, 1), dtype=np.int32)
     nodes = np.zeros(max(cnt, 1), dtype=np.int64)
     hashes = np.zeros(max(cnt, 1), dtype=np.uint64)
+    total = ctypes.c_int64()
     rc = lib.orc_solve_many(cnt, sizes.ctypes.data, counts.ctypes.data,
-                            edges.ctypes.data, k, budget, threads,
+                            edges.ctypes.data, k, budget, threads, passes,
                             colors.ctypes.data, status.ctypes.data,
-                            nodes.ctypes.data, hashes.ctypes.data)
+                            nodes.ctypes.data, hashes.ctypes.data, ctypes.byref(total))
     if rc != 0:
         raise ValueError(f"orc_solve_many failed: {rc}")
     return {"status": status[:cnt], "nodes": nodes[:cnt],
-            "trace_hash": hashes[:cnt], "colors": colors}
+            "trace_hash": hashes[:cnt], "colors": colors[:int(sizes.sum())],
+            "total_nodes": total.value}
 
 
 def ec_matrix(n: int, edges, k: int):

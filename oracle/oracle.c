@@ -11,6 +11,7 @@
 #include "oracle.h"
 
 #include <pthread.h>
+#include <stdatomic.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -781,11 +782,17 @@ out:
 
 /* ------------------------------------------------------------------------
  * Many components on several host threads (timing only; per component the
- * result is orc_solve_component's).
+ * result is orc_solve_component's).  The workers live for the whole call
+ * and repeat the set `passes` times: task t is component t % count of pass
+ * t / count, claimed in chunks from one atomic counter.  Pass 0 writes the
+ * outputs; later passes solve into each worker's own scratch, so no two
+ * threads write the same output.
  * ---------------------------------------------------------------------- */
 
+enum { ORC_POOL_CHUNK = 4 };
+
 typedef struct {
-  int32_t count, k;
+  int32_t count, k, passes, max_n;
   int64_t budget;
   const int32_t* sizes;
   const int64_t* edge_off;
@@ -795,53 +802,83 @@ typedef struct {
   int32_t* status;
   int64_t* nodes;
   uint64_t* hash;
-  int32_t next;          /* next component to take (guarded by mu) */
-  int32_t err;
-  pthread_mutex_t mu;
+  _Atomic int64_t next;        /* next task to claim */
+  _Atomic int64_t total_nodes; /* search nodes over every pass */
+  _Atomic int32_t err;
 } orc_pool;
 
 static void* pool_worker(void* arg) {
   orc_pool* p = (orc_pool*)arg;
+  const int64_t tasks = (int64_t)p->count * p->passes;
+  int8_t* scratch = (int8_t*)malloc((size_t)(p->max_n > 0 ? p->max_n : 1));
+  if (!scratch) { atomic_store(&p->err, -2); return NULL; }
+  int64_t mine = 0;
   for (;;) {
-    pthread_mutex_lock(&p->mu);
-    const int32_t i = p->next++;
-    pthread_mutex_unlock(&p->mu);
-    if (i >= p->count) break;
-    const int64_t m = p->edge_off[i + 1] - p->edge_off[i];
-    int32_t rc = orc_solve_component(p->sizes[i], m, p->edges + 2 * p->edge_off[i],
-                                     p->k, p->budget, p->colors + p->node_off[i],
-                                     &p->status[i], &p->nodes[i], &p->hash[i], NULL);
-    if (rc) {
-      pthread_mutex_lock(&p->mu);
-      p->err = rc;
-      pthread_mutex_unlock(&p->mu);
+    const int64_t t0 = atomic_fetch_add(&p->next, (int64_t)ORC_POOL_CHUNK);
+    if (t0 >= tasks) break;
+    const int64_t t1 = t0 + ORC_POOL_CHUNK < tasks ? t0 + ORC_POOL_CHUNK : tasks;
+    for (int64_t t = t0; t < t1; ++t) {
+      const int32_t i = (int32_t)(t % p->count);
+      const int first = t < p->count;
+      const int64_t m = p->edge_off[i + 1] - p->edge_off[i];
+      int32_t st;
+      int64_t nd;
+      uint64_t h;
+      int32_t rc = orc_solve_component(p->sizes[i], m, p->edges + 2 * p->edge_off[i], p->k,
+                                       p->budget, first ? p->colors + p->node_off[i] : scratch,
+                                       &st, &nd, &h, NULL);
+      if (rc) atomic_store(&p->err, rc);
+      if (first) {
+        p->status[i] = st;
+        p->nodes[i] = nd;
+        p->hash[i] = h;
+      }
+      mine += nd;
     }
   }
+  atomic_fetch_add(&p->total_nodes, mine);
+  free(scratch);
   return NULL;
 }
 
 int32_t orc_solve_many(int32_t count, const int32_t* sizes,
                        const int64_t* edge_counts, const int32_t* edges,
-                       int32_t k, int64_t budget, int32_t threads,
+                       int32_t k, int64_t budget, int32_t threads, int32_t passes,
                        int8_t* colors, int32_t* status, int64_t* nodes,
-                       uint64_t* trace_hash) {
-  if (count < 0 || threads < 1) return -1;
+                       uint64_t* trace_hash, int64_t* total_nodes) {
+  if (count < 0 || threads < 1 || passes < 1) return -1;
+  if (total_nodes) *total_nodes = 0;
+  if (count == 0) return 0;
   int64_t* eo = (int64_t*)malloc(sizeof(int64_t) * ((size_t)count + 1));
   int64_t* no = (int64_t*)malloc(sizeof(int64_t) * ((size_t)count + 1));
   pthread_t* th = (pthread_t*)malloc(sizeof(pthread_t) * (size_t)threads);
   if (!eo || !no || !th) { free(eo); free(no); free(th); return -2; }
   eo[0] = 0; no[0] = 0;
+  int32_t max_n = 0;
   for (int32_t i = 0; i < count; ++i) {
+    if (sizes[i] < 0 || edge_counts[i] < 0) { free(eo); free(no); free(th); return -1; }
     eo[i + 1] = eo[i] + edge_counts[i];
     no[i + 1] = no[i] + sizes[i];
+    if (sizes[i] > max_n) max_n = sizes[i];
   }
-  orc_pool p = {count, k, budget, sizes, eo, no, edges, colors, status, nodes,
-                trace_hash, 0, 0, PTHREAD_MUTEX_INITIALIZER};
-  int32_t started = 0;
-  for (int32_t t = 0; t < threads; ++t)
-    if (pthread_create(&th[t], NULL, pool_worker, &p) == 0) ++started;
-  if (started == 0) pool_worker(&p);
-  for (int32_t t = 0; t < started; ++t) pthread_join(th[t], NULL);
+  orc_pool p;
+  p.count = count; p.k = k; p.passes = passes; p.max_n = max_n; p.budget = budget;
+  p.sizes = sizes; p.edge_off = eo; p.node_off = no; p.edges = edges;
+  p.colors = colors; p.status = status; p.nodes = nodes; p.hash = trace_hash;
+  atomic_init(&p.next, 0);
+  atomic_init(&p.total_nodes, 0);
+  atomic_init(&p.err, 0);
+  if (threads == 1) {
+    /* one thread: the caller's own (keeps any CPU affinity it has set) */
+    pool_worker(&p);
+  } else {
+    int32_t started = 0;
+    for (int32_t t = 0; t < threads; ++t)
+      if (pthread_create(&th[started], NULL, pool_worker, &p) == 0) ++started;
+    if (started == 0) pool_worker(&p);
+    for (int32_t t = 0; t < started; ++t) pthread_join(th[t], NULL);
+  }
+  if (total_nodes) *total_nodes = atomic_load(&p.total_nodes);
   free(eo); free(no); free(th);
-  return p.err;
+  return atomic_load(&p.err);
 }

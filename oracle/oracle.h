@@ -105,12 +105,16 @@ int32_t orc_mark_conflicts(int32_t n, int64_t m, const int32_t* edges, int32_t k
 
 /* Solves many components (concatenated local edge lists) on `threads`
  * threads, each component independently with orc_solve_component's
- * semantics.  Used only to time the oracle on all host cores. */
+ * semantics, and repeats the whole set `passes` times in the same call
+ * (the threads stay alive across passes).  The outputs hold the first
+ * pass; *total_nodes (may be NULL) is the search-node sum over every pass.
+ * threads == 1 runs on the calling thread.  Used only to time the oracle
+ * on the host cores. */
 int32_t orc_solve_many(int32_t count, const int32_t* sizes,
                        const int64_t* edge_counts, const int32_t* edges,
-                       int32_t k, int64_t budget, int32_t threads,
+                       int32_t k, int64_t budget, int32_t threads, int32_t passes,
                        int8_t* colors, int32_t* status, int64_t* nodes,
-                       uint64_t* trace_hash);
+                       uint64_t* trace_hash, int64_t* total_nodes);
 
 /* Builds the exact-cover matrix of a component (for inspection in tests):
  * rows R = n*k, columns C = n + m*k; returns CSR over rows (row_ptr R+1,
