@@ -96,55 +96,130 @@ def oracle_components(rects, w):
     return g, sizes, edge_lists
 
 
-def cpu_baseline(rects, w, seconds: float):
-    """The oracle as it stands, single-threaded, on a bounded sample: whole
-    passes over every component of the workload until `seconds` elapse."""
-    import numpy as np
-    import oracle
-    _, sizes, edge_lists = oracle_components(rects, w)
-    passes, nodes, t0 = 0, 0, time.perf_counter()
-    while True:
-        r = oracle.solve_many(sizes, edge_lists, w.k, w.budget, threads=1)
-        nodes += int(np.sum(r["nodes"]))
-        passes += 1
-        el = time.perf_counter() - t0
-        if el >= seconds or el * (passes + 1) / passes > 3 * seconds:
-            break
-    return {"value": nodes / el, "unit": "search nodes/s", "cores": 1, "kind": "oracle",
-            "sample": f"{passes} single-threaded pass(es) of the oracle's dancing-links search "
-                      f"over all {len(sizes)} components of the workload "
-                      f"({nodes // passes} search nodes per pass), {el:.2f} s",
-            "components_per_s": passes * len(sizes) / el}
-
-
-def cpu_all_cores(rects, w, seconds: float):
-    """The same oracle with the components spread dynamically over every host
-    core (its own thread pool), whole passes until `seconds` elapse."""
-    import numpy as np
-    import oracle
-    _, sizes, edge_lists = oracle_components(rects, w)
-    threads = os.cpu_count() or 1
-    passes, nodes, t0 = 0, 0, time.perf_counter()
-    while True:
-        r = oracle.solve_many(sizes, edge_lists, w.k, w.budget, threads=threads)
-        nodes += int(np.sum(r["nodes"]))
-        passes += 1
-        el = time.perf_counter() - t0
-        if el >= seconds or el * (passes + 1) / passes > 3 * seconds:
-            break
-    model = ""
+def _cpu_model() -> str:
     try:
         with open("/proc/cpuinfo") as fh:
             for line in fh:
                 if line.startswith("model name"):
-                    model = line.split(":", 1)[1].strip()
-                    break
+                    return line.split(":", 1)[1].strip()
     except OSError:
         pass
-    return {"value": nodes / el, "unit": "search nodes/s", "cores": threads, "kind": "oracle",
-            "wall_ms_per_pass": 1000 * el / passes, "cpu_model": model,
-            "sample": f"{passes} pass(es) over all {len(sizes)} components on {threads} threads, "
-                      f"{el:.2f} s"}
+    return ""
+
+
+def _timed_passes(sizes, edge_lists, w, threads: int, seconds: float):
+    """One call of the oracle's runner with as many whole passes over every
+    component as fit in about `seconds` (sized from one untimed pass)."""
+    import oracle
+    t = time.perf_counter()
+    first = oracle.solve_many(sizes, edge_lists, w.k, w.budget, threads=threads)
+    one = max(time.perf_counter() - t, 1e-6)
+    passes = max(1, min(1 << 20, int(seconds / one)))
+    t0 = time.perf_counter()
+    r = oracle.solve_many(sizes, edge_lists, w.k, w.budget, threads=threads, passes=passes)
+    el = time.perf_counter() - t0
+    return first, r, passes, el
+
+
+def cpu_legs(rects, w, seconds: float, gpu_comps):
+    """The oracle as it stands on a bounded sample of the workload: whole
+    passes over every component in one call of its runner, (1) on one
+    thread pinned to one core, (2) on every host core (threads alive across
+    passes, components claimed in chunks).  Both must reproduce the GPU
+    batch's per-component status and node counts."""
+    import numpy as np
+    _, sizes, edge_lists = oracle_components(rects, w)
+    allowed = sorted(os.sched_getaffinity(0))
+    core = allowed[-1]
+    os.sched_setaffinity(0, {core})
+    try:
+        first1, r1, p1, el1 = _timed_passes(sizes, edge_lists, w, 1, seconds)
+    finally:
+        os.sched_setaffinity(0, set(allowed))
+    threads = len(allowed)
+    firstn, rn, pn, eln = _timed_passes(sizes, edge_lists, w, threads, seconds / 2)
+    per_pass = int(np.sum(first1["nodes"]))
+    agree = bool(np.array_equal(first1["status"], gpu_comps["status"])
+                 and np.array_equal(first1["nodes"], gpu_comps["nodes"])
+                 and np.array_equal(firstn["status"], first1["status"])
+                 and np.array_equal(firstn["nodes"], first1["nodes"])
+                 and r1["total_nodes"] == p1 * per_pass and rn["total_nodes"] == pn * per_pass)
+    one = {"value": r1["total_nodes"] / el1, "unit": "search nodes/s", "cores": 1,
+           "kind": "oracle",
+           "sample": f"{p1} single-threaded pass(es) of the oracle's dancing-links search over "
+                     f"all {len(sizes)} components of the workload ({per_pass} search nodes per "
+                     f"pass) in one call, pinned to core {core}, {el1:.2f} s",
+           "components_per_s": p1 * len(sizes) / el1,
+           "agree": agree, "host": {"nproc": os.cpu_count(), "allowed_cores": threads,
+                                    "cpu_model": _cpu_model()}}
+    alln = {"value": rn["total_nodes"] / eln, "unit": "search nodes/s", "cores": threads,
+            "kind": "oracle", "wall_ms_per_pass": 1000 * eln / pn,
+            "cpu_model": _cpu_model(), "over_one_core": (rn["total_nodes"] / eln) /
+            (r1["total_nodes"] / el1),
+            "sample": f"{pn} pass(es) over all {len(sizes)} components on {threads} threads in "
+                      f"one call, {eln:.2f} s", "agree": agree}
+    return one, alln
+
+
+def config_leg(mp, ctx, cfg: int, steps: int, split: bool):
+    """Another workload as a device-resident batch: the host front-end, one
+    untimed sequential solve as the reference, then `steps` back-to-back
+    solves (with the heavy-component engine when `split`), whose status,
+    node counts and colors must equal the reference's; plus the device
+    solve time from image H2D to results D2H."""
+    import numpy as np
+    import torch
+
+    import workload
+    from workload.configs import CONFIGS
+    w = CONFIGS[cfg]
+    rects, skipped = workload.generate(w.n_rects, w.side_nm, w.seed)
+    t0 = time.perf_counter()
+    g = mp.mpld_build_graph(rects, w.dmin_nm, w.split_len_nm)
+    t1 = time.perf_counter()
+    b = mp.Batch(ctx, g, w.k, w.budget, mp.MPLD_SIMPLIFY)
+    t2 = time.perf_counter()
+    b.solve(direct=True)
+    ref = b.result()
+    rc = ref.components
+
+    def same(r):
+        return bool(np.array_equal(r.components["status"], rc["status"])
+                    and np.array_equal(r.components["nodes"], rc["nodes"])
+                    and np.array_equal(r.colors, ref.colors))
+
+    b.solve(direct=True, split=split)
+    ok = same(b.result())
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    for _ in range(steps):
+        b.solve(direct=True, split=split, timed=False)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - ts
+    ok = ok and same(b.result())
+    b.solve(direct=True, split=split, roundtrip=True)
+    torch.cuda.synchronize()
+    info = b.info()
+    ok = ok and same(b.result())
+    b.close()
+    nodes = int(rc["nodes"].sum())
+    return {"workload": f"config {cfg}: {w.name} ({w.n_rects} rectangles, "
+                        f"{w.side_nm // 1000} um window, d_min {w.dmin_nm} nm, k={w.k}, "
+                        f"split {w.split_len_nm} nm, budget {w.budget}, seed {w.seed})",
+            "placed": int(len(rects)), "skipped": int(skipped), "layout_nodes": g.num_nodes,
+            "conflict_edges": int(len(g.ce)), "components": len(rc),
+            "max_component": int(rc["size"].max()) if len(rc) else 0,
+            "tiers": {"wave": info["num_wave"], "lds": info["num_lds"],
+                      "global": info["num_global"], "device": info["num_device"]},
+            "search_nodes_per_step": nodes, "steps": steps, "heavy_engine": split,
+            "ms_per_step": 1000 * wall / steps, "search_nodes_per_s": nodes * steps / wall,
+            "components_per_s": len(rc) * steps / wall,
+            "device_solve_ms": info["last_roundtrip_ms"],
+            "statuses": {"feasible": int(np.sum(rc["status"] == 0)),
+                         "infeasible": int(np.sum(rc["status"] == 1)),
+                         "budget": int(np.sum(rc["status"] == 2))},
+            "frontend_ms": {"graph": 1000 * (t1 - t0), "simplify_pack_upload": 1000 * (t2 - t1)},
+            "same_as_sequential": ok}
 
 
 def serve_leg(mp, ctx, count: int, seed: int, graph_builders: int = 0,
@@ -289,6 +364,10 @@ def main() -> int:
                     help="batched solve: replay the captured HIP graph or launch directly")
     ap.add_argument("--kernel-reps", type=int, default=50,
                     help="direct launches timed one by one for the kernel duration")
+    ap.add_argument("--other-config-steps", type=int, default=20,
+                    help="steps of the config 2 (heavy engine) and config 3 legs (0: skip)")
+    ap.add_argument("--roundtrip-reps", type=int, default=20,
+                    help="solves timed from image H2D to results D2H")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-latency-probe", action="store_true")
@@ -298,7 +377,7 @@ def main() -> int:
                     help="comma-separated probe names to run (default: all)")
     ap.add_argument("--no-mark", action="store_true",
                     help="skip the conflict-marking leg (MPLD_MARK_CONFLICTS on the same workload)")
-    ap.add_argument("--serve-requests", type=int, default=1000,
+    ap.add_argument("--serve-requests", type=int, default=10000,
                     help="serving leg: requests of the serving workload (0 = skip)")
     ap.add_argument("--stitch-steps", type=int, default=5,
                     help="steps of the stitch-order leg on the stitch workload (0: skip)")
@@ -324,13 +403,19 @@ def main() -> int:
 
     if args.split_only:
         ctx = mp.Context(0)
-        print(json.dumps({"device_split": split_leg(mp, ctx)}), flush=True)
+        out = {"device_split": split_leg(mp, ctx)}
+        torch.cuda.synchronize()
+        ctx.close()
+        print(json.dumps(out), flush=True)
         return 0
 
     if args.probe_only:
         ctx = mp.Context(0)
         names = [x for x in args.probes.split(",") if x]
-        print(json.dumps({"latency_probe": latency_probe(mp, ctx, names=names)}), flush=True)
+        out = {"latency_probe": latency_probe(mp, ctx, names=names)}
+        torch.cuda.synchronize()
+        ctx.close()
+        print(json.dumps(out), flush=True)
         return 0
 
     w = CONFIGS[args.config]
@@ -401,6 +486,22 @@ def main() -> int:
     kernel_ms = dev_ms / args.steps if one_kernel else single_ms
     tune = b.get_tune()
     assert info["launches"] >= 1
+
+    # ---- device solve time: the packed image copied from page-locked host
+    # memory to the device, the search, records and colors copied back,
+    # between two HIP events (MPLD_ROUNDTRIP); then the result is checked
+    rts = []
+    for _ in range(args.roundtrip_reps):
+        b.solve(direct=True, split=split, roundtrip=True)
+        torch.cuda.synchronize()
+        rts.append(b.info()["last_roundtrip_ms"])
+    res_rt = b.result()
+    roundtrip = {"ms_median": float(np.median(rts)), "ms_min": float(np.min(rts)),
+                 "reps": len(rts), "image_bytes": info["image_bytes"],
+                 "search_nodes_per_s": total_nodes / (float(np.median(rts)) * 1e-3),
+                 "same_result": bool(np.array_equal(res_rt.components["nodes"], comps["nodes"])
+                                     and np.array_equal(res_rt.colors, res.colors))}
+    log(f"device solve (H2D, search, D2H): {roundtrip['ms_median']:.4f} ms median")
 
     # ---- plain solver: one launch per component on the same batch
     b.solve(plain=True)
@@ -476,13 +577,25 @@ def main() -> int:
         dst.copy_(src)
         torch.cuda.synchronize()
 
-    # ---- roofline of the dominant kernel.  Algorithmic HBM bytes per launch:
-    # per component a 32 B descriptor, a 4 B queue entry and a 24 B record;
-    # per node its neighbour mask (8 B, register tier) or adjacency words
-    # (LDS tiers) and its 1 B color.
-    algo_bytes = (ncomp * (32 + 4 + 24) + info["core_nodes"] * 1
-                  + 8 * int(np.sum(comps["size"][comps["size"] <= 64]))
-                  + 4 * int(np.sum((comps["size"] + 2 + 2 * comps["num_edges"])[comps["size"] > 64])))
+    # ---- roofline of the dominant kernel.  Algorithmic bytes per search
+    # node of the bitset search: the k + 1 planes of W = ceil(n / 64) words
+    # read by the count, 3 d_w words for the cover, the removed words kept
+    # and the uncover (d_w = words that N(v) touches, min(W, mean degree)),
+    # 2 words of stack push / pop: B_node = 8 ((k + 1) W + 3 d_w + 2); per
+    # launch the sum over components of nodes x B_node.  The image bytes
+    # (per component a 32 B descriptor, a 4 B queue entry and a 24 B record;
+    # per node its neighbour mask or adjacency words and its 1 B color) are
+    # reported beside it.
+    def node_bytes(n, m):
+        wds = (n + 63) // 64
+        dw = min(wds, max(1, -(-2 * m // max(n, 1))))
+        return 8 * ((w.k + 1) * wds + 3 * dw + 2)
+
+    algo_bytes = int(sum(int(c["nodes"]) * node_bytes(int(c["size"]), int(c["num_edges"]))
+                         for c in comps))
+    image_bytes = (ncomp * (32 + 4 + 24) + info["core_nodes"] * 1
+                   + 8 * int(np.sum(comps["size"][comps["size"] <= 64]))
+                   + 4 * int(np.sum((comps["size"] + 2 + 2 * comps["num_edges"])[comps["size"] > 64])))
     achieved = algo_bytes / (kernel_ms * 1e-3) / 1e9
     traffic = None
     issue = None
@@ -504,12 +617,10 @@ def main() -> int:
                 "single_solve_us": round(single_ms * 1000.0, 3),
                 "issue": issue,
                 "algorithmic_bytes_per_launch": algo_bytes,
+                "bytes_per_search_node_w1": node_bytes(2, 1),
+                "image_bytes_per_launch": image_bytes,
+                "image_GBps": round(image_bytes / (kernel_ms * 1e-3) / 1e9, 3),
                 "ns_per_search_node_per_wave": None}
-    # state-bytes model per search node (k+1 bitset planes scanned, cover /
-    # uncover of the touched words, stack push/pop): 8 * ((k + 1) * W + 5)
-    state_bytes = 8 * ((w.k + 1) * 1 + 5) * total_nodes
-    roofline["state_bytes_per_launch"] = state_bytes
-    roofline["state_GBps"] = round(state_bytes / (kernel_ms * 1e-3) / 1e9, 3)
     heavy = int(comps["nodes"].max()) if ncomp else 0
     if heavy:
         roofline["ns_per_search_node_per_wave"] = round(kernel_ms * 1e6 / heavy, 2)
@@ -538,6 +649,7 @@ def main() -> int:
                    "layout_nodes": g.num_nodes, "conflict_edges": int(len(g.ce))},
         "components_per_s": ncomp * args.steps / wall,
         "device_ms_per_step": dev_ms / args.steps,
+        "device_solve": roundtrip,
         "launch": args.launch,
         "split_heavy": args.split,
         "heavy_engine": ({"tune": {x: tune[x] for x in ("heavy_first_cap", "heavy_round_cap",
@@ -560,6 +672,13 @@ def main() -> int:
                      "budget": int(np.sum(comps["status"] == 2))},
         "stitches": res.stitches, "uncolored": res.uncolored,
     }
+    out["other_configs"] = {}
+    for cfg, split_c in ((2, True), (3, False)):
+        if cfg == args.config or not args.other_config_steps:
+            continue
+        log(f"config {cfg} leg")
+        out["other_configs"][f"config {cfg}"] = config_leg(mp, ctx, cfg, args.other_config_steps,
+                                                          split_c)
     log("device split leg")
     out["device_split"] = split_leg(mp, ctx)
     if not args.no_latency_probe:
@@ -572,9 +691,11 @@ def main() -> int:
         out["p99_latency_ms"] = out["serving"]["p99_ms"]
     if not args.no_cpu_baseline:
         log("timing the CPU oracle")
-        out["cpu_baseline"] = cpu_baseline(rects, w, args.cpu_seconds)
-        out["cpu_baseline"]["host"] = {"nproc": os.cpu_count()}
-        out["cpu_all_cores"] = cpu_all_cores(rects, w, args.cpu_seconds / 2)
+        out["cpu_baseline"], out["cpu_all_cores"] = cpu_legs(rects, w, args.cpu_seconds, comps)
+        if not out["cpu_baseline"]["agree"]:
+            log("ERROR: the oracle's per-component status / node counts differ from the GPU batch")
+            print(json.dumps(out), flush=True)
+            return 1
     b.close()
     ctx.close()
     print(json.dumps(out), flush=True)

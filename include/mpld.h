@@ -26,9 +26,9 @@
  *   - sub-graphs: connected components of the remaining nodes, ordered by
  *     smallest id; local index = BFS order from that node (neighbours in
  *     ascending id);
- *   - column choice (Algorithm 1 "only one related row or in BFS order"):
- *     the uncovered primary column with the fewest rows, lowest local index
- *     on ties; rows tried in ascending color; the first exact cover ends the
+ *   - column choice (Algorithm 1, column selection: a column with a single
+ *     related row first, else BFS order): the uncovered primary column with
+ *     the fewest rows, lowest local index on ties; rows tried in ascending color; the first exact cover ends the
  *     search; an empty column is a dead end (no conflict-candidate marking);
  *   - a search node is one entry into the search that passes the budget
  *     test (budget tested before counting), so nodes <= budget always and
@@ -61,7 +61,7 @@
 extern "C" {
 #endif
 
-#define MPLD_ABI_VERSION 2u
+#define MPLD_ABI_VERSION 3u
 #define MPLD_MAX_K 8
 
 enum {
@@ -116,7 +116,7 @@ enum {
                                   counted on the colors.  Decompose, batches
                                   and mpld_solve_components only (a server
                                   rejects it with MPLD_E_UNSUPPORTED). */
-  MPLD_STITCH_ORDER = 1u << 11 /* stitch-aware row order (Eq. 1 counts a stitch
+  MPLD_STITCH_ORDER = 1u << 11, /* stitch-aware row order (Eq. 1 counts a stitch
                                   for each pair of split halves colored
                                   differently): when the chosen column's node
                                   has its stitch partner in the component and
@@ -127,6 +127,14 @@ enum {
                                   forced LDS/global/device tier give
                                   MPLD_E_UNSUPPORTED; disables
                                   MPLD_SPLIT_HEAVY; not with a server. */
+  MPLD_ROUNDTRIP = 1u << 12    /* mpld_batch_solve: the whole device solve -
+                                  copy of the packed image from page-locked
+                                  host memory to the device, the search, copy
+                                  of the records and local colors back to
+                                  page-locked host memory - enqueued between
+                                  two HIP events; mpld_batch_info's
+                                  last_roundtrip_ms reads their distance.  The
+                                  result is the same as without the flag. */
 };
 
 typedef struct { int32_t x0, y0, x1, y1; } mpld_rect;  /* nm, closed box */
@@ -286,6 +294,10 @@ typedef struct {
   int32_t split_rounds;      /* ... task rounds                              */
   int32_t split_tasks;       /* ... subtree tasks run                        */
   int32_t split_reruns;      /* ... components re-run sequentially (budget)  */
+  float last_roundtrip_ms;   /* last MPLD_ROUNDTRIP solve: first byte of the
+                                image copied to the device .. last result byte
+                                back on the host (0 before)                  */
+  int32_t reserved;
 } mpld_batch_info;
 int32_t mpld_batch_get_info(mpld_batch* b, mpld_batch_info* info);
 void mpld_batch_free(mpld_batch* b);

@@ -9,7 +9,10 @@ the binding raises, and without a gfx950 device the context call fails.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
+import sys
+import weakref
 from dataclasses import dataclass
 
 import numpy as np
@@ -119,6 +122,38 @@ def _owned_graph(h) -> Graph:
         _lib.mpld_owned_graph_free(h)
 
 
+# ---- lifetimes ----------------------------------------------------------
+# Servers, batches and contexts still open when the interpreter exits are
+# closed by an exit hook, in that order (a server uses its context; a
+# batch's and a context's device memory goes back through the torch
+# allocator callback), while torch is still alive.  A destructor that runs
+# during interpreter finalisation does nothing: calling the library then
+# could call back into a torn-down torch.
+
+_LIVE: dict = {0: weakref.WeakSet(), 1: weakref.WeakSet(), 2: weakref.WeakSet()}
+_RANK = {"Server": 0, "Batch": 1, "Context": 2}
+
+
+def _register(obj) -> None:
+    _LIVE[_RANK[type(obj).__name__]].add(obj)
+
+
+def _close_all() -> None:
+    for rank in (0, 1, 2):
+        for obj in list(_LIVE[rank]):
+            try:
+                obj.close()
+            except Exception:
+                pass
+
+
+atexit.register(_close_all)
+
+
+def _finalizing() -> bool:
+    return sys.is_finalizing()
+
+
 # ---- context ------------------------------------------------------------
 
 class _TorchAllocator:
@@ -165,6 +200,7 @@ class Context:
             handle = ctypes.c_void_p(self.stream.cuda_stream)
         _check(_lib.mpld_context_create(device, alloc_ptr, handle, ctypes.byref(self.handle)),
                "mpld_context_create")
+        _register(self)
 
     def close(self):
         if self.handle:
@@ -172,6 +208,8 @@ class Context:
             self.handle = ctypes.c_void_p()
 
     def __del__(self):
+        if _finalizing():
+            return
         try:
             self.close()
         except Exception:
@@ -245,11 +283,13 @@ class Batch:
         view = g.view()
         _check(_lib.mpld_batch_create(ctx.handle, ctypes.byref(view), ctypes.byref(opt),
                                       ctypes.byref(self.handle)), "mpld_batch_create")
+        _register(self)
 
     def solve(self, plain: bool = False, direct: bool = False, split: bool = False,
-              timed: bool = True) -> None:
+              timed: bool = True, roundtrip: bool = False) -> None:
         flags = ((MPLD_PLAIN if plain else 0) | (_ffi.MPLD_DIRECT if direct else 0)
-                 | (MPLD_SPLIT_HEAVY if split else 0) | (0 if timed else _ffi.MPLD_UNTIMED))
+                 | (MPLD_SPLIT_HEAVY if split else 0) | (0 if timed else _ffi.MPLD_UNTIMED)
+                 | (_ffi.MPLD_ROUNDTRIP if roundtrip else 0))
         _check(_lib.mpld_batch_solve(self.handle, flags), "mpld_batch_solve")
 
     def result(self) -> Result:
@@ -287,6 +327,8 @@ class Batch:
             self.handle = ctypes.c_void_p()
 
     def __del__(self):
+        if _finalizing():
+            return
         try:
             self.close()
         except Exception:
@@ -366,6 +408,7 @@ class Server:
                                      0 if device_split else -1, 0)
         _check(_lib.mpld_server_create(ctx.handle, ctypes.byref(o), ctypes.byref(self.handle)),
                "mpld_server_create")
+        _register(self)
 
     def submit_layout(self, rects: np.ndarray, dmin_nm: int, split_len_nm: int, k: int,
                       budget: int, flags: int = MPLD_SIMPLIFY) -> int:
@@ -412,6 +455,8 @@ class Server:
             self.handle = ctypes.c_void_p()
 
     def __del__(self):
+        if _finalizing():
+            return
         try:
             self.close()
         except Exception:

@@ -30,6 +30,7 @@ MPLD_SPLIT_HEAVY = 1 << 8
 MPLD_UNTIMED = 1 << 9
 MPLD_MARK_CONFLICTS = 1 << 10
 MPLD_STITCH_ORDER = 1 << 11
+MPLD_ROUNDTRIP = 1 << 12
 
 c_i32, c_i64, c_u32, c_u64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint64
 vp = ctypes.c_void_p
@@ -73,7 +74,7 @@ class mpld_batch_info(ctypes.Structure):
                 ("image_bytes", c_i64), ("core_edges", c_i64), ("last_search_ms", ctypes.c_float),
                 ("last_total_ms", ctypes.c_float), ("launches", c_i32), ("num_device", c_i32),
                 ("heavy_components", c_i32), ("split_rounds", c_i32), ("split_tasks", c_i32),
-                ("split_reruns", c_i32)]
+                ("split_reruns", c_i32), ("last_roundtrip_ms", ctypes.c_float), ("reserved", c_i32)]
 
 
 class mpld_tune(ctypes.Structure):

@@ -256,7 +256,11 @@ int32_t mpld_batch_solve(mpld_batch* b, uint32_t flags) {
     if (!b) fail(MPLD_E_INVALID, "batch is NULL");
     use_device(b->ctx);
     const uint32_t how = MPLD_PLAIN | MPLD_DIRECT;
-    device_solve(b->db, (b->opt.flags & ~how) | (flags & (how | MPLD_SPLIT_HEAVY | MPLD_UNTIMED)));
+    const uint32_t f = (b->opt.flags & ~how) | (flags & (how | MPLD_SPLIT_HEAVY | MPLD_UNTIMED));
+    if (flags & MPLD_ROUNDTRIP)
+      device_roundtrip(b->db, b->im, f);
+    else
+      device_solve(b->db, f);
     b->solved = true;
   });
 }
@@ -300,6 +304,7 @@ int32_t mpld_batch_get_info(mpld_batch* b, mpld_batch_info* info) {
     info->split_rounds = (int32_t)b->db.sp_rounds;
     info->split_tasks = (int32_t)b->db.sp_tasks_run;
     info->split_reruns = (int32_t)b->db.sp_reruns;
+    info->last_roundtrip_ms = b->db.last_roundtrip_ms;
   });
 }
 

@@ -6,6 +6,7 @@
 // deterministic, so any difference is a bug and fails the call).  The best
 // is adopted and, with a cache path, appended as one JSON line keyed by the
 // device and the batch's shape.
+#include <new>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -209,6 +210,12 @@ int32_t mpld_batch_set_tune(mpld_batch* b, const mpld_tune* in) {
   } catch (const Error& e) {
     set_last_error(e.what);
     return e.code;
+  } catch (const std::bad_alloc&) {
+    set_last_error("host allocation failed");
+    return MPLD_E_NOMEM;
+  } catch (...) {
+    set_last_error("unexpected exception");
+    return MPLD_E_INTERNAL;
   }
 }
 
@@ -300,6 +307,12 @@ int32_t mpld_batch_autotune(mpld_batch* b, int32_t reps, const char* cache_path,
   } catch (const Error& e) {
     set_last_error(e.what);
     return e.code;
+  } catch (const std::bad_alloc&) {
+    set_last_error("host allocation failed");
+    return MPLD_E_NOMEM;
+  } catch (...) {
+    set_last_error("unexpected exception");
+    return MPLD_E_INTERNAL;
   }
 }
 

@@ -121,6 +121,8 @@ void image_finish(Image& im, int order) {
 
 DeviceBatch::~DeviceBatch() {
   if (graph) hipGraphExecDestroy(graph);
+  for (hipEvent_t e : rt_ev)
+    if (e) (void)hipEventDestroy(e);
 }
 
 static int blocks_for_lds(mpld_context* ctx, int lds_bytes) {
@@ -239,6 +241,48 @@ void device_upload(mpld_context* ctx, const Image& im, DeviceBatch& db, const Tu
   if (db.n_dev)
     check_hip(hipMemsetAsync(db.dev_keys.p, 0xff, sizeof(uint64_t) * 4, s), "clear keys");
   check_hip(hipStreamSynchronize(s), "upload");
+  db.host_items = std::move(items);
+  db.rt_ready = false;
+}
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+void device_roundtrip(DeviceBatch& db, const Image& im, uint32_t flags) {
+  mpld_context* ctx = db.ctx;
+  hipStream_t s = ctx->stream;
+  const size_t nd = sizeof(DevDesc) * db.host_desc.size(), ni = db.host_items.size(),
+               na = sizeof(uint32_t) * im.adj32.size();
+  const size_t nr = sizeof(DevRecord) * (size_t)db.num_comps, nc = (size_t)db.total_nodes;
+  if (!db.rt_ready) {
+    if (!db.rt_up.reserve(align256(nd) + align256(ni) + align256(na) + 256) ||
+        !db.rt_down.reserve(align256(nr) + align256(nc) + 256))
+      fail(MPLD_E_NOMEM, "page-locked staging of the round trip");
+    auto* up = db.rt_up.as<uint8_t>();
+    if (nd) std::memcpy(up, db.host_desc.data(), nd);
+    if (ni) std::memcpy(up + align256(nd), db.host_items.data(), ni);
+    if (na) std::memcpy(up + align256(nd) + align256(ni), im.adj32.data(), na);
+    for (hipEvent_t& e : db.rt_ev)
+      if (!e) check_hip(hipEventCreate(&e), "round-trip event");
+    db.rt_ready = true;
+  }
+  const auto* up = db.rt_up.as<uint8_t>();
+  auto* down = db.rt_down.as<uint8_t>();
+  db.rt_timed = false;
+  check_hip(hipEventRecord(db.rt_ev[0], s), "event");
+  if (nd) check_hip(hipMemcpyAsync(db.desc.p, up, nd, hipMemcpyHostToDevice, s), "upload descriptors");
+  if (ni)
+    check_hip(hipMemcpyAsync(db.regitems.p, up + align256(nd), ni, hipMemcpyHostToDevice, s),
+              "upload register items");
+  if (na)
+    check_hip(hipMemcpyAsync(db.adj32.p, up + align256(nd) + align256(ni), na,
+                             hipMemcpyHostToDevice, s), "upload adjacency");
+  device_solve(db, flags);
+  if (nr) check_hip(hipMemcpyAsync(down, db.recs.p, nr, hipMemcpyDeviceToHost, s), "download records");
+  if (nc)
+    check_hip(hipMemcpyAsync(down + align256(nr), db.colors.p, nc, hipMemcpyDeviceToHost, s),
+              "download colors");
+  check_hip(hipEventRecord(db.rt_ev[1], s), "event");
+  db.rt_timed = true;
 }
 
 static void enqueue_batched(DeviceBatch& db, bool trace, uint64_t cap, hipStream_t s) {
@@ -854,6 +898,15 @@ void device_solve(DeviceBatch& db, uint32_t flags) {
 }
 
 bool device_time(DeviceBatch& db) {
+  if (db.rt_timed) {
+    float ms = 0.f;
+    const hipError_t e = hipEventElapsedTime(&ms, db.rt_ev[0], db.rt_ev[1]);
+    if (e != hipErrorNotReady) {
+      check_hip(e, "event time");
+      db.last_roundtrip_ms = ms;
+      db.rt_timed = false;
+    }
+  }
   if (!db.timed) return false;
   float ms = 0.f;
   const hipError_t e = hipEventElapsedTime(&ms, db.ctx->ev[0], db.ctx->ev[1]);

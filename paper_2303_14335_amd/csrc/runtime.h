@@ -243,6 +243,13 @@ struct DeviceBatch {
   hipGraphExec_t graph = nullptr;
   uint32_t graph_flags = 0xffffffffu;
   bool timed = false;               // events of the last solve not read yet
+  std::vector<uint8_t> host_items;  // register-tier items as uploaded
+  // MPLD_ROUNDTRIP: page-locked copies of the image and the results, and
+  // the two events around the whole solve
+  PinnedBuf rt_up, rt_down;
+  bool rt_ready = false, rt_timed = false;
+  hipEvent_t rt_ev[2] = {nullptr, nullptr};
+  float last_roundtrip_ms = 0.f;
   std::vector<int32_t> host_queue;  // component ids in launch order (all tiers)
   std::vector<DevDesc> host_desc;   // descriptors in launch order
   ~DeviceBatch();
@@ -258,6 +265,10 @@ void assemble_result(const Graph& g, const Split& s, const Image& im, const mpld
                      const std::vector<DevRecord>& recs, const std::vector<int8_t>& lcol,
                      mpld_result* r);
 
+// The whole device solve: image H2D from page-locked memory, the search
+// (device_solve with `flags`), records and local colors D2H, between two
+// events (read by device_time into last_roundtrip_ms).
+void device_roundtrip(DeviceBatch& db, const Image& im, uint32_t flags);
 // Reads the last solve's event time if the stream has passed it.
 bool device_time(DeviceBatch& db);
 // Waits, then copies records and colors back.

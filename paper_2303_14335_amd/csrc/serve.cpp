@@ -202,6 +202,10 @@ void mpld_server::finish(Request* r) {
       r->error = e.code;
       r->error_text = e.what;
       r->result.reset();
+    } catch (...) {
+      r->error = MPLD_E_NOMEM;
+      r->error_text = "host allocation failed while assembling the result";
+      r->result.reset();
     }
   }
   // free the bulky parts early; the result and records are all that is kept
@@ -506,16 +510,28 @@ void mpld_server::scheduler_loop() {
       if (waited) ++stats.admission_waits;
     }
     if (admitted.empty() && active.empty()) continue;
+    int32_t err = MPLD_OK;
+    std::string err_text;
     try {
       for (Request* r : admitted) upload(r);
       tick(admitted);
     } catch (const Error& e) {
+      err = e.code;
+      err_text = e.what;
+    } catch (const std::bad_alloc&) {
+      err = MPLD_E_NOMEM;
+      err_text = "host allocation failed in the scheduler";
+    } catch (...) {
+      err = MPLD_E_INTERNAL;
+      err_text = "unexpected exception in the scheduler";
+    }
+    if (err != MPLD_OK) {
       // a device error ends the server: every resident and waiting request fails
       std::lock_guard<std::mutex> lk(mu);
       for (auto& kv : pending) {
         Request* r = kv.second;
-        r->error = e.code;
-        r->error_text = e.what;
+        r->error = err;
+        r->error_text = err_text;
       }
       stop = true;
       cv_work.notify_all();

@@ -37,7 +37,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_abi_version_and_error_strings():
     import paper_2303_14335_amd as mp
-    assert mp.mpld_abi_version() == 2
+    assert mp.mpld_abi_version() == 3
     lib = mp._lib
     for code in (0, -1, -2, -3, -4, -5, -6, -7):
         assert lib.mpld_error_string(code)
@@ -58,6 +58,22 @@ def test_front_end_graph_matches_oracle(n, side, dmin, split, seed):
     assert g.num_nodes == ref.num_nodes
     assert np.array_equal(g.ce, ref.ce)
     assert np.array_equal(g.se, ref.se)
+
+
+@pytest.mark.parametrize("cfg", [1, 2, 3])
+def test_front_end_graph_matches_oracle_full_configs(cfg):
+    """The host graph builder (several scan threads) against the oracle's
+    own builder at the full sizes of the 200k-rect and 40k-rect workloads."""
+    import paper_2303_14335_amd as mp
+    from workload.configs import CONFIGS
+    w = CONFIGS[cfg]
+    rects, _ = workload.generate(w.n_rects, w.side_nm, w.seed)
+    g = mp.mpld_build_graph(rects, w.dmin_nm, w.split_len_nm)
+    ref = oracle.build_graph(rects, w.dmin_nm, w.split_len_nm)
+    assert g.num_nodes == ref.num_nodes
+    assert np.array_equal(g.ce, ref.ce)
+    assert np.array_equal(g.se, ref.se)
+    assert len(ref.ce) > 100000
 
 
 def test_front_end_rejects_bad_boxes():

@@ -41,3 +41,27 @@ def test_issue_fractions_committed_summary():
     got = bench.issue_fractions(p, 4.4e-3)
     assert got is not None
     assert 0.0 < got["salu_frac"] < 1.0 and 0.0 < got["valu_frac"] < 1.0
+
+
+def test_cpu_legs_agree_with_the_batch_and_flag_a_mismatch():
+    """The CPU legs reproduce the per-component status and node counts they
+    are given (here the oracle's own decomposition of the small workload) and
+    report agree = False when one node count differs."""
+    import numpy as np
+
+    import oracle
+    import workload
+    from workload.configs import CONFIGS
+    w = CONFIGS[0]
+    rects, _ = workload.generate(w.n_rects, w.side_nm, w.seed)
+    ref = oracle.decompose(oracle.build_graph(rects, w.dmin_nm, w.split_len_nm), w.k, w.budget)
+    comps = ref.comps
+    one, alln = bench.cpu_legs(rects, w, 0.05, comps)
+    assert one["agree"] and alln["agree"]
+    assert one["cores"] == 1 and alln["cores"] >= 1
+    assert one["value"] > 0 and alln["value"] > 0
+    bad = comps.copy()
+    bad["nodes"][0] += 1
+    one, _ = bench.cpu_legs(rects, w, 0.05, bad)
+    assert not one["agree"]
+    assert np.array_equal(comps["nodes"], ref.comps["nodes"])

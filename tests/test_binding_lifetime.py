@@ -1,0 +1,54 @@
+"""CPU test of the binding's teardown order: servers, then batches, then
+contexts still open at exit are closed by the exit hook while torch is
+alive, and destructors do nothing during interpreter finalisation (where a
+library call could reach a torn-down torch allocator)."""
+import paper_2303_14335_amd as mp
+
+
+class _FakeLib:
+    def __init__(self):
+        self.calls = []
+
+    def mpld_server_destroy(self, h):
+        self.calls.append(("server", h.value))
+
+    def mpld_batch_free(self, h):
+        self.calls.append(("batch", h.value))
+
+    def mpld_context_destroy(self, h):
+        self.calls.append(("context", h.value))
+
+
+def _fake(cls, value):
+    import ctypes
+    obj = object.__new__(cls)
+    obj.handle = ctypes.c_void_p(value)
+    mp._register(obj)
+    return obj
+
+
+def test_exit_hook_closes_servers_then_batches_then_contexts(monkeypatch):
+    fake = _FakeLib()
+    monkeypatch.setattr(mp, "_lib", fake)
+    c = _fake(mp.Context, 1)
+    b = _fake(mp.Batch, 2)
+    s = _fake(mp.Server, 3)
+    mp._close_all()
+    kinds = [k for k, _ in fake.calls]
+    assert kinds == ["server", "batch", "context"], fake.calls
+    # closed objects are not closed again
+    mp._close_all()
+    assert len(fake.calls) == 3
+    del c, b, s
+
+
+def test_destructor_is_inert_during_finalisation(monkeypatch):
+    fake = _FakeLib()
+    monkeypatch.setattr(mp, "_lib", fake)
+    monkeypatch.setattr(mp, "_finalizing", lambda: True)
+    c = _fake(mp.Context, 7)
+    c.__del__()
+    assert fake.calls == []
+    monkeypatch.setattr(mp, "_finalizing", lambda: False)
+    c.__del__()
+    assert fake.calls == [("context", 7)]

@@ -36,6 +36,18 @@ def compare_decomposition(got, ref):
                                                              ref.uncolored)
 
 
+def both_graphs(rects, w):
+    """The product's layout graph and the oracle's own, built independently
+    from the same rectangles; they must be equal."""
+    import paper_2303_14335_amd as mp
+    g = mp.mpld_build_graph(rects, w.dmin_nm, w.split_len_nm)
+    og = oracle.build_graph(rects, w.dmin_nm, w.split_len_nm)
+    assert g.num_nodes == og.num_nodes
+    assert np.array_equal(g.ce, og.ce)
+    assert np.array_equal(g.se, og.se)
+    return g, og
+
+
 def graph_of(cfg, n_rects=None):
     w = CONFIGS[cfg]
     rects, _ = workload.generate(n_rects or w.n_rects, w.side_nm, w.seed)
@@ -47,8 +59,8 @@ def test_config_parity(ctx, cfg):
     import paper_2303_14335_amd as mp
     w, rects = graph_of(cfg)
     say("config", cfg, w.name)
-    g = mp.mpld_build_graph(rects, w.dmin_nm, w.split_len_nm)
-    ref = oracle.decompose(oracle.Graph(g.num_nodes, g.ce, g.se), w.k, w.budget)
+    g, og = both_graphs(rects, w)
+    ref = oracle.decompose(og, w.k, w.budget)
     got = mp.mpld_decompose(ctx, g, w.k, w.budget, SIMPLIFY | TRACE)
     compare_decomposition(got, ref)
 
@@ -57,8 +69,8 @@ def test_config2_parity_stitches(ctx):
     import paper_2303_14335_amd as mp
     w, rects = graph_of(2)
     say("config 2", w.name)
-    g = mp.mpld_build_graph(rects, w.dmin_nm, w.split_len_nm)
-    ref = oracle.decompose(oracle.Graph(g.num_nodes, g.ce, g.se), w.k, w.budget)
+    g, og = both_graphs(rects, w)
+    ref = oracle.decompose(og, w.k, w.budget)
     got = mp.mpld_decompose(ctx, g, w.k, w.budget, SIMPLIFY | TRACE)
     compare_decomposition(got, ref)
     assert got.stitches > 0
@@ -68,8 +80,8 @@ def test_config3_giant_parity(ctx):
     import paper_2303_14335_amd as mp
     w, rects = graph_of(3)
     say("config 3", w.name)
-    g = mp.mpld_build_graph(rects, w.dmin_nm, w.split_len_nm)
-    ref = oracle.decompose(oracle.Graph(g.num_nodes, g.ce, g.se), w.k, w.budget)
+    g, og = both_graphs(rects, w)
+    ref = oracle.decompose(og, w.k, w.budget)
     got = mp.mpld_decompose(ctx, g, w.k, w.budget, SIMPLIFY | TRACE)
     compare_decomposition(got, ref)
     assert got.components["size"].max() > 30000
@@ -118,7 +130,7 @@ def test_lane_and_tier_boundaries(ctx):
         comps.append((n, cycle(n)))
     say("boundary sizes")
     for flags in (0, FORCE["lds"], FORCE["global"]):
-        solve_both(ctx, [c for c in comps if c[0] <= 64 or flags != 0 or True], 3, 50000, flags)
+        solve_both(ctx, comps, 3, 50000, flags)
 
 
 def test_budget_sweep(ctx):
@@ -128,6 +140,17 @@ def test_budget_sweep(ctx):
     for b in list(range(1, 40)) + [100, 1000]:
         solve_both(ctx, comps, 3, b, 0)
         solve_both(ctx, comps, 3, b, FORCE["lds"])
+
+
+def test_budget_sweep_device_tier(ctx):
+    """Budget cuts on the device-wide tier (one cooperative launch per
+    component): status, node count, hash and depth at every budget."""
+    rng = np.random.default_rng(19)
+    comps = [(int(n), random_graph(rng, int(n), 0.42)) for n in (9, 12, 14)]
+    comps.append((90, random_graph(rng, 90, 4.6 / 90)))
+    say("budget sweep, device-wide tier")
+    for b in list(range(1, 25)) + [40, 100, 1000]:
+        solve_both(ctx, comps, 3, b, FORCE["device"])
 
 
 def test_larger_components_lds_tiers(ctx):
@@ -167,8 +190,8 @@ def test_config3_giant_device_tier(ctx):
     import paper_2303_14335_amd as mp
     w, rects = graph_of(3)
     say("config 3 on the device-wide tier")
-    g = mp.mpld_build_graph(rects, w.dmin_nm, w.split_len_nm)
-    ref = oracle.decompose(oracle.Graph(g.num_nodes, g.ce, g.se), w.k, w.budget)
+    g, og = both_graphs(rects, w)
+    ref = oracle.decompose(og, w.k, w.budget)
     got = mp.mpld_decompose(ctx, g, w.k, w.budget, SIMPLIFY | TRACE | FORCE["device"])
     compare_decomposition(got, ref)
 
@@ -248,6 +271,71 @@ def test_invalid_arguments(ctx):
     assert e.value.code == -7
 
 
+def test_product_validation_rejects_bad_graphs(ctx):
+    """The library's own validation of a layout graph (no oracle involved):
+    self loops, duplicate pairs in either orientation, a pair that is both a
+    conflict and a stitch pair, a node in two stitch pairs, ids out of range
+    and a negative node count are MPLD_E_INVALID, through the one-shot call,
+    a batch and a server."""
+    import paper_2303_14335_amd as mp
+    say("product validation")
+    z = np.zeros((0, 2), np.int32)
+    bad = [
+        mp.Graph(3, np.array([[1, 1]], np.int32), z),                       # self loop
+        mp.Graph(3, np.array([[0, 1], [0, 1]], np.int32), z),               # duplicate
+        mp.Graph(3, np.array([[0, 1], [1, 0]], np.int32), z),               # duplicate, reversed
+        mp.Graph(4, np.array([[0, 1]], np.int32), np.array([[1, 0]], np.int32)),  # CE and SE
+        mp.Graph(4, np.array([[0, 2]], np.int32), np.array([[0, 1], [0, 3]], np.int32)),  # two SE
+        mp.Graph(4, np.array([[0, 2]], np.int32), np.array([[2, 2]], np.int32)),  # SE self loop
+        mp.Graph(3, np.array([[0, -1]], np.int32), z),                      # negative id
+        mp.Graph(3, np.array([[0, 1]], np.int32), np.array([[0, 3]], np.int32)),  # SE out of range
+    ]
+    for i, g in enumerate(bad):
+        with pytest.raises(mp.MpldError) as e:
+            mp.mpld_decompose(ctx, g, 3, 100, SIMPLIFY)
+        assert e.value.code == -1, i
+        with pytest.raises(mp.MpldError) as e:
+            mp.Batch(ctx, g, 3, 100, SIMPLIFY)
+        assert e.value.code == -1, i
+    srv = mp.Server(ctx)
+    for i, g in enumerate(bad):
+        t = srv.submit(g, 3, 100)
+        with pytest.raises(mp.MpldError) as e:
+            srv.wait(t, 60_000_000)
+        assert e.value.code == -1, i
+    srv.close()
+    # a valid graph still works after the rejections
+    ok = mp.Graph(4, np.array([[0, 2], [1, 2]], np.int32), np.array([[0, 1]], np.int32))
+    got = mp.mpld_decompose(ctx, ok, 3, 100, SIMPLIFY | TRACE)
+    ref = oracle.decompose(oracle.Graph(4, ok.ce, ok.se), 3, 100)
+    compare_decomposition(got, ref)
+
+
+def test_roundtrip_solve_equals_plain_solve(ctx):
+    """MPLD_ROUNDTRIP (image copied up from page-locked memory, search,
+    results copied down, between events) gives the ordinary solve's result
+    and a positive device solve time."""
+    import paper_2303_14335_amd as mp
+    w, rects = graph_of(2, 40000)
+    say("round-trip solve, 40k rects of config 2")
+    g = mp.mpld_build_graph(rects, w.dmin_nm, w.split_len_nm)
+    b = mp.Batch(ctx, g, w.k, 20000, SIMPLIFY | TRACE)
+    b.solve(direct=True)
+    ref = b.result()
+    for rep in range(3):
+        b.solve(direct=True, roundtrip=True)
+        got = b.result()
+        for f in ref.components.dtype.names:
+            assert np.array_equal(got.components[f], ref.components[f]), (rep, f)
+        assert np.array_equal(got.colors, ref.colors)
+        assert b.info()["last_roundtrip_ms"] > 0
+    b.set_tune(use_graph=1)
+    b.solve(roundtrip=True)
+    got = b.result()
+    assert np.array_equal(got.colors, ref.colors)
+    b.close()
+
+
 def test_autotune_keeps_results_and_caches(ctx, tmp_path):
     import paper_2303_14335_amd as mp
     w, rects = graph_of(2, 30000)
@@ -312,8 +400,8 @@ def test_split_heavy_config2_matches_oracle(ctx):
     import paper_2303_14335_amd as mp
     w, rects = graph_of(2)
     say("config 2 with the heavy-component engine")
-    g = mp.mpld_build_graph(rects, w.dmin_nm, w.split_len_nm)
-    ref = oracle.decompose(oracle.Graph(g.num_nodes, g.ce, g.se), w.k, w.budget)
+    g, og = both_graphs(rects, w)
+    ref = oracle.decompose(og, w.k, w.budget)
     got = mp.mpld_decompose(ctx, g, w.k, w.budget, SIMPLIFY | SPLIT)
     for f in ("size", "status", "nodes", "depth_at_stop", "stitches", "first_node"):
         assert np.array_equal(got.components[f], ref.comps[f]), f
@@ -328,8 +416,8 @@ def test_split_heavy_engines_agree(ctx, device_rounds):
     import paper_2303_14335_amd as mp
     w, rects = graph_of(2)
     say("config 2, heavy engine with device rounds =", device_rounds)
-    g = mp.mpld_build_graph(rects, w.dmin_nm, w.split_len_nm)
-    ref = oracle.decompose(oracle.Graph(g.num_nodes, g.ce, g.se), w.k, w.budget)
+    g, og = both_graphs(rects, w)
+    ref = oracle.decompose(og, w.k, w.budget)
     b = mp.Batch(ctx, g, w.k, w.budget, SIMPLIFY)
     b.set_tune(heavy_device=device_rounds, heavy_first_cap=256, heavy_round_cap=128)
     for rep in range(2):
@@ -385,8 +473,8 @@ def test_config_parity_untraced(ctx, cfg):
     import paper_2303_14335_amd as mp
     w, rects = graph_of(cfg)
     say("config", cfg, w.name, "untraced")
-    g = mp.mpld_build_graph(rects, w.dmin_nm, w.split_len_nm)
-    ref = oracle.decompose(oracle.Graph(g.num_nodes, g.ce, g.se), w.k, w.budget)
+    g, og = both_graphs(rects, w)
+    ref = oracle.decompose(og, w.k, w.budget)
     got = mp.mpld_decompose(ctx, g, w.k, w.budget, SIMPLIFY)
     for f in ("size", "status", "nodes", "depth_at_stop", "stitches", "first_node", "num_edges"):
         assert np.array_equal(got.components[f], ref.comps[f]), f

@@ -29,6 +29,22 @@ def same(a, b):
     assert (a.stitches, a.conflicts, a.uncolored) == (b.stitches, b.conflicts, b.uncolored)
 
 
+def check_oracle(got, req, budget, flags):
+    """A served result against the oracle's own pipeline (its own graph
+    builder, simplification, search, recovery) on the request's rectangles."""
+    ref = oracle.decompose(oracle.build_graph(req["rects"], req["dmin"], req["split"]), req["k"],
+                           budget, simplify=bool(flags & SIMPLIFY))
+    assert np.array_equal(got.colors, ref.colors)
+    assert np.array_equal(got.component_of, ref.comp_of)
+    fields = ["size", "status", "nodes", "depth_at_stop", "stitches", "first_node", "num_edges"]
+    if flags & TRACE:
+        fields.append("trace_hash")
+    for f in fields:
+        assert np.array_equal(got.components[f], ref.comps[f]), f
+    assert (got.stitches, got.conflicts, got.uncolored) == (ref.stitches, ref.conflicts,
+                                                             ref.uncolored)
+
+
 def requests(count, seed, n_max=6000, k=3, dmin=80, split=0):
     t = workload.request_trace(seed, count, n_min=100, n_max=n_max)
     out = []
@@ -59,6 +75,7 @@ def test_mix_equals_alone(ctx, slice_nodes):
     for r, got in zip(reqs, results):
         assert got is not None
         same(got, alone(ctx, r, 10**6, SIMPLIFY | TRACE))
+        check_oracle(got, r, 10**6, SIMPLIFY | TRACE)
         assert got.total_us >= got.queue_us >= 0
 
 
@@ -83,6 +100,7 @@ def test_device_front_end_equals_alone(ctx, simplify, builders, device_split):
     assert sum(len(r["rects"]) >= 4096 for r in reqs) >= 5
     for r, got in zip(reqs, results):
         same(got, alone(ctx, r, 20000, flags))
+        check_oracle(got, r, 20000, flags)
 
 
 def test_stitched_k4_heavy_components_sliced(ctx):
@@ -97,11 +115,8 @@ def test_stitched_k4_heavy_components_sliced(ctx):
     srv.close()
     for r, got in zip(reqs, results):
         same(got, alone(ctx, r, 20000, SIMPLIFY))
+        check_oracle(got, r, 20000, SIMPLIFY)
     assert ticks > 5   # heavy components took several ticks
-    # and one of them against the oracle directly
-    r = reqs[0]
-    ref = oracle.decompose(oracle.build_graph(r["rects"], r["dmin"], r["split"]), 4, 20000)
-    assert np.array_equal(results[0].colors, ref.colors)
 
 
 def test_admission_waits_for_device_bytes(ctx):
@@ -124,6 +139,7 @@ def test_admission_waits_for_device_bytes(ctx):
     assert st["peak_bytes"] <= 6 << 10
     for r, got in zip(reqs, results):
         same(got, alone(ctx, r, 10**6, SIMPLIFY))
+        check_oracle(got, r, 10**6, SIMPLIFY)
 
 
 def test_oversize_request_is_nomem_not_a_hang(ctx):
@@ -177,3 +193,33 @@ def test_lds_tier_components_in_the_mix(ctx):
         assert np.array_equal(got.components["trace_hash"], ref.comps["trace_hash"])
     for r, got in zip(small, results[3:]):
         same(got, alone(ctx, r, 5000, SIMPLIFY | TRACE))
+        check_oracle(got, dict(r, split=0, k=3), 5000, SIMPLIFY | TRACE)
+
+
+def test_largest_serving_requests_vs_oracle(ctx):
+    """The largest requests of the serving workload's own trace (10,000
+    requests, seed 0; feature counts of at least 40,000, up to 50,000),
+    served together with small ones at the serving options, each against
+    the oracle's pipeline."""
+    import paper_2303_14335_amd as mp
+    from workload.configs import SERVE
+    t = workload.request_trace(SERVE["seed"], SERVE["count"], rate=SERVE["rate"],
+                               n_min=SERVE["n_min"], n_max=SERVE["n_max"],
+                               base_side=SERVE["base_side"], base_n=SERVE["base_n"])
+    big = [int(i) for i in np.flatnonzero(t["n_rects"] >= 40000)[:6]]
+    small = [int(i) for i in np.flatnonzero(t["n_rects"] < 2000)[:10]]
+    assert len(big) == 6
+    reqs = []
+    for i in big + small:
+        rects, _ = workload.generate(int(t["n_rects"][i]), int(t["side_nm"][i]), int(t["seed"][i]))
+        reqs.append(dict(rects=rects, dmin=SERVE["dmin_nm"], split=0, k=SERVE["k"]))
+    say("serve the largest trace requests", big)
+    srv = mp.Server(ctx)
+    flags = SIMPLIFY | TRACE
+    tickets = [srv.submit_layout(r["rects"], r["dmin"], r["split"], r["k"], SERVE["budget"], flags)
+               for r in reqs]
+    results = [srv.wait(tk, 60_000_000) for tk in tickets]
+    srv.close()
+    assert max(len(r["rects"]) for r in reqs) >= 40000
+    for r, got in zip(reqs, results):
+        check_oracle(got, r, SERVE["budget"], flags)

@@ -2,8 +2,8 @@
  * layoutgen.h - seeded synthetic layout and request-trace generator.
  *
  * This module produces INPUTS only: axis-aligned rectangles standing in for
- * the layout features of the paper's problem statement (Sec. 2.1, the layout
- * graph built from "a vector of rectangle pointers", Sec. 2.2), and arrival
+ * the layout features of the paper's problem statement (Sec. 2.1; the flow
+ * of Sec. 2.2 builds its layout graph from the layout's rectangles), and arrival
  * traces for a serving workload.  It holds none of the decomposition method's
  * arithmetic (no conflict test, no graph, no search) and is shared, as a
  * separate library, by the product library's callers and by the oracle's
