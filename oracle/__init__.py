@@ -19,7 +19,8 @@ _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 FEASIBLE, INFEASIBLE, BUDGET = 0, 1, 2
-SIMPLIFY, MARK, STITCH = 1, 2, 4
+SIMPLIFY, MARK, STITCH, MINIMIZE = 1, 2, 4, 8
+MINIMIZE_MAX_N = 64
 
 
 class OrcComp(ctypes.Structure):
@@ -27,7 +28,7 @@ class OrcComp(ctypes.Structure):
                 ("nodes", ctypes.c_int64), ("trace_hash", ctypes.c_uint64),
                 ("depth_at_stop", ctypes.c_int32), ("stitches", ctypes.c_int32),
                 ("first_node", ctypes.c_int32), ("num_edges", ctypes.c_int32),
-                ("conflicts", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("conflicts", ctypes.c_int32), ("min_nodes", ctypes.c_int32)]
 
 
 def build() -> str:
@@ -59,7 +60,7 @@ def _load():
         lib.orc_decompose.restype = ctypes.c_int32
         lib.orc_decompose.argtypes = [ctypes.c_int32, ctypes.c_int64, vp,
                                       ctypes.c_int64, vp, ctypes.c_int32,
-                                      ctypes.c_int64, ctypes.c_uint32, vp, vp,
+                                      ctypes.c_int64, ctypes.c_int64, ctypes.c_uint32, vp, vp,
                                       _p(ctypes.c_int32), _p(vp),
                                       _p(ctypes.c_int64), _p(ctypes.c_int64),
                                       _p(ctypes.c_int64)]
@@ -78,6 +79,11 @@ def _load():
         lib.orc_mark_conflicts.restype = ctypes.c_int32
         lib.orc_mark_conflicts.argtypes = [ctypes.c_int32, ctypes.c_int64, vp,
                                            ctypes.c_int32, vp]
+        lib.orc_minimize_component.restype = ctypes.c_int32
+        lib.orc_minimize_component.argtypes = [ctypes.c_int32, ctypes.c_int64, vp,
+                                               ctypes.c_int32, vp, ctypes.c_int64, vp,
+                                               _p(ctypes.c_int64), _p(ctypes.c_int32),
+                                               _p(ctypes.c_int32)]
         lib.orc_solve_many.restype = ctypes.c_int32
         lib.orc_solve_many.argtypes = [ctypes.c_int32, vp, vp, vp,
                                        ctypes.c_int32, ctypes.c_int64,
@@ -148,14 +154,17 @@ COMP_DTYPE = np.dtype([("size", np.int32), ("status", np.int32),
                        ("nodes", np.int64), ("trace_hash", np.uint64),
                        ("depth_at_stop", np.int32), ("stitches", np.int32),
                        ("first_node", np.int32), ("num_edges", np.int32),
-                       ("conflicts", np.int32), ("reserved", np.int32)])
+                       ("conflicts", np.int32), ("min_nodes", np.int32)])
 
 
 def decompose(g: Graph, k: int, budget: int, simplify: bool = True,
-              mark: bool = False, stitch: bool = False) -> Decomposition:
+              mark: bool = False, stitch: bool = False, minimize: bool = False,
+              min_budget: int = 10000) -> Decomposition:
     """Whole flow; mark=True colors the components left without a solution
     by the conflict-marking descent (mark_conflicts); stitch=True searches
-    with the stitch-aware row order."""
+    with the stitch-aware row order; minimize=True (implies mark) runs the
+    Eq. 1 branch and bound (minimize_component, min_budget nodes) on every
+    component of at most MINIMIZE_MAX_N nodes with a positive cost."""
     lib = _load()
     n = g.num_nodes
     ce = np.ascontiguousarray(g.ce, dtype=np.int32).reshape(-1, 2)
@@ -168,8 +177,9 @@ def decompose(g: Graph, k: int, budget: int, simplify: bool = True,
     cn = ctypes.c_int64()
     un = ctypes.c_int64()
     rc = lib.orc_decompose(n, len(ce), ce.ctypes.data, len(se), se.ctypes.data,
-                           k, budget, (SIMPLIFY if simplify else 0) | (MARK if mark else 0)
-                           | (STITCH if stitch else 0),
+                           k, budget, min_budget,
+                           (SIMPLIFY if simplify else 0) | (MARK if mark else 0)
+                           | (STITCH if stitch else 0) | (MINIMIZE if minimize else 0),
                            colors.ctypes.data, comp_of.ctypes.data,
                            ctypes.byref(nc), ctypes.byref(pcs),
                            ctypes.byref(st), ctypes.byref(cn), ctypes.byref(un))
@@ -222,6 +232,34 @@ def mark_conflicts(n: int, edges, k: int) -> np.ndarray:
     if rc != 0:
         raise ValueError(f"orc_mark_conflicts failed: {rc}")
     return colors[:n].copy()
+
+
+@dataclass
+class Minimized:
+    colors: np.ndarray
+    nodes: int
+    stopped: bool
+    cost: int
+
+
+def minimize_component(n: int, edges, k: int, colors, budget: int, partner=None) -> Minimized:
+    """Eq. 1 branch and bound on one component from the complete incumbent
+    `colors`; cost = 10 conflicts + stitches."""
+    lib = _load()
+    e = np.ascontiguousarray(np.asarray(edges, dtype=np.int32).reshape(-1, 2))
+    col = np.zeros(max(n, 1), dtype=np.int8)
+    col[:n] = np.asarray(colors, dtype=np.int8)[:n]
+    part = None if partner is None else np.ascontiguousarray(np.asarray(partner, dtype=np.int32))
+    nodes = ctypes.c_int64()
+    stopped = ctypes.c_int32()
+    cost = ctypes.c_int32()
+    rc = lib.orc_minimize_component(n, len(e), e.ctypes.data, k,
+                                    None if part is None else part.ctypes.data, budget,
+                                    col.ctypes.data, ctypes.byref(nodes), ctypes.byref(stopped),
+                                    ctypes.byref(cost))
+    if rc != 0:
+        raise ValueError(f"orc_minimize_component failed: {rc}")
+    return Minimized(col[:n].copy(), nodes.value, bool(stopped.value), cost.value)
 
 
 def solve_many(sizes, edge_lists, k: int, budget: int, threads: int, passes: int = 1):

@@ -12,6 +12,7 @@
 
 #include <pthread.h>
 #include <stdatomic.h>
+#include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -529,6 +530,166 @@ done:
 }
 
 /* ------------------------------------------------------------------------
+ * Eq. 1 minimisation (Sec. 2.1 objective with alpha = 0.1; Algorithm 1's
+ * conflict candidates generalised).  Reading: the exact-cover search is
+ * relaxed so that a row whose secondary columns are already covered may
+ * still be taken, each such covered (edge, color) column counting one
+ * conflict; a row (v, c) whose node's stitch partner already holds another
+ * color counts one stitch.  Cost = 10 conflicts + stitches (Eq. 1 scaled by
+ * 10, integers).  A depth-first branch and bound over the rows finds a
+ * coloring of least cost, starting from an incumbent coloring (the first
+ * solution, or the conflict-marking descent):
+ *   - penalty p(u, c) of an uncolored node = 10 x (colored neighbours of
+ *     color c) + 1 if its partner is colored with a color other than c;
+ *   - lower bound = cost so far + sum over uncolored u of min_c p(u, c)
+ *     (each term charges edges to colored nodes only, so the terms are
+ *     disjoint and can only grow);
+ *   - a node entry that passes the budget test counts one node; with every
+ *     node colored it replaces the incumbent if cheaper; otherwise it
+ *     returns when the bound reaches the incumbent's cost, else takes the
+ *     uncolored node with the fewest conflict-free colors (lowest index on
+ *     ties) and tries its colors in ascending order, skipping a color whose
+ *     child bound (bound - min_c p(v, c) + p(v, c)) reaches the incumbent's
+ *     cost at the moment it is tried.
+ * ---------------------------------------------------------------------- */
+
+typedef struct {
+  int32_t n, k;
+  const int64_t* ap;      /* adjacency (both directions) */
+  const int32_t* adj;
+  const int32_t* partner; /* stitch partner (-1 none) or NULL */
+  int8_t* col;            /* current colors, -1 uncolored */
+  int32_t* cnt;           /* cnt[u * k + c]: colored neighbours of u with color c */
+  int8_t* pcol;           /* color of u's partner, -1 none or uncolored */
+  int64_t budget, nodes;
+  int32_t stopped;
+  int32_t cost, best;
+  int8_t* best_col;
+} orc_bb;
+
+static int32_t bb_pen(const orc_bb* b, int32_t u, int32_t c) {
+  return 10 * b->cnt[(int64_t)u * b->k + c] + ((b->pcol[u] >= 0 && b->pcol[u] != c) ? 1 : 0);
+}
+
+static int32_t bb_minpen(const orc_bb* b, int32_t u) {
+  int32_t m = bb_pen(b, u, 0);
+  for (int32_t c = 1; c < b->k; ++c) {
+    const int32_t p = bb_pen(b, u, c);
+    if (p < m) m = p;
+  }
+  return m;
+}
+
+/* colors c with no colored neighbour of color c (the node's open rows) */
+static int32_t bb_open(const orc_bb* b, int32_t u) {
+  int32_t o = 0;
+  for (int32_t c = 0; c < b->k; ++c) o += b->cnt[(int64_t)u * b->k + c] == 0;
+  return o;
+}
+
+/* colors v with c (delta = +1) or takes that color back (delta = -1) */
+static void bb_set(orc_bb* b, int32_t v, int32_t c, int32_t delta) {
+  for (int64_t t = b->ap[v]; t < b->ap[v + 1]; ++t) b->cnt[(int64_t)b->adj[t] * b->k + c] += delta;
+  if (b->partner && b->partner[v] >= 0) b->pcol[b->partner[v]] = (int8_t)(delta > 0 ? c : -1);
+  b->col[v] = (int8_t)(delta > 0 ? c : -1);
+}
+
+static void bb_search(orc_bb* b) {
+  if (b->nodes == b->budget) {
+    b->stopped = 1;
+    return;
+  }
+  b->nodes++;
+  int32_t lb = b->cost, v = -1, vopen = b->k + 1;
+  for (int32_t u = 0; u < b->n; ++u) {
+    if (b->col[u] >= 0) continue;
+    lb += bb_minpen(b, u);
+    const int32_t o = bb_open(b, u);
+    if (o < vopen) { vopen = o; v = u; }
+  }
+  if (v < 0) {   /* every node colored */
+    if (b->cost < b->best) {
+      b->best = b->cost;
+      memcpy(b->best_col, b->col, (size_t)b->n);
+    }
+    return;
+  }
+  if (lb >= b->best) return;
+  const int32_t mpv = bb_minpen(b, v);
+  for (int32_t c = 0; c < b->k; ++c) {
+    const int32_t pen = bb_pen(b, v, c);
+    if (lb - mpv + pen >= b->best) continue;
+    bb_set(b, v, c, +1);
+    b->cost += pen;
+    bb_search(b);
+    b->cost -= pen;
+    bb_set(b, v, c, -1);
+    if (b->stopped) return;
+  }
+}
+
+/* Eq. 1 cost of a complete coloring: 10 per conflict edge colored alike,
+ * 1 per stitch pair colored differently (each pair once). */
+static int32_t eq1_cost(int32_t n, int64_t m, const int32_t* edges, const int32_t* partner,
+                        const int8_t* colors) {
+  int32_t cost = 0;
+  for (int64_t e = 0; e < m; ++e)
+    if (colors[edges[2 * e]] == colors[edges[2 * e + 1]]) cost += 10;
+  if (partner)
+    for (int32_t v = 0; v < n; ++v)
+      if (partner[v] > v && colors[v] != colors[partner[v]]) cost += 1;
+  return cost;
+}
+
+int32_t orc_minimize_component(int32_t n, int64_t m, const int32_t* edges, int32_t k,
+                               const int32_t* partner, int64_t budget, int8_t* colors,
+                               int64_t* nodes, int32_t* stopped, int32_t* cost) {
+  if (n < 0 || m < 0 || k < 1 || k > 127 || budget < 1 || (m > 0 && !edges)) return -1;
+  for (int32_t v = 0; v < n; ++v) {
+    if (colors[v] < 0 || colors[v] >= k) return -1;   /* the incumbent is complete */
+    if (partner && (partner[v] >= n || partner[v] == v ||
+                    (partner[v] >= 0 && partner[partner[v]] != v)))
+      return -1;
+  }
+  *nodes = 0;
+  *stopped = 0;
+  *cost = eq1_cost(n, m, edges, partner, colors);
+  if (*cost == 0) return 0;   /* nothing to improve: not run */
+  int64_t* ap = (int64_t*)calloc((size_t)n + 1, sizeof(int64_t));
+  int32_t* adj = (int32_t*)malloc(sizeof(int32_t) * (size_t)(2 * m + 1));
+  int64_t* fill = (int64_t*)malloc(sizeof(int64_t) * ((size_t)n + 1));
+  int32_t* cnt = (int32_t*)calloc((size_t)n * (size_t)k + 1, sizeof(int32_t));
+  int8_t* col = (int8_t*)malloc((size_t)n + 1);
+  int8_t* pcol = (int8_t*)malloc((size_t)n + 1);
+  int32_t rc = 0;
+  if (!ap || !adj || !fill || !cnt || !col || !pcol) { rc = -2; goto done; }
+  for (int64_t e = 0; e < m; ++e) {
+    const int32_t u = edges[2 * e], w = edges[2 * e + 1];
+    if (u < 0 || w < 0 || u >= n || w >= n || u == w) { rc = -1; goto done; }
+    ap[u + 1]++; ap[w + 1]++;
+  }
+  for (int32_t v = 0; v < n; ++v) ap[v + 1] += ap[v];
+  memcpy(fill, ap, sizeof(int64_t) * ((size_t)n + 1));
+  for (int64_t e = 0; e < m; ++e) {
+    adj[fill[edges[2 * e]]++] = edges[2 * e + 1];
+    adj[fill[edges[2 * e + 1]]++] = edges[2 * e];
+  }
+  for (int32_t v = 0; v < n; ++v) { col[v] = -1; pcol[v] = -1; }
+  orc_bb b;
+  b.n = n; b.k = k; b.ap = ap; b.adj = adj; b.partner = partner;
+  b.col = col; b.cnt = cnt; b.pcol = pcol;
+  b.budget = budget; b.nodes = 0; b.stopped = 0;
+  b.cost = 0; b.best = *cost; b.best_col = colors;
+  bb_search(&b);
+  *nodes = b.nodes;
+  *stopped = b.stopped;
+  *cost = b.best;
+done:
+  free(ap); free(adj); free(fill); free(cnt); free(col); free(pcol);
+  return rc;
+}
+
+/* ------------------------------------------------------------------------
  * Whole flow (Sec. 2.2).
  * Simplification reading: iterative removal of nodes with conflict degree
  * < k, first-in first-out - seed the queue with every such node in
@@ -657,12 +818,13 @@ int32_t orc_simplify(int32_t num_nodes, int64_t num_ce, const int32_t* ce,
 
 int32_t orc_decompose(int32_t num_nodes, int64_t num_ce, const int32_t* ce,
                       int64_t num_se, const int32_t* se, int32_t k,
-                      int64_t budget, uint32_t flags, int8_t* colors,
+                      int64_t budget, int64_t min_budget, uint32_t flags, int8_t* colors,
                       int32_t* comp_of, int32_t* num_comps, orc_comp** comps,
                       int64_t* total_stitches, int64_t* total_conflicts,
                       int64_t* total_uncolored) {
   if (num_nodes < 0 || num_ce < 0 || num_se < 0 || k < 1 || k > 64 || budget < 1)
     return -1;
+  if ((flags & ORC_MINIMIZE) && (min_budget < 1 || min_budget > INT32_MAX)) return -1;
   const int32_t n = num_nodes;
   int32_t rc = 0;
   int64_t* ap = (int64_t*)malloc(sizeof(int64_t) * ((size_t)n + 1));
@@ -708,7 +870,7 @@ int32_t orc_decompose(int32_t num_nodes, int64_t num_ce, const int32_t* ce,
     r->size = size;
     r->first_node = nodes[0];
     r->num_edges = (int32_t)lm;
-    if (flags & ORC_STITCH)   /* stitch partners inside the component, local ids */
+    if (flags & (ORC_STITCH | ORC_MINIMIZE))   /* stitch partners inside the component, local ids */
       for (int32_t i = 0; i < size; ++i) {
         const int32_t p = partner[nodes[i]];
         lpartner[i] = p >= 0 && comp_of[p] == c ? local[p] : -1;
@@ -717,10 +879,19 @@ int32_t orc_decompose(int32_t num_nodes, int64_t num_ce, const int32_t* ce,
                                     (flags & ORC_STITCH) ? lpartner : NULL, lcolors,
                                     &r->status, &r->nodes, &r->trace_hash, &r->depth_at_stop);
     if (rc) goto out;
-    const int marked = r->status != ORC_FEASIBLE && (flags & ORC_MARK);
+    const int marked = r->status != ORC_FEASIBLE && (flags & (ORC_MARK | ORC_MINIMIZE));
     if (marked) {
       rc = orc_mark_conflicts(size, lm, ledges, k, lcolors);
       if (rc) goto out;
+    }
+    r->min_nodes = 0;
+    if ((flags & ORC_MINIMIZE) && size <= ORC_MINIMIZE_MAX_N) {
+      int64_t bn = 0;
+      int32_t stopped = 0, cost = 0;
+      rc = orc_minimize_component(size, lm, ledges, k, lpartner, min_budget, lcolors, &bn,
+                                  &stopped, &cost);
+      if (rc) goto out;
+      r->min_nodes = (int32_t)(stopped ? -bn : bn);
     }
     for (int32_t i = 0; i < size; ++i) colors[nodes[i]] = lcolors[i];
     r->stitches = 0;
@@ -733,7 +904,6 @@ int32_t orc_decompose(int32_t num_nodes, int64_t num_ce, const int32_t* ce,
     for (int64_t e = 0; e < lm; ++e)
       if (lcolors[ledges[2 * e]] >= 0 && lcolors[ledges[2 * e]] == lcolors[ledges[2 * e + 1]])
         r->conflicts++;
-    r->reserved = 0;
   }
 
   /* recovery, reverse removal order */

@@ -26,7 +26,9 @@ extern "C" {
 #endif
 
 enum { ORC_FEASIBLE = 0, ORC_INFEASIBLE = 1, ORC_BUDGET = 2 };
-enum { ORC_SIMPLIFY = 1, ORC_MARK = 2, ORC_STITCH = 4 };
+enum { ORC_SIMPLIFY = 1, ORC_MARK = 2, ORC_STITCH = 4, ORC_MINIMIZE = 8 };
+/* ORC_MINIMIZE applies to components of at most this many nodes. */
+enum { ORC_MINIMIZE_MAX_N = 64 };
 
 typedef struct { int32_t x0, y0, x1, y1; } orc_rect;
 
@@ -41,7 +43,8 @@ typedef struct {
   int32_t first_node;    /* smallest original node id                  */
   int32_t num_edges;     /* conflict edges inside                      */
   int32_t conflicts;     /* conflict edges inside whose ends share a color */
-  int32_t reserved;
+  int32_t min_nodes;     /* ORC_MINIMIZE: branch-and-bound nodes, negated when its
+                            budget stopped it (least cost not proven); 0 = not run */
 } orc_comp;
 
 /* Builds the node list and conflict/stitch edges of a rectangle layout.
@@ -58,13 +61,17 @@ int32_t orc_build_graph(const orc_rect* rects, int32_t n, int32_t dmin,
 /* Full decomposition of a graph.  flags: ORC_SIMPLIFY, ORC_MARK (components
  * the search leaves without a solution are colored by orc_mark_conflicts),
  * ORC_STITCH (stitch-aware row order, orc_solve_component_stitch, with each
- * node's stitch partner when the partner is in the same component).
+ * node's stitch partner when the partner is in the same component),
+ * ORC_MINIMIZE (implies ORC_MARK for unsolved components; then every
+ * component of at most ORC_MINIMIZE_MAX_N nodes whose coloring has a
+ * positive Eq. 1 cost goes through orc_minimize_component with min_budget
+ * nodes, stitch partners inside the component included).
  * colors (num_nodes, -1 = uncolored) and
  * comp_of (num_nodes, -1 = removed by simplification) are caller-allocated;
  * *comps is malloc'ed (free with orc_free).  Totals may be NULL. */
 int32_t orc_decompose(int32_t num_nodes, int64_t num_ce, const int32_t* ce,
                       int64_t num_se, const int32_t* se, int32_t k,
-                      int64_t budget, uint32_t flags, int8_t* colors,
+                      int64_t budget, int64_t min_budget, uint32_t flags, int8_t* colors,
                       int32_t* comp_of, int32_t* num_comps, orc_comp** comps,
                       int64_t* total_stitches, int64_t* total_conflicts,
                       int64_t* total_uncolored);
@@ -102,6 +109,18 @@ int32_t orc_solve_component_stitch(int32_t n, int64_t m, const int32_t* edges,
  * caller-allocated; every node is colored. */
 int32_t orc_mark_conflicts(int32_t n, int64_t m, const int32_t* edges, int32_t k,
                            int8_t* colors);
+
+/* Eq. 1 minimisation of one component (local numbering) from a complete
+ * incumbent coloring `colors` (in/out): a depth-first branch and bound over
+ * the relaxed exact cover in which a row may be taken over covered
+ * secondary columns at one conflict each; cost = 10 conflicts + stitches
+ * (alpha = 0.1 scaled by 10).  partner: local stitch partners (-1 none) or
+ * NULL.  *cost: the incumbent's cost in, the best cost out; *nodes: nodes
+ * counted (budget tested before counting); *stopped: 1 when the budget
+ * ended it.  An incumbent of cost 0 returns at once with 0 nodes. */
+int32_t orc_minimize_component(int32_t n, int64_t m, const int32_t* edges, int32_t k,
+                               const int32_t* partner, int64_t budget, int8_t* colors,
+                               int64_t* nodes, int32_t* stopped, int32_t* cost);
 
 /* Solves many components (concatenated local edge lists) on `threads`
  * threads, each component independently with orc_solve_component's

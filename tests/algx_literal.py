@@ -226,3 +226,88 @@ def grotzsch():
         e.append((v + 5, u))
     e += [(10, i + 5) for i in range(5)]
     return 11, e
+
+
+def eq1_cost(n: int, edges, colors, partner=None) -> int:
+    """10 per conflict edge colored alike + 1 per stitch pair colored
+    differently (Eq. 1 with alpha = 0.1, scaled by 10)."""
+    c = sum(10 for u, w in edges if colors[u] == colors[w])
+    if partner is not None:
+        c += sum(1 for v in range(n) if partner[v] > v and colors[v] != colors[partner[v]])
+    return c
+
+
+def bb_sets(n: int, edges, k: int, colors, budget: int, partner=None):
+    """The Eq. 1 branch and bound restated without incremental state: every
+    penalty is recounted from the current partial coloring.  Penalty of
+    (u, c) = 10 x colored neighbours of color c + 1 when u's partner is
+    colored otherwise; bound = cost + sum of the uncolored nodes' least
+    penalties; node entry counted after the budget test; leaf replaces the
+    incumbent when cheaper; prune at bound >= incumbent; branch on the
+    uncolored node with the fewest colors free of colored neighbours of that
+    color (lowest index on ties), colors ascending, a color skipped when
+    bound - least(v) + penalty(v, c) >= incumbent.  Returns (colors, nodes,
+    stopped, cost)."""
+    nbrs = [set() for _ in range(n)]
+    for u, w in edges:
+        nbrs[u].add(w)
+        nbrs[w].add(u)
+    cur = {}
+    best = {"cost": eq1_cost(n, edges, colors, partner), "colors": list(colors)}
+    st = {"nodes": 0, "stopped": False, "cost": 0}
+    if best["cost"] == 0:
+        return np.asarray(colors, np.int8), 0, False, 0
+
+    def pen(u, c):
+        p = 10 * sum(1 for w in nbrs[u] if cur.get(w) == c)
+        if partner is not None and partner[u] >= 0 and partner[u] in cur and cur[partner[u]] != c:
+            p += 1
+        return p
+
+    def free(u):
+        return sum(1 for c in range(k) if all(cur.get(w) != c for w in nbrs[u]))
+
+    def rec():
+        if st["nodes"] == budget:
+            st["stopped"] = True
+            return
+        st["nodes"] += 1
+        unc = [u for u in range(n) if u not in cur]
+        if not unc:
+            if st["cost"] < best["cost"]:
+                best["cost"] = st["cost"]
+                best["colors"] = [cur[u] for u in range(n)]
+            return
+        lb = st["cost"] + sum(min(pen(u, c) for c in range(k)) for u in unc)
+        if lb >= best["cost"]:
+            return
+        v = min(unc, key=lambda u: (free(u), u))
+        least = min(pen(v, c) for c in range(k))
+        for c in range(k):
+            p = pen(v, c)
+            if lb - least + p >= best["cost"]:
+                continue
+            cur[v] = c
+            st["cost"] += p
+            rec()
+            st["cost"] -= p
+            del cur[v]
+            if st["stopped"]:
+                return
+
+    rec()
+    return np.asarray(best["colors"], np.int8), st["nodes"], st["stopped"], best["cost"]
+
+
+def min_eq1_cost(n: int, edges, k: int, partner=None) -> int:
+    """Least Eq. 1 cost (10 conflicts + stitches) over all k-colorings."""
+    e = np.asarray(list(edges), dtype=np.int64).reshape(-1, 2)
+    pairs = ([(v, int(partner[v])) for v in range(n) if partner is not None and partner[v] > v])
+    s = np.asarray(pairs, dtype=np.int64).reshape(-1, 2)
+    best = None
+    for chunk in _colorings(n, k):
+        cost = 10 * (chunk[:, e[:, 0]] == chunk[:, e[:, 1]]).sum(axis=1) if len(e) else 0
+        cost = cost + ((chunk[:, s[:, 0]] != chunk[:, s[:, 1]]).sum(axis=1) if len(s) else 0)
+        m = int(np.min(cost))
+        best = m if best is None else min(best, m)
+    return 0 if best is None else best
