@@ -127,7 +127,7 @@ enum {
                                   forced LDS/global/device tier give
                                   MPLD_E_UNSUPPORTED; disables
                                   MPLD_SPLIT_HEAVY; not with a server. */
-  MPLD_ROUNDTRIP = 1u << 12    /* mpld_batch_solve: the whole device solve -
+  MPLD_ROUNDTRIP = 1u << 12,   /* mpld_batch_solve: the whole device solve -
                                   copy of the packed image from page-locked
                                   host memory to the device, the search, copy
                                   of the records and local colors back to
@@ -135,6 +135,32 @@ enum {
                                   two HIP events; mpld_batch_info's
                                   last_roundtrip_ms reads their distance.  The
                                   result is the same as without the flag. */
+  MPLD_MINIMIZE = 1u << 13     /* Eq. 1 minimisation: after the search (and the
+                                  conflict marking, which this flag implies),
+                                  every component of the register tier (at
+                                  most 64 nodes) whose coloring costs anything
+                                  - cost = 10 x conflicts + stitches, Eq. 1
+                                  with alpha = 0.1 scaled by 10 - is searched
+                                  again by a depth-first branch and bound over
+                                  the exact cover relaxed so that a row may be
+                                  taken over covered (edge, color) columns at
+                                  one conflict each: penalty of (u, c) = 10 x
+                                  colored neighbours of color c + 1 when u's
+                                  stitch partner has another color; bound =
+                                  cost + sum of the uncolored nodes' least
+                                  penalties; branch on the uncolored node with
+                                  the fewest conflict-free colors (lowest
+                                  index on ties), colors ascending, a color
+                                  skipped when its child bound reaches the
+                                  incumbent's cost; at most
+                                  mpld_options.min_budget nodes per component.
+                                  The best coloring replaces the incumbent;
+                                  status, nodes, hash and depth stay the
+                                  search's; mpld_comp_record.min_nodes tells
+                                  whether least cost was proven.  Decompose,
+                                  batches and mpld_solve_components; not with
+                                  a forced LDS, global or device tier
+                                  (MPLD_E_UNSUPPORTED); a server rejects it. */
 };
 
 typedef struct { int32_t x0, y0, x1, y1; } mpld_rect;  /* nm, closed box */
@@ -157,7 +183,8 @@ typedef struct {
   int32_t k;              /* mask count, 2 .. MPLD_MAX_K                */
   int64_t node_budget;    /* per component, >= 1                        */
   uint32_t flags;         /* MPLD_* flags                               */
-  int32_t reserved;
+  int32_t min_budget;     /* MPLD_MINIMIZE: branch-and-bound nodes per
+                             component; 0 = 10000; < 0 is MPLD_E_INVALID */
 } mpld_options;
 
 /* Per component record (48 bytes). */
@@ -173,7 +200,10 @@ typedef struct {
   int32_t num_edges;      /* conflict edges inside                          */
   int32_t conflicts;      /* conflict edges inside whose ends share a color
                              (0 unless MPLD_MARK_CONFLICTS marked it)        */
-  int32_t reserved;
+  int32_t min_nodes;      /* MPLD_MINIMIZE: branch-and-bound nodes; negated
+                             when min_budget stopped it (least cost not
+                             proven); 0 when it did not run (cost 0, or more
+                             than 64 nodes)                                 */
 } mpld_comp_record;
 
 /* One component given directly in its local numbering (no simplification,

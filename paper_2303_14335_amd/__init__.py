@@ -20,8 +20,8 @@ import numpy as np
 from . import _ffi
 from ._ffi import (MPLD_BUDGET_EXHAUSTED, MPLD_FEASIBLE, MPLD_FORCE_DEVICE,  # noqa: F401
                    MPLD_FORCE_GLOBAL, MPLD_FORCE_LDS, MPLD_FORCE_WAVE, MPLD_INFEASIBLE,
-                   MPLD_MARK_CONFLICTS, MPLD_PLAIN, MPLD_SIMPLIFY, MPLD_SPLIT_HEAVY, MPLD_STITCH_ORDER,
-                   MPLD_TRACE_HASH)
+                   MPLD_MARK_CONFLICTS, MPLD_MINIMIZE, MPLD_PLAIN, MPLD_SIMPLIFY, MPLD_SPLIT_HEAVY,
+                   MPLD_STITCH_ORDER, MPLD_TRACE_HASH)
 
 _lib = _ffi.load()
 
@@ -29,7 +29,7 @@ RECORD_DTYPE = np.dtype([("size", np.int32), ("status", np.int32), ("nodes", np.
                          ("trace_hash", np.uint64), ("depth_at_stop", np.int32),
                          ("stitches", np.int32), ("first_node", np.int32),
                          ("num_edges", np.int32), ("conflicts", np.int32),
-                         ("reserved", np.int32)])
+                         ("min_nodes", np.int32)])
 assert RECORD_DTYPE.itemsize == ctypes.sizeof(_ffi.mpld_comp_record)
 
 
@@ -50,8 +50,9 @@ def mpld_abi_version() -> int:
     return int(_lib.mpld_abi_version())
 
 
-def options(k: int, budget: int, flags: int = MPLD_SIMPLIFY) -> _ffi.mpld_options:
-    return _ffi.mpld_options(ctypes.sizeof(_ffi.mpld_options), k, budget, flags, 0)
+def options(k: int, budget: int, flags: int = MPLD_SIMPLIFY,
+            min_budget: int = 0) -> _ffi.mpld_options:
+    return _ffi.mpld_options(ctypes.sizeof(_ffi.mpld_options), k, budget, flags, min_budget)
 
 
 # ---- graphs -------------------------------------------------------------
@@ -264,8 +265,8 @@ def _take_result(h) -> Result:
 
 
 def mpld_decompose(ctx: Context, g: Graph, k: int, budget: int,
-                   flags: int = MPLD_SIMPLIFY) -> Result:
-    opt = options(k, budget, flags)
+                   flags: int = MPLD_SIMPLIFY, min_budget: int = 0) -> Result:
+    opt = options(k, budget, flags, min_budget)
     view = g.view()
     h = ctypes.c_void_p()
     _check(_lib.mpld_decompose(ctx.handle, ctypes.byref(view), ctypes.byref(opt),
@@ -276,10 +277,11 @@ def mpld_decompose(ctx: Context, g: Graph, k: int, budget: int,
 class Batch:
     """Front-end + packed image resident on the device; solve repeatedly."""
 
-    def __init__(self, ctx: Context, g: Graph, k: int, budget: int, flags: int = MPLD_SIMPLIFY):
+    def __init__(self, ctx: Context, g: Graph, k: int, budget: int, flags: int = MPLD_SIMPLIFY,
+                 min_budget: int = 0):
         self.ctx = ctx
         self.handle = ctypes.c_void_p()
-        opt = options(k, budget, flags)
+        opt = options(k, budget, flags, min_budget)
         view = g.view()
         _check(_lib.mpld_batch_create(ctx.handle, ctypes.byref(view), ctypes.byref(opt),
                                       ctypes.byref(self.handle)), "mpld_batch_create")
@@ -369,7 +371,8 @@ def mpld_batch_set_tune(b: Batch, **kw) -> None:
     b.set_tune(**kw)
 
 
-def mpld_solve_components(ctx: Context, comps, k: int, budget: int, flags: int = 0):
+def mpld_solve_components(ctx: Context, comps, k: int, budget: int, flags: int = 0,
+                          min_budget: int = 0):
     """comps: list of (n, edges [m, 2]) in local numbering.  Returns
     (records RECORD_DTYPE[count], list of per-component int8 colors)."""
     arrs = []
@@ -382,7 +385,7 @@ def mpld_solve_components(ctx: Context, comps, k: int, budget: int, flags: int =
         total += n
     recs = (_ffi.mpld_comp_record * max(len(comps), 1))()
     colors = np.zeros(max(total, 1), dtype=np.int8)
-    opt = options(k, budget, flags)
+    opt = options(k, budget, flags, min_budget)
     _check(_lib.mpld_solve_components(ctx.handle, cs, len(comps), ctypes.byref(opt), recs,
                                       colors.ctypes.data), "mpld_solve_components")
     out = np.frombuffer(bytes(recs), dtype=RECORD_DTYPE)[: len(comps)].copy()

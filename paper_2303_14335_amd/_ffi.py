@@ -31,6 +31,7 @@ MPLD_UNTIMED = 1 << 9
 MPLD_MARK_CONFLICTS = 1 << 10
 MPLD_STITCH_ORDER = 1 << 11
 MPLD_ROUNDTRIP = 1 << 12
+MPLD_MINIMIZE = 1 << 13
 
 c_i32, c_i64, c_u32, c_u64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint64
 vp = ctypes.c_void_p
@@ -47,13 +48,13 @@ class mpld_graph(ctypes.Structure):
 
 class mpld_options(ctypes.Structure):
     _fields_ = [("struct_size", c_u32), ("k", c_i32), ("node_budget", c_i64),
-                ("flags", c_u32), ("reserved", c_i32)]
+                ("flags", c_u32), ("min_budget", c_i32)]
 
 
 class mpld_comp_record(ctypes.Structure):
     _fields_ = [("size", c_i32), ("status", c_i32), ("nodes", c_i64), ("trace_hash", c_u64),
                 ("depth_at_stop", c_i32), ("stitches", c_i32), ("first_node", c_i32),
-                ("num_edges", c_i32), ("conflicts", c_i32), ("reserved", c_i32)]
+                ("num_edges", c_i32), ("conflicts", c_i32), ("min_nodes", c_i32)]
 
 
 class mpld_component(ctypes.Structure):

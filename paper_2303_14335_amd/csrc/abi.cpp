@@ -47,6 +47,7 @@ void check_options(const mpld_options* opt) {
   const uint32_t forced =
       opt->flags & (MPLD_FORCE_WAVE | MPLD_FORCE_LDS | MPLD_FORCE_GLOBAL | MPLD_FORCE_DEVICE);
   if (forced & (forced - 1)) fail(MPLD_E_INVALID, "at most one MPLD_FORCE_* flag");
+  if (opt->min_budget < 0) fail(MPLD_E_INVALID, "min_budget must be >= 0 (0 = 10000)");
 }
 
 constexpr int32_t kDeviceSplitMinNodes = 32768;
@@ -77,11 +78,17 @@ void batch_build(mpld_context* ctx, const mpld_graph* g, const mpld_options* opt
   batch_pack(b, t);
 }
 
+uint32_t min_budget_of(const mpld_options* opt) {
+  return opt->min_budget > 0 ? (uint32_t)opt->min_budget : 10000u;
+}
+
 void batch_collect(mpld_batch* b, mpld_result* r) {
   std::vector<DevRecord> recs;
   std::vector<int8_t> lcol;
-  device_fetch(b->db, recs, lcol);
-  assemble_result(b->g, b->s, b->im, b->opt, recs, lcol, r);
+  std::vector<int32_t> mins;
+  const bool minimize = b->opt.flags & MPLD_MINIMIZE;
+  device_fetch(b->db, recs, lcol, minimize ? &mins : nullptr);
+  assemble_result(b->g, b->s, b->im, b->opt, recs, lcol, r, minimize ? &mins : nullptr);
 }
 
 }  // namespace
@@ -373,10 +380,12 @@ int32_t mpld_solve_components(mpld_context* ctx, const mpld_component* comps, in
     image_finish(im);
     DeviceBatch db;
     device_upload(ctx, im, db);
+    db.min_budget = min_budget_of(opt);
     device_solve(db, opt->flags | MPLD_DIRECT);
     std::vector<DevRecord> recs;
     std::vector<int8_t> lcol;
-    device_fetch(db, recs, lcol);
+    std::vector<int32_t> mins;
+    device_fetch(db, recs, lcol, &mins);
     const bool trace = opt->flags & MPLD_TRACE_HASH;
     for (int32_t c = 0; c < count; ++c) {
       mpld_comp_record& r = out[c];
@@ -385,11 +394,12 @@ int32_t mpld_solve_components(mpld_context* ctx, const mpld_component* comps, in
       r.nodes = (int64_t)recs[c].nodes;
       r.trace_hash = trace ? recs[c].hash : 0;
       r.depth_at_stop = recs[c].depth;
-      r.stitches = r.status == MPLD_FEASIBLE || (opt->flags & MPLD_MARK_CONFLICTS) ? 0 : -1;
+      r.stitches = r.status == MPLD_FEASIBLE || (opt->flags & (MPLD_MARK_CONFLICTS | MPLD_MINIMIZE))
+                       ? 0 : -1;
       r.first_node = -1;
       r.num_edges = (int32_t)comps[c].m;
       r.conflicts = 0;
-      r.reserved = 0;
+      r.min_nodes = (opt->flags & MPLD_MINIMIZE) ? mins[(size_t)c] : 0;
       const int8_t* cc = lcol.data() + im.desc[c].out_off;
       for (int64_t e = 0; e < comps[c].m; ++e) {
         const int8_t a = cc[comps[c].edges[2 * e]];

@@ -26,6 +26,7 @@ void batch_pack(mpld_batch* b, const Tune& t) {
   const int32_t nc = (int32_t)b->s.comp_ptr.size() - 1;
   std::vector<int32_t> pairs, part;
   const bool stitch = b->opt.flags & MPLD_STITCH_ORDER;
+  const bool partners = stitch || (b->opt.flags & MPLD_MINIMIZE);
   for (int32_t c = 0; c < nc; ++c) {
     local_edges(b->g, b->s, c, pairs);
     const int32_t n = b->s.comp_ptr[c + 1] - b->s.comp_ptr[c];
@@ -33,7 +34,7 @@ void batch_pack(mpld_batch* b, const Tune& t) {
     if (t.giant_device && n >= t.giant_min_nodes && !stitch &&
         !(flags & (MPLD_FORCE_WAVE | MPLD_FORCE_LDS | MPLD_FORCE_GLOBAL)))
       flags |= MPLD_FORCE_DEVICE;
-    if (stitch) {   // stitch partners inside the component, in its local numbering
+    if (partners) {   // stitch partners inside the component, in its local numbering
       part.assign((size_t)n, -1);
       for (int32_t i = 0; i < n; ++i) {
         const int32_t q = b->g.partner[b->s.order[b->s.comp_ptr[c] + i]];
@@ -41,11 +42,12 @@ void batch_pack(mpld_batch* b, const Tune& t) {
       }
     }
     image_add(im, b->ctx, n, pairs.data(), (int64_t)pairs.size() / 2, b->opt.k,
-              b->opt.node_budget, flags, stitch ? part.data() : nullptr);
+              b->opt.node_budget, flags, partners ? part.data() : nullptr);
   }
   image_finish(im, t.order);
   b->im = std::move(im);
   device_upload(b->ctx, b->im, b->db, t);   // reallocates every buffer it uses
+  b->db.min_budget = b->opt.min_budget > 0 ? (uint32_t)b->opt.min_budget : 10000u;
 }
 
 static std::string shape_key(mpld_batch* b) {

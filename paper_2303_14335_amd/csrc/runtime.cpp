@@ -33,6 +33,11 @@ void image_add(Image& im, mpld_context* ctx, int32_t n, const int32_t* pairs, in
   const bool force_lds = flags & MPLD_FORCE_LDS, force_glb = flags & MPLD_FORCE_GLOBAL,
              force_reg = flags & MPLD_FORCE_WAVE, force_dev = flags & MPLD_FORCE_DEVICE;
   const bool stitch = flags & MPLD_STITCH_ORDER;
+  const bool minimize = flags & MPLD_MINIMIZE;
+  if (minimize && (force_lds || force_glb || force_dev))
+    fail(MPLD_E_UNSUPPORTED, "the Eq. 1 minimisation runs on the register tier; a forced LDS, "
+                             "global or device tier cannot take it");
+  if (minimize) im.minimize = true;
   if (stitch && (n > 64 || force_lds || force_glb || force_dev))
     fail(MPLD_E_UNSUPPORTED, "the stitch-aware order runs on the register tier (components of at "
                              "most 64 nodes); component has " + std::to_string(n));
@@ -40,8 +45,8 @@ void image_add(Image& im, mpld_context* ctx, int32_t n, const int32_t* pairs, in
     d.nbr_off = (int64_t)im.masks.size();
     im.masks.resize(im.masks.size() + (size_t)n, 0ull);
     im.partner8.resize(im.masks.size(), 0xffu);
-    if (stitch) {
-      im.stitch = true;
+    if (stitch) im.stitch = true;
+    if (stitch || minimize) {
       if (partner)
         for (int32_t v = 0; v < n; ++v)
           if (partner[v] >= 0) im.partner8[(size_t)d.nbr_off + v] = (uint8_t)partner[v];
@@ -243,6 +248,16 @@ void device_upload(mpld_context* ctx, const Image& im, DeviceBatch& db, const Tu
   check_hip(hipStreamSynchronize(s), "upload");
   db.host_items = std::move(items);
   db.rt_ready = false;
+  db.partners.release();
+  db.min_out.release();
+  if (im.minimize) {
+    db.partners.alloc(ctx, std::max<size_t>(im.partner8.size(), 1));
+    db.min_out.alloc(ctx, sizeof(int32_t) * std::max<size_t>(im.desc.size(), 1));
+    if (!im.partner8.empty())
+      check_hip(hipMemcpyAsync(db.partners.p, im.partner8.data(), im.partner8.size(),
+                               hipMemcpyHostToDevice, s), "upload stitch partners");
+    check_hip(hipStreamSynchronize(s), "upload");
+  }
 }
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -802,6 +817,16 @@ static void heavy_engine_host(DeviceBatch& db) {
 
 // Conflict marking of every component whose record is not FEASIBLE (after
 // all search work of the batch, on the same stream).
+// Eq. 1 minimisation of the register-tier items (after the marking).
+static void enqueue_minimize(DeviceBatch& db, hipStream_t s) {
+  if (!db.n_reg) return;
+  if (!db.min_out.p) fail(MPLD_E_INTERNAL, "batch was not packed for MPLD_MINIMIZE");
+  check_hip(launch_min_reg(db.k, std::min(db.n_reg, 65535), db.reg_items(),
+                           db.n_reg, db.partners.as<uint8_t>(), db.colors.as<int8_t>(),
+                           db.min_out.as<int32_t>(), db.min_budget, s),
+            "Eq. 1 minimisation (register tier)");
+}
+
 static void enqueue_mark(DeviceBatch& db, hipStream_t s) {
   mpld_context* ctx = db.ctx;
   auto* recs = db.recs.as<DevRecord>();
@@ -821,7 +846,8 @@ static void enqueue_mark(DeviceBatch& db, hipStream_t s) {
 void device_solve(DeviceBatch& db, uint32_t flags) {
   mpld_context* ctx = db.ctx;
   hipStream_t s = ctx->stream;
-  const bool mark = flags & MPLD_MARK_CONFLICTS;
+  const bool minimize = flags & MPLD_MINIMIZE;
+  const bool mark = flags & (MPLD_MARK_CONFLICTS | MPLD_MINIMIZE);
   if (mark && db.mark_lds > ctx->lds_per_block)
     fail(MPLD_E_UNSUPPORTED, "a component is too large for conflict marking (" +
                                  std::to_string(db.mark_lds) + " bytes of LDS)");
@@ -857,6 +883,7 @@ void device_solve(DeviceBatch& db, uint32_t flags) {
       ++db.launches;
     }
     if (mark) enqueue_mark(db, s);
+    if (minimize) enqueue_minimize(db, s);
     check_hip(hipEventRecord(ctx->ev[1], s), "event");
   } else if ((flags & MPLD_DIRECT) || !db.tune.use_graph || db.n_dev) {
     // direct launches (cooperative launches stay out of graphs)
@@ -864,6 +891,7 @@ void device_solve(DeviceBatch& db, uint32_t flags) {
     enqueue_batched(db, trace, cap, s);
     if (split) heavy_engine(db);
     if (mark) enqueue_mark(db, s);
+    if (minimize) enqueue_minimize(db, s);
     if (timed) check_hip(hipEventRecord(ctx->ev[1], s), "event");
   } else {
     // capture the tiered launches once, replay the graph afterwards
@@ -892,6 +920,7 @@ void device_solve(DeviceBatch& db, uint32_t flags) {
     check_hip(hipGraphLaunch(db.graph, s), "graph launch");
     if (split) heavy_engine(db);
     if (mark) enqueue_mark(db, s);
+    if (minimize) enqueue_minimize(db, s);
     if (timed) check_hip(hipEventRecord(ctx->ev[1], s), "event");
   }
   db.timed = timed;
@@ -918,7 +947,8 @@ bool device_time(DeviceBatch& db) {
   return true;
 }
 
-void device_fetch(DeviceBatch& db, std::vector<DevRecord>& recs, std::vector<int8_t>& colors) {
+void device_fetch(DeviceBatch& db, std::vector<DevRecord>& recs, std::vector<int8_t>& colors,
+                  std::vector<int32_t>* min_nodes) {
   mpld_context* ctx = db.ctx;
   hipStream_t s = ctx->stream;
   (void)ctx;
@@ -932,6 +962,20 @@ void device_fetch(DeviceBatch& db, std::vector<DevRecord>& recs, std::vector<int
   if (db.total_nodes)
     check_hip(hipMemcpyAsync(colors.data(), db.colors.p, colors.size(), hipMemcpyDeviceToHost, s),
               "download colors");
+  if (min_nodes) {
+    min_nodes->assign((size_t)db.num_comps, 0);
+    if (db.min_out.p && db.n_reg) {
+      std::vector<int32_t> all((size_t)db.num_comps, 0);
+      check_hip(hipMemcpyAsync(all.data(), db.min_out.p, sizeof(int32_t) * all.size(),
+                               hipMemcpyDeviceToHost, s), "download minimisation counts");
+      check_hip(hipStreamSynchronize(s), "download");
+      // only register-tier items write their entry
+      for (int32_t i = 0; i < db.n_reg; ++i) {
+        const int32_t c = db.host_queue[(size_t)i];
+        (*min_nodes)[(size_t)c] = all[(size_t)c];
+      }
+    }
+  }
   check_hip(hipStreamSynchronize(s), "download");
   for (const auto& r : recs)
     if (r.status < 0 || r.status > MPLD_BUDGET_EXHAUSTED)
@@ -940,7 +984,7 @@ void device_fetch(DeviceBatch& db, std::vector<DevRecord>& recs, std::vector<int
 
 void assemble_result(const Graph& g, const Split& s, const Image& im, const mpld_options& opt,
                      const std::vector<DevRecord>& recs, const std::vector<int8_t>& lcol,
-                     mpld_result* r) {
+                     mpld_result* r, const std::vector<int32_t>* min_nodes) {
   const bool trace = opt.flags & MPLD_TRACE_HASH;
   r->colors.assign((size_t)g.n, -1);
   r->comp_of = s.comp_of;
@@ -974,10 +1018,11 @@ void assemble_result(const Graph& g, const Split& s, const Image& im, const mpld
       if (q > x && s.comp_of[q] == c && r->colors[q] != cx) ++st;
     }
     rec.num_edges = (int32_t)(edges2 / 2);
-    const bool colored = rec.status == MPLD_FEASIBLE || (opt.flags & MPLD_MARK_CONFLICTS);
+    const bool colored =
+        rec.status == MPLD_FEASIBLE || (opt.flags & (MPLD_MARK_CONFLICTS | MPLD_MINIMIZE));
     rec.stitches = colored ? st : -1;
     rec.conflicts = (int32_t)(same2 / 2);
-    rec.reserved = 0;
+    rec.min_nodes = min_nodes && !min_nodes->empty() ? (*min_nodes)[(size_t)c] : 0;
   }
   if (opt.flags & MPLD_SIMPLIFY) recover(g, s, opt.k, r->colors);
   tallies(g, r->colors, &r->stitches, &r->conflicts, &r->uncolored);

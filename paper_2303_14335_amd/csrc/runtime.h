@@ -67,6 +67,12 @@ hipError_t launch_mark_reg(int k, int grid, RegItems items, int32_t qlen, const 
 hipError_t launch_mark_lds(int grid, int lds_bytes, const DevDesc* descs, const uint32_t* adj32,
                            int32_t qlen, const DevRecord* recs, int8_t* colors, hipStream_t s);
 int64_t mark_lds_bytes(int32_t n, int32_t k);
+// Eq. 1 minimisation (MPLD_MINIMIZE) of the register-tier items from the
+// incumbent colors in `colors`; partners: stitch partner byte per node
+// (indexed like the masks, 0xff none); min_out[comp]: nodes, negated when
+// stopped by `budget`, 0 when the incumbent costs nothing.
+hipError_t launch_min_reg(int k, int grid, RegItems items, int32_t qlen, const uint8_t* partners,
+                          int8_t* colors, int32_t* min_out, uint32_t budget, hipStream_t s);
 // LDS bytes of one LDS-tier component (adj_words = n + 1 + 2m) and the
 // global stack words of a big one.
 int64_t lds_bytes_for(int32_t n, int32_t k, int64_t adj_words, int32_t max_deg, bool big);
@@ -165,6 +171,7 @@ struct Image {
   std::vector<uint64_t> masks;     // register tier: one neighbour mask per node
   std::vector<uint8_t> partner8;   // register tier: local stitch partner per node (0xff none)
   bool stitch = false;             // MPLD_STITCH_ORDER: items carry the partners
+  bool minimize = false;           // MPLD_MINIMIZE: partner8 holds the partners
   std::vector<uint32_t> adj32;     // LDS tiers: row offsets, ids, max degree
   std::vector<int32_t> q_reg, q_lds, q_big, q_dev;   // component ids per tier
   int32_t total_nodes = 0;
@@ -222,6 +229,8 @@ struct DeviceBatch {
                     reg_stitch ? kRegItemHead + 8u * reg_width : 0u};
   }
   DevBuf dev_keys, dev_stacks;      // device-wide tier
+  DevBuf partners, min_out;         // MPLD_MINIMIZE: stitch partners, per-component node counts
+  uint32_t min_budget = 10000;      // MPLD_MINIMIZE: nodes per component
   DevBuf sp_tasks, sp_out, sp_pool, sp_writes;      // heavy-component engine
   PinnedBuf sp_host_tasks, sp_host_out, sp_host_pool, sp_host_writes, sp_host_recs;
   DevBuf en_meta, en_tasks, en_blocks, en_pool;     // device-resident rounds
@@ -263,7 +272,7 @@ void device_solve(DeviceBatch& db, uint32_t flags);
 // nodes and computes the Eq. 1 tallies.
 void assemble_result(const Graph& g, const Split& s, const Image& im, const mpld_options& opt,
                      const std::vector<DevRecord>& recs, const std::vector<int8_t>& lcol,
-                     mpld_result* r);
+                     mpld_result* r, const std::vector<int32_t>* min_nodes = nullptr);
 
 // The whole device solve: image H2D from page-locked memory, the search
 // (device_solve with `flags`), records and local colors D2H, between two
@@ -271,8 +280,11 @@ void assemble_result(const Graph& g, const Split& s, const Image& im, const mpld
 void device_roundtrip(DeviceBatch& db, const Image& im, uint32_t flags);
 // Reads the last solve's event time if the stream has passed it.
 bool device_time(DeviceBatch& db);
-// Waits, then copies records and colors back.
-void device_fetch(DeviceBatch& db, std::vector<DevRecord>& recs, std::vector<int8_t>& colors);
+// Waits, then copies records and colors back (and, when the batch was
+// packed for MPLD_MINIMIZE and min_nodes is given, the minimisation's node
+// counts per component: 0 for components off the register tier).
+void device_fetch(DeviceBatch& db, std::vector<DevRecord>& recs, std::vector<int8_t>& colors,
+                  std::vector<int32_t>* min_nodes = nullptr);
 
 }  // namespace mpld
 

@@ -33,6 +33,7 @@
 
 #include "device_types.h"
 #include "mpld.h"
+#include "reg_items.h"
 #include "wave_ops.h"
 
 namespace mpld {
@@ -56,26 +57,6 @@ __device__ __forceinline__ uint64_t trace_node(uint64_t h, uint32_t depth, uint3
   h = fnv_u32(h, row_in);
   h = fnv_u32(h, col);
   return fnv_u32(h, size);
-}
-
-__device__ __forceinline__ uint32_t rdlane(uint32_t x, uint32_t lane) {
-  return (uint32_t)__builtin_amdgcn_readlane((int)x, (int)lane);
-}
-__device__ __forceinline__ uint64_t rdlane64(uint32_t lo, uint32_t hi, uint32_t lane) {
-  return (uint64_t)rdlane(lo, lane) | ((uint64_t)rdlane(hi, lane) << 32);
-}
-// v_writelane: `old` with lane `lane` replaced by the uniform `val`.
-__device__ int mpld_writelane(int val, int lane, int old) __asm("llvm.amdgcn.writelane.i32");
-__device__ __forceinline__ uint32_t wrlane(uint32_t old, uint32_t lane, uint32_t val) {
-  return (uint32_t)mpld_writelane((int)val, (int)lane, (int)old);
-}
-// Index of the lowest set bit of a nonzero 64-bit mask.
-__device__ __forceinline__ uint32_t low_bit(uint64_t x) { return (uint32_t)__builtin_ctzll(x); }
-__device__ __forceinline__ uint32_t uniform(uint32_t x) {
-  return (uint32_t)__builtin_amdgcn_readfirstlane((int)x);
-}
-__device__ __forceinline__ uint64_t uniform64(uint64_t x) {
-  return (uint64_t)uniform((uint32_t)x) | ((uint64_t)uniform((uint32_t)(x >> 32)) << 32);
 }
 
 constexpr int bit_width(int x) { return x == 0 ? 0 : 1 + bit_width(x >> 1); }
@@ -364,23 +345,6 @@ __device__ __forceinline__ void reg_finish(const RegState<K>& s, int32_t n,
 // loads are in flight together.  cap < budget stops the search after `cap`
 // nodes (status -1 in the record: the component is left to the
 // heavy-component engine).
-__device__ __forceinline__ const DevDesc& item_desc(const RegItems& R, int32_t i) {
-  return *reinterpret_cast<const DevDesc*>(R.base + (uint64_t)i * R.stride);
-}
-__device__ __forceinline__ uint64_t item_mask(const RegItems& R, int32_t i, uint32_t lane) {
-  const uint64_t* m = reinterpret_cast<const uint64_t*>(R.base + (uint64_t)i * R.stride + kRegItemHead);
-  return lane < R.width ? m[lane] : 0ull;   // zero past n
-}
-// Stitch partner (local id) of node `lane`, 0xff for none: byte `lane` of
-// the item's partner block, which is 8-byte aligned and padded, so it is
-// read as a 32-bit word.
-__device__ __forceinline__ uint32_t item_partner(const RegItems& R, int32_t i, uint32_t lane) {
-  const uint32_t* p = reinterpret_cast<const uint32_t*>(R.base + (uint64_t)i * R.stride + R.part_off);
-  const bool in = lane < R.width;
-  const uint32_t w = p[in ? lane >> 2 : 0u];   // word 0 always exists
-  return in ? (w >> ((lane & 3u) * 8u)) & 0xffu : 0xffu;
-}
-
 template <bool TRACE, int K, bool STITCH = false>
 __device__ __forceinline__ void solve_reg(const RegItems& items, int32_t item,
                                           int8_t* __restrict__ colors_base,

@@ -573,6 +573,8 @@ void check_opts(const mpld_options* o) {
     fail(MPLD_E_UNSUPPORTED, "serving does not mark conflicts (MPLD_MARK_CONFLICTS)");
   if (o->flags & MPLD_STITCH_ORDER)
     fail(MPLD_E_UNSUPPORTED, "serving keeps the ascending row order (MPLD_STITCH_ORDER)");
+  if (o->flags & MPLD_MINIMIZE)
+    fail(MPLD_E_UNSUPPORTED, "serving does not run the Eq. 1 minimisation (MPLD_MINIMIZE)");
 }
 
 int32_t submit_request(mpld_server* s, Request* r, uint64_t* ticket) {
