@@ -379,7 +379,7 @@ def main() -> int:
                     help="skip the conflict-marking leg (MPLD_MARK_CONFLICTS on the same workload)")
     ap.add_argument("--serve-requests", type=int, default=10000,
                     help="serving leg: requests of the serving workload (0 = skip)")
-    ap.add_argument("--stitch-steps", type=int, default=5,
+    ap.add_argument("--stitch-steps", type=int, default=20,
                     help="steps of the stitch-order leg on the stitch workload (0: skip)")
     ap.add_argument("--split-only", action="store_true",
                     help="only the device simplification/split leg (for profiling its kernels)")
@@ -543,7 +543,8 @@ def main() -> int:
 
     # ---- stitch-aware row order (Eq. 1's stitch term) on the stitch
     # workload: the same batch searched in ascending row order and with
-    # MPLD_STITCH_ORDER; a separate leg, not the headline value
+    # MPLD_STITCH_ORDER, both with the heavy-component engine (each checked
+    # against its own sequential solve); a separate leg, not the headline
     stitch = None
     if args.stitch_steps:
         ws = next(c for c in CONFIGS.values() if c.split_len_nm > 0)
@@ -552,11 +553,13 @@ def main() -> int:
         legs = {}
         for name, fl in (("ascending", 0), ("stitch_order", mp.MPLD_STITCH_ORDER)):
             bs = mp.Batch(ctx, gs, ws.k, ws.budget, mp.MPLD_SIMPLIFY | fl)
-            bs.solve(direct=direct, timed=False)
+            bs.solve(direct=True, timed=False)
+            seq = bs.result()
+            bs.solve(direct=direct, split=True, timed=False)
             torch.cuda.synchronize()
             tq = time.perf_counter()
             for _ in range(args.stitch_steps):
-                bs.solve(direct=direct, timed=False)
+                bs.solve(direct=direct, split=True, timed=False)
             torch.cuda.synchronize()
             rq = bs.result()
             cs = rq.components["stitches"]
@@ -564,7 +567,10 @@ def main() -> int:
                           "search_nodes": int(rq.components["nodes"].sum()),
                           "stitches": int(rq.stitches),
                           "stitches_in_searched_components": int(cs[cs >= 0].sum()),
-                          "uncolored": int(rq.uncolored)}
+                          "uncolored": int(rq.uncolored), "heavy_engine": True,
+                          "same_as_sequential": bool(
+                              np.array_equal(rq.colors, seq.colors)
+                              and np.array_equal(rq.components["nodes"], seq.components["nodes"]))}
             bs.close()
         stitch = {"workload": ws.name, "steps": args.stitch_steps, **legs}
         log(f"stitch order: {legs['ascending']['stitches_in_searched_components']} -> "

@@ -99,7 +99,10 @@ enum {
                                   recomputed exactly from the subtrees' counts
                                   in search order (not with MPLD_TRACE_HASH; a
                                   component cut by its budget is re-run
-                                  sequentially).  Makes mpld_batch_solve wait. */
+                                  sequentially).  Makes mpld_batch_solve wait.
+                                  mpld_decompose and mpld_solve_components,
+                                  which wait anyway, use it for every untraced
+                                  solve whether or not the flag is given. */
   MPLD_UNTIMED = 1u << 9,      /* mpld_batch_solve: record no HIP events around
                                   the search (last_search_ms keeps the value of
                                   the last timed solve); for callers timing
@@ -125,8 +128,10 @@ enum {
                                   the others follow ascending.  Register tier
                                   only: components of more than 64 nodes or a
                                   forced LDS/global/device tier give
-                                  MPLD_E_UNSUPPORTED; disables
-                                  MPLD_SPLIT_HEAVY; not with a server. */
+                                  MPLD_E_UNSUPPORTED; with MPLD_SPLIT_HEAVY
+                                  the subtree tasks rebuild each path's row
+                                  order (device-resident rounds only); not
+                                  with a server. */
   MPLD_ROUNDTRIP = 1u << 12,   /* mpld_batch_solve: the whole device solve -
                                   copy of the packed image from page-locked
                                   host memory to the device, the search, copy

@@ -332,7 +332,9 @@ int32_t mpld_decompose(mpld_context* ctx, const mpld_graph* g, const mpld_option
     use_device(ctx);
     mpld_batch b;
     batch_build(ctx, g, opt, &b);
-    device_solve(b.db, opt->flags | MPLD_DIRECT);   // one-shot: no graph to capture
+    // one-shot: no graph to capture; it waits anyway, so heavy components
+    // always go to the subtree engine (untraced solves)
+    device_solve(b.db, opt->flags | MPLD_DIRECT | MPLD_SPLIT_HEAVY);
     b.solved = true;
     auto* r = new mpld_result();
     try {
@@ -381,7 +383,7 @@ int32_t mpld_solve_components(mpld_context* ctx, const mpld_component* comps, in
     DeviceBatch db;
     device_upload(ctx, im, db);
     db.min_budget = min_budget_of(opt);
-    device_solve(db, opt->flags | MPLD_DIRECT);
+    device_solve(db, opt->flags | MPLD_DIRECT | MPLD_SPLIT_HEAVY);
     std::vector<DevRecord> recs;
     std::vector<int8_t> lcol;
     std::vector<int32_t> mins;

@@ -605,8 +605,12 @@ static void heavy_engine_device(DeviceBatch& db) {
 
 static void heavy_engine_host(DeviceBatch& db);
 
+// The device-resident engine also follows the stitch-aware order (its
+// tasks rebuild each path's row order and tried sets); the host-driven one
+// replays rows in ascending order only, so stitch-ordered batches always
+// take the device engine.
 static void heavy_engine(DeviceBatch& db) {
-  if (db.tune.heavy_device) heavy_engine_device(db);
+  if (db.tune.heavy_device || db.reg_stitch) heavy_engine_device(db);
   else heavy_engine_host(db);
 }
 
@@ -852,8 +856,7 @@ void device_solve(DeviceBatch& db, uint32_t flags) {
     fail(MPLD_E_UNSUPPORTED, "a component is too large for conflict marking (" +
                                  std::to_string(db.mark_lds) + " bytes of LDS)");
   const bool trace = flags & MPLD_TRACE_HASH;
-  const bool split = (flags & MPLD_SPLIT_HEAVY) && !trace && !(flags & MPLD_PLAIN) && db.n_reg > 0 &&
-                     !db.reg_stitch;   // the subtree engine replays rows in ascending order
+  const bool split = (flags & MPLD_SPLIT_HEAVY) && !trace && !(flags & MPLD_PLAIN) && db.n_reg > 0;
   const uint64_t cap = split ? (uint64_t)db.tune.heavy_first_cap : ~0ull;
   const bool timed = !(flags & MPLD_UNTIMED) || (flags & MPLD_PLAIN);
   db.timed = false;

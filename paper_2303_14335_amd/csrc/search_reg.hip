@@ -719,11 +719,31 @@ __global__ __launch_bounds__(256) void reg_tick_kernel(
 
 // ---- heavy-component engine: subtree tasks --------------------------------
 
+// Stitch-aware order at a forward step on column v (the sequential
+// search's rule): when v's stitch partner is on the path (covered) and the
+// row of the partner's color is open, that row goes first, the rest follow
+// ascending.  In: c = v's lowest open row.  Out: the row to take and the set
+// of rows tried once it is taken.
+template <int K>
+__device__ __forceinline__ void stitch_pick(const RegState<K>& s, const uint32_t v, uint32_t& c,
+                                            uint32_t& tried) {
+  const uint32_t R = rows_of(s.O, v);
+  tried = R & ((2u << c) - 1u);
+  const uint32_t x = uniform(rdlane(s.pc, v));
+  const uint32_t p = x >> 8, cp = x & 0x1fu;
+  const bool use = p < 64u && !((s.P >> (p & 63u)) & 1ull) && ((R >> cp) & 1u);
+  c = uniform(use ? cp : c);
+  tried = uniform(use ? 1u << cp : tried);
+}
+
 // Rebuilds the search state at the end of a path of rows from the root:
 // cover each row's column and take the row, in order (the same steps the
 // sequential search made on the way down, so planes, snapshots and the
-// untried-rows set match).
-template <int K>
+// untried-rows set match).  With the stitch-aware order the row order at
+// each step is rebuilt the same way (partner colors come from the rows
+// already replayed), and the frame's tried set is every row up to the
+// path's row in that order.
+template <int K, bool STITCH = false>
 __device__ __forceinline__ void reg_replay(RegState<K>& s, const uint32_t nb_lo,
                                            const uint32_t nb_hi, const int32_t k,
                                            const uint16_t* __restrict__ rows, uint32_t d) {
@@ -731,8 +751,18 @@ __device__ __forceinline__ void reg_replay(RegState<K>& s, const uint32_t nb_lo,
     const uint32_t vc = uniform(rows[j]);
     const uint32_t v = vc & 0xffu, c = vc >> 8;
     const uint32_t R = rows_of(s.O, v);
+    uint32_t tried = 0;
+    uint64_t alt;
+    if (STITCH) {
+      uint32_t first = (uint32_t)__builtin_ctz(R), t0 = 0;
+      stitch_pick(s, v, first, t0);   // first = the row this node tries first
+      tried = c == first ? t0 : ((R & ((2u << c) - 1u)) | (1u << first));
+      alt = (R & ~tried) != 0 ? 1ull : 0ull;
+    } else {
+      alt = (R & (0xfffffffeu << c)) != 0 ? 1ull : 0ull;
+    }
     s.P &= ~(1ull << v);
-    take_row(s, rdlane64(nb_lo, nb_hi, v), v, c, (R & (0xfffffffeu << c)) != 0 ? 1ull : 0ull);
+    take_row<K, STITCH>(s, rdlane64(nb_lo, nb_hi, v), v, c, alt, tried);
     s.row_in = v * (uint32_t)k + c;
   }
 }
@@ -1000,7 +1030,7 @@ hipError_t launch_reg_split(int k, int grid, const SplitTask* tasks, int32_t nta
 // and the i-th subtask becomes task children_base + i: its path is this
 // task's path plus the rows down to depth d + levels, which sit in lanes
 // 0 .. d + levels - 1 of the frame register.
-template <int K>
+template <int K, bool STITCH = false>
 __device__ __forceinline__ int32_t engine_enumerate(RegState<K>& s, const uint32_t nb_lo,
                                                     const uint32_t nb_hi, const int32_t n,
                                                     const uint32_t d, const uint32_t levels,
@@ -1038,7 +1068,7 @@ __device__ __forceinline__ int32_t engine_enumerate(RegState<K>& s, const uint32
     seg = 0;
   };
   for (;;) {
-    uint32_t v = 0, c = 0;
+    uint32_t v = 0, c = 0, tried = 0;
     uint64_t alt = 0;
     bool back;
     if (s.depth == limit) {
@@ -1061,15 +1091,15 @@ __device__ __forceinline__ int32_t engine_enumerate(RegState<K>& s, const uint32
         v = low_bit(min_count_columns(s.O, s.P, ge2));
         c = first_color(s.O, v);
         alt = (ge2 >> v) & 1ull;
+        if (STITCH) stitch_pick(s, v, c, tried);
         s.P &= ~(1ull << v);
       }
     }
-    uint32_t tried_unused = 0;
-    if (back && !retreat(s, d, v, c, alt, tried_unused)) {
+    if (back && !retreat<K, STITCH>(s, d, v, c, alt, tried)) {
       emit(1);
       break;
     }
-    take_row(s, rdlane64(nb_lo, nb_hi, v), v, c, alt);
+    take_row<K, STITCH>(s, rdlane64(nb_lo, nb_hi, v), v, c, alt, tried);
   }
   return count;
 }
@@ -1091,7 +1121,7 @@ __global__ void engine_advance_kernel(EngineHead* head, int32_t task_cap) {
 // component whose explored nodes pass its limit, or a split that does not
 // fit, is not split (status kEngineSkipped; its reserved task slots that
 // exist are marked skip) and the host re-runs that component sequentially.
-template <int K>
+template <int K, bool STITCH>
 __global__ __launch_bounds__(256) void engine_round_kernel(
     EngineHead* __restrict__ head, EngineTask* __restrict__ tasks, int32_t task_cap,
     uint8_t* __restrict__ blocks, EngineItem* __restrict__ pool, int32_t pool_cap,
@@ -1124,10 +1154,12 @@ __global__ __launch_bounds__(256) void engine_round_kernel(
       const DevDesc dd = item_desc(regitems, it);
       const uint64_t nb = item_mask(regitems, it, lane);
       const uint32_t nb_lo = (uint32_t)nb, nb_hi = (uint32_t)(nb >> 32);
+      const uint32_t part = STITCH ? (item_partner(regitems, it, lane) << 8) | 0xffu : 0u;
       RegState<K> s;
       reg_init(s, dd.n, dd.k);
-      reg_replay(s, nb_lo, nb_hi, dd.k, task->rows, d);
-      reg_run<false, K>(s, nb_lo, nb_hi, dd.k, ~0ull, cap, d);
+      if (STITCH) s.pc = part;
+      reg_replay<K, STITCH>(s, nb_lo, nb_hi, dd.k, task->rows, d);
+      reg_run<false, K, STITCH>(s, nb_lo, nb_hi, dd.k, ~0ull, cap, d);
       res.nodes = s.nodes;
       if (s.status == MPLD_FEASIBLE) {
         if (lane < s.depth && (s.fr & 0xffu) < (uint32_t)dd.n)
@@ -1141,10 +1173,11 @@ __global__ __launch_bounds__(256) void engine_round_kernel(
         // could be merged with the queue pop's and split the wave).
         RegState<K> r;
         reg_init(r, dd.n, dd.k);
-        reg_replay(r, nb_lo, nb_hi, dd.k, task->rows, d);
+        if (STITCH) r.pc = part;
+        reg_replay<K, STITCH>(r, nb_lo, nb_hi, dd.k, task->rows, d);
         int32_t nchild = 0;
-        const int32_t nitems = engine_enumerate(r, nb_lo, nb_hi, dd.n, d, levels, nullptr, nullptr,
-                                                0, it, hc, sol, nchild);
+        const int32_t nitems = engine_enumerate<K, STITCH>(r, nb_lo, nb_hi, dd.n, d, levels, nullptr,
+                                                           nullptr, 0, it, hc, sol, nchild);
         // the component's explored nodes: the guard reads the total as of
         // the previous round (a plain load), and the add does not wait for
         // its result, so the reservations are the only round trips
@@ -1166,10 +1199,11 @@ __global__ __launch_bounds__(256) void engine_round_kernel(
                           (int64_t)cb + nchild <= task_cap;
         if (fits) {
           reg_init(r, dd.n, dd.k);
-          reg_replay(r, nb_lo, nb_hi, dd.k, task->rows, d);
+          if (STITCH) r.pc = part;
+          reg_replay<K, STITCH>(r, nb_lo, nb_hi, dd.k, task->rows, d);
           int32_t nc2 = 0;
-          engine_enumerate(r, nb_lo, nb_hi, dd.n, d, levels, pool + io, tasks, (int32_t)cb, it, hc,
-                           sol, nc2);
+          engine_enumerate<K, STITCH>(r, nb_lo, nb_hi, dd.n, d, levels, pool + io, tasks,
+                                      (int32_t)cb, it, hc, sol, nc2);
           res.status = -1;
           res.nitems = nitems;
           res.item_off = io;
@@ -1207,10 +1241,15 @@ hipError_t launch_engine_round(int k, int grid, EngineHead* head, EngineTask* ta
                                unsigned long long* hc_nodes, const uint64_t* hc_limit,
                                uint64_t cap, uint32_t levels, hipStream_t s) {
   if (levels < 1 || levels > (uint32_t)kSplitMaxLevels) return hipErrorInvalidValue;
+  const bool stitch = regitems.part_off != 0;   // the items carry stitch partners
   with_planes(k, [&](auto kp) {
     constexpr int K = decltype(kp)::value;
-    hipLaunchKernelGGL((engine_round_kernel<K>), dim3(grid), dim3(256), 0, s, head, tasks, task_cap,
-                       blocks, pool, pool_cap, regitems, hc_nodes, hc_limit, cap, levels);
+    if (stitch)
+      hipLaunchKernelGGL((engine_round_kernel<K, true>), dim3(grid), dim3(256), 0, s, head, tasks,
+                         task_cap, blocks, pool, pool_cap, regitems, hc_nodes, hc_limit, cap, levels);
+    else
+      hipLaunchKernelGGL((engine_round_kernel<K, false>), dim3(grid), dim3(256), 0, s, head, tasks,
+                         task_cap, blocks, pool, pool_cap, regitems, hc_nodes, hc_limit, cap, levels);
   });
   return hipGetLastError();
 }

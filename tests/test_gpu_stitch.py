@@ -148,3 +148,59 @@ def test_stitch_rejects_other_tiers(ctx):
         srv.submit(small, 3, 100, SIMPLIFY | STITCH)
     assert e.value.code == -7   # MPLD_E_UNSUPPORTED
     srv.close()
+
+
+def heavy_stitch_layout(rng, k, count, deg):
+    """Components of 40-64 nodes near the colorability threshold (long
+    searches) with random stitch pairs between non-adjacent nodes."""
+    ce, se, base = [], [], 0
+    for _ in range(count):
+        n = int(rng.integers(40, 65))
+        e = random_graph(rng, n, deg / n)
+        adj = {tuple(x) for x in e} | {(b, a) for a, b in e}
+        used = set()
+        for _ in range(n):
+            a, b = (int(x) for x in rng.integers(0, n, 2))
+            if a != b and a not in used and b not in used and (a, b) not in adj:
+                used |= {a, b}
+                se.append((base + a, base + b))
+        ce += [(base + a, base + b) for a, b in e]
+        base += n
+    return base, np.array(ce, np.int32).reshape(-1, 2), np.array(se, np.int32).reshape(-1, 2)
+
+
+@pytest.mark.parametrize("k,deg,budget", [(3, 4.6, 300000), (4, 8.4, 300000), (3, 4.6, 20000)])
+def test_stitch_with_heavy_engine(ctx, k, deg, budget):
+    """The subtree engine under the stitch-aware order: tasks rebuild each
+    path's row order and tried sets, so status, node count, depth and colors
+    equal the sequential stitch-ordered search (budget cuts re-run
+    sequentially); small caps force many rounds and deep splits."""
+    import paper_2303_14335_amd as mp
+    rng = np.random.default_rng(900 + 10 * k + (budget > 100000))
+    n, ce, se = heavy_stitch_layout(rng, k, 30, deg)
+    ref = oracle.decompose(oracle.Graph(n, ce, se), k, budget, simplify=False, stitch=True)
+    assert int(ref.comps["nodes"].max()) > 1000
+    g = mp.Graph(n, ce, se)
+    say("stitch order with the heavy engine, k", k, "budget", budget)
+    b = mp.Batch(ctx, g, k, budget, STITCH)
+    for caps in ((64, 16, 0), (128, 256, 2), (256, 64, 1)):
+        b.set_tune(heavy_first_cap=caps[0], heavy_round_cap=caps[1], heavy_levels=caps[2],
+                   heavy_device=0)   # the host-driven setting still takes the device rounds
+        b.solve(split=True)
+        compare(b.result(), ref, UNTRACED)
+    info = b.info()
+    assert info["heavy_components"] > 0 and info["split_rounds"] >= 2
+    b.close()
+
+
+def test_stitch_config2_heavy_engine(ctx):
+    import paper_2303_14335_amd as mp
+    w, g = config_graph(2)
+    say("stitch order, config 2, heavy engine")
+    ref = oracle.decompose(oracle.Graph(g.num_nodes, g.ce, g.se), w.k, w.budget, stitch=True)
+    b = mp.Batch(ctx, g, w.k, w.budget, SIMPLIFY | STITCH)
+    for _ in range(2):
+        b.solve(split=True)
+        compare(b.result(), ref, UNTRACED)
+    assert b.info()["heavy_components"] > 0
+    b.close()
