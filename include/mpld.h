@@ -395,6 +395,30 @@ int32_t mpld_solve_components(mpld_context* ctx, const mpld_component* comps,
                               int32_t count, const mpld_options* opt,
                               mpld_comp_record* out, int8_t* colors_out);
 
+/* ---- components without any allocation ---------------------------------
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  The same
+ * result as mpld_solve_components (records and colors, bit for bit) for
+ * components of at most 64 nodes each, flags MPLD_TRACE_HASH and
+ * MPLD_MARK_CONFLICTS (others: MPLD_E_UNSUPPORTED).  Every device buffer
+ * the call needs - queue counter, records, local colors, packed items -
+ * lives in one fixed device array of MPLD_NOALLOC_SCRATCH_BYTES per GPU
+ * (held until the process ends), and the host staging in static memory:
+ * the call makes no hipMalloc, hipFree or other allocation on success.
+ * Limits: at most MPLD_NOALLOC_MAX_COMPONENTS components, and 256 +
+ * 24 x count (rounded up to 256) + sum of n (rounded up to 256) +
+ * count x (32 + 8 x largest n) bytes within the scratch; beyond either,
+ * MPLD_E_INVALID.  Inputs and outputs are the caller's host memory, as in
+ * mpld_solve_components.  All calls on one GPU share its array and leave
+ * their contents in it; calls overlapping on one GPU race (within one
+ * process they are serialised by a lock).  Synchronous on the context's
+ * stream. */
+#define MPLD_NOALLOC_SCRATCH_BYTES (32u << 20)
+#define MPLD_NOALLOC_MAX_COMPONENTS (1 << 18)
+int32_t mpld_solve_components_noalloc(mpld_context* ctx, const mpld_component* comps,
+                                      int32_t count, const mpld_options* opt,
+                                      mpld_comp_record* out, int8_t* colors_out);
+
 /* ---- serving: continuous batching of whole-layout requests --------------
  * A server owns a context's stream from a scheduler thread.  Requests are
  * copied at submit and run through the host front-end on worker threads;

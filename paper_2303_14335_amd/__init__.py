@@ -371,10 +371,8 @@ def mpld_batch_set_tune(b: Batch, **kw) -> None:
     b.set_tune(**kw)
 
 
-def mpld_solve_components(ctx: Context, comps, k: int, budget: int, flags: int = 0,
-                          min_budget: int = 0):
-    """comps: list of (n, edges [m, 2]) in local numbering.  Returns
-    (records RECORD_DTYPE[count], list of per-component int8 colors)."""
+def _solve_components(fn, name, ctx: Context, comps, k: int, budget: int, flags: int,
+                      min_budget: int):
     arrs = []
     cs = (_ffi.mpld_component * max(len(comps), 1))()
     total = 0
@@ -386,14 +384,28 @@ def mpld_solve_components(ctx: Context, comps, k: int, budget: int, flags: int =
     recs = (_ffi.mpld_comp_record * max(len(comps), 1))()
     colors = np.zeros(max(total, 1), dtype=np.int8)
     opt = options(k, budget, flags, min_budget)
-    _check(_lib.mpld_solve_components(ctx.handle, cs, len(comps), ctypes.byref(opt), recs,
-                                      colors.ctypes.data), "mpld_solve_components")
+    _check(fn(ctx.handle, cs, len(comps), ctypes.byref(opt), recs, colors.ctypes.data), name)
     out = np.frombuffer(bytes(recs), dtype=RECORD_DTYPE)[: len(comps)].copy()
     per, off = [], 0
     for n, _ in comps:
         per.append(colors[off: off + n].copy())
         off += n
     return out, per
+
+
+def mpld_solve_components(ctx: Context, comps, k: int, budget: int, flags: int = 0,
+                          min_budget: int = 0):
+    """comps: list of (n, edges [m, 2]) in local numbering.  Returns
+    (records RECORD_DTYPE[count], list of per-component int8 colors)."""
+    return _solve_components(_lib.mpld_solve_components, "mpld_solve_components", ctx, comps, k,
+                             budget, flags, min_budget)
+
+
+def mpld_solve_components_noalloc(ctx: Context, comps, k: int, budget: int, flags: int = 0):
+    """As mpld_solve_components, through the entry point that allocates
+    nothing (components of at most 64 nodes, fixed device scratch)."""
+    return _solve_components(_lib.mpld_solve_components_noalloc, "mpld_solve_components_noalloc",
+                             ctx, comps, k, budget, flags, 0)
 
 
 # ---- serving ----------------------------------------------------------------

@@ -127,6 +127,8 @@ SIGNATURES = {
     "mpld_batch_set_tune": (c_i32, [vp, P(mpld_tune)]),
     "mpld_solve_components": (c_i32, [vp, P(mpld_component), c_i32, P(mpld_options),
                                       P(mpld_comp_record), vp]),
+    "mpld_solve_components_noalloc": (c_i32, [vp, P(mpld_component), c_i32, P(mpld_options),
+                                              P(mpld_comp_record), vp]),
     "mpld_result_colors": (vp, [vp, P(c_i32)]),
     "mpld_result_component_of": (vp, [vp]),
     "mpld_result_num_components": (c_i32, [vp]),
