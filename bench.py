@@ -36,13 +36,27 @@ def log(*a):
 
 
 def kernel_source_hash() -> str:
-    """Hash of the register-tier kernel's sources and of the build script
-    (flags): the stored traffic counters belong to that kernel."""
+    """Hash of the register-tier kernel's sources and of its compile flags
+    (include paths left out, as they differ between machines): the stored
+    traffic counters belong to that kernel."""
+    import importlib.util
     h = hashlib.sha256()
     pkg = os.path.join(ROOT, "paper_2303_14335_amd")
-    for f in ("csrc/search_reg.hip", "csrc/device_types.h", "build.py"):
+    for f in ("csrc/search_reg.hip", "csrc/reg_items.h", "csrc/wave_ops.h", "csrc/device_types.h"):
         with open(os.path.join(pkg, f), "rb") as fh:
             h.update(fh.read())
+    spec = importlib.util.spec_from_file_location("_mpld_build_flags", os.path.join(pkg, "build.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    flags, skip = [], False
+    for x in mod.COMMON + mod.EXTRA.get("search_reg.hip", []):
+        if skip:
+            skip = False
+        elif x == "-I":
+            skip = True
+        else:
+            flags.append(x)
+    h.update(" ".join(flags).encode())
     return h.hexdigest()[:16]
 
 
@@ -325,7 +339,35 @@ PROBES = [
 ]
 
 
-def latency_probe(mp, ctx, reps=3, names=None):
+def lds_rate(mp, ctx):
+    """The chip's LDS read rate with ds_read_b64 and ds_read_b128 (every CU,
+    no bank conflicts)."""
+    import torch
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    out = {"cus": cus}
+    for width in (8, 16):
+        r = mp.mpld_measure_lds_read_rate(ctx, width, 2000)
+        out[f"ds_read_b{8 * width}"] = {"GBps": round(r["GBps"], 1),
+                                        "bytes_per_clock_per_cu": round(r["bytes_per_clock_per_cu"], 2)}
+    out["peak_GBps"] = max(out["ds_read_b64"]["GBps"], out["ds_read_b128"]["GBps"])
+    return out
+
+
+def bitset_bytes_per_node(n: int, k: int, avg_degree: float) -> int:
+    """Algorithmic bytes per search node of the bitset search: the k + 1
+    planes of W = ceil(n / 64) words read by the count, 3 d_w words for the
+    cover, the removed words kept and the uncover (d_w = min(W, mean degree
+    rounded up)), 2 words of stack: 8 ((k + 1) W + 3 d_w + 2)."""
+    import math
+    w = (n + 63) // 64
+    dw = min(w, max(1, math.ceil(avg_degree)))
+    return 8 * ((k + 1) * w + 3 * dw + 2)
+
+
+def latency_probe(mp, ctx, reps=3, names=None, lds=None):
+    """lds: the measured LDS read rate (lds_rate()); the LDS-tier probes then
+    carry their bitset bytes per node over their time as a fraction of one
+    CU's share of it (a component runs on one CU)."""
     import numpy as np
     import torch
     import workload
@@ -346,6 +388,13 @@ def latency_probe(mp, ctx, reps=3, names=None):
         b.close()
         out[name] = {"n": n, "k": k, "avg_degree": deg, "seed": seed, "nodes": nodes,
                      "ms": round(min(ms), 4), "ns_per_node": round(1e6 * min(ms) / max(nodes, 1), 2)}
+        bpn = bitset_bytes_per_node(n, k, deg)
+        gbps = bpn * nodes / (min(ms) * 1e-3) / 1e9
+        out[name]["bitset_bytes_per_node"] = bpn
+        out[name]["bitset_GBps"] = round(gbps, 3)
+        if lds and flag != "MPLD_FORCE_WAVE":
+            per_cu = lds["peak_GBps"] / lds["cus"]
+            out[name]["lds_frac_of_one_cu"] = gbps / per_cu
     return out
 
 
@@ -412,7 +461,8 @@ def main() -> int:
     if args.probe_only:
         ctx = mp.Context(0)
         names = [x for x in args.probes.split(",") if x]
-        out = {"latency_probe": latency_probe(mp, ctx, names=names)}
+        lds = lds_rate(mp, ctx)
+        out = {"lds_rate": lds, "latency_probe": latency_probe(mp, ctx, names=names, lds=lds)}
         torch.cuda.synchronize()
         ctx.close()
         print(json.dumps(out), flush=True)
@@ -593,9 +643,7 @@ def main() -> int:
     # per node its neighbour mask or adjacency words and its 1 B color) are
     # reported beside it.
     def node_bytes(n, m):
-        wds = (n + 63) // 64
-        dw = min(wds, max(1, -(-2 * m // max(n, 1))))
-        return 8 * ((w.k + 1) * wds + 3 * dw + 2)
+        return bitset_bytes_per_node(n, w.k, 2 * m / max(n, 1))
 
     algo_bytes = int(sum(int(c["nodes"]) * node_bytes(int(c["size"]), int(c["num_edges"]))
                          for c in comps))
@@ -688,8 +736,9 @@ def main() -> int:
     log("device split leg")
     out["device_split"] = split_leg(mp, ctx)
     if not args.no_latency_probe:
-        log("latency probes")
-        out["latency_probe"] = latency_probe(mp, ctx)
+        log("LDS read rate and latency probes")
+        out["lds_rate"] = lds_rate(mp, ctx)
+        out["latency_probe"] = latency_probe(mp, ctx, lds=out["lds_rate"])
     if args.serve_requests:
         log(f"serving leg: {args.serve_requests} requests")
         out["serving"] = serve_leg(mp, ctx, args.serve_requests, 0)

@@ -479,6 +479,19 @@ int32_t mpld_server_get_stats(mpld_server* s, mpld_server_stats* out);
  * complete with MPLD_E_CANCELLED (their results cannot be fetched). */
 int32_t mpld_server_destroy(mpld_server* s);
 
+/* ---- measurement ----------------------------------------------------------
+ * The chip's LDS read rate, for the roofline of the LDS-tier kernels (Sec.
+ * 2.3 keeps the matrix cover in on-chip shared memory): every CU runs
+ * workgroups of 256 lanes that read 32 KB of LDS each with ds_read_b64
+ * (bytes_per_lane = 8) or ds_read_b128 (16), iters x 16 reads per lane,
+ * contiguous per wave (no bank conflicts); *gbytes_per_s = bytes read over
+ * the kernel time of the second of two runs (HIP events on the context
+ * stream), *bytes_per_clock_per_cu (may be NULL) the same per CU and cycle
+ * of the device's reported clock.  Synchronous.  MPLD_E_INVALID for a
+ * NULL pointer, another width or iters outside [1, 2^24]. */
+int32_t mpld_measure_lds_read_rate(mpld_context* ctx, int32_t bytes_per_lane, int32_t iters,
+                                   double* gbytes_per_s, double* bytes_per_clock_per_cu);
+
 /* ---- results ------------------------------------------------------------ */
 const int8_t* mpld_result_colors(const mpld_result* r, int32_t* num_nodes);
 const int32_t* mpld_result_component_of(const mpld_result* r); /* -1 = removed */

@@ -408,6 +408,15 @@ def mpld_solve_components_noalloc(ctx: Context, comps, k: int, budget: int, flag
                              ctx, comps, k, budget, flags, 0)
 
 
+def mpld_measure_lds_read_rate(ctx: Context, bytes_per_lane: int = 16, iters: int = 2000) -> dict:
+    """The chip's LDS read rate (ds_read_b64 / ds_read_b128 on every CU)."""
+    gbps = ctypes.c_double()
+    per = ctypes.c_double()
+    _check(_lib.mpld_measure_lds_read_rate(ctx.handle, bytes_per_lane, iters, ctypes.byref(gbps),
+                                           ctypes.byref(per)), "mpld_measure_lds_read_rate")
+    return {"GBps": gbps.value, "bytes_per_clock_per_cu": per.value}
+
+
 # ---- serving ----------------------------------------------------------------
 
 class Server:

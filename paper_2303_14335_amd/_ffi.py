@@ -129,6 +129,8 @@ SIGNATURES = {
                                       P(mpld_comp_record), vp]),
     "mpld_solve_components_noalloc": (c_i32, [vp, P(mpld_component), c_i32, P(mpld_options),
                                               P(mpld_comp_record), vp]),
+    "mpld_measure_lds_read_rate": (c_i32, [vp, c_i32, c_i32, P(ctypes.c_double),
+                                           P(ctypes.c_double)]),
     "mpld_result_colors": (vp, [vp, P(c_i32)]),
     "mpld_result_component_of": (vp, [vp]),
     "mpld_result_num_components": (c_i32, [vp]),

@@ -14,7 +14,7 @@ LIB = os.path.join(HERE, "libmpld.so")
 
 SOURCES = ["frontend.cpp", "runtime.cpp", "abi.cpp", "serve.cpp", "autotune.cpp", "search_reg.hip",
            "search_lds.hip", "search_device.hip", "graph_device.hip", "search_min.hip",
-           "noalloc.hip"]
+           "noalloc.hip", "measure.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # -packed-fp32-ops: never emit packed fp32 ALU ops in device code.

@@ -1,0 +1,108 @@
+// measure.hip - LDS read-rate measurement used for the roofline of the
+// LDS-tier kernels: every CU runs workgroups that read their LDS with
+// ds_read_b64 or ds_read_b128 (each wave reads contiguous bytes, so no bank
+// conflicts), and the bytes read over the kernel's time give the chip's
+// achievable LDS read rate.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "internal.h"
+#include "mpld.h"
+#include "runtime.h"
+
+namespace mpld {
+
+constexpr int kLdsProbeThreads = 256;
+constexpr int kLdsProbeUnroll = 16;
+
+// 32 KB of LDS per workgroup (five workgroups, twenty waves, per CU).  Per
+// iteration a lane reads kLdsProbeUnroll vectors at immediate offsets from
+// a base that alternates between two halves; an empty asm statement with a
+// memory clobber ends every iteration, so the compiler must read LDS again
+// (it may not hoist the loads or fold the XORs across iterations), and the
+// XOR of everything read is kept so that the loads are not removed.
+template <typename V>
+__global__ __launch_bounds__(kLdsProbeThreads) void lds_read_kernel(uint32_t iters,
+                                                                    uint32_t* __restrict__ sink) {
+  constexpr int kElems = 32768 / (int)sizeof(V);
+  constexpr int kStride = (kElems - 2 * kLdsProbeThreads) / kLdsProbeUnroll;
+  __shared__ V buf[kElems];
+  for (int i = threadIdx.x; i < kElems; i += kLdsProbeThreads) {
+    V v;
+    uint32_t* w = reinterpret_cast<uint32_t*>(&v);
+    for (int j = 0; j < (int)(sizeof(V) / 4); ++j) w[j] = (uint32_t)(i * 4 + j);
+    buf[i] = v;
+  }
+  __syncthreads();
+  uint32_t acc = 0;
+  for (uint32_t it = 0; it < iters; ++it) {
+    const V* p = buf + threadIdx.x + ((it & 1u) ? kLdsProbeThreads : 0);
+#pragma unroll
+    for (int j = 0; j < kLdsProbeUnroll; ++j) {
+      const V v = p[j * kStride];
+      const uint32_t* w = reinterpret_cast<const uint32_t*>(&v);
+#pragma unroll
+      for (int q = 0; q < (int)(sizeof(V) / 4); ++q) acc ^= w[q];
+    }
+    __asm__ volatile("" ::: "memory");
+  }
+  if (acc == 0x9e3779b9u) sink[blockIdx.x] = acc;   // never true for these contents in practice
+}
+
+}  // namespace mpld
+
+using namespace mpld;
+
+extern "C" int32_t mpld_measure_lds_read_rate(mpld_context* ctx, int32_t bytes_per_lane,
+                                              int32_t iters, double* gbytes_per_s,
+                                              double* bytes_per_clock_per_cu) {
+  try {
+    if (!ctx || !gbytes_per_s) fail(MPLD_E_INVALID, "NULL argument");
+    if (bytes_per_lane != 8 && bytes_per_lane != 16)
+      fail(MPLD_E_INVALID, "bytes_per_lane must be 8 (ds_read_b64) or 16 (ds_read_b128)");
+    if (iters < 1 || iters > (1 << 24)) fail(MPLD_E_INVALID, "iters must be in [1, 2^24]");
+    check_hip(hipSetDevice(ctx->device), "hipSetDevice");
+    hipStream_t s = ctx->stream;
+    const int grid = ctx->num_cus * 5 * 8;   // five resident workgroups per CU, eight rounds
+    DevBuf sink;
+    sink.alloc(ctx, sizeof(uint32_t) * (size_t)grid);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    check_hip(hipEventCreate(&e0), "event");
+    check_hip(hipEventCreate(&e1), "event");
+    float ms = 0.f;
+    hipError_t err = hipSuccess;
+    for (int rep = 0; rep < 2 && err == hipSuccess; ++rep) {   // the first run warms up
+      err = hipEventRecord(e0, s);
+      if (bytes_per_lane == 8)
+        hipLaunchKernelGGL((lds_read_kernel<uint2>), dim3(grid), dim3(kLdsProbeThreads), 0, s,
+                           (uint32_t)iters, sink.as<uint32_t>());
+      else
+        hipLaunchKernelGGL((lds_read_kernel<uint4>), dim3(grid), dim3(kLdsProbeThreads), 0, s,
+                           (uint32_t)iters, sink.as<uint32_t>());
+      if (err == hipSuccess) err = hipGetLastError();
+      if (err == hipSuccess) err = hipEventRecord(e1, s);
+      if (err == hipSuccess) err = hipEventSynchronize(e1);
+      if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    check_hip(err, "LDS read-rate kernel");
+    const double bytes = (double)grid * kLdsProbeThreads * (double)iters * kLdsProbeUnroll *
+                         (double)bytes_per_lane;
+    *gbytes_per_s = bytes / ((double)ms * 1e-3) / 1e9;
+    if (bytes_per_clock_per_cu) {
+      int khz = 0;
+      check_hip(hipDeviceGetAttribute(&khz, hipDeviceAttributeClockRate, ctx->device), "clock rate");
+      *bytes_per_clock_per_cu = khz > 0 ? *gbytes_per_s * 1e9 / ((double)khz * 1e3) / ctx->num_cus : 0.0;
+    }
+    set_last_error("");
+    return MPLD_OK;
+  } catch (const Error& e) {
+    set_last_error(e.what);
+    return e.code;
+  } catch (...) {
+    set_last_error("unexpected exception in the LDS read-rate measurement");
+    return MPLD_E_INTERNAL;
+  }
+}
