@@ -52,6 +52,28 @@ struct DevRecord {
 };
 static_assert(sizeof(DevRecord) == 24, "record is 24 bytes");
 
+// A subtree task of an LDS-tier or big-tier component (the heavy-component
+// split beyond the register tier): the subtree of root row `row` searched
+// with its own node budget; its colors go to task colors + col_off.
+struct LdsTask {
+  int32_t item;        // launch-ordered descriptor index
+  int32_t row;         // root row (color of node 0)
+  int64_t budget;      // >= 1
+  int64_t col_off;
+};
+static_assert(sizeof(LdsTask) == 24, "LDS task is 24 bytes");
+// A resolved LDS-tier or big-tier component of the split: its record and
+// where its colors come from.
+struct LdsResolved {
+  int32_t comp;        // record index
+  int32_t out_off;     // first color entry
+  int32_t n;
+  int32_t pad;
+  int64_t src_off;     // colors in the task color area, -1: none (all -1)
+  DevRecord rec;
+};
+static_assert(sizeof(LdsResolved) == 48, "resolved entry is 48 bytes");
+
 // Heavy-component engine (parallel subtree search).  A task is the subtree
 // of the node reached from a component's root by taking `depth` rows
 // (v | c << 8 each).

@@ -300,7 +300,9 @@ void device_roundtrip(DeviceBatch& db, const Image& im, uint32_t flags) {
   db.rt_timed = true;
 }
 
-static void enqueue_batched(DeviceBatch& db, bool trace, uint64_t cap, hipStream_t s) {
+// split: the LDS and big tiers are left to csr_split (subtree tasks).
+static void enqueue_batched(DeviceBatch& db, bool trace, uint64_t cap, hipStream_t s,
+                            bool split = false) {
   const auto* desc = db.desc.as<DevDesc>();
   const RegItems items = db.reg_items();
   const auto* adj = db.adj32.as<uint32_t>();
@@ -317,13 +319,13 @@ static void enqueue_batched(DeviceBatch& db, bool trace, uint64_t cap, hipStream
               "register-tier launch");
     ++db.launches;
   }
-  if (db.n_lds) {
+  if (db.n_lds && !split) {
     check_hip(launch_lds_batched(trace, false, 1, db.grid_lds, db.lds_small, desc + db.n_reg, adj,
                                  db.n_lds, cnt + 1, nullptr, 0, recs, colors, s),
               "LDS-tier launch");
     ++db.launches;
   }
-  if (db.n_big) {
+  if (db.n_big && !split) {
     check_hip(launch_lds_batched(trace, true, db.big_waves, db.grid_big, db.lds_big, desc + db.n_reg + db.n_lds,
                                  adj, db.n_big, cnt + 2, gstack, db.big_stack_words, recs, colors,
                                  s),
@@ -603,6 +605,188 @@ static void heavy_engine_device(DeviceBatch& db) {
   check_hip(hipStreamSynchronize(s), "heavy: write back");
 }
 
+// LDS-tier and big-tier components as subtree tasks (untraced).  At the
+// root every column has all k rows, so the root column is node 0 and the
+// root node's children are its k rows; task (component, c) searches the
+// subtree of root row c with budget B - 1 (the root node is counted once,
+// here).  The sequential result follows from the tasks in row order: acc
+// starts at 1; an exhausted subtree adds its count and the next row
+// follows; a subtree holding a solution ends the search (FEASIBLE, acc +
+// its count, its depth and colors); the budget reached exactly before a
+// row means the next node entry fails its test (BUDGET at depth 1); a
+// subtree whose count would cross the budget (or that ran into it) is where
+// the sequential search stops: it is searched again with budget B - acc for
+// the depth at the stop (row 0's task already ran with exactly that
+// budget).  Every row exhausted: INFEASIBLE with acc nodes.
+static void csr_split(DeviceBatch& db) {
+  const int32_t first = db.n_reg, count = db.n_lds + db.n_big;
+  if (count == 0) return;
+  mpld_context* ctx = db.ctx;
+  hipStream_t s = ctx->stream;
+  struct Comp {
+    int32_t pos = 0;      // launch position
+    uint64_t acc = 1;
+    int32_t rerun_row = -1;
+    bool done = false;
+    LdsResolved res{};
+  };
+  std::vector<Comp> comps((size_t)count);
+  std::vector<LdsTask> tasks;
+  std::vector<int32_t> task_of((size_t)count, -1);   // first phase-1 task of each component
+  int64_t col = 0;
+  for (int32_t i = 0; i < count; ++i) {
+    Comp& cp = comps[(size_t)i];
+    cp.pos = first + i;
+    const DevDesc& d = db.host_desc[(size_t)cp.pos];
+    cp.res.comp = d.comp;
+    cp.res.out_off = d.out_off;
+    cp.res.n = d.n;
+    cp.res.src_off = -1;
+    cp.res.rec.hash = 0xcbf29ce484222325ull;
+    if (d.budget == 1) {   // the root takes the whole budget
+      cp.res.rec.status = MPLD_BUDGET_EXHAUSTED;
+      cp.res.rec.nodes = 1;
+      cp.res.rec.depth = 1;
+      cp.done = true;
+      continue;
+    }
+    task_of[(size_t)i] = (int32_t)tasks.size();
+    for (int32_t c = 0; c < d.k; ++c) {
+      tasks.push_back(LdsTask{cp.pos, c, d.budget - 1, col});
+      col += d.n;
+    }
+  }
+  // Runs a task list (LDS-tier tasks before big-tier ones, as built) and
+  // returns their records; task colors land in ct_colors at their col_off.
+  auto run = [&](const std::vector<LdsTask>& list, int64_t colors_bytes) {
+    std::vector<DevRecord> out(list.size());
+    if (list.empty()) return out;
+    size_t nsmall = 0;
+    while (nsmall < list.size() && list[nsmall].item < first + db.n_lds) ++nsmall;
+    const size_t tb = sizeof(LdsTask) * list.size(), rb = sizeof(DevRecord) * list.size();
+    if (db.ct_tasks.bytes < tb) db.ct_tasks.alloc(ctx, tb);
+    if (db.ct_recs.bytes < rb) db.ct_recs.alloc(ctx, rb);
+    if (db.ct_colors.bytes < (size_t)std::max<int64_t>(colors_bytes, 1))
+      db.ct_colors.alloc(ctx, (size_t)std::max<int64_t>(colors_bytes, 1));
+    if (!db.ct_host.reserve(std::max(tb, rb))) fail(MPLD_E_NOMEM, "subtree tasks: pinned host memory");
+    std::memcpy(db.ct_host.p, list.data(), tb);
+    check_hip(hipMemcpyAsync(db.ct_tasks.p, db.ct_host.p, tb, hipMemcpyHostToDevice, s),
+              "subtree tasks: upload");
+    const auto* dt = db.ct_tasks.as<LdsTask>();
+    auto* drec = db.ct_recs.as<DevRecord>();
+    if (nsmall)
+      check_hip(launch_lds_tasks(false, 1,
+                                 std::max(1, std::min((int)nsmall, blocks_for_lds(ctx, db.lds_small))),
+                                 db.lds_small, db.desc.as<DevDesc>(), db.adj32.as<uint32_t>(), dt,
+                                 (int32_t)nsmall, nullptr, 0, drec, db.ct_colors.as<int8_t>(), s),
+                "subtree tasks (LDS tier)");
+    if (nsmall < list.size())
+      check_hip(launch_lds_tasks(true, db.big_waves,
+                                 std::max(1, std::min((int)(list.size() - nsmall), db.grid_big)),
+                                 db.lds_big, db.desc.as<DevDesc>(), db.adj32.as<uint32_t>(),
+                                 dt + nsmall, (int32_t)(list.size() - nsmall), db.gstack.as<uint64_t>(),
+                                 db.big_stack_words, drec + nsmall, db.ct_colors.as<int8_t>(), s),
+                "subtree tasks (big tier)");
+    check_hip(hipMemcpyAsync(db.ct_host.p, drec, rb, hipMemcpyDeviceToHost, s), "subtree tasks: records");
+    check_hip(hipStreamSynchronize(s), "subtree tasks");
+    std::memcpy(out.data(), db.ct_host.p, rb);
+    return out;
+  };
+  const std::vector<DevRecord> r1 = run(tasks, col);
+  db.sp_tasks_run += (int64_t)tasks.size();
+  // resolve in row order; collect the re-runs
+  std::vector<LdsTask> again;
+  std::vector<int32_t> again_comp;
+  for (int32_t i = 0; i < count; ++i) {
+    Comp& cp = comps[(size_t)i];
+    if (cp.done) continue;
+    const DevDesc& d = db.host_desc[(size_t)cp.pos];
+    const uint64_t B = (uint64_t)d.budget;
+    const int32_t t0 = task_of[(size_t)i];
+    for (int32_t c = 0; c < d.k; ++c) {
+      if (cp.acc == B) {   // the next node entry fails its budget test
+        cp.res.rec.status = MPLD_BUDGET_EXHAUSTED;
+        cp.res.rec.nodes = B;
+        cp.res.rec.depth = 1;
+        cp.done = true;
+        break;
+      }
+      const DevRecord& r = r1[(size_t)(t0 + c)];
+      const bool fits = cp.acc + r.nodes <= B;
+      if (r.status == MPLD_INFEASIBLE && fits) {
+        cp.acc += r.nodes;
+        continue;
+      }
+      if ((r.status == MPLD_FEASIBLE && fits) || c == 0) {
+        // a solution inside the budget, or row 0, which ran with exactly
+        // the budget left (B - 1): the task's result is the search's
+        cp.res.rec.status = r.status;
+        cp.res.rec.nodes = cp.acc + r.nodes;
+        cp.res.rec.depth = r.status == MPLD_INFEASIBLE ? 0 : r.depth;
+        if (r.status == MPLD_FEASIBLE) cp.res.src_off = tasks[(size_t)(t0 + c)].col_off;
+        cp.done = true;
+        break;
+      }
+      // the sequential search stops inside this subtree
+      again.push_back(LdsTask{cp.pos, c, (int64_t)(B - cp.acc), 0});
+      again_comp.push_back(i);
+      cp.rerun_row = c;
+      break;
+    }
+    if (!cp.done && cp.rerun_row < 0) {   // every row exhausted
+      cp.res.rec.status = MPLD_INFEASIBLE;
+      cp.res.rec.nodes = cp.acc;
+      cp.res.rec.depth = 0;
+      cp.done = true;
+    }
+  }
+  if (!again.empty()) {
+    // the re-runs write their colors past the first phase's, which are kept
+    int64_t col2 = col;
+    for (LdsTask& t : again) {
+      t.col_off = col2;
+      col2 += db.host_desc[(size_t)t.item].n;
+    }
+    if (db.ct_colors.bytes < (size_t)col2) {
+      DevBuf bigger;
+      bigger.alloc(ctx, (size_t)col2);
+      if (col > 0)
+        check_hip(hipMemcpyAsync(bigger.p, db.ct_colors.p, (size_t)col, hipMemcpyDeviceToDevice, s),
+                  "subtree tasks: colors");
+      check_hip(hipStreamSynchronize(s), "subtree tasks: colors");
+      std::swap(db.ct_colors.p, bigger.p);
+      std::swap(db.ct_colors.bytes, bigger.bytes);   // `bigger` frees the old area
+    }
+    const std::vector<DevRecord> r2 = run(again, col2);
+    db.sp_tasks_run += (int64_t)again.size();
+    db.sp_reruns += (int64_t)again.size();
+    for (size_t j = 0; j < again.size(); ++j) {
+      Comp& cp = comps[(size_t)again_comp[j]];
+      const DevRecord& r = r2[j];
+      cp.res.rec.status = r.status;
+      cp.res.rec.nodes = cp.acc + r.nodes;
+      cp.res.rec.depth = r.status == MPLD_INFEASIBLE ? 0 : r.depth;
+      cp.res.src_off = r.status == MPLD_FEASIBLE ? again[j].col_off : -1;
+      cp.done = true;
+    }
+  }
+  // write back records and colors
+  std::vector<LdsResolved> w;
+  w.reserve(comps.size());
+  for (const Comp& cp : comps) w.push_back(cp.res);
+  const size_t wb = sizeof(LdsResolved) * w.size();
+  if (db.ct_resolved.bytes < wb) db.ct_resolved.alloc(ctx, wb);
+  if (!db.ct_host.reserve(wb)) fail(MPLD_E_NOMEM, "subtree tasks: pinned host memory");
+  std::memcpy(db.ct_host.p, w.data(), wb);
+  check_hip(hipMemcpyAsync(db.ct_resolved.p, db.ct_host.p, wb, hipMemcpyHostToDevice, s),
+            "subtree tasks: resolved");
+  check_hip(launch_csr_writeback(db.ct_resolved.as<LdsResolved>(), (int32_t)w.size(),
+                                 db.ct_colors.as<int8_t>(), db.recs.as<DevRecord>(),
+                                 db.colors.as<int8_t>(), s),
+            "subtree tasks: write-back");
+  check_hip(hipStreamSynchronize(s), "subtree tasks: write-back");
+}
+
 static void heavy_engine_host(DeviceBatch& db);
 
 // The device-resident engine also follows the stitch-aware order (its
@@ -856,8 +1040,8 @@ void device_solve(DeviceBatch& db, uint32_t flags) {
     fail(MPLD_E_UNSUPPORTED, "a component is too large for conflict marking (" +
                                  std::to_string(db.mark_lds) + " bytes of LDS)");
   const bool trace = flags & MPLD_TRACE_HASH;
-  const bool split = (flags & MPLD_SPLIT_HEAVY) && !trace && !(flags & MPLD_PLAIN) && db.n_reg > 0;
-  const uint64_t cap = split ? (uint64_t)db.tune.heavy_first_cap : ~0ull;
+  const bool split = (flags & MPLD_SPLIT_HEAVY) && !trace && !(flags & MPLD_PLAIN);
+  const uint64_t cap = split && db.n_reg > 0 ? (uint64_t)db.tune.heavy_first_cap : ~0ull;
   const bool timed = !(flags & MPLD_UNTIMED) || (flags & MPLD_PLAIN);
   db.timed = false;
   if (flags & MPLD_PLAIN) {
@@ -891,8 +1075,12 @@ void device_solve(DeviceBatch& db, uint32_t flags) {
   } else if ((flags & MPLD_DIRECT) || !db.tune.use_graph || db.n_dev) {
     // direct launches (cooperative launches stay out of graphs)
     if (timed) check_hip(hipEventRecord(ctx->ev[0], s), "event");
-    enqueue_batched(db, trace, cap, s);
-    if (split) heavy_engine(db);
+    enqueue_batched(db, trace, cap, s, split);
+    if (split) {
+      db.sp_rounds = db.sp_tasks_run = db.sp_heavy = db.sp_reruns = 0;
+      if (db.n_reg) heavy_engine(db);
+      csr_split(db);
+    }
     if (mark) enqueue_mark(db, s);
     if (minimize) enqueue_minimize(db, s);
     if (timed) check_hip(hipEventRecord(ctx->ev[1], s), "event");
@@ -907,7 +1095,7 @@ void device_solve(DeviceBatch& db, uint32_t flags) {
       hipGraph_t g = nullptr;
       check_hip(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed), "begin capture");
       try {
-        enqueue_batched(db, trace, cap, s);
+        enqueue_batched(db, trace, cap, s, split);
       } catch (...) {
         (void)hipStreamEndCapture(s, &g);
         if (g) (void)hipGraphDestroy(g);
@@ -921,7 +1109,11 @@ void device_solve(DeviceBatch& db, uint32_t flags) {
     }
     if (timed) check_hip(hipEventRecord(ctx->ev[0], s), "event");
     check_hip(hipGraphLaunch(db.graph, s), "graph launch");
-    if (split) heavy_engine(db);
+    if (split) {
+      db.sp_rounds = db.sp_tasks_run = db.sp_heavy = db.sp_reruns = 0;
+      if (db.n_reg) heavy_engine(db);
+      csr_split(db);
+    }
     if (mark) enqueue_mark(db, s);
     if (minimize) enqueue_minimize(db, s);
     if (timed) check_hip(hipEventRecord(ctx->ev[1], s), "event");

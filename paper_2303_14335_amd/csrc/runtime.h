@@ -57,6 +57,16 @@ hipError_t launch_lds_batched(bool trace, bool big, int waves, int grid, int lds
 hipError_t launch_lds_single(bool trace, bool big, int waves, int lds_bytes, const DevDesc* descs,
                              const uint32_t* adj32, int32_t item, uint64_t* gstack,
                              DevRecord* recs, int8_t* colors, hipStream_t s);
+// Subtree tasks of LDS-tier (big = false) or big-tier components.
+hipError_t launch_lds_tasks(bool big, int waves, int grid, int lds_bytes, const DevDesc* descs,
+                            const uint32_t* adj32, const LdsTask* tasks, int32_t ntasks,
+                            uint64_t* gstack, uint64_t stack_words, DevRecord* task_recs,
+                            int8_t* task_colors, hipStream_t s);
+// Writes resolved components' records (rec[i] to recs[comp[i]]) and colors
+// (n[i] bytes from src + src_off[i], or -1 when src_off[i] < 0, to colors +
+// out_off[i]).
+hipError_t launch_csr_writeback(const LdsResolved* w, int32_t count, const int8_t* src,
+                                DevRecord* recs, int8_t* colors, hipStream_t s);
 // Waves per workgroup for big LDS-tier components of at most max_n nodes.
 int lds_big_waves(int32_t max_n);
 // Conflict marking (MPLD_MARK_CONFLICTS) of the components whose record is
@@ -234,6 +244,8 @@ struct DeviceBatch {
   DevBuf sp_tasks, sp_out, sp_pool, sp_writes;      // heavy-component engine
   PinnedBuf sp_host_tasks, sp_host_out, sp_host_pool, sp_host_writes, sp_host_recs;
   DevBuf en_meta, en_tasks, en_blocks, en_pool;     // device-resident rounds
+  DevBuf ct_tasks, ct_recs, ct_colors, ct_resolved; // LDS/big-tier subtree tasks
+  PinnedBuf ct_host;
   std::vector<uint8_t> sp_host_copy;                // engine results in ordinary memory
   int64_t sp_rounds = 0, sp_tasks_run = 0, sp_heavy = 0, sp_reruns = 0;  // last solve's stats
   Tune tune;

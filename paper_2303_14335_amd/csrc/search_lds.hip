@@ -147,9 +147,15 @@ __device__ __forceinline__ uint64_t make_hdr(uint32_t v, uint32_t c, uint32_t ro
 // Small components: one wave; neighbour lists, level headers and the undo
 // log in LDS, the per-depth bit set in lane registers (word l in lane l; the
 // host admits at most 64 words).
+// root_row >= 0: search only the subtree of root row (0, root_row) (a
+// subtree task of the heavy-component split): at the root every column has
+// all k rows, so the root column is node 0; its row is taken at depth 0
+// with no alternative left at that level, the root node itself is not
+// counted, and `budget` (> 0) replaces the component's.
 template <bool TRACE, int K>
 __device__ void solve_lds(const DevDesc& d, const uint32_t* __restrict__ gadj, char* lds,
-                          int8_t* __restrict__ colors, DevRecord* __restrict__ rec) {
+                          int8_t* __restrict__ colors, DevRecord* __restrict__ rec,
+                          int32_t root_row = -1, uint64_t task_budget = 0) {
   const uint32_t lane = __lane_id();
   const uint32_t n = (uint32_t)d.n;
   // adjacency block: [0..n] row offsets, [n+1 ..] neighbour ids
@@ -176,7 +182,39 @@ __device__ void solve_lds(const DevDesc& d, const uint32_t* __restrict__ gadj, c
   uint32_t depth = 0, row_in = kNoneL, esp = 0;
   uint64_t nodes = 0, h = kFnvOffsetL;
   int32_t status = -1;
-  const uint64_t budget = (uint64_t)d.budget;
+  const uint64_t budget = root_row >= 0 ? task_budget : (uint64_t)d.budget;
+  if (root_row >= 0) {
+    // take row (0, root_row) at depth 0: node 0 leaves P, its neighbours
+    // lose color root_row; level 0 has no untried row (areg stays clear)
+    const uint32_t c = (uint32_t)root_row;
+    const uint32_t beg = uni(adj[0]), deg = uni(adj[1]) - beg;
+    if (lane == 63u) {
+      ent[0] = (uint32_t)K << kEntryNodeBits;
+      atomicAnd(reinterpret_cast<unsigned long long*>(&PL[(uint32_t)K * W]), ~1ull);
+      hdr[0] = make_hdr(0u, c, (1u << K) - 1u, 0u);
+    }
+    esp = 1u;
+    unsigned long long* plane = reinterpret_cast<unsigned long long*>(PL + c * W);
+    for (uint32_t ch = 0; ch < deg; ch += 64u) {
+      bool hit = false;
+      uint32_t u = 0;
+      if (ch + lane < deg) {
+        u = ids[beg + ch + lane];
+        const uint64_t bit = 1ull << (u & 63u);
+        hit = (atomicAnd(&plane[u >> 6], ~bit) & bit) != 0ull;
+      }
+      const uint64_t bal = __ballot(hit);
+      if (hit) {
+        const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
+                                                        __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+        ent[esp + rank] = (c << kEntryNodeBits) | u;
+      }
+      esp += (uint32_t)__popcll(bal);
+    }
+    asm volatile("" ::: "memory");
+    depth = 1u;
+    row_in = c;
+  }
 
   while (status < 0) {
     // ---- one search node
@@ -310,10 +348,12 @@ __device__ void solve_lds(const DevDesc& d, const uint32_t* __restrict__ gadj, c
 // and runs on wave 0 alone; a barrier ends the node, and wave 0 publishes
 // the loop status (and the final depth) in LDS for the others.  Adjacency,
 // level headers and the undo log are in global memory.
+// root_row / task_budget: a subtree task, as for solve_lds.
 template <bool TRACE, int K>
 __device__ void solve_lds_wg(const DevDesc& d, const uint32_t* __restrict__ adj, char* lds,
                              uint64_t* gstack, int8_t* __restrict__ colors,
-                             DevRecord* __restrict__ rec) {
+                             DevRecord* __restrict__ rec, int32_t root_row = -1,
+                             uint64_t task_budget = 0) {
   const uint32_t tid = threadIdx.x, lane = __lane_id(), nthr = blockDim.x;
   const uint32_t wid = uni(tid >> 6), nw = nthr >> 6;
   const uint32_t n = (uint32_t)d.n;
@@ -341,7 +381,41 @@ __device__ void solve_lds_wg(const DevDesc& d, const uint32_t* __restrict__ adj,
   uint32_t depth = 0, row_in = kNoneL, esp = 0;
   uint64_t nodes = 1, h = kFnvOffsetL;
   int32_t status = -1;
-  const uint64_t budget = (uint64_t)d.budget;
+  const uint64_t budget = root_row >= 0 ? task_budget : (uint64_t)d.budget;
+  if (root_row >= 0) {
+    // wave 0 takes row (0, root_row) at depth 0 (A's bit for level 0 stays
+    // clear); `nodes` = 1 then counts the first node below it
+    if (wid == 0u) {
+      const uint32_t c = (uint32_t)root_row;
+      const uint32_t beg = uni(adj[0]), deg = uni(adj[1]) - beg;
+      if (lane == 63u) {
+        ent[0] = (uint32_t)K << kEntryNodeBits;
+        atomicAnd(reinterpret_cast<unsigned long long*>(&PL[(uint32_t)K * W]), ~1ull);
+        hdr[0] = make_hdr(0u, c, (1u << K) - 1u, 0u);
+      }
+      esp = 1u;
+      unsigned long long* plane = reinterpret_cast<unsigned long long*>(PL + c * W);
+      for (uint32_t ch = 0; ch < deg; ch += 64u) {
+        bool hit = false;
+        uint32_t u = 0;
+        if (ch + lane < deg) {
+          u = ids[beg + ch + lane];
+          const uint64_t bit = 1ull << (u & 63u);
+          hit = (atomicAnd(&plane[u >> 6], ~bit) & bit) != 0ull;
+        }
+        const uint64_t bal = __ballot(hit);
+        if (hit) {
+          const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
+                                                          __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+          ent[esp + rank] = (c << kEntryNodeBits) | u;
+        }
+        esp += (uint32_t)__popcll(bal);
+      }
+      depth = 1u;
+      row_in = c;
+    }
+    __syncthreads();
+  }
 
   while (ctl[0] < 0) {
     uint32_t key = kNoKey;
@@ -469,11 +543,12 @@ __device__ void solve_lds_wg(const DevDesc& d, const uint32_t* __restrict__ adj,
 
 template <bool TRACE, bool BIG>
 __device__ __forceinline__ void solve_lds_k(const DevDesc& d, const uint32_t* gadj, char* lds,
-                                            uint64_t* gstack, int8_t* colors, DevRecord* rec) {
-#define MPLD_LDS_CASE(KK)                                             \
-  case KK:                                                            \
-    if (BIG) solve_lds_wg<TRACE, KK>(d, gadj, lds, gstack, colors, rec); \
-    else solve_lds<TRACE, KK>(d, gadj, lds, colors, rec);             \
+                                            uint64_t* gstack, int8_t* colors, DevRecord* rec,
+                                            int32_t root_row = -1, uint64_t task_budget = 0) {
+#define MPLD_LDS_CASE(KK)                                                                  \
+  case KK:                                                                                 \
+    if (BIG) solve_lds_wg<TRACE, KK>(d, gadj, lds, gstack, colors, rec, root_row, task_budget); \
+    else solve_lds<TRACE, KK>(d, gadj, lds, colors, rec, root_row, task_budget);            \
     break;
   switch (d.k) {
     MPLD_LDS_CASE(2)
@@ -483,8 +558,8 @@ __device__ __forceinline__ void solve_lds_k(const DevDesc& d, const uint32_t* ga
     MPLD_LDS_CASE(6)
     MPLD_LDS_CASE(7)
     default:
-      if (BIG) solve_lds_wg<TRACE, 8>(d, gadj, lds, gstack, colors, rec);
-      else solve_lds<TRACE, 8>(d, gadj, lds, colors, rec);
+      if (BIG) solve_lds_wg<TRACE, 8>(d, gadj, lds, gstack, colors, rec, root_row, task_budget);
+      else solve_lds<TRACE, 8>(d, gadj, lds, colors, rec, root_row, task_budget);
       break;
   }
 #undef MPLD_LDS_CASE
@@ -530,6 +605,28 @@ __global__ __launch_bounds__(BIG ? 1024 : 64) void lds_single_kernel(
   extern __shared__ __align__(16) char lds[];
   const DevDesc d = descs[item];
   solve_lds_k<TRACE, BIG>(d, adj32 + d.nbr_off, lds, gstack, colors + d.out_off, recs + d.comp);
+}
+
+// Subtree tasks of the heavy-component split (untraced): task t searches
+// the subtree of root row tasks[t].row of component tasks[t].item with its
+// own budget, and writes its record to task_recs[t] and its colors to
+// task_colors + tasks[t].col_off.  Grid-stride over the tasks, one
+// workgroup each (one wave small, nw waves big; big ones use the block's
+// stack area).
+template <bool BIG>
+__global__ __launch_bounds__(BIG ? 1024 : 64) void lds_task_kernel(
+    const DevDesc* __restrict__ descs, const uint32_t* __restrict__ adj32,
+    const LdsTask* __restrict__ tasks, int32_t ntasks, uint64_t* gstack,
+    uint64_t stack_words_per_block, DevRecord* __restrict__ task_recs,
+    int8_t* __restrict__ task_colors) {
+  extern __shared__ __align__(16) char lds[];
+  uint64_t* my_stack = BIG ? gstack + (uint64_t)blockIdx.x * stack_words_per_block : nullptr;
+  for (int32_t t = (int32_t)uni(blockIdx.x); t < ntasks; t += (int32_t)gridDim.x) {
+    const LdsTask task = tasks[t];
+    const DevDesc d = descs[task.item];
+    solve_lds_k<false, BIG>(d, adj32 + d.nbr_off, lds, my_stack, task_colors + task.col_off,
+                            task_recs + t, task.row, (uint64_t)task.budget);
+  }
 }
 
 // Conflict marking (Algorithm 1: a column left with no related row is a
@@ -631,6 +728,8 @@ static void lds_attr(int bytes) {
                             hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
   (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&lds_single_kernel<TRACE, BIG>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&lds_task_kernel<BIG>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 
 int64_t mark_lds_bytes(int32_t n, int32_t k) {
@@ -698,6 +797,42 @@ static hipError_t lds_single_t(int waves, int lds_bytes, const DevDesc* descs,
                                DevRecord* recs, int8_t* colors, hipStream_t s) {
   hipLaunchKernelGGL((lds_single_kernel<TRACE, BIG>), dim3(1), dim3(64 * waves),
                      (size_t)lds_bytes, s, descs, adj32, item, gstack, recs, colors);
+  return hipGetLastError();
+}
+
+hipError_t launch_lds_tasks(bool big, int waves, int grid, int lds_bytes, const DevDesc* descs,
+                            const uint32_t* adj32, const LdsTask* tasks, int32_t ntasks,
+                            uint64_t* gstack, uint64_t stack_words, DevRecord* task_recs,
+                            int8_t* task_colors, hipStream_t s) {
+  if (ntasks <= 0) return hipSuccess;
+  if (waves < 1 || waves > 16 || (!big && waves != 1) || grid < 1) return hipErrorInvalidValue;
+  if (big)
+    hipLaunchKernelGGL((lds_task_kernel<true>), dim3(grid), dim3(64 * waves), (size_t)lds_bytes, s,
+                       descs, adj32, tasks, ntasks, gstack, stack_words, task_recs, task_colors);
+  else
+    hipLaunchKernelGGL((lds_task_kernel<false>), dim3(grid), dim3(64), (size_t)lds_bytes, s, descs,
+                       adj32, tasks, ntasks, gstack, stack_words, task_recs, task_colors);
+  return hipGetLastError();
+}
+
+// One workgroup per resolved component: its colors and record.
+__global__ __launch_bounds__(256) void csr_writeback_kernel(const LdsResolved* __restrict__ w,
+                                                            int32_t count, const int8_t* __restrict__ src,
+                                                            DevRecord* __restrict__ recs,
+                                                            int8_t* __restrict__ colors) {
+  for (int32_t i = (int32_t)blockIdx.x; i < count; i += (int32_t)gridDim.x) {
+    const LdsResolved r = w[i];
+    for (int32_t v = (int32_t)threadIdx.x; v < r.n; v += (int32_t)blockDim.x)
+      colors[r.out_off + v] = r.src_off >= 0 ? src[r.src_off + v] : (int8_t)-1;
+    if (threadIdx.x == 0) recs[r.comp] = r.rec;
+  }
+}
+
+hipError_t launch_csr_writeback(const LdsResolved* w, int32_t count, const int8_t* src,
+                                DevRecord* recs, int8_t* colors, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(csr_writeback_kernel, dim3(count < 1024 ? count : 1024), dim3(256), 0, s, w,
+                     count, src, recs, colors);
   return hipGetLastError();
 }
 

@@ -499,3 +499,83 @@ def test_root_split_budget_cuts(ctx):
     say("root split, budget cuts")
     for budget in (1, 2, 3, 7, 15, 40, 120, 1000):
         solve_untraced(ctx, comps, 3, budget)
+
+
+# ---- subtree tasks of the LDS and big tiers (untraced solves): the k root
+# rows searched in parallel, the sequential status, node count, depth and
+# colors recomputed in row order
+
+def solve_split_csr(ctx, comps, k, budget, flags):
+    import paper_2303_14335_amd as mp
+    recs, colors = mp.mpld_solve_components(ctx, comps, k, budget, flags)
+    for (n, e), r, c in zip(comps, recs, colors):
+        s = oracle.solve_component(n, e, k, budget)
+        assert (int(r["status"]), int(r["nodes"]), int(r["depth_at_stop"])) == (
+            s.status, s.nodes, s.depth_at_stop), (n, k, budget, flags)
+        assert np.array_equal(c, s.colors)
+
+
+@pytest.mark.parametrize("k", [2, 3, 4, 5])
+def test_csr_subtree_tasks_random_components(ctx, k):
+    rng = np.random.default_rng(4000 + k)
+    comps = []
+    for _ in range(30):
+        n = int(rng.integers(65, 400))
+        p = min(0.95, float(rng.uniform(0.6, 1.4)) * 2.0 * k / n)
+        comps.append((n, random_graph(rng, n, p)))
+    say("LDS/big-tier subtree tasks, random components, k", k)
+    for flags in (0, FORCE["lds"], FORCE["global"]):
+        solve_split_csr(ctx, comps, k, 30000, flags)
+
+
+def test_csr_subtree_tasks_budget_cuts(ctx):
+    """Budgets that end the search in row 0's subtree, exactly between two
+    root rows, inside a later row's subtree (the re-run) and after every
+    row."""
+    rng = np.random.default_rng(4100)
+    comps = [(int(n), random_graph(rng, int(n), 4.6 / int(n))) for n in (70, 90, 130, 200)]
+    full = [oracle.solve_component(n, e, 3, 10**6) for n, e in comps]
+    say("LDS/big-tier subtree tasks, budget cuts")
+    budgets = {1, 2, 3, 5, 17, 100, 1000}
+    for s in full:
+        budgets |= {max(1, s.nodes - 1), s.nodes, s.nodes + 1}
+    for flags in (FORCE["lds"], FORCE["global"]):
+        for b in sorted(budgets):
+            solve_split_csr(ctx, comps, 3, b, flags)
+
+
+def test_csr_subtree_tasks_exact_boundaries(ctx):
+    """Budget cuts at every node count where a root row's subtree ends, for
+    components whose search visits several root rows."""
+    rng = np.random.default_rng(4200)
+    picked = []
+    while len(picked) < 3:
+        n = int(rng.integers(70, 120))
+        e = random_graph(rng, n, 5.2 / n)
+        s = oracle.solve_component(n, e, 3, 10**6)
+        if s.status == oracle.INFEASIBLE and s.nodes > 20:
+            picked.append((n, e, s.nodes))
+    say("LDS/big-tier subtree tasks, every budget near the row boundaries")
+    for n, e, total in picked:
+        for b in range(1, min(total, 400) + 2):
+            solve_split_csr(ctx, [(n, e)], 3, b, FORCE["lds"])
+
+
+def test_csr_subtree_tasks_in_batches_and_config3(ctx):
+    import paper_2303_14335_amd as mp
+    w, rects = graph_of(3)
+    say("config 3 untraced, subtree tasks on the big tier")
+    g, og = both_graphs(rects, w)
+    ref = oracle.decompose(og, w.k, w.budget)
+    got = mp.mpld_decompose(ctx, g, w.k, w.budget, SIMPLIFY)
+    for f in ("size", "status", "nodes", "depth_at_stop", "first_node", "num_edges"):
+        assert np.array_equal(got.components[f], ref.comps[f]), f
+    assert np.array_equal(got.colors, ref.colors)
+    b = mp.Batch(ctx, g, w.k, w.budget, SIMPLIFY)
+    for split in (False, True, True):
+        b.solve(split=split)
+        r = b.result()
+        assert np.array_equal(r.components["nodes"], ref.comps["nodes"])
+        assert np.array_equal(r.colors, ref.colors)
+    assert b.info()["split_tasks"] >= 3
+    b.close()
