@@ -336,6 +336,13 @@ PROBES = [
     ("lds_small_k3_n1000", 1000, 3, 4.6, 0, 20000, "MPLD_FORCE_LDS"),
     ("lds_k3_n10000", 10000, 3, 4.6, 0, 20000, "MPLD_FORCE_GLOBAL"),
     ("device_k3_n10000", 10000, 3, 4.6, 0, 2000, "MPLD_FORCE_DEVICE"),
+    # an LDS-tier component whose search ends INFEASIBLE after visiting every
+    # root row (501,238 nodes): sequential, and as root-row subtree tasks
+    # ("..._split": the same exact counts), on the LDS and the big tier
+    ("lds_k3_n200_infeasible", 200, 3, 5.6, 4, 1000000, "MPLD_FORCE_LDS"),
+    ("lds_k3_n200_infeasible_split", 200, 3, 5.6, 4, 1000000, "MPLD_FORCE_LDS"),
+    ("big_k3_n200_infeasible", 200, 3, 5.6, 4, 1000000, "MPLD_FORCE_GLOBAL"),
+    ("big_k3_n200_infeasible_split", 200, 3, 5.6, 4, 1000000, "MPLD_FORCE_GLOBAL"),
 ]
 
 
@@ -379,9 +386,10 @@ def latency_probe(mp, ctx, reps=3, names=None, lds=None):
         g = mp.Graph(n, e, np.zeros((0, 2), np.int32))
         b = mp.Batch(ctx, g, k, budget, getattr(mp, flag))
         b.set_tune(root_split=1 if name.endswith("_root_split") else 0)
+        split = name.endswith("_split") and not name.endswith("_root_split")
         ms = []
         for _ in range(reps):
-            b.solve(direct=True)
+            b.solve(direct=True, split=split)
             torch.cuda.synchronize()
             ms.append(b.info()["last_search_ms"])
         nodes = int(b.result().components["nodes"].sum())

@@ -177,6 +177,8 @@ void device_upload(mpld_context* ctx, const Image& im, DeviceBatch& db, const Tu
   }
   db.grid_lds = std::max(1, std::min(db.n_lds, blocks_for_lds(ctx, db.lds_small)));
   db.grid_big = std::max(1, std::min(db.n_big, blocks_for_lds(ctx, db.lds_big)));
+  // subtree tasks: k per big component, each on a workgroup of its own
+  db.grid_big_tasks = std::max(db.grid_big, std::min(db.k * db.n_big, blocks_for_lds(ctx, db.lds_big)));
 
   db.host_queue.clear();
   db.host_queue.insert(db.host_queue.end(), im.q_reg.begin(), im.q_reg.end());
@@ -226,7 +228,8 @@ void device_upload(mpld_context* ctx, const Image& im, DeviceBatch& db, const Tu
   db.gstack.release();
   db.dev_keys.release();
   db.dev_stacks.release();
-  if (db.n_big) db.gstack.alloc(ctx, sizeof(uint64_t) * db.big_stack_words * (size_t)db.grid_big);
+  if (db.n_big)
+    db.gstack.alloc(ctx, sizeof(uint64_t) * db.big_stack_words * (size_t)db.grid_big_tasks);
   if (db.n_dev) {
     db.dev_keys.alloc(ctx, sizeof(uint64_t) * 4);
     db.dev_stacks.alloc(ctx, sizeof(uint64_t) * (size_t)im.dev_stack_words * (size_t)db.grid_dev);
@@ -682,7 +685,7 @@ static void csr_split(DeviceBatch& db) {
                 "subtree tasks (LDS tier)");
     if (nsmall < list.size())
       check_hip(launch_lds_tasks(true, db.big_waves,
-                                 std::max(1, std::min((int)(list.size() - nsmall), db.grid_big)),
+                                 std::max(1, std::min((int)(list.size() - nsmall), db.grid_big_tasks)),
                                  db.lds_big, db.desc.as<DevDesc>(), db.adj32.as<uint32_t>(),
                                  dt + nsmall, (int32_t)(list.size() - nsmall), db.gstack.as<uint64_t>(),
                                  db.big_stack_words, drec + nsmall, db.ct_colors.as<int8_t>(), s),

@@ -254,6 +254,7 @@ struct DeviceBatch {
   int32_t num_comps = 0, total_nodes = 0;
   int32_t k = 3;
   int grid_reg = 1, grid_lds = 1, grid_big = 1;
+  int grid_big_tasks = 1;   // big-tier subtree tasks (stack areas allocated for this many blocks)
   int lds_small = 0, lds_big = 0;
   int big_waves = 1;   // waves per workgroup on the big tier
   int32_t reg_heavy = 0;   // register-tier items (a launch-order prefix) with a root split
