@@ -99,7 +99,14 @@ enum {
                                   recomputed exactly from the subtrees' counts
                                   in search order (not with MPLD_TRACE_HASH; a
                                   component cut by its budget is re-run
-                                  sequentially).  Makes mpld_batch_solve wait.
+                                  sequentially).  LDS-tier and big-tier
+                                  components are searched as k subtree tasks,
+                                  one per root row (the root column is node
+                                  0), each on its own wave or workgroup; their
+                                  counts are added in row order, and a budget
+                                  crossed inside a later row's subtree is
+                                  found by searching that subtree again with
+                                  the budget left.  Makes mpld_batch_solve wait.
                                   mpld_decompose and mpld_solve_components,
                                   which wait anyway, use it for every untraced
                                   solve whether or not the flag is given. */
