@@ -12,7 +12,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmpld.so")
 
-SOURCES = ["frontend.cpp", "runtime.cpp", "abi.cpp", "serve.cpp", "autotune.cpp", "search_reg.hip",
+SOURCES = ["frontend.cpp", "runtime.cpp", "abi.cpp", "serve.cpp", "serve_core.cpp", "autotune.cpp", "search_reg.hip",
            "search_lds.hip", "search_device.hip", "graph_device.hip", "search_min.hip",
            "noalloc.hip", "measure.hip"]
 

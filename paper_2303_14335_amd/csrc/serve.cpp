@@ -1,5 +1,6 @@
 // serve.cpp - continuous-batching server for whole-layout decomposition
-// requests (the serving half of the decomposer library).
+// requests (the serving half of the decomposer library): the device side
+// (HipExecutor) of the scheduling core in serve_core.cpp, and the C ABI.
 //
 // Submit copies a request and hands it to a worker thread for the host
 // front-end (layout graph, simplification, sub-graphs, packing).  A single
@@ -15,100 +16,32 @@
 //   4. download of the tick's per-component records; a request whose
 //      components are all finished gets its colors downloaded, its device
 //      space released, and is finished (recovery, tallies) on a worker.
-#include <hip/hip_runtime.h>
+#include <hip/hip_runtime_api.h>
 
 #include <algorithm>
 #include <atomic>
-#include <chrono>
-#include <condition_variable>
 #include <cstring>
-#include <deque>
-#include <map>
 #include <memory>
-#include <mutex>
-#include <thread>
-#include <unordered_map>
+#include <vector>
 
-#include "range_alloc.h"
 #include "runtime.h"
+#include "serve_core.h"
 
 namespace mpld {
 namespace {
-
-using Clock = std::chrono::steady_clock;
 
 // Layout requests of at least this many rectangles build their graph on the
 // device (a fixed cost of about ten launches and two transfers, against
 // about 50-90 ns per rectangle for the host's pair search).
 constexpr int32_t kDeviceGraphMinRects = 4096;
 
-struct Request {
-  uint64_t ticket = 0;
-  bool layout = false;
-  std::vector<mpld_rect> rects;
-  int32_t dmin = 0, split = 0;
-  int32_t num_nodes = 0;
-  std::vector<int32_t> ce, se;
-  mpld_options opt{};
-  // front-end
-  Graph g;
-  Split s;
-  Image im;
-  std::vector<uint8_t> tier;  // per component: 0 register, 1 LDS, 2 big
-  int64_t off_masks = 0, off_adj = 0, off_colors = 0, bytes = 0;
-  // residency
-  int64_t arena_off = -1;
-  int64_t slot_base = -1;
-  int32_t remaining = 0;
-  std::vector<DevRecord> recs;
-  std::vector<int8_t> lcol;
-  std::vector<DevDesc> ddesc;  // slot descriptors as uploaded (kept until the tick syncs)
-  // completion
-  int32_t error = MPLD_OK;
-  std::string error_text;
-  Clock::time_point t_submit, t_admit;
-  std::unique_ptr<mpld_result> result;
-};
-
-struct Job {
-  int kind;  // 0 front-end, 1 finish
-  Request* r;
-};
-
-// One resident register-tier component.
-struct Active {
-  Request* r;
-  int32_t comp;
-  int32_t slot;
-  bool fresh;
-};
-
-}  // namespace
-}  // namespace mpld
-
-using namespace mpld;
-
-struct mpld_server {
+class HipExecutor : public ServeExecutor {
+ public:
   mpld_context* ctx = nullptr;
   mpld_server_options opt{};
-  // device
   DevBuf arena, slot_desc, slot_rec, slot_state, list, tick_out, lds_desc, lds_out, counter, gstack;
   int32_t max_slots = 0;
-  RangeAlloc arena_alloc, slot_alloc;
   int64_t gstack_words = 0;
-  // host state
-  std::mutex mu;
-  std::condition_variable cv_work, cv_sched, cv_done;
-  std::deque<Job> jobs;
-  std::deque<Request*> ready;
-  std::vector<Active> active;
-  std::unordered_map<uint64_t, Request*> pending;  // submitted, not yet finished
-  std::unordered_map<uint64_t, Request*> done;     // finished, not yet fetched
-  uint64_t next_ticket = 1;
-  bool stop = false;
-  mpld_server_stats stats{};
-  std::vector<std::thread> workers;
-  std::thread scheduler;
   // device layout-graph builders for large layout requests (own stream
   // each), taken in turn so that concurrent large requests do not queue on
   // one builder's lock
@@ -116,20 +49,22 @@ struct mpld_server {
   std::atomic<uint32_t> gb_next{0};
   bool device_split = false;   // device-built layouts also split on the device
 
-  void worker_loop();
-  void scheduler_loop();
-  void front_end(Request* r);
-  void finish(Request* r);
-  void complete(Request* r);  // caller holds mu
-  bool try_admit(Request* r);
-  void upload(Request* r);
-  void tick(std::vector<Request*>& admitted);
-  void release(Request* r);
+  ~HipExecutor() override {
+    if (ctx) {
+      (void)hipSetDevice(ctx->device);
+      (void)hipStreamSynchronize(ctx->stream);
+    }
+    for (GraphBuilder* gb : gbuilders) graph_builder_destroy(gb);
+  }
+  void front_end(Request* r) override;
+  void finish(Request* r) override;
+  void upload(Request* r) override;
+  void tick(std::vector<Request*>& admitted, std::vector<ServeActive>& active,
+            std::vector<Request*>& finished, double* device_ms) override;
+  void bind_thread() override { check_hip(hipSetDevice(ctx->device), "serve: hipSetDevice"); }
 };
 
-// ---------------------------------------------------------------------------
-
-void mpld_server::front_end(Request* r) {
+void HipExecutor::front_end(Request* r) {
   try {
     bool built = false, split_done = false;
     if (r->layout) {
@@ -189,12 +124,12 @@ void mpld_server::front_end(Request* r) {
   }
 }
 
-void mpld_server::finish(Request* r) {
+void HipExecutor::finish(Request* r) {
   if (r->error == MPLD_OK) {
     try {
       r->result.reset(new mpld_result());
       assemble_result(r->g, r->s, r->im, r->opt, r->recs, r->lcol, r->result.get());
-      const auto now = Clock::now();
+      const auto now = ServeClock::now();
       r->result->queue_us =
           std::chrono::duration<double, std::micro>(r->t_admit - r->t_submit).count();
       r->result->total_us = std::chrono::duration<double, std::micro>(now - r->t_submit).count();
@@ -216,77 +151,12 @@ void mpld_server::finish(Request* r) {
   std::vector<int32_t>().swap(r->se);
   std::vector<int8_t>().swap(r->lcol);
   std::vector<DevDesc>().swap(r->ddesc);
-  std::lock_guard<std::mutex> lk(mu);
-  complete(r);
-}
-
-void mpld_server::complete(Request* r) {
-  pending.erase(r->ticket);
-  done[r->ticket] = r;
-  if (r->error == MPLD_OK) {
-    ++stats.completed;
-    for (const auto& rec : r->recs) stats.search_nodes += (int64_t)rec.nodes;
-  } else {
-    ++stats.failed;
-  }
-  cv_done.notify_all();
-}
-
-void mpld_server::worker_loop() {
-  for (;;) {
-    Job j;
-    {
-      std::unique_lock<std::mutex> lk(mu);
-      cv_work.wait(lk, [&] { return stop || !jobs.empty(); });
-      if (jobs.empty()) return;
-      j = jobs.front();
-      jobs.pop_front();
-    }
-    if (j.kind == 0) {
-      front_end(j.r);
-      std::lock_guard<std::mutex> lk(mu);
-      ready.push_back(j.r);
-      cv_sched.notify_one();
-    } else {
-      finish(j.r);
-    }
-  }
-}
-
-// Admission by device bytes and slots (caller holds mu).
-bool mpld_server::try_admit(Request* r) {
-  const int64_t nc = (int64_t)r->recs.size();
-  const int64_t off = arena_alloc.alloc(std::max<int64_t>(r->bytes, 256), 256);
-  if (off < 0) return false;
-  int64_t sb = 0;
-  if (nc > 0) {
-    sb = slot_alloc.alloc(nc, 1);
-    if (sb < 0) {
-      arena_alloc.release(off, std::max<int64_t>(r->bytes, 256));
-      return false;
-    }
-  }
-  r->arena_off = off;
-  r->slot_base = sb;
-  r->t_admit = Clock::now();
-  stats.resident_bytes = arena_alloc.used();
-  stats.resident_components = slot_alloc.used();
-  stats.peak_bytes = std::max(stats.peak_bytes, stats.resident_bytes);
-  return true;
-}
-
-void mpld_server::release(Request* r) {
-  std::lock_guard<std::mutex> lk(mu);
-  arena_alloc.release(r->arena_off, std::max<int64_t>(r->bytes, 256));
-  if (!r->recs.empty()) slot_alloc.release(r->slot_base, (int64_t)r->recs.size());
-  stats.resident_bytes = arena_alloc.used();
-  stats.resident_components = slot_alloc.used();
 }
 
 // Enqueues the copy of an admitted request's image to its arena range and
 // of its slot descriptors (arena-absolute offsets); the tick's
 // synchronisation covers them.
-void mpld_server::upload(Request* r) {
+void HipExecutor::upload(Request* r) {
   hipStream_t s = ctx->stream;
   uint8_t* base = arena.as<uint8_t>() + r->arena_off;
   if (!r->im.masks.empty())
@@ -313,7 +183,8 @@ void mpld_server::upload(Request* r) {
 
 static int count_bits_host(int k) { return k < 4 ? 2 : (k < 8 ? 3 : 4); }
 
-void mpld_server::tick(std::vector<Request*>& admitted) {
+void HipExecutor::tick(std::vector<Request*>& admitted, std::vector<ServeActive>& active,
+                       std::vector<Request*>& finished, double* device_ms) {
   hipStream_t s = ctx->stream;
   // LDS-tier components of the newly admitted requests, run to completion
   struct LdsItem { Request* r; int32_t comp; };
@@ -356,7 +227,7 @@ void mpld_server::tick(std::vector<Request*>& admitted) {
     lds_d.push_back(staged(lds_big[i], (int32_t)(lds_small.size() + i)));
 
   // register tier: group by (trace, count width) so each launch has one template
-  std::stable_sort(active.begin(), active.end(), [](const Active& a, const Active& b) {
+  std::stable_sort(active.begin(), active.end(), [](const ServeActive& a, const ServeActive& b) {
     const int ka = count_bits_host(a.r->opt.k) + ((a.r->opt.flags & MPLD_TRACE_HASH) ? 8 : 0);
     const int kb = count_bits_host(b.r->opt.k) + ((b.r->opt.flags & MPLD_TRACE_HASH) ? 8 : 0);
     return ka < kb;
@@ -430,14 +301,13 @@ void mpld_server::tick(std::vector<Request*>& admitted) {
               "serve: download LDS records");
   check_hip(hipStreamSynchronize(s), "serve: tick");
   float ms = 0.f;
-  if (hipEventElapsedTime(&ms, ctx->ev[2], ctx->ev[3]) == hipSuccess) stats.device_ms += ms;
+  if (hipEventElapsedTime(&ms, ctx->ev[2], ctx->ev[3]) == hipSuccess) *device_ms += ms;
 
   // bookkeeping: finished components leave the active set
-  std::vector<Request*> finished;
-  std::vector<Active> keep;
+  std::vector<ServeActive> keep;
   keep.reserve(active.size());
   for (int32_t i = 0; i < len; ++i) {
-    Active a = active[i];
+    ServeActive a = active[i];
     if (out[i].status < 0) {
       a.fresh = false;
       keep.push_back(a);
@@ -457,7 +327,7 @@ void mpld_server::tick(std::vector<Request*>& admitted) {
   }
   for (Request* r : admitted)
     if (r->recs.empty()) finished.push_back(r);   // nothing to search
-  // colors of finished requests, then release their device space
+  // colors of finished requests (the core then releases their device space)
   for (Request* r : finished) {
     r->lcol.resize((size_t)r->im.total_nodes);
     if (!r->lcol.empty())
@@ -466,82 +336,18 @@ void mpld_server::tick(std::vector<Request*>& admitted) {
                 "serve: download colors");
   }
   if (!finished.empty()) check_hip(hipStreamSynchronize(s), "serve: colors");
-  for (Request* r : finished) release(r);
-  std::lock_guard<std::mutex> lk(mu);
-  ++stats.ticks;
-  for (Request* r : finished) jobs.push_back({1, r});
-  if (!finished.empty()) cv_work.notify_all();
 }
 
-void mpld_server::scheduler_loop() {
-  check_hip(hipSetDevice(ctx->device), "serve: hipSetDevice");
-  for (;;) {
-    std::vector<Request*> admitted;
-    {
-      std::unique_lock<std::mutex> lk(mu);
-      if (stop) break;
-      if (ready.empty() && active.empty()) {
-        cv_sched.wait_for(lk, std::chrono::milliseconds(2));
-        if (stop) break;
-      }
-      bool waited = false;
-      while (!ready.empty()) {
-        Request* r = ready.front();
-        if (r->error != MPLD_OK) {
-          ready.pop_front();
-          complete(r);
-          continue;
-        }
-        if (r->bytes > arena_alloc.capacity() || (int64_t)r->recs.size() > max_slots) {
-          ready.pop_front();
-          r->error = MPLD_E_NOMEM;
-          r->error_text = "request needs " + std::to_string(r->bytes) + " device bytes and " +
-                          std::to_string(r->recs.size()) + " component slots, more than the server has";
-          complete(r);
-          continue;
-        }
-        if (!try_admit(r)) {
-          waited = true;
-          break;
-        }
-        ready.pop_front();
-        admitted.push_back(r);
-      }
-      if (waited) ++stats.admission_waits;
-    }
-    if (admitted.empty() && active.empty()) continue;
-    int32_t err = MPLD_OK;
-    std::string err_text;
-    try {
-      for (Request* r : admitted) upload(r);
-      tick(admitted);
-    } catch (const Error& e) {
-      err = e.code;
-      err_text = e.what;
-    } catch (const std::bad_alloc&) {
-      err = MPLD_E_NOMEM;
-      err_text = "host allocation failed in the scheduler";
-    } catch (...) {
-      err = MPLD_E_INTERNAL;
-      err_text = "unexpected exception in the scheduler";
-    }
-    if (err != MPLD_OK) {
-      // a device error ends the server: every resident and waiting request fails
-      std::lock_guard<std::mutex> lk(mu);
-      for (auto& kv : pending) {
-        Request* r = kv.second;
-        r->error = err;
-        r->error_text = err_text;
-      }
-      stop = true;
-      cv_work.notify_all();
-      cv_done.notify_all();
-      break;
-    }
-  }
-}
+}  // namespace
+}  // namespace mpld
 
-// ---------------------------------------------------------------------------
+using namespace mpld;
+
+struct mpld_server {
+  HipExecutor exec;
+  std::unique_ptr<ServeCore> core;   // destroyed first: it stops the threads using `exec`
+  ~mpld_server() { core.reset(); }
+};
 
 namespace {
 
@@ -577,21 +383,6 @@ void check_opts(const mpld_options* o) {
     fail(MPLD_E_UNSUPPORTED, "serving does not run the Eq. 1 minimisation (MPLD_MINIMIZE)");
 }
 
-int32_t submit_request(mpld_server* s, Request* r, uint64_t* ticket) {
-  r->t_submit = Clock::now();
-  std::lock_guard<std::mutex> lk(s->mu);
-  if (s->stop) {
-    delete r;
-    fail(MPLD_E_CANCELLED, "server is stopping");
-  }
-  r->ticket = s->next_ticket++;
-  s->pending[r->ticket] = r;
-  ++s->stats.submitted;
-  s->jobs.push_back({0, r});
-  s->cv_work.notify_one();
-  *ticket = r->ticket;
-  return MPLD_OK;
-}
 
 }  // namespace
 
@@ -614,42 +405,39 @@ int32_t mpld_server_create(mpld_context* ctx, const mpld_server_options* opt, mp
     if (o.host_threads <= 0) o.host_threads = host_threads();
     check_hip(hipSetDevice(ctx->device), "hipSetDevice");
     auto* s = new mpld_server();
-    s->ctx = ctx;
-    s->opt = o;
-    s->max_slots = o.max_components;
+    s->exec.ctx = ctx;
+    s->exec.opt = o;
+    s->exec.max_slots = o.max_components;
+    HipExecutor* x = &s->exec;
     try {
-      s->arena.alloc(ctx, (size_t)o.arena_bytes);
-      s->slot_desc.alloc(ctx, sizeof(DevDesc) * (size_t)s->max_slots);
-      s->slot_rec.alloc(ctx, sizeof(DevRecord) * (size_t)s->max_slots);
-      s->slot_state.alloc(ctx, kRegStateBytes * (size_t)s->max_slots);
-      s->list.alloc(ctx, sizeof(int32_t) * (size_t)s->max_slots);
-      s->tick_out.alloc(ctx, sizeof(DevRecord) * (size_t)s->max_slots);
-      s->lds_desc.alloc(ctx, sizeof(DevDesc) * (size_t)s->max_slots);
-      s->lds_out.alloc(ctx, sizeof(DevRecord) * (size_t)s->max_slots);
-      s->counter.alloc(ctx, sizeof(int32_t) * 4);
+      x->arena.alloc(ctx, (size_t)o.arena_bytes);
+      x->slot_desc.alloc(ctx, sizeof(DevDesc) * (size_t)x->max_slots);
+      x->slot_rec.alloc(ctx, sizeof(DevRecord) * (size_t)x->max_slots);
+      x->slot_state.alloc(ctx, kRegStateBytes * (size_t)x->max_slots);
+      x->list.alloc(ctx, sizeof(int32_t) * (size_t)x->max_slots);
+      x->tick_out.alloc(ctx, sizeof(DevRecord) * (size_t)x->max_slots);
+      x->lds_desc.alloc(ctx, sizeof(DevDesc) * (size_t)x->max_slots);
+      x->lds_out.alloc(ctx, sizeof(DevRecord) * (size_t)x->max_slots);
+      x->counter.alloc(ctx, sizeof(int32_t) * 4);
       // one builder by default: with four, the measured p99 latency of a
       // Poisson mix of layout requests rose by about a third
       const int nb = o.graph_builders == 0 ? 1 : std::max(0, o.graph_builders);
       for (int i = 0; i < nb; ++i) {
-        s->gbuilders.push_back(graph_builder_create(ctx, true));
+        x->gbuilders.push_back(graph_builder_create(ctx, true));
         // sized ahead for layouts of up to 64k nodes: growing a builder
         // while requests wait behind it cost several milliseconds each time
-        graph_builder_reserve(*s->gbuilders.back(), 1 << 16);
+        graph_builder_reserve(*x->gbuilders.back(), 1 << 16);
       }
       // device split by default: over three paired runs of 1,000 requests
       // it took p99 latency from 2.9-3.5 ms (host split) to 2.5-2.7 ms
-      s->device_split = o.device_split >= 0;
-      check_hip(hipMemsetAsync(s->counter.p, 0, sizeof(int32_t) * 4, ctx->stream), "serve: clear");
+      x->device_split = o.device_split >= 0;
+      check_hip(hipMemsetAsync(x->counter.p, 0, sizeof(int32_t) * 4, ctx->stream), "serve: clear");
       check_hip(hipStreamSynchronize(ctx->stream), "serve: clear");
+      s->core.reset(new ServeCore(x, o.arena_bytes, x->max_slots, o.host_threads));
     } catch (...) {
-      for (GraphBuilder* gb : s->gbuilders) graph_builder_destroy(gb);
       delete s;
       throw;
     }
-    s->arena_alloc.reset(o.arena_bytes);
-    s->slot_alloc.reset(s->max_slots);
-    for (int t = 0; t < o.host_threads; ++t) s->workers.emplace_back([s] { s->worker_loop(); });
-    s->scheduler = std::thread([s] { s->scheduler_loop(); });
     *out = s;
   });
 }
@@ -667,7 +455,7 @@ int32_t mpld_server_submit(mpld_server* s, const mpld_graph* g, const mpld_optio
     r->num_nodes = g->num_nodes;
     r->ce.assign(g->ce, g->ce + 2 * g->num_ce);
     r->se.assign(g->se, g->se + 2 * g->num_se);
-    submit_request(s, r, ticket);
+    s->core->submit(r, ticket);
   });
 }
 
@@ -683,72 +471,30 @@ int32_t mpld_server_submit_layout(mpld_server* s, const mpld_rect* rects, int32_
     r->rects.assign(rects, rects + n);
     r->dmin = dmin_nm;
     r->split = split_len_nm;
-    submit_request(s, r, ticket);
+    s->core->submit(r, ticket);
   });
-}
-
-static int32_t take_done(mpld_server* s, uint64_t ticket, mpld_result** out) {
-  // caller holds mu; the ticket is finished
-  Request* r = s->done[ticket];
-  s->done.erase(ticket);
-  const int32_t code = r->error;
-  set_last_error(r->error_text);
-  if (code == MPLD_OK) *out = r->result.release();
-  delete r;
-  return code;
 }
 
 int32_t mpld_server_poll(mpld_server* s, uint64_t ticket, mpld_result** out) {
   if (!s || !out) return MPLD_E_INVALID;
-  *out = nullptr;
-  std::lock_guard<std::mutex> lk(s->mu);
-  if (s->done.count(ticket)) return take_done(s, ticket, out);
-  if (s->pending.count(ticket)) return MPLD_E_NOT_READY;
-  set_last_error("unknown ticket");
-  return MPLD_E_INVALID;
+  return s->core->poll(ticket, out);
 }
 
 int32_t mpld_server_wait(mpld_server* s, uint64_t ticket, int64_t timeout_us, mpld_result** out) {
   if (!s || !out) return MPLD_E_INVALID;
-  *out = nullptr;
-  std::unique_lock<std::mutex> lk(s->mu);
-  auto ready = [&] { return s->done.count(ticket) || !s->pending.count(ticket) || s->stop; };
-  if (timeout_us < 0)
-    s->cv_done.wait(lk, ready);
-  else
-    s->cv_done.wait_for(lk, std::chrono::microseconds(timeout_us), ready);
-  if (s->done.count(ticket)) return take_done(s, ticket, out);
-  if (s->pending.count(ticket)) return s->stop ? MPLD_E_CANCELLED : MPLD_E_NOT_READY;
-  set_last_error("unknown ticket");
-  return MPLD_E_INVALID;
+  return s->core->wait(ticket, timeout_us, out);
 }
 
 int32_t mpld_server_get_stats(mpld_server* s, mpld_server_stats* out) {
   if (!s || !out) return MPLD_E_INVALID;
-  std::lock_guard<std::mutex> lk(s->mu);
-  *out = s->stats;
+  *out = s->core->stats();
   return MPLD_OK;
 }
 
 int32_t mpld_server_destroy(mpld_server* s) {
   if (!s) return MPLD_OK;
-  {
-    std::lock_guard<std::mutex> lk(s->mu);
-    s->stop = true;
-    s->cv_sched.notify_all();
-    s->cv_work.notify_all();
-    s->cv_done.notify_all();
-  }
-  if (s->scheduler.joinable()) s->scheduler.join();
-  for (auto& t : s->workers)
-    if (t.joinable()) t.join();
-  (void)hipSetDevice(s->ctx->device);
-  (void)hipStreamSynchronize(s->ctx->stream);
-  // every request is either pending (not finished) or done (not fetched)
-  for (auto& kv : s->pending) delete kv.second;
-  for (auto& kv : s->done) delete kv.second;
-  for (GraphBuilder* gb : s->gbuilders) graph_builder_destroy(gb);
-  delete s;
+  s->core->shutdown();
+  delete s;   // the core's requests, then the executor's device buffers and builders
   return MPLD_OK;
 }
 
