@@ -433,9 +433,11 @@ int32_t mpld_solve_components_noalloc(mpld_context* ctx, const mpld_component* c
  * image fits the device arena and enough component slots are free (admission
  * by device bytes).  Every tick advances every resident register-tier
  * component by at most `slice_nodes` search nodes from the state it keeps in
- * device memory (larger components run to completion in the tick that
- * admits them), so requests that arrive while others are on the device join
- * at the next tick and their work shares the same launches.  A request's
+ * device memory (larger components run to completion on a second stream,
+ * started by the tick that admits them and collected by a later one, so a
+ * long one does not hold up the ticks), so requests that arrive while
+ * others are on the device join at the next tick and their work shares the
+ * same launches.  A request's
  * result depends only on its graph and options - not on arrival time, the
  * mix or the slice.  While a server exists its context must not be used
  * elsewhere.  A request larger than the whole arena (or than all slots)

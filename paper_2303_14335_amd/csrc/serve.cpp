@@ -21,6 +21,7 @@
 #include <algorithm>
 #include <atomic>
 #include <cstring>
+#include <deque>
 #include <memory>
 #include <vector>
 
@@ -39,23 +40,47 @@ class HipExecutor : public ServeExecutor {
  public:
   mpld_context* ctx = nullptr;
   mpld_server_options opt{};
-  DevBuf arena, slot_desc, slot_rec, slot_state, list, tick_out, lds_desc, lds_out, counter, gstack;
+  DevBuf arena, slot_desc, slot_rec, slot_state, list, tick_out, counter;
   int32_t max_slots = 0;
-  int64_t gstack_words = 0;
   // device layout-graph builders for large layout requests (own stream
   // each), taken in turn so that concurrent large requests do not queue on
   // one builder's lock
   std::vector<GraphBuilder*> gbuilders;
   std::atomic<uint32_t> gb_next{0};
   bool device_split = false;   // device-built layouts also split on the device
+  // Components above the register tier run to completion on a stream of
+  // their own (default priority), one "flight" per tick that admits some,
+  // so that a long LDS-tier search does not hold up the register-tier ticks
+  // of every other request; flights run in order on that stream, and each
+  // tick collects the ones that have finished.
+  struct Flight {
+    std::vector<std::pair<Request*, int32_t>> items;   // (request, component)
+    DevBuf desc, out, gstack;
+    PinnedBuf host;             // descriptors up, then the records down
+    hipEvent_t start = nullptr, done = nullptr;
+    ~Flight() {
+      if (start) (void)hipEventDestroy(start);
+      if (done) (void)hipEventDestroy(done);
+    }
+  };
+  hipStream_t lds_stream = nullptr;
+  hipEvent_t up_ev = nullptr;   // the admitted images are on the device
+  std::deque<std::unique_ptr<Flight>> flights;   // in launch order
+  std::vector<std::unique_ptr<Flight>> spare;
 
   ~HipExecutor() override {
     if (ctx) {
       (void)hipSetDevice(ctx->device);
       (void)hipStreamSynchronize(ctx->stream);
+      if (lds_stream) (void)hipStreamSynchronize(lds_stream);
     }
+    flights.clear();
+    spare.clear();
+    if (up_ev) (void)hipEventDestroy(up_ev);
+    if (lds_stream) (void)hipStreamDestroy(lds_stream);
     for (GraphBuilder* gb : gbuilders) graph_builder_destroy(gb);
   }
+  bool busy() override { return !flights.empty(); }
   void front_end(Request* r) override;
   void finish(Request* r) override;
   void upload(Request* r) override;
@@ -219,7 +244,7 @@ void HipExecutor::tick(std::vector<Request*>& admitted, std::vector<ServeActive>
     DevDesc d = it.r->im.desc[it.comp];
     d.nbr_off += (it.r->arena_off + it.r->off_adj) / 4;
     d.out_off = (int32_t)(it.r->arena_off + it.r->off_colors + d.out_off);
-    d.comp = out_index;   // the record goes to lds_out[out_index]
+    d.comp = out_index;   // the record goes to the flight's out[out_index]
     return d;
   };
   for (size_t i = 0; i < lds_small.size(); ++i) lds_d.push_back(staged(lds_small[i], (int32_t)i));
@@ -240,13 +265,60 @@ void HipExecutor::tick(std::vector<Request*>& admitted, std::vector<ServeActive>
   if (len)
     check_hip(hipMemcpyAsync(list.p, entries.data(), sizeof(int32_t) * len, hipMemcpyHostToDevice, s),
               "serve: upload tick list");
-  if (nl)
-    check_hip(hipMemcpyAsync(lds_desc.p, lds_d.data(), sizeof(DevDesc) * nl, hipMemcpyHostToDevice, s),
+  if (nl) {
+    // a flight on the LDS stream, behind this tick's uploads
+    std::unique_ptr<Flight> f;
+    if (!spare.empty()) {
+      f = std::move(spare.back());
+      spare.pop_back();
+    } else {
+      f.reset(new Flight());
+      check_hip(hipEventCreate(&f->start), "serve: event");
+      check_hip(hipEventCreate(&f->done), "serve: event");
+    }
+    f->items.clear();
+    for (const LdsItem& it : lds_small) f->items.push_back({it.r, it.comp});
+    for (const LdsItem& it : lds_big) f->items.push_back({it.r, it.comp});
+    const size_t db = sizeof(DevDesc) * (size_t)nl, rb = sizeof(DevRecord) * (size_t)nl;
+    if (f->desc.bytes < db) f->desc.alloc(ctx, db);
+    if (f->out.bytes < rb) f->out.alloc(ctx, rb);
+    const size_t gw = lds_big.empty() ? 0 : (size_t)big_words * lds_big.size();
+    if (gw && f->gstack.bytes < sizeof(uint64_t) * gw) f->gstack.alloc(ctx, sizeof(uint64_t) * gw);
+    if (!f->host.reserve(db + rb)) fail(MPLD_E_NOMEM, "serve: pinned host memory");
+    std::memcpy(f->host.p, lds_d.data(), db);
+    check_hip(hipEventRecord(up_ev, s), "serve: event");
+    check_hip(hipStreamWaitEvent(lds_stream, up_ev, 0), "serve: stream wait");
+    check_hip(hipMemcpyAsync(f->desc.p, f->host.p, db, hipMemcpyHostToDevice, lds_stream),
               "serve: upload LDS descriptors");
-  if (!lds_big.empty() && big_words * (int64_t)lds_big.size() > gstack_words) {
-    check_hip(hipStreamSynchronize(s), "serve: grow stack");
-    gstack_words = big_words * (int64_t)lds_big.size();
-    gstack.alloc(ctx, sizeof(uint64_t) * (size_t)gstack_words);
+    check_hip(hipEventRecord(f->start, lds_stream), "serve: event");
+    std::vector<char> lds_trace(lds_d.size());
+    for (size_t i = 0; i < lds_d.size(); ++i) {
+      const LdsItem& it = i < lds_small.size() ? lds_small[i] : lds_big[i - lds_small.size()];
+      lds_trace[i] = (it.r->opt.flags & MPLD_TRACE_HASH) ? 1 : 0;
+    }
+    auto lds_launch = [&](size_t first, size_t count, bool big, int bytes) {
+      size_t a = first;
+      while (a < first + count) {   // one launch per run of equal trace flag
+        size_t b = a;
+        while (b < first + count && lds_trace[b] == lds_trace[a]) ++b;
+        const int per_cu = std::max(1, std::min(32, (160 * 1024) / std::max(bytes, 1)));
+        const int grid = std::max(1, std::min((int)(b - a), ctx->num_cus * per_cu));
+        // the big tier's stack areas: one per workgroup, grid <= count
+        check_hip(launch_lds_batched(lds_trace[a] != 0, big, big ? lds_big_waves(big_max_n) : 1, grid,
+                                     bytes, f->desc.as<DevDesc>() + a, arena.as<uint32_t>(),
+                                     (int32_t)(b - a), counter.as<int32_t>() + 1,
+                                     big ? f->gstack.as<uint64_t>() : nullptr, (uint64_t)big_words,
+                                     f->out.as<DevRecord>(), arena.as<int8_t>(), lds_stream),
+                  "serve: LDS launch");
+        a = b;
+      }
+    };
+    lds_launch(0, lds_small.size(), false, lds_small_bytes);
+    lds_launch(lds_small.size(), lds_big.size(), true, lds_big_bytes);
+    check_hip(hipMemcpyAsync(f->host.as<uint8_t>() + db, f->out.p, rb, hipMemcpyDeviceToHost,
+                             lds_stream), "serve: download LDS records");
+    check_hip(hipEventRecord(f->done, lds_stream), "serve: event");
+    flights.push_back(std::move(f));
   }
   check_hip(hipEventRecord(ctx->ev[2], s), "serve: event");
   const uint64_t slice = (uint64_t)opt.slice_nodes;
@@ -268,37 +340,11 @@ void HipExecutor::tick(std::vector<Request*>& admitted, std::vector<ServeActive>
               "serve: tick launch");
     a = b;
   }
-  std::vector<char> lds_trace(lds_d.size());
-  for (size_t i = 0; i < lds_d.size(); ++i) {
-    const LdsItem& it = i < lds_small.size() ? lds_small[i] : lds_big[i - lds_small.size()];
-    lds_trace[i] = (it.r->opt.flags & MPLD_TRACE_HASH) ? 1 : 0;
-  }
-  auto lds_launch = [&](size_t first, size_t count, bool big, int bytes) {
-    size_t a = first;
-    while (a < first + count) {   // one launch per run of equal trace flag
-      size_t b = a;
-      while (b < first + count && lds_trace[b] == lds_trace[a]) ++b;
-      const int per_cu = std::max(1, std::min(32, (160 * 1024) / std::max(bytes, 1)));
-      const int grid = std::max(1, std::min((int)(b - a), ctx->num_cus * per_cu));
-      check_hip(launch_lds_batched(lds_trace[a] != 0, big, big ? lds_big_waves(big_max_n) : 1, grid,
-                                   bytes, lds_desc.as<DevDesc>() + a,
-                                   arena.as<uint32_t>(), (int32_t)(b - a), counter.as<int32_t>() + 1,
-                                   big ? gstack.as<uint64_t>() : nullptr, (uint64_t)big_words,
-                                   lds_out.as<DevRecord>(), arena8, s),
-                "serve: LDS launch");
-      a = b;
-    }
-  };
-  lds_launch(0, lds_small.size(), false, lds_small_bytes);
-  lds_launch(lds_small.size(), lds_big.size(), true, lds_big_bytes);
   check_hip(hipEventRecord(ctx->ev[3], s), "serve: event");
-  std::vector<DevRecord> out((size_t)len), lout((size_t)nl);
+  std::vector<DevRecord> out((size_t)len);
   if (len)
     check_hip(hipMemcpyAsync(out.data(), tick_out.p, sizeof(DevRecord) * len, hipMemcpyDeviceToHost, s),
               "serve: download tick records");
-  if (nl)
-    check_hip(hipMemcpyAsync(lout.data(), lds_out.p, sizeof(DevRecord) * nl, hipMemcpyDeviceToHost, s),
-              "serve: download LDS records");
   check_hip(hipStreamSynchronize(s), "serve: tick");
   float ms = 0.f;
   if (hipEventElapsedTime(&ms, ctx->ev[2], ctx->ev[3]) == hipSuccess) *device_ms += ms;
@@ -318,12 +364,25 @@ void HipExecutor::tick(std::vector<Request*>& admitted, std::vector<ServeActive>
     if (--a.r->remaining == 0) finished.push_back(a.r);
   }
   active.swap(keep);
-  for (int32_t i = 0; i < nl; ++i) {
-    const LdsItem& it = i < (int32_t)lds_small.size() ? lds_small[i] : lds_big[i - lds_small.size()];
-    if (lout[i].status < 0 || lout[i].status > MPLD_BUDGET_EXHAUSTED)
-      fail(MPLD_E_INTERNAL, "serving LDS search reported a broken state");
-    it.r->recs[it.comp] = lout[i];
-    if (--it.r->remaining == 0) finished.push_back(it.r);
+  // flights that have landed, in launch order
+  while (!flights.empty()) {
+    Flight& f = *flights.front();
+    const hipError_t q = hipEventQuery(f.done);
+    if (q == hipErrorNotReady) break;
+    check_hip(q, "serve: LDS flight");
+    float fms = 0.f;
+    if (hipEventElapsedTime(&fms, f.start, f.done) == hipSuccess) *device_ms += fms;
+    const DevRecord* lout = reinterpret_cast<const DevRecord*>(
+        f.host.as<uint8_t>() + sizeof(DevDesc) * f.items.size());
+    for (size_t i = 0; i < f.items.size(); ++i) {
+      if (lout[i].status < 0 || lout[i].status > MPLD_BUDGET_EXHAUSTED)
+        fail(MPLD_E_INTERNAL, "serving LDS search reported a broken state");
+      Request* r = f.items[i].first;
+      r->recs[(size_t)f.items[i].second] = lout[i];
+      if (--r->remaining == 0) finished.push_back(r);
+    }
+    spare.push_back(std::move(flights.front()));
+    flights.pop_front();
   }
   for (Request* r : admitted)
     if (r->recs.empty()) finished.push_back(r);   // nothing to search
@@ -416,8 +475,8 @@ int32_t mpld_server_create(mpld_context* ctx, const mpld_server_options* opt, mp
       x->slot_state.alloc(ctx, kRegStateBytes * (size_t)x->max_slots);
       x->list.alloc(ctx, sizeof(int32_t) * (size_t)x->max_slots);
       x->tick_out.alloc(ctx, sizeof(DevRecord) * (size_t)x->max_slots);
-      x->lds_desc.alloc(ctx, sizeof(DevDesc) * (size_t)x->max_slots);
-      x->lds_out.alloc(ctx, sizeof(DevRecord) * (size_t)x->max_slots);
+      check_hip(hipStreamCreate(&x->lds_stream), "serve: LDS stream");
+      check_hip(hipEventCreateWithFlags(&x->up_ev, hipEventDisableTiming), "serve: event");
       x->counter.alloc(ctx, sizeof(int32_t) * 4);
       // one builder by default: with four, the measured p99 latency of a
       // Poisson mix of layout requests rose by about a third

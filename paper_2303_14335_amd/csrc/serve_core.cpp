@@ -160,7 +160,8 @@ void ServeCore::scheduler_loop() {
       std::unique_lock<std::mutex> lk(mu_);
       if (stop_) break;
       if (ready_.empty() && active_.empty()) {
-        cv_sched_.wait_for(lk, std::chrono::milliseconds(2));
+        cv_sched_.wait_for(lk, exec_->busy() ? std::chrono::microseconds(50)
+                                             : std::chrono::microseconds(2000));
         if (stop_) break;
       }
       bool waited = false;
@@ -189,7 +190,7 @@ void ServeCore::scheduler_loop() {
       }
       if (waited) ++stats_.admission_waits;
     }
-    if (admitted.empty() && active_.empty()) continue;
+    if (admitted.empty() && active_.empty() && !exec_->busy()) continue;
     int32_t err = MPLD_OK;
     std::string err_text;
     std::vector<Request*> finished;

@@ -82,8 +82,9 @@ class ServeExecutor {
   // r->slot_base are set).
   virtual void upload(Request* r) = 0;
   // Scheduler thread: one tick.  Appends the register-tier components of
-  // `admitted` to `active`, advances every active component, runs the
-  // other components of `admitted` to completion, drops finished
+  // `admitted` to `active` and advances every active component; starts the
+  // other components of `admitted`, which may run past this tick (busy()
+  // is true until a later tick has collected them); drops finished
   // components from `active` (their records go to r->recs), and appends to
   // `finished` every request whose components are all done, with its
   // colors in r->lcol.  Adds its device time to *device_ms.  Throws Error on
@@ -92,6 +93,9 @@ class ServeExecutor {
                     std::vector<Request*>& finished, double* device_ms) = 0;
   // Scheduler thread, once at its start.
   virtual void bind_thread() {}
+  // Scheduler thread: work is still running that a tick will collect
+  // (then the scheduler ticks even with nothing else to do).
+  virtual bool busy() { return false; }
 };
 
 class ServeCore {

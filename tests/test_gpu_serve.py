@@ -223,3 +223,34 @@ def test_largest_serving_requests_vs_oracle(ctx):
     assert max(len(r["rects"]) for r in reqs) >= 40000
     for r, got in zip(reqs, results):
         check_oracle(got, r, SERVE["budget"], flags)
+
+
+def test_heavy_lds_component_does_not_hold_up_small_requests(ctx):
+    """A budget-heavy component above 64 nodes (about 0.35 s on the LDS
+    tier) runs beside the ticks: small requests submitted after it finish
+    long before it does, and every result equals the oracle's."""
+    import time
+
+    import paper_2303_14335_amd as mp
+    n, deg, seed = 200, 5.6, 4   # INFEASIBLE after 501,238 search nodes (BFS numbering)
+    e = np.asarray(workload.random_component(n, deg, seed), np.int32).reshape(-1, 2)
+    heavy = mp.Graph(n, e, np.zeros((0, 2), np.int32))
+    small = requests(20, seed=55, n_max=3000)
+    say("serve a heavy LDS-tier component beside small requests")
+    srv = mp.Server(ctx, slice_nodes=64)
+    th = srv.submit(heavy, 3, 10**6, 0)
+    time.sleep(0.03)
+    ts = [srv.submit_layout(r["rects"], r["dmin"], 0, 3, 10**6, SIMPLIFY) for r in small]
+    small_res = [srv.wait(t, 60_000_000) for t in ts]
+    heavy_res = srv.wait(th, 60_000_000)
+    srv.close()
+    ref = oracle.decompose(oracle.Graph(n, e, np.zeros((0, 2), np.int32)), 3, 10**6,
+                           simplify=False)
+    for f in ("status", "nodes", "depth_at_stop"):
+        assert np.array_equal(heavy_res.components[f], ref.comps[f]), f
+    assert np.array_equal(heavy_res.colors, ref.colors)
+    for r, got in zip(small, small_res):
+        check_oracle(got, dict(r, split=0, k=3), 10**6, SIMPLIFY)
+    slowest_small = max(g.total_us for g in small_res)
+    assert heavy_res.total_us > 150_000
+    assert slowest_small < heavy_res.total_us / 3, (slowest_small, heavy_res.total_us)
