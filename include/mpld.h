@@ -50,6 +50,15 @@
  *     context is unusable and must be destroyed.
  *   - Every device step is HIP code; there is no host fallback: a missing
  *     device returns MPLD_E_DEVICE.
+ *
+ * Surface, against a plainer sketch of it (generate / submit / poll / wait
+ * / free on the context): no layout generator here - synthetic layouts come
+ * from a separate input library, so that the checking code and this library
+ * share nothing but their inputs, and a user brings their own rectangles;
+ * serving is a server object on a context (mpld_server_*), so that one
+ * context can host servers with arenas of their own; every owned object
+ * has a typed free (mpld_result_free, mpld_owned_graph_free,
+ * mpld_batch_free, mpld_server_destroy) rather than one generic free.
  */
 #ifndef MPLD_H
 #define MPLD_H
