@@ -132,9 +132,9 @@ enum {
                                   takes the color of the row it lost last.
                                   Status, node count, hash and depth stay the
                                   search's; `conflicts` and `stitches` are
-                                  counted on the colors.  Decompose, batches
-                                  and mpld_solve_components only (a server
-                                  rejects it with MPLD_E_UNSUPPORTED). */
+                                  counted on the colors.  Decompose, batches,
+                                  mpld_solve_components and servers (a served
+                                  component is marked when its search ends). */
   MPLD_STITCH_ORDER = 1u << 11, /* stitch-aware row order (Eq. 1 counts a stitch
                                   for each pair of split halves colored
                                   differently): when the chosen column's node

@@ -617,12 +617,9 @@ __global__ __launch_bounds__(64) void reg_single_kernel(const RegItems items,
 // conflicts with the neighbour that took that color.  Lane u holds N(u) and
 // the color u lost last; the planes are wave-uniform.  Every node is colored.
 template <int K>
-__device__ __forceinline__ void mark_reg(const RegItems& items, int32_t item,
-                                         int8_t* __restrict__ colors_base) {
+__device__ __forceinline__ void mark_core(uint32_t n, const uint64_t nb, int8_t* __restrict__ colors) {
   const uint32_t lane = __lane_id();
-  const DevDesc d = item_desc(items, item);
-  const uint64_t nb = item_mask(items, item, lane);
-  const uint32_t n = uniform((uint32_t)d.n);
+  n = uniform(n);
   uint64_t P = n >= 64u ? ~0ull : ((1ull << n) - 1ull);
   uint64_t O[K];
 #pragma unroll
@@ -655,7 +652,14 @@ __device__ __forceinline__ void mark_reg(const RegItems& items, int32_t item,
       }
     if ((removed >> lane) & 1ull) last = c;
   }
-  if (lane < n) colors_base[d.out_off + lane] = (int8_t)color;
+  if (lane < n) colors[lane] = (int8_t)color;
+}
+
+template <int K>
+__device__ __forceinline__ void mark_reg(const RegItems& items, int32_t item,
+                                         int8_t* __restrict__ colors_base) {
+  const DevDesc d = item_desc(items, item);
+  mark_core<K>((uint32_t)d.n, item_mask(items, item, __lane_id()), colors_base + d.out_off);
 }
 
 // One wave per workgroup over the register-tier items; components whose
@@ -672,9 +676,10 @@ __global__ __launch_bounds__(64) void mark_reg_kernel(const RegItems items, int3
 }
 
 // Serving tick: every listed component advances by at most `slice` search
-// nodes from its saved state (entries with bit 31 set start fresh).  A
-// finished search writes its colors and record; a paused one saves its
-// state.  tick_out[i] receives the record of list entry i (status -1 while
+// nodes from its saved state (entries with bit 31 set start fresh; bit 30:
+// a component left without a solution is then colored by the conflict
+// marking).  A finished search writes its colors and record; a paused one
+// saves its state.  tick_out[i] receives the record of list entry i (status -1 while
 // the search is still running).  Work distribution as in the batched kernel.
 template <bool TRACE, int K>
 __global__ __launch_bounds__(256) void reg_tick_kernel(
@@ -686,7 +691,7 @@ __global__ __launch_bounds__(256) void reg_tick_kernel(
   int32_t item = (int32_t)uniform(xcd_block() * 4u + (threadIdx.x >> 6));
   while (item < len) {
     const uint32_t entry = uniform((uint32_t)list[item]);
-    const int32_t slot = (int32_t)(entry & 0x7fffffffu);
+    const int32_t slot = (int32_t)(entry & 0x3fffffffu);
     const DevDesc d = slot_desc[slot];
     const uint32_t lane = __lane_id();
     const uint64_t nb = lane < (uint32_t)d.n ? arena64[d.nbr_off + lane] : 0ull;
@@ -699,10 +704,15 @@ __global__ __launch_bounds__(256) void reg_tick_kernel(
     const uint64_t budget = (uint64_t)d.budget;
     const uint64_t stop = budget - s.nodes > slice ? s.nodes + slice : budget;
     reg_run<TRACE, K>(s, (uint32_t)nb, (uint32_t)(nb >> 32), d.k, budget, stop);
-    if (s.status >= 0)
+    if (s.status >= 0) {
       reg_finish(s, d.n, arena8 + d.out_off, slot_rec + slot);
-    else
+      // conflict marking of a component left without a solution (the
+      // wave's own stores, so they follow reg_finish's)
+      if (((entry >> 30) & 1u) && s.status != MPLD_FEASIBLE)
+        mark_core<K>((uint32_t)d.n, nb, arena8 + d.out_off);
+    } else {
       reg_save(s, base);
+    }
     DevRecord* o = tick_out + item;
     o->status = s.status;
     o->depth = (int32_t)s.depth;

@@ -55,7 +55,7 @@ class HipExecutor : public ServeExecutor {
   // tick collects the ones that have finished.
   struct Flight {
     std::vector<std::pair<Request*, int32_t>> items;   // (request, component)
-    DevBuf desc, out, gstack;
+    DevBuf desc, out, gstack, mark_desc;
     PinnedBuf host;             // descriptors up, then the records down
     hipEvent_t start = nullptr, done = nullptr;
     ~Flight() {
@@ -259,7 +259,8 @@ void HipExecutor::tick(std::vector<Request*>& admitted, std::vector<ServeActive>
   });
   std::vector<int32_t> entries(active.size());
   for (size_t i = 0; i < active.size(); ++i)
-    entries[i] = active[i].slot | (active[i].fresh ? (int32_t)0x80000000u : 0);
+    entries[i] = active[i].slot | (active[i].fresh ? (int32_t)0x80000000u : 0) |
+                 ((active[i].r->opt.flags & MPLD_MARK_CONFLICTS) ? 0x40000000 : 0);
   const int32_t len = (int32_t)entries.size();
   const int32_t nl = (int32_t)lds_d.size();
   if (len)
@@ -284,8 +285,23 @@ void HipExecutor::tick(std::vector<Request*>& admitted, std::vector<ServeActive>
     if (f->out.bytes < rb) f->out.alloc(ctx, rb);
     const size_t gw = lds_big.empty() ? 0 : (size_t)big_words * lds_big.size();
     if (gw && f->gstack.bytes < sizeof(uint64_t) * gw) f->gstack.alloc(ctx, sizeof(uint64_t) * gw);
-    if (!f->host.reserve(db + rb)) fail(MPLD_E_NOMEM, "serve: pinned host memory");
+    // conflict marking of the components of requests that asked for it
+    // (the marking kernel skips the ones whose record is FEASIBLE)
+    std::vector<DevDesc> md;
+    int64_t mark_bytes = 0;
+    for (int32_t i = 0; i < nl; ++i)
+      if (f->items[(size_t)i].first->opt.flags & MPLD_MARK_CONFLICTS) {
+        md.push_back(lds_d[(size_t)i]);
+        mark_bytes = std::max(mark_bytes, mark_lds_bytes(lds_d[(size_t)i].n, lds_d[(size_t)i].k));
+      }
+    if (mark_bytes > ctx->lds_per_block)
+      fail(MPLD_E_UNSUPPORTED, "a component is too large for conflict marking");
+    const size_t mb = sizeof(DevDesc) * md.size();
+    // staging: descriptors up, records down, marking descriptors up (sized
+    // once, before any copy from it is enqueued)
+    if (!f->host.reserve(db + rb + mb)) fail(MPLD_E_NOMEM, "serve: pinned host memory");
     std::memcpy(f->host.p, lds_d.data(), db);
+    if (mb) std::memcpy(f->host.as<uint8_t>() + db + rb, md.data(), mb);
     check_hip(hipEventRecord(up_ev, s), "serve: event");
     check_hip(hipStreamWaitEvent(lds_stream, up_ev, 0), "serve: stream wait");
     check_hip(hipMemcpyAsync(f->desc.p, f->host.p, db, hipMemcpyHostToDevice, lds_stream),
@@ -315,6 +331,15 @@ void HipExecutor::tick(std::vector<Request*>& admitted, std::vector<ServeActive>
     };
     lds_launch(0, lds_small.size(), false, lds_small_bytes);
     lds_launch(lds_small.size(), lds_big.size(), true, lds_big_bytes);
+    if (!md.empty()) {
+      if (f->mark_desc.bytes < mb) f->mark_desc.alloc(ctx, mb);
+      check_hip(hipMemcpyAsync(f->mark_desc.p, f->host.as<uint8_t>() + db + rb, mb,
+                               hipMemcpyHostToDevice, lds_stream), "serve: upload marking descriptors");
+      check_hip(launch_mark_lds(std::max(1, std::min((int)md.size(), ctx->num_cus * 4)), (int)mark_bytes,
+                                f->mark_desc.as<DevDesc>(), arena.as<uint32_t>(), (int32_t)md.size(),
+                                f->out.as<DevRecord>(), arena.as<int8_t>(), lds_stream),
+                "serve: conflict marking");
+    }
     check_hip(hipMemcpyAsync(f->host.as<uint8_t>() + db, f->out.p, rb, hipMemcpyDeviceToHost,
                              lds_stream), "serve: download LDS records");
     check_hip(hipEventRecord(f->done, lds_stream), "serve: event");
@@ -434,8 +459,6 @@ void check_opts(const mpld_options* o) {
   if (o->node_budget < 1) fail(MPLD_E_INVALID, "node_budget must be >= 1");
   if (o->flags & (MPLD_PLAIN | MPLD_FORCE_WAVE | MPLD_FORCE_LDS | MPLD_FORCE_GLOBAL | MPLD_FORCE_DEVICE))
     fail(MPLD_E_INVALID, "serving takes no PLAIN or FORCE_* flags");
-  if (o->flags & MPLD_MARK_CONFLICTS)
-    fail(MPLD_E_UNSUPPORTED, "serving does not mark conflicts (MPLD_MARK_CONFLICTS)");
   if (o->flags & MPLD_STITCH_ORDER)
     fail(MPLD_E_UNSUPPORTED, "serving keeps the ascending row order (MPLD_STITCH_ORDER)");
   if (o->flags & MPLD_MINIMIZE)

@@ -123,12 +123,17 @@ def test_batch_marks_on_every_solve(ctx):
     b.close()
 
 
-def test_server_rejects_marking(ctx):
+def test_server_marks_conflicts(ctx):
+    """A served request with MPLD_MARK_CONFLICTS (K4 and a 5-cycle with three
+    masks: the clique is infeasible, so it is marked) equals the one-shot
+    decomposition and the oracle's."""
     import paper_2303_14335_amd as mp
-    say("server rejects MPLD_MARK_CONFLICTS")
+    say("server marks conflicts (K4 + C5)")
+    edges = complete(4) + [(4 + a, 4 + b) for a, b in cycle(5)]
+    g = mp.Graph(9, np.array(edges, dtype=np.int32), np.zeros((0, 2), np.int32))
     srv = mp.Server(ctx)
-    g = mp.Graph(4, np.array(complete(4), dtype=np.int32), np.zeros((0, 2), np.int32))
-    with pytest.raises(mp.MpldError) as e:
-        srv.submit(g, 3, 100, SIMPLIFY | MARK)
-    assert e.value.code == -7
+    got = srv.wait(srv.submit(g, 3, 100, SIMPLIFY | TRACE | MARK), 30_000_000)
     srv.close()
+    ref = oracle.decompose(oracle.Graph(g.num_nodes, g.ce, g.se), 3, 100, mark=True)
+    compare(got, ref)
+    assert got.conflicts == 1 and got.uncolored == 0

@@ -254,3 +254,41 @@ def test_heavy_lds_component_does_not_hold_up_small_requests(ctx):
     slowest_small = max(g.total_us for g in small_res)
     assert heavy_res.total_us > 150_000
     assert slowest_small < heavy_res.total_us / 3, (slowest_small, heavy_res.total_us)
+
+
+def test_conflict_marking_served(ctx):
+    """MPLD_MARK_CONFLICTS in serving: register-tier components marked in
+    the tick that ends their search, LDS-tier ones in their flight; every
+    result equals the one-shot decomposition and the oracle's (marking on),
+    for any slice."""
+    import paper_2303_14335_amd as mp
+    from algx_literal import random_graph
+    MARK = 1 << 10
+    rng = np.random.default_rng(12)
+    graphs = []
+    for n in (70, 120, 260):   # LDS tier, near the 3-colorability threshold
+        e = np.array(random_graph(rng, n, 5.4 / n), dtype=np.int32).reshape(-1, 2)
+        graphs.append(mp.Graph(n, e, np.zeros((0, 2), np.int32)))
+    small = requests(16, seed=21, n_max=8000)
+    for slice_nodes in (3, 4096):
+        say("serve with conflict marking, slice", slice_nodes)
+        srv = mp.Server(ctx, slice_nodes=slice_nodes)
+        tg = [srv.submit(g, 3, 20000, SIMPLIFY | MARK) for g in graphs]
+        ts = [srv.submit_layout(r["rects"], r["dmin"], 0, 3, 20000, SIMPLIFY | MARK | TRACE)
+              for r in small]
+        got_g = [srv.wait(t, 60_000_000) for t in tg]
+        got_s = [srv.wait(t, 60_000_000) for t in ts]
+        srv.close()
+        for g, got in zip(graphs, got_g):
+            same(got, mp.mpld_decompose(ctx, g, 3, 20000, SIMPLIFY | MARK))
+            ref = oracle.decompose(oracle.Graph(g.num_nodes, g.ce, g.se), 3, 20000, mark=True)
+            assert np.array_equal(got.colors, ref.colors)
+            for f in ("status", "nodes", "conflicts", "stitches"):
+                assert np.array_equal(got.components[f], ref.comps[f]), f
+            assert got.uncolored == 0
+        for r, got in zip(small, got_s):
+            ref = oracle.decompose(oracle.build_graph(r["rects"], r["dmin"], 0), 3, 20000, mark=True)
+            assert np.array_equal(got.colors, ref.colors)
+            for f in ("status", "nodes", "trace_hash", "conflicts", "stitches"):
+                assert np.array_equal(got.components[f], ref.comps[f]), f
+            assert (got.conflicts, got.uncolored) == (ref.conflicts, ref.uncolored)
