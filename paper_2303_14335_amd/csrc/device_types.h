@@ -43,6 +43,10 @@ struct RegItems {
 constexpr uint32_t kRegItemHead = 32;
 inline uint32_t reg_item_width(int32_t max_n) { return max_n < 1 ? 1u : (uint32_t)max_n; }
 
+// Largest component of the one-wave LDS tier (one 32-bit node word per
+// lane of a wave).
+constexpr int32_t kLds1MaxN = 2048;
+
 // One record per component (24 bytes), written by the search.
 struct DevRecord {
   int32_t status;   // MPLD_FEASIBLE / MPLD_INFEASIBLE / MPLD_BUDGET_EXHAUSTED

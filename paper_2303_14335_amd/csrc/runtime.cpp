@@ -90,7 +90,7 @@ void image_add(Image& im, mpld_context* ctx, int32_t n, const int32_t* pairs, in
       im.dev_stack_words = std::max(im.dev_stack_words, device_tier_stack_words(n, (int32_t)maxdeg));
       im.dev_max_n = std::max(im.dev_max_n, n);
       im.q_dev.push_back(id);
-    } else if (!force_glb && small <= limit && (n + 63) / 64 <= 64) {
+    } else if (!force_glb && small <= limit && n <= kLds1MaxN) {
       im.lds_bytes_small = std::max(im.lds_bytes_small, small);
       im.q_lds.push_back(id);
     } else if (big <= ctx->lds_per_block) {

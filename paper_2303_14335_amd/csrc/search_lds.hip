@@ -144,9 +144,63 @@ __device__ __forceinline__ uint64_t make_hdr(uint32_t v, uint32_t c, uint32_t ro
   return (uint64_t)v | ((uint64_t)c << 24) | ((uint64_t)rows << 28) | ((uint64_t)est << 36);
 }
 
-// Small components: one wave; neighbour lists, level headers and the undo
-// log in LDS, the per-depth bit set in lane registers (word l in lane l; the
-// host admits at most 64 words).
+// ---- one-wave tier --------------------------------------------------------
+//
+// Components of at most kLds1MaxN nodes: one wave, 32-bit plane words, one
+// node word per lane (lane l holds nodes 32l .. 32l+31), everything in LDS:
+//   planes   64 node words x S dwords: word w of plane c (c < k) at w*S + c,
+//            P at w*S + k, so a lane reads all of its word's planes with
+//            S/4 ds_read_b128 (S = k+1 rounded up to 4, 8 or 16);
+//   offs     per node: first neighbour (low 16 bits) | degree << 16;
+//   ids      16-bit neighbour ids;
+//   hdr      per depth: {offs of the level's column, est | rows << 16 | c << 24}
+//            (est: the level's first log entry, which holds the column's P
+//            bit, so the column itself is read back from the log);
+//   ent      the undo log.
+// The per-depth "untried rows" bit set is one 32-bit word per lane (depth d
+// in lane d >> 5).  Per node the dependent chain is: the plane words (read
+// at the end of the previous node, behind its cover atomics), the count and
+// narrowing in each lane, a wave minimum, then the winner's row set and
+// offs word (each lane reads the offs word of its own candidate before the
+// minimum, so the winner's is already in a register), one read of the
+// neighbour ids, and one atomic AND per neighbour (lane 0 clears the
+// column's P bit in the same instruction).
+__host__ __device__ constexpr uint32_t lds1_stride(int32_t k) {
+  return k + 1 <= 4 ? 4u : (k + 1 <= 8 ? 8u : 16u);
+}
+
+struct Lds1Layout {
+  uint32_t offs_off, ids_off, hdr_off, ent_off, total;
+};
+
+__host__ __device__ inline Lds1Layout lds1_layout(int32_t n, int32_t k, int64_t adj_words) {
+  Lds1Layout L;
+  const uint32_t m2 = (uint32_t)(adj_words - n - 1);
+  L.offs_off = 64u * 4u * lds1_stride(k);
+  L.ids_off = L.offs_off + 4u * (uint32_t)n;
+  L.hdr_off = (L.ids_off + 2u * m2 + 7u) & ~7u;
+  L.ent_off = L.hdr_off + 8u * (uint32_t)n;
+  L.total = (L.ent_off + 4u * lds_log_entries(n, k, adj_words) + 15u) & ~15u;
+  return L;
+}
+
+template <int K>
+struct Lds1Words {
+  static constexpr int S = (int)lds1_stride(K);
+  uint32_t a[S];
+  __device__ __forceinline__ void load(const uint32_t* PL, uint32_t lane) {
+    const uint4* q = reinterpret_cast<const uint4*>(PL + lane * (uint32_t)S);
+#pragma unroll
+    for (int j = 0; j < S / 4; ++j) {
+      const uint4 x = q[j];
+      a[4 * j] = x.x;
+      a[4 * j + 1] = x.y;
+      a[4 * j + 2] = x.z;
+      a[4 * j + 3] = x.w;
+    }
+  }
+};
+
 // root_row >= 0: search only the subtree of root row (0, root_row) (a
 // subtree task of the heavy-component split): at the root every column has
 // all k rows, so the root column is node 0; its row is taken at depth 0
@@ -156,73 +210,146 @@ template <bool TRACE, int K>
 __device__ void solve_lds(const DevDesc& d, const uint32_t* __restrict__ gadj, char* lds,
                           int8_t* __restrict__ colors, DevRecord* __restrict__ rec,
                           int32_t root_row = -1, uint64_t task_budget = 0) {
+  constexpr uint32_t S = lds1_stride(K);
+  constexpr int NB = bits_for(K);
+  constexpr uint32_t kNodeMask = (1u << kEntryNodeBits) - 1u;
   const uint32_t lane = __lane_id();
   const uint32_t n = (uint32_t)d.n;
-  // adjacency block: [0..n] row offsets, [n+1 ..] neighbour ids
-  const uint32_t adj_words = uni(gadj[n]) + n + 1u;
-  const LdsLayout L = lds_layout((int32_t)n, K, adj_words, false);
-  const uint32_t W = L.W;
-  uint64_t* PL = reinterpret_cast<uint64_t*>(lds + L.pl_off);
-  uint32_t* la = reinterpret_cast<uint32_t*>(lds + L.adj_off);
-  for (uint32_t i = lane; i < adj_words; i += 64) la[i] = gadj[i];
-  const uint32_t* adj = la;
-  uint64_t* hdr = reinterpret_cast<uint64_t*>(lds + L.hdr_off);
+  const uint32_t m2 = uni(gadj[n]);
+  const Lds1Layout L = lds1_layout((int32_t)n, K, (int64_t)m2 + n + 1);
+  uint32_t* PL = reinterpret_cast<uint32_t*>(lds);
+  uint32_t* offs = reinterpret_cast<uint32_t*>(lds + L.offs_off);
+  uint16_t* ids = reinterpret_cast<uint16_t*>(lds + L.ids_off);
+  uint2* hdr = reinterpret_cast<uint2*>(lds + L.hdr_off);
   uint32_t* ent = reinterpret_cast<uint32_t*>(lds + L.ent_off);
-  const uint32_t* ids = adj + n + 1;
-  // initial state: every node uncovered with all k colors open
-  for (uint32_t w = lane; w < W; w += 64) {
-    const uint32_t cnt = n - w * 64u >= 64u ? 64u : n - w * 64u;
-    const uint64_t val = cnt == 64u ? ~0ull : ((1ull << cnt) - 1ull);
-#pragma unroll
-    for (int c = 0; c <= K; ++c) PL[(uint32_t)c * W + w] = val;
+  for (uint32_t v = lane; v < n; v += 64) {
+    const uint32_t b = gadj[v], e = gadj[v + 1];
+    offs[v] = b | ((e - b) << 16);
   }
-  uint64_t areg = 0;   // per-depth bit set, word `lane`
+  for (uint32_t i = lane; i < m2; i += 64) ids[i] = (uint16_t)gadj[n + 1 + i];
+  {
+    // every node uncovered with all k colors open; words past n are empty
+    const uint32_t base = lane * 32u;
+    const uint32_t cnt = base >= n ? 0u : (n - base >= 32u ? 32u : n - base);
+    const uint32_t val = cnt == 32u ? ~0u : ((1u << cnt) - 1u);
+#pragma unroll
+    for (uint32_t c = 0; c < S; ++c) PL[lane * S + c] = c <= (uint32_t)K ? val : 0u;
+  }
   __syncthreads();
 
   uint32_t depth = 0, row_in = kNoneL, esp = 0;
   uint64_t nodes = 0, h = kFnvOffsetL;
   int32_t status = -1;
+  uint32_t areg = 0;   // untried-rows bit of depth 32 * lane + b
   const uint64_t budget = root_row >= 0 ? task_budget : (uint64_t)d.budget;
-  if (root_row >= 0) {
-    // take row (0, root_row) at depth 0: node 0 leaves P, its neighbours
-    // lose color root_row; level 0 has no untried row (areg stays clear)
-    const uint32_t c = (uint32_t)root_row;
-    const uint32_t beg = uni(adj[0]), deg = uni(adj[1]) - beg;
-    if (lane == 63u) {
-      ent[0] = (uint32_t)K << kEntryNodeBits;
-      atomicAnd(reinterpret_cast<unsigned long long*>(&PL[(uint32_t)K * W]), ~1ull);
-      hdr[0] = make_hdr(0u, c, (1u << K) - 1u, 0u);
-    }
-    esp = 1u;
-    unsigned long long* plane = reinterpret_cast<unsigned long long*>(PL + c * W);
-    for (uint32_t ch = 0; ch < deg; ch += 64u) {
-      bool hit = false;
-      uint32_t u = 0;
-      if (ch + lane < deg) {
-        u = ids[beg + ch + lane];
-        const uint64_t bit = 1ull << (u & 63u);
-        hit = (atomicAnd(&plane[u >> 6], ~bit) & bit) != 0ull;
+  const uint32_t nm1 = n - 1u;
+  Lds1Words<K> W;
+
+  // Take row (v, c) at `depth`: the level's header and untried-rows bit,
+  // then one atomic AND per neighbour of v on plane c (lanes 1 .. deg) and,
+  // if `cover_v`, on v's P bit (lane 0); the removed rows go to the log from
+  // `est` (v's P bit first), and the plane words of the next node are read
+  // right behind the atomics.
+  auto take_row = [&](uint32_t v, uint32_t c, uint32_t rows, uint32_t offv, uint32_t est,
+                      bool cover_v, bool more) {
+    const uint32_t beg = offv & 0xffffu, deg = offv >> 16;
+    const uint32_t first = deg < 63u ? deg : 63u;
+    const bool act = lane == 0u ? cover_v : lane <= first;
+    uint32_t u = v, pl = (uint32_t)K, old = 0u, bitm = 0u;
+    if (act) {
+      if (lane != 0u) {
+        u = ids[beg + lane - 1u];
+        pl = c;
       }
-      const uint64_t bal = __ballot(hit);
+      bitm = 1u << (u & 31u);
+      old = atomicAnd(&PL[(u >> 5) * S + pl], ~bitm);
+    }
+    // the next node's plane words, behind the atomics (read again below
+    // when v has more than 63 neighbours)
+    W.load(PL, lane);
+    if (lane == 0u) hdr[depth] = make_uint2(offv, est | (rows << 16) | (c << 24));
+    {
+      const uint32_t dl = depth >> 5, db = 1u << (depth & 31u);
+      const uint32_t w = rdlane(areg, dl);
+      areg = wrlane(areg, dl, more ? (w | db) : (w & ~db));
+    }
+    uint32_t slot = cover_v ? est : est + 1u;
+    auto log_hits = [&](bool hit, uint32_t uu, uint32_t pp) {
+      const uint64_t bal = __builtin_amdgcn_ballot_w64(hit);
       if (hit) {
         const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
                                                         __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
-        ent[esp + rank] = (c << kEntryNodeBits) | u;
+        ent[slot + rank] = (pp << kEntryNodeBits) | uu;
       }
-      esp += (uint32_t)__popcll(bal);
+      slot += (uint32_t)__popcll(bal);
+    };
+    log_hits(act && (old & bitm) != 0u, u, pl);
+    if (deg > 63u) {
+      for (uint32_t ch = 63u; ch < deg; ch += 64u) {
+        bool hit = false;
+        uint32_t uu = 0;
+        if (ch + lane < deg) {
+          uu = ids[beg + ch + lane];
+          const uint32_t b = 1u << (uu & 31u);
+          hit = (atomicAnd(&PL[(uu >> 5) * S + c], ~b) & b) != 0u;
+        }
+        log_hits(hit, uu, c);
+      }
+      W.load(PL, lane);
     }
+    esp = slot;
+    // One wave executes its LDS operations in order, so the next node's
+    // loads see these writes; this only keeps the compiler from caching
+    // LDS values across the loop.
     asm volatile("" ::: "memory");
+  };
+
+  if (root_row >= 0) {
+    // row (0, root_row) at depth 0, with no alternative at that level
+    const uint32_t c = (uint32_t)root_row;
+    take_row(0u, c, (1u << K) - 1u, uni(offs[0]), 0u, true, false);
     depth = 1u;
     row_in = c;
+  } else {
+    W.load(PL, lane);
   }
 
   while (status < 0) {
     // ---- one search node
     if (nodes == budget) { status = MPLD_BUDGET_EXHAUSTED; break; }
     ++nodes;
-    uint32_t key = kNoKey;
-    for (uint32_t w = lane; w < W; w += 64) key = min(key, word_key<K>(PL, W, w));
-    key = wave_min(key);
+    // column choice: bit-sliced counts of this lane's word, narrowed from
+    // the top count bit to the lowest-count uncovered columns
+    uint32_t cnt[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) cnt[b] = 0u;
+#pragma unroll
+    for (int c = 0; c < K; ++c) {
+      uint32_t carry = W.a[c];
+#pragma unroll
+      for (int b = 0; b < bits_for(c + 1); ++b) {
+        const uint32_t t = cnt[b] & carry;
+        cnt[b] ^= carry;
+        carry = t;
+      }
+    }
+    const uint32_t p = W.a[K];
+    uint32_t cand = p, t = 0u;
+#pragma unroll
+    for (int b = NB - 1; b >= 0; --b) {
+      const uint32_t x = cand & ~cnt[b];
+      if (x) cand = x;
+      else t |= 1u << b;
+    }
+    const uint32_t bit = (uint32_t)__builtin_ctz(cand | 0x80000000u);
+    const uint32_t vl = (lane << 5) | bit;
+    uint32_t r = 0;
+#pragma unroll
+    for (int c = 0; c < K; ++c) r |= __builtin_amdgcn_ubfe(W.a[c], bit, 1u) << c;
+    const uint32_t pre = offs[vl < nm1 ? vl : nm1];
+    // issue that read before the minimum (which it then overlaps)
+    asm volatile("" ::: "memory");
+    const uint32_t key = wave_min(p ? ((t << 24) | vl) : kNoKey);
     if (key == kNoKey) {   // no uncovered column: the levels hold a solution
       if (TRACE) h = trace_node_l(h, depth, row_in, kNoneL, 0);
       status = MPLD_FEASIBLE;
@@ -231,102 +358,49 @@ __device__ void solve_lds(const DevDesc& d, const uint32_t* __restrict__ gadj, c
     uint32_t v = key & 0xffffffu;
     const uint32_t size = key >> 24;
     if (TRACE) h = trace_node_l(h, depth, row_in, v, size);
-    uint32_t c, rows, est, beg, deg, u0;
     if (size != 0) {
-      // rows of v and its neighbour list, loaded together
-      const uint32_t b0 = adj[v], b1 = adj[v + 1];
-      uint32_t r = 0;
-#pragma unroll
-      for (int j = 0; j < K; ++j) r |= (uint32_t)((PL[(uint32_t)j * W + (v >> 6)] >> (v & 63u)) & 1ull) << j;
-      beg = uni(b0);
-      deg = uni(b1) - beg;
-      u0 = lane < deg ? ids[beg + lane] : 0u;
-      rows = uni(r);
-      c = (uint32_t)__builtin_ctz(rows);
-      // cover column v: its P bit becomes the first entry of the level
-      est = esp;
-      if (lane == 63u) {
-        ent[est] = ((uint32_t)K << kEntryNodeBits) | v;
-        atomicAnd(reinterpret_cast<unsigned long long*>(&PL[(uint32_t)K * W + (v >> 6)]),
-                  ~(1ull << (v & 63u)));
-      }
-      esp = est + 1u;
+      const uint32_t wl = v >> 5;
+      const uint32_t rows = rdlane(r, wl);
+      const uint32_t c = (uint32_t)__builtin_ctz(rows);
+      take_row(v, c, rows, rdlane(pre, wl), esp, true, (rows >> (c + 1u)) != 0u);
+      row_in = v * (uint32_t)K + c;
     } else {
       // dead end: back to the deepest level whose column has an untried row
       uint32_t f = kNoneL;
       if (depth != 0) {
-        const uint32_t d1 = depth - 1u, dw = d1 >> 6;
-        const uint64_t below = ~0ull >> (63u - (d1 & 63u));
-        const uint64_t m = lane < dw ? areg : (lane == dw ? areg & below : 0ull);
-        const uint64_t bal = __ballot(m != 0ull);
+        const uint32_t d1 = depth - 1u, dw = d1 >> 5;
+        const uint32_t below = ~0u >> (31u - (d1 & 31u));
+        const uint32_t m = lane < dw ? areg : (lane == dw ? areg & below : 0u);
+        const uint64_t bal = __ballot(m != 0u);
         if (bal) {
           const uint32_t l = 63u - (uint32_t)__builtin_clzll(bal);
-          const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)m, (int)l);
-          const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(m >> 32), (int)l);
-          const uint64_t bits = ((uint64_t)hi << 32) | lo;
-          f = l * 64u + 63u - (uint32_t)__builtin_clzll(bits);
+          f = l * 32u + 31u - (uint32_t)__builtin_clz(rdlane(m, l));
         }
       }
       if (f == kNoneL) { status = MPLD_INFEASIBLE; break; }
-      const uint64_t hd = uni64(hdr[f]);
-      v = (uint32_t)hd & 0xffffffu;
-      const uint32_t cp = (uint32_t)(hd >> 24) & 0xfu;
-      rows = (uint32_t)(hd >> 28) & 0xffu;
-      est = (uint32_t)(hd >> 36);
-      beg = uni(adj[v]);
-      deg = uni(adj[v + 1]) - beg;
-      u0 = lane < deg ? ids[beg + lane] : 0u;
-      // uncover every level above f, and the rows level f removed; v stays covered
+      const uint2 hd = hdr[f];
+      const uint32_t offv = uni(hd.x), d1w = uni(hd.y);
+      const uint32_t est = d1w & 0xffffu, rows = (d1w >> 16) & 0xffu, cp = (d1w >> 24) & 0xfu;
+      // uncover every level above f, and the rows level f removed; the
+      // column stays covered (its P bit is entry est)
       for (uint32_t i = est + 1u + lane; i < esp; i += 64) {
         const uint32_t e = ent[i];
-        const uint32_t u = e & ((1u << kEntryNodeBits) - 1u);
-        atomicOr(reinterpret_cast<unsigned long long*>(&PL[(e >> kEntryNodeBits) * W + (u >> 6)]),
-                 1ull << (u & 63u));
+        const uint32_t u = e & kNodeMask;
+        atomicOr(&PL[(u >> 5) * S + (e >> kEntryNodeBits)], 1u << (u & 31u));
       }
-      c = (uint32_t)__builtin_ctz(rows & ~((2u << cp) - 1u));
+      if (TRACE) v = uni(ent[est]) & kNodeMask;
+      const uint32_t c = (uint32_t)__builtin_ctz(rows & ~((2u << cp) - 1u));
       depth = f;
-      esp = est + 1u;
+      take_row(v, c, rows, offv, est, false, (rows >> (c + 1u)) != 0u);
+      row_in = v * (uint32_t)K + c;
     }
-    // ---- include row (v, c) at this depth: record the level, then v's
-    // neighbours lose color c
-    {
-      const bool more = (rows >> (c + 1u)) != 0u;
-      const uint64_t bit = 1ull << (depth & 63u);
-      const uint64_t set = more ? areg | bit : areg & ~bit;
-      areg = lane == (depth >> 6) ? set : areg;
-      if (lane == 63u) hdr[depth] = make_hdr(v, c, rows, est);
-    }
-    {
-      unsigned long long* plane = reinterpret_cast<unsigned long long*>(PL + c * W);
-      uint32_t u = u0;
-      for (uint32_t ch = 0; ch < deg; ch += 64u) {
-        if (ch != 0u) u = ch + lane < deg ? ids[beg + ch + lane] : 0u;
-        bool hit = false;
-        if (ch + lane < deg) {
-          const uint64_t bit = 1ull << (u & 63u);
-          hit = (atomicAnd(&plane[u >> 6], ~bit) & bit) != 0ull;
-        }
-        const uint64_t bal = __ballot(hit);
-        if (hit) {
-          const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
-                                                          __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
-          ent[esp + rank] = (c << kEntryNodeBits) | u;
-        }
-        esp += (uint32_t)__popcll(bal);
-      }
-    }
-    // One wave executes its LDS operations in order, so the next node's
-    // loads see these writes; this only keeps the compiler from caching
-    // LDS values across the loop.
-    asm volatile("" ::: "memory");
     ++depth;
-    row_in = v * (uint32_t)K + c;
   }
   __syncthreads();
   if (status == MPLD_FEASIBLE) {
     for (uint32_t f = lane; f < depth; f += 64) {
-      const uint64_t hd = hdr[f];
-      colors[(uint32_t)hd & 0xffffffu] = (int8_t)((hd >> 24) & 0xfu);
+      const uint32_t d1w = hdr[f].y;
+      colors[ent[d1w & 0xffffu] & kNodeMask] = (int8_t)((d1w >> 24) & 0xfu);
     }
   } else {
     for (uint32_t v = lane; v < n; v += 64) colors[v] = -1;
@@ -715,7 +789,8 @@ __global__ __launch_bounds__(64) void mark_lds_kernel(const DevDesc* __restrict_
 int64_t lds_bytes_for(int32_t n, int32_t k, int64_t adj_words, int32_t max_deg, bool big) {
   // adj_words: row offsets + neighbour ids (n + 1 + 2m)
   (void)max_deg;
-  return (int64_t)lds_layout(n, k, adj_words, big).total;
+  return big ? (int64_t)lds_layout(n, k, adj_words, true).total
+             : (int64_t)lds1_layout(n, k, adj_words).total;
 }
 
 int64_t lds_stack_words(int32_t n, int32_t k, int64_t adj_words) {
