@@ -211,6 +211,7 @@ __device__ void solve_lds(const DevDesc& d, const uint32_t* __restrict__ gadj, c
                           int8_t* __restrict__ colors, DevRecord* __restrict__ rec,
                           int32_t root_row = -1, uint64_t task_budget = 0) {
   constexpr uint32_t S = lds1_stride(K);
+  constexpr uint32_t kLS = S == 4u ? 2u : (S == 8u ? 3u : 4u);   // log2(S)
   constexpr int NB = bits_for(K);
   constexpr uint32_t kNodeMask = (1u << kEntryNodeBits) - 1u;
   const uint32_t lane = __lane_id();
@@ -247,43 +248,49 @@ __device__ void solve_lds(const DevDesc& d, const uint32_t* __restrict__ gadj, c
 
   // Take row (v, c) at `depth`: the level's header and untried-rows bit,
   // then one atomic AND per neighbour of v on plane c (lanes 1 .. deg) and,
-  // if `cover_v`, on v's P bit (lane 0); the removed rows go to the log from
+  // if `lane_lo` is 0, on v's P bit (lane 0); the removed rows go to the log from
   // `est` (v's P bit first), and the plane words of the next node are read
   // right behind the atomics.
+  const uint16_t* ids_m1 = ids - 1;   // lane j reads neighbour j - 1
+  const uint32_t is_l0 = lane == 0u ? ~0u : 0u;
   auto take_row = [&](uint32_t v, uint32_t c, uint32_t rows, uint32_t offv, uint32_t est,
-                      bool cover_v, bool more) {
+                      uint32_t lane_lo, bool more) {
     const uint32_t beg = offv & 0xffffu, deg = offv >> 16;
     const uint32_t first = deg < 63u ? deg : 63u;
-    const bool act = lane == 0u ? cover_v : lane <= first;
-    uint32_t u = v, pl = (uint32_t)K, old = 0u, bitm = 0u;
+    // lane 0: v's P bit (lane_lo 0); lanes 1 .. first: the first neighbours
+    // (lane 0 reads the halfword before the list, a valid LDS word it ignores)
+    const bool act = lane >= lane_lo && lane <= first;
+    uint32_t old = 0u, bitm = 0u, entry = 0u;
     if (act) {
-      if (lane != 0u) {
-        u = ids[beg + lane - 1u];
-        pl = c;
-      }
+      const uint32_t idv = ids_m1[beg + lane];
+      const uint32_t u = (is_l0 & v) | (~is_l0 & idv);
+      const uint32_t pl4 = (is_l0 & ((uint32_t)K * 4u)) | (~is_l0 & (c * 4u));
       bitm = 1u << (u & 31u);
-      old = atomicAnd(&PL[(u >> 5) * S + pl], ~bitm);
+      old = atomicAnd(reinterpret_cast<uint32_t*>(lds + (((u >> 5) << (kLS + 2u)) | pl4)), ~bitm);
+      entry = (pl4 << 24) | u;
     }
     // the next node's plane words, behind the atomics (read again below
-    // when v has more than 63 neighbours)
+    // when v has more than 63 neighbours); the empty asm keeps the use of
+    // the atomic's result after that read is issued
     W.load(PL, lane);
+    asm volatile("" : "+v"(old) : : "memory");
     if (lane == 0u) hdr[depth] = make_uint2(offv, est | (rows << 16) | (c << 24));
     {
       const uint32_t dl = depth >> 5, db = 1u << (depth & 31u);
-      const uint32_t w = rdlane(areg, dl);
-      areg = wrlane(areg, dl, more ? (w | db) : (w & ~db));
+      const uint32_t sel = lane == dl ? db : 0u;
+      areg = (sel & (more ? ~0u : 0u)) | (~sel & areg);
     }
-    uint32_t slot = cover_v ? est : est + 1u;
-    auto log_hits = [&](bool hit, uint32_t uu, uint32_t pp) {
+    uint32_t slot = est + lane_lo;
+    auto log_hits = [&](bool hit, uint32_t e) {
       const uint64_t bal = __builtin_amdgcn_ballot_w64(hit);
       if (hit) {
         const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
                                                         __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
-        ent[slot + rank] = (pp << kEntryNodeBits) | uu;
+        ent[slot + rank] = e;
       }
       slot += (uint32_t)__popcll(bal);
     };
-    log_hits(act && (old & bitm) != 0u, u, pl);
+    log_hits((old & bitm) != 0u, entry);
     if (deg > 63u) {
       for (uint32_t ch = 63u; ch < deg; ch += 64u) {
         bool hit = false;
@@ -293,7 +300,7 @@ __device__ void solve_lds(const DevDesc& d, const uint32_t* __restrict__ gadj, c
           const uint32_t b = 1u << (uu & 31u);
           hit = (atomicAnd(&PL[(uu >> 5) * S + c], ~b) & b) != 0u;
         }
-        log_hits(hit, uu, c);
+        log_hits(hit, (c << kEntryNodeBits) | uu);
       }
       W.load(PL, lane);
     }
@@ -307,7 +314,7 @@ __device__ void solve_lds(const DevDesc& d, const uint32_t* __restrict__ gadj, c
   if (root_row >= 0) {
     // row (0, root_row) at depth 0, with no alternative at that level
     const uint32_t c = (uint32_t)root_row;
-    take_row(0u, c, (1u << K) - 1u, uni(offs[0]), 0u, true, false);
+    take_row(0u, c, (1u << K) - 1u, uni(offs[0]), 0u, 0u, false);
     depth = 1u;
     row_in = c;
   } else {
@@ -358,12 +365,13 @@ __device__ void solve_lds(const DevDesc& d, const uint32_t* __restrict__ gadj, c
     uint32_t v = key & 0xffffffu;
     const uint32_t size = key >> 24;
     if (TRACE) h = trace_node_l(h, depth, row_in, v, size);
+    uint32_t rows, offv, est, lane_lo;
     if (size != 0) {
       const uint32_t wl = v >> 5;
-      const uint32_t rows = rdlane(r, wl);
-      const uint32_t c = (uint32_t)__builtin_ctz(rows);
-      take_row(v, c, rows, rdlane(pre, wl), esp, true, (rows >> (c + 1u)) != 0u);
-      row_in = v * (uint32_t)K + c;
+      rows = rdlane(r, wl);
+      offv = rdlane(pre, wl);
+      est = esp;
+      lane_lo = 0u;
     } else {
       // dead end: back to the deepest level whose column has an untried row
       uint32_t f = kNoneL;
@@ -371,7 +379,7 @@ __device__ void solve_lds(const DevDesc& d, const uint32_t* __restrict__ gadj, c
         const uint32_t d1 = depth - 1u, dw = d1 >> 5;
         const uint32_t below = ~0u >> (31u - (d1 & 31u));
         const uint32_t m = lane < dw ? areg : (lane == dw ? areg & below : 0u);
-        const uint64_t bal = __ballot(m != 0u);
+        const uint64_t bal = __builtin_amdgcn_ballot_w64(m != 0u);
         if (bal) {
           const uint32_t l = 63u - (uint32_t)__builtin_clzll(bal);
           f = l * 32u + 31u - (uint32_t)__builtin_clz(rdlane(m, l));
@@ -379,8 +387,10 @@ __device__ void solve_lds(const DevDesc& d, const uint32_t* __restrict__ gadj, c
       }
       if (f == kNoneL) { status = MPLD_INFEASIBLE; break; }
       const uint2 hd = hdr[f];
-      const uint32_t offv = uni(hd.x), d1w = uni(hd.y);
-      const uint32_t est = d1w & 0xffffu, rows = (d1w >> 16) & 0xffu, cp = (d1w >> 24) & 0xfu;
+      offv = uni(hd.x);
+      const uint32_t d1w = uni(hd.y);
+      est = d1w & 0xffffu;
+      const uint32_t cp = (d1w >> 24) & 0xfu;
       // uncover every level above f, and the rows level f removed; the
       // column stays covered (its P bit is entry est)
       for (uint32_t i = est + 1u + lane; i < esp; i += 64) {
@@ -389,11 +399,14 @@ __device__ void solve_lds(const DevDesc& d, const uint32_t* __restrict__ gadj, c
         atomicOr(&PL[(u >> 5) * S + (e >> kEntryNodeBits)], 1u << (u & 31u));
       }
       if (TRACE) v = uni(ent[est]) & kNodeMask;
-      const uint32_t c = (uint32_t)__builtin_ctz(rows & ~((2u << cp) - 1u));
+      // the level's remaining rows: those after color cp
+      rows = ((d1w >> 16) & 0xffu) & ~((2u << cp) - 1u);
       depth = f;
-      take_row(v, c, rows, offv, est, false, (rows >> (c + 1u)) != 0u);
-      row_in = v * (uint32_t)K + c;
+      lane_lo = 1u;
     }
+    const uint32_t c = (uint32_t)__builtin_ctz(rows);
+    take_row(v, c, rows, offv, est, lane_lo, (rows >> (c + 1u)) != 0u);
+    row_in = v * (uint32_t)K + c;
     ++depth;
   }
   __syncthreads();
