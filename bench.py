@@ -686,6 +686,12 @@ def main() -> int:
     heavy = int(comps["nodes"].max()) if ncomp else 0
     if heavy:
         roofline["ns_per_search_node_per_wave"] = round(kernel_ms * 1e6 / heavy, 2)
+    # the fixed cost of a launch inside the step: empty kernels launched back
+    # to back (one workgroup of 256 lanes per component, and one wave)
+    roofline["launch_floor_us"] = {
+        "grid": max(1, ncomp), "block": 256,
+        "us": round(mp.mpld_measure_launch_floor(ctx, max(1, ncomp), 256, 200), 3),
+        "one_wave_us": round(mp.mpld_measure_launch_floor(ctx, 1, 64, 200), 3)}
 
     out = {
         "metric": METRIC,

@@ -509,6 +509,15 @@ int32_t mpld_server_destroy(mpld_server* s);
  * NULL pointer, another width or iters outside [1, 2^24]. */
 int32_t mpld_measure_lds_read_rate(mpld_context* ctx, int32_t bytes_per_lane, int32_t iters,
                                    double* gbytes_per_s, double* bytes_per_clock_per_cu);
+/* The fixed cost of one kernel launch inside a timed step (not a step of
+ * the paper's method; it puts the search kernels' times in context): `reps`
+ * launches of an empty kernel of `grid` workgroups of `block` lanes, back
+ * to back on the context stream after one warm-up launch, timed with two
+ * HIP events; *us_per_launch = their distance / reps.  Synchronous.
+ * MPLD_E_INVALID for a NULL pointer, grid outside [1, 2^20], block not a
+ * multiple of 64 in [64, 1024], or reps outside [1, 100000]. */
+int32_t mpld_measure_launch_floor(mpld_context* ctx, int32_t grid, int32_t block, int32_t reps,
+                                  double* us_per_launch);
 
 /* ---- results ------------------------------------------------------------ */
 const int8_t* mpld_result_colors(const mpld_result* r, int32_t* num_nodes);

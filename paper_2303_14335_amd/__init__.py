@@ -417,6 +417,15 @@ def mpld_measure_lds_read_rate(ctx: Context, bytes_per_lane: int = 16, iters: in
     return {"GBps": gbps.value, "bytes_per_clock_per_cu": per.value}
 
 
+def mpld_measure_launch_floor(ctx: Context, grid: int, block: int = 256, reps: int = 200) -> float:
+    """Microseconds per launch of an empty kernel of `grid` x `block`
+    lanes, launched back to back on the context stream."""
+    us = ctypes.c_double()
+    _check(_lib.mpld_measure_launch_floor(ctx.handle, grid, block, reps, ctypes.byref(us)),
+           "mpld_measure_launch_floor")
+    return us.value
+
+
 # ---- serving ----------------------------------------------------------------
 
 class Server:

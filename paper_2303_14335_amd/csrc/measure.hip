@@ -1,8 +1,10 @@
-// measure.hip - LDS read-rate measurement used for the roofline of the
-// LDS-tier kernels: every CU runs workgroups that read their LDS with
-// ds_read_b64 or ds_read_b128 (each wave reads contiguous bytes, so no bank
-// conflicts), and the bytes read over the kernel's time give the chip's
-// achievable LDS read rate.
+// measure.hip - measurements that put the search kernels' times in
+// context: the LDS read rate used for the roofline of the LDS-tier kernels
+// (every CU runs workgroups that read their LDS with ds_read_b64 or
+// ds_read_b128; each wave reads contiguous bytes, so no bank conflicts; the
+// bytes read over the kernel's time give the chip's achievable LDS read
+// rate), and the time per launch of an empty kernel launched back to back
+// (the fixed cost inside a step of one search launch).
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -49,6 +51,9 @@ __global__ __launch_bounds__(kLdsProbeThreads) void lds_read_kernel(uint32_t ite
   }
   if (acc == 0x9e3779b9u) sink[blockIdx.x] = acc;   // never true for these contents in practice
 }
+
+// Does nothing: its back-to-back launches time dispatch and completion.
+__global__ void empty_kernel() {}
 
 }  // namespace mpld
 
@@ -103,6 +108,45 @@ extern "C" int32_t mpld_measure_lds_read_rate(mpld_context* ctx, int32_t bytes_p
     return e.code;
   } catch (...) {
     set_last_error("unexpected exception in the LDS read-rate measurement");
+    return MPLD_E_INTERNAL;
+  }
+}
+
+extern "C" int32_t mpld_measure_launch_floor(mpld_context* ctx, int32_t grid, int32_t block,
+                                             int32_t reps, double* us_per_launch) {
+  try {
+    if (!ctx || !us_per_launch) fail(MPLD_E_INVALID, "NULL argument");
+    if (grid < 1 || grid > (1 << 20)) fail(MPLD_E_INVALID, "grid must be in [1, 2^20]");
+    if (block < 64 || block > 1024 || block % 64 != 0)
+      fail(MPLD_E_INVALID, "block must be a multiple of 64 in [64, 1024]");
+    if (reps < 1 || reps > 100000) fail(MPLD_E_INVALID, "reps must be in [1, 100000]");
+    check_hip(hipSetDevice(ctx->device), "hipSetDevice");
+    hipStream_t s = ctx->stream;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    check_hip(hipEventCreate(&e0), "event");
+    check_hip(hipEventCreate(&e1), "event");
+    float ms = 0.f;
+    hipLaunchKernelGGL(empty_kernel, dim3(grid), dim3(block), 0, s);   // warm-up
+    hipError_t err = hipGetLastError();
+    if (err == hipSuccess) err = hipEventRecord(e0, s);
+    for (int32_t r = 0; r < reps && err == hipSuccess; ++r) {
+      hipLaunchKernelGGL(empty_kernel, dim3(grid), dim3(block), 0, s);
+      err = hipGetLastError();
+    }
+    if (err == hipSuccess) err = hipEventRecord(e1, s);
+    if (err == hipSuccess) err = hipEventSynchronize(e1);
+    if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    check_hip(err, "empty-kernel launches");
+    *us_per_launch = (double)ms * 1e3 / reps;
+    set_last_error("");
+    return MPLD_OK;
+  } catch (const Error& e) {
+    set_last_error(e.what);
+    return e.code;
+  } catch (...) {
+    set_last_error("unexpected exception in the launch-floor measurement");
     return MPLD_E_INTERNAL;
   }
 }
