@@ -33,9 +33,14 @@
  *   - a search node is one entry into the search that passes the budget
  *     test (budget tested before counting), so nodes <= budget always and
  *     BUDGET_EXHAUSTED implies nodes == budget;
- *   - trace hash: FNV-1a 64 over 16 bytes per search node - depth, entering
- *     row (v*k + c; 0xFFFFFFFF at the root), chosen column (0xFFFFFFFF at a
- *     solution), its row count - each u32 little-endian.
+ *   - trace hash (a fingerprint of the search order; the method defines
+ *     none): each search node contributes x = FNV-1a 64 of its 16 bytes -
+ *     depth, entering row (v*k + c; 0xFFFFFFFF at the root), chosen column
+ *     (0xFFFFFFFF at a solution), its row count; u32 little-endian each -
+ *     from the offset basis, and N nodes in search order give
+ *     sum x_i * B^(N-i) mod 2^64, B = 0x100000001B3 (h = h*B + x per node
+ *     from 0).  A trace followed by another of n nodes has h1 * B^n + h2,
+ *     so subtrees searched apart combine exactly.
  *
  * Conventions:
  *   - Return codes are int32: 0 = ok, negative = error (enum below).  No
@@ -213,7 +218,7 @@ typedef struct {
   int32_t size;           /* nodes                                          */
   int32_t status;         /* MPLD_FEASIBLE / MPLD_INFEASIBLE / MPLD_BUDGET_EXHAUSTED */
   int64_t nodes;          /* search nodes                                   */
-  uint64_t trace_hash;    /* FNV-1a trace hash (0 unless MPLD_TRACE_HASH)   */
+  uint64_t trace_hash;    /* trace hash above (0 unless MPLD_TRACE_HASH)    */
   int32_t depth_at_stop;  /* rows in the partial solution when it stopped (0 if infeasible) */
   int32_t stitches;       /* stitch pairs inside colored differently; -1 unless colored
                              (feasible, or marked with MPLD_MARK_CONFLICTS) */

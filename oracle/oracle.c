@@ -251,10 +251,15 @@ static void dlx_uncover(orc_dlx* x, int32_t c) {
   x->R[x->L[c]] = c;
 }
 
-/* Trace hash: FNV-1a 64 (Fowler/Noll/Vo) over the 16 bytes of each counted
- * search node: depth, entering row, chosen column, its size; each u32
- * little-endian (entering row 0xFFFFFFFF at the root, column 0xFFFFFFFF at a
- * solution). */
+/* Trace fingerprint (our check of the search order; the method defines no
+ * such value).  Each counted search node contributes x = FNV-1a 64
+ * (Fowler/Noll/Vo) of its 16 bytes - depth, entering row, chosen column,
+ * its size; each u32 little-endian (entering row 0xFFFFFFFF at the root,
+ * column 0xFFFFFFFF at a solution) - started from the offset basis; the
+ * fingerprint of N nodes in search order is the sum of x_i * B^(N-i) modulo
+ * 2^64 with B the FNV prime, i.e. h = h * B + x per node from h = 0.  The
+ * fingerprint of a trace S followed by a trace T is then h(S) * B^|T| +
+ * h(T), so subtrees searched apart can be combined in search order. */
 static uint64_t fnv_u32(uint64_t h, uint32_t v) {
   for (int b = 0; b < 4; ++b) {
     h ^= (v >> (8 * b)) & 0xffu;
@@ -265,12 +270,12 @@ static uint64_t fnv_u32(uint64_t h, uint32_t v) {
 
 static void trace_node(orc_dlx* x, uint32_t depth, uint32_t row_in, uint32_t col,
                        uint32_t size) {
-  uint64_t h = x->hash;
+  uint64_t h = 0xcbf29ce484222325ULL;
   h = fnv_u32(h, depth);
   h = fnv_u32(h, row_in);
   h = fnv_u32(h, col);
   h = fnv_u32(h, size);
-  x->hash = h;
+  x->hash = x->hash * 0x100000001b3ULL + h;
 }
 
 /* Algorithm X (Algorithm 1): stop when every primary column is covered (the
@@ -426,7 +431,7 @@ int32_t orc_solve_component_stitch(int32_t n, int64_t m, const int32_t* edges,
   }
   x.budget = budget;
   x.nodes = 0;
-  x.hash = 0xcbf29ce484222325ULL;
+  x.hash = 0;
   x.status = -1;
   x.depth_at_stop = 0;
   dlx_search(&x, 0, -1);

@@ -37,7 +37,7 @@ typedef struct {
   int32_t size;          /* nodes in the component                     */
   int32_t status;        /* ORC_FEASIBLE / ORC_INFEASIBLE / ORC_BUDGET */
   int64_t nodes;         /* search nodes counted                       */
-  uint64_t trace_hash;   /* FNV-1a 64 over the node trace              */
+  uint64_t trace_hash;   /* fingerprint of the node trace (oracle.c)   */
   int32_t depth_at_stop; /* rows in the partial solution at the stop   */
   int32_t stitches;      /* SE pairs inside, colored differently; -1 unless colored */
   int32_t first_node;    /* smallest original node id                  */

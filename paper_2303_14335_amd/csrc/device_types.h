@@ -52,7 +52,7 @@ struct DevRecord {
   int32_t status;   // MPLD_FEASIBLE / MPLD_INFEASIBLE / MPLD_BUDGET_EXHAUSTED
   int32_t depth;    // rows in the partial solution at the stop (0 if infeasible)
   uint64_t nodes;   // search nodes
-  uint64_t hash;    // FNV-1a trace hash (offset basis when tracing is off)
+  uint64_t hash;    // trace fingerprint (trace.h; 0 when tracing is off)
 };
 static_assert(sizeof(DevRecord) == 24, "record is 24 bytes");
 

@@ -406,7 +406,7 @@ bool resolve(HComp& hc, const DevDesc& d, const std::vector<HTask>& tasks) {
       hc.rec.status = MPLD_FEASIBLE;
       hc.rec.depth = d.n;
       hc.rec.nodes = acc;
-      hc.rec.hash = 0xcbf29ce484222325ull;
+      hc.rec.hash = 0;
       hc.colors.assign(t.sol, t.sol + d.n);
       return true;
     }
@@ -414,7 +414,7 @@ bool resolve(HComp& hc, const DevDesc& d, const std::vector<HTask>& tasks) {
   hc.rec.status = MPLD_INFEASIBLE;
   hc.rec.depth = 0;
   hc.rec.nodes = acc;
-  hc.rec.hash = 0xcbf29ce484222325ull;
+  hc.rec.hash = 0;
   hc.colors.assign((size_t)d.n, -1);
   return true;
 }
@@ -583,7 +583,7 @@ static void heavy_engine_device(DeviceBatch& db) {
     e.rec.status = found ? MPLD_FEASIBLE : MPLD_INFEASIBLE;
     e.rec.depth = found ? d.n : 0;
     e.rec.nodes = acc;
-    e.rec.hash = 0xcbf29ce484222325ull;
+    e.rec.hash = 0;
     if (found) std::memcpy(e.colors, sol, (size_t)d.n);
     else std::memset(e.colors, -1, (size_t)d.n);
     wb.push_back(e);
@@ -645,7 +645,7 @@ static void csr_split(DeviceBatch& db) {
     cp.res.out_off = d.out_off;
     cp.res.n = d.n;
     cp.res.src_off = -1;
-    cp.res.rec.hash = 0xcbf29ce484222325ull;
+    cp.res.rec.hash = 0;
     if (d.budget == 1) {   // the root takes the whole budget
       cp.res.rec.status = MPLD_BUDGET_EXHAUSTED;
       cp.res.rec.nodes = 1;

@@ -21,33 +21,15 @@
 
 #include "device_types.h"
 #include "mpld.h"
+#include "trace.h"
 
 namespace cg = cooperative_groups;
 
 namespace mpld {
 
-static constexpr uint64_t kFnvOffsetD = 0xcbf29ce484222325ull;
-static constexpr uint64_t kFnvPrimeD = 0x100000001b3ull;
 static constexpr uint32_t kNoneD = 0xffffffffu;
 static constexpr uint16_t kCovered = 0x8000u;
 static constexpr int kDevThreads = 256;
-
-__device__ __forceinline__ uint64_t fnv_u32_d(uint64_t h, uint32_t v) {
-#pragma unroll
-  for (int b = 0; b < 4; ++b) {
-    h ^= (v >> (8 * b)) & 0xffu;
-    h *= kFnvPrimeD;
-  }
-  return h;
-}
-
-__device__ __forceinline__ uint64_t trace_node_d(uint64_t h, uint32_t depth, uint32_t row_in,
-                                                 uint32_t col, uint32_t size) {
-  h = fnv_u32_d(h, depth);
-  h = fnv_u32_d(h, row_in);
-  h = fnv_u32_d(h, col);
-  return fnv_u32_d(h, size);
-}
 
 __device__ __forceinline__ uint64_t min64(uint64_t a, uint64_t b) { return a < b ? a : b; }
 
@@ -94,7 +76,7 @@ __global__ __launch_bounds__(kDevThreads) void device_tier_kernel(
   for (uint32_t v = lo + tid; v < hi; v += kDevThreads) rm[v - lo] = full;
   __syncthreads();
 
-  uint64_t nodes = 0, h = kFnvOffsetD;
+  uint64_t nodes = 0, h = 0;
   uint32_t depth = 0, open = (uint32_t)n, row_in = kNoneD;
   int32_t status = -1;
   const uint64_t budget = (uint64_t)d.budget;
@@ -140,7 +122,7 @@ __global__ __launch_bounds__(kDevThreads) void device_tier_kernel(
     if (nodes == budget) { status = MPLD_BUDGET_EXHAUSTED; break; }
     ++nodes;
     if (open == 0) {
-      if (TRACE) h = trace_node_d(h, depth, row_in, kNoneD, 0);
+      if (TRACE) h = trace_node(h, depth, row_in, kNoneD, 0);
       status = MPLD_FEASIBLE;
       break;
     }
@@ -163,7 +145,7 @@ __global__ __launch_bounds__(kDevThreads) void device_tier_kernel(
     uint32_t v = (uint32_t)(win >> 8);
     const uint32_t size = (uint32_t)(win >> 40);
     uint32_t rows = (uint32_t)win & 0xffu;
-    if (TRACE) h = trace_node_d(h, depth, row_in, v, size);
+    if (TRACE) h = trace_node(h, depth, row_in, v, size);
     // 3. the same decision, replayed on this block's slice
     uint32_t c;
     if (size != 0) {

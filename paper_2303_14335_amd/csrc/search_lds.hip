@@ -32,32 +32,14 @@
 
 #include "device_types.h"
 #include "mpld.h"
+#include "trace.h"
 #include "wave_ops.h"
 
 namespace mpld {
 
-static constexpr uint64_t kFnvOffsetL = 0xcbf29ce484222325ull;
-static constexpr uint64_t kFnvPrimeL = 0x100000001b3ull;
 static constexpr uint32_t kNoneL = 0xffffffffu;
 static constexpr uint32_t kNoKey = 0xffffffffu;
 static constexpr uint32_t kEntryNodeBits = 26;   // undo entry: plane << 26 | node
-
-__device__ __forceinline__ uint64_t fnv_u32_l(uint64_t h, uint32_t v) {
-#pragma unroll
-  for (int b = 0; b < 4; ++b) {
-    h ^= (v >> (8 * b)) & 0xffu;
-    h *= kFnvPrimeL;
-  }
-  return h;
-}
-
-__device__ __forceinline__ uint64_t trace_node_l(uint64_t h, uint32_t depth, uint32_t row_in,
-                                                 uint32_t col, uint32_t size) {
-  h = fnv_u32_l(h, depth);
-  h = fnv_u32_l(h, row_in);
-  h = fnv_u32_l(h, col);
-  return fnv_u32_l(h, size);
-}
 
 __device__ __forceinline__ uint32_t uni(uint32_t x) {
   return (uint32_t)__builtin_amdgcn_readfirstlane((int)x);
@@ -239,7 +221,7 @@ __device__ void solve_lds(const DevDesc& d, const uint32_t* __restrict__ gadj, c
   __syncthreads();
 
   uint32_t depth = 0, row_in = kNoneL, esp = 0;
-  uint64_t nodes = 0, h = kFnvOffsetL;
+  uint64_t nodes = 0, h = 0;
   int32_t status = -1;
   uint32_t areg = 0;   // untried-rows bit of depth 32 * lane + b
   const uint64_t budget = root_row >= 0 ? task_budget : (uint64_t)d.budget;
@@ -358,13 +340,13 @@ __device__ void solve_lds(const DevDesc& d, const uint32_t* __restrict__ gadj, c
     asm volatile("" ::: "memory");
     const uint32_t key = wave_min(p ? ((t << 24) | vl) : kNoKey);
     if (key == kNoKey) {   // no uncovered column: the levels hold a solution
-      if (TRACE) h = trace_node_l(h, depth, row_in, kNoneL, 0);
+      if (TRACE) h = trace_node(h, depth, row_in, kNoneL, 0);
       status = MPLD_FEASIBLE;
       break;
     }
     uint32_t v = key & 0xffffffu;
     const uint32_t size = key >> 24;
-    if (TRACE) h = trace_node_l(h, depth, row_in, v, size);
+    if (TRACE) h = trace_node(h, depth, row_in, v, size);
     uint32_t rows, offv, est, lane_lo;
     if (size != 0) {
       const uint32_t wl = v >> 5;
@@ -466,7 +448,7 @@ __device__ void solve_lds_wg(const DevDesc& d, const uint32_t* __restrict__ adj,
 
   // search state, kept by wave 0
   uint32_t depth = 0, row_in = kNoneL, esp = 0;
-  uint64_t nodes = 1, h = kFnvOffsetL;
+  uint64_t nodes = 1, h = 0;
   int32_t status = -1;
   const uint64_t budget = root_row >= 0 ? task_budget : (uint64_t)d.budget;
   if (root_row >= 0) {
@@ -515,12 +497,12 @@ __device__ void solve_lds_wg(const DevDesc& d, const uint32_t* __restrict__ adj,
     }
     if (wid == 0u) {
       if (key == kNoKey) {   // no uncovered column: the levels hold a solution
-        if (TRACE) h = trace_node_l(h, depth, row_in, kNoneL, 0);
+        if (TRACE) h = trace_node(h, depth, row_in, kNoneL, 0);
         status = MPLD_FEASIBLE;
       } else {
         uint32_t v = key & 0xffffffu;
         const uint32_t size = key >> 24;
-        if (TRACE) h = trace_node_l(h, depth, row_in, v, size);
+        if (TRACE) h = trace_node(h, depth, row_in, v, size);
         uint32_t c = 0, rows = 0, est = 0, beg = 0, deg = 0;
         if (size != 0) {
           const uint32_t b0 = adj[v], b1 = adj[v + 1];

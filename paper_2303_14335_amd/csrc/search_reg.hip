@@ -34,30 +34,12 @@
 #include "device_types.h"
 #include "mpld.h"
 #include "reg_items.h"
+#include "trace.h"
 #include "wave_ops.h"
 
 namespace mpld {
 
-static constexpr uint64_t kFnvOffset = 0xcbf29ce484222325ull;
-static constexpr uint64_t kFnvPrime = 0x100000001b3ull;
 static constexpr uint32_t kNone = 0xffffffffu;
-
-__device__ __forceinline__ uint64_t fnv_u32(uint64_t h, uint32_t v) {
-#pragma unroll
-  for (int b = 0; b < 4; ++b) {
-    h ^= (v >> (8 * b)) & 0xffu;
-    h *= kFnvPrime;
-  }
-  return h;
-}
-
-__device__ __forceinline__ uint64_t trace_node(uint64_t h, uint32_t depth, uint32_t row_in,
-                                               uint32_t col, uint32_t size) {
-  h = fnv_u32(h, depth);
-  h = fnv_u32(h, row_in);
-  h = fnv_u32(h, col);
-  return fnv_u32(h, size);
-}
 
 constexpr int bit_width(int x) { return x == 0 ? 0 : 1 + bit_width(x >> 1); }
 
@@ -96,7 +78,7 @@ __device__ __forceinline__ void reg_init(RegState<K>& s, int32_t n, int32_t k) {
   s.P = all;
   s.A = 0;
   s.nodes = 0;
-  s.h = kFnvOffset;
+  s.h = 0;
   s.depth = 0;
   s.row_in = kNone;
   s.status = -1;

@@ -36,6 +36,17 @@ def fnv1a_words(h: int, words) -> int:
     return h
 
 
+def trace_step(h: int, words) -> int:
+    """One counted node in the trace fingerprint: h * B + FNV-1a of the
+    node's four u32 words (B the FNV prime; a trace starts at h = 0)."""
+    return (h * _FNV_PRIME + fnv1a_words(_FNV_OFFSET, words)) & _M64
+
+
+def trace_concat(h_first: int, h_second: int, n_second: int) -> int:
+    """Fingerprint of a trace followed by another of n_second nodes."""
+    return (h_first * pow(_FNV_PRIME, n_second, 1 << 64) + h_second) & _M64
+
+
 def algx_sets(n: int, edges, k: int, budget: int, partner=None):
     """partner (n ints, -1 none): stitch-aware row order - a column whose
     node's partner is colored on the current path tries the row of that
@@ -53,7 +64,7 @@ def algx_sets(n: int, edges, k: int, budget: int, partner=None):
     for v in range(n):
         cols.setdefault(("p", v), set())
 
-    st = {"nodes": 0, "hash": _FNV_OFFSET, "status": None, "depth": 0}
+    st = {"nodes": 0, "hash": 0, "status": None, "depth": 0}
     solution = []
 
     def choose_row(r):
@@ -83,13 +94,13 @@ def algx_sets(n: int, edges, k: int, budget: int, partner=None):
         st["nodes"] += 1
         open_prim = [v for v in range(n) if ("p", v) in cols]
         if not open_prim:
-            st["hash"] = fnv1a_words(st["hash"], [depth, row_in, NONE32, 0])
+            st["hash"] = trace_step(st["hash"], [depth, row_in, NONE32, 0])
             st["status"] = FEASIBLE
             st["depth"] = depth
             return
         best = min(open_prim, key=lambda v: (len(cols[("p", v)]), v))
         size = len(cols[("p", best)])
-        st["hash"] = fnv1a_words(st["hash"], [depth, row_in, best, size])
+        st["hash"] = trace_step(st["hash"], [depth, row_in, best, size])
         if size == 0:
             return
         order = sorted(cols[("p", best)])
