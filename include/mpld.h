@@ -109,21 +109,24 @@ enum {
   MPLD_SPLIT_HEAVY = 1u << 8,  /* register-tier components still searching after
                                   a first capped pass are searched in parallel
                                   subtrees by many wavefronts; the sequential
-                                  status, node count, depth and colors are
-                                  recomputed exactly from the subtrees' counts
-                                  in search order (not with MPLD_TRACE_HASH; a
+                                  status, node count, depth, colors and trace
+                                  hash are recomputed exactly from the
+                                  subtrees' counts and hashes in search order
+                                  (each subtree's hash appended with the
+                                  concatenation rule of the trace hash; a
                                   component cut by its budget is re-run
                                   sequentially).  LDS-tier and big-tier
                                   components are searched as k subtree tasks,
                                   one per root row (the root column is node
                                   0), each on its own wave or workgroup; their
-                                  counts are added in row order, and a budget
-                                  crossed inside a later row's subtree is
-                                  found by searching that subtree again with
-                                  the budget left.  Makes mpld_batch_solve wait.
-                                  mpld_decompose and mpld_solve_components,
-                                  which wait anyway, use it for every untraced
-                                  solve whether or not the flag is given. */
+                                  counts and hashes are added in row order,
+                                  and a budget crossed inside a later row's
+                                  subtree is found by searching that subtree
+                                  again with the budget left.  Makes
+                                  mpld_batch_solve wait.  mpld_decompose and
+                                  mpld_solve_components, which wait anyway,
+                                  use it for every solve whether or not the
+                                  flag is given. */
   MPLD_UNTIMED = 1u << 9,      /* mpld_batch_solve: record no HIP events around
                                   the search (last_search_ms keeps the value of
                                   the last timed solve); for callers timing

@@ -333,7 +333,7 @@ int32_t mpld_decompose(mpld_context* ctx, const mpld_graph* g, const mpld_option
     mpld_batch b;
     batch_build(ctx, g, opt, &b);
     // one-shot: no graph to capture; it waits anyway, so heavy components
-    // always go to the subtree engine (untraced solves)
+    // always go to the subtree engine
     device_solve(b.db, opt->flags | MPLD_DIRECT | MPLD_SPLIT_HEAVY);
     b.solved = true;
     auto* r = new mpld_result();

@@ -94,8 +94,9 @@ struct SplitResult {
   uint64_t nodes;      // nodes explored (the subtree's own count when finished)
   uint32_t item_off;   // first of the task's items in the round's item pool
   uint32_t pad;
+  uint64_t hash;       // traced engine, finished task: trace hash of its own nodes
 };
-static_assert(sizeof(SplitResult) == 24, "result is 24 bytes");
+static_assert(sizeof(SplitResult) == 32, "result is 32 bytes");
 // One item of the split of a capped task, in depth-first order: `seg` nodes
 // of the task's top levels are visited, then (kind 0) the subtree of the
 // node reached by rows[0..levels-1] below the task root, or (kind 1) the
@@ -112,8 +113,8 @@ constexpr int kSplitMaxLevels = 4;
 // local node, when the task found one).  A capped task's split items go to
 // a pool shared by the round, at an offset taken with one atomic, so only
 // the items that exist are read back.
-constexpr uint32_t kSplitSolOffset = 24;
-constexpr uint32_t kSplitBlockBytes = 88;
+constexpr uint32_t kSplitSolOffset = 32;
+constexpr uint32_t kSplitBlockBytes = 96;
 // Device-resident heavy-component engine.  Tasks of every round live in one
 // array: round r runs the tasks [begin, end) and appends the subtasks of
 // its capped tasks at `alloc`; a one-thread kernel between rounds moves the
@@ -143,8 +144,9 @@ struct EngineItem {
   uint32_t kind;        // 0 subtask, 1 end, 2 solution
   int32_t child;        // kind 0: task index of the subtask
   uint32_t pad;
+  uint64_t hash;        // traced engine: trace hash of the seg nodes
 };
-static_assert(sizeof(EngineItem) == 16, "engine item is 16 bytes");
+static_assert(sizeof(EngineItem) == 24, "engine item is 24 bytes");
 constexpr int32_t kEngineSkipped = -3;   // task status: not run (skip slot) or not split (budget or space)
 
 // A resolved heavy component written back by the device: its record and

@@ -1,6 +1,7 @@
 // runtime.cpp - device context, exact-cover image packing, upload, tiered
 // launches and result download (host side of the decomposer library).
 #include "runtime.h"
+#include "trace.h"
 
 #include <hip/hip_runtime.h>
 
@@ -315,7 +316,7 @@ static void enqueue_batched(DeviceBatch& db, bool trace, uint64_t cap, hipStream
   auto* gstack = db.gstack.as<uint64_t>();
   db.launches = 0;
   if (db.n_reg) {
-    const int32_t heavy = (!trace && cap == ~0ull) ? db.reg_heavy : 0;
+    const int32_t heavy = cap == ~0ull ? db.reg_heavy : 0;
     const int grid = heavy ? heavy + (db.n_reg - heavy + 3) / 4 : db.grid_reg;
     check_hip(launch_reg_batched(trace, db.k, grid, db.tune.waves_per_block, items, db.n_reg, cnt,
                                  recs, colors, cap, heavy, (uint32_t)db.tune.root_split_chunk, s),
@@ -429,7 +430,7 @@ constexpr int32_t kEnginePoolCap = 1 << 21;   // split items (16 B each)
 constexpr int32_t kEngineMaxRounds = 96;      // depth <= 64: far more than needed
 constexpr int32_t kEngineRoundsPerCheck = 3;  // rounds enqueued between looks at the head
 
-static void heavy_engine_device(DeviceBatch& db) {
+static void heavy_engine_device(DeviceBatch& db, bool trace) {
   mpld_context* ctx = db.ctx;
   hipStream_t s = ctx->stream;
   db.sp_rounds = db.sp_tasks_run = db.sp_heavy = db.sp_reruns = 0;
@@ -499,7 +500,7 @@ static void heavy_engine_device(DeviceBatch& db) {
       check_hip(launch_engine_advance(head, kEngineTaskCap, s), "heavy: advance");
       check_hip(launch_engine_round(db.k, grid, head, tasks, kEngineTaskCap, blocks, pool, kEnginePoolCap,
                                     db.reg_items(), hc_nodes, hc_limit,
-                                    (uint64_t)db.tune.heavy_round_cap, (uint32_t)levels, s),
+                                    (uint64_t)db.tune.heavy_round_cap, (uint32_t)levels, trace, s),
                 "heavy: round");
     }
     check_hip(hipMemcpyAsync(db.sp_host_out.p, head, sizeof(EngineHead), hipMemcpyDeviceToHost, s),
@@ -536,7 +537,8 @@ static void heavy_engine_device(DeviceBatch& db) {
     return r;
   };
   auto solution = [&](int32_t t) { return reinterpret_cast<const int8_t*>(hb + (size_t)kSplitBlockBytes * t + kSplitSolOffset); };
-  // each component in search order: a depth-first walk of its task tree
+  // each component in search order: a depth-first walk of its task tree;
+  // the trace hash appends each finished task's and each item's seg hash
   std::vector<HeavyWrite> wb;
   std::vector<int32_t> rerun;
   struct Walk { int32_t task, next; };
@@ -544,7 +546,7 @@ static void heavy_engine_device(DeviceBatch& db) {
   for (int32_t h = 0; h < H; ++h) {
     const DevDesc& d = db.host_desc[heavy[h]];
     const uint64_t budget = (uint64_t)d.budget;
-    uint64_t acc = 0;
+    uint64_t acc = 0, hash = 0;
     bool redo = false, found = false;
     const int8_t* sol = nullptr;
     stack.clear();
@@ -555,6 +557,7 @@ static void heavy_engine_device(DeviceBatch& db) {
       if (w.next < 0) {   // first visit
         if (r.status == MPLD_INFEASIBLE || r.status == MPLD_FEASIBLE) {
           acc += r.nodes;
+          hash = trace_concat(hash, r.hash, r.nodes);
           if (acc > budget) { redo = true; break; }
           if (r.status == MPLD_FEASIBLE) { found = true; sol = solution(w.task); break; }
           stack.pop_back();
@@ -568,6 +571,7 @@ static void heavy_engine_device(DeviceBatch& db) {
       if (w.next >= r.nitems) { stack.pop_back(); continue; }
       const EngineItem it = hi[r.item_off + (uint32_t)w.next++];
       acc += it.seg;
+      hash = trace_concat(hash, it.hash, it.seg);
       if (acc > budget) { redo = true; break; }
       if (it.kind == 1) { stack.pop_back(); continue; }
       if (it.kind == 2) { found = true; sol = solution(w.task); break; }
@@ -583,14 +587,14 @@ static void heavy_engine_device(DeviceBatch& db) {
     e.rec.status = found ? MPLD_FEASIBLE : MPLD_INFEASIBLE;
     e.rec.depth = found ? d.n : 0;
     e.rec.nodes = acc;
-    e.rec.hash = 0;
+    e.rec.hash = trace ? hash : 0;
     if (found) std::memcpy(e.colors, sol, (size_t)d.n);
     else std::memset(e.colors, -1, (size_t)d.n);
     wb.push_back(e);
   }
   for (int32_t item : rerun) {
     ++db.sp_reruns;
-    check_hip(launch_reg_single(false, db.k, db.reg_items(), item, db.recs.as<DevRecord>(),
+    check_hip(launch_reg_single(trace, db.k, db.reg_items(), item, db.recs.as<DevRecord>(),
                                 db.colors.as<int8_t>(), s), "heavy: sequential re-run");
   }
   if (!wb.empty()) {
@@ -608,7 +612,7 @@ static void heavy_engine_device(DeviceBatch& db) {
   check_hip(hipStreamSynchronize(s), "heavy: write back");
 }
 
-// LDS-tier and big-tier components as subtree tasks (untraced).  At the
+// LDS-tier and big-tier components as subtree tasks.  At the
 // root every column has all k rows, so the root column is node 0 and the
 // root node's children are its k rows; task (component, c) searches the
 // subtree of root row c with budget B - 1 (the root node is counted once,
@@ -620,8 +624,10 @@ static void heavy_engine_device(DeviceBatch& db) {
 // subtree whose count would cross the budget (or that ran into it) is where
 // the sequential search stops: it is searched again with budget B - acc for
 // the depth at the stop (row 0's task already ran with exactly that
-// budget).  Every row exhausted: INFEASIBLE with acc nodes.
-static void csr_split(DeviceBatch& db) {
+// budget).  Every row exhausted: INFEASIBLE with acc nodes.  The trace hash
+// follows the same order: the root node's, then each counted subtree's
+// appended (trace S then T: h(S) B^|T| + h(T)).
+static void csr_split(DeviceBatch& db, bool trace) {
   const int32_t first = db.n_reg, count = db.n_lds + db.n_big;
   if (count == 0) return;
   mpld_context* ctx = db.ctx;
@@ -629,6 +635,7 @@ static void csr_split(DeviceBatch& db) {
   struct Comp {
     int32_t pos = 0;      // launch position
     uint64_t acc = 1;
+    uint64_t hash = 0;    // trace hash of the nodes counted in acc
     int32_t rerun_row = -1;
     bool done = false;
     LdsResolved res{};
@@ -645,7 +652,17 @@ static void csr_split(DeviceBatch& db) {
     cp.res.out_off = d.out_off;
     cp.res.n = d.n;
     cp.res.src_off = -1;
-    cp.res.rec.hash = 0;
+    if (d.n == 0) {   // no column: the root is a solution
+      cp.res.rec.status = MPLD_FEASIBLE;
+      cp.res.rec.nodes = 1;
+      cp.res.rec.depth = 0;
+      cp.res.rec.hash = trace ? trace_node(0, 0u, 0xffffffffu, 0xffffffffu, 0u) : 0;
+      cp.done = true;
+      continue;
+    }
+    // the root node: column 0 (every column has all k rows), entering row none
+    cp.hash = trace_node(0, 0u, 0xffffffffu, 0u, (uint32_t)d.k);
+    cp.res.rec.hash = trace ? cp.hash : 0;
     if (d.budget == 1) {   // the root takes the whole budget
       cp.res.rec.status = MPLD_BUDGET_EXHAUSTED;
       cp.res.rec.nodes = 1;
@@ -678,13 +695,13 @@ static void csr_split(DeviceBatch& db) {
     const auto* dt = db.ct_tasks.as<LdsTask>();
     auto* drec = db.ct_recs.as<DevRecord>();
     if (nsmall)
-      check_hip(launch_lds_tasks(false, 1,
+      check_hip(launch_lds_tasks(trace, false, 1,
                                  std::max(1, std::min((int)nsmall, blocks_for_lds(ctx, db.lds_small))),
                                  db.lds_small, db.desc.as<DevDesc>(), db.adj32.as<uint32_t>(), dt,
                                  (int32_t)nsmall, nullptr, 0, drec, db.ct_colors.as<int8_t>(), s),
                 "subtree tasks (LDS tier)");
     if (nsmall < list.size())
-      check_hip(launch_lds_tasks(true, db.big_waves,
+      check_hip(launch_lds_tasks(trace, true, db.big_waves,
                                  std::max(1, std::min((int)(list.size() - nsmall), db.grid_big_tasks)),
                                  db.lds_big, db.desc.as<DevDesc>(), db.adj32.as<uint32_t>(),
                                  dt + nsmall, (int32_t)(list.size() - nsmall), db.gstack.as<uint64_t>(),
@@ -711,6 +728,7 @@ static void csr_split(DeviceBatch& db) {
         cp.res.rec.status = MPLD_BUDGET_EXHAUSTED;
         cp.res.rec.nodes = B;
         cp.res.rec.depth = 1;
+        cp.res.rec.hash = trace ? cp.hash : 0;
         cp.done = true;
         break;
       }
@@ -718,6 +736,7 @@ static void csr_split(DeviceBatch& db) {
       const bool fits = cp.acc + r.nodes <= B;
       if (r.status == MPLD_INFEASIBLE && fits) {
         cp.acc += r.nodes;
+        cp.hash = trace_concat(cp.hash, r.hash, r.nodes);
         continue;
       }
       if ((r.status == MPLD_FEASIBLE && fits) || c == 0) {
@@ -725,6 +744,7 @@ static void csr_split(DeviceBatch& db) {
         // the budget left (B - 1): the task's result is the search's
         cp.res.rec.status = r.status;
         cp.res.rec.nodes = cp.acc + r.nodes;
+        cp.res.rec.hash = trace ? trace_concat(cp.hash, r.hash, r.nodes) : 0;
         cp.res.rec.depth = r.status == MPLD_INFEASIBLE ? 0 : r.depth;
         if (r.status == MPLD_FEASIBLE) cp.res.src_off = tasks[(size_t)(t0 + c)].col_off;
         cp.done = true;
@@ -739,6 +759,7 @@ static void csr_split(DeviceBatch& db) {
     if (!cp.done && cp.rerun_row < 0) {   // every row exhausted
       cp.res.rec.status = MPLD_INFEASIBLE;
       cp.res.rec.nodes = cp.acc;
+      cp.res.rec.hash = trace ? cp.hash : 0;
       cp.res.rec.depth = 0;
       cp.done = true;
     }
@@ -768,6 +789,7 @@ static void csr_split(DeviceBatch& db) {
       const DevRecord& r = r2[j];
       cp.res.rec.status = r.status;
       cp.res.rec.nodes = cp.acc + r.nodes;
+      cp.res.rec.hash = trace ? trace_concat(cp.hash, r.hash, r.nodes) : 0;
       cp.res.rec.depth = r.status == MPLD_INFEASIBLE ? 0 : r.depth;
       cp.res.src_off = r.status == MPLD_FEASIBLE ? again[j].col_off : -1;
       cp.done = true;
@@ -793,11 +815,12 @@ static void csr_split(DeviceBatch& db) {
 static void heavy_engine_host(DeviceBatch& db);
 
 // The device-resident engine also follows the stitch-aware order (its
-// tasks rebuild each path's row order and tried sets); the host-driven one
-// replays rows in ascending order only, so stitch-ordered batches always
-// take the device engine.
-static void heavy_engine(DeviceBatch& db) {
-  if (db.tune.heavy_device || db.reg_stitch) heavy_engine_device(db);
+// tasks rebuild each path's row order and tried sets) and carries trace
+// hashes; the host-driven one replays rows in ascending order only and
+// counts nodes only, so stitch-ordered or traced batches always take the
+// device engine.
+static void heavy_engine(DeviceBatch& db, bool trace) {
+  if (db.tune.heavy_device || db.reg_stitch || trace) heavy_engine_device(db, trace);
   else heavy_engine_host(db);
 }
 
@@ -1043,7 +1066,7 @@ void device_solve(DeviceBatch& db, uint32_t flags) {
     fail(MPLD_E_UNSUPPORTED, "a component is too large for conflict marking (" +
                                  std::to_string(db.mark_lds) + " bytes of LDS)");
   const bool trace = flags & MPLD_TRACE_HASH;
-  const bool split = (flags & MPLD_SPLIT_HEAVY) && !trace && !(flags & MPLD_PLAIN);
+  const bool split = (flags & MPLD_SPLIT_HEAVY) && !(flags & MPLD_PLAIN);
   const uint64_t cap = split && db.n_reg > 0 ? (uint64_t)db.tune.heavy_first_cap : ~0ull;
   const bool timed = !(flags & MPLD_UNTIMED) || (flags & MPLD_PLAIN);
   db.timed = false;
@@ -1081,8 +1104,8 @@ void device_solve(DeviceBatch& db, uint32_t flags) {
     enqueue_batched(db, trace, cap, s, split);
     if (split) {
       db.sp_rounds = db.sp_tasks_run = db.sp_heavy = db.sp_reruns = 0;
-      if (db.n_reg) heavy_engine(db);
-      csr_split(db);
+      if (db.n_reg) heavy_engine(db, trace);
+      csr_split(db, trace);
     }
     if (mark) enqueue_mark(db, s);
     if (minimize) enqueue_minimize(db, s);
@@ -1114,8 +1137,8 @@ void device_solve(DeviceBatch& db, uint32_t flags) {
     check_hip(hipGraphLaunch(db.graph, s), "graph launch");
     if (split) {
       db.sp_rounds = db.sp_tasks_run = db.sp_heavy = db.sp_reruns = 0;
-      if (db.n_reg) heavy_engine(db);
-      csr_split(db);
+      if (db.n_reg) heavy_engine(db, trace);
+      csr_split(db, trace);
     }
     if (mark) enqueue_mark(db, s);
     if (minimize) enqueue_minimize(db, s);

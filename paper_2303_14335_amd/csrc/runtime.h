@@ -32,13 +32,14 @@ hipError_t launch_reg_split(int k, int grid, const SplitTask* tasks, int32_t nta
 // Device-resident heavy engine: move the round window on (one thread), and
 // run the current round's tasks (persistent grid; the window comes from
 // head).  hc_nodes / hc_limit: per heavy component, explored nodes and the
-// limit past which its tasks stop splitting.
+// limit past which its tasks stop splitting.  trace: tasks and split items
+// also carry the trace hashes of their nodes.
 hipError_t launch_engine_advance(EngineHead* head, int32_t task_cap, hipStream_t s);
 hipError_t launch_engine_round(int k, int grid, EngineHead* head, EngineTask* tasks,
                                int32_t task_cap, uint8_t* blocks, EngineItem* pool,
                                int32_t pool_cap, RegItems regitems,
                                unsigned long long* hc_nodes, const uint64_t* hc_limit,
-                               uint64_t cap, uint32_t levels, hipStream_t s);
+                               uint64_t cap, uint32_t levels, bool trace, hipStream_t s);
 // Scatters `count` resolved heavy components (records and colors).
 hipError_t launch_heavy_writeback(const HeavyWrite* w, int32_t count, DevRecord* recs,
                                   int8_t* colors, hipStream_t s);
@@ -57,8 +58,9 @@ hipError_t launch_lds_batched(bool trace, bool big, int waves, int grid, int lds
 hipError_t launch_lds_single(bool trace, bool big, int waves, int lds_bytes, const DevDesc* descs,
                              const uint32_t* adj32, int32_t item, uint64_t* gstack,
                              DevRecord* recs, int8_t* colors, hipStream_t s);
-// Subtree tasks of LDS-tier (big = false) or big-tier components.
-hipError_t launch_lds_tasks(bool big, int waves, int grid, int lds_bytes, const DevDesc* descs,
+// Subtree tasks of LDS-tier (big = false) or big-tier components (trace:
+// each task record holds the trace hash of its own nodes).
+hipError_t launch_lds_tasks(bool trace, bool big, int waves, int grid, int lds_bytes, const DevDesc* descs,
                             const uint32_t* adj32, const LdsTask* tasks, int32_t ntasks,
                             uint64_t* gstack, uint64_t stack_words, DevRecord* task_recs,
                             int8_t* task_colors, hipStream_t s);

@@ -676,13 +676,13 @@ __global__ __launch_bounds__(BIG ? 1024 : 64) void lds_single_kernel(
   solve_lds_k<TRACE, BIG>(d, adj32 + d.nbr_off, lds, gstack, colors + d.out_off, recs + d.comp);
 }
 
-// Subtree tasks of the heavy-component split (untraced): task t searches
-// the subtree of root row tasks[t].row of component tasks[t].item with its
-// own budget, and writes its record to task_recs[t] and its colors to
-// task_colors + tasks[t].col_off.  Grid-stride over the tasks, one
+// Subtree tasks of the heavy-component split: task t searches the subtree
+// of root row tasks[t].row of component tasks[t].item with its own budget,
+// and writes its record (with TRACE, the trace hash of its own nodes) to
+// task_recs[t] and its colors to task_colors + tasks[t].col_off.  Grid-stride over the tasks, one
 // workgroup each (one wave small, nw waves big; big ones use the block's
 // stack area).
-template <bool BIG>
+template <bool TRACE, bool BIG>
 __global__ __launch_bounds__(BIG ? 1024 : 64) void lds_task_kernel(
     const DevDesc* __restrict__ descs, const uint32_t* __restrict__ adj32,
     const LdsTask* __restrict__ tasks, int32_t ntasks, uint64_t* gstack,
@@ -693,7 +693,7 @@ __global__ __launch_bounds__(BIG ? 1024 : 64) void lds_task_kernel(
   for (int32_t t = (int32_t)uni(blockIdx.x); t < ntasks; t += (int32_t)gridDim.x) {
     const LdsTask task = tasks[t];
     const DevDesc d = descs[task.item];
-    solve_lds_k<false, BIG>(d, adj32 + d.nbr_off, lds, my_stack, task_colors + task.col_off,
+    solve_lds_k<TRACE, BIG>(d, adj32 + d.nbr_off, lds, my_stack, task_colors + task.col_off,
                             task_recs + t, task.row, (uint64_t)task.budget);
   }
 }
@@ -798,7 +798,7 @@ static void lds_attr(int bytes) {
                             hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
   (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&lds_single_kernel<TRACE, BIG>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&lds_task_kernel<BIG>),
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&lds_task_kernel<TRACE, BIG>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 
@@ -870,18 +870,31 @@ static hipError_t lds_single_t(int waves, int lds_bytes, const DevDesc* descs,
   return hipGetLastError();
 }
 
-hipError_t launch_lds_tasks(bool big, int waves, int grid, int lds_bytes, const DevDesc* descs,
-                            const uint32_t* adj32, const LdsTask* tasks, int32_t ntasks,
-                            uint64_t* gstack, uint64_t stack_words, DevRecord* task_recs,
-                            int8_t* task_colors, hipStream_t s) {
+template <bool TRACE>
+static void lds_tasks_t(bool big, int waves, int grid, int lds_bytes, const DevDesc* descs,
+                        const uint32_t* adj32, const LdsTask* tasks, int32_t ntasks,
+                        uint64_t* gstack, uint64_t stack_words, DevRecord* task_recs,
+                        int8_t* task_colors, hipStream_t s) {
+  if (big)
+    hipLaunchKernelGGL((lds_task_kernel<TRACE, true>), dim3(grid), dim3(64 * waves), (size_t)lds_bytes,
+                       s, descs, adj32, tasks, ntasks, gstack, stack_words, task_recs, task_colors);
+  else
+    hipLaunchKernelGGL((lds_task_kernel<TRACE, false>), dim3(grid), dim3(64), (size_t)lds_bytes, s,
+                       descs, adj32, tasks, ntasks, gstack, stack_words, task_recs, task_colors);
+}
+
+hipError_t launch_lds_tasks(bool trace, bool big, int waves, int grid, int lds_bytes,
+                            const DevDesc* descs, const uint32_t* adj32, const LdsTask* tasks,
+                            int32_t ntasks, uint64_t* gstack, uint64_t stack_words,
+                            DevRecord* task_recs, int8_t* task_colors, hipStream_t s) {
   if (ntasks <= 0) return hipSuccess;
   if (waves < 1 || waves > 16 || (!big && waves != 1) || grid < 1) return hipErrorInvalidValue;
-  if (big)
-    hipLaunchKernelGGL((lds_task_kernel<true>), dim3(grid), dim3(64 * waves), (size_t)lds_bytes, s,
-                       descs, adj32, tasks, ntasks, gstack, stack_words, task_recs, task_colors);
+  if (trace)
+    lds_tasks_t<true>(big, waves, grid, lds_bytes, descs, adj32, tasks, ntasks, gstack, stack_words,
+                      task_recs, task_colors, s);
   else
-    hipLaunchKernelGGL((lds_task_kernel<false>), dim3(grid), dim3(64), (size_t)lds_bytes, s, descs,
-                       adj32, tasks, ntasks, gstack, stack_words, task_recs, task_colors);
+    lds_tasks_t<false>(big, waves, grid, lds_bytes, descs, adj32, tasks, ntasks, gstack, stack_words,
+                       task_recs, task_colors, s);
   return hipGetLastError();
 }
 

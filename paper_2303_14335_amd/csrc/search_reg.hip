@@ -344,28 +344,29 @@ __device__ __forceinline__ void solve_reg(const RegItems& items, int32_t item,
   reg_finish(s, d.n, colors_base + d.out_off, recs + d.comp);
 }
 
-// Root split for the heaviest items (no trace hash, no cap): one
+// Root split for the heaviest items (no cap): one
 // workgroup of four waves per item.  At the root every column has all k
 // rows, so the root column v0 is node 0 and its rows are the k colors.
 // Wave 0 (the owner) counts the root node and searches the subtree of row
 // 0; wave c = 1 .. min(k, 4) - 1 (a helper) searches the subtree of row c
 // from the same start, in chunks of `chunk` nodes with a check of the
-// owner's release between them, and publishes its node count, status and
-// solution in LDS.  The owner takes the rows in order: for a helper's row it
-// waits for the helper and adds its count (an exhausted subtree: next row;
-// a solution: done), exactly as the sequential search would have counted
+// owner's release between them, and publishes its node count, status,
+// trace hash of its own nodes and solution in LDS.  The owner takes the rows
+// in order: for a helper's row it waits for the helper and adds its count
+// and appends its trace hash (an exhausted subtree: next row; a solution:
+// done), exactly as the sequential search would have counted and hashed
 // them; a helper that ran into the budget, or whose count would cross it,
 // is searched again by the owner.  The owner releases the helpers it no
-// longer needs.  Status, node count, depth and colors equal the sequential
-// search's.
+// longer needs.  Status, node count, trace hash, depth and colors equal the
+// sequential search's.
 struct RootSplitLds {
   uint32_t flag[4], stop[4];
-  uint64_t nodes[4];
+  uint64_t nodes[4], hash[4];
   int32_t status[4], depth[4];
   int8_t colors[4][64];
 };
 
-template <int K, bool STITCH>
+template <bool TRACE, int K, bool STITCH>
 __device__ __forceinline__ void root_split(const RegItems& items, int32_t item, uint32_t wave,
                                            uint32_t chunk, int8_t* __restrict__ colors_base,
                                            DevRecord* __restrict__ recs) {
@@ -387,7 +388,7 @@ __device__ __forceinline__ void root_split(const RegItems& items, int32_t item, 
   if (wave > kHelpers) return;
   if (s.P == 0ull) {   // empty component: the root is a solution
     if (wave == 0u) {
-      reg_run<false, K>(s, nb_lo, nb_hi, d.k, budget, budget);
+      reg_run<TRACE, K>(s, nb_lo, nb_hi, d.k, budget, budget);
       reg_finish(s, d.n, colors_base + d.out_off, recs + d.comp);
     }
     return;
@@ -404,7 +405,7 @@ __device__ __forceinline__ void root_split(const RegItems& items, int32_t item, 
     take_row<K, STITCH>(s, nbv0, v0, c, 0ull, R0 & ((2u << c) - 1u));
     s.row_in = v0 * (uint32_t)d.k + c;
     for (;;) {
-      reg_run<false, K, STITCH>(s, nb_lo, nb_hi, d.k, ~0ull, s.nodes + chunk, 1);
+      reg_run<TRACE, K, STITCH>(s, nb_lo, nb_hi, d.k, ~0ull, s.nodes + chunk, 1);
       if (s.status >= 0) break;
       if (__hip_atomic_load(&L.stop[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) != 0u)
         return;   // no longer needed
@@ -418,13 +419,16 @@ __device__ __forceinline__ void root_split(const RegItems& items, int32_t item, 
     if (lane == 63u) {
       L.status[c] = s.status;
       L.nodes[c] = s.nodes;
+      L.hash[c] = s.h;   // the subtree's own trace hash (from 0)
       L.depth[c] = (int32_t)depth;
     }
     __hip_atomic_store(&L.flag[c], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
     return;
   }
-  // ---- owner: the root node, then the root rows in order
+  // ---- owner: the root node, then the root rows in order; with the trace
+  // hash, a helper's subtree hash is appended to the owner's
   ++s.nodes;
+  if (TRACE) s.h = trace_node(s.h, 0u, kNone, v0, (uint32_t)__popc(R0));
   const Planes<K> O0 = s.O;
   const uint64_t P0 = s.P;
   int32_t taken = -1;   // helper whose solution ends the search
@@ -440,6 +444,7 @@ __device__ __forceinline__ void root_split(const RegItems& items, int32_t item, 
       const uint64_t hn = uniform64(L.nodes[c]);
       if (hs >= 0 && s.nodes + hn <= budget) {
         s.nodes += hn;
+        if (TRACE) s.h = trace_concat(s.h, uniform64(L.hash[c]), hn);
         if (hs == MPLD_FEASIBLE) {
           status = MPLD_FEASIBLE;
           taken = (int32_t)c;
@@ -453,7 +458,7 @@ __device__ __forceinline__ void root_split(const RegItems& items, int32_t item, 
     s.depth = 0;
     take_row<K, STITCH>(s, nbv0, v0, c, rem != 0u ? 1ull : 0ull, R0 & ((2u << c) - 1u));
     s.row_in = v0 * (uint32_t)d.k + c;
-    reg_run<false, K, STITCH>(s, nb_lo, nb_hi, d.k, budget, budget, 1);
+    reg_run<TRACE, K, STITCH>(s, nb_lo, nb_hi, d.k, budget, budget, 1);
     if (s.status != MPLD_INFEASIBLE) {
       status = s.status;
       break;
@@ -556,16 +561,16 @@ __global__ __launch_bounds__(256) void reg_batched_kernel(
     DevRecord* __restrict__ recs, int8_t* __restrict__ colors, uint64_t cap, int32_t heavy,
     uint32_t chunk) {
   const uint32_t wpb = blockDim.x >> 6;   // waves per workgroup
-  if (!TRACE && heavy > 0) {
+  if (heavy > 0) {
     // root split: workgroups 0 .. heavy-1 take items 0 .. heavy-1 (four
     // waves each), the rest one item per wave; the host sized the grid so
     // that every item is handed out here
     const uint32_t b = xcd_block(), wave = uniform(threadIdx.x >> 6);
     if (b < (uint32_t)heavy) {
-      root_split<K, STITCH>(items, (int32_t)b, wave, uniform(chunk), colors, recs);
+      root_split<TRACE, K, STITCH>(items, (int32_t)b, wave, uniform(chunk), colors, recs);
     } else {
       const int32_t item = heavy + (int32_t)((b - (uint32_t)heavy) * wpb + wave);
-      if (item < qlen) solve_reg<false, K, STITCH>(items, item, colors, recs, cap);
+      if (item < qlen) solve_reg<TRACE, K, STITCH>(items, item, colors, recs, cap);
     }
     return;
   }
@@ -881,6 +886,7 @@ __global__ __launch_bounds__(256) void reg_split_kernel(
     res.nodes = s.nodes;
     res.item_off = item_off;
     res.pad = 0;
+    res.hash = 0;
     *reinterpret_cast<SplitResult*>(block) = res;   // same value from every lane
     if (gw >= ntasks) break;
     int32_t r = 0;
@@ -926,7 +932,7 @@ hipError_t launch_reg_batched(bool trace, int k, int grid, int wpb, RegItems ite
   // the root split needs four waves per workgroup and a grid that hands
   // out every item at once
   if (heavy < 0 || heavy > qlen || chunk < 1) return hipErrorInvalidValue;
-  if (heavy > 0 && (trace || wpb != 4 || cap != ~0ull ||
+  if (heavy > 0 && (wpb != 4 || cap != ~0ull ||
                     (int64_t)grid < heavy + ((int64_t)qlen - heavy + wpb - 1) / wpb))
     return hipErrorInvalidValue;
   const bool stitch = items.part_off != 0;   // the items carry stitch partners
@@ -1021,10 +1027,12 @@ hipError_t launch_reg_split(int k, int grid, const SplitTask* tasks, int32_t nta
 // and sets nchild to the kind-0 items.  Otherwise item j goes to items[j]
 // and the i-th subtask becomes task children_base + i: its path is this
 // task's path plus the rows down to depth d + levels, which sit in lanes
-// 0 .. d + levels - 1 of the frame register.
-template <int K, bool STITCH = false>
+// 0 .. d + levels - 1 of the frame register.  TRACE: each item also holds
+// the trace hash of its seg nodes.
+template <bool TRACE, int K, bool STITCH = false>
 __device__ __forceinline__ int32_t engine_enumerate(RegState<K>& s, const uint32_t nb_lo,
                                                     const uint32_t nb_hi, const int32_t n,
+                                                    const int32_t k,
                                                     const uint32_t d, const uint32_t levels,
                                                     EngineItem* __restrict__ items,
                                                     EngineTask* __restrict__ tasks,
@@ -1034,6 +1042,7 @@ __device__ __forceinline__ int32_t engine_enumerate(RegState<K>& s, const uint32
   const uint32_t lane = __lane_id();
   const uint32_t limit = d + levels;
   uint32_t seg = 0;
+  uint64_t segh = 0;
   int32_t count = 0;
   nchild = 0;
   auto emit = [&](uint32_t kind) {
@@ -1052,12 +1061,14 @@ __device__ __forceinline__ int32_t engine_enumerate(RegState<K>& s, const uint32
         it.kind = kind;
         it.child = kind == 0 ? children_base + nchild : -1;
         it.pad = 0;
+        it.hash = segh;
         items[count] = it;
       }
     }
     if (kind == 0) ++nchild;
     ++count;
     seg = 0;
+    segh = 0;
   };
   for (;;) {
     uint32_t v = 0, c = 0, tried = 0;
@@ -1069,6 +1080,7 @@ __device__ __forceinline__ int32_t engine_enumerate(RegState<K>& s, const uint32
     } else {
       ++seg;
       if (s.P == 0) {   // a solution among the top levels
+        if (TRACE) segh = trace_node(segh, s.depth, s.row_in, kNone, 0);
         if (lane < s.depth && (s.fr & 0xffu) < (uint32_t)n)
           sol[s.fr & 0xffu] = (int8_t)((s.fr >> 8) & 0xffu);
         emit(2);
@@ -1077,10 +1089,14 @@ __device__ __forceinline__ int32_t engine_enumerate(RegState<K>& s, const uint32
       uint64_t any = s.O[0];
 #pragma unroll
       for (int j = 1; j < K; ++j) any |= s.O[j];
-      back = (s.P & ~any) != 0;
-      if (!back) {
+      const uint64_t zero = s.P & ~any;
+      back = zero != 0;
+      if (back) {
+        if (TRACE) segh = trace_node(segh, s.depth, s.row_in, low_bit(zero), 0);
+      } else {
         uint64_t ge2;
         v = low_bit(min_count_columns(s.O, s.P, ge2));
+        if (TRACE) segh = trace_node(segh, s.depth, s.row_in, v, (uint32_t)__popc(rows_of(s.O, v)));
         c = first_color(s.O, v);
         alt = (ge2 >> v) & 1ull;
         if (STITCH) stitch_pick(s, v, c, tried);
@@ -1092,6 +1108,7 @@ __device__ __forceinline__ int32_t engine_enumerate(RegState<K>& s, const uint32
       break;
     }
     take_row<K, STITCH>(s, rdlane64(nb_lo, nb_hi, v), v, c, alt, tried);
+    s.row_in = v * (uint32_t)k + c;
   }
   return count;
 }
@@ -1113,7 +1130,7 @@ __global__ void engine_advance_kernel(EngineHead* head, int32_t task_cap) {
 // component whose explored nodes pass its limit, or a split that does not
 // fit, is not split (status kEngineSkipped; its reserved task slots that
 // exist are marked skip) and the host re-runs that component sequentially.
-template <int K, bool STITCH>
+template <bool TRACE, int K, bool STITCH>
 __global__ __launch_bounds__(256) void engine_round_kernel(
     EngineHead* __restrict__ head, EngineTask* __restrict__ tasks, int32_t task_cap,
     uint8_t* __restrict__ blocks, EngineItem* __restrict__ pool, int32_t pool_cap,
@@ -1139,6 +1156,7 @@ __global__ __launch_bounds__(256) void engine_round_kernel(
     res.nodes = 0;
     res.item_off = 0;
     res.pad = 0;
+    res.hash = 0;
     if (uniform((uint32_t)task->skip) == 0) {
       const int32_t it = (int32_t)uniform((uint32_t)task->item);
       const uint32_t d = uniform((uint32_t)task->depth);
@@ -1151,8 +1169,9 @@ __global__ __launch_bounds__(256) void engine_round_kernel(
       reg_init(s, dd.n, dd.k);
       if (STITCH) s.pc = part;
       reg_replay<K, STITCH>(s, nb_lo, nb_hi, dd.k, task->rows, d);
-      reg_run<false, K, STITCH>(s, nb_lo, nb_hi, dd.k, ~0ull, cap, d);
+      reg_run<TRACE, K, STITCH>(s, nb_lo, nb_hi, dd.k, ~0ull, cap, d);
       res.nodes = s.nodes;
+      res.hash = s.h;   // the task's own nodes, from its root
       if (s.status == MPLD_FEASIBLE) {
         if (lane < s.depth && (s.fr & 0xffu) < (uint32_t)dd.n)
           sol[s.fr & 0xffu] = (int8_t)((s.fr >> 8) & 0xffu);
@@ -1168,8 +1187,9 @@ __global__ __launch_bounds__(256) void engine_round_kernel(
         if (STITCH) r.pc = part;
         reg_replay<K, STITCH>(r, nb_lo, nb_hi, dd.k, task->rows, d);
         int32_t nchild = 0;
-        const int32_t nitems = engine_enumerate<K, STITCH>(r, nb_lo, nb_hi, dd.n, d, levels, nullptr,
-                                                           nullptr, 0, it, hc, sol, nchild);
+        const int32_t nitems = engine_enumerate<false, K, STITCH>(r, nb_lo, nb_hi, dd.n, dd.k, d,
+                                                                  levels, nullptr, nullptr, 0, it,
+                                                                  hc, sol, nchild);
         // the component's explored nodes: the guard reads the total as of
         // the previous round (a plain load), and the add does not wait for
         // its result, so the reservations are the only round trips
@@ -1194,8 +1214,8 @@ __global__ __launch_bounds__(256) void engine_round_kernel(
           if (STITCH) r.pc = part;
           reg_replay<K, STITCH>(r, nb_lo, nb_hi, dd.k, task->rows, d);
           int32_t nc2 = 0;
-          engine_enumerate<K, STITCH>(r, nb_lo, nb_hi, dd.n, d, levels, pool + io, tasks,
-                                      (int32_t)cb, it, hc, sol, nc2);
+          engine_enumerate<TRACE, K, STITCH>(r, nb_lo, nb_hi, dd.n, dd.k, d, levels, pool + io,
+                                             tasks, (int32_t)cb, it, hc, sol, nc2);
           res.status = -1;
           res.nitems = nitems;
           res.item_off = io;
@@ -1231,17 +1251,27 @@ hipError_t launch_engine_round(int k, int grid, EngineHead* head, EngineTask* ta
                                int32_t task_cap, uint8_t* blocks, EngineItem* pool,
                                int32_t pool_cap, RegItems regitems,
                                unsigned long long* hc_nodes, const uint64_t* hc_limit,
-                               uint64_t cap, uint32_t levels, hipStream_t s) {
+                               uint64_t cap, uint32_t levels, bool trace, hipStream_t s) {
   if (levels < 1 || levels > (uint32_t)kSplitMaxLevels) return hipErrorInvalidValue;
   const bool stitch = regitems.part_off != 0;   // the items carry stitch partners
   with_planes(k, [&](auto kp) {
     constexpr int K = decltype(kp)::value;
-    if (stitch)
-      hipLaunchKernelGGL((engine_round_kernel<K, true>), dim3(grid), dim3(256), 0, s, head, tasks,
-                         task_cap, blocks, pool, pool_cap, regitems, hc_nodes, hc_limit, cap, levels);
+    if (trace && stitch)
+      hipLaunchKernelGGL((engine_round_kernel<true, K, true>), dim3(grid), dim3(256), 0, s, head,
+                         tasks, task_cap, blocks, pool, pool_cap, regitems, hc_nodes, hc_limit, cap,
+                         levels);
+    else if (trace)
+      hipLaunchKernelGGL((engine_round_kernel<true, K, false>), dim3(grid), dim3(256), 0, s, head,
+                         tasks, task_cap, blocks, pool, pool_cap, regitems, hc_nodes, hc_limit, cap,
+                         levels);
+    else if (stitch)
+      hipLaunchKernelGGL((engine_round_kernel<false, K, true>), dim3(grid), dim3(256), 0, s, head,
+                         tasks, task_cap, blocks, pool, pool_cap, regitems, hc_nodes, hc_limit, cap,
+                         levels);
     else
-      hipLaunchKernelGGL((engine_round_kernel<K, false>), dim3(grid), dim3(256), 0, s, head, tasks,
-                         task_cap, blocks, pool, pool_cap, regitems, hc_nodes, hc_limit, cap, levels);
+      hipLaunchKernelGGL((engine_round_kernel<false, K, false>), dim3(grid), dim3(256), 0, s, head,
+                         tasks, task_cap, blocks, pool, pool_cap, regitems, hc_nodes, hc_limit, cap,
+                         levels);
   });
   return hipGetLastError();
 }

@@ -454,6 +454,78 @@ def test_split_heavy_random_components(ctx, k, deg, budget):
         assert np.array_equal(got.colors, ref.colors)
 
 
+# ---- traced subtree engines: every subtree's trace hash appended in search
+# order must give the sequential search's hash
+
+@pytest.mark.parametrize("device_rounds", [0, 1])
+def test_split_heavy_traced_matches_oracle(ctx, device_rounds):
+    """Config 2 traced through the heavy-component engine with small caps
+    (many rounds and split items), the hash included; traced batches always
+    take the device-resident engine."""
+    import paper_2303_14335_amd as mp
+    w, rects = graph_of(2)
+    say("config 2 traced, heavy engine, device rounds =", device_rounds)
+    g, og = both_graphs(rects, w)
+    ref = oracle.decompose(og, w.k, w.budget)
+    b = mp.Batch(ctx, g, w.k, w.budget, SIMPLIFY | TRACE)
+    b.set_tune(heavy_device=device_rounds, heavy_first_cap=256, heavy_round_cap=128)
+    for rep in range(2):
+        b.solve(split=True)
+        got = b.result()
+        for f in ("status", "nodes", "trace_hash", "depth_at_stop"):
+            assert np.array_equal(got.components[f], ref.comps[f]), (f, rep)
+        assert np.array_equal(got.colors, ref.colors), rep
+    assert b.info()["split_rounds"] >= 3
+    b.close()
+
+
+@pytest.mark.parametrize("k,deg,budget", [(3, 4.6, 300000), (4, 8.4, 300000), (3, 4.6, 20000)])
+def test_split_heavy_traced_random_components(ctx, k, deg, budget):
+    import paper_2303_14335_amd as mp
+    comps = heavy_graphs(k * 100 + int(deg) + 7, 30, 40, 64, deg)
+    say("traced heavy random components k", k, "budget", budget)
+    for n, e in comps:
+        g = mp.Graph(n, np.asarray(e, np.int32).reshape(-1, 2), np.zeros((0, 2), np.int32))
+        b = mp.Batch(ctx, g, k, budget, TRACE)
+        b.set_tune(heavy_first_cap=64, heavy_round_cap=64)
+        b.solve(split=True)
+        got = b.result()
+        b.close()
+        ref = oracle.decompose(oracle.Graph(n, g.ce, g.se), k, budget, simplify=False)
+        for f in ("status", "nodes", "trace_hash", "depth_at_stop"):
+            assert np.array_equal(got.components[f], ref.comps[f]), (f, n, k, budget)
+        assert np.array_equal(got.colors, ref.colors)
+
+
+@pytest.mark.parametrize("k", [2, 3, 4, 5, 8])
+def test_root_split_traced_random_components(ctx, k):
+    """The root split with the trace hash (helpers' subtree hashes appended
+    by the owner): a batch of random register-tier components, solved
+    without the subtree engine (so every item of at least four nodes is
+    root-split), at several budgets."""
+    import paper_2303_14335_amd as mp
+    rng = np.random.default_rng(5000 + k)
+    edges, base = [], 0
+    for _ in range(150):
+        n = int(rng.integers(1, 65))
+        p = min(0.95, float(rng.uniform(0.5, 1.6)) * 2.0 * k / max(n, 1))
+        edges += [(a + base, b + base) for a, b in random_graph(rng, n, p)]
+        base += n
+    ce = np.asarray(edges, np.int32).reshape(-1, 2)
+    g = mp.Graph(base, ce, np.zeros((0, 2), np.int32))
+    og = oracle.Graph(base, ce, np.zeros((0, 2), np.int32))
+    say("root split traced, batch of random components, k", k)
+    for budget in (20000, 1, 2, 3, 7, 40):
+        ref = oracle.decompose(og, k, budget, simplify=False)
+        b = mp.Batch(ctx, g, k, budget, TRACE)
+        b.solve()
+        got = b.result()
+        b.close()
+        for f in ("status", "nodes", "trace_hash", "depth_at_stop"):
+            assert np.array_equal(got.components[f], ref.comps[f]), (f, budget)
+        assert np.array_equal(got.colors, ref.colors), budget
+
+
 # ---- untraced solves: the root split (helper waves searching the root's
 # rows 1..3 of the largest register-tier components) must give the
 # sequential status, node count, depth and colors
@@ -559,6 +631,18 @@ def test_csr_subtree_tasks_exact_boundaries(ctx):
     for n, e, total in picked:
         for b in range(1, min(total, 400) + 2):
             solve_split_csr(ctx, [(n, e)], 3, b, FORCE["lds"])
+
+
+def test_csr_subtree_tasks_empty_and_tiny(ctx):
+    """Components with no node (the root is the solution), one node and one
+    edge on the forced LDS and big tiers, where every solve goes through the
+    root-row subtree tasks, traced and untraced, at budgets 1..4."""
+    comps = [(0, []), (1, []), (2, [(0, 1)]), (3, [(0, 1), (1, 2), (0, 2)])]
+    say("LDS/big-tier subtree tasks, empty and tiny components")
+    for flags in (FORCE["lds"], FORCE["global"]):
+        for budget in (1, 2, 3, 4, 100):
+            solve_split_csr(ctx, comps, 3, budget, flags)
+            solve_both(ctx, comps, 3, budget, flags)
 
 
 def test_csr_subtree_tasks_in_batches_and_config3(ctx):
