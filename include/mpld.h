@@ -149,13 +149,16 @@ enum {
                                   has its stitch partner in the component and
                                   already colored on the path, the row of the
                                   partner's color (if open) is tried first,
-                                  the others follow ascending.  Register tier
-                                  only: components of more than 64 nodes or a
-                                  forced LDS/global/device tier give
+                                  the others follow ascending.  Register, LDS
+                                  and big tiers (the CSR blocks of the LDS
+                                  tiers then end with each node's partner); a
+                                  forced device-wide tier gives
                                   MPLD_E_UNSUPPORTED; with MPLD_SPLIT_HEAVY
                                   the subtree tasks rebuild each path's row
-                                  order (device-resident rounds only); not
-                                  with a server. */
+                                  order (device-resident rounds only; the
+                                  root-row tasks of the LDS tiers start where
+                                  no partner is colored yet); not with a
+                                  server. */
   MPLD_ROUNDTRIP = 1u << 12,   /* mpld_batch_solve: the whole device solve -
                                   copy of the packed image from page-locked
                                   host memory to the device, the search, copy

@@ -20,7 +20,9 @@ void check_hip(hipError_t e, const char* what) {
 
 // ---------------------------------------------------------------------------
 // Packing.  Register tier (n <= 64): one uint64 neighbour mask per node.
-// LDS tiers: row offsets (n + 1), neighbour ids (2m), largest degree.
+// LDS tiers: row offsets (n + 1), neighbour ids (2m), largest degree, and
+// with the stitch-aware order each node's stitch partner (local id, -1
+// none).
 
 void image_add(Image& im, mpld_context* ctx, int32_t n, const int32_t* pairs, int64_t m, int32_t k,
                int64_t budget, uint32_t flags, const int32_t* partner) {
@@ -39,9 +41,9 @@ void image_add(Image& im, mpld_context* ctx, int32_t n, const int32_t* pairs, in
     fail(MPLD_E_UNSUPPORTED, "the Eq. 1 minimisation runs on the register tier; a forced LDS, "
                              "global or device tier cannot take it");
   if (minimize) im.minimize = true;
-  if (stitch && (n > 64 || force_lds || force_glb || force_dev))
-    fail(MPLD_E_UNSUPPORTED, "the stitch-aware order runs on the register tier (components of at "
-                             "most 64 nodes); component has " + std::to_string(n));
+  if (stitch && force_dev)
+    fail(MPLD_E_UNSUPPORTED, "the stitch-aware order runs on the register, LDS and big tiers, not "
+                             "on the device-wide tier");
   if (n <= 64 && !force_lds && !force_glb && !force_dev) {
     d.nbr_off = (int64_t)im.masks.size();
     im.masks.resize(im.masks.size() + (size_t)n, 0ull);
@@ -63,7 +65,12 @@ void image_add(Image& im, mpld_context* ctx, int32_t n, const int32_t* pairs, in
     if (force_reg) fail(MPLD_E_UNSUPPORTED, "register tier takes at most 64 nodes, component has " + std::to_string(n));
     d.nbr_off = (int64_t)im.adj32.size();
     const int64_t adj_words = (int64_t)n + 1 + 2 * m;
-    im.adj32.resize(im.adj32.size() + (size_t)adj_words + 1, 0u);
+    im.adj32.resize(im.adj32.size() + (size_t)adj_words + 1 + (stitch ? (size_t)n : 0u), 0u);
+    if (stitch) {
+      im.csr_stitch = true;
+      uint32_t* pw = im.adj32.data() + d.nbr_off + adj_words + 1;
+      for (int32_t v = 0; v < n; ++v) pw[v] = partner && partner[v] >= 0 ? (uint32_t)partner[v] : 0xffffffffu;
+    }
     uint32_t* ptr = im.adj32.data() + d.nbr_off;
     uint32_t* ids = ptr + n + 1;
     for (int64_t e = 0; e < m; ++e) {
@@ -83,8 +90,8 @@ void image_add(Image& im, mpld_context* ctx, int32_t n, const int32_t* pairs, in
     }
     for (int32_t v = 0; v < n; ++v) std::sort(ids + ptr[v], ids + ptr[v + 1]);
     ids[2 * m] = maxdeg;
-    const int64_t small = lds_bytes_for(n, k, adj_words, (int32_t)maxdeg, false);
-    const int64_t big = lds_bytes_for(n, k, adj_words, (int32_t)maxdeg, true);
+    const int64_t small = lds_bytes_for(n, k, adj_words, (int32_t)maxdeg, false, stitch);
+    const int64_t big = lds_bytes_for(n, k, adj_words, (int32_t)maxdeg, true, stitch);
     const int64_t limit = std::min<int64_t>(kLdsSmallLimit, ctx->lds_per_block);
     im.mark_lds = std::max(im.mark_lds, mark_lds_bytes(n, k));
     if (force_dev) {
@@ -206,6 +213,7 @@ void device_upload(mpld_context* ctx, const Image& im, DeviceBatch& db, const Tu
   for (int32_t i = 0; i < db.n_reg; ++i) max_reg_n = std::max(max_reg_n, ordered[(size_t)i].n);
   db.reg_width = reg_item_width(max_reg_n);
   db.reg_stitch = im.stitch;
+  db.csr_stitch = im.csr_stitch;
   const RegItems shape = db.reg_items();
   const size_t stride = shape.stride;
   std::vector<uint8_t> items(stride * (size_t)db.n_reg, 0);
@@ -324,13 +332,13 @@ static void enqueue_batched(DeviceBatch& db, bool trace, uint64_t cap, hipStream
     ++db.launches;
   }
   if (db.n_lds && !split) {
-    check_hip(launch_lds_batched(trace, false, 1, db.grid_lds, db.lds_small, desc + db.n_reg, adj,
+    check_hip(launch_lds_batched(trace, false, db.csr_stitch, 1, db.grid_lds, db.lds_small, desc + db.n_reg, adj,
                                  db.n_lds, cnt + 1, nullptr, 0, recs, colors, s),
               "LDS-tier launch");
     ++db.launches;
   }
   if (db.n_big && !split) {
-    check_hip(launch_lds_batched(trace, true, db.big_waves, db.grid_big, db.lds_big, desc + db.n_reg + db.n_lds,
+    check_hip(launch_lds_batched(trace, true, db.csr_stitch, db.big_waves, db.grid_big, db.lds_big, desc + db.n_reg + db.n_lds,
                                  adj, db.n_big, cnt + 2, gstack, db.big_stack_words, recs, colors,
                                  s),
               "big-tier launch");
@@ -695,13 +703,13 @@ static void csr_split(DeviceBatch& db, bool trace) {
     const auto* dt = db.ct_tasks.as<LdsTask>();
     auto* drec = db.ct_recs.as<DevRecord>();
     if (nsmall)
-      check_hip(launch_lds_tasks(trace, false, 1,
+      check_hip(launch_lds_tasks(trace, false, db.csr_stitch, 1,
                                  std::max(1, std::min((int)nsmall, blocks_for_lds(ctx, db.lds_small))),
                                  db.lds_small, db.desc.as<DevDesc>(), db.adj32.as<uint32_t>(), dt,
                                  (int32_t)nsmall, nullptr, 0, drec, db.ct_colors.as<int8_t>(), s),
                 "subtree tasks (LDS tier)");
     if (nsmall < list.size())
-      check_hip(launch_lds_tasks(trace, true, db.big_waves,
+      check_hip(launch_lds_tasks(trace, true, db.csr_stitch, db.big_waves,
                                  std::max(1, std::min((int)(list.size() - nsmall), db.grid_big_tasks)),
                                  db.lds_big, db.desc.as<DevDesc>(), db.adj32.as<uint32_t>(),
                                  dt + nsmall, (int32_t)(list.size() - nsmall), db.gstack.as<uint64_t>(),
@@ -1085,9 +1093,9 @@ void device_solve(DeviceBatch& db, uint32_t flags) {
       if (i < db.n_reg)
         e = launch_reg_single(trace, db.k, items, i, recs, colors, s);
       else if (i < db.n_reg + db.n_lds)
-        e = launch_lds_single(trace, false, 1, db.lds_small, desc, adj, i, nullptr, recs, colors, s);
+        e = launch_lds_single(trace, false, db.csr_stitch, 1, db.lds_small, desc, adj, i, nullptr, recs, colors, s);
       else if (i < db.n_reg + db.n_lds + db.n_big)
-        e = launch_lds_single(trace, true, db.big_waves, db.lds_big, desc, adj, i, gstack, recs, colors, s);
+        e = launch_lds_single(trace, true, db.csr_stitch, db.big_waves, db.lds_big, desc, adj, i, gstack, recs, colors, s);
       else
         e = launch_device_tier(trace, db.grid_dev, db.lds_dev, desc + i, adj,
                                db.dev_keys.as<unsigned long long>(), db.dev_stacks.as<uint64_t>(),

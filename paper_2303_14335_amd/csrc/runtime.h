@@ -51,16 +51,18 @@ hipError_t launch_reg_tick(bool trace, int k, int grid, const int32_t* list, int
                            int32_t* counter, const DevDesc* slot_desc, uint8_t* slot_state,
                            DevRecord* slot_rec, const uint64_t* arena64, int8_t* arena8,
                            uint64_t slice, DevRecord* tick_out, hipStream_t s);
-hipError_t launch_lds_batched(bool trace, bool big, int waves, int grid, int lds_bytes,
-                              const DevDesc* descs, const uint32_t* adj32, int32_t qlen,
-                              int32_t* counter, uint64_t* gstack, uint64_t stack_words,
-                              DevRecord* recs, int8_t* colors, hipStream_t s);
-hipError_t launch_lds_single(bool trace, bool big, int waves, int lds_bytes, const DevDesc* descs,
-                             const uint32_t* adj32, int32_t item, uint64_t* gstack,
-                             DevRecord* recs, int8_t* colors, hipStream_t s);
+// stitch: the stitch-aware row order (the CSR blocks end with the partners).
+hipError_t launch_lds_batched(bool trace, bool big, bool stitch, int waves, int grid,
+                              int lds_bytes, const DevDesc* descs, const uint32_t* adj32,
+                              int32_t qlen, int32_t* counter, uint64_t* gstack,
+                              uint64_t stack_words, DevRecord* recs, int8_t* colors,
+                              hipStream_t s);
+hipError_t launch_lds_single(bool trace, bool big, bool stitch, int waves, int lds_bytes,
+                             const DevDesc* descs, const uint32_t* adj32, int32_t item,
+                             uint64_t* gstack, DevRecord* recs, int8_t* colors, hipStream_t s);
 // Subtree tasks of LDS-tier (big = false) or big-tier components (trace:
 // each task record holds the trace hash of its own nodes).
-hipError_t launch_lds_tasks(bool trace, bool big, int waves, int grid, int lds_bytes, const DevDesc* descs,
+hipError_t launch_lds_tasks(bool trace, bool big, bool stitch, int waves, int grid, int lds_bytes, const DevDesc* descs,
                             const uint32_t* adj32, const LdsTask* tasks, int32_t ntasks,
                             uint64_t* gstack, uint64_t stack_words, DevRecord* task_recs,
                             int8_t* task_colors, hipStream_t s);
@@ -87,7 +89,8 @@ hipError_t launch_min_reg(int k, int grid, RegItems items, int32_t qlen, const u
                           int8_t* colors, int32_t* min_out, uint32_t budget, hipStream_t s);
 // LDS bytes of one LDS-tier component (adj_words = n + 1 + 2m) and the
 // global stack words of a big one.
-int64_t lds_bytes_for(int32_t n, int32_t k, int64_t adj_words, int32_t max_deg, bool big);
+int64_t lds_bytes_for(int32_t n, int32_t k, int64_t adj_words, int32_t max_deg, bool big,
+                      bool stitch = false);
 int64_t lds_stack_words(int32_t n, int32_t k, int64_t adj_words);
 // Device-wide tier (cooperative launch over `grid` workgroups, one per CU).
 hipError_t launch_device_tier(bool trace, int grid, int lds_bytes, const DevDesc* desc,
@@ -183,6 +186,7 @@ struct Image {
   std::vector<uint64_t> masks;     // register tier: one neighbour mask per node
   std::vector<uint8_t> partner8;   // register tier: local stitch partner per node (0xff none)
   bool stitch = false;             // MPLD_STITCH_ORDER: items carry the partners
+  bool csr_stitch = false;         // MPLD_STITCH_ORDER: CSR blocks end with the partners
   bool minimize = false;           // MPLD_MINIMIZE: partner8 holds the partners
   std::vector<uint32_t> adj32;     // LDS tiers: row offsets, ids, max degree
   std::vector<int32_t> q_reg, q_lds, q_big, q_dev;   // component ids per tier
@@ -235,6 +239,7 @@ struct DeviceBatch {
   DevBuf desc, regitems, adj32, counters, recs, colors, gstack;  // desc in launch order
   uint32_t reg_width = 1;   // masks per register-tier item
   bool reg_stitch = false;  // items carry stitch partners
+  bool csr_stitch = false;  // CSR blocks end with stitch partners (LDS and big tiers)
   RegItems reg_items() const {
     const uint32_t pb = reg_stitch ? (reg_width + 7u) & ~7u : 0u;
     return RegItems{regitems.as<uint8_t>(), reg_width, kRegItemHead + 8u * reg_width + pb,

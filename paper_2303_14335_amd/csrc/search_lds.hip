@@ -30,6 +30,8 @@
 // a per-worker scratch area).
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "device_types.h"
 #include "mpld.h"
 #include "trace.h"
@@ -88,7 +90,7 @@ __device__ __forceinline__ uint32_t word_key(const uint64_t* PL, uint32_t W, uin
 
 // Byte layout of the LDS area of one component.
 struct LdsLayout {
-  uint32_t W, E, pl_off, a_off, adj_off, hdr_off, ent_off, ctl_off, total;
+  uint32_t W, E, pl_off, a_off, adj_off, hdr_off, ent_off, ctl_off, col_off, total;
 };
 
 // Undo-log capacity: one entry per level (its P bit) plus the removed rows,
@@ -99,7 +101,8 @@ __host__ __device__ inline uint32_t lds_log_entries(int32_t n, int32_t k, int64_
   return (uint32_t)(n + (incid < nk ? incid : nk));
 }
 
-__host__ __device__ inline LdsLayout lds_layout(int32_t n, int32_t k, int64_t adj_words, bool big) {
+__host__ __device__ inline LdsLayout lds_layout(int32_t n, int32_t k, int64_t adj_words, bool big,
+                                               bool stitch = false) {
   LdsLayout L;
   L.W = (uint32_t)((n + 63) / 64);
   L.E = lds_log_entries(n, k, adj_words);
@@ -110,6 +113,8 @@ __host__ __device__ inline LdsLayout lds_layout(int32_t n, int32_t k, int64_t ad
   if (big) off += 8u * L.W;   // one bit per depth 0 .. n-1 (small: in registers)
   L.ctl_off = off;
   if (big) off += 128u;       // per-wave minima, loop status, final depth
+  L.col_off = off;            // stitch-aware order: each covered node's color
+  if (big && stitch) off += (uint32_t)n;
   L.adj_off = off;
   if (!big) off += 4u * (uint32_t)adj_words;
   off = (off + 7u) & ~7u;
@@ -135,10 +140,13 @@ __device__ __forceinline__ uint64_t make_hdr(uint32_t v, uint32_t c, uint32_t ro
 //            S/4 ds_read_b128 (S = k+1 rounded up to 4, 8 or 16);
 //   offs     per node: first neighbour (low 16 bits) | degree << 16;
 //   ids      16-bit neighbour ids;
-//   hdr      per depth: {offs of the level's column, est | rows << 16 | c << 24}
-//            (est: the level's first log entry, which holds the column's P
-//            bit, so the column itself is read back from the log);
-//   ent      the undo log.
+//   hdr      per depth: {offs of the level's column, est | untried << 16 |
+//            c << 24} (est: the level's first log entry, which holds the
+//            column's P bit, so the column itself is read back from the log;
+//            untried: the column's rows not tried yet at this level);
+//   ent      the undo log;
+//   (stitch-aware order) each node's stitch partner and the color of each
+//            covered node.
 // The per-depth "untried rows" bit set is one 32-bit word per lane (depth d
 // in lane d >> 5).  Per node the dependent chain is: the plane words (read
 // at the end of the previous node, behind its cover atomics), the count and
@@ -152,17 +160,22 @@ __host__ __device__ constexpr uint32_t lds1_stride(int32_t k) {
 }
 
 struct Lds1Layout {
-  uint32_t offs_off, ids_off, hdr_off, ent_off, total;
+  uint32_t offs_off, ids_off, hdr_off, ent_off, part_off, col_off, total;
 };
 
-__host__ __device__ inline Lds1Layout lds1_layout(int32_t n, int32_t k, int64_t adj_words) {
+// stitch: also each node's stitch partner (16 bits, 0xffff none) and the
+// color of each covered node (one byte).
+__host__ __device__ inline Lds1Layout lds1_layout(int32_t n, int32_t k, int64_t adj_words,
+                                                 bool stitch = false) {
   Lds1Layout L;
   const uint32_t m2 = (uint32_t)(adj_words - n - 1);
   L.offs_off = 64u * 4u * lds1_stride(k);
   L.ids_off = L.offs_off + 4u * (uint32_t)n;
   L.hdr_off = (L.ids_off + 2u * m2 + 7u) & ~7u;
   L.ent_off = L.hdr_off + 8u * (uint32_t)n;
-  L.total = (L.ent_off + 4u * lds_log_entries(n, k, adj_words) + 15u) & ~15u;
+  L.part_off = L.ent_off + 4u * lds_log_entries(n, k, adj_words);
+  L.col_off = L.part_off + (stitch ? 2u * (uint32_t)n : 0u);
+  L.total = (L.col_off + (stitch ? (uint32_t)n : 0u) + 15u) & ~15u;
   return L;
 }
 
@@ -188,7 +201,10 @@ struct Lds1Words {
 // all k rows, so the root column is node 0; its row is taken at depth 0
 // with no alternative left at that level, the root node itself is not
 // counted, and `budget` (> 0) replaces the component's.
-template <bool TRACE, int K>
+// STITCH: the stitch-aware row order (a column whose stitch partner is on
+// the path tries the partner's color first when that row is open, then the
+// others ascending); the CSR block then ends with the partners.
+template <bool TRACE, int K, bool STITCH>
 __device__ void solve_lds(const DevDesc& d, const uint32_t* __restrict__ gadj, char* lds,
                           int8_t* __restrict__ colors, DevRecord* __restrict__ rec,
                           int32_t root_row = -1, uint64_t task_budget = 0) {
@@ -199,15 +215,21 @@ __device__ void solve_lds(const DevDesc& d, const uint32_t* __restrict__ gadj, c
   const uint32_t lane = __lane_id();
   const uint32_t n = (uint32_t)d.n;
   const uint32_t m2 = uni(gadj[n]);
-  const Lds1Layout L = lds1_layout((int32_t)n, K, (int64_t)m2 + n + 1);
+  const Lds1Layout L = lds1_layout((int32_t)n, K, (int64_t)m2 + n + 1, STITCH);
   uint32_t* PL = reinterpret_cast<uint32_t*>(lds);
   uint32_t* offs = reinterpret_cast<uint32_t*>(lds + L.offs_off);
   uint16_t* ids = reinterpret_cast<uint16_t*>(lds + L.ids_off);
   uint2* hdr = reinterpret_cast<uint2*>(lds + L.hdr_off);
   uint32_t* ent = reinterpret_cast<uint32_t*>(lds + L.ent_off);
+  uint16_t* spart = reinterpret_cast<uint16_t*>(lds + L.part_off);
+  uint8_t* scol = reinterpret_cast<uint8_t*>(lds + L.col_off);
   for (uint32_t v = lane; v < n; v += 64) {
     const uint32_t b = gadj[v], e = gadj[v + 1];
     offs[v] = b | ((e - b) << 16);
+    if (STITCH) {
+      const uint32_t p = gadj[n + 1 + m2 + 1 + v];
+      spart[v] = p < n ? (uint16_t)p : (uint16_t)0xffffu;
+    }
   }
   for (uint32_t i = lane; i < m2; i += 64) ids[i] = (uint16_t)gadj[n + 1 + i];
   {
@@ -256,7 +278,10 @@ __device__ void solve_lds(const DevDesc& d, const uint32_t* __restrict__ gadj, c
     // the atomic's result after that read is issued
     W.load(PL, lane);
     asm volatile("" : "+v"(old) : : "memory");
-    if (lane == 0u) hdr[depth] = make_uint2(offv, est | (rows << 16) | (c << 24));
+    if (lane == 0u) {
+      hdr[depth] = make_uint2(offv, est | (rows << 16) | (c << 24));
+      if (STITCH) scol[v] = (uint8_t)c;
+    }
     {
       const uint32_t dl = depth >> 5, db = 1u << (depth & 31u);
       const uint32_t sel = lane == dl ? db : 0u;
@@ -296,7 +321,7 @@ __device__ void solve_lds(const DevDesc& d, const uint32_t* __restrict__ gadj, c
   if (root_row >= 0) {
     // row (0, root_row) at depth 0, with no alternative at that level
     const uint32_t c = (uint32_t)root_row;
-    take_row(0u, c, (1u << K) - 1u, uni(offs[0]), 0u, 0u, false);
+    take_row(0u, c, 0u, uni(offs[0]), 0u, 0u, false);
     depth = 1u;
     row_in = c;
   } else {
@@ -336,7 +361,8 @@ __device__ void solve_lds(const DevDesc& d, const uint32_t* __restrict__ gadj, c
 #pragma unroll
     for (int c = 0; c < K; ++c) r |= __builtin_amdgcn_ubfe(W.a[c], bit, 1u) << c;
     const uint32_t pre = offs[vl < nm1 ? vl : nm1];
-    // issue that read before the minimum (which it then overlaps)
+    const uint32_t prp = STITCH ? (uint32_t)spart[vl < nm1 ? vl : nm1] : 0xffffu;
+    // issue those reads before the minimum (which they then overlap)
     asm volatile("" ::: "memory");
     const uint32_t key = wave_min(p ? ((t << 24) | vl) : kNoKey);
     if (key == kNoKey) {   // no uncovered column: the levels hold a solution
@@ -347,13 +373,24 @@ __device__ void solve_lds(const DevDesc& d, const uint32_t* __restrict__ gadj, c
     uint32_t v = key & 0xffffffu;
     const uint32_t size = key >> 24;
     if (TRACE) h = trace_node(h, depth, row_in, v, size);
-    uint32_t rows, offv, est, lane_lo;
+    uint32_t rows, offv, est, lane_lo, c;
     if (size != 0) {
       const uint32_t wl = v >> 5;
       rows = rdlane(r, wl);
       offv = rdlane(pre, wl);
       est = esp;
       lane_lo = 0u;
+      c = (uint32_t)__builtin_ctz(rows);
+      if (STITCH) {
+        // the partner's color first when the partner is covered (its P bit,
+        // in its lane's word, is clear) and that row of v is open
+        const uint32_t p = rdlane(prp, wl);
+        if (p != 0xffffu && !((rdlane(W.a[K], p >> 5) >> (p & 31u)) & 1u)) {
+          const uint32_t cp = uni((uint32_t)scol[p]);
+          if ((rows >> cp) & 1u) c = cp;
+        }
+      }
+      rows &= ~(1u << c);   // the level's untried rows
     } else {
       // dead end: back to the deepest level whose column has an untried row
       uint32_t f = kNoneL;
@@ -372,7 +409,6 @@ __device__ void solve_lds(const DevDesc& d, const uint32_t* __restrict__ gadj, c
       offv = uni(hd.x);
       const uint32_t d1w = uni(hd.y);
       est = d1w & 0xffffu;
-      const uint32_t cp = (d1w >> 24) & 0xfu;
       // uncover every level above f, and the rows level f removed; the
       // column stays covered (its P bit is entry est)
       for (uint32_t i = est + 1u + lane; i < esp; i += 64) {
@@ -380,14 +416,15 @@ __device__ void solve_lds(const DevDesc& d, const uint32_t* __restrict__ gadj, c
         const uint32_t u = e & kNodeMask;
         atomicOr(&PL[(u >> 5) * S + (e >> kEntryNodeBits)], 1u << (u & 31u));
       }
-      if (TRACE) v = uni(ent[est]) & kNodeMask;
-      // the level's remaining rows: those after color cp
-      rows = ((d1w >> 16) & 0xffu) & ~((2u << cp) - 1u);
+      if (TRACE || STITCH) v = uni(ent[est]) & kNodeMask;
+      // the next untried row of the level, in ascending order
+      rows = (d1w >> 16) & 0xffu;
+      c = (uint32_t)__builtin_ctz(rows);
+      rows &= rows - 1u;
       depth = f;
       lane_lo = 1u;
     }
-    const uint32_t c = (uint32_t)__builtin_ctz(rows);
-    take_row(v, c, rows, offv, est, lane_lo, (rows >> (c + 1u)) != 0u);
+    take_row(v, c, rows, offv, est, lane_lo, rows != 0u);
     row_in = v * (uint32_t)K + c;
     ++depth;
   }
@@ -417,8 +454,11 @@ __device__ void solve_lds(const DevDesc& d, const uint32_t* __restrict__ gadj, c
 // and runs on wave 0 alone; a barrier ends the node, and wave 0 publishes
 // the loop status (and the final depth) in LDS for the others.  Adjacency,
 // level headers and the undo log are in global memory.
-// root_row / task_budget: a subtree task, as for solve_lds.
-template <bool TRACE, int K>
+// root_row / task_budget: a subtree task, as for solve_lds.  STITCH: the
+// stitch-aware row order, as for solve_lds (partners from the CSR block,
+// the color of each covered node in LDS).  Level headers hold the rows
+// not tried yet.
+template <bool TRACE, int K, bool STITCH>
 __device__ void solve_lds_wg(const DevDesc& d, const uint32_t* __restrict__ adj, char* lds,
                              uint64_t* gstack, int8_t* __restrict__ colors,
                              DevRecord* __restrict__ rec, int32_t root_row = -1,
@@ -427,10 +467,12 @@ __device__ void solve_lds_wg(const DevDesc& d, const uint32_t* __restrict__ adj,
   const uint32_t wid = uni(tid >> 6), nw = nthr >> 6;
   const uint32_t n = (uint32_t)d.n;
   const uint32_t adj_words = uni(adj[n]) + n + 1u;
-  const LdsLayout L = lds_layout((int32_t)n, K, adj_words, true);
+  const LdsLayout L = lds_layout((int32_t)n, K, adj_words, true, STITCH);
   const uint32_t W = L.W;
   uint64_t* PL = reinterpret_cast<uint64_t*>(lds + L.pl_off);
   uint64_t* A = reinterpret_cast<uint64_t*>(lds + L.a_off);
+  uint8_t* scol = reinterpret_cast<uint8_t*>(lds + L.col_off);
+  const uint32_t* gpart = adj + adj_words + 1u;   // STITCH: partner of each node
   uint32_t* red = reinterpret_cast<uint32_t*>(lds + L.ctl_off);   // per-wave minima
   int32_t* ctl = reinterpret_cast<int32_t*>(lds + L.ctl_off + 64);  // status, depth
   uint64_t* hdr = gstack;
@@ -460,7 +502,8 @@ __device__ void solve_lds_wg(const DevDesc& d, const uint32_t* __restrict__ adj,
       if (lane == 63u) {
         ent[0] = (uint32_t)K << kEntryNodeBits;
         atomicAnd(reinterpret_cast<unsigned long long*>(&PL[(uint32_t)K * W]), ~1ull);
-        hdr[0] = make_hdr(0u, c, (1u << K) - 1u, 0u);
+        hdr[0] = make_hdr(0u, c, 0u, 0u);   // no other row at this level
+        if (STITCH) scol[0] = (uint8_t)c;
       }
       esp = 1u;
       unsigned long long* plane = reinterpret_cast<unsigned long long*>(PL + c * W);
@@ -513,6 +556,16 @@ __device__ void solve_lds_wg(const DevDesc& d, const uint32_t* __restrict__ adj,
           deg = uni(b1) - beg;
           rows = uni(r);
           c = (uint32_t)__builtin_ctz(rows);
+          if (STITCH) {
+            // the partner's color first when the partner is covered and
+            // that row of v is open
+            const uint32_t p = uni(gpart[v]);
+            if (p < n && !((uni64(PL[(uint32_t)K * W + (p >> 6)]) >> (p & 63u)) & 1ull)) {
+              const uint32_t cp = uni((uint32_t)scol[p]);
+              if ((rows >> cp) & 1u) c = cp;
+            }
+          }
+          rows &= ~(1u << c);   // the level's untried rows
           est = esp;
           if (lane == 63u) {
             ent[est] = ((uint32_t)K << kEntryNodeBits) | v;
@@ -535,8 +588,7 @@ __device__ void solve_lds_wg(const DevDesc& d, const uint32_t* __restrict__ adj,
           } else {
             const uint64_t hd = uni64(hdr[f]);
             v = (uint32_t)hd & 0xffffffu;
-            const uint32_t cp = (uint32_t)(hd >> 24) & 0xfu;
-            rows = (uint32_t)(hd >> 28) & 0xffu;
+            rows = (uint32_t)(hd >> 28) & 0xffu;   // untried rows, next in ascending order
             est = (uint32_t)(hd >> 36);
             beg = uni(adj[v]);
             deg = uni(adj[v + 1]) - beg;
@@ -547,7 +599,8 @@ __device__ void solve_lds_wg(const DevDesc& d, const uint32_t* __restrict__ adj,
               atomicOr(reinterpret_cast<unsigned long long*>(&PL[(e >> kEntryNodeBits) * W + (u >> 6)]),
                        1ull << (u & 63u));
             }
-            c = (uint32_t)__builtin_ctz(rows & ~((2u << cp) - 1u));
+            c = (uint32_t)__builtin_ctz(rows);
+            rows &= rows - 1u;
             depth = f;
             esp = est + 1u;
           }
@@ -556,8 +609,9 @@ __device__ void solve_lds_wg(const DevDesc& d, const uint32_t* __restrict__ adj,
           // include row (v, c) at this depth
           if (lane == 63u) {
             hdr[depth] = make_hdr(v, c, rows, est);
+            if (STITCH) scol[v] = (uint8_t)c;
             const uint64_t bit = 1ull << (depth & 63u);
-            if (rows >> (c + 1u)) atomicOr(reinterpret_cast<unsigned long long*>(&A[depth >> 6]), bit);
+            if (rows != 0u) atomicOr(reinterpret_cast<unsigned long long*>(&A[depth >> 6]), bit);
             else atomicAnd(reinterpret_cast<unsigned long long*>(&A[depth >> 6]), ~bit);
           }
           unsigned long long* plane = reinterpret_cast<unsigned long long*>(PL + c * W);
@@ -610,14 +664,14 @@ __device__ void solve_lds_wg(const DevDesc& d, const uint32_t* __restrict__ adj,
   __syncthreads();
 }
 
-template <bool TRACE, bool BIG>
+template <bool TRACE, bool BIG, bool STITCH>
 __device__ __forceinline__ void solve_lds_k(const DevDesc& d, const uint32_t* gadj, char* lds,
                                             uint64_t* gstack, int8_t* colors, DevRecord* rec,
                                             int32_t root_row = -1, uint64_t task_budget = 0) {
 #define MPLD_LDS_CASE(KK)                                                                  \
   case KK:                                                                                 \
-    if (BIG) solve_lds_wg<TRACE, KK>(d, gadj, lds, gstack, colors, rec, root_row, task_budget); \
-    else solve_lds<TRACE, KK>(d, gadj, lds, colors, rec, root_row, task_budget);            \
+    if (BIG) solve_lds_wg<TRACE, KK, STITCH>(d, gadj, lds, gstack, colors, rec, root_row, task_budget); \
+    else solve_lds<TRACE, KK, STITCH>(d, gadj, lds, colors, rec, root_row, task_budget);            \
     break;
   switch (d.k) {
     MPLD_LDS_CASE(2)
@@ -627,8 +681,8 @@ __device__ __forceinline__ void solve_lds_k(const DevDesc& d, const uint32_t* ga
     MPLD_LDS_CASE(6)
     MPLD_LDS_CASE(7)
     default:
-      if (BIG) solve_lds_wg<TRACE, 8>(d, gadj, lds, gstack, colors, rec, root_row, task_budget);
-      else solve_lds<TRACE, 8>(d, gadj, lds, colors, rec, root_row, task_budget);
+      if (BIG) solve_lds_wg<TRACE, 8, STITCH>(d, gadj, lds, gstack, colors, rec, root_row, task_budget);
+      else solve_lds<TRACE, 8, STITCH>(d, gadj, lds, colors, rec, root_row, task_budget);
       break;
   }
 #undef MPLD_LDS_CASE
@@ -638,7 +692,7 @@ __device__ __forceinline__ void solve_lds_k(const DevDesc& d, const uint32_t* ga
 // components, nw waves for big ones); work distribution as in the register
 // tier: static first item, then atomic pops by one thread, the last pop
 // resets the counter.
-template <bool TRACE, bool BIG>
+template <bool TRACE, bool BIG, bool STITCH>
 __global__ __launch_bounds__(BIG ? 1024 : 64) void lds_batched_kernel(
     const DevDesc* __restrict__ descs, const uint32_t* __restrict__ adj32, int32_t qlen,
     int32_t* __restrict__ counter, uint64_t* gstack, uint64_t stack_words_per_wave,
@@ -649,7 +703,7 @@ __global__ __launch_bounds__(BIG ? 1024 : 64) void lds_batched_kernel(
   int32_t item = (int32_t)uni(blockIdx.x);
   while (item < qlen) {
     const DevDesc d = descs[item];
-    solve_lds_k<TRACE, BIG>(d, adj32 + d.nbr_off, lds, my_stack, colors + d.out_off, recs + d.comp);
+    solve_lds_k<TRACE, BIG, STITCH>(d, adj32 + d.nbr_off, lds, my_stack, colors + d.out_off, recs + d.comp);
     if (gw >= qlen) break;
     int32_t r = 0;
     if constexpr (BIG) {   // one pop per workgroup, shared through LDS
@@ -667,13 +721,13 @@ __global__ __launch_bounds__(BIG ? 1024 : 64) void lds_batched_kernel(
   }
 }
 
-template <bool TRACE, bool BIG>
+template <bool TRACE, bool BIG, bool STITCH>
 __global__ __launch_bounds__(BIG ? 1024 : 64) void lds_single_kernel(
     const DevDesc* __restrict__ descs, const uint32_t* __restrict__ adj32, int32_t item,
     uint64_t* gstack, DevRecord* __restrict__ recs, int8_t* __restrict__ colors) {
   extern __shared__ __align__(16) char lds[];
   const DevDesc d = descs[item];
-  solve_lds_k<TRACE, BIG>(d, adj32 + d.nbr_off, lds, gstack, colors + d.out_off, recs + d.comp);
+  solve_lds_k<TRACE, BIG, STITCH>(d, adj32 + d.nbr_off, lds, gstack, colors + d.out_off, recs + d.comp);
 }
 
 // Subtree tasks of the heavy-component split: task t searches the subtree
@@ -682,7 +736,7 @@ __global__ __launch_bounds__(BIG ? 1024 : 64) void lds_single_kernel(
 // task_recs[t] and its colors to task_colors + tasks[t].col_off.  Grid-stride over the tasks, one
 // workgroup each (one wave small, nw waves big; big ones use the block's
 // stack area).
-template <bool TRACE, bool BIG>
+template <bool TRACE, bool BIG, bool STITCH>
 __global__ __launch_bounds__(BIG ? 1024 : 64) void lds_task_kernel(
     const DevDesc* __restrict__ descs, const uint32_t* __restrict__ adj32,
     const LdsTask* __restrict__ tasks, int32_t ntasks, uint64_t* gstack,
@@ -693,7 +747,7 @@ __global__ __launch_bounds__(BIG ? 1024 : 64) void lds_task_kernel(
   for (int32_t t = (int32_t)uni(blockIdx.x); t < ntasks; t += (int32_t)gridDim.x) {
     const LdsTask task = tasks[t];
     const DevDesc d = descs[task.item];
-    solve_lds_k<TRACE, BIG>(d, adj32 + d.nbr_off, lds, my_stack, task_colors + task.col_off,
+    solve_lds_k<TRACE, BIG, STITCH>(d, adj32 + d.nbr_off, lds, my_stack, task_colors + task.col_off,
                             task_recs + t, task.row, (uint64_t)task.budget);
   }
 }
@@ -781,24 +835,25 @@ __global__ __launch_bounds__(64) void mark_lds_kernel(const DevDesc* __restrict_
 
 // ---- host side --------------------------------------------------------------
 
-int64_t lds_bytes_for(int32_t n, int32_t k, int64_t adj_words, int32_t max_deg, bool big) {
+int64_t lds_bytes_for(int32_t n, int32_t k, int64_t adj_words, int32_t max_deg, bool big,
+                      bool stitch) {
   // adj_words: row offsets + neighbour ids (n + 1 + 2m)
   (void)max_deg;
-  return big ? (int64_t)lds_layout(n, k, adj_words, true).total
-             : (int64_t)lds1_layout(n, k, adj_words).total;
+  return big ? (int64_t)lds_layout(n, k, adj_words, true, stitch).total
+             : (int64_t)lds1_layout(n, k, adj_words, stitch).total;
 }
 
 int64_t lds_stack_words(int32_t n, int32_t k, int64_t adj_words) {
   // level headers (one u64 per depth) and the undo log (u32 entries)
   return (int64_t)n + ((int64_t)lds_log_entries(n, k, adj_words) + 1) / 2;
 }
-template <bool TRACE, bool BIG>
+template <bool TRACE, bool BIG, bool STITCH>
 static void lds_attr(int bytes) {
-  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&lds_batched_kernel<TRACE, BIG>),
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&lds_batched_kernel<TRACE, BIG, STITCH>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&lds_single_kernel<TRACE, BIG>),
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&lds_single_kernel<TRACE, BIG, STITCH>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&lds_task_kernel<TRACE, BIG>),
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&lds_task_kernel<TRACE, BIG, STITCH>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 
@@ -819,10 +874,14 @@ hipError_t launch_mark_lds(int grid, int lds_bytes, const DevDesc* descs, const 
 void lds_configure(int bytes) {
   (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&mark_lds_kernel),
                             hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-  lds_attr<true, true>(bytes);
-  lds_attr<true, false>(bytes);
-  lds_attr<false, true>(bytes);
-  lds_attr<false, false>(bytes);
+  lds_attr<true, true, false>(bytes);
+  lds_attr<true, false, false>(bytes);
+  lds_attr<false, true, false>(bytes);
+  lds_attr<false, false, false>(bytes);
+  lds_attr<true, true, true>(bytes);
+  lds_attr<true, false, true>(bytes);
+  lds_attr<false, true, true>(bytes);
+  lds_attr<false, false, true>(bytes);
   (void)hipGetLastError();
 }
 
@@ -833,69 +892,48 @@ int lds_big_waves(int32_t max_n) {
   return w < 1 ? 1 : (w > 16 ? 16 : w);
 }
 
-template <bool TRACE, bool BIG>
-static hipError_t lds_batched_t(int waves, int grid, int lds_bytes, const DevDesc* descs,
-                                const uint32_t* adj32, int32_t qlen, int32_t* counter,
-                                uint64_t* gstack, uint64_t stack_words, DevRecord* recs,
-                                int8_t* colors, hipStream_t s) {
-  hipLaunchKernelGGL((lds_batched_kernel<TRACE, BIG>), dim3(grid), dim3(64 * waves),
-                     (size_t)lds_bytes, s, descs, adj32, qlen, counter, gstack, stack_words, recs,
-                     colors);
+// Calls f(trace, big, stitch) with each flag as a std::integral_constant,
+// so that the launch names the matching kernel instantiation.
+template <typename F>
+static hipError_t lds_dispatch(bool trace, bool big, bool stitch, F&& f) {
+  auto with_stitch = [&](auto t, auto g) {
+    if (stitch) f(t, g, std::true_type{});
+    else f(t, g, std::false_type{});
+  };
+  auto with_big = [&](auto t) {
+    if (big) with_stitch(t, std::true_type{});
+    else with_stitch(t, std::false_type{});
+  };
+  if (trace) with_big(std::true_type{});
+  else with_big(std::false_type{});
   return hipGetLastError();
 }
 
-hipError_t launch_lds_batched(bool trace, bool big, int waves, int grid, int lds_bytes,
-                              const DevDesc* descs, const uint32_t* adj32, int32_t qlen,
-                              int32_t* counter, uint64_t* gstack, uint64_t stack_words,
-                              DevRecord* recs, int8_t* colors, hipStream_t s) {
+hipError_t launch_lds_batched(bool trace, bool big, bool stitch, int waves, int grid,
+                              int lds_bytes, const DevDesc* descs, const uint32_t* adj32,
+                              int32_t qlen, int32_t* counter, uint64_t* gstack,
+                              uint64_t stack_words, DevRecord* recs, int8_t* colors,
+                              hipStream_t s) {
   if (qlen <= 0) return hipSuccess;
   if (waves < 1 || waves > 16 || (!big && waves != 1)) return hipErrorInvalidValue;
-  if (trace)
-    return big ? lds_batched_t<true, true>(waves, grid, lds_bytes, descs, adj32, qlen, counter,
-                                           gstack, stack_words, recs, colors, s)
-               : lds_batched_t<true, false>(1, grid, lds_bytes, descs, adj32, qlen, counter,
-                                            gstack, stack_words, recs, colors, s);
-  return big ? lds_batched_t<false, true>(waves, grid, lds_bytes, descs, adj32, qlen, counter,
-                                          gstack, stack_words, recs, colors, s)
-             : lds_batched_t<false, false>(1, grid, lds_bytes, descs, adj32, qlen, counter,
-                                           gstack, stack_words, recs, colors, s);
+  return lds_dispatch(trace, big, stitch, [&](auto t, auto g, auto st) {
+    hipLaunchKernelGGL((lds_batched_kernel<decltype(t)::value, decltype(g)::value, decltype(st)::value>),
+                       dim3(grid), dim3(64 * waves), (size_t)lds_bytes, s, descs, adj32, qlen,
+                       counter, gstack, stack_words, recs, colors);
+  });
 }
 
-template <bool TRACE, bool BIG>
-static hipError_t lds_single_t(int waves, int lds_bytes, const DevDesc* descs,
-                               const uint32_t* adj32, int32_t item, uint64_t* gstack,
-                               DevRecord* recs, int8_t* colors, hipStream_t s) {
-  hipLaunchKernelGGL((lds_single_kernel<TRACE, BIG>), dim3(1), dim3(64 * waves),
-                     (size_t)lds_bytes, s, descs, adj32, item, gstack, recs, colors);
-  return hipGetLastError();
-}
-
-template <bool TRACE>
-static void lds_tasks_t(bool big, int waves, int grid, int lds_bytes, const DevDesc* descs,
-                        const uint32_t* adj32, const LdsTask* tasks, int32_t ntasks,
-                        uint64_t* gstack, uint64_t stack_words, DevRecord* task_recs,
-                        int8_t* task_colors, hipStream_t s) {
-  if (big)
-    hipLaunchKernelGGL((lds_task_kernel<TRACE, true>), dim3(grid), dim3(64 * waves), (size_t)lds_bytes,
-                       s, descs, adj32, tasks, ntasks, gstack, stack_words, task_recs, task_colors);
-  else
-    hipLaunchKernelGGL((lds_task_kernel<TRACE, false>), dim3(grid), dim3(64), (size_t)lds_bytes, s,
-                       descs, adj32, tasks, ntasks, gstack, stack_words, task_recs, task_colors);
-}
-
-hipError_t launch_lds_tasks(bool trace, bool big, int waves, int grid, int lds_bytes,
+hipError_t launch_lds_tasks(bool trace, bool big, bool stitch, int waves, int grid, int lds_bytes,
                             const DevDesc* descs, const uint32_t* adj32, const LdsTask* tasks,
                             int32_t ntasks, uint64_t* gstack, uint64_t stack_words,
                             DevRecord* task_recs, int8_t* task_colors, hipStream_t s) {
   if (ntasks <= 0) return hipSuccess;
   if (waves < 1 || waves > 16 || (!big && waves != 1) || grid < 1) return hipErrorInvalidValue;
-  if (trace)
-    lds_tasks_t<true>(big, waves, grid, lds_bytes, descs, adj32, tasks, ntasks, gstack, stack_words,
-                      task_recs, task_colors, s);
-  else
-    lds_tasks_t<false>(big, waves, grid, lds_bytes, descs, adj32, tasks, ntasks, gstack, stack_words,
-                       task_recs, task_colors, s);
-  return hipGetLastError();
+  return lds_dispatch(trace, big, stitch, [&](auto t, auto g, auto st) {
+    hipLaunchKernelGGL((lds_task_kernel<decltype(t)::value, decltype(g)::value, decltype(st)::value>),
+                       dim3(grid), dim3(64 * waves), (size_t)lds_bytes, s, descs, adj32, tasks,
+                       ntasks, gstack, stack_words, task_recs, task_colors);
+  });
 }
 
 // One workgroup per resolved component: its colors and record.
@@ -919,19 +957,15 @@ hipError_t launch_csr_writeback(const LdsResolved* w, int32_t count, const int8_
   return hipGetLastError();
 }
 
-hipError_t launch_lds_single(bool trace, bool big, int waves, int lds_bytes, const DevDesc* descs,
-                             const uint32_t* adj32, int32_t item, uint64_t* gstack,
-                             DevRecord* recs, int8_t* colors, hipStream_t s) {
+hipError_t launch_lds_single(bool trace, bool big, bool stitch, int waves, int lds_bytes,
+                             const DevDesc* descs, const uint32_t* adj32, int32_t item,
+                             uint64_t* gstack, DevRecord* recs, int8_t* colors, hipStream_t s) {
   if (waves < 1 || waves > 16 || (!big && waves != 1)) return hipErrorInvalidValue;
-  if (trace)
-    return big ? lds_single_t<true, true>(waves, lds_bytes, descs, adj32, item, gstack, recs,
-                                          colors, s)
-               : lds_single_t<true, false>(1, lds_bytes, descs, adj32, item, gstack, recs,
-                                           colors, s);
-  return big ? lds_single_t<false, true>(waves, lds_bytes, descs, adj32, item, gstack, recs,
-                                         colors, s)
-             : lds_single_t<false, false>(1, lds_bytes, descs, adj32, item, gstack, recs,
-                                          colors, s);
+  return lds_dispatch(trace, big, stitch, [&](auto t, auto g, auto st) {
+    hipLaunchKernelGGL((lds_single_kernel<decltype(t)::value, decltype(g)::value, decltype(st)::value>),
+                       dim3(1), dim3(64 * waves), (size_t)lds_bytes, s, descs, adj32, item, gstack,
+                       recs, colors);
+  });
 }
 
 }  // namespace mpld

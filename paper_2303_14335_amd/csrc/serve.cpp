@@ -320,7 +320,7 @@ void HipExecutor::tick(std::vector<Request*>& admitted, std::vector<ServeActive>
         const int per_cu = std::max(1, std::min(32, (160 * 1024) / std::max(bytes, 1)));
         const int grid = std::max(1, std::min((int)(b - a), ctx->num_cus * per_cu));
         // the big tier's stack areas: one per workgroup, grid <= count
-        check_hip(launch_lds_batched(lds_trace[a] != 0, big, big ? lds_big_waves(big_max_n) : 1, grid,
+        check_hip(launch_lds_batched(lds_trace[a] != 0, big, false, big ? lds_big_waves(big_max_n) : 1, grid,
                                      bytes, f->desc.as<DevDesc>() + a, arena.as<uint32_t>(),
                                      (int32_t)(b - a), counter.as<int32_t>() + 1,
                                      big ? f->gstack.as<uint64_t>() : nullptr, (uint64_t)big_words,

@@ -16,7 +16,7 @@ from workload.configs import CONFIGS
 pytestmark = pytest.mark.gpu
 
 SIMPLIFY, TRACE = 1 << 0, 1 << 1
-FORCE_LDS = 1 << 4
+FORCE_LDS, FORCE_GLOBAL, FORCE_DEVICE = 1 << 4, 1 << 5, 1 << 7
 STITCH = 1 << 11
 FIELDS = ("size", "status", "nodes", "trace_hash", "depth_at_stop", "stitches", "first_node",
           "num_edges")
@@ -66,7 +66,7 @@ def test_stitch_without_partners_is_plain(ctx, cfg):
 
 
 def random_layout(rng, k, count, n_lo, n_hi):
-    """Disjoint random components (<= 64 nodes each) with random stitch
+    """Disjoint random components of n_lo..n_hi nodes with random stitch
     pairs between non-adjacent nodes of the same component."""
     ce, se, base = [], [], 0
     for _ in range(count):
@@ -132,16 +132,43 @@ def test_stitch_budget_cuts(ctx):
         compare(mp.mpld_decompose(ctx, g, 3, budget, STITCH), ref, UNTRACED)
 
 
-def test_stitch_rejects_other_tiers(ctx):
+@pytest.mark.parametrize("k", [2, 3, 4])
+def test_stitch_lds_and_big_tiers(ctx, k):
+    """The stitch-aware order on the LDS and big tiers: components of 65-400
+    nodes with stitch pairs (placed on the LDS tier, or forced onto the big
+    tier), and small ones forced onto either; traced and untraced, at
+    budgets that end inside the search and one that lets it finish."""
     import paper_2303_14335_amd as mp
-    w, g = config_graph(3)   # one component of about 40k nodes
-    say("stitch order rejects a component beyond the register tier")
-    with pytest.raises(mp.MpldError) as e:
-        mp.mpld_decompose(ctx, g, w.k, w.budget, SIMPLIFY | STITCH)
-    assert e.value.code == -7   # MPLD_E_UNSUPPORTED
+    rng = np.random.default_rng(6100 + k)
+    big_layout = random_layout(rng, k, 12, 65, 400)
+    small_layout = random_layout(rng, k, 60, 2, 64)
+    for name, (n, ce, se), extra in (("65-400 nodes", big_layout, 0),
+                                     ("65-400 nodes, big tier", big_layout, FORCE_GLOBAL),
+                                     ("small, LDS tier", small_layout, FORCE_LDS),
+                                     ("small, big tier", small_layout, FORCE_GLOBAL)):
+        g = mp.Graph(n, ce, se)
+        og = oracle.Graph(n, ce, se)
+        for budget in (30000, 300, 17):
+            say("stitch order,", name, "k", k, "budget", budget)
+            ref = oracle.decompose(og, k, budget, simplify=False, stitch=True)
+            compare(mp.mpld_decompose(ctx, g, k, budget, STITCH | TRACE | extra), ref)
+            compare(mp.mpld_decompose(ctx, g, k, budget, STITCH | extra), ref, UNTRACED)
+
+
+def test_stitch_config3_big_tier(ctx):
+    import paper_2303_14335_amd as mp
+    w, g = config_graph(3)   # one component of about 40k nodes, big tier
+    say("stitch order, config 3 on the big tier")
+    ref = oracle.decompose(oracle.Graph(g.num_nodes, g.ce, g.se), w.k, w.budget, stitch=True)
+    compare(mp.mpld_decompose(ctx, g, w.k, w.budget, SIMPLIFY | STITCH | TRACE), ref)
+
+
+def test_stitch_rejects_device_tier_and_server(ctx):
+    import paper_2303_14335_amd as mp
+    say("stitch order rejected on the device-wide tier and by a server")
     small = mp.Graph(3, np.array([[0, 1]], np.int32), np.zeros((0, 2), np.int32))
     with pytest.raises(mp.MpldError) as e:
-        mp.mpld_decompose(ctx, small, 3, 100, STITCH | FORCE_LDS)
+        mp.mpld_decompose(ctx, small, 3, 100, STITCH | FORCE_DEVICE)
     assert e.value.code == -7   # MPLD_E_UNSUPPORTED
     srv = mp.Server(ctx)
     with pytest.raises(mp.MpldError) as e:
