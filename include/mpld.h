@@ -157,8 +157,9 @@ enum {
                                   the subtree tasks rebuild each path's row
                                   order (device-resident rounds only; the
                                   root-row tasks of the LDS tiers start where
-                                  no partner is colored yet); not with a
-                                  server. */
+                                  no partner is colored yet); servers take it
+                                  (the partner registers are part of the
+                                  resumable state). */
   MPLD_ROUNDTRIP = 1u << 12,   /* mpld_batch_solve: the whole device solve -
                                   copy of the packed image from page-locked
                                   host memory to the device, the search, copy

@@ -164,7 +164,7 @@ static_assert(sizeof(HeavyWrite) == 104, "write-back entry is 104 bytes");
 // Device bytes of the resumable register-tier search state of one
 // component (serving): a 128-byte uniform head (counters, then up to eight
 // 64-bit color planes), then 64 lanes x (u32 frame, u64 P snapshot, up to
-// eight u64 plane snapshots).
-constexpr uint64_t kRegStateBytes = 128 + 64 * 4 * (3 + 2 * 8);
+// eight u64 plane snapshots, u32 stitch partner and its color).
+constexpr uint64_t kRegStateBytes = 128 + 64 * 4 * (3 + 2 * 8 + 1);
 
 }  // namespace mpld

@@ -47,10 +47,11 @@ hipError_t launch_reg_single(bool trace, int k, RegItems items, int32_t item,
                              DevRecord* recs, int8_t* colors, hipStream_t s);
 int reg_batched_blocks_per_cu(bool trace);
 // Serving tick over register-tier components (see the kernel).
-hipError_t launch_reg_tick(bool trace, int k, int grid, const int32_t* list, int32_t len,
-                           int32_t* counter, const DevDesc* slot_desc, uint8_t* slot_state,
-                           DevRecord* slot_rec, const uint64_t* arena64, int8_t* arena8,
-                           uint64_t slice, DevRecord* tick_out, hipStream_t s);
+hipError_t launch_reg_tick(bool trace, bool stitch, int k, int grid, const int32_t* list,
+                           int32_t len, int32_t* counter, const DevDesc* slot_desc,
+                           uint8_t* slot_state, DevRecord* slot_rec, const uint64_t* arena64,
+                           int8_t* arena8, const uint8_t* part8, uint64_t slice,
+                           DevRecord* tick_out, hipStream_t s);
 // stitch: the stitch-aware row order (the CSR blocks end with the partners).
 hipError_t launch_lds_batched(bool trace, bool big, bool stitch, int waves, int grid,
                               int lds_bytes, const DevDesc* descs, const uint32_t* adj32,

@@ -487,9 +487,10 @@ struct RegStateHead {
   uint32_t depth, row_in;
 };
 static_assert(sizeof(RegStateHead) == 40, "state head is 40 bytes");
-static_assert(kRegStateBytes >= 128 + 256 * (3 + 2 * 8), "state layout");
+static_assert(kRegStateBytes >= 128 + 256 * (3 + 2 * 8 + 1), "state layout");
+constexpr uint32_t kStatePcLane = (3 + 2 * 8) * 64;   // u32 index of the partner registers
 
-template <int K>
+template <int K, bool STITCH = false>
 __device__ __forceinline__ void reg_save(const RegState<K>& s, uint8_t* base) {
   const uint32_t lane = __lane_id();
   RegStateHead* hd = reinterpret_cast<RegStateHead*>(base);
@@ -511,9 +512,10 @@ __device__ __forceinline__ void reg_save(const RegState<K>& s, uint8_t* base) {
     lanes[(3 + 2 * c) * 64 + lane] = s.so_lo[c];
     lanes[(4 + 2 * c) * 64 + lane] = s.so_hi[c];
   }
+  if (STITCH) lanes[kStatePcLane + lane] = s.pc;
 }
 
-template <int K>
+template <int K, bool STITCH = false>
 __device__ __forceinline__ void reg_load(RegState<K>& s, const uint8_t* base) {
   const uint32_t lane = __lane_id();
   const RegStateHead* hd = reinterpret_cast<const RegStateHead*>(base);
@@ -535,6 +537,7 @@ __device__ __forceinline__ void reg_load(RegState<K>& s, const uint8_t* base) {
     s.so_lo[c] = lanes[(3 + 2 * c) * 64 + lane];
     s.so_hi[c] = lanes[(4 + 2 * c) * 64 + lane];
   }
+  if (STITCH) s.pc = lanes[kStatePcLane + lane];
   s.status = -1;
 }
 
@@ -668,12 +671,15 @@ __global__ __launch_bounds__(64) void mark_reg_kernel(const RegItems items, int3
 // marking).  A finished search writes its colors and record; a paused one
 // saves its state.  tick_out[i] receives the record of list entry i (status -1 while
 // the search is still running).  Work distribution as in the batched kernel.
-template <bool TRACE, int K>
+// STITCH: the stitch-aware row order; part8[w] is the stitch partner (local
+// id, 0xff none) of the node whose neighbour mask is arena64[w], and the
+// lanes' partner registers are part of the saved state.
+template <bool TRACE, int K, bool STITCH>
 __global__ __launch_bounds__(256) void reg_tick_kernel(
     const int32_t* __restrict__ list, int32_t len, int32_t* __restrict__ counter,
     const DevDesc* __restrict__ slot_desc, uint8_t* slot_state, DevRecord* __restrict__ slot_rec,
-    const uint64_t* __restrict__ arena64, int8_t* __restrict__ arena8, uint64_t slice,
-    DevRecord* __restrict__ tick_out) {
+    const uint64_t* __restrict__ arena64, int8_t* __restrict__ arena8,
+    const uint8_t* __restrict__ part8, uint64_t slice, DevRecord* __restrict__ tick_out) {
   const int32_t gw = (int32_t)gridDim.x * 4;
   int32_t item = (int32_t)uniform(xcd_block() * 4u + (threadIdx.x >> 6));
   while (item < len) {
@@ -684,13 +690,15 @@ __global__ __launch_bounds__(256) void reg_tick_kernel(
     const uint64_t nb = lane < (uint32_t)d.n ? arena64[d.nbr_off + lane] : 0ull;
     uint8_t* base = slot_state + (uint64_t)slot * kRegStateBytes;
     RegState<K> s;
-    if (entry >> 31)
+    if (entry >> 31) {
       reg_init(s, d.n, d.k);
-    else
-      reg_load(s, base);
+      if (STITCH) s.pc = ((lane < (uint32_t)d.n ? (uint32_t)part8[d.nbr_off + lane] : 0xffu) << 8) | 0xffu;
+    } else {
+      reg_load<K, STITCH>(s, base);
+    }
     const uint64_t budget = (uint64_t)d.budget;
     const uint64_t stop = budget - s.nodes > slice ? s.nodes + slice : budget;
-    reg_run<TRACE, K>(s, (uint32_t)nb, (uint32_t)(nb >> 32), d.k, budget, stop);
+    reg_run<TRACE, K, STITCH>(s, (uint32_t)nb, (uint32_t)(nb >> 32), d.k, budget, stop);
     if (s.status >= 0) {
       reg_finish(s, d.n, arena8 + d.out_off, slot_rec + slot);
       // conflict marking of a component left without a solution (the
@@ -698,7 +706,7 @@ __global__ __launch_bounds__(256) void reg_tick_kernel(
       if (((entry >> 30) & 1u) && s.status != MPLD_FEASIBLE)
         mark_core<K>((uint32_t)d.n, nb, arena8 + d.out_off);
     } else {
-      reg_save(s, base);
+      reg_save<K, STITCH>(s, base);
     }
     DevRecord* o = tick_out + item;
     o->status = s.status;
@@ -989,19 +997,23 @@ hipError_t launch_reg_single(bool trace, int k, RegItems items, int32_t item,
   return hipGetLastError();
 }
 
-hipError_t launch_reg_tick(bool trace, int k, int grid, const int32_t* list, int32_t len,
-                           int32_t* counter, const DevDesc* slot_desc, uint8_t* slot_state,
-                           DevRecord* slot_rec, const uint64_t* arena64, int8_t* arena8,
-                           uint64_t slice, DevRecord* tick_out, hipStream_t s) {
+hipError_t launch_reg_tick(bool trace, bool stitch, int k, int grid, const int32_t* list,
+                           int32_t len, int32_t* counter, const DevDesc* slot_desc,
+                           uint8_t* slot_state, DevRecord* slot_rec, const uint64_t* arena64,
+                           int8_t* arena8, const uint8_t* part8, uint64_t slice,
+                           DevRecord* tick_out, hipStream_t s) {
   if (len <= 0) return hipSuccess;
   with_planes(k, [&](auto kp) {
     constexpr int K = decltype(kp)::value;
-    if (trace)
-      hipLaunchKernelGGL((reg_tick_kernel<true, K>), dim3(grid), dim3(256), 0, s, list, len,
-                         counter, slot_desc, slot_state, slot_rec, arena64, arena8, slice, tick_out);
-    else
-      hipLaunchKernelGGL((reg_tick_kernel<false, K>), dim3(grid), dim3(256), 0, s, list, len,
-                         counter, slot_desc, slot_state, slot_rec, arena64, arena8, slice, tick_out);
+    auto go = [&](auto t, auto st) {
+      hipLaunchKernelGGL((reg_tick_kernel<decltype(t)::value, K, decltype(st)::value>), dim3(grid),
+                         dim3(256), 0, s, list, len, counter, slot_desc, slot_state, slot_rec,
+                         arena64, arena8, part8, slice, tick_out);
+    };
+    if (trace && stitch) go(std::true_type{}, std::true_type{});
+    else if (trace) go(std::true_type{}, std::false_type{});
+    else if (stitch) go(std::false_type{}, std::true_type{});
+    else go(std::false_type{}, std::false_type{});
   });
   return hipGetLastError();
 }

@@ -41,6 +41,9 @@ class HipExecutor : public ServeExecutor {
   mpld_context* ctx = nullptr;
   mpld_server_options opt{};
   DevBuf arena, slot_desc, slot_rec, slot_state, list, tick_out, counter;
+  // stitch partner (local id, 0xff none) of the node whose neighbour mask
+  // is arena word w, at byte w: written for stitch-ordered requests
+  DevBuf part8;
   int32_t max_slots = 0;
   // device layout-graph builders for large layout requests (own stream
   // each), taken in turn so that concurrent large requests do not queue on
@@ -122,12 +125,20 @@ void HipExecutor::front_end(Request* r) {
     }
     if (!split_done) r->s = simplify_and_split(r->g, r->opt.k, r->opt.flags & MPLD_SIMPLIFY);
     const int32_t nc = (int32_t)r->s.comp_ptr.size() - 1;
-    std::vector<int32_t> pairs;
+    const bool stitch = r->opt.flags & MPLD_STITCH_ORDER;
+    std::vector<int32_t> pairs, part;
     for (int32_t c = 0; c < nc; ++c) {
       local_edges(r->g, r->s, c, pairs);
       const int32_t n = r->s.comp_ptr[c + 1] - r->s.comp_ptr[c];
+      if (stitch) {   // stitch partners inside the component, in its local numbering
+        part.assign((size_t)n, -1);
+        for (int32_t i = 0; i < n; ++i) {
+          const int32_t q = r->g.partner[r->s.order[r->s.comp_ptr[c] + i]];
+          if (q >= 0 && r->s.comp_of[q] == c) part[(size_t)i] = r->s.local[q];
+        }
+      }
       image_add(r->im, ctx, n, pairs.data(), (int64_t)pairs.size() / 2, r->opt.k,
-                r->opt.node_budget, r->opt.flags);
+                r->opt.node_budget, r->opt.flags, stitch ? part.data() : nullptr);
     }
     r->tier.assign((size_t)nc, 0);
     for (int32_t c : r->im.q_lds) r->tier[c] = 1;
@@ -184,9 +195,14 @@ void HipExecutor::finish(Request* r) {
 void HipExecutor::upload(Request* r) {
   hipStream_t s = ctx->stream;
   uint8_t* base = arena.as<uint8_t>() + r->arena_off;
-  if (!r->im.masks.empty())
+  if (!r->im.masks.empty()) {
     check_hip(hipMemcpyAsync(base + r->off_masks, r->im.masks.data(), r->im.masks.size() * 8,
                              hipMemcpyHostToDevice, s), "serve: upload masks");
+    if (r->im.stitch)   // the partners at the masks' word offsets
+      check_hip(hipMemcpyAsync(part8.as<uint8_t>() + (r->arena_off + r->off_masks) / 8,
+                               r->im.partner8.data(), r->im.masks.size(), hipMemcpyHostToDevice, s),
+                "serve: upload stitch partners");
+  }
   if (!r->im.adj32.empty())
     check_hip(hipMemcpyAsync(base + r->off_adj, r->im.adj32.data(), r->im.adj32.size() * 4,
                              hipMemcpyHostToDevice, s), "serve: upload adjacency");
@@ -207,6 +223,12 @@ void HipExecutor::upload(Request* r) {
 }
 
 static int count_bits_host(int k) { return k < 4 ? 2 : (k < 8 ? 3 : 4); }
+// Launch group of a register-tier component: count width, 8 traced, 16
+// stitch-ordered.
+static int tick_key(const Request* r) {
+  return count_bits_host(r->opt.k) + ((r->opt.flags & MPLD_TRACE_HASH) ? 8 : 0) +
+         ((r->opt.flags & MPLD_STITCH_ORDER) ? 16 : 0);
+}
 
 void HipExecutor::tick(std::vector<Request*>& admitted, std::vector<ServeActive>& active,
                        std::vector<Request*>& finished, double* device_ms) {
@@ -231,10 +253,12 @@ void HipExecutor::tick(std::vector<Request*>& admitted, std::vector<ServeActive>
       const int32_t maxdeg = (int32_t)blk[adj_words];
       if (r->tier[c] == 1) {
         lds_small.push_back({r, c});
-        lds_small_bytes = std::max<int>(lds_small_bytes, (int)lds_bytes_for(hd.n, hd.k, adj_words, maxdeg, false));
+        lds_small_bytes = std::max<int>(lds_small_bytes, (int)lds_bytes_for(hd.n, hd.k, adj_words, maxdeg, false,
+                                                                            (r->opt.flags & MPLD_STITCH_ORDER) != 0));
       } else {
         lds_big.push_back({r, c});
-        lds_big_bytes = std::max<int>(lds_big_bytes, (int)lds_bytes_for(hd.n, hd.k, adj_words, maxdeg, true));
+        lds_big_bytes = std::max<int>(lds_big_bytes, (int)lds_bytes_for(hd.n, hd.k, adj_words, maxdeg, true,
+                                                                        (r->opt.flags & MPLD_STITCH_ORDER) != 0));
         big_words = std::max<int64_t>(big_words, lds_stack_words(hd.n, hd.k, adj_words));
         big_max_n = std::max(big_max_n, hd.n);
       }
@@ -251,11 +275,10 @@ void HipExecutor::tick(std::vector<Request*>& admitted, std::vector<ServeActive>
   for (size_t i = 0; i < lds_big.size(); ++i)
     lds_d.push_back(staged(lds_big[i], (int32_t)(lds_small.size() + i)));
 
-  // register tier: group by (trace, count width) so each launch has one template
+  // register tier: group by (trace, stitch order, count width) so each
+  // launch has one template
   std::stable_sort(active.begin(), active.end(), [](const ServeActive& a, const ServeActive& b) {
-    const int ka = count_bits_host(a.r->opt.k) + ((a.r->opt.flags & MPLD_TRACE_HASH) ? 8 : 0);
-    const int kb = count_bits_host(b.r->opt.k) + ((b.r->opt.flags & MPLD_TRACE_HASH) ? 8 : 0);
-    return ka < kb;
+    return tick_key(a.r) < tick_key(b.r);
   });
   std::vector<int32_t> entries(active.size());
   for (size_t i = 0; i < active.size(); ++i)
@@ -307,20 +330,23 @@ void HipExecutor::tick(std::vector<Request*>& admitted, std::vector<ServeActive>
     check_hip(hipMemcpyAsync(f->desc.p, f->host.p, db, hipMemcpyHostToDevice, lds_stream),
               "serve: upload LDS descriptors");
     check_hip(hipEventRecord(f->start, lds_stream), "serve: event");
+    // per item: 1 traced, 2 stitch-ordered
     std::vector<char> lds_trace(lds_d.size());
     for (size_t i = 0; i < lds_d.size(); ++i) {
       const LdsItem& it = i < lds_small.size() ? lds_small[i] : lds_big[i - lds_small.size()];
-      lds_trace[i] = (it.r->opt.flags & MPLD_TRACE_HASH) ? 1 : 0;
+      lds_trace[i] = (char)(((it.r->opt.flags & MPLD_TRACE_HASH) ? 1 : 0) |
+                            ((it.r->opt.flags & MPLD_STITCH_ORDER) ? 2 : 0));
     }
     auto lds_launch = [&](size_t first, size_t count, bool big, int bytes) {
       size_t a = first;
-      while (a < first + count) {   // one launch per run of equal trace flag
+      while (a < first + count) {   // one launch per run of equal trace and stitch flags
         size_t b = a;
         while (b < first + count && lds_trace[b] == lds_trace[a]) ++b;
         const int per_cu = std::max(1, std::min(32, (160 * 1024) / std::max(bytes, 1)));
         const int grid = std::max(1, std::min((int)(b - a), ctx->num_cus * per_cu));
         // the big tier's stack areas: one per workgroup, grid <= count
-        check_hip(launch_lds_batched(lds_trace[a] != 0, big, false, big ? lds_big_waves(big_max_n) : 1, grid,
+        check_hip(launch_lds_batched((lds_trace[a] & 1) != 0, big, (lds_trace[a] & 2) != 0,
+                                     big ? lds_big_waves(big_max_n) : 1, grid,
                                      bytes, f->desc.as<DevDesc>() + a, arena.as<uint32_t>(),
                                      (int32_t)(b - a), counter.as<int32_t>() + 1,
                                      big ? f->gstack.as<uint64_t>() : nullptr, (uint64_t)big_words,
@@ -352,16 +378,15 @@ void HipExecutor::tick(std::vector<Request*>& admitted, std::vector<ServeActive>
   for (int32_t a = 0; a < len;) {
     int32_t b = a;
     const Request* ra = active[a].r;
-    const int key = count_bits_host(ra->opt.k) + ((ra->opt.flags & MPLD_TRACE_HASH) ? 8 : 0);
-    while (b < len && count_bits_host(active[b].r->opt.k) +
-                              ((active[b].r->opt.flags & MPLD_TRACE_HASH) ? 8 : 0) == key)
-      ++b;
+    const int key = tick_key(ra);
+    while (b < len && tick_key(active[b].r) == key) ++b;
     const int32_t cnt = b - a;
     const int grid = std::max(1, std::min((cnt + 3) / 4, ctx->num_cus * ctx->reg_blocks_per_cu));
-    check_hip(launch_reg_tick(key >= 8, ra->opt.k, grid, list.as<int32_t>() + a, cnt,
-                              counter.as<int32_t>(), slot_desc.as<DevDesc>(), slot_state.as<uint8_t>(),
-                              slot_rec.as<DevRecord>(), arena64, arena8, slice,
-                              tick_out.as<DevRecord>() + a, s),
+    check_hip(launch_reg_tick((key & 8) != 0, (key & 16) != 0, ra->opt.k, grid,
+                              list.as<int32_t>() + a, cnt, counter.as<int32_t>(),
+                              slot_desc.as<DevDesc>(), slot_state.as<uint8_t>(),
+                              slot_rec.as<DevRecord>(), arena64, arena8, part8.as<uint8_t>(),
+                              slice, tick_out.as<DevRecord>() + a, s),
               "serve: tick launch");
     a = b;
   }
@@ -459,8 +484,6 @@ void check_opts(const mpld_options* o) {
   if (o->node_budget < 1) fail(MPLD_E_INVALID, "node_budget must be >= 1");
   if (o->flags & (MPLD_PLAIN | MPLD_FORCE_WAVE | MPLD_FORCE_LDS | MPLD_FORCE_GLOBAL | MPLD_FORCE_DEVICE))
     fail(MPLD_E_INVALID, "serving takes no PLAIN or FORCE_* flags");
-  if (o->flags & MPLD_STITCH_ORDER)
-    fail(MPLD_E_UNSUPPORTED, "serving keeps the ascending row order (MPLD_STITCH_ORDER)");
   if (o->flags & MPLD_MINIMIZE)
     fail(MPLD_E_UNSUPPORTED, "serving does not run the Eq. 1 minimisation (MPLD_MINIMIZE)");
 }
@@ -493,6 +516,7 @@ int32_t mpld_server_create(mpld_context* ctx, const mpld_server_options* opt, mp
     HipExecutor* x = &s->exec;
     try {
       x->arena.alloc(ctx, (size_t)o.arena_bytes);
+      x->part8.alloc(ctx, (size_t)o.arena_bytes / 8 + 8);
       x->slot_desc.alloc(ctx, sizeof(DevDesc) * (size_t)x->max_slots);
       x->slot_rec.alloc(ctx, sizeof(DevRecord) * (size_t)x->max_slots);
       x->slot_state.alloc(ctx, kRegStateBytes * (size_t)x->max_slots);

@@ -292,3 +292,68 @@ def test_conflict_marking_served(ctx):
             for f in ("status", "nodes", "trace_hash", "conflicts", "stitches"):
                 assert np.array_equal(got.components[f], ref.comps[f]), f
             assert (got.conflicts, got.uncolored) == (ref.conflicts, ref.uncolored)
+
+
+def test_stitch_order_served(ctx):
+    """MPLD_STITCH_ORDER in serving: stitch-ordered and plain requests in one
+    server (separate tick launches), register-tier components resumed across
+    ticks with their partner registers in the saved state (slice 3), and
+    LDS-tier components with stitch pairs in the flights; every result
+    equals the oracle's stitch-ordered decomposition."""
+    import paper_2303_14335_amd as mp
+    from algx_literal import random_graph
+    STITCH = 1 << 11
+    rng = np.random.default_rng(13)
+
+    def stitched(count, n_lo, n_hi, k):
+        ce, se, base = [], [], 0
+        for _ in range(count):
+            n = int(rng.integers(n_lo, n_hi + 1))
+            e = random_graph(rng, n, min(0.95, float(rng.uniform(0.5, 1.4)) * 2.0 * k / n))
+            adj = {tuple(x) for x in e} | {(b, a) for a, b in e}
+            used = set()
+            for _ in range(n):
+                a, b = (int(x) for x in rng.integers(0, n, 2))
+                if a != b and a not in used and b not in used and (a, b) not in adj:
+                    used |= {a, b}
+                    se.append((base + a, base + b))
+            ce += [(base + a, base + b) for a, b in e]
+            base += n
+        return mp.Graph(base, np.array(ce, np.int32).reshape(-1, 2),
+                        np.array(se, np.int32).reshape(-1, 2))
+
+    graphs = [stitched(40, 4, 64, 3), stitched(6, 65, 300, 3), stitched(30, 4, 64, 4)]
+    ks = [3, 3, 4]
+    layouts = requests(6, seed=31, n_max=6000, split=120)
+    for slice_nodes in (3, 4096):
+        say("serve with the stitch-aware order, slice", slice_nodes)
+        srv = mp.Server(ctx, slice_nodes=slice_nodes)
+        tg = [srv.submit(g, k, 20000, STITCH | (TRACE if i % 2 else 0))
+              for i, (g, k) in enumerate(zip(graphs, ks))]
+        tp = [srv.submit(g, k, 20000, TRACE) for g, k in zip(graphs, ks)]   # plain order
+        tl = [srv.submit_layout(r["rects"], r["dmin"], r["split"], 3, 20000,
+                                SIMPLIFY | STITCH | TRACE) for r in layouts]
+        got_g = [srv.wait(t, 60_000_000) for t in tg]
+        got_p = [srv.wait(t, 60_000_000) for t in tp]
+        got_l = [srv.wait(t, 60_000_000) for t in tl]
+        srv.close()
+        for i, (g, k, got) in enumerate(zip(graphs, ks, got_g)):
+            ref = oracle.decompose(oracle.Graph(g.num_nodes, g.ce, g.se), k, 20000,
+                                   simplify=False, stitch=True)
+            assert np.array_equal(got.colors, ref.colors)
+            fields = ["status", "nodes", "depth_at_stop", "stitches"] + (["trace_hash"] if i % 2 else [])
+            for f in fields:
+                assert np.array_equal(got.components[f], ref.comps[f]), (f, i)
+            assert got.stitches == ref.stitches
+        for g, k, got in zip(graphs, ks, got_p):
+            ref = oracle.decompose(oracle.Graph(g.num_nodes, g.ce, g.se), k, 20000, simplify=False)
+            assert np.array_equal(got.colors, ref.colors)
+            for f in ("status", "nodes", "trace_hash", "stitches"):
+                assert np.array_equal(got.components[f], ref.comps[f]), f
+        for r, got in zip(layouts, got_l):
+            ref = oracle.decompose(oracle.build_graph(r["rects"], r["dmin"], r["split"]), 3, 20000,
+                                   stitch=True)
+            assert np.array_equal(got.colors, ref.colors)
+            for f in ("status", "nodes", "trace_hash", "stitches", "depth_at_stop"):
+                assert np.array_equal(got.components[f], ref.comps[f]), f
+            assert (got.stitches, got.uncolored) == (ref.stitches, ref.uncolored)

@@ -163,18 +163,13 @@ def test_stitch_config3_big_tier(ctx):
     compare(mp.mpld_decompose(ctx, g, w.k, w.budget, SIMPLIFY | STITCH | TRACE), ref)
 
 
-def test_stitch_rejects_device_tier_and_server(ctx):
+def test_stitch_rejects_device_tier(ctx):
     import paper_2303_14335_amd as mp
-    say("stitch order rejected on the device-wide tier and by a server")
+    say("stitch order rejected on the device-wide tier")
     small = mp.Graph(3, np.array([[0, 1]], np.int32), np.zeros((0, 2), np.int32))
     with pytest.raises(mp.MpldError) as e:
         mp.mpld_decompose(ctx, small, 3, 100, STITCH | FORCE_DEVICE)
     assert e.value.code == -7   # MPLD_E_UNSUPPORTED
-    srv = mp.Server(ctx)
-    with pytest.raises(mp.MpldError) as e:
-        srv.submit(small, 3, 100, SIMPLIFY | STITCH)
-    assert e.value.code == -7   # MPLD_E_UNSUPPORTED
-    srv.close()
 
 
 def heavy_stitch_layout(rng, k, count, deg):
