@@ -191,9 +191,11 @@ enum {
                                   status, nodes, hash and depth stay the
                                   search's; mpld_comp_record.min_nodes tells
                                   whether least cost was proven.  Decompose,
-                                  batches and mpld_solve_components; not with
-                                  a forced LDS, global or device tier
-                                  (MPLD_E_UNSUPPORTED); a server rejects it. */
+                                  batches, mpld_solve_components and servers
+                                  (a served register-tier component is
+                                  minimised by the tick that ends its
+                                  search); not with a forced LDS, global or
+                                  device tier (MPLD_E_UNSUPPORTED). */
 };
 
 typedef struct { int32_t x0, y0, x1, y1; } mpld_rect;  /* nm, closed box */

@@ -137,6 +137,12 @@ _RANK = {"Server": 0, "Batch": 1, "Context": 2}
 
 def _register(obj) -> None:
     _LIVE[_RANK[type(obj).__name__]].add(obj)
+    ctx = getattr(obj, "ctx", None)
+    if ctx is not None:   # a server or batch: its context closes it first
+        children = getattr(ctx, "_children", None)
+        if children is None:
+            children = ctx._children = weakref.WeakSet()
+        children.add(obj)
 
 
 def _close_all() -> None:
@@ -204,6 +210,14 @@ class Context:
         _register(self)
 
     def close(self):
+        # servers and batches made on this context go first: they use its
+        # stream and memory until they are destroyed
+        for rank in (0, 1):
+            for child in [c for c in list(getattr(self, "_children", ())) if _RANK[type(c).__name__] == rank]:
+                try:
+                    child.close()
+                except Exception:
+                    pass
         if self.handle:
             _lib.mpld_context_destroy(self.handle)
             self.handle = ctypes.c_void_p()
@@ -444,17 +458,18 @@ class Server:
         _register(self)
 
     def submit_layout(self, rects: np.ndarray, dmin_nm: int, split_len_nm: int, k: int,
-                      budget: int, flags: int = MPLD_SIMPLIFY) -> int:
+                      budget: int, flags: int = MPLD_SIMPLIFY, min_budget: int = 0) -> int:
         r = np.ascontiguousarray(rects, dtype=np.int32).reshape(-1, 4)
-        opt = options(k, budget, flags)
+        opt = options(k, budget, flags, min_budget)
         t = ctypes.c_uint64()
         _check(_lib.mpld_server_submit_layout(self.handle, r.ctypes.data, len(r), dmin_nm,
                                               split_len_nm, ctypes.byref(opt), ctypes.byref(t)),
                "mpld_server_submit_layout")
         return t.value
 
-    def submit(self, g: Graph, k: int, budget: int, flags: int = MPLD_SIMPLIFY) -> int:
-        opt = options(k, budget, flags)
+    def submit(self, g: Graph, k: int, budget: int, flags: int = MPLD_SIMPLIFY,
+               min_budget: int = 0) -> int:
+        opt = options(k, budget, flags, min_budget)
         view = g.view()
         t = ctypes.c_uint64()
         _check(_lib.mpld_server_submit(self.handle, ctypes.byref(view), ctypes.byref(opt),

@@ -50,8 +50,8 @@ int reg_batched_blocks_per_cu(bool trace);
 hipError_t launch_reg_tick(bool trace, bool stitch, int k, int grid, const int32_t* list,
                            int32_t len, int32_t* counter, const DevDesc* slot_desc,
                            uint8_t* slot_state, DevRecord* slot_rec, const uint64_t* arena64,
-                           int8_t* arena8, const uint8_t* part8, uint64_t slice,
-                           DevRecord* tick_out, hipStream_t s);
+                           int8_t* arena8, const uint8_t* part8, const uint32_t* slot_minb,
+                           int32_t* slot_min, uint64_t slice, DevRecord* tick_out, hipStream_t s);
 // stitch: the stitch-aware row order (the CSR blocks end with the partners).
 hipError_t launch_lds_batched(bool trace, bool big, bool stitch, int waves, int grid,
                               int lds_bytes, const DevDesc* descs, const uint32_t* adj32,

@@ -32,6 +32,7 @@
 #include <type_traits>
 
 #include "device_types.h"
+#include "min_core.h"
 #include "mpld.h"
 #include "reg_items.h"
 #include "trace.h"
@@ -668,7 +669,9 @@ __global__ __launch_bounds__(64) void mark_reg_kernel(const RegItems items, int3
 // Serving tick: every listed component advances by at most `slice` search
 // nodes from its saved state (entries with bit 31 set start fresh; bit 30:
 // a component left without a solution is then colored by the conflict
-// marking).  A finished search writes its colors and record; a paused one
+// marking; bit 29: the finished component's colors are then minimised for
+// Eq. 1 with a budget of slot_minb[slot] nodes, the count going to
+// slot_min[slot] as for the batched minimisation).  A finished search writes its colors and record; a paused one
 // saves its state.  tick_out[i] receives the record of list entry i (status -1 while
 // the search is still running).  Work distribution as in the batched kernel.
 // STITCH: the stitch-aware row order; part8[w] is the stitch partner (local
@@ -679,12 +682,13 @@ __global__ __launch_bounds__(256) void reg_tick_kernel(
     const int32_t* __restrict__ list, int32_t len, int32_t* __restrict__ counter,
     const DevDesc* __restrict__ slot_desc, uint8_t* slot_state, DevRecord* __restrict__ slot_rec,
     const uint64_t* __restrict__ arena64, int8_t* __restrict__ arena8,
-    const uint8_t* __restrict__ part8, uint64_t slice, DevRecord* __restrict__ tick_out) {
+    const uint8_t* __restrict__ part8, const uint32_t* __restrict__ slot_minb,
+    int32_t* __restrict__ slot_min, uint64_t slice, DevRecord* __restrict__ tick_out) {
   const int32_t gw = (int32_t)gridDim.x * 4;
   int32_t item = (int32_t)uniform(xcd_block() * 4u + (threadIdx.x >> 6));
   while (item < len) {
     const uint32_t entry = uniform((uint32_t)list[item]);
-    const int32_t slot = (int32_t)(entry & 0x3fffffffu);
+    const int32_t slot = (int32_t)(entry & 0x1fffffffu);
     const DevDesc d = slot_desc[slot];
     const uint32_t lane = __lane_id();
     const uint64_t nb = lane < (uint32_t)d.n ? arena64[d.nbr_off + lane] : 0ull;
@@ -705,6 +709,12 @@ __global__ __launch_bounds__(256) void reg_tick_kernel(
       // wave's own stores, so they follow reg_finish's)
       if (((entry >> 30) & 1u) && s.status != MPLD_FEASIBLE)
         mark_core<K>((uint32_t)d.n, nb, arena8 + d.out_off);
+      if ((entry >> 29) & 1u) {
+        // the minimisation reads the colors this wave just stored
+        __builtin_amdgcn_s_waitcnt(0);
+        const int32_t mr = minimize_core<K>(d, nb, part8, arena8, slot_minb[slot]);
+        slot_min[slot] = mr;   // the same value from every lane
+      }
     } else {
       reg_save<K, STITCH>(s, base);
     }
@@ -1000,15 +1010,15 @@ hipError_t launch_reg_single(bool trace, int k, RegItems items, int32_t item,
 hipError_t launch_reg_tick(bool trace, bool stitch, int k, int grid, const int32_t* list,
                            int32_t len, int32_t* counter, const DevDesc* slot_desc,
                            uint8_t* slot_state, DevRecord* slot_rec, const uint64_t* arena64,
-                           int8_t* arena8, const uint8_t* part8, uint64_t slice,
-                           DevRecord* tick_out, hipStream_t s) {
+                           int8_t* arena8, const uint8_t* part8, const uint32_t* slot_minb,
+                           int32_t* slot_min, uint64_t slice, DevRecord* tick_out, hipStream_t s) {
   if (len <= 0) return hipSuccess;
   with_planes(k, [&](auto kp) {
     constexpr int K = decltype(kp)::value;
     auto go = [&](auto t, auto st) {
       hipLaunchKernelGGL((reg_tick_kernel<decltype(t)::value, K, decltype(st)::value>), dim3(grid),
                          dim3(256), 0, s, list, len, counter, slot_desc, slot_state, slot_rec,
-                         arena64, arena8, part8, slice, tick_out);
+                         arena64, arena8, part8, slot_minb, slot_min, slice, tick_out);
     };
     if (trace && stitch) go(std::true_type{}, std::true_type{});
     else if (trace) go(std::true_type{}, std::false_type{});

@@ -44,6 +44,8 @@ class HipExecutor : public ServeExecutor {
   // stitch partner (local id, 0xff none) of the node whose neighbour mask
   // is arena word w, at byte w: written for stitch-ordered requests
   DevBuf part8;
+  // MPLD_MINIMIZE: per slot the minimisation's node budget and its result
+  DevBuf slot_minb, slot_min;
   int32_t max_slots = 0;
   // device layout-graph builders for large layout requests (own stream
   // each), taken in turn so that concurrent large requests do not queue on
@@ -126,11 +128,12 @@ void HipExecutor::front_end(Request* r) {
     if (!split_done) r->s = simplify_and_split(r->g, r->opt.k, r->opt.flags & MPLD_SIMPLIFY);
     const int32_t nc = (int32_t)r->s.comp_ptr.size() - 1;
     const bool stitch = r->opt.flags & MPLD_STITCH_ORDER;
+    const bool partners = stitch || (r->opt.flags & MPLD_MINIMIZE);
     std::vector<int32_t> pairs, part;
     for (int32_t c = 0; c < nc; ++c) {
       local_edges(r->g, r->s, c, pairs);
       const int32_t n = r->s.comp_ptr[c + 1] - r->s.comp_ptr[c];
-      if (stitch) {   // stitch partners inside the component, in its local numbering
+      if (partners) {   // stitch partners inside the component, in its local numbering
         part.assign((size_t)n, -1);
         for (int32_t i = 0; i < n; ++i) {
           const int32_t q = r->g.partner[r->s.order[r->s.comp_ptr[c] + i]];
@@ -138,7 +141,7 @@ void HipExecutor::front_end(Request* r) {
         }
       }
       image_add(r->im, ctx, n, pairs.data(), (int64_t)pairs.size() / 2, r->opt.k,
-                r->opt.node_budget, r->opt.flags, stitch ? part.data() : nullptr);
+                r->opt.node_budget, r->opt.flags, partners ? part.data() : nullptr);
     }
     r->tier.assign((size_t)nc, 0);
     for (int32_t c : r->im.q_lds) r->tier[c] = 1;
@@ -164,7 +167,14 @@ void HipExecutor::finish(Request* r) {
   if (r->error == MPLD_OK) {
     try {
       r->result.reset(new mpld_result());
-      assemble_result(r->g, r->s, r->im, r->opt, r->recs, r->lcol, r->result.get());
+      const bool minimize = r->opt.flags & MPLD_MINIMIZE;
+      if (minimize) {   // only register-tier slots hold a minimisation count
+        r->mins.resize(r->recs.size(), 0);
+        for (size_t c = 0; c < r->mins.size(); ++c)
+          if (r->tier[c] != 0) r->mins[c] = 0;
+      }
+      assemble_result(r->g, r->s, r->im, r->opt, r->recs, r->lcol, r->result.get(),
+                      minimize ? &r->mins : nullptr);
       const auto now = ServeClock::now();
       r->result->queue_us =
           std::chrono::duration<double, std::micro>(r->t_admit - r->t_submit).count();
@@ -187,6 +197,8 @@ void HipExecutor::finish(Request* r) {
   std::vector<int32_t>().swap(r->se);
   std::vector<int8_t>().swap(r->lcol);
   std::vector<DevDesc>().swap(r->ddesc);
+  std::vector<uint32_t>().swap(r->minb);
+  std::vector<int32_t>().swap(r->mins);
 }
 
 // Enqueues the copy of an admitted request's image to its arena range and
@@ -198,7 +210,7 @@ void HipExecutor::upload(Request* r) {
   if (!r->im.masks.empty()) {
     check_hip(hipMemcpyAsync(base + r->off_masks, r->im.masks.data(), r->im.masks.size() * 8,
                              hipMemcpyHostToDevice, s), "serve: upload masks");
-    if (r->im.stitch)   // the partners at the masks' word offsets
+    if (r->im.stitch || r->im.minimize)   // the partners at the masks' word offsets
       check_hip(hipMemcpyAsync(part8.as<uint8_t>() + (r->arena_off + r->off_masks) / 8,
                                r->im.partner8.data(), r->im.masks.size(), hipMemcpyHostToDevice, s),
                 "serve: upload stitch partners");
@@ -220,6 +232,12 @@ void HipExecutor::upload(Request* r) {
   check_hip(hipMemcpyAsync(slot_desc.as<DevDesc>() + r->slot_base, r->ddesc.data(),
                            sizeof(DevDesc) * (size_t)nc, hipMemcpyHostToDevice, s),
             "serve: upload descriptors");
+  if (r->opt.flags & MPLD_MINIMIZE) {
+    r->minb.assign((size_t)nc, r->opt.min_budget > 0 ? (uint32_t)r->opt.min_budget : 10000u);
+    check_hip(hipMemcpyAsync(slot_minb.as<uint32_t>() + r->slot_base, r->minb.data(),
+                             sizeof(uint32_t) * (size_t)nc, hipMemcpyHostToDevice, s),
+              "serve: upload minimisation budgets");
+  }
 }
 
 static int count_bits_host(int k) { return k < 4 ? 2 : (k < 8 ? 3 : 4); }
@@ -283,7 +301,8 @@ void HipExecutor::tick(std::vector<Request*>& admitted, std::vector<ServeActive>
   std::vector<int32_t> entries(active.size());
   for (size_t i = 0; i < active.size(); ++i)
     entries[i] = active[i].slot | (active[i].fresh ? (int32_t)0x80000000u : 0) |
-                 ((active[i].r->opt.flags & MPLD_MARK_CONFLICTS) ? 0x40000000 : 0);
+                 ((active[i].r->opt.flags & (MPLD_MARK_CONFLICTS | MPLD_MINIMIZE)) ? 0x40000000 : 0) |
+                 ((active[i].r->opt.flags & MPLD_MINIMIZE) ? 0x20000000 : 0);
   const int32_t len = (int32_t)entries.size();
   const int32_t nl = (int32_t)lds_d.size();
   if (len)
@@ -313,7 +332,7 @@ void HipExecutor::tick(std::vector<Request*>& admitted, std::vector<ServeActive>
     std::vector<DevDesc> md;
     int64_t mark_bytes = 0;
     for (int32_t i = 0; i < nl; ++i)
-      if (f->items[(size_t)i].first->opt.flags & MPLD_MARK_CONFLICTS) {
+      if (f->items[(size_t)i].first->opt.flags & (MPLD_MARK_CONFLICTS | MPLD_MINIMIZE)) {
         md.push_back(lds_d[(size_t)i]);
         mark_bytes = std::max(mark_bytes, mark_lds_bytes(lds_d[(size_t)i].n, lds_d[(size_t)i].k));
       }
@@ -386,7 +405,8 @@ void HipExecutor::tick(std::vector<Request*>& admitted, std::vector<ServeActive>
                               list.as<int32_t>() + a, cnt, counter.as<int32_t>(),
                               slot_desc.as<DevDesc>(), slot_state.as<uint8_t>(),
                               slot_rec.as<DevRecord>(), arena64, arena8, part8.as<uint8_t>(),
-                              slice, tick_out.as<DevRecord>() + a, s),
+                              slot_minb.as<uint32_t>(), slot_min.as<int32_t>(), slice,
+                              tick_out.as<DevRecord>() + a, s),
               "serve: tick launch");
     a = b;
   }
@@ -443,6 +463,12 @@ void HipExecutor::tick(std::vector<Request*>& admitted, std::vector<ServeActive>
       check_hip(hipMemcpyAsync(r->lcol.data(), arena.as<uint8_t>() + r->arena_off + r->off_colors,
                                r->lcol.size(), hipMemcpyDeviceToHost, s),
                 "serve: download colors");
+    if ((r->opt.flags & MPLD_MINIMIZE) && !r->recs.empty()) {
+      r->mins.assign(r->recs.size(), 0);
+      check_hip(hipMemcpyAsync(r->mins.data(), slot_min.as<int32_t>() + r->slot_base,
+                               sizeof(int32_t) * r->mins.size(), hipMemcpyDeviceToHost, s),
+                "serve: download minimisation counts");
+    }
   }
   if (!finished.empty()) check_hip(hipStreamSynchronize(s), "serve: colors");
 }
@@ -482,10 +508,9 @@ void check_opts(const mpld_options* o) {
   if (!o || o->struct_size != sizeof(mpld_options)) fail(MPLD_E_INVALID, "bad options");
   if (o->k < 2 || o->k > MPLD_MAX_K) fail(MPLD_E_INVALID, "k must be in [2, 8]");
   if (o->node_budget < 1) fail(MPLD_E_INVALID, "node_budget must be >= 1");
+  if (o->min_budget < 0) fail(MPLD_E_INVALID, "min_budget must be >= 0 (0 = 10000)");
   if (o->flags & (MPLD_PLAIN | MPLD_FORCE_WAVE | MPLD_FORCE_LDS | MPLD_FORCE_GLOBAL | MPLD_FORCE_DEVICE))
     fail(MPLD_E_INVALID, "serving takes no PLAIN or FORCE_* flags");
-  if (o->flags & MPLD_MINIMIZE)
-    fail(MPLD_E_UNSUPPORTED, "serving does not run the Eq. 1 minimisation (MPLD_MINIMIZE)");
 }
 
 
@@ -504,6 +529,7 @@ int32_t mpld_server_create(mpld_context* ctx, const mpld_server_options* opt, mp
       o = *opt;
     }
     if (o.max_components <= 0) o.max_components = 65536;
+    if (o.max_components > (1 << 28)) fail(MPLD_E_INVALID, "max_components is at most 2^28");
     if (o.arena_bytes <= 0) o.arena_bytes = 256ll << 20;
     if (o.arena_bytes > (2ll << 30) - 256) fail(MPLD_E_INVALID, "arena_bytes is at most 2 GiB");
     if (o.slice_nodes <= 0) o.slice_nodes = 4096;
@@ -517,6 +543,8 @@ int32_t mpld_server_create(mpld_context* ctx, const mpld_server_options* opt, mp
     try {
       x->arena.alloc(ctx, (size_t)o.arena_bytes);
       x->part8.alloc(ctx, (size_t)o.arena_bytes / 8 + 8);
+      x->slot_minb.alloc(ctx, sizeof(uint32_t) * (size_t)x->max_slots);
+      x->slot_min.alloc(ctx, sizeof(int32_t) * (size_t)x->max_slots);
       x->slot_desc.alloc(ctx, sizeof(DevDesc) * (size_t)x->max_slots);
       x->slot_rec.alloc(ctx, sizeof(DevRecord) * (size_t)x->max_slots);
       x->slot_state.alloc(ctx, kRegStateBytes * (size_t)x->max_slots);

@@ -53,6 +53,8 @@ struct Request {
   std::vector<DevRecord> recs;   // one per component
   std::vector<int8_t> lcol;
   std::vector<DevDesc> ddesc;    // slot descriptors as uploaded (kept until the tick syncs)
+  std::vector<uint32_t> minb;    // MPLD_MINIMIZE: per slot node budget (kept as ddesc)
+  std::vector<int32_t> mins;     // MPLD_MINIMIZE: per component minimisation nodes
   // completion
   int32_t error = MPLD_OK;
   std::string error_text;

@@ -1,7 +1,8 @@
 """CPU test of the binding's teardown order: servers, then batches, then
 contexts still open at exit are closed by the exit hook while torch is
-alive, and destructors do nothing during interpreter finalisation (where a
-library call could reach a torn-down torch allocator)."""
+alive; closing a context first closes the servers and batches made on it;
+destructors do nothing during interpreter finalisation (where a library
+call could reach a torn-down torch allocator)."""
 import paper_2303_14335_amd as mp
 
 
@@ -52,3 +53,27 @@ def test_destructor_is_inert_during_finalisation(monkeypatch):
     monkeypatch.setattr(mp, "_finalizing", lambda: False)
     c.__del__()
     assert fake.calls == [("context", 7)]
+
+
+def _fake_on(cls, value, ctx):
+    import ctypes
+    obj = object.__new__(cls)
+    obj.handle = ctypes.c_void_p(value)
+    obj.ctx = ctx
+    mp._register(obj)
+    return obj
+
+
+def test_context_close_closes_its_servers_and_batches_first(monkeypatch):
+    fake = _FakeLib()
+    monkeypatch.setattr(mp, "_lib", fake)
+    c = _fake(mp.Context, 11)
+    other = _fake(mp.Context, 12)
+    b = _fake_on(mp.Batch, 13, c)
+    s = _fake_on(mp.Server, 14, c)
+    kept = _fake_on(mp.Server, 15, other)
+    c.close()
+    assert fake.calls == [("server", 14), ("batch", 13), ("context", 11)], fake.calls
+    mp._close_all()   # only the other context's objects are left
+    assert fake.calls[3:] == [("server", 15), ("context", 12)], fake.calls
+    del c, other, b, s, kept

@@ -127,7 +127,6 @@ def test_unsupported_and_invalid(ctx):
     assert e.value.code == -1
     srv = mp.Server(ctx)
     with pytest.raises(mp.MpldError) as e:
-        t = srv.submit(g, 3, 100, MINIMIZE)
-        srv.wait(t, 60_000_000)
-    assert e.value.code == -7
+        srv.submit(g, 3, 100, MINIMIZE, min_budget=-1)
+    assert e.value.code == -1
     srv.close()

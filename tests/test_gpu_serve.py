@@ -357,3 +357,66 @@ def test_stitch_order_served(ctx):
             for f in ("status", "nodes", "trace_hash", "stitches", "depth_at_stop"):
                 assert np.array_equal(got.components[f], ref.comps[f]), f
             assert (got.stitches, got.uncolored) == (ref.stitches, ref.uncolored)
+
+
+def test_minimize_served(ctx):
+    """MPLD_MINIMIZE in serving: a register-tier component is marked and
+    minimised for Eq. 1 by the wave that ends its search in a tick (its
+    budget and node count per slot), LDS-tier components keep the marking's
+    colors; with and without the stitch-aware order, at slices 3 and 4096,
+    mixed with plain requests; every result equals the one-shot
+    decomposition's and the oracle's (colors, node counts, minimisation
+    counts, conflicts, stitches)."""
+    import paper_2303_14335_amd as mp
+    from algx_literal import random_graph
+    MINIMIZE, STITCH = 1 << 13, 1 << 11
+    rng = np.random.default_rng(17)
+
+    def stitched(count, n_lo, n_hi, k, dens):
+        ce, se, base = [], [], 0
+        for _ in range(count):
+            n = int(rng.integers(n_lo, n_hi + 1))
+            e = random_graph(rng, n, min(0.95, float(rng.uniform(0.8, 1.6)) * dens * k / n))
+            adj = {tuple(x) for x in e} | {(b, a) for a, b in e}
+            used = set()
+            for _ in range(n):
+                a, b = (int(x) for x in rng.integers(0, n, 2))
+                if a != b and a not in used and b not in used and (a, b) not in adj:
+                    used |= {a, b}
+                    se.append((base + a, base + b))
+            ce += [(base + a, base + b) for a, b in e]
+            base += n
+        return mp.Graph(base, np.array(ce, np.int32).reshape(-1, 2),
+                        np.array(se, np.int32).reshape(-1, 2))
+
+    cases = [(stitched(40, 3, 40, 3, 2.0), 3, 0, 300), (stitched(20, 3, 64, 4, 2.2), 4, STITCH, 20000),
+             (stitched(4, 65, 200, 3, 2.2), 3, 0, 50)]
+    layouts = requests(4, seed=51, n_max=5000, dmin=100, split=120)
+    for slice_nodes in (3, 4096):
+        say("serve with the Eq. 1 minimisation, slice", slice_nodes)
+        srv = mp.Server(ctx, slice_nodes=slice_nodes)
+        tg = [srv.submit(g, k, 20000, MINIMIZE | extra, min_budget=mb) for g, k, extra, mb in cases]
+        tp = [srv.submit(g, k, 20000, 0) for g, k, _, _ in cases]
+        tl = [srv.submit_layout(r["rects"], r["dmin"], r["split"], 3, 20000,
+                                SIMPLIFY | MINIMIZE | TRACE) for r in layouts]
+        got_g = [srv.wait(t, 60_000_000) for t in tg]
+        got_p = [srv.wait(t, 60_000_000) for t in tp]
+        got_l = [srv.wait(t, 60_000_000) for t in tl]
+        srv.close()
+        for (g, k, extra, mb), got in zip(cases, got_g):
+            same(got, mp.mpld_decompose(ctx, g, k, 20000, MINIMIZE | extra, min_budget=mb))
+            ref = oracle.decompose(oracle.Graph(g.num_nodes, g.ce, g.se), k, 20000, simplify=False,
+                                   minimize=True, min_budget=mb, stitch=bool(extra & STITCH))
+            assert np.array_equal(got.colors, ref.colors)
+            for f in ("status", "nodes", "min_nodes", "conflicts", "stitches"):
+                assert np.array_equal(got.components[f], ref.comps[f]), f
+            assert (got.conflicts, got.stitches, got.uncolored) == (ref.conflicts, ref.stitches,
+                                                                     ref.uncolored)
+        for (g, k, _, _), got in zip(cases, got_p):
+            same(got, mp.mpld_decompose(ctx, g, k, 20000, 0))
+        for r, got in zip(layouts, got_l):
+            ref = oracle.decompose(oracle.build_graph(r["rects"], r["dmin"], r["split"]), 3, 20000,
+                                   minimize=True)
+            assert np.array_equal(got.colors, ref.colors)
+            for f in ("status", "nodes", "trace_hash", "min_nodes", "conflicts", "stitches"):
+                assert np.array_equal(got.components[f], ref.comps[f]), f
