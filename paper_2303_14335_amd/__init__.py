@@ -223,10 +223,11 @@ class Context:
             self.handle = ctypes.c_void_p()
 
     def __del__(self):
-        if _finalizing():
-            return
+        # at exit the module's globals may already be cleared (a lookup then
+        # fails): the exit hook has closed every open object by then
         try:
-            self.close()
+            if self.handle and not _finalizing():
+                self.close()
         except Exception:
             pass
 
@@ -343,10 +344,11 @@ class Batch:
             self.handle = ctypes.c_void_p()
 
     def __del__(self):
-        if _finalizing():
-            return
+        # at exit the module's globals may already be cleared (a lookup then
+        # fails): the exit hook has closed every open object by then
         try:
-            self.close()
+            if self.handle and not _finalizing():
+                self.close()
         except Exception:
             pass
 
@@ -503,10 +505,11 @@ class Server:
             self.handle = ctypes.c_void_p()
 
     def __del__(self):
-        if _finalizing():
-            return
+        # at exit the module's globals may already be cleared (a lookup then
+        # fails): the exit hook has closed every open object by then
         try:
-            self.close()
+            if self.handle and not _finalizing():
+                self.close()
         except Exception:
             pass
 

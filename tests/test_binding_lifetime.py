@@ -77,3 +77,19 @@ def test_context_close_closes_its_servers_and_batches_first(monkeypatch):
     mp._close_all()   # only the other context's objects are left
     assert fake.calls[3:] == [("server", 15), ("context", 12)], fake.calls
     del c, other, b, s, kept
+
+
+def test_del_after_module_globals_cleared(monkeypatch):
+    """At exit the module's globals can be cleared before the last objects
+    are collected; their destructors must then do nothing, quietly."""
+    fake = _FakeLib()
+    monkeypatch.setattr(mp, "_lib", fake)
+    c = _fake(mp.Context, 21)
+    b = _fake_on(mp.Batch, 22, c)
+    monkeypatch.setattr(mp, "_finalizing", None)
+    b.__del__()
+    c.__del__()
+    assert fake.calls == []
+    monkeypatch.setattr(mp, "_finalizing", lambda: False)
+    c.close()
+    assert fake.calls == [("batch", 22), ("context", 21)]
