@@ -335,6 +335,10 @@ PROBES = [
     ("register_k4_n64", 64, 4, 8.4, 0, 200000, "MPLD_FORCE_WAVE"),
     ("lds_small_k3_n1000", 1000, 3, 4.6, 0, 20000, "MPLD_FORCE_LDS"),
     ("lds_k3_n10000", 10000, 3, 4.6, 0, 20000, "MPLD_FORCE_GLOBAL"),
+    # the same on the big tier's workgroup layout (lists in global memory)
+    ("lds_k3_n10000_workgroup", 10000, 3, 4.6, 0, 20000, "MPLD_FORCE_GLOBAL"),
+    ("lds_k3_n4000", 4000, 3, 4.6, 0, 20000, "MPLD_FORCE_GLOBAL"),
+    ("lds_k3_n4000_workgroup", 4000, 3, 4.6, 0, 20000, "MPLD_FORCE_GLOBAL"),
     ("device_k3_n10000", 10000, 3, 4.6, 0, 2000, "MPLD_FORCE_DEVICE"),
     # an LDS-tier component whose search ends INFEASIBLE after visiting every
     # root row (501,238 nodes): sequential, and as root-row subtree tasks
@@ -385,7 +389,8 @@ def latency_probe(mp, ctx, reps=3, names=None, lds=None):
         e = workload.random_component(n, deg, seed)
         g = mp.Graph(n, e, np.zeros((0, 2), np.int32))
         b = mp.Batch(ctx, g, k, budget, getattr(mp, flag))
-        b.set_tune(root_split=1 if name.endswith("_root_split") else 0)
+        b.set_tune(root_split=1 if name.endswith("_root_split") else 0,
+                   big_one_wave=0 if name.endswith("_workgroup") else 1)
         split = name.endswith("_split") and not name.endswith("_root_split")
         ms = []
         for _ in range(reps):

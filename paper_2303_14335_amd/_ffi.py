@@ -75,7 +75,7 @@ class mpld_batch_info(ctypes.Structure):
                 ("image_bytes", c_i64), ("core_edges", c_i64), ("last_search_ms", ctypes.c_float),
                 ("last_total_ms", ctypes.c_float), ("launches", c_i32), ("num_device", c_i32),
                 ("heavy_components", c_i32), ("split_rounds", c_i32), ("split_tasks", c_i32),
-                ("split_reruns", c_i32), ("last_roundtrip_ms", ctypes.c_float), ("reserved", c_i32)]
+                ("split_reruns", c_i32), ("last_roundtrip_ms", ctypes.c_float), ("big_waves", c_i32)]
 
 
 class mpld_tune(ctypes.Structure):
@@ -85,7 +85,8 @@ class mpld_tune(ctypes.Structure):
                 ("default_ms", ctypes.c_float), ("candidates", c_i32), ("from_cache", c_i32),
                 ("heavy_first_cap", c_i32), ("heavy_round_cap", c_i32), ("heavy_levels", c_i32),
                 ("heavy_device", c_i32), ("root_split", c_i32), ("root_split_min_n", c_i32),
-                ("root_split_max", c_i32), ("root_split_chunk", c_i32)]
+                ("root_split_max", c_i32), ("root_split_chunk", c_i32),
+                ("big_one_wave", c_i32)]
 
 
 class mpld_server_options(ctypes.Structure):

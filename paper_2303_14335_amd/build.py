@@ -26,7 +26,10 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
 # Per-source flags.  The register tier's search loop branches only on
 # wave-uniform values; leaving those regions unstructurized keeps the
 # branches as scalar branches instead of exec-mask flow blocks.
-EXTRA = {"search_reg.hip": ["-mllvm", "-structurizecfg-skip-uniform-regions"]}
+EXTRA = {"search_reg.hip": ["-mllvm", "-structurizecfg-skip-uniform-regions"],
+         # single-lane LDS atomics (the wide tier's per-depth bits) need no
+         # rewrite into one atomic per wave
+         "search_lds.hip": ["-mllvm", "-amdgpu-atomic-optimizer-strategy=None"]}
 
 
 def _compile(src: str) -> str:

@@ -118,6 +118,7 @@ bool tune_from_cache(mpld_batch* b, const char* path, Tune* t) {
   if (field(hit, "root_split_min_n", &v)) t->root_split_min_n = (int32_t)std::max(2L, v);
   if (field(hit, "root_split_max", &v)) t->root_split_max = (int32_t)std::max(0L, v);
   if (field(hit, "root_split_chunk", &v)) t->root_split_chunk = (int32_t)std::max(1L, v);
+  if (field(hit, "big_one_wave", &v)) t->big_one_wave = v ? 1 : 0;
   if (field(hit, "heavy_levels", &v))
     t->heavy_levels = (int32_t)std::max(0L, std::min((long)kSplitMaxLevels, v));
   b->tuned_from_cache = true;
@@ -175,6 +176,7 @@ static void to_abi(const Tune& t, mpld_tune* o) {
   o->root_split_min_n = t.root_split_min_n;
   o->root_split_max = t.root_split_max;
   o->root_split_chunk = t.root_split_chunk;
+  o->big_one_wave = t.big_one_wave;
 }
 
 extern "C" {
@@ -205,6 +207,7 @@ int32_t mpld_batch_set_tune(mpld_batch* b, const mpld_tune* in) {
     t.root_split_min_n = std::max(2, in->root_split_min_n);
     t.root_split_max = std::max(0, in->root_split_max);
     t.root_split_chunk = std::max(1, in->root_split_chunk);
+    t.big_one_wave = in->big_one_wave ? 1 : 0;
     batch_pack(b, t);
     b->solved = false;
     set_last_error("");
@@ -268,6 +271,12 @@ int32_t mpld_batch_autotune(mpld_batch* b, int32_t reps, const char* cache_path,
         cands.push_back(t);
       }
     }
+    // big tier: a workgroup sharing the column scan instead of one wave
+    if (b->db.n_big > 0 && b->db.big_waves == 0) {
+      Tune t;
+      t.big_one_wave = 0;
+      cands.push_back(t);
+    }
     Tune best = base;
     float best_ms = base_ms;
     for (const Tune& t : cands) {
@@ -300,7 +309,8 @@ int32_t mpld_batch_autotune(mpld_batch* b, int32_t reps, const char* cache_path,
           << ", \"heavy_device\": " << best.heavy_device << ", \"root_split\": " << best.root_split
           << ", \"root_split_min_n\": " << best.root_split_min_n
           << ", \"root_split_max\": " << best.root_split_max
-          << ", \"root_split_chunk\": " << best.root_split_chunk << ", \"best_ms\": " << best_ms
+          << ", \"root_split_chunk\": " << best.root_split_chunk
+          << ", \"big_one_wave\": " << best.big_one_wave << ", \"best_ms\": " << best_ms
           << ", \"default_ms\": " << base_ms << "}\n";
       }
     }

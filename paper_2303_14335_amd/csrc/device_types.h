@@ -46,6 +46,14 @@ inline uint32_t reg_item_width(int32_t max_n) { return max_n < 1 ? 1u : (uint32_
 // Largest component of the one-wave LDS tier (one 32-bit node word per
 // lane of a wave).
 constexpr int32_t kLds1MaxN = 2048;
+// One-wave wide tier (big components whose planes and neighbour lists fit
+// in LDS): at most 8 node words of 32 nodes per lane, so at most 16384
+// nodes, and k <= 4 (every plane word of a lane in registers); its offs
+// words hold the first neighbour in 17 bits and the degree above them.
+constexpr int32_t kWideMaxWords = 8;
+constexpr int32_t kWideMaxK = 4;
+constexpr int32_t kWideMaxN = 64 * 32 * kWideMaxWords;
+constexpr uint32_t kWideBegBits = 17;
 
 // One record per component (24 bytes), written by the search.
 struct DevRecord {

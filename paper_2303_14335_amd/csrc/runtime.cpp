@@ -103,6 +103,9 @@ void image_add(Image& im, mpld_context* ctx, int32_t n, const int32_t* pairs, in
       im.q_lds.push_back(id);
     } else if (big <= ctx->lds_per_block) {
       im.lds_bytes_big = std::max(im.lds_bytes_big, big);
+      const int64_t wide = lds_wide_bytes(n, k, adj_words, (int32_t)maxdeg, stitch);
+      if (wide < 0 || wide > ctx->lds_per_block) im.big_wide = false;
+      else im.lds_bytes_wide = std::max(im.lds_bytes_wide, wide);
       im.big_stack_words = std::max(im.big_stack_words, lds_stack_words(n, k, adj_words));
       im.big_max_n = std::max(im.big_max_n, n);
       im.q_big.push_back(id);
@@ -174,8 +177,12 @@ void device_upload(mpld_context* ctx, const Image& im, DeviceBatch& db, const Tu
   }
   db.lds_dev = device_tier_lds_bytes(std::max(1, im.dev_max_n), db.grid_dev);
   db.lds_small = (int)im.lds_bytes_small;
-  db.lds_big = (int)im.lds_bytes_big;
-  db.big_waves = lds_big_waves(im.big_max_n);
+  // big tier: one wave with the neighbour lists in LDS (waves = 0, the wide
+  // layout) when every big component fits it, else a workgroup sharing the
+  // column scan
+  const bool wide = tune.big_one_wave && im.big_wide && !im.q_big.empty();
+  db.lds_big = (int)(wide ? im.lds_bytes_wide : im.lds_bytes_big);
+  db.big_waves = wide ? 0 : lds_big_waves(im.big_max_n);
   db.mark_lds = im.mark_lds;
   db.big_stack_words = (uint64_t)im.big_stack_words;
   {

@@ -73,6 +73,8 @@ hipError_t launch_lds_tasks(bool trace, bool big, bool stitch, int waves, int gr
 hipError_t launch_csr_writeback(const LdsResolved* w, int32_t count, const int8_t* src,
                                 DevRecord* recs, int8_t* colors, hipStream_t s);
 // Waves per workgroup for big LDS-tier components of at most max_n nodes.
+// The big-tier launchers take waves = 0 for the one-wave wide layout
+// (lds_wide_bytes of LDS).
 int lds_big_waves(int32_t max_n);
 // Conflict marking (MPLD_MARK_CONFLICTS) of the components whose record is
 // not FEASIBLE: register-tier items, and CSR components (LDS, big and
@@ -93,6 +95,9 @@ hipError_t launch_min_reg(int k, int grid, RegItems items, int32_t qlen, const u
 int64_t lds_bytes_for(int32_t n, int32_t k, int64_t adj_words, int32_t max_deg, bool big,
                       bool stitch = false);
 int64_t lds_stack_words(int32_t n, int32_t k, int64_t adj_words);
+// LDS bytes of a big component on one wave with its neighbour lists in LDS
+// (the wide layout), or -1 when that layout does not apply to it.
+int64_t lds_wide_bytes(int32_t n, int32_t k, int64_t adj_words, int32_t max_deg, bool stitch);
 // Device-wide tier (cooperative launch over `grid` workgroups, one per CU).
 hipError_t launch_device_tier(bool trace, int grid, int lds_bytes, const DevDesc* desc,
                               const uint32_t* adj32, unsigned long long* keys, uint64_t* stacks,
@@ -196,6 +201,8 @@ struct Image {
   int64_t core_edges = 0;
   int64_t lds_bytes_small = 0;     // largest footprint on the LDS tier
   int64_t lds_bytes_big = 0;       // largest footprint on the big tier
+  int64_t lds_bytes_wide = 0;      // ... in the one-wave wide layout
+  bool big_wide = true;            // every big component fits the wide layout
   int64_t big_stack_words = 0;     // largest global stack of the big tier
   int32_t big_max_n = 0;           // largest component of the big tier
   int64_t mark_lds = 0;            // LDS of the conflict marking of CSR components
@@ -222,6 +229,7 @@ struct Tune {
   int32_t root_split_min_n = 4;    // smallest item that gets one
   int32_t root_split_max = 0;      // most items that get one; 0 = all
   int32_t root_split_chunk = 16;   // helper nodes between release checks
+  int32_t big_one_wave = 1;        // big tier on one wave (wide layout) when every component fits
 };
 
 // Adds one component (local numbering, pairs i < j or j < i) to the image.

@@ -170,11 +170,11 @@ __host__ __device__ inline Lds1Layout lds1_layout(int32_t n, int32_t k, int64_t 
   Lds1Layout L;
   const uint32_t m2 = (uint32_t)(adj_words - n - 1);
   L.offs_off = 64u * 4u * lds1_stride(k);
-  L.ids_off = L.offs_off + 4u * (uint32_t)n;
+  L.ids_off = L.offs_off + 4u * (uint32_t)(n > 0 ? n : 1);   // one offs word at least
   L.hdr_off = (L.ids_off + 2u * m2 + 7u) & ~7u;
   L.ent_off = L.hdr_off + 8u * (uint32_t)n;
   L.part_off = L.ent_off + 4u * lds_log_entries(n, k, adj_words);
-  L.col_off = L.part_off + (stitch ? 2u * (uint32_t)n : 0u);
+  L.col_off = L.part_off + (stitch ? 2u * (uint32_t)(n > 0 ? n : 1) : 0u);
   L.total = (L.col_off + (stitch ? (uint32_t)n : 0u) + 15u) & ~15u;
   return L;
 }
@@ -247,7 +247,6 @@ __device__ void solve_lds(const DevDesc& d, const uint32_t* __restrict__ gadj, c
   int32_t status = -1;
   uint32_t areg = 0;   // untried-rows bit of depth 32 * lane + b
   const uint64_t budget = root_row >= 0 ? task_budget : (uint64_t)d.budget;
-  const uint32_t nm1 = n - 1u;
   Lds1Words<K> W;
 
   // Take row (v, c) at `depth`: the level's header and untried-rows bit,
@@ -360,8 +359,9 @@ __device__ void solve_lds(const DevDesc& d, const uint32_t* __restrict__ gadj, c
     uint32_t r = 0;
 #pragma unroll
     for (int c = 0; c < K; ++c) r |= __builtin_amdgcn_ubfe(W.a[c], bit, 1u) << c;
-    const uint32_t pre = offs[vl < nm1 ? vl : nm1];
-    const uint32_t prp = STITCH ? (uint32_t)spart[vl < nm1 ? vl : nm1] : 0xffffu;
+    const uint32_t vc = vl < n ? vl : 0u;   // lanes past n read node 0's words
+    const uint32_t pre = offs[vc];
+    const uint32_t prp = STITCH ? (uint32_t)spart[vc] : 0xffffu;
     // issue those reads before the minimum (which they then overlap)
     asm volatile("" ::: "memory");
     const uint32_t key = wave_min(p ? ((t << 24) | vl) : kNoKey);
@@ -440,6 +440,355 @@ __device__ void solve_lds(const DevDesc& d, const uint32_t* __restrict__ gadj, c
   // Every lane stores the same (uniform) record: no branch in the loop may
   // share the queue pop's "lane 0" condition, or the compiler can thread the
   // two across the loop back-edge and split the wave at the pop.
+  rec->status = status;
+  rec->depth = status == MPLD_INFEASIBLE ? 0 : (int32_t)depth;
+  rec->nodes = nodes;
+  rec->hash = h;
+  __syncthreads();
+}
+
+// ---- one-wave wide tier ---------------------------------------------------
+//
+// Big components whose planes and neighbour lists fit in LDS: one wave, as
+// the one-wave tier, but up to kWideMaxWords 32-bit node words per lane
+// (word w in lane w & 63), so no barrier per node, and the column choice
+// reads a cache of per-word keys instead of recounting every word: key(w) =
+// count << 28 | node << 4 | rows of the lowest-count, lowest-index
+// uncovered column of word w (kNoKey when w has none).  A cover changes
+// only the words of the column and of its neighbours, so after the cover
+// atomics each lane that made one reads its word's planes back and
+// rewrites that word's key; after a backtrack (the undo log touches any
+// words) every key is recomputed.  Per node a lane reads its keys (at most
+// eight, two ds_read_b128), takes their minimum, and the wave minimum is
+// the column with its count and rows.  LDS: the planes, the keys, the
+// per-depth "untried rows" bit set, offs (first neighbour | degree << 17),
+// 16-bit neighbour ids, and for the stitch-aware order the partners and the
+// color of each covered node.  Level headers {log start, v | untried << 16
+// | c << 24} and the undo log go to the worker's global area: the forward
+// path only stores to it (nothing waits for those stores), and a backtrack
+// - rare on components this large - reads it back after a fence.
+__host__ __device__ inline uint32_t wide_words(int32_t n) {
+  const uint32_t w = (uint32_t)((n + 2047) / 2048);   // 64 lanes x 32 nodes
+  return w < 1u ? 1u : w;
+}
+
+struct WideLayout {
+  uint32_t pl_off, key_off, bits_off, offs_off, ids_off, part_off, col_off, total;
+};
+
+__host__ __device__ inline WideLayout wide_layout(int32_t n, int32_t k, int64_t adj_words,
+                                                  bool stitch) {
+  WideLayout L;
+  const uint32_t m2 = (uint32_t)(adj_words - n - 1);
+  const uint32_t n1 = (uint32_t)(n > 0 ? n : 1);   // one offs word at least
+  L.pl_off = 16u;   // the workgroup's queue pop result first
+  L.key_off = L.pl_off + 64u * wide_words(n) * 4u * lds1_stride(k);
+  L.bits_off = L.key_off + 64u * 4u * (uint32_t)kWideMaxWords;
+  L.offs_off = L.bits_off + ((4u * (((uint32_t)n + 31u) / 32u) + 15u) & ~15u);
+  L.ids_off = L.offs_off + 4u * n1;
+  L.part_off = (L.ids_off + 2u * m2 + 15u) & ~15u;
+  L.col_off = L.part_off + (stitch ? 2u * n1 : 0u);
+  L.total = (L.col_off + (stitch ? (uint32_t)n : 0u) + 15u) & ~15u;
+  return L;
+}
+
+// Key of word w (planes in W): count << 28 | node << 4 | rows (k <= 4).
+template <int K>
+__device__ __forceinline__ uint32_t wide_key(const Lds1Words<K>& W, uint32_t w) {
+  constexpr int NB = bits_for(K);
+  uint32_t cnt[NB];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) cnt[b] = 0u;
+#pragma unroll
+  for (int c = 0; c < K; ++c) {
+    uint32_t carry = W.a[c];
+#pragma unroll
+    for (int b = 0; b < bits_for(c + 1); ++b) {
+      const uint32_t t = cnt[b] & carry;
+      cnt[b] ^= carry;
+      carry = t;
+    }
+  }
+  const uint32_t p = W.a[K];
+  uint32_t cand = p, t = 0u;
+#pragma unroll
+  for (int b = NB - 1; b >= 0; --b) {
+    const uint32_t x = cand & ~cnt[b];
+    if (x) cand = x;
+    else t |= 1u << b;
+  }
+  const uint32_t bit = (uint32_t)__builtin_ctz(cand | 0x80000000u);
+  uint32_t r = 0;
+#pragma unroll
+  for (int c = 0; c < K; ++c) r |= __builtin_amdgcn_ubfe(W.a[c], bit, 1u) << c;
+  return p ? (t << 28) | (((w << 5) | bit) << 4) | r : kNoKey;
+}
+
+template <bool TRACE, int K, bool STITCH>
+__device__ void solve_lds_wide(const DevDesc& d, const uint32_t* __restrict__ gadj, char* lds,
+                               uint64_t* gstack, int8_t* __restrict__ colors,
+                               DevRecord* __restrict__ rec, int32_t root_row = -1,
+                               uint64_t task_budget = 0) {
+  static_assert(K <= 4, "keys hold the count and the rows in 4 bits each");
+  constexpr uint32_t S = lds1_stride(K);
+  constexpr uint32_t kLS = S == 4u ? 2u : (S == 8u ? 3u : 4u);   // log2(S)
+  constexpr uint32_t NW = (uint32_t)kWideMaxWords;
+  constexpr uint32_t kNodeMask = (1u << kEntryNodeBits) - 1u;
+  const uint32_t lane = __lane_id();
+  const uint32_t n = (uint32_t)d.n;
+  const uint32_t m2 = uni(gadj[n]);
+  const WideLayout L = wide_layout((int32_t)n, K, (int64_t)m2 + n + 1, STITCH);
+  const uint32_t nwl = wide_words((int32_t)n);   // node words per lane (uniform)
+  uint32_t* PL = reinterpret_cast<uint32_t*>(lds + L.pl_off);
+  uint32_t* keys = reinterpret_cast<uint32_t*>(lds + L.key_off);   // word w at (w & 63) * NW + (w >> 6)
+  uint32_t* dbits = reinterpret_cast<uint32_t*>(lds + L.bits_off);
+  uint32_t* offs = reinterpret_cast<uint32_t*>(lds + L.offs_off);
+  uint16_t* ids = reinterpret_cast<uint16_t*>(lds + L.ids_off);
+  uint16_t* spart = reinterpret_cast<uint16_t*>(lds + L.part_off);
+  uint8_t* scol = reinterpret_cast<uint8_t*>(lds + L.col_off);
+  uint2* hdr = reinterpret_cast<uint2*>(gstack);
+  uint32_t* ent = reinterpret_cast<uint32_t*>(gstack + n);
+  for (uint32_t v = lane; v < n; v += 64) {
+    const uint32_t b = gadj[v], e = gadj[v + 1];
+    offs[v] = b | ((e - b) << kWideBegBits);
+    if (STITCH) {
+      const uint32_t p = gadj[n + 1 + m2 + 1 + v];
+      spart[v] = p < n ? (uint16_t)p : (uint16_t)0xffffu;
+    }
+  }
+  for (uint32_t i = lane; i < m2; i += 64) ids[i] = (uint16_t)gadj[n + 1 + i];
+  for (uint32_t w = lane; w < 64u * nwl; w += 64) {
+    // every node uncovered with all k colors open; words past n are empty
+    const uint32_t base = w * 32u;
+    const uint32_t cnt = base >= n ? 0u : (n - base >= 32u ? 32u : n - base);
+    const uint32_t val = cnt == 32u ? ~0u : ((1u << cnt) - 1u);
+#pragma unroll
+    for (uint32_t c = 0; c < S; ++c) PL[w * S + c] = c <= (uint32_t)K ? val : 0u;
+  }
+#pragma unroll
+  for (uint32_t j = 0; j < NW; ++j) keys[lane * NW + j] = kNoKey;
+  __syncthreads();
+
+  uint32_t depth = 0, row_in = kNoneL, esp = 0;
+  uint64_t nodes = 0, h = 0;
+  int32_t status = -1;
+  const uint64_t budget = root_row >= 0 ? task_budget : (uint64_t)d.budget;
+  Lds1Words<K> W;
+  // every key of this lane's words, from the planes
+  auto all_keys = [&]() {
+#pragma unroll
+    for (uint32_t j = 0; j < NW; ++j) {
+      if (j < nwl) {
+        const uint32_t w = lane + 64u * j;
+        W.load(PL, w);
+        keys[lane * NW + j] = wide_key<K>(W, w);
+      }
+    }
+  };
+  all_keys();
+
+  // This lane's keys for the next node's column choice (words j >= nwl
+  // hold kNoKey).
+  uint4 ka, kb = make_uint4(kNoKey, kNoKey, kNoKey, kNoKey);
+  auto read_keys = [&]() {
+    ka = *reinterpret_cast<const uint4*>(keys + lane * NW);
+    if (nwl > 4u) kb = *reinterpret_cast<const uint4*>(keys + lane * NW + 4u);
+  };
+
+  // Take row (v, c) at `depth`: one atomic AND per neighbour of v on plane
+  // c (lanes 1 .. deg) and, if `lane_lo` is 0, on v's P bit (lane 0); then
+  // the keys of the words those atomics changed (every key when `full` or
+  // with more than 63 neighbours) and this lane's keys for the next node,
+  // read before the header, the untried-rows bit and the removed rows
+  // (global memory) are written, so that their latency overlaps that work.
+  const uint16_t* ids_m1 = ids - 1;   // lane j reads neighbour j - 1
+  const uint32_t is_l0 = lane == 0u ? ~0u : 0u;
+  auto take_row = [&](uint32_t v, uint32_t c, uint32_t rows, uint32_t offv, uint32_t est,
+                      uint32_t lane_lo, bool more, bool full) {
+    const uint32_t beg = offv & ((1u << kWideBegBits) - 1u), deg = offv >> kWideBegBits;
+    const uint32_t first = deg < 63u ? deg : 63u;
+    full = full || deg > 63u;
+    const bool act = lane >= lane_lo && lane <= first;
+    uint32_t old = 0u, bitm = 0u, entry = 0u, u = 0u;
+    if (act) {
+      const uint32_t idv = ids_m1[beg + lane];
+      u = (is_l0 & v) | (~is_l0 & idv);
+      const uint32_t pl4 = (is_l0 & ((uint32_t)K * 4u)) | (~is_l0 & (c * 4u));
+      bitm = 1u << (u & 31u);
+      old = atomicAnd(reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(PL) +
+                                                  (((u >> 5) << (kLS + 2u)) | pl4)),
+                      ~bitm);
+      entry = (pl4 << 24) | u;
+      // the changed word, read right behind the atomic (LDS operations of
+      // one wave complete in order)
+      if (!full) W.load(PL, u >> 5);
+    }
+    asm volatile("" : "+v"(old) : : "memory");
+    if (!full) {
+      // lanes on the same word compute the same key
+      if (act) {
+        const uint32_t w = u >> 5;
+        keys[(w & 63u) * NW + (w >> 6)] = wide_key<K>(W, w);
+      }
+      read_keys();
+    }
+    asm volatile("" ::: "memory");
+    if (lane == 0u) {
+      hdr[depth] = make_uint2(est, v | (rows << 16) | (c << 24));
+      const uint32_t db = 1u << (depth & 31u);
+      atomicAnd(&dbits[depth >> 5], ~db);
+      if (more) atomicOr(&dbits[depth >> 5], db);
+      if (STITCH) scol[v] = (uint8_t)c;
+    }
+    uint32_t slot = est + lane_lo;
+    auto log_hits = [&](bool hit, uint32_t e) {
+      const uint64_t bal = __builtin_amdgcn_ballot_w64(hit);
+      if (hit) {
+        const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
+                                                        __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+        ent[slot + rank] = e;
+      }
+      slot += (uint32_t)__popcll(bal);
+    };
+    log_hits((old & bitm) != 0u, entry);
+    if (deg > 63u) {
+      for (uint32_t ch = 63u; ch < deg; ch += 64u) {
+        bool hit = false;
+        uint32_t uu = 0;
+        if (ch + lane < deg) {
+          uu = ids[beg + ch + lane];
+          const uint32_t b = 1u << (uu & 31u);
+          hit = (atomicAnd(&PL[(uu >> 5) * S + c], ~b) & b) != 0u;
+        }
+        log_hits(hit, (c << kEntryNodeBits) | uu);
+      }
+    }
+    esp = slot;
+    asm volatile("" ::: "memory");
+    if (full) {
+      all_keys();
+      read_keys();
+    }
+    asm volatile("" ::: "memory");
+  };
+
+  if (root_row >= 0) {
+    // row (0, root_row) at depth 0, with no alternative at that level
+    const uint32_t c = (uint32_t)root_row;
+    take_row(0u, c, 0u, uni(offs[0]), 0u, 0u, false, false);
+    depth = 1u;
+    row_in = c;
+  } else {
+    read_keys();
+  }
+
+  while (status < 0) {
+    // ---- one search node
+    if (nodes == budget) { status = MPLD_BUDGET_EXHAUSTED; break; }
+    ++nodes;
+    // column choice: the lowest key of this lane's words, then of the wave
+    const uint32_t best = min(min(min(ka.x, ka.y), min(ka.z, ka.w)),
+                              min(min(kb.x, kb.y), min(kb.z, kb.w)));
+    // (kNoKey's node field is past n: read node 0's words instead)
+    const uint32_t vl = (best >> 4) & 0xffffffu, vc = vl < n ? vl : 0u;
+    const uint32_t pre = offs[vc];
+    asm volatile("" ::: "memory");
+    const uint32_t key = wave_min(best);
+    if (key == kNoKey) {   // no uncovered column: the levels hold a solution
+      if (TRACE) h = trace_node(h, depth, row_in, kNoneL, 0);
+      status = MPLD_FEASIBLE;
+      break;
+    }
+    uint32_t v = (key >> 4) & 0xffffffu;
+    const uint32_t size = key >> 28;
+    if (TRACE) h = trace_node(h, depth, row_in, v, size);
+    uint32_t rows, offv, est, lane_lo, c;
+    bool full;
+    if (size != 0) {
+      rows = key & 0xfu;
+      offv = rdlane(pre, (v >> 5) & 63u);
+      est = esp;
+      lane_lo = 0u;
+      full = false;
+      c = (uint32_t)__builtin_ctz(rows);
+      if (STITCH) {
+        // the partner's color first when the partner is covered (its P bit
+        // is clear) and that row of v is open
+        const uint32_t p = uni((uint32_t)spart[v]);
+        if (p != 0xffffu && !((uni(PL[(p >> 5) * S + K]) >> (p & 31u)) & 1u)) {
+          const uint32_t cp = uni((uint32_t)scol[p]);
+          if ((rows >> cp) & 1u) c = cp;
+        }
+      }
+      rows &= ~(1u << c);   // the level's untried rows
+    } else {
+      // dead end: the headers and the log written so far must be visible
+      // to this wave's loads (stores done, the CU's vector cache dropped)
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "agent");
+      // back to the deepest level below `depth` whose column has an untried row
+      uint32_t f = kNoneL;
+      if (depth != 0) {
+        const uint32_t d1 = depth - 1u, top = d1 >> 5;
+        const uint32_t below = ~0u >> (31u - (d1 & 31u));
+        for (uint32_t base = 0; base <= top && f == kNoneL; base += 64u) {
+          // lane l looks at word top - base - l
+          const bool in = base + lane <= top;
+          const uint32_t wi = in ? top - base - lane : 0u;
+          uint32_t m = in ? dbits[wi] : 0u;
+          if (in && wi == top) m &= below;
+          const uint64_t bal = __builtin_amdgcn_ballot_w64(m != 0u);
+          if (bal) {
+            const uint32_t l = (uint32_t)__builtin_ctzll(bal);
+            f = (top - base - l) * 32u + 31u - (uint32_t)__builtin_clz(rdlane(m, l));
+          }
+        }
+      }
+      if (f == kNoneL) { status = MPLD_INFEASIBLE; break; }
+      const uint2 hd = hdr[f];
+      est = uni(hd.x);
+      const uint32_t y = uni(hd.y);
+      v = y & 0xffffu;
+      offv = uni(offs[v]);
+      // uncover every level above f, and the rows level f removed; the
+      // column stays covered (its P bit is entry est); eight entries per
+      // lane in flight at a time
+      for (uint32_t i0 = est + 1u; i0 < esp; i0 += 64u * 8u) {
+        uint32_t e[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const uint32_t i = i0 + 64u * (uint32_t)q + lane;
+          e[q] = i < esp ? ent[i] : 0xffffffffu;
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          if (e[q] != 0xffffffffu) {
+            const uint32_t uu = e[q] & kNodeMask;
+            atomicOr(&PL[(uu >> 5) * S + (e[q] >> kEntryNodeBits)], 1u << (uu & 31u));
+          }
+        }
+      }
+      // the next untried row of the level, in ascending order
+      rows = (y >> 16) & 0xffu;
+      c = (uint32_t)__builtin_ctz(rows);
+      rows &= rows - 1u;
+      depth = f;
+      lane_lo = 1u;
+      full = true;
+    }
+    take_row(v, c, rows, offv, est, lane_lo, rows != 0u, full);
+    row_in = v * (uint32_t)K + c;
+    ++depth;
+  }
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "agent");
+  __syncthreads();
+  if (status == MPLD_FEASIBLE) {
+    for (uint32_t f = lane; f < depth; f += 64) {
+      const uint32_t y = hdr[f].y;
+      colors[y & 0xffffu] = (int8_t)((y >> 24) & 0xfu);
+    }
+  } else {
+    for (uint32_t v = lane; v < n; v += 64) colors[v] = -1;
+  }
   rec->status = status;
   rec->depth = status == MPLD_INFEASIBLE ? 0 : (int32_t)depth;
   rec->nodes = nodes;
@@ -667,11 +1016,13 @@ __device__ void solve_lds_wg(const DevDesc& d, const uint32_t* __restrict__ adj,
 template <bool TRACE, bool BIG, bool STITCH>
 __device__ __forceinline__ void solve_lds_k(const DevDesc& d, const uint32_t* gadj, char* lds,
                                             uint64_t* gstack, int8_t* colors, DevRecord* rec,
-                                            int32_t root_row = -1, uint64_t task_budget = 0) {
-#define MPLD_LDS_CASE(KK)                                                                  \
-  case KK:                                                                                 \
-    if (BIG) solve_lds_wg<TRACE, KK, STITCH>(d, gadj, lds, gstack, colors, rec, root_row, task_budget); \
-    else solve_lds<TRACE, KK, STITCH>(d, gadj, lds, colors, rec, root_row, task_budget);            \
+                                            uint32_t wide, int32_t root_row = -1,
+                                            uint64_t task_budget = 0) {
+#define MPLD_LDS_CASE(KK)                                                                     \
+  case KK:                                                                                    \
+    if (BIG && KK <= kWideMaxK && wide) solve_lds_wide<TRACE, (KK <= kWideMaxK ? KK : 2), STITCH>(d, gadj, lds, gstack, colors, rec, root_row, task_budget); \
+    else if (BIG) solve_lds_wg<TRACE, KK, STITCH>(d, gadj, lds, gstack, colors, rec, root_row, task_budget); \
+    else solve_lds<TRACE, KK, STITCH>(d, gadj, lds, colors, rec, root_row, task_budget);     \
     break;
   switch (d.k) {
     MPLD_LDS_CASE(2)
@@ -696,14 +1047,15 @@ template <bool TRACE, bool BIG, bool STITCH>
 __global__ __launch_bounds__(BIG ? 1024 : 64) void lds_batched_kernel(
     const DevDesc* __restrict__ descs, const uint32_t* __restrict__ adj32, int32_t qlen,
     int32_t* __restrict__ counter, uint64_t* gstack, uint64_t stack_words_per_wave,
-    DevRecord* __restrict__ recs, int8_t* __restrict__ colors) {
+    DevRecord* __restrict__ recs, int8_t* __restrict__ colors, uint32_t wide) {
   extern __shared__ __align__(16) char lds[];
   uint64_t* my_stack = BIG ? gstack + (uint64_t)blockIdx.x * stack_words_per_wave : nullptr;
   const int32_t gw = (int32_t)gridDim.x;
   int32_t item = (int32_t)uni(blockIdx.x);
   while (item < qlen) {
     const DevDesc d = descs[item];
-    solve_lds_k<TRACE, BIG, STITCH>(d, adj32 + d.nbr_off, lds, my_stack, colors + d.out_off, recs + d.comp);
+    solve_lds_k<TRACE, BIG, STITCH>(d, adj32 + d.nbr_off, lds, my_stack, colors + d.out_off, recs + d.comp,
+                                    wide);
     if (gw >= qlen) break;
     int32_t r = 0;
     if constexpr (BIG) {   // one pop per workgroup, shared through LDS
@@ -724,10 +1076,11 @@ __global__ __launch_bounds__(BIG ? 1024 : 64) void lds_batched_kernel(
 template <bool TRACE, bool BIG, bool STITCH>
 __global__ __launch_bounds__(BIG ? 1024 : 64) void lds_single_kernel(
     const DevDesc* __restrict__ descs, const uint32_t* __restrict__ adj32, int32_t item,
-    uint64_t* gstack, DevRecord* __restrict__ recs, int8_t* __restrict__ colors) {
+    uint64_t* gstack, DevRecord* __restrict__ recs, int8_t* __restrict__ colors, uint32_t wide) {
   extern __shared__ __align__(16) char lds[];
   const DevDesc d = descs[item];
-  solve_lds_k<TRACE, BIG, STITCH>(d, adj32 + d.nbr_off, lds, gstack, colors + d.out_off, recs + d.comp);
+  solve_lds_k<TRACE, BIG, STITCH>(d, adj32 + d.nbr_off, lds, gstack, colors + d.out_off, recs + d.comp,
+                                  wide);
 }
 
 // Subtree tasks of the heavy-component split: task t searches the subtree
@@ -741,14 +1094,14 @@ __global__ __launch_bounds__(BIG ? 1024 : 64) void lds_task_kernel(
     const DevDesc* __restrict__ descs, const uint32_t* __restrict__ adj32,
     const LdsTask* __restrict__ tasks, int32_t ntasks, uint64_t* gstack,
     uint64_t stack_words_per_block, DevRecord* __restrict__ task_recs,
-    int8_t* __restrict__ task_colors) {
+    int8_t* __restrict__ task_colors, uint32_t wide) {
   extern __shared__ __align__(16) char lds[];
   uint64_t* my_stack = BIG ? gstack + (uint64_t)blockIdx.x * stack_words_per_block : nullptr;
   for (int32_t t = (int32_t)uni(blockIdx.x); t < ntasks; t += (int32_t)gridDim.x) {
     const LdsTask task = tasks[t];
     const DevDesc d = descs[task.item];
     solve_lds_k<TRACE, BIG, STITCH>(d, adj32 + d.nbr_off, lds, my_stack, task_colors + task.col_off,
-                            task_recs + t, task.row, (uint64_t)task.budget);
+                                    task_recs + t, wide, task.row, (uint64_t)task.budget);
   }
 }
 
@@ -843,6 +1196,16 @@ int64_t lds_bytes_for(int32_t n, int32_t k, int64_t adj_words, int32_t max_deg, 
              : (int64_t)lds1_layout(n, k, adj_words, stitch).total;
 }
 
+int64_t lds_wide_bytes(int32_t n, int32_t k, int64_t adj_words, int32_t max_deg, bool stitch) {
+  // -1: the one-wave wide layout does not apply (too many nodes, or ids or
+  // degrees beyond its offs fields)
+  const int64_t m2 = adj_words - n - 1;
+  if (k > kWideMaxK || n > kWideMaxN || m2 >= (int64_t)1 << kWideBegBits ||
+      (int64_t)max_deg >= (int64_t)1 << (32 - kWideBegBits))
+    return -1;
+  return (int64_t)wide_layout(n, k, adj_words, stitch).total;
+}
+
 int64_t lds_stack_words(int32_t n, int32_t k, int64_t adj_words) {
   // level headers (one u64 per depth) and the undo log (u32 entries)
   return (int64_t)n + ((int64_t)lds_log_entries(n, k, adj_words) + 1) / 2;
@@ -915,11 +1278,12 @@ hipError_t launch_lds_batched(bool trace, bool big, bool stitch, int waves, int 
                               uint64_t stack_words, DevRecord* recs, int8_t* colors,
                               hipStream_t s) {
   if (qlen <= 0) return hipSuccess;
-  if (waves < 1 || waves > 16 || (!big && waves != 1)) return hipErrorInvalidValue;
+  if (waves < 0 || waves > 16 || (!big && waves != 1)) return hipErrorInvalidValue;
+  const uint32_t wide = waves == 0 ? 1u : 0u;   // big tier, one wave, wide layout
   return lds_dispatch(trace, big, stitch, [&](auto t, auto g, auto st) {
     hipLaunchKernelGGL((lds_batched_kernel<decltype(t)::value, decltype(g)::value, decltype(st)::value>),
-                       dim3(grid), dim3(64 * waves), (size_t)lds_bytes, s, descs, adj32, qlen,
-                       counter, gstack, stack_words, recs, colors);
+                       dim3(grid), dim3(64 * (wide ? 1 : waves)), (size_t)lds_bytes, s, descs, adj32,
+                       qlen, counter, gstack, stack_words, recs, colors, wide);
   });
 }
 
@@ -928,11 +1292,12 @@ hipError_t launch_lds_tasks(bool trace, bool big, bool stitch, int waves, int gr
                             int32_t ntasks, uint64_t* gstack, uint64_t stack_words,
                             DevRecord* task_recs, int8_t* task_colors, hipStream_t s) {
   if (ntasks <= 0) return hipSuccess;
-  if (waves < 1 || waves > 16 || (!big && waves != 1) || grid < 1) return hipErrorInvalidValue;
+  if (waves < 0 || waves > 16 || (!big && waves != 1) || grid < 1) return hipErrorInvalidValue;
+  const uint32_t wide = waves == 0 ? 1u : 0u;   // big tier, one wave, wide layout
   return lds_dispatch(trace, big, stitch, [&](auto t, auto g, auto st) {
     hipLaunchKernelGGL((lds_task_kernel<decltype(t)::value, decltype(g)::value, decltype(st)::value>),
-                       dim3(grid), dim3(64 * waves), (size_t)lds_bytes, s, descs, adj32, tasks,
-                       ntasks, gstack, stack_words, task_recs, task_colors);
+                       dim3(grid), dim3(64 * (wide ? 1 : waves)), (size_t)lds_bytes, s, descs, adj32,
+                       tasks, ntasks, gstack, stack_words, task_recs, task_colors, wide);
   });
 }
 
@@ -960,11 +1325,12 @@ hipError_t launch_csr_writeback(const LdsResolved* w, int32_t count, const int8_
 hipError_t launch_lds_single(bool trace, bool big, bool stitch, int waves, int lds_bytes,
                              const DevDesc* descs, const uint32_t* adj32, int32_t item,
                              uint64_t* gstack, DevRecord* recs, int8_t* colors, hipStream_t s) {
-  if (waves < 1 || waves > 16 || (!big && waves != 1)) return hipErrorInvalidValue;
+  if (waves < 0 || waves > 16 || (!big && waves != 1)) return hipErrorInvalidValue;
+  const uint32_t wide = waves == 0 ? 1u : 0u;   // big tier, one wave, wide layout
   return lds_dispatch(trace, big, stitch, [&](auto t, auto g, auto st) {
     hipLaunchKernelGGL((lds_single_kernel<decltype(t)::value, decltype(g)::value, decltype(st)::value>),
-                       dim3(1), dim3(64 * waves), (size_t)lds_bytes, s, descs, adj32, item, gstack,
-                       recs, colors);
+                       dim3(1), dim3(64 * (wide ? 1 : waves)), (size_t)lds_bytes, s, descs, adj32,
+                       item, gstack, recs, colors, wide);
   });
 }
 

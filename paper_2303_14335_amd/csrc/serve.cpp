@@ -258,6 +258,10 @@ void HipExecutor::tick(std::vector<Request*>& admitted, std::vector<ServeActive>
   int lds_small_bytes = 0, lds_big_bytes = 0;
   int64_t big_words = 0;
   int32_t big_max_n = 0;
+  // big components run on one wave with their lists in LDS (the wide
+  // layout) when all of this flight's fit it
+  bool big_wide = true;
+  int lds_wide_bytes_max = 0;
   for (Request* r : admitted) {
     const int32_t nc = (int32_t)r->recs.size();
     for (int32_t c = 0; c < nc; ++c) {
@@ -275,8 +279,11 @@ void HipExecutor::tick(std::vector<Request*>& admitted, std::vector<ServeActive>
                                                                             (r->opt.flags & MPLD_STITCH_ORDER) != 0));
       } else {
         lds_big.push_back({r, c});
-        lds_big_bytes = std::max<int>(lds_big_bytes, (int)lds_bytes_for(hd.n, hd.k, adj_words, maxdeg, true,
-                                                                        (r->opt.flags & MPLD_STITCH_ORDER) != 0));
+        const bool st = (r->opt.flags & MPLD_STITCH_ORDER) != 0;
+        lds_big_bytes = std::max<int>(lds_big_bytes, (int)lds_bytes_for(hd.n, hd.k, adj_words, maxdeg, true, st));
+        const int64_t wb = lds_wide_bytes(hd.n, hd.k, adj_words, maxdeg, st);
+        if (wb < 0 || wb > ctx->lds_per_block) big_wide = false;
+        else lds_wide_bytes_max = std::max<int>(lds_wide_bytes_max, (int)wb);
         big_words = std::max<int64_t>(big_words, lds_stack_words(hd.n, hd.k, adj_words));
         big_max_n = std::max(big_max_n, hd.n);
       }
@@ -365,7 +372,7 @@ void HipExecutor::tick(std::vector<Request*>& admitted, std::vector<ServeActive>
         const int grid = std::max(1, std::min((int)(b - a), ctx->num_cus * per_cu));
         // the big tier's stack areas: one per workgroup, grid <= count
         check_hip(launch_lds_batched((lds_trace[a] & 1) != 0, big, (lds_trace[a] & 2) != 0,
-                                     big ? lds_big_waves(big_max_n) : 1, grid,
+                                     big ? (big_wide ? 0 : lds_big_waves(big_max_n)) : 1, grid,
                                      bytes, f->desc.as<DevDesc>() + a, arena.as<uint32_t>(),
                                      (int32_t)(b - a), counter.as<int32_t>() + 1,
                                      big ? f->gstack.as<uint64_t>() : nullptr, (uint64_t)big_words,
@@ -375,7 +382,7 @@ void HipExecutor::tick(std::vector<Request*>& admitted, std::vector<ServeActive>
       }
     };
     lds_launch(0, lds_small.size(), false, lds_small_bytes);
-    lds_launch(lds_small.size(), lds_big.size(), true, lds_big_bytes);
+    lds_launch(lds_small.size(), lds_big.size(), true, big_wide ? lds_wide_bytes_max : lds_big_bytes);
     if (!md.empty()) {
       if (f->mark_desc.bytes < mb) f->mark_desc.alloc(ctx, mb);
       check_hip(hipMemcpyAsync(f->mark_desc.p, f->host.as<uint8_t>() + db + rb, mb,
