@@ -696,7 +696,10 @@ def main() -> int:
     roofline["launch_floor_us"] = {
         "grid": max(1, ncomp), "block": 256,
         "us": round(mp.mpld_measure_launch_floor(ctx, max(1, ncomp), 256, 200), 3),
-        "one_wave_us": round(mp.mpld_measure_launch_floor(ctx, 1, 64, 200), 3)}
+        "one_wave_us": round(mp.mpld_measure_launch_floor(ctx, 1, 64, 200), 3),
+        # the same grid, every wave loading 64 B and storing 8 B: the floor
+        # of a launch that touches device memory, as the search does
+        "touch_us": round(mp.mpld_measure_touch_floor(ctx, max(1, ncomp), 256, 200), 3)}
 
     out = {
         "metric": METRIC,

@@ -541,6 +541,13 @@ int32_t mpld_measure_lds_read_rate(mpld_context* ctx, int32_t bytes_per_lane, in
  * multiple of 64 in [64, 1024], or reps outside [1, 100000]. */
 int32_t mpld_measure_launch_floor(mpld_context* ctx, int32_t grid, int32_t block, int32_t reps,
                                   double* us_per_launch);
+/* As mpld_measure_launch_floor, for a kernel whose every wave reads 64
+ * bytes of its own and writes 8 bytes (as a search wave loads its item and
+ * stores its record): the fixed cost of a launch that touches device memory
+ * both ways.  Device buffers of 72 bytes per wave come from the context's
+ * allocator for the call.  Same arguments and errors, plus MPLD_E_NOMEM. */
+int32_t mpld_measure_touch_floor(mpld_context* ctx, int32_t grid, int32_t block, int32_t reps,
+                                 double* us_per_launch);
 
 /* ---- results ------------------------------------------------------------ */
 const int8_t* mpld_result_colors(const mpld_result* r, int32_t* num_nodes);

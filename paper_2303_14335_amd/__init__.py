@@ -442,6 +442,15 @@ def mpld_measure_launch_floor(ctx: Context, grid: int, block: int = 256, reps: i
     return us.value
 
 
+def mpld_measure_touch_floor(ctx: Context, grid: int, block: int = 256, reps: int = 200) -> float:
+    """Microseconds per launch of a kernel of `grid` x `block` lanes whose
+    every wave reads 64 bytes and writes 8, launched back to back."""
+    us = ctypes.c_double()
+    _check(_lib.mpld_measure_touch_floor(ctx.handle, grid, block, reps, ctypes.byref(us)),
+           "mpld_measure_touch_floor")
+    return us.value
+
+
 # ---- serving ----------------------------------------------------------------
 
 class Server:

@@ -133,6 +133,7 @@ SIGNATURES = {
     "mpld_measure_lds_read_rate": (c_i32, [vp, c_i32, c_i32, P(ctypes.c_double),
                                            P(ctypes.c_double)]),
     "mpld_measure_launch_floor": (c_i32, [vp, c_i32, c_i32, c_i32, P(ctypes.c_double)]),
+    "mpld_measure_touch_floor": (c_i32, [vp, c_i32, c_i32, c_i32, P(ctypes.c_double)]),
     "mpld_result_colors": (vp, [vp, P(c_i32)]),
     "mpld_result_component_of": (vp, [vp]),
     "mpld_result_num_components": (c_i32, [vp]),

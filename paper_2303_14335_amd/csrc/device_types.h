@@ -149,12 +149,13 @@ static_assert(sizeof(EngineTask) == 144, "engine task is 144 bytes");
 // index instead of its rows).
 struct EngineItem {
   uint32_t seg;
-  uint32_t kind;        // 0 subtask, 1 end, 2 solution
-  int32_t child;        // kind 0: task index of the subtask
-  uint32_t pad;
+  int32_t child;        // >= 0: the subtask's task index; kEngineItemEnd: the
+                        // task ends; kEngineItemSolution: the last seg node
+                        // was a solution
   uint64_t hash;        // traced engine: trace hash of the seg nodes
 };
-static_assert(sizeof(EngineItem) == 24, "engine item is 24 bytes");
+static_assert(sizeof(EngineItem) == 16, "engine item is 16 bytes");
+constexpr int32_t kEngineItemEnd = -1, kEngineItemSolution = -2;
 constexpr int32_t kEngineSkipped = -3;   // task status: not run (skip slot) or not split (budget or space)
 
 // A resolved heavy component written back by the device: its record and

@@ -55,6 +55,19 @@ __global__ __launch_bounds__(kLdsProbeThreads) void lds_read_kernel(uint32_t ite
 // Does nothing: its back-to-back launches time dispatch and completion.
 __global__ void empty_kernel() {}
 
+// Each wave w reads the 64 bytes at in + 64 w (lanes 0..7) and lane 0
+// writes 8 bytes to out[w]: the fixed cost of a launch whose waves touch
+// device memory once each way, as every search wave loads its item and
+// stores its record.
+__global__ void touch_kernel(const uint64_t* __restrict__ in, uint64_t* __restrict__ out) {
+  const uint32_t w = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6), l = threadIdx.x & 63u;
+  uint64_t v = l < 8u ? in[(uint64_t)w * 8u + l] : 0ull;
+  v ^= __shfl_xor(v, 1);
+  v ^= __shfl_xor(v, 2);
+  v ^= __shfl_xor(v, 4);
+  if (l == 0u) out[w] = v;
+}
+
 }  // namespace mpld
 
 using namespace mpld;
@@ -147,6 +160,53 @@ extern "C" int32_t mpld_measure_launch_floor(mpld_context* ctx, int32_t grid, in
     return e.code;
   } catch (...) {
     set_last_error("unexpected exception in the launch-floor measurement");
+    return MPLD_E_INTERNAL;
+  }
+}
+
+extern "C" int32_t mpld_measure_touch_floor(mpld_context* ctx, int32_t grid, int32_t block,
+                                            int32_t reps, double* us_per_launch) {
+  try {
+    if (!ctx || !us_per_launch) fail(MPLD_E_INVALID, "NULL argument");
+    if (grid < 1 || grid > (1 << 20)) fail(MPLD_E_INVALID, "grid must be in [1, 2^20]");
+    if (block < 64 || block > 1024 || block % 64 != 0)
+      fail(MPLD_E_INVALID, "block must be a multiple of 64 in [64, 1024]");
+    if (reps < 1 || reps > 100000) fail(MPLD_E_INVALID, "reps must be in [1, 100000]");
+    check_hip(hipSetDevice(ctx->device), "hipSetDevice");
+    hipStream_t s = ctx->stream;
+    const size_t waves = (size_t)grid * (size_t)(block / 64);
+    DevBuf in, out;
+    in.alloc(ctx, 64 * waves);
+    out.alloc(ctx, 8 * waves);
+    check_hip(hipMemsetAsync(in.p, 0, 64 * waves, s), "clear the input");
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    check_hip(hipEventCreate(&e0), "event");
+    check_hip(hipEventCreate(&e1), "event");
+    float ms = 0.f;
+    hipLaunchKernelGGL(touch_kernel, dim3(grid), dim3(block), 0, s, in.as<const uint64_t>(),
+                       out.as<uint64_t>());   // warm-up
+    hipError_t err = hipGetLastError();
+    if (err == hipSuccess) err = hipEventRecord(e0, s);
+    for (int32_t r = 0; r < reps && err == hipSuccess; ++r) {
+      hipLaunchKernelGGL(touch_kernel, dim3(grid), dim3(block), 0, s, in.as<const uint64_t>(),
+                         out.as<uint64_t>());
+      err = hipGetLastError();
+    }
+    if (err == hipSuccess) err = hipEventRecord(e1, s);
+    if (err == hipSuccess) err = hipEventSynchronize(e1);
+    if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    check_hip(err, "touch-kernel launches");
+    check_hip(hipStreamSynchronize(s), "touch-kernel drain");
+    *us_per_launch = (double)ms * 1e3 / reps;
+    set_last_error("");
+    return MPLD_OK;
+  } catch (const Error& e) {
+    set_last_error(e.what);
+    return e.code;
+  } catch (...) {
+    set_last_error("unexpected exception in the touch-floor measurement");
     return MPLD_E_INTERNAL;
   }
 }

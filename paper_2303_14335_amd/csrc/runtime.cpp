@@ -572,7 +572,7 @@ static void heavy_engine_device(DeviceBatch& db, bool trace) {
       if (w.next < 0) {   // first visit
         if (r.status == MPLD_INFEASIBLE || r.status == MPLD_FEASIBLE) {
           acc += r.nodes;
-          hash = trace_concat(hash, r.hash, r.nodes);
+          if (trace) hash = trace_concat(hash, r.hash, r.nodes);
           if (acc > budget) { redo = true; break; }
           if (r.status == MPLD_FEASIBLE) { found = true; sol = solution(w.task); break; }
           stack.pop_back();
@@ -586,10 +586,10 @@ static void heavy_engine_device(DeviceBatch& db, bool trace) {
       if (w.next >= r.nitems) { stack.pop_back(); continue; }
       const EngineItem it = hi[r.item_off + (uint32_t)w.next++];
       acc += it.seg;
-      hash = trace_concat(hash, it.hash, it.seg);
+      if (trace) hash = trace_concat(hash, it.hash, it.seg);
       if (acc > budget) { redo = true; break; }
-      if (it.kind == 1) { stack.pop_back(); continue; }
-      if (it.kind == 2) { found = true; sol = solution(w.task); break; }
+      if (it.child == kEngineItemEnd) { stack.pop_back(); continue; }
+      if (it.child == kEngineItemSolution) { found = true; sol = solution(w.task); break; }
       if (it.child < 0 || it.child >= ntasks) fail(MPLD_E_INTERNAL, "heavy-component engine: bad subtask");
       const int32_t child = it.child;
       stack.push_back({child, -1});   // invalidates w

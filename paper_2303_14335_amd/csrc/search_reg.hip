@@ -1080,9 +1080,8 @@ __device__ __forceinline__ int32_t engine_enumerate(RegState<K>& s, const uint32
       if (lane == ((uint32_t)count & 63u)) {   // one owner lane per item
         EngineItem it;
         it.seg = seg;
-        it.kind = kind;
-        it.child = kind == 0 ? children_base + nchild : -1;
-        it.pad = 0;
+        it.child = kind == 0 ? children_base + nchild
+                             : (kind == 1 ? kEngineItemEnd : kEngineItemSolution);
         it.hash = segh;
         items[count] = it;
       }

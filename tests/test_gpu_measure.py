@@ -34,3 +34,14 @@ def test_launch_floor(ctx):
     for grid, block, reps in ((0, 64, 10), (1, 65, 10), (1, 2048, 10), (1, 64, 0)):
         with pytest.raises(mp.MpldError):
             mp.mpld_measure_launch_floor(ctx, grid, block, reps)
+
+
+def test_touch_floor(ctx):
+    import paper_2303_14335_amd as mp
+    say("touch floor, 1 x 64 and 868 x 256")
+    one = mp.mpld_measure_touch_floor(ctx, 1, 64, 50)
+    many = mp.mpld_measure_touch_floor(ctx, 868, 256, 50)
+    assert 0 < one < 1000 and 0 < many < 1000
+    for grid, block, reps in ((0, 64, 10), (1, 65, 10), (1, 2048, 10), (1, 64, 0)):
+        with pytest.raises(mp.MpldError):
+            mp.mpld_measure_touch_floor(ctx, grid, block, reps)
