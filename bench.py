@@ -42,7 +42,8 @@ def kernel_source_hash() -> str:
     import importlib.util
     h = hashlib.sha256()
     pkg = os.path.join(ROOT, "paper_2303_14335_amd")
-    for f in ("csrc/search_reg.hip", "csrc/reg_items.h", "csrc/wave_ops.h", "csrc/device_types.h"):
+    for f in ("csrc/search_reg.hip", "csrc/reg_items.h", "csrc/wave_ops.h", "csrc/device_types.h",
+              "csrc/trace.h", "csrc/min_core.h"):
         with open(os.path.join(pkg, f), "rb") as fh:
             h.update(fh.read())
     spec = importlib.util.spec_from_file_location("_mpld_build_flags", os.path.join(pkg, "build.py"))

@@ -176,9 +176,11 @@ __device__ __forceinline__ void cover(Planes<K>& O, const uint32_t c, const uint
 // Bits 0 .. d-1 (d <= 64).
 __device__ __forceinline__ uint64_t below(uint32_t d) { return d >= 64u ? ~0ull : (1ull << d) - 1ull; }
 
-// Sets bit d of A to `on` (0 or 1), without a branch.
+// Sets bit d of A to `on` (0 or 1), without a branch: s_bitset0, then the
+// bit ORed in.
 __device__ __forceinline__ uint64_t with_bit(uint64_t A, uint32_t d, uint64_t on) {
-  return (A & ~(1ull << d)) | (on << d);
+  asm("s_bitset0_b64 %0, %1" : "+s"(A) : "s"(uniform(d)));
+  return A | (on << d);
 }
 
 // Takes row (v, c) at the current depth (column v already removed from P):
@@ -244,19 +246,19 @@ template <bool TRACE, int K, bool STITCH = false>
 __device__ __forceinline__ void reg_run(RegState<K>& s, const uint32_t nb_lo, const uint32_t nb_hi,
                                         const int32_t k, const uint64_t budget,
                                         const uint64_t stop_at, const uint32_t floor = 0) {
-  int32_t status = -1;
-  while (status < 0) {
+  int32_t status;
+  for (;;) {
     // ---- one search node
     if (__builtin_expect(s.nodes == stop_at, 0)) {
-      if (s.nodes != budget) break;   // paused: resumable here
-      status = MPLD_BUDGET_EXHAUSTED;
-      continue;
+      // paused short of the budget (resumable here), or out of budget
+      status = s.nodes != budget ? -1 : MPLD_BUDGET_EXHAUSTED;
+      break;
     }
     ++s.nodes;
     if (__builtin_expect(s.P == 0, 0)) {
       if (TRACE) s.h = trace_node(s.h, s.depth, s.row_in, kNone, 0);
       status = MPLD_FEASIBLE;
-      continue;
+      break;
     }
     uint64_t any = s.O[0];
 #pragma unroll
@@ -290,7 +292,7 @@ __device__ __forceinline__ void reg_run(RegState<K>& s, const uint32_t nb_lo, co
       if (TRACE) s.h = trace_node(s.h, s.depth, s.row_in, low_bit(zero), 0);
       if (!retreat<K, STITCH>(s, floor, v, c, alt, tried)) {
         status = MPLD_INFEASIBLE;
-        continue;
+        break;
       }
     }
     // ---- include row (v, c)
