@@ -280,9 +280,10 @@ static void trace_node(orc_dlx* x, uint32_t depth, uint32_t row_in, uint32_t col
 
 /* Algorithm X (Algorithm 1): stop when every primary column is covered (the
  * first solution ends the search); otherwise take the uncovered primary
- * column with the fewest rows, ties to the lowest index (reading of "a
- * column with only one related row or in BFS order": the index is the BFS
- * position), cover it, and try its rows in ascending order - include the
+ * column with the fewest rows, ties to the lowest index (our reading of
+ * Algorithm 1's column rule, which prefers single-row columns and otherwise
+ * follows BFS order: the index is the BFS position), cover it, and try its
+ * rows in ascending order - include the
  * row, cover its other columns, recurse, uncover, exclude - then uncover the
  * column.  An empty column is a dead end (the hot path reports INFEASIBLE
  * instead of marking conflict candidates).  A search node is an entry that
