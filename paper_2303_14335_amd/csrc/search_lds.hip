@@ -682,7 +682,7 @@ __device__ void solve_lds_wide(const DevDesc& d, const uint32_t* __restrict__ ga
     read_keys();
   }
 
-  while (status < 0) {
+  for (;;) {   // every exit sets the status
     // ---- one search node
     if (nodes == budget) { status = MPLD_BUDGET_EXHAUSTED; break; }
     ++nodes;
