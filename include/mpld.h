@@ -99,7 +99,10 @@ enum {
   MPLD_PLAIN = 1u << 2,        /* one kernel launch per component (comparison) */
   MPLD_FORCE_WAVE = 1u << 3,   /* force the register tier (n <= 64)           */
   MPLD_FORCE_LDS = 1u << 4,    /* force the LDS tier                          */
-  MPLD_FORCE_GLOBAL = 1u << 5, /* force the global-memory tier                */
+  MPLD_FORCE_GLOBAL = 1u << 5, /* force the big tier: level headers and undo
+                                  log in global memory, the lists in LDS on
+                                  one wave or in global memory on a workgroup
+                                  (mpld_tune.big_one_wave)                    */
   MPLD_DIRECT = 1u << 6,       /* batched solve: launch the kernels directly
                                   instead of replaying the captured HIP graph */
   MPLD_FORCE_DEVICE = 1u << 7, /* force the device-wide tier: one component at a
@@ -345,7 +348,7 @@ typedef struct {
   int32_t num_components;
   int32_t num_wave;          /* components on the register tier (n <= 64) */
   int32_t num_lds;           /* components on the LDS tier                */
-  int32_t num_global;        /* components on the global-memory tier      */
+  int32_t num_global;        /* components on the big tier                */
   int32_t core_nodes;        /* nodes left after simplification           */
   int32_t max_size;
   int64_t image_bytes;       /* packed device image                       */
