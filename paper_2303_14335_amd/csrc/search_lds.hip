@@ -540,7 +540,11 @@ __device__ void solve_lds_wide(const DevDesc& d, const uint32_t* __restrict__ ga
   const WideLayout L = wide_layout((int32_t)n, K, (int64_t)m2 + n + 1, STITCH);
   const uint32_t nwl = wide_words((int32_t)n);   // node words per lane (uniform)
   uint32_t* PL = reinterpret_cast<uint32_t*>(lds + L.pl_off);
-  uint32_t* keys = reinterpret_cast<uint32_t*>(lds + L.key_off);   // word w at (w & 63) * NW + (w >> 6)
+  // key of word w (lane w & 63, its j = w >> 6) at key_pos(w): a lane's keys
+  // j < 4 and j >= 4 each fill 16 contiguous bytes, and the lanes' blocks
+  // follow each other, so both ds_read_b128 of the keys are conflict-free
+  uint32_t* keys = reinterpret_cast<uint32_t*>(lds + L.key_off);
+  auto key_pos = [](uint32_t w) { return ((w >> 8) << 8) | ((w & 63u) << 2) | ((w >> 6) & 3u); };
   uint32_t* dbits = reinterpret_cast<uint32_t*>(lds + L.bits_off);
   uint32_t* offs = reinterpret_cast<uint32_t*>(lds + L.offs_off);
   uint16_t* ids = reinterpret_cast<uint16_t*>(lds + L.ids_off);
@@ -566,7 +570,7 @@ __device__ void solve_lds_wide(const DevDesc& d, const uint32_t* __restrict__ ga
     for (uint32_t c = 0; c < S; ++c) PL[w * S + c] = c <= (uint32_t)K ? val : 0u;
   }
 #pragma unroll
-  for (uint32_t j = 0; j < NW; ++j) keys[lane * NW + j] = kNoKey;
+  for (uint32_t j = 0; j < NW; ++j) keys[j * 64u + lane] = kNoKey;
   __syncthreads();
 
   uint32_t depth = 0, row_in = kNoneL, esp = 0;
@@ -581,7 +585,7 @@ __device__ void solve_lds_wide(const DevDesc& d, const uint32_t* __restrict__ ga
       if (j < nwl) {
         const uint32_t w = lane + 64u * j;
         W.load(PL, w);
-        keys[lane * NW + j] = wide_key<K>(W, w);
+        keys[key_pos(w)] = wide_key<K>(W, w);
       }
     }
   };
@@ -591,8 +595,8 @@ __device__ void solve_lds_wide(const DevDesc& d, const uint32_t* __restrict__ ga
   // hold kNoKey).
   uint4 ka, kb = make_uint4(kNoKey, kNoKey, kNoKey, kNoKey);
   auto read_keys = [&]() {
-    ka = *reinterpret_cast<const uint4*>(keys + lane * NW);
-    if (nwl > 4u) kb = *reinterpret_cast<const uint4*>(keys + lane * NW + 4u);
+    ka = *reinterpret_cast<const uint4*>(keys + lane * 4u);
+    if (nwl > 4u) kb = *reinterpret_cast<const uint4*>(keys + 256u + lane * 4u);
   };
 
   // Take row (v, c) at `depth`: one atomic AND per neighbour of v on plane
@@ -628,7 +632,7 @@ __device__ void solve_lds_wide(const DevDesc& d, const uint32_t* __restrict__ ga
       // lanes on the same word compute the same key
       if (act) {
         const uint32_t w = u >> 5;
-        keys[(w & 63u) * NW + (w >> 6)] = wide_key<K>(W, w);
+        keys[key_pos(w)] = wide_key<K>(W, w);
       }
       read_keys();
     }
