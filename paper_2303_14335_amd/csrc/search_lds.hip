@@ -727,8 +727,9 @@ __device__ void solve_lds_wide(const DevDesc& d, const uint32_t* __restrict__ ga
       rows &= ~(1u << c);   // the level's untried rows
     } else {
       // dead end: the headers and the log written so far must be visible
-      // to this wave's loads (stores done, the CU's vector cache dropped)
-      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "agent");
+      // to this wave's loads: a workgroup-scope fence waits for the stores
+      // (the workgroup's waves share the CU's write-through vector cache)
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
       // back to the deepest level below `depth` whose column has an untried row
       uint32_t f = kNoneL;
       if (depth != 0) {
@@ -783,7 +784,7 @@ __device__ void solve_lds_wide(const DevDesc& d, const uint32_t* __restrict__ ga
     row_in = v * (uint32_t)K + c;
     ++depth;
   }
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "agent");
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
   __syncthreads();
   if (status == MPLD_FEASIBLE) {
     for (uint32_t f = lane; f < depth; f += 64) {
