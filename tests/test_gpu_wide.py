@@ -238,3 +238,20 @@ def test_served_big_component(ctx):
             compare(srv.wait(t, 120_000_000), ref)
     finally:
         srv.close()
+
+
+def test_budget_sweep_big_layouts(ctx):
+    """Budget cuts at every node count from 1 to 60 and a few larger ones
+    on a 300-node component near the 3-colorability threshold, forced onto
+    the big tier in both layouts: status, nodes, hash, depth at stop."""
+    import paper_2303_14335_amd as mp
+    n = 300
+    e = workload.random_component(n, 5.0, 13)
+    g = mp.Graph(n, e, np.zeros((0, 2), np.int32))
+    og = oracle.Graph(n, e, np.zeros((0, 2), np.int32))
+    say("budget sweep, both big-tier layouts, n 300")
+    for budget in list(range(1, 61)) + [97, 1000, 4999, 65537]:
+        ref = oracle.decompose(og, 3, budget, simplify=False)
+        for one_wave in (1, 0):
+            got, _ = batch_solve(ctx, g, 3, budget, TRACE | FORCE_GLOBAL, one_wave)
+            compare(got, ref)
