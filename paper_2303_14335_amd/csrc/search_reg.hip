@@ -396,9 +396,10 @@ __device__ __forceinline__ void root_split(const RegItems& items, int32_t item, 
     }
     return;
   }
-  uint64_t ge2;
-  const uint32_t v0 = uniform(low_bit(min_count_columns(s.O, s.P, ge2)));
-  const uint32_t R0 = uniform(rows_of(s.O, v0));
+  // the root column and its rows without counting: every column has all
+  // k rows, so the fewest-rows, lowest-index column is node 0
+  constexpr uint32_t v0 = 0u;
+  const uint32_t R0 = uniform((1u << (uint32_t)d.k) - 1u);
   s.P &= ~(1ull << v0);
   const uint64_t nbv0 = rdlane64(nb_lo, nb_hi, v0);
   if (wave != 0u) {
