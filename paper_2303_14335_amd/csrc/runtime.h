@@ -16,7 +16,7 @@ namespace mpld {
 // k: the batch's mask count (every component of a batch shares it).
 // wpb: waves per workgroup (1..4); cap < budget stops components after cap
 // nodes (status -1, for the heavy-component engine).
-// heavy > 0: root split of items 0 .. heavy-1 (no trace, cap = ~0, wpb = 4,
+// heavy > 0: root split of items 0 .. heavy-1 (cap = ~0, wpb = 4,
 // grid >= heavy + ceil((qlen - heavy) / 4)).
 hipError_t launch_reg_batched(bool trace, int k, int grid, int wpb, RegItems items,
                               int32_t qlen, int32_t* counter, DevRecord* recs, int8_t* colors,

@@ -965,10 +965,10 @@ hipError_t launch_reg_batched(bool trace, int k, int grid, int wpb, RegItems ite
     const dim3 g(grid), b(64 * wg_waves);
     if (trace && stitch)
       hipLaunchKernelGGL((reg_batched_kernel<true, K, true>), g, b, 0, s, items, qlen, counter, recs,
-                         colors, cap, 0, chunk);
+                         colors, cap, heavy, chunk);
     else if (trace)
       hipLaunchKernelGGL((reg_batched_kernel<true, K, false>), g, b, 0, s, items, qlen, counter,
-                         recs, colors, cap, 0, chunk);
+                         recs, colors, cap, heavy, chunk);
     else if (stitch)
       hipLaunchKernelGGL((reg_batched_kernel<false, K, true>), g, b, 0, s, items, qlen, counter,
                          recs, colors, cap, heavy, chunk);
