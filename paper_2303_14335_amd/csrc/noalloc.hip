@@ -162,11 +162,8 @@ void solve_noalloc(mpld_context* ctx, const mpld_component* comps, int32_t count
   const int cap = ctx->num_cus * ctx->reg_blocks_per_cu;
   const int grid = std::max(1, std::min((count + 3) / 4, cap));
   check_hip(launch_reg_batched(trace, opt->k, grid, 4, ri, count, counter, recs, colors, ~0ull, 0, 16u,
-                               s),
+                               (opt->flags & MPLD_MARK_CONFLICTS) != 0, s),
             "register-tier launch");
-  if (opt->flags & MPLD_MARK_CONFLICTS)
-    check_hip(launch_mark_reg(opt->k, std::min(count, ctx->num_cus * 8), ri, count, recs, colors, s),
-              "conflict marking");
   check_hip(hipMemcpyAsync(g_stage.recs, recs, sizeof(DevRecord) * (size_t)count,
                            hipMemcpyDeviceToHost, s), "download records");
   if (total_nodes)

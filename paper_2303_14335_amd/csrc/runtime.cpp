@@ -320,8 +320,10 @@ void device_roundtrip(DeviceBatch& db, const Image& im, uint32_t flags) {
 }
 
 // split: the LDS and big tiers are left to csr_split (subtree tasks).
+// mark: the register-tier kernel also marks the components its search
+// leaves without a solution (uncapped launches only).
 static void enqueue_batched(DeviceBatch& db, bool trace, uint64_t cap, hipStream_t s,
-                            bool split = false) {
+                            bool split = false, bool mark = false) {
   const auto* desc = db.desc.as<DevDesc>();
   const RegItems items = db.reg_items();
   const auto* adj = db.adj32.as<uint32_t>();
@@ -334,7 +336,8 @@ static void enqueue_batched(DeviceBatch& db, bool trace, uint64_t cap, hipStream
     const int32_t heavy = cap == ~0ull ? db.reg_heavy : 0;
     const int grid = heavy ? heavy + (db.n_reg - heavy + 3) / 4 : db.grid_reg;
     check_hip(launch_reg_batched(trace, db.k, grid, db.tune.waves_per_block, items, db.n_reg, cnt,
-                                 recs, colors, cap, heavy, (uint32_t)db.tune.root_split_chunk, s),
+                                 recs, colors, cap, heavy, (uint32_t)db.tune.root_split_chunk,
+                                 mark && cap == ~0ull, s),
               "register-tier launch");
     ++db.launches;
   }
@@ -1056,11 +1059,13 @@ static void enqueue_minimize(DeviceBatch& db, hipStream_t s) {
             "Eq. 1 minimisation (register tier)");
 }
 
-static void enqueue_mark(DeviceBatch& db, hipStream_t s) {
+// reg: also the register-tier items (not when their batched launch marked
+// them already).
+static void enqueue_mark(DeviceBatch& db, hipStream_t s, bool reg = true) {
   mpld_context* ctx = db.ctx;
   auto* recs = db.recs.as<DevRecord>();
   auto* colors = db.colors.as<int8_t>();
-  if (db.n_reg)
+  if (db.n_reg && reg)
     check_hip(launch_mark_reg(db.k, std::min(db.n_reg, ctx->num_cus * 8), db.reg_items(), db.n_reg,
                               recs, colors, s),
               "conflict marking (register tier)");
@@ -1116,18 +1121,19 @@ void device_solve(DeviceBatch& db, uint32_t flags) {
   } else if ((flags & MPLD_DIRECT) || !db.tune.use_graph || db.n_dev) {
     // direct launches (cooperative launches stay out of graphs)
     if (timed) check_hip(hipEventRecord(ctx->ev[0], s), "event");
-    enqueue_batched(db, trace, cap, s, split);
+    enqueue_batched(db, trace, cap, s, split, mark && !split);
     if (split) {
       db.sp_rounds = db.sp_tasks_run = db.sp_heavy = db.sp_reruns = 0;
       if (db.n_reg) heavy_engine(db, trace);
       csr_split(db, trace);
     }
-    if (mark) enqueue_mark(db, s);
+    if (mark) enqueue_mark(db, s, split);
     if (minimize) enqueue_minimize(db, s);
     if (timed) check_hip(hipEventRecord(ctx->ev[1], s), "event");
   } else {
     // capture the tiered launches once, replay the graph afterwards
-    const uint32_t key = (trace ? 1u : 0u) | (split ? 2u : 0u);
+    const bool mark_fused = mark && !split;
+    const uint32_t key = (trace ? 1u : 0u) | (split ? 2u : 0u) | (mark_fused ? 4u : 0u);
     if (!db.graph || db.graph_flags != key) {
       if (db.graph) {
         check_hip(hipGraphExecDestroy(db.graph), "graph destroy");
@@ -1136,7 +1142,7 @@ void device_solve(DeviceBatch& db, uint32_t flags) {
       hipGraph_t g = nullptr;
       check_hip(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed), "begin capture");
       try {
-        enqueue_batched(db, trace, cap, s, split);
+        enqueue_batched(db, trace, cap, s, split, mark_fused);
       } catch (...) {
         (void)hipStreamEndCapture(s, &g);
         if (g) (void)hipGraphDestroy(g);
@@ -1155,7 +1161,7 @@ void device_solve(DeviceBatch& db, uint32_t flags) {
       if (db.n_reg) heavy_engine(db, trace);
       csr_split(db, trace);
     }
-    if (mark) enqueue_mark(db, s);
+    if (mark) enqueue_mark(db, s, split);
     if (minimize) enqueue_minimize(db, s);
     if (timed) check_hip(hipEventRecord(ctx->ev[1], s), "event");
   }

@@ -17,10 +17,13 @@ namespace mpld {
 // wpb: waves per workgroup (1..4); cap < budget stops components after cap
 // nodes (status -1, for the heavy-component engine).
 // heavy > 0: root split of items 0 .. heavy-1 (cap = ~0, wpb = 4,
-// grid >= heavy + ceil((qlen - heavy) / 4)).
+// grid >= heavy + ceil((qlen - heavy) / 4)).  mark (cap = ~0 only): a
+// component whose search ends without a solution is colored by the
+// conflict marking in the same wave.
 hipError_t launch_reg_batched(bool trace, int k, int grid, int wpb, RegItems items,
                               int32_t qlen, int32_t* counter, DevRecord* recs, int8_t* colors,
-                              uint64_t cap, int32_t heavy, uint32_t chunk, hipStream_t s);
+                              uint64_t cap, int32_t heavy, uint32_t chunk, bool mark,
+                              hipStream_t s);
 // Heavy-component engine: explore / split subtree tasks.
 // Task t writes its output block at out + t * kSplitBlockBytes and its
 // split items to pool at an offset taken from *pool_count (zero before the

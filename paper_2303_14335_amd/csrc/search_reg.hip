@@ -325,6 +325,53 @@ __device__ __forceinline__ void reg_finish(const RegState<K>& s, int32_t n,
   rec->hash = s.h;
 }
 
+// Conflict marking (Algorithm 1: a column left with no related row is a
+// conflict candidate (cl, cl'), cl' the column whose cover removed cl's
+// final row) for a component whose search ended without a solution: one
+// descent of the search that never backtracks.  The column is chosen by the
+// search's rule (fewest rows, lowest index) and takes its lowest open color;
+// a column with no row left takes the color of the row it lost last, which
+// conflicts with the neighbour that took that color.  Lane u holds N(u) and
+// the color u lost last; the planes are wave-uniform.  Every node is colored.
+template <int K>
+__device__ __forceinline__ void mark_core(uint32_t n, const uint64_t nb, int8_t* __restrict__ colors) {
+  const uint32_t lane = __lane_id();
+  n = uniform(n);
+  uint64_t P = n >= 64u ? ~0ull : ((1ull << n) - 1ull);
+  uint64_t O[K];
+#pragma unroll
+  for (int c = 0; c < K; ++c) O[c] = P;
+  uint32_t last = 0, color = 0;
+  while (P != 0ull) {
+    uint32_t cnt = 0;
+#pragma unroll
+    for (int c = 0; c < K; ++c) cnt += (uint32_t)((O[c] >> lane) & 1ull);
+    const uint32_t key = wave_min_u32(((P >> lane) & 1ull) ? (cnt << 8) | lane : ~0u);
+    const uint32_t v = key & 0xffu;
+    uint32_t c = (uint32_t)__builtin_amdgcn_readlane((int)last, (int)v);
+    if ((key >> 8) != 0u) {   // lowest open color of v
+      c = K - 1;
+#pragma unroll
+      for (int j = K - 2; j >= 0; --j)
+        if ((O[j] >> v) & 1ull) c = (uint32_t)j;
+    }
+    c = uniform(c);
+    P &= ~(1ull << v);
+    if (lane == v) color = c;
+    const uint64_t nv = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(nb >> 32), (int)v) << 32) |
+                        (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)nb, (int)v);
+    uint64_t removed = 0;
+#pragma unroll
+    for (int j = 0; j < K; ++j)
+      if ((uint32_t)j == c) {
+        removed = nv & O[j];
+        O[j] &= ~nv;
+      }
+    if ((removed >> lane) & 1ull) last = c;
+  }
+  if (lane < n) colors[lane] = (int8_t)color;
+}
+
 // Solves one register-tier item.  The descriptor (scalar loads) and the
 // lane's neighbour mask (a vector load) come from one record, so both
 // loads are in flight together.  cap < budget stops the search after `cap`
@@ -334,7 +381,7 @@ template <bool TRACE, int K, bool STITCH = false>
 __device__ __forceinline__ void solve_reg(const RegItems& items, int32_t item,
                                           int8_t* __restrict__ colors_base,
                                           DevRecord* __restrict__ recs,
-                                          const uint64_t cap = ~0ull) {
+                                          const uint64_t cap = ~0ull, const uint32_t mark = 0u) {
   const uint32_t lane = __lane_id();
   const uint64_t nb = item_mask(items, item, lane);
   const DevDesc d = item_desc(items, item);
@@ -345,6 +392,10 @@ __device__ __forceinline__ void solve_reg(const RegItems& items, int32_t item,
   reg_run<TRACE, K, STITCH>(s, (uint32_t)nb, (uint32_t)(nb >> 32), d.k, budget,
                             cap < budget ? cap : budget, 0);
   reg_finish(s, d.n, colors_base + d.out_off, recs + d.comp);
+  // mark: a search that ended without a solution is colored by the conflict
+  // marking right away, by the same wave (lane u rewrites color u)
+  if (mark && s.status != MPLD_FEASIBLE && s.status >= 0)
+    mark_core<K>((uint32_t)d.n, nb, colors_base + d.out_off);
 }
 
 // Root split for the heaviest items (no cap): one
@@ -372,7 +423,7 @@ struct RootSplitLds {
 template <bool TRACE, int K, bool STITCH>
 __device__ __forceinline__ void root_split(const RegItems& items, int32_t item, uint32_t wave,
                                            uint32_t chunk, int8_t* __restrict__ colors_base,
-                                           DevRecord* __restrict__ recs) {
+                                           DevRecord* __restrict__ recs, const uint32_t mark = 0u) {
   __shared__ RootSplitLds L;
   const uint32_t lane = __lane_id();
   constexpr uint32_t kHelpers = (K < 4 ? K : 4) - 1;
@@ -481,6 +532,7 @@ __device__ __forceinline__ void root_split(const RegItems& items, int32_t item, 
   }
   s.status = status;
   reg_finish(s, d.n, colors, rec);
+  if (mark && status != MPLD_FEASIBLE) mark_core<K>((uint32_t)d.n, nb, colors);
 }
 
 // Resumable state in device memory (kRegStateBytes per component): the
@@ -566,7 +618,7 @@ template <bool TRACE, int K, bool STITCH>
 __global__ __launch_bounds__(256) void reg_batched_kernel(
     const RegItems items, int32_t qlen, int32_t* __restrict__ counter,
     DevRecord* __restrict__ recs, int8_t* __restrict__ colors, uint64_t cap, int32_t heavy,
-    uint32_t chunk) {
+    uint32_t chunk, uint32_t mark) {
   const uint32_t wpb = blockDim.x >> 6;   // waves per workgroup
   if (heavy > 0) {
     // root split: workgroups 0 .. heavy-1 take items 0 .. heavy-1 (four
@@ -574,17 +626,18 @@ __global__ __launch_bounds__(256) void reg_batched_kernel(
     // that every item is handed out here
     const uint32_t b = xcd_block(), wave = uniform(threadIdx.x >> 6);
     if (b < (uint32_t)heavy) {
-      root_split<TRACE, K, STITCH>(items, (int32_t)b, wave, uniform(chunk), colors, recs);
+      root_split<TRACE, K, STITCH>(items, (int32_t)b, wave, uniform(chunk), colors, recs,
+                                   uniform(mark));
     } else {
       const int32_t item = heavy + (int32_t)((b - (uint32_t)heavy) * wpb + wave);
-      if (item < qlen) solve_reg<TRACE, K, STITCH>(items, item, colors, recs, cap);
+      if (item < qlen) solve_reg<TRACE, K, STITCH>(items, item, colors, recs, cap, uniform(mark));
     }
     return;
   }
   const int32_t gw = (int32_t)(gridDim.x * wpb);
   int32_t item = (int32_t)uniform(xcd_block() * wpb + (threadIdx.x >> 6));
   while (item < qlen) {
-    solve_reg<TRACE, K, STITCH>(items, item, colors, recs, cap);
+    solve_reg<TRACE, K, STITCH>(items, item, colors, recs, cap, uniform(mark));
     if (gw >= qlen) break;   // every item was handed out statically
     int32_t r = 0;
     if (__lane_id() == 0) r = atomicAdd(counter, 1);
@@ -600,53 +653,6 @@ __global__ __launch_bounds__(64) void reg_single_kernel(const RegItems items,
                                                         int32_t item, DevRecord* __restrict__ recs,
                                                         int8_t* __restrict__ colors) {
   solve_reg<TRACE, K, STITCH>(items, item, colors, recs);
-}
-
-// Conflict marking (Algorithm 1: a column left with no related row is a
-// conflict candidate (cl, cl'), cl' the column whose cover removed cl's
-// final row) for a component whose search ended without a solution: one
-// descent of the search that never backtracks.  The column is chosen by the
-// search's rule (fewest rows, lowest index) and takes its lowest open color;
-// a column with no row left takes the color of the row it lost last, which
-// conflicts with the neighbour that took that color.  Lane u holds N(u) and
-// the color u lost last; the planes are wave-uniform.  Every node is colored.
-template <int K>
-__device__ __forceinline__ void mark_core(uint32_t n, const uint64_t nb, int8_t* __restrict__ colors) {
-  const uint32_t lane = __lane_id();
-  n = uniform(n);
-  uint64_t P = n >= 64u ? ~0ull : ((1ull << n) - 1ull);
-  uint64_t O[K];
-#pragma unroll
-  for (int c = 0; c < K; ++c) O[c] = P;
-  uint32_t last = 0, color = 0;
-  while (P != 0ull) {
-    uint32_t cnt = 0;
-#pragma unroll
-    for (int c = 0; c < K; ++c) cnt += (uint32_t)((O[c] >> lane) & 1ull);
-    const uint32_t key = wave_min_u32(((P >> lane) & 1ull) ? (cnt << 8) | lane : ~0u);
-    const uint32_t v = key & 0xffu;
-    uint32_t c = (uint32_t)__builtin_amdgcn_readlane((int)last, (int)v);
-    if ((key >> 8) != 0u) {   // lowest open color of v
-      c = K - 1;
-#pragma unroll
-      for (int j = K - 2; j >= 0; --j)
-        if ((O[j] >> v) & 1ull) c = (uint32_t)j;
-    }
-    c = uniform(c);
-    P &= ~(1ull << v);
-    if (lane == v) color = c;
-    const uint64_t nv = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(nb >> 32), (int)v) << 32) |
-                        (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)nb, (int)v);
-    uint64_t removed = 0;
-#pragma unroll
-    for (int j = 0; j < K; ++j)
-      if ((uint32_t)j == c) {
-        removed = nv & O[j];
-        O[j] &= ~nv;
-      }
-    if ((removed >> lane) & 1ull) last = c;
-  }
-  if (lane < n) colors[lane] = (int8_t)color;
 }
 
 template <int K>
@@ -947,12 +953,14 @@ static void with_planes(int k, F&& f) {
 
 hipError_t launch_reg_batched(bool trace, int k, int grid, int wpb, RegItems items,
                               int32_t qlen, int32_t* counter, DevRecord* recs, int8_t* colors,
-                              uint64_t cap, int32_t heavy, uint32_t chunk, hipStream_t s) {
+                              uint64_t cap, int32_t heavy, uint32_t chunk, bool mark, hipStream_t s) {
   if (qlen <= 0) return hipSuccess;
   if (wpb < 1 || wpb > 4) return hipErrorInvalidValue;
   // the root split needs four waves per workgroup and a grid that hands
   // out every item at once
   if (heavy < 0 || heavy > qlen || chunk < 1) return hipErrorInvalidValue;
+  if (mark && cap != ~0ull) return hipErrorInvalidValue;   // capped records are not final
+  const uint32_t mk = mark ? 1u : 0u;
   if (heavy > 0 && (wpb != 4 || cap != ~0ull ||
                     (int64_t)grid < heavy + ((int64_t)qlen - heavy + wpb - 1) / wpb))
     return hipErrorInvalidValue;
@@ -965,16 +973,16 @@ hipError_t launch_reg_batched(bool trace, int k, int grid, int wpb, RegItems ite
     const dim3 g(grid), b(64 * wg_waves);
     if (trace && stitch)
       hipLaunchKernelGGL((reg_batched_kernel<true, K, true>), g, b, 0, s, items, qlen, counter, recs,
-                         colors, cap, heavy, chunk);
+                         colors, cap, heavy, chunk, mk);
     else if (trace)
       hipLaunchKernelGGL((reg_batched_kernel<true, K, false>), g, b, 0, s, items, qlen, counter,
-                         recs, colors, cap, heavy, chunk);
+                         recs, colors, cap, heavy, chunk, mk);
     else if (stitch)
       hipLaunchKernelGGL((reg_batched_kernel<false, K, true>), g, b, 0, s, items, qlen, counter,
-                         recs, colors, cap, heavy, chunk);
+                         recs, colors, cap, heavy, chunk, mk);
     else
       hipLaunchKernelGGL((reg_batched_kernel<false, K, false>), g, b, 0, s, items, qlen, counter,
-                         recs, colors, cap, heavy, chunk);
+                         recs, colors, cap, heavy, chunk, mk);
   });
   return hipGetLastError();
 }
