@@ -419,7 +419,7 @@ typedef struct {
                                 on one wave with their neighbour lists in LDS
                                 (level headers and undo log in global memory)
                                 when every big component of the batch fits
-                                that layout (k <= 4, at most 16384 nodes, 2m < 2^17,
+                                that layout (k <= 6, at most 16384 nodes, 2m < 2^17,
                                 degrees < 2^15, within the workgroup's LDS);
                                 0: a workgroup of up to 16 waves shares the
                                 column scan, lists in global memory          */

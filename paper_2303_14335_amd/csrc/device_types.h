@@ -48,10 +48,11 @@ inline uint32_t reg_item_width(int32_t max_n) { return max_n < 1 ? 1u : (uint32_
 constexpr int32_t kLds1MaxN = 2048;
 // One-wave wide tier (big components whose planes and neighbour lists fit
 // in LDS): at most 8 node words of 32 nodes per lane, so at most 16384
-// nodes, and k <= 4 (every plane word of a lane in registers); its offs
-// words hold the first neighbour in 17 bits and the degree above them.
+// nodes, and k <= 6 (beyond it the kernels it shares with the workgroup
+// layout would need scratch memory); its offs words hold the first
+// neighbour in 17 bits and the degree above them.
 constexpr int32_t kWideMaxWords = 8;
-constexpr int32_t kWideMaxK = 4;
+constexpr int32_t kWideMaxK = 6;
 constexpr int32_t kWideMaxN = 64 * 32 * kWideMaxWords;
 constexpr uint32_t kWideBegBits = 17;
 

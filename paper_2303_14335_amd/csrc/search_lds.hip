@@ -453,7 +453,7 @@ __device__ void solve_lds(const DevDesc& d, const uint32_t* __restrict__ gadj, c
 // the one-wave tier, but up to kWideMaxWords 32-bit node words per lane
 // (word w in lane w & 63), so no barrier per node, and the column choice
 // reads a cache of per-word keys instead of recounting every word: key(w) =
-// count << 28 | node << 4 | rows of the lowest-count, lowest-index
+// count << 28 | node << 8 | rows of the lowest-count, lowest-index
 // uncovered column of word w (kNoKey when w has none).  A cover changes
 // only the words of the column and of its neighbours, so after the cover
 // atomics each lane that made one reads its word's planes back and
@@ -492,7 +492,8 @@ __host__ __device__ inline WideLayout wide_layout(int32_t n, int32_t k, int64_t 
   return L;
 }
 
-// Key of word w (planes in W): count << 28 | node << 4 | rows (k <= 4).
+// Key of word w (planes in W): count << 28 | node << 8 | rows (count <= k <= 8,
+// node < 2^20).
 template <int K>
 __device__ __forceinline__ uint32_t wide_key(const Lds1Words<K>& W, uint32_t w) {
   constexpr int NB = bits_for(K);
@@ -521,7 +522,7 @@ __device__ __forceinline__ uint32_t wide_key(const Lds1Words<K>& W, uint32_t w) 
   uint32_t r = 0;
 #pragma unroll
   for (int c = 0; c < K; ++c) r |= __builtin_amdgcn_ubfe(W.a[c], bit, 1u) << c;
-  return p ? (t << 28) | (((w << 5) | bit) << 4) | r : kNoKey;
+  return p ? (t << 28) | (((w << 5) | bit) << 8) | r : kNoKey;
 }
 
 template <bool TRACE, int K, bool STITCH>
@@ -529,7 +530,6 @@ __device__ void solve_lds_wide(const DevDesc& d, const uint32_t* __restrict__ ga
                                uint64_t* gstack, int8_t* __restrict__ colors,
                                DevRecord* __restrict__ rec, int32_t root_row = -1,
                                uint64_t task_budget = 0) {
-  static_assert(K <= 4, "keys hold the count and the rows in 4 bits each");
   constexpr uint32_t S = lds1_stride(K);
   constexpr uint32_t kLS = S == 4u ? 2u : (S == 8u ? 3u : 4u);   // log2(S)
   constexpr uint32_t NW = (uint32_t)kWideMaxWords;
@@ -694,7 +694,7 @@ __device__ void solve_lds_wide(const DevDesc& d, const uint32_t* __restrict__ ga
     const uint32_t best = min(min(min(ka.x, ka.y), min(ka.z, ka.w)),
                               min(min(kb.x, kb.y), min(kb.z, kb.w)));
     // (kNoKey's node field is past n: read node 0's words instead)
-    const uint32_t vl = (best >> 4) & 0xffffffu, vc = vl < n ? vl : 0u;
+    const uint32_t vl = (best >> 8) & 0xfffffu, vc = vl < n ? vl : 0u;
     const uint32_t pre = offs[vc];
     asm volatile("" ::: "memory");
     const uint32_t key = wave_min(best);
@@ -703,13 +703,13 @@ __device__ void solve_lds_wide(const DevDesc& d, const uint32_t* __restrict__ ga
       status = MPLD_FEASIBLE;
       break;
     }
-    uint32_t v = (key >> 4) & 0xffffffu;
+    uint32_t v = (key >> 8) & 0xfffffu;
     const uint32_t size = key >> 28;
     if (TRACE) h = trace_node(h, depth, row_in, v, size);
     uint32_t rows, offv, est, lane_lo, c;
     bool full;
     if (size != 0) {
-      rows = key & 0xfu;
+      rows = key & 0xffu;
       offv = rdlane(pre, (v >> 5) & 63u);
       est = esp;
       lane_lo = 0u;
@@ -1037,7 +1037,8 @@ __device__ __forceinline__ void solve_lds_k(const DevDesc& d, const uint32_t* ga
     MPLD_LDS_CASE(6)
     MPLD_LDS_CASE(7)
     default:
-      if (BIG) solve_lds_wg<TRACE, 8, STITCH>(d, gadj, lds, gstack, colors, rec, root_row, task_budget);
+      if (BIG && wide) solve_lds_wide<TRACE, 8, STITCH>(d, gadj, lds, gstack, colors, rec, root_row, task_budget);
+      else if (BIG) solve_lds_wg<TRACE, 8, STITCH>(d, gadj, lds, gstack, colors, rec, root_row, task_budget);
       else solve_lds<TRACE, 8, STITCH>(d, gadj, lds, colors, rec, root_row, task_budget);
       break;
   }

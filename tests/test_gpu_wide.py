@@ -59,11 +59,13 @@ def batch_solve(ctx, g, k, budget, flags, one_wave, split=False):
 
 @pytest.mark.parametrize("one_wave", [1, 0])
 @pytest.mark.parametrize("k,deg,fits", [(3, 4.6, True), (2, 2.2, True), (4, 6.0, True),
-                                        (4, 8.0, False)])
+                                        (4, 8.0, False), (5, 5.0, True), (6, 5.5, True),
+                                        (7, 5.5, False)])
 def test_big_components_vs_oracle(ctx, one_wave, k, deg, fits):
-    """fits: every component's one-wave layout fits the workgroup's LDS (at
-    k = 4 and average degree 8 the 9000-node component's 144 KB of
-    neighbour ids do not, and the batch keeps the workgroup layout)."""
+    """fits: every component takes the one-wave layout (at k = 4 and average
+    degree 8 the 9000-node component's 144 KB of neighbour ids do not fit
+    the workgroup's LDS, and k = 7 is past the layout's k, so those batches
+    keep the workgroup layout)."""
     import paper_2303_14335_amd as mp
     parts = [(n, workload.random_component(n, deg, 40 + i))
              for i, n in enumerate((2049, 3000, 5200, 9000))]
