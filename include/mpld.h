@@ -365,8 +365,9 @@ typedef struct {
   float last_roundtrip_ms;   /* last MPLD_ROUNDTRIP solve: first byte of the
                                 image copied to the device .. last result byte
                                 back on the host (0 before)                  */
-  int32_t big_waves;         /* waves per workgroup of the big tier; 0: one
-                                wave with the neighbour lists in LDS         */
+  int32_t big_waves;         /* waves per workgroup of the big tier's
+                                workgroup layout; 0: every big component runs
+                                on one wave with its lists in LDS            */
 } mpld_batch_info;
 int32_t mpld_batch_get_info(mpld_batch* b, mpld_batch_info* info);
 void mpld_batch_free(mpld_batch* b);
@@ -415,14 +416,15 @@ typedef struct {
   int32_t root_split_max;    /* most components that get one; 0 = all         */
   int32_t root_split_chunk;  /* helper nodes between checks of the owner's
                                 release (>= 1)                                  */
-  int32_t big_one_wave;      /* 1 (default): components of the big tier run
-                                on one wave with their neighbour lists in LDS
-                                (level headers and undo log in global memory)
-                                when every big component of the batch fits
-                                that layout (k <= 6, at most 16384 nodes, 2m < 2^17,
-                                degrees < 2^15, within the workgroup's LDS);
-                                0: a workgroup of up to 16 waves shares the
-                                column scan, lists in global memory          */
+  int32_t big_one_wave;      /* 1 (default): each component of the big tier
+                                that fits runs on one wave with its neighbour
+                                lists in LDS (level headers and undo log in
+                                global memory; k <= 6, at most 16384 nodes,
+                                2m < 2^17, degrees < 2^15, within the
+                                workgroup's LDS), the others on a workgroup;
+                                0: every one on a workgroup of up to 16 waves
+                                sharing the column scan, lists in global
+                                memory                                        */
 } mpld_tune;
 int32_t mpld_batch_autotune(mpld_batch* b, int32_t reps, const char* cache_path, mpld_tune* out);
 int32_t mpld_batch_get_tune(mpld_batch* b, mpld_tune* out);

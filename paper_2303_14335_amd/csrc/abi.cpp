@@ -312,7 +312,7 @@ int32_t mpld_batch_get_info(mpld_batch* b, mpld_batch_info* info) {
     info->split_tasks = (int32_t)b->db.sp_tasks_run;
     info->split_reruns = (int32_t)b->db.sp_reruns;
     info->last_roundtrip_ms = b->db.last_roundtrip_ms;
-    info->big_waves = b->db.big_waves;
+    info->big_waves = b->db.n_big > b->db.n_wide ? b->db.big_waves : 0;
   });
 }
 

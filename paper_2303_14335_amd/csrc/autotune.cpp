@@ -272,7 +272,7 @@ int32_t mpld_batch_autotune(mpld_batch* b, int32_t reps, const char* cache_path,
       }
     }
     // big tier: a workgroup sharing the column scan instead of one wave
-    if (b->db.n_big > 0 && b->db.big_waves == 0) {
+    if (b->db.n_wide > 0) {
       Tune t;
       t.big_one_wave = 0;
       cands.push_back(t);

@@ -104,8 +104,12 @@ void image_add(Image& im, mpld_context* ctx, int32_t n, const int32_t* pairs, in
     } else if (big <= ctx->lds_per_block) {
       im.lds_bytes_big = std::max(im.lds_bytes_big, big);
       const int64_t wide = lds_wide_bytes(n, k, adj_words, (int32_t)maxdeg, stitch);
-      if (wide < 0 || wide > ctx->lds_per_block) im.big_wide = false;
-      else im.lds_bytes_wide = std::max(im.lds_bytes_wide, wide);
+      if (im.big_bytes_wg.size() <= (size_t)id) {
+        im.big_bytes_wg.resize((size_t)id + 1, 0);
+        im.big_bytes_wide.resize((size_t)id + 1, -1);
+      }
+      im.big_bytes_wg[(size_t)id] = big;
+      im.big_bytes_wide[(size_t)id] = wide > ctx->lds_per_block ? -1 : wide;
       im.big_stack_words = std::max(im.big_stack_words, lds_stack_words(n, k, adj_words));
       im.big_max_n = std::max(im.big_max_n, n);
       im.q_big.push_back(id);
@@ -177,12 +181,32 @@ void device_upload(mpld_context* ctx, const Image& im, DeviceBatch& db, const Tu
   }
   db.lds_dev = device_tier_lds_bytes(std::max(1, im.dev_max_n), db.grid_dev);
   db.lds_small = (int)im.lds_bytes_small;
-  // big tier: one wave with the neighbour lists in LDS (waves = 0, the wide
-  // layout) when every big component fits it, else a workgroup sharing the
-  // column scan
-  const bool wide = tune.big_one_wave && im.big_wide && !im.q_big.empty();
-  db.lds_big = (int)(wide ? im.lds_bytes_wide : im.lds_bytes_big);
-  db.big_waves = wide ? 0 : lds_big_waves(im.big_max_n);
+  // big tier: the components whose lists fit LDS run on one wave (the
+  // one-wave layout, launched with waves = 0) and come first; the others
+  // run on a workgroup sharing the column scan
+  std::vector<int32_t> q_big;
+  q_big.reserve(im.q_big.size());
+  int64_t wide_bytes = 0, wg_bytes = 0;
+  int32_t wg_max_n = 0;
+  for (int pass = 0; pass < 2; ++pass)
+    for (int32_t c : im.q_big) {
+      const int64_t wb = im.big_bytes_wide[(size_t)c];
+      const bool one_wave = tune.big_one_wave && wb >= 0;
+      if (one_wave != (pass == 0)) continue;
+      q_big.push_back(c);
+      if (one_wave) {
+        wide_bytes = std::max(wide_bytes, wb);
+      } else {
+        wg_bytes = std::max(wg_bytes, im.big_bytes_wg[(size_t)c]);
+        wg_max_n = std::max(wg_max_n, im.desc[(size_t)c].n);
+      }
+    }
+  db.n_wide = 0;
+  for (int32_t c : q_big)
+    if (tune.big_one_wave && im.big_bytes_wide[(size_t)c] >= 0) ++db.n_wide;
+  db.lds_wide = (int)wide_bytes;
+  db.lds_big = (int)wg_bytes;
+  db.big_waves = lds_big_waves(std::max(1, wg_max_n));
   db.mark_lds = im.mark_lds;
   db.big_stack_words = (uint64_t)im.big_stack_words;
   {
@@ -191,14 +215,21 @@ void device_upload(mpld_context* ctx, const Image& im, DeviceBatch& db, const Tu
     db.grid_reg = std::max(1, std::min((db.n_reg + wpb - 1) / wpb, cap));
   }
   db.grid_lds = std::max(1, std::min(db.n_lds, blocks_for_lds(ctx, db.lds_small)));
-  db.grid_big = std::max(1, std::min(db.n_big, blocks_for_lds(ctx, db.lds_big)));
-  // subtree tasks: k per big component, each on a workgroup of its own
-  db.grid_big_tasks = std::max(db.grid_big, std::min(db.k * db.n_big, blocks_for_lds(ctx, db.lds_big)));
+  {
+    const int32_t n_wg = db.n_big - db.n_wide;
+    db.grid_wide = std::max(1, std::min(db.n_wide, blocks_for_lds(ctx, db.lds_wide)));
+    db.grid_big = std::max(1, std::min(n_wg, blocks_for_lds(ctx, db.lds_big)));
+    // subtree tasks: k per big component, each on a workgroup of its own;
+    // the stack areas serve the launches of either layout, one at a time
+    db.grid_big_tasks = std::max({db.grid_wide, db.grid_big,
+                                  std::min(db.k * db.n_wide, blocks_for_lds(ctx, db.lds_wide)),
+                                  std::min(db.k * n_wg, blocks_for_lds(ctx, db.lds_big))});
+  }
 
   db.host_queue.clear();
   db.host_queue.insert(db.host_queue.end(), im.q_reg.begin(), im.q_reg.end());
   db.host_queue.insert(db.host_queue.end(), im.q_lds.begin(), im.q_lds.end());
-  db.host_queue.insert(db.host_queue.end(), im.q_big.begin(), im.q_big.end());
+  db.host_queue.insert(db.host_queue.end(), q_big.begin(), q_big.end());
   db.host_queue.insert(db.host_queue.end(), im.q_dev.begin(), im.q_dev.end());
 
   std::vector<DevDesc>& ordered = db.host_desc;
@@ -347,11 +378,18 @@ static void enqueue_batched(DeviceBatch& db, bool trace, uint64_t cap, hipStream
               "LDS-tier launch");
     ++db.launches;
   }
-  if (db.n_big && !split) {
-    check_hip(launch_lds_batched(trace, true, db.csr_stitch, db.big_waves, db.grid_big, db.lds_big, desc + db.n_reg + db.n_lds,
-                                 adj, db.n_big, cnt + 2, gstack, db.big_stack_words, recs, colors,
-                                 s),
-              "big-tier launch");
+  if (db.n_wide && !split) {   // one-wave layout
+    check_hip(launch_lds_batched(trace, true, db.csr_stitch, 0, db.grid_wide, db.lds_wide,
+                                 desc + db.n_reg + db.n_lds, adj, db.n_wide, cnt + 3, gstack,
+                                 db.big_stack_words, recs, colors, s),
+              "big-tier launch (one wave)");
+    ++db.launches;
+  }
+  if (db.n_big > db.n_wide && !split) {   // workgroup layout
+    check_hip(launch_lds_batched(trace, true, db.csr_stitch, db.big_waves, db.grid_big, db.lds_big,
+                                 desc + db.n_reg + db.n_lds + db.n_wide, adj, db.n_big - db.n_wide,
+                                 cnt + 2, gstack, db.big_stack_words, recs, colors, s),
+              "big-tier launch (workgroup)");
     ++db.launches;
   }
   for (int32_t i = 0; i < db.n_dev; ++i) {   // one cooperative launch per giant
@@ -699,8 +737,10 @@ static void csr_split(DeviceBatch& db, bool trace) {
   auto run = [&](const std::vector<LdsTask>& list, int64_t colors_bytes) {
     std::vector<DevRecord> out(list.size());
     if (list.empty()) return out;
-    size_t nsmall = 0;
+    size_t nsmall = 0, nwide = 0;
     while (nsmall < list.size() && list[nsmall].item < first + db.n_lds) ++nsmall;
+    while (nsmall + nwide < list.size() && list[nsmall + nwide].item < first + db.n_lds + db.n_wide)
+      ++nwide;
     const size_t tb = sizeof(LdsTask) * list.size(), rb = sizeof(DevRecord) * list.size();
     if (db.ct_tasks.bytes < tb) db.ct_tasks.alloc(ctx, tb);
     if (db.ct_recs.bytes < rb) db.ct_recs.alloc(ctx, rb);
@@ -718,13 +758,23 @@ static void csr_split(DeviceBatch& db, bool trace) {
                                  db.lds_small, db.desc.as<DevDesc>(), db.adj32.as<uint32_t>(), dt,
                                  (int32_t)nsmall, nullptr, 0, drec, db.ct_colors.as<int8_t>(), s),
                 "subtree tasks (LDS tier)");
-    if (nsmall < list.size())
-      check_hip(launch_lds_tasks(trace, true, db.csr_stitch, db.big_waves,
-                                 std::max(1, std::min((int)(list.size() - nsmall), db.grid_big_tasks)),
-                                 db.lds_big, db.desc.as<DevDesc>(), db.adj32.as<uint32_t>(),
-                                 dt + nsmall, (int32_t)(list.size() - nsmall), db.gstack.as<uint64_t>(),
+    if (nwide)
+      check_hip(launch_lds_tasks(trace, true, db.csr_stitch, 0,
+                                 std::max(1, std::min({(int)nwide, db.grid_big_tasks,
+                                                       blocks_for_lds(ctx, db.lds_wide)})),
+                                 db.lds_wide, db.desc.as<DevDesc>(), db.adj32.as<uint32_t>(),
+                                 dt + nsmall, (int32_t)nwide, db.gstack.as<uint64_t>(),
                                  db.big_stack_words, drec + nsmall, db.ct_colors.as<int8_t>(), s),
-                "subtree tasks (big tier)");
+                "subtree tasks (big tier, one wave)");
+    const size_t nbig = nsmall + nwide;
+    if (nbig < list.size())
+      check_hip(launch_lds_tasks(trace, true, db.csr_stitch, db.big_waves,
+                                 std::max(1, std::min({(int)(list.size() - nbig), db.grid_big_tasks,
+                                                       blocks_for_lds(ctx, db.lds_big)})),
+                                 db.lds_big, db.desc.as<DevDesc>(), db.adj32.as<uint32_t>(),
+                                 dt + nbig, (int32_t)(list.size() - nbig), db.gstack.as<uint64_t>(),
+                                 db.big_stack_words, drec + nbig, db.ct_colors.as<int8_t>(), s),
+                "subtree tasks (big tier, workgroup)");
     check_hip(hipMemcpyAsync(db.ct_host.p, drec, rb, hipMemcpyDeviceToHost, s), "subtree tasks: records");
     check_hip(hipStreamSynchronize(s), "subtree tasks");
     std::memcpy(out.data(), db.ct_host.p, rb);
@@ -1106,6 +1156,8 @@ void device_solve(DeviceBatch& db, uint32_t flags) {
         e = launch_reg_single(trace, db.k, items, i, recs, colors, s);
       else if (i < db.n_reg + db.n_lds)
         e = launch_lds_single(trace, false, db.csr_stitch, 1, db.lds_small, desc, adj, i, nullptr, recs, colors, s);
+      else if (i < db.n_reg + db.n_lds + db.n_wide)
+        e = launch_lds_single(trace, true, db.csr_stitch, 0, db.lds_wide, desc, adj, i, gstack, recs, colors, s);
       else if (i < db.n_reg + db.n_lds + db.n_big)
         e = launch_lds_single(trace, true, db.csr_stitch, db.big_waves, db.lds_big, desc, adj, i, gstack, recs, colors, s);
       else

@@ -204,8 +204,9 @@ struct Image {
   int64_t core_edges = 0;
   int64_t lds_bytes_small = 0;     // largest footprint on the LDS tier
   int64_t lds_bytes_big = 0;       // largest footprint on the big tier
-  int64_t lds_bytes_wide = 0;      // ... in the one-wave wide layout
-  bool big_wide = true;            // every big component fits the wide layout
+  // per component id, big tier: its LDS bytes in the workgroup layout and
+  // in the one-wave layout (-1: that layout does not take it)
+  std::vector<int64_t> big_bytes_wg, big_bytes_wide;
   int64_t big_stack_words = 0;     // largest global stack of the big tier
   int32_t big_max_n = 0;           // largest component of the big tier
   int64_t mark_lds = 0;            // LDS of the conflict marking of CSR components
@@ -269,6 +270,11 @@ struct DeviceBatch {
   int64_t sp_rounds = 0, sp_tasks_run = 0, sp_heavy = 0, sp_reruns = 0;  // last solve's stats
   Tune tune;
   int32_t n_reg = 0, n_lds = 0, n_big = 0, n_dev = 0;
+  // the first n_wide big-tier components take the one-wave layout
+  // (lds_wide bytes, grid_wide workgroups), the rest the workgroup layout
+  // (lds_big bytes, big_waves waves, grid_big workgroups)
+  int32_t n_wide = 0;
+  int lds_wide = 0, grid_wide = 1;
   int grid_dev = 1, lds_dev = 0;
   int32_t num_comps = 0, total_nodes = 0;
   int32_t k = 3;

@@ -253,15 +253,14 @@ void HipExecutor::tick(std::vector<Request*>& admitted, std::vector<ServeActive>
   hipStream_t s = ctx->stream;
   // LDS-tier components of the newly admitted requests, run to completion
   struct LdsItem { Request* r; int32_t comp; };
-  std::vector<LdsItem> lds_small, lds_big;
+  // big components: those whose lists fit LDS run on one wave (the
+  // one-wave layout), the others on a workgroup; lds_big holds the first
+  // group, then the second
+  std::vector<LdsItem> lds_small, lds_big, lds_big_wg;
   std::vector<DevDesc> lds_d;
-  int lds_small_bytes = 0, lds_big_bytes = 0;
+  int lds_small_bytes = 0, lds_big_bytes = 0, lds_wide_bytes_max = 0;
   int64_t big_words = 0;
   int32_t big_max_n = 0;
-  // big components run on one wave with their lists in LDS (the wide
-  // layout) when all of this flight's fit it
-  bool big_wide = true;
-  int lds_wide_bytes_max = 0;
   for (Request* r : admitted) {
     const int32_t nc = (int32_t)r->recs.size();
     for (int32_t c = 0; c < nc; ++c) {
@@ -278,17 +277,22 @@ void HipExecutor::tick(std::vector<Request*>& admitted, std::vector<ServeActive>
         lds_small_bytes = std::max<int>(lds_small_bytes, (int)lds_bytes_for(hd.n, hd.k, adj_words, maxdeg, false,
                                                                             (r->opt.flags & MPLD_STITCH_ORDER) != 0));
       } else {
-        lds_big.push_back({r, c});
         const bool st = (r->opt.flags & MPLD_STITCH_ORDER) != 0;
-        lds_big_bytes = std::max<int>(lds_big_bytes, (int)lds_bytes_for(hd.n, hd.k, adj_words, maxdeg, true, st));
         const int64_t wb = lds_wide_bytes(hd.n, hd.k, adj_words, maxdeg, st);
-        if (wb < 0 || wb > ctx->lds_per_block) big_wide = false;
-        else lds_wide_bytes_max = std::max<int>(lds_wide_bytes_max, (int)wb);
+        if (wb >= 0 && wb <= ctx->lds_per_block) {
+          lds_big.push_back({r, c});
+          lds_wide_bytes_max = std::max<int>(lds_wide_bytes_max, (int)wb);
+        } else {
+          lds_big_wg.push_back({r, c});
+          lds_big_bytes = std::max<int>(lds_big_bytes, (int)lds_bytes_for(hd.n, hd.k, adj_words, maxdeg, true, st));
+          big_max_n = std::max(big_max_n, hd.n);
+        }
         big_words = std::max<int64_t>(big_words, lds_stack_words(hd.n, hd.k, adj_words));
-        big_max_n = std::max(big_max_n, hd.n);
       }
     }
   }
+  const size_t n_wide = lds_big.size();
+  lds_big.insert(lds_big.end(), lds_big_wg.begin(), lds_big_wg.end());
   auto staged = [&](const LdsItem& it, int32_t out_index) {
     DevDesc d = it.r->im.desc[it.comp];
     d.nbr_off += (it.r->arena_off + it.r->off_adj) / 4;
@@ -363,7 +367,7 @@ void HipExecutor::tick(std::vector<Request*>& admitted, std::vector<ServeActive>
       lds_trace[i] = (char)(((it.r->opt.flags & MPLD_TRACE_HASH) ? 1 : 0) |
                             ((it.r->opt.flags & MPLD_STITCH_ORDER) ? 2 : 0));
     }
-    auto lds_launch = [&](size_t first, size_t count, bool big, int bytes) {
+    auto lds_launch = [&](size_t first, size_t count, bool big, int waves, int bytes) {
       size_t a = first;
       while (a < first + count) {   // one launch per run of equal trace and stitch flags
         size_t b = a;
@@ -371,8 +375,7 @@ void HipExecutor::tick(std::vector<Request*>& admitted, std::vector<ServeActive>
         const int per_cu = std::max(1, std::min(32, (160 * 1024) / std::max(bytes, 1)));
         const int grid = std::max(1, std::min((int)(b - a), ctx->num_cus * per_cu));
         // the big tier's stack areas: one per workgroup, grid <= count
-        check_hip(launch_lds_batched((lds_trace[a] & 1) != 0, big, (lds_trace[a] & 2) != 0,
-                                     big ? (big_wide ? 0 : lds_big_waves(big_max_n)) : 1, grid,
+        check_hip(launch_lds_batched((lds_trace[a] & 1) != 0, big, (lds_trace[a] & 2) != 0, waves, grid,
                                      bytes, f->desc.as<DevDesc>() + a, arena.as<uint32_t>(),
                                      (int32_t)(b - a), counter.as<int32_t>() + 1,
                                      big ? f->gstack.as<uint64_t>() : nullptr, (uint64_t)big_words,
@@ -381,8 +384,10 @@ void HipExecutor::tick(std::vector<Request*>& admitted, std::vector<ServeActive>
         a = b;
       }
     };
-    lds_launch(0, lds_small.size(), false, lds_small_bytes);
-    lds_launch(lds_small.size(), lds_big.size(), true, big_wide ? lds_wide_bytes_max : lds_big_bytes);
+    lds_launch(0, lds_small.size(), false, 1, lds_small_bytes);
+    lds_launch(lds_small.size(), n_wide, true, 0, lds_wide_bytes_max);   // one-wave layout
+    lds_launch(lds_small.size() + n_wide, lds_big.size() - n_wide, true,
+               lds_big_waves(std::max(1, big_max_n)), lds_big_bytes);   // workgroup layout
     if (!md.empty()) {
       if (f->mark_desc.bytes < mb) f->mark_desc.alloc(ctx, mb);
       check_hip(hipMemcpyAsync(f->mark_desc.p, f->host.as<uint8_t>() + db + rb, mb,

@@ -257,3 +257,47 @@ def test_budget_sweep_big_layouts(ctx):
         for one_wave in (1, 0):
             got, _ = batch_solve(ctx, g, 3, budget, TRACE | FORCE_GLOBAL, one_wave)
             compare(got, ref)
+
+
+def test_one_wave_word_boundaries(ctx):
+    """Sizes at the one-wave layout's word boundaries: 2,048 (one node word
+    per lane, forced onto the big tier) and 2,049, 4,096 and 4,097, 8,192
+    (a lane's keys in one 16-byte read) and 8,193 (in two)."""
+    import paper_2303_14335_amd as mp
+    parts = [(n, workload.random_component(n, 3.6, 70 + i))
+             for i, n in enumerate((2048, 2049, 4096, 4097, 8192, 8193))]
+    n, ce = disjoint(parts)
+    g = mp.Graph(n, ce, np.zeros((0, 2), np.int32))
+    og = oracle.Graph(n, ce, np.zeros((0, 2), np.int32))
+    for budget in (12000, 2049, 5):
+        say("one-wave word boundaries, budget", budget)
+        ref = oracle.decompose(og, 3, budget, simplify=False)
+        got, info = batch_solve(ctx, g, 3, budget, TRACE | FORCE_GLOBAL, 1)
+        assert info["big_waves"] == 0 and info["num_global"] == 6
+        compare(got, ref)
+
+
+def test_mixed_big_layouts(ctx):
+    """A batch whose big components take different layouts: 3,000 and 6,000
+    nodes on one wave, 16,500 nodes (past the one-wave layout) on a
+    workgroup; batched, as subtree tasks, and served."""
+    import paper_2303_14335_amd as mp
+    parts = [(3000, workload.random_component(3000, 4.6, 81)),
+             (16500, workload.random_component(16500, 2.6, 82)),
+             (6000, workload.random_component(6000, 4.6, 83))]
+    n, ce = disjoint(parts)
+    g = mp.Graph(n, ce, np.zeros((0, 2), np.int32))
+    og = oracle.Graph(n, ce, np.zeros((0, 2), np.int32))
+    for budget in (25000, 333):
+        ref = oracle.decompose(og, 3, budget, simplify=False)
+        for split in (False, True):
+            say("mixed big-tier layouts, budget", budget, "subtree tasks", split)
+            got, info = batch_solve(ctx, g, 3, budget, TRACE, 1, split=split)
+            assert info["num_global"] == 3 and info["big_waves"] > 0
+            compare(got, ref)
+        srv = mp.Server(ctx)
+        try:
+            say("mixed big-tier layouts, served, budget", budget)
+            compare(srv.wait(srv.submit(g, 3, budget, TRACE), 120_000_000), ref)
+        finally:
+            srv.close()
