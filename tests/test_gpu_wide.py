@@ -301,3 +301,30 @@ def test_mixed_big_layouts(ctx):
             compare(srv.wait(srv.submit(g, 3, budget, TRACE), 120_000_000), ref)
         finally:
             srv.close()
+
+
+def test_autotune_tries_the_workgroup_layout(ctx, tmp_path):
+    """A batch whose big components take the one-wave layout: the autotuner
+    also times the workgroup layout (big_one_wave = 0) and must get the same
+    records and colors from every candidate; the schedule it keeps goes to
+    the cache with its big_one_wave."""
+    import paper_2303_14335_amd as mp
+    parts = [(n, workload.random_component(n, 4.6, 95 + i)) for i, n in enumerate((2500, 3500))]
+    n, ce = disjoint(parts)
+    g = mp.Graph(n, ce, np.zeros((0, 2), np.int32))
+    ref = oracle.decompose(oracle.Graph(n, ce, np.zeros((0, 2), np.int32)), 3, 4000, simplify=False)
+    say("autotune with one-wave big components")
+    b = mp.Batch(ctx, g, 3, 4000, 0)
+    cache = str(tmp_path / "tune.jsonl")
+    t = b.autotune(reps=2, cache_path=cache)
+    assert t["candidates"] >= 2
+    b.solve()
+    compare(b.result(), ref, UNTRACED)
+    for one_wave in (0, 1):
+        b.set_tune(big_one_wave=one_wave)
+        assert (b.info()["big_waves"] == 0) == bool(one_wave)
+        b.solve()
+        compare(b.result(), ref, UNTRACED)
+    b.close()
+    with open(cache) as fh:
+        assert '"big_one_wave": %d' % t["big_one_wave"] in fh.read()
