@@ -328,3 +328,25 @@ def test_autotune_tries_the_workgroup_layout(ctx, tmp_path):
     b.close()
     with open(cache) as fh:
         assert '"big_one_wave": %d' % t["big_one_wave"] in fh.read()
+
+
+@pytest.mark.parametrize("k", [3, 4])
+def test_random_big_components(ctx, k):
+    """Seeded random components of 2,049-12,000 nodes and average degree
+    2.5-5.5, traced, at two budgets, on the default (per-component) big-tier
+    layouts and on the workgroup layout alone."""
+    import paper_2303_14335_amd as mp
+    rng = np.random.default_rng(9100 + k)
+    parts = []
+    for i in range(8):
+        n = int(rng.integers(2049, 12001))
+        parts.append((n, workload.random_component(n, float(rng.uniform(2.5, 5.5)), 900 + 10 * k + i)))
+    n, ce = disjoint(parts)
+    g = mp.Graph(n, ce, np.zeros((0, 2), np.int32))
+    og = oracle.Graph(n, ce, np.zeros((0, 2), np.int32))
+    for budget in (3000, 137):
+        ref = oracle.decompose(og, k, budget, simplify=False)
+        for one_wave in (1, 0):
+            say("random big components, k", k, "budget", budget, "one wave", one_wave)
+            got, _ = batch_solve(ctx, g, k, budget, TRACE, one_wave)
+            compare(got, ref)
