@@ -449,6 +449,9 @@ def main() -> int:
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run one device copy of this size (counter scaling probe)")
     args = ap.parse_args()
+    for name in ("plain_steps", "kernel_reps", "roundtrip_reps"):
+        if getattr(args, name) < 1:
+            ap.error(f"--{name.replace('_', '-')} must be at least 1")
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -619,7 +622,10 @@ def main() -> int:
             bs = mp.Batch(ctx, gs, ws.k, ws.budget, mp.MPLD_SIMPLIFY | fl)
             bs.solve(direct=True, timed=False)
             seq = bs.result()
-            bs.solve(direct=direct, split=True, timed=False)
+            # untimed warm-up solves: after the plain leg's thousands of tiny
+            # launches the first engine solves run measurably slower
+            for _ in range(8):
+                bs.solve(direct=direct, split=True, timed=False)
             torch.cuda.synchronize()
             tq = time.perf_counter()
             for _ in range(args.stitch_steps):
