@@ -631,9 +631,10 @@ def main() -> int:
             for _ in range(args.stitch_steps):
                 bs.solve(direct=direct, split=True, timed=False)
             torch.cuda.synchronize()
+            ms = 1000.0 * (time.perf_counter() - tq) / args.stitch_steps
             rq = bs.result()
             cs = rq.components["stitches"]
-            legs[name] = {"ms_per_step": 1000.0 * (time.perf_counter() - tq) / args.stitch_steps,
+            legs[name] = {"ms_per_step": ms,
                           "search_nodes": int(rq.components["nodes"].sum()),
                           "stitches": int(rq.stitches),
                           "stitches_in_searched_components": int(cs[cs >= 0].sum()),
