@@ -86,10 +86,9 @@ extern "C" int32_t mpld_measure_lds_read_rate(mpld_context* ctx, int32_t bytes_p
     DevBuf sink;
     sink.alloc(ctx, sizeof(uint32_t) * (size_t)grid);
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    check_hip(hipEventCreate(&e0), "event");
-    check_hip(hipEventCreate(&e1), "event");
     float ms = 0.f;
-    hipError_t err = hipSuccess;
+    hipError_t err = hipEventCreate(&e0);
+    if (err == hipSuccess) err = hipEventCreate(&e1);
     for (int rep = 0; rep < 2 && err == hipSuccess; ++rep) {   // the first run warms up
       err = hipEventRecord(e0, s);
       if (bytes_per_lane == 8)
@@ -103,9 +102,13 @@ extern "C" int32_t mpld_measure_lds_read_rate(mpld_context* ctx, int32_t bytes_p
       if (err == hipSuccess) err = hipEventSynchronize(e1);
       if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    // whatever failed, the sink is released only once the stream has
+    // drained what was enqueued on it
+    const hipError_t drained = hipStreamSynchronize(s);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
     check_hip(err, "LDS read-rate kernel");
+    check_hip(drained, "LDS read-rate drain");
     const double bytes = (double)grid * kLdsProbeThreads * (double)iters * kLdsProbeUnroll *
                          (double)bytes_per_lane;
     *gbytes_per_s = bytes / ((double)ms * 1e-3) / 1e9;
@@ -136,11 +139,13 @@ extern "C" int32_t mpld_measure_launch_floor(mpld_context* ctx, int32_t grid, in
     check_hip(hipSetDevice(ctx->device), "hipSetDevice");
     hipStream_t s = ctx->stream;
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    check_hip(hipEventCreate(&e0), "event");
-    check_hip(hipEventCreate(&e1), "event");
     float ms = 0.f;
-    hipLaunchKernelGGL(empty_kernel, dim3(grid), dim3(block), 0, s);   // warm-up
-    hipError_t err = hipGetLastError();
+    hipError_t err = hipEventCreate(&e0);
+    if (err == hipSuccess) err = hipEventCreate(&e1);
+    if (err == hipSuccess) {
+      hipLaunchKernelGGL(empty_kernel, dim3(grid), dim3(block), 0, s);   // warm-up
+      err = hipGetLastError();
+    }
     if (err == hipSuccess) err = hipEventRecord(e0, s);
     for (int32_t r = 0; r < reps && err == hipSuccess; ++r) {
       hipLaunchKernelGGL(empty_kernel, dim3(grid), dim3(block), 0, s);
@@ -149,8 +154,8 @@ extern "C" int32_t mpld_measure_launch_floor(mpld_context* ctx, int32_t grid, in
     if (err == hipSuccess) err = hipEventRecord(e1, s);
     if (err == hipSuccess) err = hipEventSynchronize(e1);
     if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
     check_hip(err, "empty-kernel launches");
     *us_per_launch = (double)ms * 1e3 / reps;
     set_last_error("");
@@ -178,14 +183,16 @@ extern "C" int32_t mpld_measure_touch_floor(mpld_context* ctx, int32_t grid, int
     DevBuf in, out;
     in.alloc(ctx, 64 * waves);
     out.alloc(ctx, 8 * waves);
-    check_hip(hipMemsetAsync(in.p, 0, 64 * waves, s), "clear the input");
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    check_hip(hipEventCreate(&e0), "event");
-    check_hip(hipEventCreate(&e1), "event");
     float ms = 0.f;
-    hipLaunchKernelGGL(touch_kernel, dim3(grid), dim3(block), 0, s, in.as<const uint64_t>(),
-                       out.as<uint64_t>());   // warm-up
-    hipError_t err = hipGetLastError();
+    hipError_t err = hipMemsetAsync(in.p, 0, 64 * waves, s);
+    if (err == hipSuccess) err = hipEventCreate(&e0);
+    if (err == hipSuccess) err = hipEventCreate(&e1);
+    if (err == hipSuccess) {
+      hipLaunchKernelGGL(touch_kernel, dim3(grid), dim3(block), 0, s, in.as<const uint64_t>(),
+                         out.as<uint64_t>());   // warm-up
+      err = hipGetLastError();
+    }
     if (err == hipSuccess) err = hipEventRecord(e0, s);
     for (int32_t r = 0; r < reps && err == hipSuccess; ++r) {
       hipLaunchKernelGGL(touch_kernel, dim3(grid), dim3(block), 0, s, in.as<const uint64_t>(),
@@ -195,10 +202,13 @@ extern "C" int32_t mpld_measure_touch_floor(mpld_context* ctx, int32_t grid, int
     if (err == hipSuccess) err = hipEventRecord(e1, s);
     if (err == hipSuccess) err = hipEventSynchronize(e1);
     if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    // whatever failed, the buffers are released only once the stream has
+    // drained what was enqueued on them
+    const hipError_t drained = hipStreamSynchronize(s);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
     check_hip(err, "touch-kernel launches");
-    check_hip(hipStreamSynchronize(s), "touch-kernel drain");
+    check_hip(drained, "touch-kernel drain");
     *us_per_launch = (double)ms * 1e3 / reps;
     set_last_error("");
     return MPLD_OK;
