@@ -1,5 +1,5 @@
 """bench.py's host-side pieces that need no GPU: the refusal of more than
-one GPU, and the issue fractions read from a rocprofv3 SQ summary (the
+one GPU and of zero repetition counts, and the issue fractions read from a rocprofv3 SQ summary (the
 committed one and a hand-made one with known figures)."""
 import os
 import subprocess
@@ -17,6 +17,15 @@ def test_more_than_one_gpu_is_refused():
                          capture_output=True, text=True, timeout=120)
     assert out.returncode == 2
     assert "exactly one GPU" in out.stdout
+
+
+@pytest.mark.parametrize("flag", ["--plain-steps", "--kernel-reps", "--roundtrip-reps"])
+def test_zero_repetitions_are_refused(flag):
+    # argparse rejects the value before anything is imported or timed
+    out = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), flag, "0"],
+                         capture_output=True, text=True, timeout=120)
+    assert out.returncode == 2
+    assert f"{flag} must be at least 1" in out.stderr
 
 
 def test_issue_fractions_hand_made(tmp_path):
