@@ -97,3 +97,16 @@ def test_no_device_is_a_device_error():
     with pytest.raises(mp.MpldError) as e:
         mp.Context(0, use_torch=False)
     assert e.value.code == -3
+
+
+def test_measurement_entry_points_reject_bad_arguments_before_any_device_call():
+    # argument checks come first, so these hold with no GPU: a NULL context
+    # or output is MPLD_E_INVALID, with the reason in the last error
+    import paper_2303_14335_amd as mp
+    lib = mp._lib
+    out = ctypes.c_double()
+    for fn in (lib.mpld_measure_launch_floor, lib.mpld_measure_touch_floor):
+        assert fn(None, 868, 256, 10, ctypes.byref(out)) == -1
+        assert b"NULL" in lib.mpld_last_error()
+        assert fn(None, 868, 256, 10, None) == -1
+    assert lib.mpld_measure_lds_read_rate(None, 16, 100, ctypes.byref(out), None) == -1
